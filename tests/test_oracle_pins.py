@@ -1,0 +1,245 @@
+"""Pins for the CPU FP64 oracle against facts fixed by the paper and by the
+mathematics, independent of the oracle's own formulas.
+
+* H = 1 reduces to the floating-mean Lomb-Scargle power (weighted linear
+  least squares on [1, cos, sin]; Section 1 model, Section 2 template).
+* 0 <= P <= 1 (Cauchy-Schwarz) and P_FTP(H) <= P_MHLS(H) (nested models).
+* a noiseless injected template gives P = 1 and recovers theta (Section 2).
+* invariances of P = (chi2_0 - chi2)/chi2_0 (Section 1 definition).
+* brute force over a dense theta_2 grid with observation-level P.
+* the polynomial pieces agree with observation-level MM(theta), YM(theta)
+  and with R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta (Eq. theta2cond).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ftp_oracle as O
+from synthetic import tiny_case, small_fp64_case, eval_template, Template
+
+
+def _run(tmpl, lc, **kw):
+    return O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, lc.n_f, **kw)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_h1_equals_floating_mean_lomb_scargle(seed):
+    tmpl, lc = tiny_case(seed, n_obs=60, H=1, n_f=40)
+    r = _run(tmpl, lc)
+    gls = np.array([O.gls_power(lc.t, lc.y, lc.sigma, j * lc.df) for j in range(1, lc.n_f + 1)])
+    assert np.max(np.abs(r["power"] - gls)) < 1e-12
+
+
+@pytest.mark.parametrize("seed,H", [(0, 2), (1, 3), (2, 4), (3, 6)])
+def test_bounds_and_mhls(seed, H):
+    tmpl, lc = tiny_case(seed, n_obs=70, H=H, n_f=40, cadence="nightly")
+    r = _run(tmpl, lc)
+    P = r["power"]
+    assert np.all(P >= 0.0) and np.all(P <= 1.0 + 1e-13)
+    mh = np.array([O.mhls_power(lc.t, lc.y, lc.sigma, j * lc.df, H) for j in range(1, lc.n_f + 1)])
+    assert np.all(P <= mh + 1e-12)
+
+
+@pytest.mark.parametrize("seed,H", [(0, 1), (1, 3), (2, 5)])
+def test_noiseless_injection_recovers_parameters(seed, H):
+    rng = np.random.default_rng(100 + seed)
+    tm = Template(rng.standard_normal(H), rng.standard_normal(H))
+    t = np.sort(rng.uniform(0, 20, 80))
+    df = 1.0 / (5 * (t.max() - t.min()))
+    j0 = 37
+    f0 = j0 * df
+    A, phi, B = 1.7, 2.1, -0.4
+    y = A * eval_template(tm, 2 * np.pi * f0 * t - phi) + B
+    sigma = rng.uniform(0.5, 2.0, len(t))
+    r = O.periodogram(t, y, sigma, tm.c, tm.s, df, freq_index=[j0])
+    assert abs(r["power"][0] - 1.0) < 1e-10
+    if H == 1:
+        # M(x + pi) = -M(x): (phi, A) and (phi + pi, -A) tie; the tie rule picks A > 0
+        pass
+    assert abs(r["amp"][0] - A) < 1e-8
+    d = (r["phase"][0] - phi + np.pi) % (2 * np.pi) - np.pi
+    assert abs(d) < 1e-8
+    assert abs(r["offset"][0] - B) < 1e-8
+
+
+def test_negative_amplitude_and_tie_rule():
+    # H=1: the sign flip with a pi shift gives an exact tie; theta1 > 0 wins.
+    rng = np.random.default_rng(7)
+    tm = Template(np.array([0.3]), np.array([1.1]))
+    t = np.sort(rng.uniform(0, 10, 50))
+    df = 1.0 / (5 * (t.max() - t.min()))
+    y = -2.0 * eval_template(tm, 2 * np.pi * 20 * df * t - 0.5) + 0.01 * rng.standard_normal(50)
+    r = O.periodogram(t, y, np.ones(50), tm.c, tm.s, df, freq_index=[20])
+    assert r["amp"][0] > 0
+    # a template with no such symmetry keeps the negative amplitude (Section 2.2 default)
+    tm2 = Template(np.array([1.0, 0.6, 0.3]), np.array([0.0, 0.5, -0.4]))
+    y2 = -1.5 * eval_template(tm2, 2 * np.pi * 20 * df * t - 0.5)
+    r2 = O.periodogram(t, y2, np.ones(50), tm2.c, tm2.s, df, freq_index=[20])
+    assert abs(r2["power"][0] - 1.0) < 1e-10 and abs(r2["amp"][0] + 1.5) < 1e-8
+
+
+@pytest.mark.parametrize("seed,H", [(0, 1), (1, 2), (2, 3), (3, 4)])
+def test_brute_force_theta_grid(seed, H):
+    tmpl, lc = tiny_case(seed, n_obs=45, H=H, n_f=25)
+    r = _run(tmpl, lc)
+    th = np.linspace(0.0, 2 * np.pi, 100_001)[:-1]
+    dth = th[1] - th[0]
+    for j in range(1, lc.n_f + 1):
+        f = j * lc.df
+        Pg = O.direct_power_at_phase(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, f, th)
+        k = int(np.argmax(Pg))
+        # golden-section refinement of the grid maximum
+        a, b = th[k] - dth, th[k] + dth
+        g = (math.sqrt(5) - 1) / 2
+        for _ in range(60):
+            c1, c2 = b - g * (b - a), a + g * (b - a)
+            if O.direct_power_at_phase(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, f, c1) > \
+               O.direct_power_at_phase(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, f, c2):
+                b = c2
+            else:
+                a = c1
+        Pref = O.direct_power_at_phase(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, f, 0.5 * (a + b))
+        Pc = r["power"][j - 1]
+        assert Pc >= Pg.max() - 1e-13
+        assert abs(Pc - max(Pref, Pg.max())) < 1e-10
+        # the reported phase reproduces the reported power at observation level
+        Pd = O.direct_power_at_phase(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, f, r["phase"][j - 1])
+        assert abs(Pd - Pc) < 1e-12
+
+
+def test_invariances():
+    tmpl, lc = tiny_case(11, n_obs=55, H=3, n_f=30, cadence="nightly")
+    base = _run(tmpl, lc)
+    P0 = base["power"]
+    # time shift: P unchanged, theta2 shifts by w * dt
+    dt = 3.25
+    sh = O.periodogram(lc.t + dt, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, lc.n_f)
+    assert np.max(np.abs(sh["power"] - P0)) < 1e-11
+    w = 2 * np.pi * lc.df * np.arange(1, lc.n_f + 1)
+    d = (sh["phase"] - base["phase"] - w * dt + np.pi) % (2 * np.pi) - np.pi
+    good = P0 > 1e-6
+    assert np.max(np.abs(d[good])) < 1e-7
+    # affine y, sigma scale, template scale
+    r = O.periodogram(lc.t, -3.0 * lc.y + 7.0, 2.5 * lc.sigma, 4.0 * tmpl.c, 4.0 * tmpl.s, lc.df, lc.n_f)
+    assert np.max(np.abs(r["power"] - P0)) < 1e-11
+    # template shift M(x) -> M(x - phi): P unchanged
+    phi = 0.7
+    n = np.arange(1, 4)
+    # M(x - phi) = sum c_n cos(n x - n phi) + s_n sin(n x - n phi)
+    c2 = tmpl.c * np.cos(n * phi) - tmpl.s * np.sin(n * phi)
+    s2 = tmpl.s * np.cos(n * phi) + tmpl.c * np.sin(n * phi)
+    r = O.periodogram(lc.t, lc.y, lc.sigma, c2, s2, lc.df, lc.n_f)
+    assert np.max(np.abs(r["power"] - P0)) < 1e-11
+    # permutation of observations
+    perm = np.random.default_rng(0).permutation(len(lc.t))
+    r = O.periodogram(lc.t[perm], lc.y[perm], lc.sigma[perm], tmpl.c, tmpl.s, lc.df, lc.n_f)
+    assert np.max(np.abs(r["power"] - P0)) < 1e-12
+    # duplicating an observation == halving its variance
+    i = 5
+    t2 = np.append(lc.t, lc.t[i]); y2 = np.append(lc.y, lc.y[i]); s2_ = np.append(lc.sigma, lc.sigma[i])
+    s3 = lc.sigma.copy(); s3[i] = lc.sigma[i] / np.sqrt(2.0)
+    ra = O.periodogram(t2, y2, s2_, tmpl.c, tmpl.s, lc.df, lc.n_f)
+    rb = O.periodogram(lc.t, lc.y, s3, tmpl.c, tmpl.s, lc.df, lc.n_f)
+    assert np.max(np.abs(ra["power"] - rb["power"])) < 1e-12
+
+
+def test_covariances_against_scalar_loops():
+    tmpl, lc = tiny_case(3, n_obs=12, H=3, n_f=4)
+    w = O.weights(lc.sigma)
+    ybar, YY = O.moments(lc.y, w)
+    freqs = np.array([2, 3], dtype=np.float64) * lc.df
+    cov = O.covariances(lc.t, lc.y, w, ybar, freqs, 3)
+    for q, f in enumerate(freqs):
+        x = [2 * math.pi * f * ti for ti in lc.t]
+        for n in range(1, 4):
+            Cn = math.fsum(wi * math.cos(n * xi) for wi, xi in zip(w, x))
+            Sn = math.fsum(wi * math.sin(n * xi) for wi, xi in zip(w, x))
+            assert abs(cov["C"][q, n - 1] - Cn) < 1e-12 and abs(cov["S"][q, n - 1] - Sn) < 1e-12
+            YCn = math.fsum(wi * (yi - ybar) * math.cos(n * xi) for wi, yi, xi in zip(w, lc.y, x))
+            assert abs(cov["YC"][q, n - 1] - YCn) < 1e-12
+            for m in range(1, 4):
+                Cm = math.fsum(wi * math.cos(m * xi) for wi, xi in zip(w, x))
+                Sm = math.fsum(wi * math.sin(m * xi) for wi, xi in zip(w, x))
+                cc = math.fsum(wi * math.cos(n * xi) * math.cos(m * xi) for wi, xi in zip(w, x)) - Cn * Cm
+                cs = math.fsum(wi * math.cos(n * xi) * math.sin(m * xi) for wi, xi in zip(w, x)) - Cn * Sm
+                ss = math.fsum(wi * math.sin(n * xi) * math.sin(m * xi) for wi, xi in zip(w, x)) - Sn * Sm
+                assert abs(cov["CC"][q, n - 1, m - 1] - cc) < 1e-12
+                assert abs(cov["CS"][q, n - 1, m - 1] - cs) < 1e-12
+                assert abs(cov["SS"][q, n - 1, m - 1] - ss) < 1e-12
+
+
+@pytest.mark.parametrize("H", [1, 2, 4, 6])
+def test_polynomial_matches_observation_level_definitions(H):
+    tmpl, lc = tiny_case(20 + H, n_obs=50, H=H, n_f=10, cadence="nightly")
+    w = O.weights(lc.sigma)
+    ybar, YY = O.moments(lc.y, w)
+    f = 7 * lc.df
+    cov = O.covariances(lc.t, lc.y, w, ybar, np.array([f]), H)
+    CCt, CSt, SSt = O.tilde_matrices(cov["CC"], cov["CS"], cov["SS"])
+    alpha = O.alpha_from_template(tmpl.c, tmpl.s)
+    MMp = O.mm_prime(alpha, CCt, CSt, SSt)[0]
+    YMp = O.ym_prime(alpha, cov["YC"], cov["YS"])[0]
+    p = O.final_poly(MMp, YMp)
+    # leading psi^{6H-1} coefficient cancels identically
+    assert abs(p[-1]) < 1e-14 * np.max(np.abs(p))
+    pD = p[:-1]
+    # anti-self-inversive: p_k = -conj(p_{D-k})
+    assert np.max(np.abs(pD + np.conj(pD[::-1]))) < 1e-13 * np.max(np.abs(pD))
+    x = 2 * np.pi * np.array([float((np.longdouble(ti) * np.longdouble(f)) % 1) for ti in lc.t])
+
+    def direct(theta):
+        M = O.template_values(tmpl.c, tmpl.s, x - theta)
+        Mb = np.sum(w * M)
+        MM = np.sum(w * (M - Mb) ** 2)
+        YM = np.sum(w * (M - Mb) * (lc.y - ybar))
+        return MM, YM
+
+    R = O.real_trig_poly(pD)
+    for theta in np.linspace(0.1, 6.0, 7):
+        psi = np.exp(1j * theta)
+        MMd, YMd = direct(theta)
+        MMa = np.real(psi ** (-2 * H) * np.polynomial.polynomial.polyval(psi, MMp))
+        YMa = np.real(psi ** (-H) * np.polynomial.polynomial.polyval(psi, YMp))
+        assert abs(MMa - MMd) < 1e-12 and abs(YMa - YMd) < 1e-12
+        h = 1e-5
+        MMp_, YMp_ = direct(theta + h)
+        MMm_, YMm_ = direct(theta - h)
+        dMM = (MMp_ - MMm_) / (2 * h)
+        dYM = (YMp_ - YMm_) / (2 * h)
+        Rd = 2 * MMd * dYM - YMd * dMM
+        assert abs(R(theta) - Rd) < 1e-7 * max(1.0, abs(Rd))
+
+
+def test_degenerate_and_error_inputs():
+    rng = np.random.default_rng(5)
+    tm = Template(np.array([1.0, 0.3]), np.array([0.2, -0.5]))
+    # strictly periodic sampling (t integer days): at f = 1/day all phases coincide
+    t = np.arange(40, dtype=np.float64)
+    y = rng.standard_normal(40)
+    df = 1.0 / 200.0
+    r = O.periodogram(t, y, np.ones(40), tm.c, tm.s, df, freq_index=[200, 37])
+    assert r["flag"][0] == 1 and r["power"][0] == 0.0 and r["amp"][0] == 0.0
+    assert abs(r["offset"][0] - np.mean(y)) < 1e-12
+    assert r["flag"][1] == 0 and r["power"][1] > 0
+    # all sigma = 0 -> uniform weights
+    ra = O.periodogram(t + 0.1 * rng.random(40), y, np.zeros(40), tm.c, tm.s, df, 20)
+    rb = O.periodogram(t + 0.1 * rng.random(40) * 0, y, np.ones(40), tm.c, tm.s, df, 20)
+    assert np.all(np.isfinite(ra["power"])) and np.all(np.isfinite(rb["power"]))
+    with pytest.raises(O.OracleError):
+        O.periodogram(t, y, np.r_[0.0, np.ones(39)], tm.c, tm.s, df, 5)
+    with pytest.raises(O.OracleError):
+        O.periodogram(t, np.ones(40), np.ones(40), tm.c, tm.s, df, 5)
+    with pytest.raises(O.OracleError):
+        O.periodogram(t, y, -np.ones(40), tm.c, tm.s, df, 5)
+    with pytest.raises(O.OracleError):
+        O.periodogram(t, y, np.ones(40), tm.c, tm.s, -1.0, 5)
+
+
+def test_small_fp64_workload_peak():
+    tmpl, lc = small_fp64_case()
+    r = _run(tmpl, lc)
+    j = int(np.argmax(r["power"])) + 1
+    assert abs(j * lc.df - 1 / 0.7) <= lc.df
+    assert r["power"][j - 1] > 0.95
+    assert abs(r["amp"][j - 1] - 1.0) < 0.05
