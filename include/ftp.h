@@ -1,0 +1,187 @@
+/*
+ * ftp.h -- C ABI of the MI355X (gfx950) fast template periodogram library.
+ *
+ * The method is Hoffman, Vanderplas, Hartman & Bakos, "A Fast Template
+ * Periodogram" (arXiv:2101.12348).  Given observations S = {(t_i, y_i,
+ * sigma_i)} and a template fixed by its truncated Fourier coefficients
+ * M(x) = sum_{n=1..H} c_n cos(n x) + s_n sin(n x) (Section 2), the library
+ * fits y ~ theta_1 M(w t - theta_2) + theta_3 at every trial frequency
+ * f_j = j df, j = 1..n_f (w = 2 pi f_j) and returns the periodogram
+ * P = (chi2_0 - chi2)/chi2_0 (Section 1, Eq. lsp; Section 2:
+ * P = YM^2/(YY MM)) with the best theta_2, theta_1 and theta_3.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: 0 on success, a negative FTP_E_* code otherwise.  Host-
+ *    detectable problems are reported synchronously; nothing is enqueued then.
+ *  - "device" pointers are HIP device allocations (e.g. torch tensors on
+ *    cuda:0); "host" pointers are ordinary host memory.  The caller owns every
+ *    array it passes; the library never frees them.
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued asynchronously on it; outputs are valid once
+ *    that stream has completed the call's work.
+ *  - Data-dependent problems found on the device (NaN/Inf in inputs,
+ *    sigma < 0, mixed zero and non-zero sigma, Var(y) = 0) make every
+ *    frequency of that lightcurve report FTP_ST_BAD_LC in `status` with
+ *    P = 0; per-frequency conditions use the other FTP_ST_* codes.
+ *  - theta_2 (phase) is reported in [0, 2 pi) relative to t = 0 as given.
+ *  - A plan must not be used from two host threads at once, and calls on one
+ *    plan must not overlap on different streams (the plan's scratch is
+ *    reused in stream order).
+ */
+#ifndef FTP_H
+#define FTP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define FTP_OK 0
+#define FTP_E_NULL -1          /* a required pointer is NULL */
+#define FTP_E_H -2             /* H < 1, H > FTP_MAX_H, or all c = s = 0 */
+#define FTP_E_NOBS -3          /* n_obs < 3 (or a ragged batch segment < 3) */
+#define FTP_E_DF -4            /* df <= 0 or not finite */
+#define FTP_E_NF -5            /* n_f < 1 */
+#define FTP_E_OFFSETS -6       /* obs_off / freq_off not monotone or not starting at 0 */
+#define FTP_E_SIZE -7          /* a size overflows the library's limits */
+#define FTP_E_HIP -8           /* a HIP runtime call failed (see ftp_last_error) */
+#define FTP_E_OPTION -9        /* an option value is invalid */
+#define FTP_E_NO_MODEL -10     /* learned solver requested but no network loaded */
+
+/* per-frequency status values (uint8) */
+#define FTP_ST_OK 0
+#define FTP_ST_DEGENERATE 1    /* MM ~ 0 at every candidate (all phases coincide): P = 0 */
+#define FTP_ST_CONSTANT 2      /* the phase polynomial vanishes: P does not depend on theta_2 */
+#define FTP_ST_NO_CONVERGE 3   /* companion QR hit its iteration limit */
+#define FTP_ST_BAD_LC 4        /* the lightcurve was rejected (see above) */
+#define FTP_ST_FALLBACK 8      /* bit: learned proposal fell back to the companion solve */
+
+#define FTP_MAX_H 16
+
+/* precision of the NFFT stage (spreading, FFT, sums); assembly, roots and
+ * scoring are always FP64 */
+#define FTP_FP32_SUMS 0
+#define FTP_FP64 1
+
+/* root solver */
+#define FTP_SOLVER_PLAIN 0     /* companion-matrix eigenvalues (Section 2) */
+#define FTP_SOLVER_LEARNED 1   /* MLP seeds + Newton + Sturm check, companion fallback */
+#define FTP_SOLVER_UNIFORM 2   /* as LEARNED but with 2H uniform seeds (ablation) */
+
+/* option flags */
+#define FTP_FLAG_FORCE_FALLBACK 1u  /* learned path: send every frequency to the companion solve */
+#define FTP_FLAG_TIME_STAGES 2u     /* record HIP events around the NFFT and per-frequency stages
+                                       (read back by ftp_last_stats) */
+
+typedef struct ftp_plan ftp_plan;
+
+typedef struct {
+  int precision;        /* FTP_FP32_SUMS (default) or FTP_FP64 */
+  int solver;           /* FTP_SOLVER_* (default PLAIN) */
+  double nfft_R;        /* minimum grid oversampling; 0 = 2.0 */
+  int nfft_msp;         /* Gaussian half-width in cells; 0 = 7 (FP32) / 12 (FP64) */
+  int solve_waves;      /* persistent solve grid in waves; 0 = autotuned default */
+  unsigned flags;       /* FTP_FLAG_* */
+} ftp_options;
+
+typedef struct {
+  uint64_t n_pairs;        /* frequencies solved by the last call */
+  uint64_t n_fallback;     /* of which went to the companion solve (learned path) */
+  uint64_t qr_sweeps;      /* Francis double-shift sweeps performed */
+  uint64_t newton_iters;   /* Newton iterations performed (learned path) */
+  uint64_t roots_found;    /* distinct real roots accepted (learned path) */
+  double ms_nfft;          /* device time of the NFFT stage (ms, 0 if not timed) */
+  double ms_solve;         /* device time of the per-frequency stage (ms) */
+} ftp_stats;
+
+/* Fill `opt` with the defaults.  Returns FTP_E_NULL if opt is NULL. */
+int ftp_options_default(ftp_options* opt);
+
+/*
+ * Create a plan for one template (Section 2: c_n, s_n, n = 1..H; host arrays
+ * of length H, copied).  `opt` may be NULL (defaults).  *out receives the plan.
+ * Errors: FTP_E_NULL, FTP_E_H, FTP_E_OPTION, FTP_E_HIP.
+ */
+int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, const ftp_options* opt);
+
+/* Release a plan and its device scratch (synchronises the device). */
+int ftp_plan_destroy(ftp_plan* plan);
+
+/*
+ * Template periodogram of one lightcurve (Section 2).
+ *   t, y, sigma : device, n_obs FP64 each; t in any order; sigma >= 0
+ *                 (all zero = uniform weights, Section 2).
+ *   df, n_f     : trial frequencies f_j = j df, j = 1..n_f (Section 1 grid).
+ *   power, phase, amp, offset : device, n_f FP64 each (P, theta_2, theta_1,
+ *                 theta_3 of Section 2).  status: device, n_f uint8, may be NULL.
+ * Errors: FTP_E_NULL, FTP_E_NOBS, FTP_E_DF, FTP_E_NF, FTP_E_SIZE, FTP_E_HIP.
+ */
+int ftp_periodogram(ftp_plan* plan, const double* t, const double* y, const double* sigma, int64_t n_obs,
+                    double df, int64_t n_f, double* power, double* phase, double* amp, double* offset,
+                    uint8_t* status, void* stream);
+
+/*
+ * Ragged batch of n_lc lightcurves sharing the plan's template.
+ *   obs_off  : host, n_lc + 1 prefix offsets into t/y/sigma (obs_off[0] = 0).
+ *   t, y, sigma : device, obs_off[n_lc] FP64 each.
+ *   df       : host, n_lc frequency spacings.
+ *   freq_off : host, n_lc + 1 prefix offsets into the outputs; lightcurve b
+ *              has n_f = freq_off[b+1] - freq_off[b] frequencies j = 1..n_f.
+ *   power, phase, amp, offset : device, freq_off[n_lc] FP64 each; status as above.
+ * Errors: as ftp_periodogram, plus FTP_E_OFFSETS.
+ */
+int ftp_periodogram_batch(ftp_plan* plan, int64_t n_lc, const int64_t* obs_off, const double* t,
+                          const double* y, const double* sigma, const double* df, const int64_t* freq_off,
+                          double* power, double* phase, double* amp, double* offset, uint8_t* status,
+                          void* stream);
+
+/*
+ * NFFT stage alone (for checking the sums): writes, per frequency j = 1..n_f,
+ * 3H complex FP64 values to `sums` (device, n_f * 6H doubles, interleaved
+ * re/im): Z_w(k j), k = 1..2H, then Z_y(k j), k = 1..H, where
+ *   Z_w(m) = sum_i w_i exp(2 pi i m df (t_i - t_ref)),
+ *   Z_y(m) = sum_i w_i (y_i - ybar) exp(2 pi i m df (t_i - t_ref))
+ * (the raw sums behind Eqs. CCdef-YSdef).  `lc_stats` (device, 4 doubles)
+ * receives t_ref, ybar, YY = chi2_0 and the lightcurve status bits.
+ * Errors: as ftp_periodogram.
+ */
+int ftp_nfft_sums(ftp_plan* plan, const double* t, const double* y, const double* sigma, int64_t n_obs,
+                  double df, int64_t n_f, double* sums, double* lc_stats, void* stream);
+
+/*
+ * Per-frequency stage alone, from given sums in the layout ftp_nfft_sums
+ * writes (device `sums`), with t_ref, ybar and YY given on the host
+ * (`lc_stats`, 3 doubles).  Outputs as ftp_periodogram.
+ * Errors: FTP_E_NULL, FTP_E_DF, FTP_E_NF, FTP_E_HIP.
+ */
+int ftp_solve_sums(ftp_plan* plan, const double* sums, const double* lc_stats, double df, int64_t n_f,
+                   double* power, double* phase, double* amp, double* offset, uint8_t* status,
+                   void* stream);
+
+/*
+ * Load the root-proposal network (learned solver): `weights` is a host FP32
+ * array of n_floats values in the order W1, b1, W2, b2, W3, b3, W4, b4 with
+ * W stored (out, in) row-major; sizes d_in = 2(6H-1), width, d_out = 4H.
+ * Errors: FTP_E_NULL, FTP_E_SIZE (n_floats does not match), FTP_E_HIP.
+ */
+int ftp_plan_load_mlp(ftp_plan* plan, const float* weights, int64_t n_floats, int width);
+
+/* Statistics accumulated over the plan's calls since the previous
+ * ftp_last_stats (or plan creation); resets the accumulation.  Synchronises
+ * `stream`, which must be the stream the calls were made on. */
+int ftp_last_stats(ftp_plan* plan, ftp_stats* out, void* stream);
+
+/* Human-readable text for an FTP_E_* or FTP_ST_* code. */
+const char* ftp_status_string(int code);
+
+/* Text of the last HIP error seen by the library (thread-local). */
+const char* ftp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTP_H */

@@ -46,7 +46,7 @@ __all__ = [
     "alpha_from_template", "mm_prime", "ym_prime", "final_poly", "trim_poly",
     "poly_roots", "score_phase", "periodogram", "direct_power_at_phase",
     "template_values", "gls_power", "mhls_power", "real_trig_poly",
-    "unit_circle_root_count", "OracleError",
+    "unit_circle_root_count", "raw_sums", "direct_fit_at_phase", "OracleError",
 ]
 
 EPS = np.finfo(np.float64).eps
@@ -82,7 +82,7 @@ def moments(y, w):
     y = np.asarray(y, dtype=np.float64)
     ybar = float(np.sum(w * y))
     YY = float(np.sum(w * (y - ybar) ** 2))
-    if not np.isfinite(YY) or YY <= 0.0:
+    if not np.isfinite(YY) or YY <= 0.0 or np.all(y == y[0]):
         raise OracleError("Var(y) = 0: the periodogram is undefined")
     return ybar, YY
 
@@ -394,3 +394,46 @@ def unit_circle_root_count(p_full, tol=1e-6):
     on = d < tol
     off = d[~on]
     return int(np.sum(on)), (float(np.min(off)) if len(off) else np.inf), r
+
+
+def raw_sums(t, y, sigma, df, freq_index, kmax_w, kmax_y, t_ref=0.0):
+    """The raw trig sums behind Eqs. CCdef-YSdef, by direct summation:
+    Zw[q, k-1] = sum_i w_i exp(2 pi i k j_q df (t_i - t_ref)), k = 1..kmax_w;
+    Zy[q, k-1] = sum_i w_i (y_i - ybar) exp(...), k = 1..kmax_y.
+    Phases are reduced in cycles in extended precision.  Returns (Zw, Zy,
+    ybar, YY)."""
+    w = weights(sigma)
+    y = np.asarray(y, dtype=np.float64)
+    ybar, YY = moments(y, w)
+    d = np.asarray(t, dtype=np.longdouble) - np.longdouble(t_ref)
+    js = np.asarray(freq_index, dtype=np.int64)
+    Zw = np.empty((len(js), kmax_w), dtype=np.complex128)
+    Zy = np.empty((len(js), kmax_y), dtype=np.complex128)
+    gy = w * (y - ybar)
+    for q, j in enumerate(js):
+        for k in range(1, max(kmax_w, kmax_y) + 1):
+            cyc = d * (np.longdouble(k * int(j)) * np.longdouble(df))
+            cyc = (cyc - np.floor(cyc)).astype(np.float64)
+            e = np.exp(2j * np.pi * cyc)
+            if k <= kmax_w:
+                Zw[q, k - 1] = np.sum(w * e)
+            if k <= kmax_y:
+                Zy[q, k - 1] = np.sum(gy * e)
+    return Zw, Zy, ybar, YY
+
+
+def direct_fit_at_phase(t, y, sigma, c, s, f, theta2):
+    """Weighted least squares of y on [M(w t - theta2), 1] at a fixed phase,
+    from the observations: returns (P, theta_1, theta_3) (Section 2)."""
+    w = weights(sigma)
+    y = np.asarray(y, dtype=np.float64)
+    ybar, YY = moments(y, w)
+    x = 2.0 * np.pi * _cycles(t, f)
+    M = template_values(c, s, x - theta2)
+    Mbar = np.sum(w * M)
+    MM = np.sum(w * (M - Mbar) ** 2)
+    YM = np.sum(w * (M - Mbar) * (y - ybar))
+    if MM <= 0:
+        return 0.0, 0.0, ybar
+    th1 = YM / MM
+    return YM * YM / (YY * MM), th1, ybar - Mbar * th1

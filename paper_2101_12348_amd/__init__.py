@@ -1,0 +1,233 @@
+"""Python binding of the gfx950 fast template periodogram library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libftp.so`` (built in-tree by ``build.py``).  Tensors are torch
+tensors on a ROCm device; the current torch stream is passed to the library.
+There is no CPU fallback: if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libftp.so")
+
+FTP_FP32_SUMS = 0
+FTP_FP64 = 1
+FTP_SOLVER_PLAIN = 0
+FTP_SOLVER_LEARNED = 1
+FTP_SOLVER_UNIFORM = 2
+FTP_FLAG_FORCE_FALLBACK = 1
+FTP_FLAG_TIME_STAGES = 2
+MAX_H = 16
+
+ST_OK, ST_DEGENERATE, ST_CONSTANT, ST_NO_CONVERGE, ST_BAD_LC, ST_FALLBACK = 0, 1, 2, 3, 4, 8
+
+EXPORTED = [
+    "ftp_options_default", "ftp_plan_create", "ftp_plan_destroy", "ftp_periodogram",
+    "ftp_periodogram_batch", "ftp_nfft_sums", "ftp_solve_sums", "ftp_plan_load_mlp",
+    "ftp_last_stats", "ftp_status_string", "ftp_last_error",
+]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("solver", ctypes.c_int), ("nfft_R", ctypes.c_double),
+                ("nfft_msp", ctypes.c_int), ("solve_waves", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64), ("qr_sweeps", ctypes.c_uint64),
+                ("newton_iters", ctypes.c_uint64), ("roots_found", ctypes.c_uint64),
+                ("ms_nfft", ctypes.c_double), ("ms_solve", ctypes.c_double)]
+
+
+class FtpError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load ``libftp.so`` and declare its C signatures (raises if absent)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise FtpError(f"HIP library not built: {p} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(p)
+    vp, i64, dbl, ip = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    lib.ftp_options_default.argtypes = [ctypes.POINTER(Options)]
+    lib.ftp_plan_create.argtypes = [ctypes.POINTER(vp), ip, vp, vp, ctypes.POINTER(Options)]
+    lib.ftp_plan_destroy.argtypes = [vp]
+    lib.ftp_periodogram.argtypes = [vp, vp, vp, vp, i64, dbl, i64, vp, vp, vp, vp, vp, vp]
+    lib.ftp_periodogram_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.ftp_nfft_sums.argtypes = [vp, vp, vp, vp, i64, dbl, i64, vp, vp, vp]
+    lib.ftp_solve_sums.argtypes = [vp, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp]
+    lib.ftp_plan_load_mlp.argtypes = [vp, vp, i64, ip]
+    lib.ftp_last_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
+    lib.ftp_status_string.argtypes = [ip]
+    lib.ftp_status_string.restype = ctypes.c_char_p
+    lib.ftp_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("ftp_status_string", "ftp_last_error"):
+            getattr(lib, name).restype = ip
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        lib = load_library()
+        msg = lib.ftp_status_string(rc).decode()
+        if rc == -8:
+            msg += ": " + lib.ftp_last_error().decode()
+        raise FtpError(f"ftp error {rc}: {msg}")
+
+
+def status_string(code: int) -> str:
+    return load_library().ftp_status_string(int(code)).decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(x, dtype, device):
+    torch = _torch()
+    t = torch.as_tensor(x, dtype=dtype, device=device)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Plan:
+    """A plan for one template (c_n, s_n, n = 1..H)."""
+
+    def __init__(self, c, s, precision: int = FTP_FP32_SUMS, solver: int = FTP_SOLVER_PLAIN,
+                 nfft_R: float = 2.0, nfft_msp: int = 0, solve_waves: int = 0, flags: int = 0):
+        import numpy as np
+        self.lib = load_library()
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        if c.shape != s.shape or c.ndim != 1:
+            raise ValueError("c and s must be 1-D arrays of equal length")
+        self.H = len(c)
+        self.c, self.s = c, s
+        opt = Options()
+        self.lib.ftp_options_default(ctypes.byref(opt))
+        opt.precision, opt.solver, opt.nfft_R = precision, solver, nfft_R
+        opt.nfft_msp, opt.solve_waves, opt.flags = nfft_msp, solve_waves, flags
+        self.options = opt
+        h = ctypes.c_void_p()
+        _check(self.lib.ftp_plan_create(ctypes.byref(h), self.H, c.ctypes.data_as(ctypes.c_void_p),
+                                         s.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opt)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.ftp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def periodogram(self, t, y, sigma, df: float, n_f: int, device="cuda", stream=None, out=None):
+        torch = _torch()
+        t = _dev(t, torch.float64, device)
+        y = _dev(y, torch.float64, device)
+        sigma = _dev(sigma, torch.float64, device)
+        if out is None:
+            out = self.alloc_outputs(n_f, t.device)
+        _check(self.lib.ftp_periodogram(self.handle, _ptr(t), _ptr(y), _ptr(sigma), t.numel(), float(df),
+                                        int(n_f), _ptr(out["power"]), _ptr(out["phase"]), _ptr(out["amp"]),
+                                        _ptr(out["offset"]), _ptr(out["status"]), _stream_ptr(stream)))
+        return out
+
+    @staticmethod
+    def alloc_outputs(n, device):
+        torch = _torch()
+        return dict(power=torch.empty(n, dtype=torch.float64, device=device),
+                    phase=torch.empty(n, dtype=torch.float64, device=device),
+                    amp=torch.empty(n, dtype=torch.float64, device=device),
+                    offset=torch.empty(n, dtype=torch.float64, device=device),
+                    status=torch.empty(n, dtype=torch.uint8, device=device))
+
+    def periodogram_batch(self, obs_off, t, y, sigma, df, freq_off, device="cuda", stream=None, out=None):
+        import numpy as np
+        torch = _torch()
+        obs_off = np.ascontiguousarray(obs_off, dtype=np.int64)
+        freq_off = np.ascontiguousarray(freq_off, dtype=np.int64)
+        df = np.ascontiguousarray(df, dtype=np.float64)
+        n_lc = len(df)
+        if len(obs_off) != n_lc + 1 or len(freq_off) != n_lc + 1:
+            raise ValueError("offsets must have n_lc + 1 entries")
+        t = _dev(t, torch.float64, device)
+        y = _dev(y, torch.float64, device)
+        sigma = _dev(sigma, torch.float64, device)
+        if out is None:
+            out = self.alloc_outputs(int(freq_off[-1]), t.device)
+        _check(self.lib.ftp_periodogram_batch(
+            self.handle, n_lc, obs_off.ctypes.data_as(ctypes.c_void_p), _ptr(t), _ptr(y), _ptr(sigma),
+            df.ctypes.data_as(ctypes.c_void_p), freq_off.ctypes.data_as(ctypes.c_void_p),
+            _ptr(out["power"]), _ptr(out["phase"]), _ptr(out["amp"]), _ptr(out["offset"]),
+            _ptr(out["status"]), _stream_ptr(stream)))
+        return out
+
+    def nfft_sums(self, t, y, sigma, df: float, n_f: int, device="cuda", stream=None):
+        """Returns (sums complex128 tensor (n_f, 3H), stats tensor [t_ref, ybar, YY, status])."""
+        torch = _torch()
+        t = _dev(t, torch.float64, device)
+        y = _dev(y, torch.float64, device)
+        sigma = _dev(sigma, torch.float64, device)
+        sums = torch.empty((n_f, 3 * self.H, 2), dtype=torch.float64, device=t.device)
+        st = torch.empty(4, dtype=torch.float64, device=t.device)
+        _check(self.lib.ftp_nfft_sums(self.handle, _ptr(t), _ptr(y), _ptr(sigma), t.numel(), float(df),
+                                      int(n_f), _ptr(sums), _ptr(st), _stream_ptr(stream)))
+        return torch.view_as_complex(sums), st
+
+    def solve_sums(self, sums, tref: float, ybar: float, yy: float, df: float, device="cuda", stream=None,
+                   out=None):
+        import numpy as np
+        torch = _torch()
+        sums = torch.as_tensor(sums, device=device)
+        if sums.is_complex():
+            sums = torch.view_as_real(sums.to(torch.complex128).contiguous())
+        sums = sums.to(torch.float64).contiguous()
+        n_f = sums.shape[0]
+        if sums.shape[1] != 3 * self.H:
+            raise ValueError("sums must have 3H columns")
+        stats = np.array([tref, ybar, yy], dtype=np.float64)
+        if out is None:
+            out = self.alloc_outputs(n_f, sums.device)
+        _check(self.lib.ftp_solve_sums(self.handle, _ptr(sums), stats.ctypes.data_as(ctypes.c_void_p),
+                                       float(df), int(n_f), _ptr(out["power"]), _ptr(out["phase"]),
+                                       _ptr(out["amp"]), _ptr(out["offset"]), _ptr(out["status"]),
+                                       _stream_ptr(stream)))
+        return out
+
+    def load_mlp(self, weights, width: int):
+        import numpy as np
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        _check(self.lib.ftp_plan_load_mlp(self.handle, w.ctypes.data_as(ctypes.c_void_p), w.size, int(width)))
+
+    def stats(self, stream=None) -> dict:
+        st = Stats()
+        _check(self.lib.ftp_last_stats(self.handle, ctypes.byref(st), _stream_ptr(stream)))
+        return {k: getattr(st, k) for k, _ in Stats._fields_}

@@ -1,0 +1,63 @@
+"""Build the gfx950 shared library ``libftp.so`` in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libftp.so")
+SOURCES = ["ftp_nfft.hip", "ftp_solve.hip", "ftp_learned.hip", "ftp_mlp.hip", "ftp_capi.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-munsafe-fp-atomics",
+    "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
+]
+
+
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs = []
+    objs = []
+    for s in srcs:
+        o = os.path.join(objdir, os.path.basename(s) + ".o")
+        objs.append(o)
+        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-fgpu-rdc", "-c", s, "-o", o]
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        if len(procs) >= jobs:
+            _wait(procs, verbose)
+            procs = []
+    _wait(procs, verbose)
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-fgpu-rdc", "--hip-link", "-shared", "-fPIC", "-o", tmp] + objs
+    _run(cmd, verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def _wait(procs, verbose):
+    for cmd, p in procs:
+        out, _ = p.communicate()
+        if verbose or p.returncode:
+            sys.stderr.write(" ".join(cmd) + "\n" + out.decode(errors="replace"))
+        if p.returncode:
+            raise RuntimeError("hipcc failed: " + " ".join(cmd))
+
+
+def _run(cmd, verbose):
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if verbose or p.returncode:
+        sys.stderr.write(" ".join(cmd) + "\n" + p.stdout.decode(errors="replace"))
+    if p.returncode:
+        raise RuntimeError("link failed")
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

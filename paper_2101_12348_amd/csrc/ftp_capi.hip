@@ -1,0 +1,672 @@
+// Host runtime and C ABI of the fast template periodogram library.
+//
+// A call runs, on the caller's stream and without host round trips:
+//   k_prep_stats -> k_prep_points (+tile histogram) -> scan -> k_bin_fill ->
+//   k_spread -> k_fft_pass (1-3 rounds) -> per-frequency solve.
+// Lightcurves are processed in chunks whose NFFT grids fit the plan's grid
+// budget; a single lightcurve is a chunk of one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ftp.h"
+#include "ftp_internal.h"
+#include "ftp_solve_common.h"
+
+namespace ftp {
+// kernels (defined in the other translation units)
+__global__ void k_prep_stats(LcInfo*, const double*, const double*, const double*);
+template <typename R>
+__global__ void k_prep_points(const LcInfo*, int64_t, const int64_t*, int64_t, const double*, const double*,
+                              const double*, PointRec<R>*, PointRec<R>*, unsigned int*);
+__global__ void k_scan_blocks(const unsigned int*, int64_t, int64_t*, int64_t*);
+__global__ void k_scan_sums(int64_t*, int64_t);
+__global__ void k_scan_add(int64_t*, int64_t, const int64_t*, const unsigned int*, int64_t*);
+template <typename R>
+__global__ void k_bin_fill(const LcInfo*, int64_t, const int64_t*, int64_t, const PointRec<R>*,
+                           const PointRec<R>*, const int64_t*, unsigned int*, int*);
+template <typename R>
+__global__ void k_spread(const LcInfo*, int64_t, const int64_t*, const PointRec<R>*, const PointRec<R>*,
+                         const int64_t*, const int*, typename Cplx<R>::T*);
+template <typename R>
+__global__ void k_fft_pass(const FftGridPass*, int64_t, const int64_t*, const typename Cplx<R>::T*,
+                           typename Cplx<R>::T*);
+template <typename R>
+__global__ void k_solve_plain(SolveArgs);
+template <typename R>
+__global__ void k_gather_sums(SolveArgs, double*);
+__global__ void k_export_stats(const LcInfo*, double*);
+}  // namespace ftp
+
+using namespace ftp;
+
+static thread_local std::string g_last_error;
+
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t _e = (expr);                                                  \
+    if (_e != hipSuccess) {                                                  \
+      g_last_error = std::string(#expr) + ": " + hipGetErrorString(_e);      \
+      return FTP_E_HIP;                                                      \
+    }                                                                        \
+  } while (0)
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  int ensure(size_t bytes) {
+    if (bytes <= cap) return FTP_OK;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      cap = 0;
+      if (e != hipSuccess) { g_last_error = hipGetErrorString(e); return FTP_E_HIP; }
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) { g_last_error = std::string("hipMalloc: ") + hipGetErrorString(e); return FTP_E_HIP; }
+    cap = want;
+    return FTP_OK;
+  }
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+  void release() { if (p) (void)hipFree(p); p = nullptr; cap = 0; }
+};
+
+int ilog2_ceil(int64_t v) {
+  int l = 0;
+  while ((1LL << l) < v) ++l;
+  return l;
+}
+
+}  // namespace
+
+struct ftp_plan {
+  int H = 0;
+  ftp_options opt{};
+  std::vector<double> c, s;
+  int device = 0;
+  int n_cu = 256;
+  size_t grid_budget = (size_t)8 << 30;   // bytes of NFFT grids per chunk
+  // device buffers
+  DevBuf alpha, twiddle32, twiddle64;
+  DevBuf lcinfo, obs_off, freq_off, grid_tile_base, pw, py, tile_count, tile_off, cursor, block_sums,
+      total, bucket, grids, fft_tab, fft_items, counters, stats_out;
+  // host staging (kept alive until the uploads completed)
+  std::vector<LcInfo> h_lc;
+  std::vector<int64_t> h_obs_off, h_freq_off, h_gtb;
+  std::vector<FftGridPass> h_fft;
+  std::vector<int64_t> h_items;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  ftp_stats last{};
+  // stage timing (FTP_FLAG_TIME_STAGES): one event triple per chunk
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  // learned
+  DevBuf mlp;
+  int mlp_width = 0;
+  bool mlp_loaded = false;
+};
+
+namespace {
+
+int validate_template(int H, const double* c, const double* s) {
+  if (!c || !s) return FTP_E_NULL;
+  if (H < 1 || H > FTP_MAX_H) return FTP_E_H;
+  bool any = false;
+  for (int i = 0; i < H; ++i) {
+    if (!std::isfinite(c[i]) || !std::isfinite(s[i])) return FTP_E_H;
+    if (c[i] != 0.0 || s[i] != 0.0) any = true;
+  }
+  return any ? FTP_OK : FTP_E_H;
+}
+
+int default_msp(int precision) { return precision == FTP_FP64 ? 12 : 7; }
+
+// FFT pass plan: passes (largest stride first) with in-LDS sizes.
+void fft_plan(int L, int precision, int* npass, int* lp) {
+  const int last = precision == FTP_FP64 ? 11 : 12;
+  const int wide = last - 4;
+  if (L <= last) { *npass = 1; lp[0] = L; return; }
+  const int rest = L - last;
+  const int npre = (rest + wide - 1) / wide;
+  int k = 0;
+  for (int p = 0; p < npre; ++p) {
+    const int take = rest / npre + (p < rest % npre ? 1 : 0);
+    lp[k++] = take;
+  }
+  lp[k++] = last;
+  *npass = k;
+}
+
+// Returns the next timing event (creating it on demand), or nullptr.
+hipEvent_t next_event(ftp_plan* P) {
+  if (!(P->opt.flags & FTP_FLAG_TIME_STAGES)) return nullptr;
+  if (P->ev_used == (int)P->ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    P->ev.push_back(e);
+  }
+  return P->ev[P->ev_used++];
+}
+
+int wait_uploads(ftp_plan* P) {
+  if (P->upload_pending) {
+    HIP_TRY(hipEventSynchronize(P->upload_done));
+    P->upload_pending = false;
+  }
+  return FTP_OK;
+}
+
+int validate_scalars(double df, int64_t n_f, int64_t n_obs) {
+  if (n_obs < 3) return FTP_E_NOBS;
+  if (!(std::isfinite(df) && df > 0.0)) return FTP_E_DF;
+  if (n_f < 1) return FTP_E_NF;
+  // grid modes 2 H n_f must fit the int64 index math and the 2^30 grid cap
+  if (n_f > (int64_t)1 << 26) return FTP_E_SIZE;
+  if (n_obs > (int64_t)1 << 29) return FTP_E_SIZE;
+  return FTP_OK;
+}
+
+struct Chunk {
+  int64_t lc0, lc1;   // [lc0, lc1)
+};
+
+// Fill LcInfo plan fields for lightcurves [lc0, lc1), return grid elements.
+int plan_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, const double* df,
+               const int64_t* freq_off, int64_t* n_grid_elems, int64_t* n_tiles) {
+  const int H = P->H;
+  const double R = P->opt.nfft_R > 0 ? P->opt.nfft_R : 2.0;
+  const int msp = P->opt.nfft_msp > 0 ? P->opt.nfft_msp : default_msp(P->opt.precision);
+  const int64_t n = lc1 - lc0;
+  P->h_lc.assign(n, LcInfo{});
+  P->h_obs_off.assign(n + 1, 0);
+  P->h_freq_off.assign(n + 1, 0);
+  P->h_gtb.assign(2 * n + 1, 0);
+  int64_t goff = 0, tbase = 0;
+  for (int64_t b = 0; b < n; ++b) {
+    LcInfo& L = P->h_lc[b];
+    const int64_t gb = lc0 + b;
+    L.obs_off = obs_off[gb] - obs_off[lc0];
+    L.n_obs = obs_off[gb + 1] - obs_off[gb];
+    L.freq_off = freq_off[gb] - freq_off[lc0];
+    L.n_f = freq_off[gb + 1] - freq_off[gb];
+    L.df = df[gb];
+    L.msp = msp;
+    P->h_obs_off[b] = L.obs_off;
+    P->h_freq_off[b] = L.freq_off;
+    for (int g = 0; g < 2; ++g) {
+      const int64_t mmax = g == 0 ? 2LL * H * L.n_f : (int64_t)H * L.n_f;
+      const int64_t M = mmax + 1;
+      int log2n = ilog2_ceil((int64_t)std::ceil(R * (double)M));
+      log2n = std::max(log2n, 12);
+      if (log2n > 30) return FTP_E_SIZE;
+      const int64_t nn = 1LL << log2n;
+      const double Reff = (double)nn / (double)M;
+      L.log2n[g] = log2n;
+      L.mc[g] = mmax / 2;
+      L.beta[g] = M_PI * (Reff - 0.5) / (msp * Reff);
+      fft_plan(log2n, P->opt.precision, &L.npass[g], L.lp[g]);
+      L.grid_off[g] = goff;
+      goff += nn;
+      L.tile_base[g] = tbase;
+      P->h_gtb[2 * b + g] = tbase;
+      tbase += nn / kTileCells;
+    }
+  }
+  P->h_obs_off[n] = obs_off[lc1] - obs_off[lc0];
+  P->h_freq_off[n] = freq_off[lc1] - freq_off[lc0];
+  P->h_gtb[2 * n] = tbase;
+  *n_grid_elems = goff;
+  *n_tiles = tbase;
+  return FTP_OK;
+}
+
+template <typename R>
+int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n_tiles, const double* t,
+             const double* y, const double* sigma, hipStream_t st) {
+  using C = typename Cplx<R>::T;
+  int rc;
+  if ((rc = P->pw.ensure(sizeof(PointRec<R>) * std::max<int64_t>(n_pts, 1)))) return rc;
+  if ((rc = P->py.ensure(sizeof(PointRec<R>) * std::max<int64_t>(n_pts, 1)))) return rc;
+  if ((rc = P->tile_count.ensure(sizeof(unsigned) * n_tiles))) return rc;
+  if ((rc = P->cursor.ensure(sizeof(unsigned) * n_tiles))) return rc;
+  if ((rc = P->tile_off.ensure(sizeof(int64_t) * (n_tiles + 1)))) return rc;
+  const int64_t nsb = (n_tiles + 1023) / 1024;
+  if ((rc = P->block_sums.ensure(sizeof(int64_t) * (nsb + 1)))) return rc;
+  if ((rc = P->total.ensure(sizeof(int64_t)))) return rc;
+  if ((rc = P->bucket.ensure(sizeof(int) * std::max<int64_t>(4 * n_pts, 1)))) return rc;
+  if ((rc = P->grids.ensure(sizeof(C) * n_grid))) return rc;
+  LcInfo* dl = P->lcinfo.as<LcInfo>();
+  hipLaunchKernelGGL(k_prep_stats, dim3((unsigned)n_lc), dim3(256), 0, st, dl, t, y, sigma);
+  HIP_TRY(hipMemsetAsync(P->tile_count.p, 0, sizeof(unsigned) * n_tiles, st));
+  HIP_TRY(hipMemsetAsync(P->cursor.p, 0, sizeof(unsigned) * n_tiles, st));
+  const unsigned pblocks = (unsigned)((n_pts + 255) / 256);
+  hipLaunchKernelGGL(k_prep_points<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc,
+                     P->obs_off.as<int64_t>(), n_pts, t, y, sigma, P->pw.as<PointRec<R>>(),
+                     P->py.as<PointRec<R>>(), P->tile_count.as<unsigned>());
+  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, st, P->tile_count.as<unsigned>(),
+                     n_tiles, P->tile_off.as<int64_t>(), P->block_sums.as<int64_t>());
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, st, P->block_sums.as<int64_t>(), nsb);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, P->tile_off.as<int64_t>(), n_tiles,
+                     P->block_sums.as<int64_t>(), P->tile_count.as<unsigned>(), P->total.as<int64_t>());
+  hipLaunchKernelGGL(k_bin_fill<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc, P->obs_off.as<int64_t>(),
+                     n_pts, P->pw.as<PointRec<R>>(), P->py.as<PointRec<R>>(), P->tile_off.as<int64_t>(),
+                     P->cursor.as<unsigned>(), P->bucket.as<int>());
+  hipLaunchKernelGGL(k_spread<R>, dim3((unsigned)n_tiles), dim3(256), 0, st, dl, 2 * n_lc,
+                     P->grid_tile_base.as<int64_t>(), P->pw.as<PointRec<R>>(), P->py.as<PointRec<R>>(),
+                     P->tile_off.as<int64_t>(), P->bucket.as<int>(), P->grids.as<C>());
+  // FFT rounds
+  int max_pass = 0;
+  for (const LcInfo& L : P->h_lc) max_pass = std::max({max_pass, L.npass[0], L.npass[1]});
+  std::vector<FftGridPass>& tab = P->h_fft;
+  std::vector<int64_t>& items = P->h_items;
+  tab.clear();
+  items.clear();
+  std::vector<int64_t> round_tab_off, round_n, round_items;
+  for (int r = 0; r < max_pass; ++r) {
+    round_tab_off.push_back((int64_t)tab.size());
+    int64_t it = 0;
+    int64_t cnt = 0;
+    for (const LcInfo& L : P->h_lc) {
+      for (int g = 0; g < 2; ++g) {
+        if (L.npass[g] <= r) continue;
+        FftGridPass fp{};
+        fp.grid_off = L.grid_off[g];
+        fp.item_begin = it;
+        fp.log2n = L.log2n[g];
+        fp.lp = L.lp[g][r];
+        int consumed = 0;
+        for (int q = 0; q <= r; ++q) consumed += L.lp[g][q];
+        fp.ls = fp.log2n - consumed;
+        const int maxel = P->opt.precision == FTP_FP64 ? 11 : 12;
+        fp.lcols = std::min(fp.ls, std::min(4, maxel - fp.lp));
+        tab.push_back(fp);
+        it += 1LL << (fp.log2n - fp.lp - fp.lcols);
+        ++cnt;
+      }
+    }
+    round_n.push_back(cnt);
+    round_items.push_back(it);
+  }
+  // item_begin arrays per round, laid out after each other (with sentinel)
+  for (int r = 0; r < max_pass; ++r) {
+    for (int64_t q = 0; q < round_n[r]; ++q) items.push_back(tab[round_tab_off[r] + q].item_begin);
+    items.push_back(round_items[r]);
+  }
+  if ((rc = P->fft_tab.ensure(sizeof(FftGridPass) * std::max<size_t>(tab.size(), 1)))) return rc;
+  if ((rc = P->fft_items.ensure(sizeof(int64_t) * std::max<size_t>(items.size(), 1)))) return rc;
+  HIP_TRY(hipMemcpyAsync(P->fft_tab.p, tab.data(), sizeof(FftGridPass) * tab.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->fft_items.p, items.data(), sizeof(int64_t) * items.size(), hipMemcpyHostToDevice,
+                         st));
+  const C* tw = reinterpret_cast<const C*>(P->opt.precision == FTP_FP64 ? P->twiddle64.p : P->twiddle32.p);
+  int64_t item_base = 0;
+  for (int r = 0; r < max_pass; ++r) {
+    hipLaunchKernelGGL(k_fft_pass<R>, dim3((unsigned)round_items[r]), dim3(256), 32768, st,
+                       P->fft_tab.as<FftGridPass>() + round_tab_off[r], round_n[r],
+                       P->fft_items.as<int64_t>() + item_base, tw, P->grids.as<C>());
+    item_base += round_n[r] + 1;
+  }
+  HIP_TRY(hipGetLastError());
+  return FTP_OK;
+}
+
+int upload_tables(ftp_plan* P, int64_t n_lc, hipStream_t st) {
+  int rc;
+  if ((rc = P->lcinfo.ensure(sizeof(LcInfo) * n_lc))) return rc;
+  if ((rc = P->obs_off.ensure(sizeof(int64_t) * (n_lc + 1)))) return rc;
+  if ((rc = P->freq_off.ensure(sizeof(int64_t) * (n_lc + 1)))) return rc;
+  if ((rc = P->grid_tile_base.ensure(sizeof(int64_t) * (2 * n_lc + 1)))) return rc;
+  HIP_TRY(hipMemcpyAsync(P->lcinfo.p, P->h_lc.data(), sizeof(LcInfo) * n_lc, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->obs_off.p, P->h_obs_off.data(), sizeof(int64_t) * (n_lc + 1),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->freq_off.p, P->h_freq_off.data(), sizeof(int64_t) * (n_lc + 1),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->grid_tile_base.p, P->h_gtb.data(), sizeof(int64_t) * (2 * n_lc + 1),
+                         hipMemcpyHostToDevice, st));
+  return FTP_OK;
+}
+
+int solve_grid_waves(ftp_plan* P) {
+  if (P->opt.solve_waves > 0) return P->opt.solve_waves;
+  return P->n_cu * 16;
+}
+
+template <typename R>
+int launch_solve(ftp_plan* P, SolveArgs a, int64_t n_pairs, hipStream_t st) {
+  const size_t lds = solve_lds_bytes(P->H);
+  if (lds > 65536) {
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_plain<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
+  const int64_t waves = std::min<int64_t>(n_pairs, solve_grid_waves(P));
+  if (waves <= 0) return FTP_OK;
+  hipLaunchKernelGGL(k_solve_plain<R>, dim3((unsigned)waves), dim3(64), lds, st, a);
+  HIP_TRY(hipGetLastError());
+  return FTP_OK;
+}
+
+SolveArgs base_args(ftp_plan* P, int64_t n_lc, int64_t n_pairs) {
+  SolveArgs a{};
+  a.lcs = P->lcinfo.as<LcInfo>();
+  a.n_lc = n_lc;
+  a.freq_off = P->freq_off.as<int64_t>();
+  a.total = n_pairs;
+  a.grids = P->grids.p;
+  a.alpha = P->alpha.as<double2>();
+  a.H = P->H;
+  a.flags = (int)P->opt.flags;
+  a.mm_tau = P->opt.precision == FTP_FP64 ? 1e-9 : 1e-5;
+  a.counters = P->counters.as<SolveCounters>();
+  return a;
+}
+
+template <typename R>
+int run_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, const double* df,
+              const int64_t* freq_off, const double* t, const double* y, const double* sigma, double* power,
+              double* phase, double* amp, double* offset, uint8_t* status, double* sums_out, hipStream_t st) {
+  int rc;
+  if ((rc = wait_uploads(P))) return rc;
+  int64_t n_grid = 0, n_tiles = 0;
+  if ((rc = plan_chunk(P, lc0, lc1, obs_off, df, freq_off, &n_grid, &n_tiles))) return rc;
+  const int64_t n_lc = lc1 - lc0;
+  if ((rc = upload_tables(P, n_lc, st))) return rc;
+  const int64_t o0 = obs_off[lc0], n_pts = obs_off[lc1] - o0;
+  const int64_t f0 = freq_off[lc0], n_pairs = freq_off[lc1] - f0;
+  hipEvent_t e0 = next_event(P);
+  if (e0) HIP_TRY(hipEventRecord(e0, st));
+  if ((rc = run_nfft<R>(P, n_lc, n_pts, n_grid, n_tiles, t + o0, y + o0, sigma + o0, st))) return rc;
+  hipEvent_t e1 = next_event(P);
+  if (e1) HIP_TRY(hipEventRecord(e1, st));
+  SolveArgs a = base_args(P, n_lc, n_pairs);
+  if (sums_out) {
+    const int64_t blocks = std::min<int64_t>(n_pairs, 65536);
+    hipLaunchKernelGGL(k_gather_sums<R>, dim3((unsigned)blocks), dim3(64), 0, st, a, sums_out);
+    HIP_TRY(hipGetLastError());
+  } else {
+    a.power = power + f0;
+    a.phase = phase + f0;
+    a.amp = amp + f0;
+    a.offset = offset + f0;
+    a.status = status ? status + f0 : nullptr;
+    if ((rc = launch_solve<R>(P, a, n_pairs, st))) return rc;
+  }
+  hipEvent_t e2 = next_event(P);
+  if (e2) HIP_TRY(hipEventRecord(e2, st));
+  HIP_TRY(hipEventRecord(P->upload_done, st));
+  P->upload_pending = true;
+  return FTP_OK;
+}
+
+int run_batch(ftp_plan* P, int64_t n_lc, const int64_t* obs_off, const double* t, const double* y,
+              const double* sigma, const double* df, const int64_t* freq_off, double* power, double* phase,
+              double* amp, double* offset, uint8_t* status, double* sums_out, hipStream_t st) {
+  int rc;
+  // chunk by grid memory
+  const size_t esz = P->opt.precision == FTP_FP64 ? 16 : 8;
+  int64_t lc0 = 0;
+  const double R = P->opt.nfft_R > 0 ? P->opt.nfft_R : 2.0;
+  while (lc0 < n_lc) {
+    int64_t lc1 = lc0;
+    size_t bytes = 0;
+    while (lc1 < n_lc) {
+      const int64_t nf = freq_off[lc1 + 1] - freq_off[lc1];
+      size_t b = 0;
+      for (int g = 0; g < 2; ++g) {
+        const int64_t M = (g == 0 ? 2LL * P->H * nf : (int64_t)P->H * nf) + 1;
+        b += ((size_t)1 << std::max(12, ilog2_ceil((int64_t)std::ceil(R * (double)M)))) * esz;
+      }
+      if (lc1 > lc0 && bytes + b > P->grid_budget) break;
+      bytes += b;
+      ++lc1;
+    }
+    if (P->opt.precision == FTP_FP64)
+      rc = run_chunk<double>(P, lc0, lc1, obs_off, df, freq_off, t, y, sigma, power, phase, amp, offset, status,
+                             sums_out, st);
+    else
+      rc = run_chunk<float>(P, lc0, lc1, obs_off, df, freq_off, t, y, sigma, power, phase, amp, offset, status,
+                            sums_out, st);
+    if (rc) return rc;
+    lc0 = lc1;
+  }
+  P->last.n_pairs += (uint64_t)freq_off[n_lc];
+  return FTP_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int ftp_options_default(ftp_options* opt) {
+  if (!opt) return FTP_E_NULL;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->precision = FTP_FP32_SUMS;
+  opt->solver = FTP_SOLVER_PLAIN;
+  opt->nfft_R = 2.0;
+  opt->nfft_msp = 0;
+  opt->solve_waves = 0;
+  opt->flags = 0;
+  return FTP_OK;
+}
+
+int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, const ftp_options* opt) {
+  if (!out) return FTP_E_NULL;
+  *out = nullptr;
+  int rc = validate_template(H, c, s);
+  if (rc) return rc;
+  ftp_options o;
+  if (opt) o = *opt; else ftp_options_default(&o);
+  if (o.precision != FTP_FP32_SUMS && o.precision != FTP_FP64) return FTP_E_OPTION;
+  if (o.solver < FTP_SOLVER_PLAIN || o.solver > FTP_SOLVER_UNIFORM) return FTP_E_OPTION;
+  if (o.nfft_R != 0.0 && !(o.nfft_R >= 1.5 && o.nfft_R <= 16.0)) return FTP_E_OPTION;
+  if (o.nfft_msp < 0 || o.nfft_msp > 24) return FTP_E_OPTION;
+  if (o.solve_waves < 0) return FTP_E_OPTION;
+  ftp_plan* P = new ftp_plan();
+  P->H = H;
+  P->opt = o;
+  P->c.assign(c, c + H);
+  P->s.assign(s, s + H);
+  hipError_t e = hipGetDevice(&P->device);
+  if (e == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) P->n_cu = prop.multiProcessorCount;
+  }
+  if (e != hipSuccess) { g_last_error = hipGetErrorString(e); delete P; return FTP_E_HIP; }
+  std::vector<double2> al(H);
+  for (int n = 0; n < H; ++n) al[n] = make_double2(0.5 * c[n], 0.5 * s[n]);
+  std::vector<float2> tw32(kTwiddleN);
+  std::vector<double2> tw64(kTwiddleN);
+  for (int k = 0; k < kTwiddleN; ++k) {
+    const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)kTwiddleN;
+    tw64[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+    tw32[k] = make_float2((float)tw64[k].x, (float)tw64[k].y);
+  }
+  if ((rc = P->alpha.ensure(sizeof(double2) * H)) || (rc = P->twiddle32.ensure(sizeof(float2) * kTwiddleN)) ||
+      (rc = P->twiddle64.ensure(sizeof(double2) * kTwiddleN)) || (rc = P->counters.ensure(sizeof(SolveCounters)))) {
+    delete P;
+    return rc;
+  }
+  if (hipMemcpy(P->alpha.p, al.data(), sizeof(double2) * H, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P->twiddle32.p, tw32.data(), sizeof(float2) * kTwiddleN, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P->twiddle64.p, tw64.data(), sizeof(double2) * kTwiddleN, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(P->counters.p, 0, sizeof(SolveCounters)) != hipSuccess ||
+      hipEventCreateWithFlags(&P->upload_done, hipEventDisableTiming) != hipSuccess) {
+    g_last_error = "plan setup copy failed";
+    delete P;
+    return FTP_E_HIP;
+  }
+  *out = P;
+  return FTP_OK;
+}
+
+int ftp_plan_destroy(ftp_plan* P) {
+  if (!P) return FTP_E_NULL;
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&P->alpha, &P->twiddle32, &P->twiddle64, &P->lcinfo, &P->obs_off, &P->freq_off,
+                    &P->grid_tile_base, &P->pw, &P->py, &P->tile_count, &P->tile_off, &P->cursor,
+                    &P->block_sums, &P->total, &P->bucket, &P->grids, &P->fft_tab, &P->fft_items,
+                    &P->counters, &P->stats_out, &P->mlp};
+  for (DevBuf* b : bufs) b->release();
+  if (P->upload_done) (void)hipEventDestroy(P->upload_done);
+  for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  delete P;
+  return FTP_OK;
+}
+
+int ftp_periodogram(ftp_plan* P, const double* t, const double* y, const double* sigma, int64_t n_obs,
+                    double df, int64_t n_f, double* power, double* phase, double* amp, double* offset,
+                    uint8_t* status, void* stream) {
+  if (!P || !t || !y || !sigma || !power || !phase || !amp || !offset) return FTP_E_NULL;
+  int rc = validate_scalars(df, n_f, n_obs);
+  if (rc) return rc;
+  const int64_t obs_off[2] = {0, n_obs};
+  const int64_t freq_off[2] = {0, n_f};
+  return run_batch(P, 1, obs_off, t, y, sigma, &df, freq_off, power, phase, amp, offset, status, nullptr,
+                   (hipStream_t)stream);
+}
+
+int ftp_periodogram_batch(ftp_plan* P, int64_t n_lc, const int64_t* obs_off, const double* t, const double* y,
+                          const double* sigma, const double* df, const int64_t* freq_off, double* power,
+                          double* phase, double* amp, double* offset, uint8_t* status, void* stream) {
+  if (!P || !obs_off || !t || !y || !sigma || !df || !freq_off || !power || !phase || !amp || !offset)
+    return FTP_E_NULL;
+  if (n_lc < 1) return FTP_E_OFFSETS;
+  if (obs_off[0] != 0 || freq_off[0] != 0) return FTP_E_OFFSETS;
+  for (int64_t b = 0; b < n_lc; ++b) {
+    if (obs_off[b + 1] < obs_off[b] || freq_off[b + 1] < freq_off[b]) return FTP_E_OFFSETS;
+    int rc = validate_scalars(df[b], freq_off[b + 1] - freq_off[b], obs_off[b + 1] - obs_off[b]);
+    if (rc) return rc;
+  }
+  if (obs_off[n_lc] > ((int64_t)1 << 30)) return FTP_E_SIZE;
+  return run_batch(P, n_lc, obs_off, t, y, sigma, df, freq_off, power, phase, amp, offset, status, nullptr,
+                   (hipStream_t)stream);
+}
+
+int ftp_nfft_sums(ftp_plan* P, const double* t, const double* y, const double* sigma, int64_t n_obs, double df,
+                  int64_t n_f, double* sums, double* lc_stats, void* stream) {
+  if (!P || !t || !y || !sigma || !sums || !lc_stats) return FTP_E_NULL;
+  int rc = validate_scalars(df, n_f, n_obs);
+  if (rc) return rc;
+  const int64_t obs_off[2] = {0, n_obs};
+  const int64_t freq_off[2] = {0, n_f};
+  rc = run_batch(P, 1, obs_off, t, y, sigma, &df, freq_off, nullptr, nullptr, nullptr, nullptr, nullptr, sums,
+                 (hipStream_t)stream);
+  if (rc) return rc;
+  // lc_stats: tref, ybar, yy, status bits
+  hipLaunchKernelGGL(k_export_stats, dim3(1), dim3(64), 0, (hipStream_t)stream, P->lcinfo.as<LcInfo>(), lc_stats);
+  HIP_TRY(hipGetLastError());
+  return FTP_OK;
+}
+
+int ftp_solve_sums(ftp_plan* P, const double* sums, const double* lc_stats, double df, int64_t n_f, double* power,
+                   double* phase, double* amp, double* offset, uint8_t* status, void* stream) {
+  if (!P || !sums || !lc_stats || !power || !phase || !amp || !offset) return FTP_E_NULL;
+  if (!(std::isfinite(df) && df > 0.0)) return FTP_E_DF;
+  if (n_f < 1) return FTP_E_NF;
+  if (!(lc_stats[2] > 0.0) || !std::isfinite(lc_stats[0]) || !std::isfinite(lc_stats[1])) return FTP_E_OPTION;
+  int rc;
+  if ((rc = wait_uploads(P))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  P->h_lc.assign(1, LcInfo{});
+  LcInfo& L = P->h_lc[0];
+  L.n_f = n_f;
+  L.df = df;
+  L.tref = lc_stats[0];
+  L.ybar = lc_stats[1];
+  L.yy = lc_stats[2];
+  L.inv_sqrt_yy = 1.0 / std::sqrt(lc_stats[2]);
+  P->h_obs_off.assign(2, 0);
+  P->h_freq_off = {0, n_f};
+  P->h_gtb.assign(3, 0);
+  if ((rc = upload_tables(P, 1, st))) return rc;
+  SolveArgs a = base_args(P, 1, n_f);
+  a.sums_in = sums;
+  a.mm_tau = 1e-14;
+  a.power = power;
+  a.phase = phase;
+  a.amp = amp;
+  a.offset = offset;
+  a.status = status;
+  rc = P->opt.precision == FTP_FP64 ? launch_solve<double>(P, a, n_f, st) : launch_solve<float>(P, a, n_f, st);
+  if (rc) return rc;
+  HIP_TRY(hipEventRecord(P->upload_done, st));
+  P->upload_pending = true;
+  P->last.n_pairs += (uint64_t)n_f;
+  return FTP_OK;
+}
+
+int ftp_plan_load_mlp(ftp_plan* P, const float* weights, int64_t n_floats, int width) {
+  if (!P || !weights) return FTP_E_NULL;
+  const int64_t din = 2 * (6 * P->H - 1), dout = 4 * P->H;
+  if (width < 16 || width > 1024 || width % 16) return FTP_E_SIZE;
+  const int64_t need = din * width + width + 2 * (width * width + width) + dout * width + dout;
+  if (n_floats != need) return FTP_E_SIZE;
+  int rc = P->mlp.ensure(sizeof(float) * need);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(P->mlp.p, weights, sizeof(float) * need, hipMemcpyHostToDevice));
+  P->mlp_width = width;
+  P->mlp_loaded = true;
+  return FTP_OK;
+}
+
+int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
+  if (!P || !out) return FTP_E_NULL;
+  SolveCounters c{};
+  HIP_TRY(hipMemcpyAsync(&c, P->counters.p, sizeof(c), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  *out = P->last;
+  out->ms_nfft = 0.0;
+  out->ms_solve = 0.0;
+  for (int k = 0; k + 3 <= P->ev_used; k += 3) {
+    float a = 0.f, b = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, P->ev[k], P->ev[k + 1]));
+    HIP_TRY(hipEventElapsedTime(&b, P->ev[k + 1], P->ev[k + 2]));
+    out->ms_nfft += a;
+    out->ms_solve += b;
+  }
+  out->n_fallback = c.fallback;
+  out->qr_sweeps = c.qr_sweeps;
+  out->newton_iters = c.newton_iters;
+  out->roots_found = c.roots_found;
+  // reset the accumulation window
+  P->ev_used = 0;
+  P->last = ftp_stats{};
+  HIP_TRY(hipMemsetAsync(P->counters.p, 0, sizeof(SolveCounters), (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return FTP_OK;
+}
+
+const char* ftp_status_string(int code) {
+  switch (code) {
+    case FTP_OK: return "ok";
+    case FTP_E_NULL: return "a required pointer is NULL";
+    case FTP_E_H: return "invalid template (H out of range, non-finite or all-zero coefficients)";
+    case FTP_E_NOBS: return "fewer than 3 observations";
+    case FTP_E_DF: return "df must be positive and finite";
+    case FTP_E_NF: return "n_f must be at least 1";
+    case FTP_E_OFFSETS: return "offsets must start at 0 and be non-decreasing";
+    case FTP_E_SIZE: return "size exceeds library limits";
+    case FTP_E_HIP: return "HIP runtime error";
+    case FTP_E_OPTION: return "invalid option";
+    case FTP_E_NO_MODEL: return "learned solver requested but no network is loaded";
+    case FTP_ST_DEGENERATE: return "degenerate frequency (MM ~ 0)";
+    case FTP_ST_CONSTANT: return "phase polynomial vanishes (P constant in phase)";
+    case FTP_ST_NO_CONVERGE: return "companion QR did not converge";
+    case FTP_ST_BAD_LC: return "lightcurve rejected (NaN/Inf, sigma < 0, mixed zero sigma or Var(y) = 0)";
+    case FTP_ST_FALLBACK: return "learned proposal fell back to the companion solve";
+    default: return "unknown code";
+  }
+}
+
+const char* ftp_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

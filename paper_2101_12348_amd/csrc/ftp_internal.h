@@ -1,0 +1,76 @@
+// Internal definitions shared by the HIP kernels and the host runtime of the
+// fast template periodogram library (gfx950).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ftp {
+
+constexpr int kMaxH = 16;             // D = 6H - 2 <= 94
+constexpr int kTileCells = 2048;      // spreading tile (cells per workgroup)
+constexpr int kFixedShift = 60;       // fixed-point scale 2^60 for exact accumulation
+constexpr int kMaxPasses = 4;
+constexpr int kTwiddleN = 4096;       // size of the in-LDS twiddle table (w_4096^r)
+
+// Per-lightcurve record.  The host fills the plan part; k_prep_stats fills the
+// statistics part on the device.
+struct LcInfo {
+  int64_t obs_off, n_obs;
+  int64_t freq_off, n_f;
+  double df;
+  int64_t grid_off[2];     // element offset of the w grid (0) and y grid (1)
+  int64_t tile_base[2];    // first global tile index of each grid
+  int64_t mc[2];           // centre mode of each grid
+  double beta[2];          // Gaussian exponent per cell^2 of each grid
+  int log2n[2];
+  int npass[2];
+  int lp[2][kMaxPasses];   // log2 sizes of the FFT passes (largest stride first)
+  int msp;                 // kernel half-width in cells
+  int pad0;
+  // filled on the device
+  double tref, ybar, yy, inv_sqrt_yy, winv;
+  int wmode;               // 0: sigma^-2 weights, 1: uniform (all sigma = 0)
+  int status;              // FTP_LC_* bits
+};
+
+// Per-lightcurve status bits (device side).
+enum : int {
+  LC_BAD_INPUT = 1,        // NaN/Inf in t, y or sigma, or sigma < 0
+  LC_MIXED_SIGMA = 2,      // some sigma = 0 and some > 0
+  LC_ZERO_VAR = 4,         // weighted variance of y is zero
+};
+
+// Per-frequency status codes written to the caller's status array.
+enum : uint8_t {
+  ST_OK = 0,
+  ST_DEGENERATE = 1,       // MM ~ 0 at every candidate: P = 0
+  ST_CONSTANT = 2,         // p == 0: P independent of phase; theta_2 = 0 scored
+  ST_NO_CONVERGE = 3,      // QR iteration limit hit (best of what was found)
+  ST_BAD_LC = 4,           // the lightcurve's input was rejected
+  ST_FALLBACK = 8,         // learned proposal fell back to the companion solve (bit)
+};
+
+template <typename R> struct PointRec;
+template <> struct PointRec<float> { int cell; float frac; float2 g; };
+template <> struct PointRec<double> { int cell; int pad; double frac; double2 g; };
+
+template <typename R> struct Cplx;
+template <> struct Cplx<float> { using T = float2; };
+template <> struct Cplx<double> { using T = double2; };
+
+// FFT work description for one pass of one grid.
+struct FftGridPass {
+  int64_t grid_off;        // element offset of the grid
+  int64_t item_begin;      // first work item of this grid in the launch
+  int log2n, lp, ls, lcols;  // log2 of size, pass size, stride, columns per item
+};
+
+struct SolveCounters {
+  unsigned long long fallback;   // frequencies sent to the companion solve
+  unsigned long long newton_iters;
+  unsigned long long roots_found;
+  unsigned long long qr_sweeps;
+};
+
+}  // namespace ftp

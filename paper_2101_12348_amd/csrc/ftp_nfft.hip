@@ -1,0 +1,486 @@
+// NFFT stage of the fast template periodogram on gfx950.
+//
+// The trig sums Z_g(m) = sum_i g_i exp(2 pi i m df (t_i - t_ref)) the method
+// needs (Section 2: "all of which can be evaluated efficiently using the
+// NFFT", Eqs. CCdef-YSdef; the harmonics up to 2H follow from the
+// product-to-sum identities) are evaluated by Gaussian gridding
+// (Dutt & Rokhlin 1993; Greengard & Lee 2004):
+//   prep     : weights, weighted mean, chi^2_0 and t_ref per lightcurve; per
+//              point the grid cell, fractional offset and complex strength
+//              (weights modulated by exp(2 pi i m_c x) to centre the needed
+//              modes), plus a tile histogram;
+//   bin      : points are bucketed by spreading tile (order inside a bucket
+//              is irrelevant, see below);
+//   spread   : one workgroup per tile accumulates Gaussian contributions in
+//              LDS as 2^60 fixed-point integers.  Integer addition is
+//              associative, so the grid is bit-for-bit independent of the
+//              order in which points arrive and no global atomics touch it;
+//   fft      : multi-pass in-place FFT, each pass an LDS-resident radix-2
+//              transform over strided columns; the output stays in mixed-radix
+//              digit-reversed order, which the gather undoes by index math.
+#include "ftp_internal.h"
+
+namespace ftp {
+
+// ------------------------------------------------------------ helpers
+
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
+  p = a * b;
+  e = fma(a, b, -p);
+}
+
+// Reduce a double-double value to [-0.5, 0.5) and return (hi, lo).
+__device__ __forceinline__ void dd_wrap_half(double& hi, double& lo) {
+  double r = rint(hi);
+  double h, l;
+  two_sum(hi - r, lo, h, l);
+  if (h >= 0.5) { h -= 1.0; }
+  else if (h < -0.5) { h += 1.0; }
+  hi = h; lo = l;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh) {
+  // 256-thread block reduction (4 waves)
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  T r = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_min(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = fmin(fmin(sh[0], sh[1]), fmin(sh[2], sh[3]));
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int64_t find_segment(const int64_t* off, int64_t n, int64_t x) {
+  // largest s in [0, n) with off[s] <= x
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------ prep
+
+// One 256-thread workgroup per lightcurve: weights (Section 1: w ~ sigma^-2,
+// sum w = 1; all sigma = 0 -> uniform), ybar, YY = chi^2_0, t_ref.
+__global__ __launch_bounds__(256) void k_prep_stats(LcInfo* lcs, const double* __restrict__ t,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ sigma) {
+  __shared__ double shd[4];
+  __shared__ int shi[4];
+  LcInfo& L = lcs[blockIdx.x];
+  const int64_t b = L.obs_off, n = L.n_obs;
+  double sinv = 0.0, tmin = INFINITY, tmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+  int nzero = 0, bad = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    double ti = t[b + i], yi = y[b + i], si = sigma[b + i];
+    if (!isfinite(ti) || !isfinite(yi) || !isfinite(si) || si < 0.0) bad = 1;
+    if (si == 0.0) nzero++;
+    else sinv += 1.0 / (si * si);
+    tmin = fmin(tmin, ti);
+    tmax = fmax(tmax, ti);
+    ymin = fmin(ymin, yi);
+    ymax = fmax(ymax, yi);
+  }
+  sinv = block_sum(sinv, shd);
+  tmin = block_min(tmin, shd);
+  tmax = -block_min(-tmax, shd);
+  ymin = block_min(ymin, shd);
+  ymax = -block_min(-ymax, shd);
+  nzero = block_sum(nzero, shi);
+  bad = block_sum(bad, shi);
+  int status = 0;
+  int wmode = 0;
+  double winv = 0.0;
+  if (bad) status |= LC_BAD_INPUT;
+  if (nzero == n) { wmode = 1; winv = 1.0 / (double)n; }
+  else if (nzero > 0) status |= LC_MIXED_SIGMA;
+  else winv = 1.0 / sinv;
+  double sy = 0.0;
+  if (status == 0) {
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+      double si = sigma[b + i];
+      double w = (wmode ? 1.0 : 1.0 / (si * si)) * winv;
+      sy += w * y[b + i];
+    }
+  }
+  double ybar = block_sum(sy, shd);
+  double syy = 0.0;
+  if (status == 0) {
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+      double si = sigma[b + i];
+      double w = (wmode ? 1.0 : 1.0 / (si * si)) * winv;
+      double d = y[b + i] - ybar;
+      syy += w * d * d;
+    }
+  }
+  double yy = block_sum(syy, shd);
+  // Var(y) = 0 means every y_i is equal (rounding may leave yy slightly > 0)
+  if (status == 0 && (!(yy > 0.0 && isfinite(yy)) || ymin == ymax)) status |= LC_ZERO_VAR;
+  if (threadIdx.x == 0) {
+    L.tref = 0.5 * (tmin + tmax);
+    L.ybar = ybar;
+    L.yy = yy;
+    L.inv_sqrt_yy = (status == 0) ? 1.0 / sqrt(yy) : 0.0;
+    L.winv = winv;
+    L.wmode = wmode;
+    L.status = status;
+  }
+}
+
+__device__ __forceinline__ void tile_span(int cell, int msp, int log2n, int& t0, int& t1) {
+  const int n = 1 << log2n;
+  const int ntile = n / kTileCells;
+  int lo = cell - msp + 1;
+  int hi = cell + msp;
+  lo = (lo % n + n) % n;
+  hi = (hi % n + n) % n;
+  t0 = lo / kTileCells;
+  t1 = hi / kTileCells;
+  if (t1 == t0) t1 = -1;
+  (void)ntile;
+}
+
+// Per point and grid: cell, fractional offset and modulated strength, and the
+// tile histogram (global atomic counts; the counts do not depend on order).
+template <typename R>
+__global__ __launch_bounds__(256) void k_prep_points(const LcInfo* __restrict__ lcs, int64_t n_lc,
+                                                     const int64_t* __restrict__ obs_off,
+                                                     int64_t n_total, const double* __restrict__ t,
+                                                     const double* __restrict__ y,
+                                                     const double* __restrict__ sigma,
+                                                     PointRec<R>* __restrict__ pw,
+                                                     PointRec<R>* __restrict__ py,
+                                                     unsigned int* __restrict__ tile_count) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_total) return;
+  const int64_t lc = find_segment(obs_off, n_lc, i);
+  const LcInfo& L = lcs[lc];
+  PointRec<R> recs[2];
+  if (L.status != 0) {
+    for (int g = 0; g < 2; ++g) { recs[g].cell = -1; recs[g].frac = 0; recs[g].g.x = 0; recs[g].g.y = 0; }
+    pw[i] = recs[0];
+    py[i] = recs[1];
+    return;
+  }
+  const double si = sigma[i];
+  const double w = (L.wmode ? 1.0 : 1.0 / (si * si)) * L.winv;
+  const double gval[2] = {w, w * (y[i] - L.ybar) * L.inv_sqrt_yy};
+  // x = df (t - tref) in double-double, reduced mod 1
+  double dh, dl;
+  two_sum(t[i], -L.tref, dh, dl);
+  double xh, xl;
+  two_prod(L.df, dh, xh, xl);
+  xl = fma(L.df, dl, xl);
+  dd_wrap_half(xh, xl);
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int log2n = L.log2n[g];
+    const double nn = (double)(1 << log2n);
+    double uh = xh * nn, ul = xl * nn;   // exact scaling by a power of two
+    double c = floor(uh);
+    double fr = (uh - c) + ul;
+    if (fr < 0.0) { fr += 1.0; c -= 1.0; }
+    if (fr >= 1.0) { fr -= 1.0; c += 1.0; }
+    long long ci = (long long)c;
+    const long long n = 1LL << log2n;
+    ci = ((ci % n) + n) % n;
+    // modulation phase frac(m_c x)
+    double ph, pl;
+    const double mc = (double)L.mc[g];
+    two_prod(mc, xh, ph, pl);
+    pl = fma(mc, xl, pl);
+    dd_wrap_half(ph, pl);
+    double phase = ph + pl;
+    double sn, cs;
+    sincospi(2.0 * phase, &sn, &cs);
+    recs[g].cell = (int)ci;
+    recs[g].frac = (R)fr;
+    recs[g].g.x = (R)(gval[g] * cs);
+    recs[g].g.y = (R)(gval[g] * sn);
+    int t0, t1;
+    tile_span((int)ci, L.msp, log2n, t0, t1);
+    atomicAdd(&tile_count[L.tile_base[g] + t0], 1u);
+    if (t1 >= 0) atomicAdd(&tile_count[L.tile_base[g] + t1], 1u);
+  }
+  pw[i] = recs[0];
+  py[i] = recs[1];
+}
+
+// Exclusive scan of 32-bit counts into 64-bit offsets: three kernels.
+__global__ __launch_bounds__(256) void k_scan_blocks(const unsigned int* __restrict__ in, int64_t n,
+                                                     int64_t* __restrict__ out,
+                                                     int64_t* __restrict__ block_sums) {
+  __shared__ int64_t sh[256];
+  const int64_t base = (int64_t)blockIdx.x * 1024;
+  int64_t v[4];
+  int64_t s = 0;
+  for (int k = 0; k < 4; ++k) {
+    int64_t idx = base + threadIdx.x * 4 + k;
+    v[k] = idx < n ? (int64_t)in[idx] : 0;
+    s += v[k];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    int64_t a = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += a;
+    __syncthreads();
+  }
+  int64_t run = sh[threadIdx.x] - s;
+  for (int k = 0; k < 4; ++k) {
+    int64_t idx = base + threadIdx.x * 4 + k;
+    if (idx < n) out[idx] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 255) block_sums[blockIdx.x] = sh[255];
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(int64_t* __restrict__ block_sums, int64_t nb) {
+  // single workgroup, sequential over chunks of 256
+  __shared__ int64_t sh[256];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < nb; c0 += 256) {
+    int64_t idx = c0 + threadIdx.x;
+    int64_t v = idx < nb ? block_sums[idx] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      int64_t a = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += a;
+      __syncthreads();
+    }
+    int64_t excl = sh[threadIdx.x] - v + carry;
+    __syncthreads();
+    if (idx < nb) block_sums[idx] = excl;
+    if (threadIdx.x == 255) carry += sh[255];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int64_t* __restrict__ out, int64_t n,
+                                                  const int64_t* __restrict__ block_sums,
+                                                  const unsigned int* __restrict__ in,
+                                                  int64_t* __restrict__ total) {
+  const int64_t base = (int64_t)blockIdx.x * 1024;
+  const int64_t add = block_sums[blockIdx.x];
+  for (int k = 0; k < 4; ++k) {
+    int64_t idx = base + threadIdx.x * 4 + k;
+    if (idx < n) {
+      out[idx] += add;
+      if (idx == n - 1) { out[n] = out[idx] + (int64_t)in[idx]; *total = out[n]; }
+    }
+  }
+}
+
+// Bucket fill: the slot inside a bucket comes from an atomic cursor.  The
+// spread result does not depend on this order (exact integer accumulation).
+template <typename R>
+__global__ __launch_bounds__(256) void k_bin_fill(const LcInfo* __restrict__ lcs, int64_t n_lc,
+                                                  const int64_t* __restrict__ obs_off, int64_t n_total,
+                                                  const PointRec<R>* __restrict__ pw,
+                                                  const PointRec<R>* __restrict__ py,
+                                                  const int64_t* __restrict__ tile_off,
+                                                  unsigned int* __restrict__ cursor,
+                                                  int* __restrict__ bucket) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_total) return;
+  const int64_t lc = find_segment(obs_off, n_lc, i);
+  const LcInfo& L = lcs[lc];
+  for (int g = 0; g < 2; ++g) {
+    int cell = g == 0 ? pw[i].cell : py[i].cell;
+    if (cell < 0) continue;
+    int t0, t1;
+    tile_span(cell, L.msp, L.log2n[g], t0, t1);
+    int64_t tt = L.tile_base[g] + t0;
+    unsigned int slot = atomicAdd(&cursor[tt], 1u);
+    bucket[tile_off[tt] + slot] = (int)((i << 1) | g) ;
+    if (t1 >= 0) {
+      tt = L.tile_base[g] + t1;
+      slot = atomicAdd(&cursor[tt], 1u);
+      bucket[tile_off[tt] + slot] = (int)((i << 1) | g);
+    }
+  }
+}
+
+// One workgroup per tile of kTileCells cells.  Gaussian weights
+// exp(-beta (cell - u)^2) for the 2 msp cells around each point; exact
+// fixed-point accumulation in LDS; the tile is written once, coalesced.
+template <typename R>
+__global__ __launch_bounds__(256) void k_spread(const LcInfo* __restrict__ lcs, int64_t n_grids,
+                                                const int64_t* __restrict__ grid_tile_base,
+                                                const PointRec<R>* __restrict__ pw,
+                                                const PointRec<R>* __restrict__ py,
+                                                const int64_t* __restrict__ tile_off,
+                                                const int* __restrict__ bucket,
+                                                typename Cplx<R>::T* __restrict__ grids) {
+  __shared__ unsigned long long acc[2 * kTileCells];
+  const int64_t tile = blockIdx.x;
+  const int64_t gi = find_segment(grid_tile_base, n_grids, tile);
+  const int64_t lc = gi >> 1;
+  const int g = (int)(gi & 1);
+  const LcInfo& L = lcs[lc];
+  const int log2n = L.log2n[g];
+  const int n = 1 << log2n;
+  const int cell0 = (int)(tile - L.tile_base[g]) * kTileCells;
+  const int msp = L.msp;
+  const R beta = (R)L.beta[g];
+  for (int c = threadIdx.x; c < 2 * kTileCells; c += 256) acc[c] = 0ull;
+  __syncthreads();
+  const int64_t e0 = tile_off[tile], e1 = tile_off[tile + 1];
+  const int64_t work = (e1 - e0) * (2 * msp);
+  const double scale = (double)(1ull << kFixedShift);
+  for (int64_t wi = threadIdx.x; wi < work; wi += 256) {
+    const int64_t e = e0 + wi / (2 * msp);
+    const int d = (int)(wi % (2 * msp)) - msp + 1;
+    const int code = bucket[e];
+    const int64_t pi = code >> 1;
+    const PointRec<R> rec = (code & 1) ? py[pi] : pw[pi];
+    int cell = rec.cell + d;
+    cell = cell >= n ? cell - n : (cell < 0 ? cell + n : cell);
+    const int local = cell - cell0;
+    if (local < 0 || local >= kTileCells) continue;
+    const R dist = (R)d - rec.frac;
+    const R wgt = exp(-beta * dist * dist);
+    const double vr = (double)(rec.g.x * wgt) * scale;
+    const double vi = (double)(rec.g.y * wgt) * scale;
+    atomicAdd(&acc[2 * local], (unsigned long long)llrint(vr));
+    atomicAdd(&acc[2 * local + 1], (unsigned long long)llrint(vi));
+  }
+  __syncthreads();
+  typename Cplx<R>::T* out = grids + L.grid_off[g] + cell0;
+  const double inv = 1.0 / scale;
+  for (int c = threadIdx.x; c < kTileCells; c += 256) {
+    typename Cplx<R>::T v;
+    v.x = (R)((double)(long long)acc[2 * c] * inv);
+    v.y = (R)((double)(long long)acc[2 * c + 1] * inv);
+    out[c] = v;
+  }
+}
+
+// ------------------------------------------------------------ FFT pass
+
+__device__ __forceinline__ void cs_pi(float x, float& s, float& c) { sincospif(x, &s, &c); }
+__device__ __forceinline__ void cs_pi(double x, double& s, double& c) { sincospi(x, &s, &c); }
+
+// One pass: for each block b and column j0 (0 <= j0 < s = 2^ls), the np-point
+// transform Y[k] = sum_m x[b np s + j0 + s m] w_np^{m k} (w = e^{+2 pi i/.}),
+// followed by the twiddle w_{np s}^{j0 k}; Y[k] is written back in place at
+// b np s + j0 + s k.  A workgroup owns 2^lcols adjacent columns.
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_pass(const FftGridPass* __restrict__ passes, int64_t n_grids,
+                                                  const int64_t* __restrict__ item_begin,
+                                                  const typename Cplx<R>::T* __restrict__ twiddle,
+                                                  typename Cplx<R>::T* __restrict__ grids) {
+  using C = typename Cplx<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const int64_t item = blockIdx.x;
+  const int64_t gi = find_segment(item_begin, n_grids, item);
+  const FftGridPass P = passes[gi];
+  const int64_t local_item = item - P.item_begin;
+  const int lp = P.lp, ls = P.ls, lcols = P.lcols;
+  const int np = 1 << lp, cols = 1 << lcols;
+  const int64_t s = 1LL << ls;
+  const int64_t groups_per_block = s >> lcols;
+  const int64_t blk = local_item / groups_per_block;
+  const int64_t j0b = (local_item % groups_per_block) << lcols;
+  C* g = grids + P.grid_off + blk * ((int64_t)np << ls) + j0b;
+  const int total = np << lcols;
+  // load: element (m, c) -> buf[m * cols + c]
+  for (int e = threadIdx.x; e < total; e += 256) {
+    const int m = e >> lcols, c = e & (cols - 1);
+    buf[e] = g[(int64_t)m * s + c];
+  }
+  __syncthreads();
+  // in-place radix-2 decimation in frequency; output in bit-reversed order
+  const int tstride = kTwiddleN >> lp;   // w_np^r = w_4096^{r * 4096/np}
+  for (int span = np >> 1, lspan = lp - 1; span >= 1; span >>= 1, --lspan) {
+    const int nb = (np >> 1) << lcols;   // butterflies per stage
+    for (int bi = threadIdx.x; bi < nb; bi += 256) {
+      const int c = bi & (cols - 1);
+      const int q = bi >> lcols;             // 0 .. np/2-1
+      const int r = q & (span - 1);
+      const int i0 = ((q >> lspan) << (lspan + 1)) + r;
+      const int i1 = i0 + span;
+      C a = buf[i0 * cols + c], b = buf[i1 * cols + c];
+      C sum, dif;
+      sum.x = a.x + b.x; sum.y = a.y + b.y;
+      dif.x = a.x - b.x; dif.y = a.y - b.y;
+      // twiddle w_{2 span}^r = w_4096^{r * 4096/(2 span)} = w_np^{r * np/(2 span)}
+      const C w = twiddle[(r << (lp - 1 - lspan)) * tstride];
+      C tw;
+      tw.x = dif.x * w.x - dif.y * w.y;
+      tw.y = dif.x * w.y + dif.y * w.x;
+      buf[i0 * cols + c] = sum;
+      buf[i1 * cols + c] = tw;
+    }
+    __syncthreads();
+  }
+  // twiddle w_{np s}^{j0 k} and store Y[k] at b np s + j0 + s k
+  const int log2L = lp + ls;
+  for (int e = threadIdx.x; e < total; e += 256) {
+    const int k = e >> lcols, c = e & (cols - 1);
+    const int kr = (int)(__brev((unsigned)k) >> (32 - lp));
+    C v = buf[kr * cols + c];
+    if (ls > 0) {
+      const int64_t j0 = j0b + c;
+      const int64_t ex = (j0 * (int64_t)k) & ((1LL << log2L) - 1);
+      R sn, cs;
+      cs_pi((R)2.0 * (R)ex / (R)(1LL << log2L), sn, cs);
+      C o;
+      o.x = v.x * cs - v.y * sn;
+      o.y = v.x * sn + v.y * cs;
+      v = o;
+    }
+    g[(int64_t)k * s + c] = v;
+  }
+  (void)lp;
+}
+
+// Explicit instantiations.
+template __global__ void k_prep_points<float>(const LcInfo*, int64_t, const int64_t*, int64_t, const double*,
+                                              const double*, const double*, PointRec<float>*,
+                                              PointRec<float>*, unsigned int*);
+template __global__ void k_prep_points<double>(const LcInfo*, int64_t, const int64_t*, int64_t, const double*,
+                                               const double*, const double*, PointRec<double>*,
+                                               PointRec<double>*, unsigned int*);
+template __global__ void k_bin_fill<float>(const LcInfo*, int64_t, const int64_t*, int64_t,
+                                           const PointRec<float>*, const PointRec<float>*, const int64_t*,
+                                           unsigned int*, int*);
+template __global__ void k_bin_fill<double>(const LcInfo*, int64_t, const int64_t*, int64_t,
+                                            const PointRec<double>*, const PointRec<double>*,
+                                            const int64_t*, unsigned int*, int*);
+template __global__ void k_spread<float>(const LcInfo*, int64_t, const int64_t*, const PointRec<float>*,
+                                         const PointRec<float>*, const int64_t*, const int*, float2*);
+template __global__ void k_spread<double>(const LcInfo*, int64_t, const int64_t*, const PointRec<double>*,
+                                          const PointRec<double>*, const int64_t*, const int*, double2*);
+template __global__ void k_fft_pass<float>(const FftGridPass*, int64_t, const int64_t*, const float2*, float2*);
+template __global__ void k_fft_pass<double>(const FftGridPass*, int64_t, const int64_t*, const double2*,
+                                            double2*);
+
+}  // namespace ftp

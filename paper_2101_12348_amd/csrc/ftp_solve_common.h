@@ -1,0 +1,230 @@
+// Device-side pieces of the per-frequency stage shared by the companion
+// solve and the learned proposal: sum gather/deconvolution, polynomial
+// assembly, trig-polynomial evaluation and candidate scoring.
+#pragma once
+
+#include "ftp_internal.h"
+
+namespace ftp {
+
+struct SolveArgs {
+  const LcInfo* lcs;
+  int64_t n_lc;
+  const int64_t* freq_off;       // device, n_lc + 1 (prefix of n_f)
+  int64_t total;                 // number of work entries (pairs or list capacity)
+  const int64_t* list;           // optional pair indices (nullptr: identity)
+  const unsigned int* list_count;  // optional device count for list
+  const void* grids;             // float2 or double2 grids
+  const double* sums_in;         // optional: per pair 3H complex sums (see gather)
+  const double2* alpha;          // template alpha_n, n = 1..H
+  int H;
+  int flags;
+  double mm_tau;                 // degenerate if MM <= mm_tau * sum|alpha|^2 at every candidate
+  double* power;
+  double* phase;
+  double* amp;
+  double* offset;
+  uint8_t* status;
+  SolveCounters* counters;
+  // learned path
+  const float* seeds;            // per pair 2H seed angles (nullptr for plain)
+  int64_t* fallback_list;
+  unsigned int* fallback_count;
+  double* poly_out;              // per pair K+1 complex r_d (learned assemble)
+  uint16_t* feat_out;            // per pair bf16 features
+};
+
+constexpr double kEps = 2.220446049250313e-16;
+
+// Shared-memory size (bytes) of one wave's per-frequency working set.
+__host__ __device__ inline size_t solve_lds_bytes(int H) {
+  const int K = 3 * H - 1, D = 2 * K, n = D, ld = n + 1;
+  size_t nd = 0;
+  nd += ((size_t)n * ld + 1) & ~(size_t)1;          // Hessenberg matrix
+  nd += 2 * (((size_t)n + 1) & ~(size_t)1);         // eigenvalues (re, im)
+  nd += 2 * (3 * H + 1);                            // Z
+  nd += 2 * (2 * H + 1);                            // mu
+  nd += 2 * (H + 1);                                // eta
+  nd += 2 * (K + 1);                                // r
+  nd += 2 * 4 * (D + 1);                            // Horner buffers
+  nd += ((size_t)D + 2) & ~(size_t)1;               // f
+  nd += 2 * H;                                      // alpha
+  return nd * sizeof(double);
+}
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ int64_t find_seg(const int64_t* off, int64_t n, int64_t x) {
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Position of mode index q (0 <= q < n) in the digit-reversed FFT output.
+__device__ __forceinline__ int64_t fft_pos(int64_t q, const LcInfo& L, int g) {
+  int64_t pos = 0;
+  int rem = L.log2n[g];
+  for (int p = 0; p < L.npass[g]; ++p) {
+    const int lp = L.lp[g][p];
+    rem -= lp;
+    const int64_t d = q & ((1LL << lp) - 1);
+    q >>= lp;
+    pos += d << rem;
+  }
+  return pos;
+}
+
+// Deconvolved sum Z(m) for harmonic index m on grid g (relative to t_ref;
+// the y grid carries the 1/sqrt(YY) normalisation).
+template <typename R>
+__device__ __forceinline__ double2 gather_mode(const LcInfo& L, int g, int64_t m,
+                                               const typename Cplx<R>::T* grids) {
+  const int log2n = L.log2n[g];
+  const int64_t n = 1LL << log2n;
+  const int64_t mp = m - L.mc[g];
+  const int64_t q = ((mp % n) + n) % n;
+  const typename Cplx<R>::T v = grids[L.grid_off[g] + fft_pos(q, L, g)];
+  const double beta = L.beta[g];
+  const double nn = (double)n;
+  const double fac = sqrt(beta / kPi) * exp(kPi * kPi * (double)mp * (double)mp / (nn * nn * beta));
+  return make_double2((double)v.x * fac, (double)v.y * fac);
+}
+
+// frac(j * df * tref) in double-double, returned in cycles [0, 1).
+__device__ __forceinline__ double ref_cycles(int64_t j, double df, double tref) {
+  double ah = (double)j * df;
+  double al = fma((double)j, df, -ah);
+  double ph = ah * tref;
+  double pl = fma(ah, tref, -ph) + al * tref;
+  double r = floor(ph);
+  double c = (ph - r) + pl;
+  c -= floor(c);
+  return c;
+}
+
+// Per-frequency working set in LDS.
+struct FreqWork {
+  double2* Z;    // Z[0..2H] w sums (Z[0] = 1), Z[2H+1 .. 3H] y sums (k = 1..H)
+  double2* mu;   // mu_e, e = 0..2H  (MM = sum_e mu_e psi^e, mu_{-e} = conj mu_e)
+  double2* eta;  // eta_k, k = 0..H  (YM = sum_k eta_k psi^k, eta_0 = 0)
+  double2* r;    // r_d, d = 0..K    (R(theta) = sum_d r_d psi^d, r_{-d} = conj r_d)
+  double2* al;   // alpha_n at al[n-1]
+};
+
+// Assemble mu, eta, r from the sums (all lanes of one wave participate).
+//   MM(psi) = sum_{n,m} a_n a_m conj(Z_{n+m} - Z_n Z_m) psi^{n+m}
+//           + 2 a_n conj(a_m) conj(Z_{n-m} - Z_n conj(Z_m)) psi^{n-m} + c.c.
+// (the CC~, CS~, SS~ terms of Section 2 written with Z_k = C_k + i S_k),
+//   YM(psi) = sum_k a_k conj(Zy_k) psi^k + c.c.   (YC~_k = conj(Zy_k)),
+//   R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta = sum_d r_d psi^d,
+//   r_d = i sum_k (3k - d) mu_{d-k} eta_k   (Eq. finalpoly with p = -i psi^K R).
+__device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane) {
+  const int K = 3 * H - 1;
+  for (int e = lane; e <= 2 * H; e += 64) {
+    double2 acc = make_double2(0.0, 0.0);
+    if (e == 0) {
+      double s = 0.0;
+      for (int n = 1; n <= H; ++n) s += cabs2(W.al[n - 1]) * (1.0 - cabs2(W.Z[n]));
+      acc.x = 2.0 * s;
+    } else {
+      const int nlo = e - H > 1 ? e - H : 1;
+      const int nhi = e - 1 < H ? e - 1 : H;
+      for (int n = nlo; n <= nhi; ++n) {
+        const int m = e - n;
+        double2 t = csub(W.Z[e], cmul(W.Z[n], W.Z[m]));
+        acc = cadd(acc, cmul(cmul(W.al[n - 1], W.al[m - 1]), cconj(t)));
+      }
+      for (int n = e + 1; n <= H; ++n) {
+        const int m = n - e;
+        double2 t = csub(W.Z[e], cmul(W.Z[n], cconj(W.Z[m])));
+        acc = cadd(acc, cscale(cmul(cmul(W.al[n - 1], cconj(W.al[m - 1])), cconj(t)), 2.0));
+      }
+    }
+    W.mu[e] = acc;
+  }
+  for (int k = lane; k <= H; k += 64) {
+    W.eta[k] = k == 0 ? make_double2(0.0, 0.0) : cmul(W.al[k - 1], cconj(W.Z[2 * H + k]));
+  }
+  __syncthreads();
+  for (int d = lane; d <= K; d += 64) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k = -H; k <= H; ++k) {
+      if (k == 0) continue;
+      const int e = d - k;
+      if (e > 2 * H || e < -2 * H) continue;
+      const double2 me = e >= 0 ? W.mu[e] : cconj(W.mu[-e]);
+      const double2 ek = k > 0 ? W.eta[k] : cconj(W.eta[-k]);
+      acc = cadd(acc, cscale(cmul(me, ek), (double)(3 * k - d)));
+    }
+    W.r[d] = make_double2(-acc.y, acc.x);  // multiply by i
+  }
+  __syncthreads();
+}
+
+// Candidate evaluation at relative phase theta: returns P (normalised,
+// YY = 1), YM, MM and Mbar.
+struct Cand { double P, YM, MM, Mbar; };
+
+__device__ __forceinline__ Cand eval_candidate(const FreqWork& W, int H, double theta) {
+  double sn, cs;
+  sincos(theta, &sn, &cs);
+  const double2 e1 = make_double2(cs, sn);
+  double2 pw = e1;
+  double YM = 0.0, MM = W.mu[0].x, Mb = 0.0;
+  for (int k = 1; k <= 2 * H; ++k) {
+    MM += 2.0 * (W.mu[k].x * pw.x - W.mu[k].y * pw.y);
+    if (k <= H) {
+      YM += 2.0 * (W.eta[k].x * pw.x - W.eta[k].y * pw.y);
+      const double2 t = cmul(cmul(W.al[k - 1], pw), cconj(W.Z[k]));
+      Mb += 2.0 * t.x;
+    }
+    pw = cmul(pw, e1);
+  }
+  Cand c;
+  c.YM = YM;
+  c.MM = MM;
+  c.Mbar = Mb;
+  c.P = MM > 0.0 ? YM * YM / MM : 0.0;
+  return c;
+}
+
+// R(theta) and dR/dtheta from r_d.
+__device__ __forceinline__ void eval_R(const FreqWork& W, int H, double theta, double& R, double& dR) {
+  const int K = 3 * H - 1;
+  double sn, cs;
+  sincos(theta, &sn, &cs);
+  const double2 e1 = make_double2(cs, sn);
+  double2 pw = e1;
+  R = W.r[0].x;
+  dR = 0.0;
+  for (int d = 1; d <= K; ++d) {
+    const double re = W.r[d].x * pw.x - W.r[d].y * pw.y;
+    const double im = W.r[d].x * pw.y + W.r[d].y * pw.x;
+    R += 2.0 * re;
+    dR += -2.0 * d * im;
+    pw = cmul(pw, e1);
+  }
+}
+
+}  // namespace ftp

@@ -1,0 +1,78 @@
+"""CPU-side checks of the C ABI: the shared library loads and exports every
+function declared in include/ftp.h (no compute calls without a GPU), and the
+header's constants match the Python binding."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ftp.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ftp_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2101_12348_amd as F
+    lib = F.load_library()
+    names = _declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(F.EXPORTED)
+
+
+def test_header_constants_match_binding():
+    import paper_2101_12348_amd as F
+    src = open(HEADER).read()
+    consts = dict(re.findall(r"#define (FTP_[A-Z0-9_]+) (-?\d+)u?", src))
+    assert int(consts["FTP_FP32_SUMS"]) == F.FTP_FP32_SUMS
+    assert int(consts["FTP_FP64"]) == F.FTP_FP64
+    assert int(consts["FTP_SOLVER_LEARNED"]) == F.FTP_SOLVER_LEARNED
+    assert int(consts["FTP_ST_BAD_LC"]) == F.ST_BAD_LC
+    assert int(consts["FTP_MAX_H"]) == F.MAX_H
+
+
+def test_status_strings_and_option_defaults():
+    import ctypes
+    import paper_2101_12348_amd as F
+    lib = F.load_library()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, 1, 2, 3, 4, 8):
+        s = lib.ftp_status_string(code).decode()
+        assert s and s != "unknown code", code
+    opt = F.Options()
+    assert lib.ftp_options_default(ctypes.byref(opt)) == 0
+    assert opt.precision == F.FTP_FP32_SUMS and opt.solver == F.FTP_SOLVER_PLAIN and opt.nfft_R == 2.0
+    assert lib.ftp_options_default(None) == -1
+
+
+def test_host_validation_without_device():
+    """Argument checks that return before touching the device."""
+    import ctypes
+    import numpy as np
+    import paper_2101_12348_amd as F
+    lib = F.load_library()
+    h = ctypes.c_void_p()
+    c = np.zeros(3)
+    s = np.zeros(3)
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert lib.ftp_plan_create(None, 3, vp(c), vp(s), None) == -1
+    assert lib.ftp_plan_create(ctypes.byref(h), 3, vp(c), vp(s), None) == -2      # all zero
+    c[0] = 1.0
+    assert lib.ftp_plan_create(ctypes.byref(h), 0, vp(c), vp(s), None) == -2      # H < 1
+    assert lib.ftp_plan_create(ctypes.byref(h), 17, vp(np.ones(17)), vp(np.ones(17)), None) == -2
+    bad = np.array([np.nan, 1.0, 1.0])
+    assert lib.ftp_plan_create(ctypes.byref(h), 3, vp(bad), vp(s), None) == -2
+    opt = F.Options()
+    lib.ftp_options_default(ctypes.byref(opt))
+    opt.precision = 7
+    assert lib.ftp_plan_create(ctypes.byref(h), 3, vp(c), vp(s), ctypes.byref(opt)) == -9
+    lib.ftp_options_default(ctypes.byref(opt))
+    opt.nfft_R = 1.0
+    assert lib.ftp_plan_create(ctypes.byref(h), 3, vp(c), vp(s), ctypes.byref(opt)) == -9
+    assert lib.ftp_periodogram(None, None, None, None, 10, 0.1, 10, None, None, None, None, None, None) == -1
+    assert lib.ftp_plan_destroy(None) == -1

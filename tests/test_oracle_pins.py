@@ -243,3 +243,30 @@ def test_small_fp64_workload_peak():
     assert abs(j * lc.df - 1 / 0.7) <= lc.df
     assert r["power"][j - 1] > 0.95
     assert abs(r["amp"][j - 1] - 1.0) < 0.05
+
+
+def test_raw_sums_agree_with_covariance_means():
+    # Z_w(k) at t_ref = 0 must equal C_k + i S_k of the covariance path, and
+    # Z_y(k) must equal YC_k + i YS_k (two independent evaluations).
+    tmpl, lc = tiny_case(9, n_obs=30, H=3, n_f=6)
+    js = np.array([1, 4, 6])
+    Zw, Zy, ybar, YY = O.raw_sums(lc.t, lc.y, lc.sigma, lc.df, js, 3, 3)
+    w = O.weights(lc.sigma)
+    cov = O.covariances(lc.t, lc.y, w, ybar, js * lc.df, 3)
+    assert np.max(np.abs(Zw - (cov["C"] + 1j * cov["S"]))) < 1e-13
+    assert np.max(np.abs(Zy - (cov["YC"] + 1j * cov["YS"]))) < 1e-13
+    # shifting t_ref multiplies Z(m) by exp(2 pi i m df t_ref)
+    Zw2, _, _, _ = O.raw_sums(lc.t, lc.y, lc.sigma, lc.df, js, 3, 1, t_ref=1.7)
+    k = np.arange(1, 4)[None, :]
+    ph = np.exp(2j * np.pi * (k * js[:, None] * lc.df * 1.7))
+    assert np.max(np.abs(Zw2 * ph - Zw)) < 1e-12
+
+
+def test_direct_fit_at_phase_matches_candidate():
+    tmpl, lc = tiny_case(4, n_obs=50, H=3, n_f=12)
+    r = _run(tmpl, lc)
+    for j in (3, 8, 12):
+        P, a, b = O.direct_fit_at_phase(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, j * lc.df, r["phase"][j - 1])
+        assert abs(P - r["power"][j - 1]) < 1e-12
+        assert abs(a - r["amp"][j - 1]) < 1e-9 * max(1, abs(a))
+        assert abs(b - r["offset"][j - 1]) < 1e-9 * max(1, abs(b))
