@@ -59,7 +59,7 @@ extern "C" {
 #define FTP_ST_BAD_LC 4        /* the lightcurve was rejected (see above) */
 #define FTP_ST_FALLBACK 8      /* bit: learned proposal fell back to the companion solve */
 
-#define FTP_MAX_H 16
+#define FTP_MAX_H 11   /* D = 6H - 2 <= 64: one wavefront lane per companion row */
 
 /* precision of the NFFT stage (spreading, FFT, sums); assembly, roots and
  * scoring are always FP64 */
@@ -95,6 +95,7 @@ typedef struct {
   uint64_t roots_found;    /* distinct real roots accepted (learned path) */
   double ms_nfft;          /* device time of the NFFT stage (ms, 0 if not timed) */
   double ms_solve;         /* device time of the per-frequency stage (ms) */
+  double ms_roots;         /* of which in the root-finding kernels (ms) */
 } ftp_stats;
 
 /* Fill `opt` with the defaults.  Returns FTP_E_NULL if opt is NULL. */

@@ -21,7 +21,7 @@ FTP_SOLVER_LEARNED = 1
 FTP_SOLVER_UNIFORM = 2
 FTP_FLAG_FORCE_FALLBACK = 1
 FTP_FLAG_TIME_STAGES = 2
-MAX_H = 16
+MAX_H = 11
 
 ST_OK, ST_DEGENERATE, ST_CONSTANT, ST_NO_CONVERGE, ST_BAD_LC, ST_FALLBACK = 0, 1, 2, 3, 4, 8
 
@@ -40,7 +40,8 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("n_pairs", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64), ("qr_sweeps", ctypes.c_uint64),
                 ("newton_iters", ctypes.c_uint64), ("roots_found", ctypes.c_uint64),
-                ("ms_nfft", ctypes.c_double), ("ms_solve", ctypes.c_double)]
+                ("ms_nfft", ctypes.c_double), ("ms_solve", ctypes.c_double),
+                ("ms_roots", ctypes.c_double)]
 
 
 class FtpError(RuntimeError):

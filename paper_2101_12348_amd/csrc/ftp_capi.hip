@@ -36,11 +36,14 @@ __global__ void k_spread(const LcInfo*, int64_t, const int64_t*, const PointRec<
 template <typename R>
 __global__ void k_fft_pass(const FftGridPass*, int64_t, const int64_t*, const typename Cplx<R>::T*,
                            typename Cplx<R>::T*);
-template <typename R>
-__global__ void k_solve_plain(SolveArgs);
-template <typename R>
-__global__ void k_gather_sums(SolveArgs, double*);
-__global__ void k_export_stats(const LcInfo*, double*);
+hipError_t launch_qr(int H, double* rec, int stride, int64_t np, const int64_t* list, const unsigned* list_count,
+                     SolveCounters* counters, int waves, hipStream_t st);
+hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64_t p0, int64_t np, int waves,
+                           hipStream_t st);
+hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves,
+                        hipStream_t st);
+hipError_t launch_gather_sums(int precision, const SolveArgs& a, double* out, int blocks, hipStream_t st);
+hipError_t launch_export_stats(const LcInfo* lcs, double* out, hipStream_t st);
 }  // namespace ftp
 
 using namespace ftp;
@@ -97,7 +100,8 @@ struct ftp_plan {
   // device buffers
   DevBuf alpha, twiddle32, twiddle64;
   DevBuf lcinfo, obs_off, freq_off, grid_tile_base, pw, py, tile_count, tile_off, cursor, block_sums,
-      total, bucket, grids, fft_tab, fft_items, counters, stats_out;
+      total, bucket, grids, fft_tab, fft_items, counters, stats_out, rec;
+  int64_t pair_chunk = (int64_t)1 << 20;  // pairs per assemble/root/score round
   // host staging (kept alive until the uploads completed)
   std::vector<LcInfo> h_lc;
   std::vector<int64_t> h_obs_off, h_freq_off, h_gtb;
@@ -106,9 +110,10 @@ struct ftp_plan {
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
   ftp_stats last{};
-  // stage timing (FTP_FLAG_TIME_STAGES): one event triple per chunk
-  std::vector<hipEvent_t> ev;
-  int ev_used = 0;
+  // stage timing (FTP_FLAG_TIME_STAGES): one event triple per lightcurve chunk
+  // (NFFT start, NFFT end, solve end) and one pair per root-kernel launch
+  std::vector<hipEvent_t> ev, evr;
+  int ev_used = 0, evr_used = 0;
   // learned
   DevBuf mlp;
   int mlp_width = 0;
@@ -147,15 +152,17 @@ void fft_plan(int L, int precision, int* npass, int* lp) {
 }
 
 // Returns the next timing event (creating it on demand), or nullptr.
-hipEvent_t next_event(ftp_plan* P) {
+hipEvent_t next_event_in(ftp_plan* P, std::vector<hipEvent_t>& pool, int& used) {
   if (!(P->opt.flags & FTP_FLAG_TIME_STAGES)) return nullptr;
-  if (P->ev_used == (int)P->ev.size()) {
+  if (used == (int)pool.size()) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    P->ev.push_back(e);
+    pool.push_back(e);
   }
-  return P->ev[P->ev_used++];
+  return pool[used++];
 }
+hipEvent_t next_event(ftp_plan* P) { return next_event_in(P, P->ev, P->ev_used); }
+hipEvent_t next_root_event(ftp_plan* P) { return next_event_in(P, P->evr, P->evr_used); }
 
 int wait_uploads(ftp_plan* P) {
   if (P->upload_pending) {
@@ -339,17 +346,26 @@ int solve_grid_waves(ftp_plan* P) {
   return P->n_cu * 16;
 }
 
-template <typename R>
-int launch_solve(ftp_plan* P, SolveArgs a, int64_t n_pairs, hipStream_t st) {
-  const size_t lds = solve_lds_bytes(P->H);
-  if (lds > 65536) {
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_plain<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+// Per-frequency stage over pair chunks: assemble -> companion QR -> score.
+int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) {
+  if (n_pairs <= 0) return FTP_OK;
+  const RecLayout RL(P->H);
+  const int64_t chunk = std::min<int64_t>(n_pairs, P->pair_chunk);
+  int rc;
+  if ((rc = P->rec.ensure(sizeof(double) * (size_t)chunk * RL.stride))) return rc;
+  double* rec = P->rec.as<double>();
+  const int waves = solve_grid_waves(P);
+  for (int64_t p0 = 0; p0 < n_pairs; p0 += chunk) {
+    const int64_t np = std::min<int64_t>(chunk, n_pairs - p0);
+    const int w = (int)std::min<int64_t>(np, waves);
+    HIP_TRY(launch_assemble(P->opt.precision, a, rec, p0, np, (int)std::min<int64_t>(np, 2 * waves), st));
+    hipEvent_t r0 = next_root_event(P);
+    if (r0) HIP_TRY(hipEventRecord(r0, st));
+    HIP_TRY(launch_qr(P->H, rec, RL.stride, np, nullptr, nullptr, P->counters.as<SolveCounters>(), w, st));
+    hipEvent_t r1 = next_root_event(P);
+    if (r1) HIP_TRY(hipEventRecord(r1, st));
+    HIP_TRY(launch_score(a, rec, p0, np, (int)std::min<int64_t>(np, 2 * waves), st));
   }
-  const int64_t waves = std::min<int64_t>(n_pairs, solve_grid_waves(P));
-  if (waves <= 0) return FTP_OK;
-  hipLaunchKernelGGL(k_solve_plain<R>, dim3((unsigned)waves), dim3(64), lds, st, a);
-  HIP_TRY(hipGetLastError());
   return FTP_OK;
 }
 
@@ -388,15 +404,14 @@ int run_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, con
   SolveArgs a = base_args(P, n_lc, n_pairs);
   if (sums_out) {
     const int64_t blocks = std::min<int64_t>(n_pairs, 65536);
-    hipLaunchKernelGGL(k_gather_sums<R>, dim3((unsigned)blocks), dim3(64), 0, st, a, sums_out);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_gather_sums(P->opt.precision, a, sums_out, (int)blocks, st));
   } else {
     a.power = power + f0;
     a.phase = phase + f0;
     a.amp = amp + f0;
     a.offset = offset + f0;
     a.status = status ? status + f0 : nullptr;
-    if ((rc = launch_solve<R>(P, a, n_pairs, st))) return rc;
+    if ((rc = run_solve(P, a, n_pairs, st))) return rc;
   }
   hipEvent_t e2 = next_event(P);
   if (e2) HIP_TRY(hipEventRecord(e2, st));
@@ -514,10 +529,11 @@ int ftp_plan_destroy(ftp_plan* P) {
   DevBuf* bufs[] = {&P->alpha, &P->twiddle32, &P->twiddle64, &P->lcinfo, &P->obs_off, &P->freq_off,
                     &P->grid_tile_base, &P->pw, &P->py, &P->tile_count, &P->tile_off, &P->cursor,
                     &P->block_sums, &P->total, &P->bucket, &P->grids, &P->fft_tab, &P->fft_items,
-                    &P->counters, &P->stats_out, &P->mlp};
+                    &P->counters, &P->stats_out, &P->mlp, &P->rec};
   for (DevBuf* b : bufs) b->release();
   if (P->upload_done) (void)hipEventDestroy(P->upload_done);
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : P->evr) (void)hipEventDestroy(e);
   delete P;
   return FTP_OK;
 }
@@ -562,8 +578,7 @@ int ftp_nfft_sums(ftp_plan* P, const double* t, const double* y, const double* s
                  (hipStream_t)stream);
   if (rc) return rc;
   // lc_stats: tref, ybar, yy, status bits
-  hipLaunchKernelGGL(k_export_stats, dim3(1), dim3(64), 0, (hipStream_t)stream, P->lcinfo.as<LcInfo>(), lc_stats);
-  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_export_stats(P->lcinfo.as<LcInfo>(), lc_stats, (hipStream_t)stream));
   return FTP_OK;
 }
 
@@ -596,8 +611,7 @@ int ftp_solve_sums(ftp_plan* P, const double* sums, const double* lc_stats, doub
   a.amp = amp;
   a.offset = offset;
   a.status = status;
-  rc = P->opt.precision == FTP_FP64 ? launch_solve<double>(P, a, n_f, st) : launch_solve<float>(P, a, n_f, st);
-  if (rc) return rc;
+  if ((rc = run_solve(P, a, n_f, st))) return rc;
   HIP_TRY(hipEventRecord(P->upload_done, st));
   P->upload_pending = true;
   P->last.n_pairs += (uint64_t)n_f;
@@ -626,6 +640,7 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
   *out = P->last;
   out->ms_nfft = 0.0;
   out->ms_solve = 0.0;
+  out->ms_roots = 0.0;
   for (int k = 0; k + 3 <= P->ev_used; k += 3) {
     float a = 0.f, b = 0.f;
     HIP_TRY(hipEventElapsedTime(&a, P->ev[k], P->ev[k + 1]));
@@ -633,12 +648,18 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
     out->ms_nfft += a;
     out->ms_solve += b;
   }
+  for (int k = 0; k + 2 <= P->evr_used; k += 2) {
+    float a = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, P->evr[k], P->evr[k + 1]));
+    out->ms_roots += a;
+  }
   out->n_fallback = c.fallback;
   out->qr_sweeps = c.qr_sweeps;
   out->newton_iters = c.newton_iters;
   out->roots_found = c.roots_found;
   // reset the accumulation window
   P->ev_used = 0;
+  P->evr_used = 0;
   P->last = ftp_stats{};
   HIP_TRY(hipMemsetAsync(P->counters.p, 0, sizeof(SolveCounters), (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));

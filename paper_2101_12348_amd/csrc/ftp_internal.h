@@ -7,7 +7,7 @@
 
 namespace ftp {
 
-constexpr int kMaxH = 16;             // D = 6H - 2 <= 94
+constexpr int kMaxH = 11;             // D = 6H - 2 <= 64
 constexpr int kTileCells = 2048;      // spreading tile (cells per workgroup)
 constexpr int kFixedShift = 60;       // fixed-point scale 2^60 for exact accumulation
 constexpr int kMaxPasses = 4;

@@ -1,63 +1,97 @@
-// Per-frequency companion-matrix solve (the method's root finding, Section 2:
-// the zeros of Eq. finalpoly are the eigenvalues of its companion matrix,
-// projected onto the unit circle and scored).
+// Per-frequency stage of the fast template periodogram: the method's phase
+// polynomial (Section 2, Eq. finalpoly), its roots as the eigenvalues of a
+// companion matrix, and the scoring of every root (Section 2: the phase
+// condition is necessary, not sufficient, so each solution is scored).
 //
-// One wavefront per trial frequency, persistent grid-stride loop.
-//   1. gather and deconvolve the NFFT sums (or read given sums);
-//   2. assemble mu (MM), eta (YM) and the trig coefficients r_d of
-//      R(theta) = i psi^{-K} p(psi), K = 3H - 1;
-//   3. Cayley map theta = phi0 + 2 atan(x): f(x) = (1 + x^2)^K R(theta(x)) is a
-//      real polynomial of degree D = 6H - 2 whose real roots are the real
-//      phases; phi0 is picked among 16 rotations to maximise |R(phi0 + pi)| (the
-//      leading coefficient of f);
-//   4. eigenvalues of the real companion matrix of f by Francis double-shift
-//      QR (the Hessenberg matrix lives in LDS, lanes own rows or columns);
-//   5. every eigenvalue is mapped back to psi, projected onto the unit circle
-//      and scored (P = YM^2/(YY MM)); the best candidate is Newton-polished
-//      on R(theta) and accepted only if P does not drop.
+// Three kernels, one wavefront per trial frequency, exchanging a per-pair
+// record through HBM (RecLayout):
+//   k_assemble : gather and deconvolve the NFFT sums (or read given sums);
+//                assemble mu (MM), eta (YM) and the trig coefficients r_d of
+//                R(theta) = i psi^{-K} p(psi), K = 3H - 1; pick a rotation
+//                phi0 among 16 that maximises |R(phi0 + pi)|; expand the
+//                Cayley polynomial f(x) = (1 + x^2)^K R(phi0 + 2 atan x), a real
+//                polynomial of degree D = 6H - 2 whose real roots are the real
+//                phases (leading coefficient R(phi0 + pi));
+//   k_qr<D>    : eigenvalues of the real companion matrix of f by Francis
+//                double-shift QR in LDS; every eigenvalue is mapped back to
+//                psi and projected onto the unit circle (a complex pair gives
+//                one candidate);
+//   k_score    : P = YM^2 / (YY MM) at every candidate, best by P with the
+//                documented tie rule, Newton polish on R(theta) kept only if P
+//                does not drop, outputs theta_2, theta_1, theta_3.
 #include "ftp_solve_common.h"
 
 namespace ftp {
 
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
 
-// Eigenvalues of the n x n upper Hessenberg matrix A (LDS, leading dim ld),
-// EISPACK hqr structure, eigenvalues only.  Returns the number of sweeps, or
-// -1 when the iteration limit is reached (remaining diagonal entries are then
-// used as eigenvalue estimates).
-__device__ int hqr_wave(double* A, int n, int ld, double* wr, double* wi, int lane) {
+// Orders this wave's LDS accesses (LDS operations of one wavefront are
+// performed in program order, so a compiler fence at wavefront scope is
+// enough; every workgroup here is a single wave).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Value of v in lane `src` (src must be wave-uniform).
+__device__ __forceinline__ double rdlane(double v, int src) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), src);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// 1/d and 1/sqrt(s) from the hardware estimates refined by two Newton steps
+// (a few ulp; the Householder step is backward stable to that level).
+__device__ __forceinline__ double fast_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double fast_rsq(double s) {
+  double y = __builtin_amdgcn_rsq(s);
+  const double h = 0.5 * s;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// ------------------------------------------------------------------ QR
+
+// Eigenvalues of the N x N upper Hessenberg matrix A (LDS, leading dim N + 1,
+// N <= 64), EISPACK hqr structure, eigenvalues only: Francis double-shift
+// sweeps over the active window [l, m], deflating at negligible subdiagonals.
+// Lane j owns column j in the row update of a chase step and row j in the
+// column update; the next bulge column is broadcast from the updating lanes'
+// registers.  Returns the number of sweeps, or -1 when the iteration limit is
+// reached (the remaining diagonal entries are then used as estimates).
+template <int N>
+__device__ __forceinline__ int hqr_wave(double* A, double* wr, double* wi, const int lane) {
+  constexpr int ld = N + 1;
   double anorm = 0.0;
-  for (int i = lane; i < n; i += 64) {
-    for (int j = (i > 0 ? i - 1 : 0); j < n; ++j) anorm += fabs(A[i * ld + j]);
+  if (lane < N) {
+    for (int j = (lane > 0 ? lane - 1 : 0); j < N; ++j) anorm += fabs(A[lane * ld + j]);
   }
   anorm = wave_sum(anorm);
   if (anorm == 0.0) anorm = 1.0;
-  int m = n - 1, its = 0, sweeps = 0;
-  const int maxit = 30 * n;
+  int m = N - 1, its = 0, sweeps = 0;
+  constexpr int maxit = 30 * N;
   bool failed = false;
   while (m >= 0) {
-    // largest l in [1, m] with a negligible subdiagonal, else 0
-    int l = 0;
-    for (int base = 0; base <= m; base += 64) {
-      const int ll = base + lane;
-      bool ok = false;
-      if (ll >= 1 && ll <= m) {
-        double s = fabs(A[(ll - 1) * ld + ll - 1]) + fabs(A[ll * ld + ll]);
-        if (s == 0.0) s = anorm;
-        ok = fabs(A[ll * ld + ll - 1]) <= kEps * s;
-      }
-      const unsigned long long mask = __ballot(ok);
-      if (mask) l = base + 63 - __clzll(mask);
+    bool ok = false;
+    if (lane >= 1 && lane <= m) {
+      double sd = fabs(A[(lane - 1) * ld + lane - 1]) + fabs(A[lane * ld + lane]);
+      if (sd == 0.0) sd = anorm;
+      ok = fabs(A[lane * ld + lane - 1]) <= kEps * sd;
     }
-    if (l > 0) {
-      if (lane == 0) A[l * ld + l - 1] = 0.0;
-    }
-    __syncthreads();
+    const unsigned long long mask = __ballot(ok);
+    const int l = mask ? 63 - __clzll(mask) : 0;
     if (l == m) {
       if (lane == 0) { wr[m] = A[m * ld + m]; wi[m] = 0.0; }
       m -= 1;
       its = 0;
-      __syncthreads();
       continue;
     }
     if (l == m - 1) {
@@ -79,89 +113,150 @@ __device__ int hqr_wave(double* A, int n, int ld, double* wr, double* wi, int la
       }
       m -= 2;
       its = 0;
-      __syncthreads();
       continue;
     }
     if (sweeps >= maxit) { failed = true; break; }
     double S, T;
+    const double amm = A[m * ld + m], am1 = A[(m - 1) * ld + m - 1];
     if (its == 10 || its == 20) {
-      const double s = fabs(A[m * ld + m - 1]) + fabs(A[(m - 1) * ld + m - 2]);
-      const double c = A[m * ld + m] + 0.75 * s;
+      const double sx = fabs(A[m * ld + m - 1]) + fabs(A[(m - 1) * ld + m - 2]);
+      const double c = amm + 0.75 * sx;
       S = 2.0 * c;
-      T = c * c - 0.4375 * s * s;
+      T = c * c - 0.4375 * sx * sx;
     } else {
-      S = A[(m - 1) * ld + m - 1] + A[m * ld + m];
-      T = A[(m - 1) * ld + m - 1] * A[m * ld + m] - A[(m - 1) * ld + m] * A[m * ld + m - 1];
+      S = am1 + amm;
+      T = am1 * amm - A[(m - 1) * ld + m] * A[m * ld + m - 1];
     }
     ++its;
     ++sweeps;
-    double x = A[l * ld + l] * A[l * ld + l] + A[l * ld + l + 1] * A[(l + 1) * ld + l] - S * A[l * ld + l] + T;
-    double y = A[(l + 1) * ld + l] * (A[l * ld + l] + A[(l + 1) * ld + l + 1] - S);
-    double z = (l + 2 <= m) ? A[(l + 2) * ld + l + 1] * A[(l + 1) * ld + l] : 0.0;
+    const double all = A[l * ld + l], al1 = A[(l + 1) * ld + l];
+    double x = all * all + A[l * ld + l + 1] * al1 - S * all + T;
+    double y = al1 * (all + A[(l + 1) * ld + l + 1] - S);
+    double z = (l + 2 <= m) ? A[(l + 2) * ld + l + 1] * al1 : 0.0;
     for (int k = l; k <= m - 1; ++k) {
       const bool three = k < m - 1;
-      if (k > l) {
-        x = A[k * ld + k - 1];
-        y = A[(k + 1) * ld + k - 1];
-        z = three ? A[(k + 2) * ld + k - 1] : 0.0;
+      const double s2 = x * x + y * y + z * z;
+      double a0n = 0.0;
+      if (s2 > 0.0) {
+        const double inv = fast_rsq(s2);
+        const double nrm = s2 * inv;
+        const double alpha = -copysign(nrm, x);
+        const double ax = fabs(x);
+        const double tau = 1.0 + ax * inv;                         // (alpha - x) / alpha
+        const double rv = copysign(fast_rcp(ax + nrm), x);        // 1 / (x - alpha)
+        const double v1 = y * rv, v2 = z * rv;
+        // row update: rows k..k+2, columns k..m (lane = column); the bulge
+        // column k-1 becomes (alpha, 0, 0)
+        if (lane >= k && lane <= m) {
+          const double b0 = A[k * ld + lane], b1 = A[(k + 1) * ld + lane];
+          const double b2 = three ? A[(k + 2) * ld + lane] : 0.0;
+          const double w = tau * (b0 + v1 * b1 + v2 * b2);
+          A[k * ld + lane] = b0 - w;
+          A[(k + 1) * ld + lane] = b1 - w * v1;
+          if (three) A[(k + 2) * ld + lane] = b2 - w * v2;
+        } else if (k > l && lane == k - 1) {
+          A[k * ld + lane] = alpha;
+          A[(k + 1) * ld + lane] = 0.0;
+          if (three) A[(k + 2) * ld + lane] = 0.0;
+        }
+        wave_sync();
+        // column update: columns k..k+2, rows l..min(k+3, m) (lane = row)
+        const int ihi = k + 3 < m ? k + 3 : m;
+        if (lane >= l && lane <= ihi) {
+          const double c0 = A[lane * ld + k], c1 = A[lane * ld + k + 1];
+          const double c2 = three ? A[lane * ld + k + 2] : 0.0;
+          const double w = tau * (c0 + v1 * c1 + v2 * c2);
+          a0n = c0 - w;
+          A[lane * ld + k] = a0n;
+          A[lane * ld + k + 1] = c1 - w * v1;
+          if (three) A[lane * ld + k + 2] = c2 - w * v2;
+        }
+        wave_sync();
+        if (k + 1 <= m - 1) {
+          x = rdlane(a0n, k + 1);
+          y = rdlane(a0n, k + 2);
+          z = (k + 1 < m - 1) ? rdlane(a0n, k + 3) : 0.0;
+        }
+      } else if (k + 1 <= m - 1) {
+        x = A[(k + 1) * ld + k];
+        y = A[(k + 2) * ld + k];
+        z = (k + 1 < m - 1) ? A[(k + 3) * ld + k] : 0.0;
       }
-      const double nrm = sqrt(x * x + y * y + z * z);
-      if (nrm == 0.0) continue;
-      const double alpha = -copysign(nrm, x);
-      const double v0 = x - alpha;
-      const double v1 = y / v0, v2 = z / v0;
-      const double tau = (alpha - x) / alpha;
-      __syncthreads();
-      if (k > l && lane == 0) {
-        A[k * ld + k - 1] = alpha;
-        A[(k + 1) * ld + k - 1] = 0.0;
-        if (three) A[(k + 2) * ld + k - 1] = 0.0;
-      }
-      // rows k..k+2, columns k..m
-      for (int j = k + lane; j <= m; j += 64) {
-        double a0 = A[k * ld + j], a1 = A[(k + 1) * ld + j];
-        double a2 = three ? A[(k + 2) * ld + j] : 0.0;
-        const double w = a0 + v1 * a1 + v2 * a2;
-        A[k * ld + j] = a0 - tau * w;
-        A[(k + 1) * ld + j] = a1 - tau * w * v1;
-        if (three) A[(k + 2) * ld + j] = a2 - tau * w * v2;
-      }
-      __syncthreads();
-      // columns k..k+2, rows l..min(k+3, m)
-      const int ihi = k + 3 < m ? k + 3 : m;
-      for (int i = l + lane; i <= ihi; i += 64) {
-        double a0 = A[i * ld + k], a1 = A[i * ld + k + 1];
-        double a2 = three ? A[i * ld + k + 2] : 0.0;
-        const double w = a0 + v1 * a1 + v2 * a2;
-        A[i * ld + k] = a0 - tau * w;
-        A[i * ld + k + 1] = a1 - tau * w * v1;
-        if (three) A[i * ld + k + 2] = a2 - tau * w * v2;
-      }
-      __syncthreads();
     }
   }
+  wave_sync();
   if (failed) {
-    for (int i = lane; i <= m; i += 64) { wr[i] = A[i * ld + i]; wi[i] = 0.0; }
-    __syncthreads();
+    if (lane <= m) { wr[lane] = A[lane * ld + lane]; wi[lane] = 0.0; }
+    wave_sync();
     return -1;
   }
   return sweeps;
 }
 
-__device__ __forceinline__ size_t align2(size_t nd) { return (nd + 1) & ~(size_t)1; }
+__host__ __device__ inline size_t qr_lds_bytes(int D) {
+  return ((size_t)D * (D + 1) + 2 * (size_t)D + 2) * sizeof(double);
+}
 
-struct SolveLayout {
-  double* A; double* wr; double* wi; FreqWork W; double2* hb[2]; double2* vb[2]; double* f;
-};
+// Companion eigenvalues for the pairs of a chunk (or of a list of them).
+// Candidates theta_rel (relative to t_ref) go to rec.cand; NaN marks none.
+template <int N>
+__global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, const int64_t* list,
+                                           const unsigned int* list_count, SolveCounters* counters) {
+  extern __shared__ double smq[];
+  constexpr int ld = N + 1;
+  double* A = smq;
+  double* wr = A + N * ld;
+  double* wi = wr + N;
+  const int lane = wave_lane();
+  const RecLayout RL((N + 2) / 6);
+  int64_t total = np;
+  if (list) total = (int64_t)*list_count;
+  unsigned long long sweeps_acc = 0;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int64_t q = list ? list[w] : w;
+    double* R = rec + q * (int64_t)stride;
+    const int st = (int)R[RL.meta + 2];
+    if (st == ST_BAD_LC || st == ST_CONSTANT) continue;
+    const double* f = R + RL.f;
+    const double lead = f[N];
+    if (lane < N) {
+      for (int j = 0; j < N; ++j) A[lane * ld + j] = 0.0;
+      if (lane > 0) A[lane * ld + lane - 1] = 1.0;
+    }
+    wave_sync();
+    if (lane < N) A[lane] = -f[N - 1 - lane] / lead;
+    wave_sync();
+    const int sw = hqr_wave<N>(A, wr, wi, lane);
+    if (sw < 0) {
+      if (lane == 0) R[RL.meta + 2] = (double)ST_NO_CONVERGE;
+    } else {
+      sweeps_acc += (unsigned long long)sw;
+    }
+    const double phi0 = R[RL.meta + 0];
+    if (lane < N) {
+      const double xr = wr[lane], xi = wi[lane];
+      double th = __longlong_as_double(0x7ff8000000000000ll);
+      if (xi >= 0.0 && isfinite(xr) && isfinite(xi)) th = phi0 + atan2(xr, 1.0 - xi) + atan2(xr, 1.0 + xi);
+      R[RL.cand + lane] = th;
+    }
+    wave_sync();
+  }
+  if (counters && lane == 0 && sweeps_acc) atomicAdd(&counters->qr_sweeps, sweeps_acc);
+}
 
-__device__ __forceinline__ SolveLayout make_layout(double* sm, int H) {
-  const int K = 3 * H - 1, D = 2 * K, n = D, ld = n + 1;
-  SolveLayout s;
-  double* p = sm;
-  s.A = p; p += ((size_t)n * ld + 1) & ~(size_t)1;
-  s.wr = p; p += ((size_t)n + 1) & ~(size_t)1;
-  s.wi = p; p += ((size_t)n + 1) & ~(size_t)1;
-  double2* q = reinterpret_cast<double2*>(p);
+// ------------------------------------------------------------- assemble
+
+__host__ __device__ inline size_t asm_lds_bytes(int H) {
+  const int K = 3 * H - 1, D = 2 * K;
+  return (size_t)(2 * ((3 * H + 1) + (2 * H + 1) + (H + 1) + (K + 1) + 4 * (D + 1) + H)) * sizeof(double);
+}
+
+struct AsmLayout { FreqWork W; double2* hb[2]; double2* vb[2]; };
+
+__device__ __forceinline__ AsmLayout asm_layout(double* sm, int H) {
+  const int K = 3 * H - 1, D = 2 * K;
+  AsmLayout s;
+  double2* q = reinterpret_cast<double2*>(sm);
   s.W.Z = q; q += 3 * H + 1;
   s.W.mu = q; q += 2 * H + 1;
   s.W.eta = q; q += H + 1;
@@ -170,9 +265,7 @@ __device__ __forceinline__ SolveLayout make_layout(double* sm, int H) {
   s.hb[1] = q; q += D + 1;
   s.vb[0] = q; q += D + 1;
   s.vb[1] = q; q += D + 1;
-  s.f = reinterpret_cast<double*>(q);
-  p = s.f + (((size_t)D + 2) & ~(size_t)1);
-  s.W.al = reinterpret_cast<double2*>(p);
+  s.W.al = q;
   return s;
 }
 
@@ -197,8 +290,103 @@ __device__ __forceinline__ void load_sums(const SolveArgs& a, const LcInfo& L, i
       W.Z[q + 1] = gather_mode<R>(L, g, (int64_t)k * j, grids);
     }
   }
-  __syncthreads();
+  wave_sync();
 }
+
+// Sums -> polynomial record for pairs [p0, p0 + np) of the chunk.
+template <typename R>
+__global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64_t p0, int64_t np) {
+  extern __shared__ double sma[];
+  const int lane = wave_lane();
+  const int H = a.H, K = 3 * H - 1, D = 2 * K;
+  const RecLayout RL(H);
+  AsmLayout S = asm_layout(sma, H);
+  const FreqWork& W = S.W;
+  for (int q = lane; q < H; q += 64) S.W.al[q] = a.alpha[q];
+  wave_sync();
+  for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
+    const int64_t pidx = p0 + w;
+    double* Rr = rec + w * (int64_t)RL.stride;
+    const int64_t lc = find_seg(a.freq_off, a.n_lc, pidx);
+    const LcInfo& L = a.lcs[lc];
+    const int64_t j = pidx - a.freq_off[lc] + 1;
+    if (L.status != 0) {
+      if (lane == 0) { Rr[RL.meta + 2] = (double)ST_BAD_LC; Rr[RL.meta + 3] = (double)lc; }
+      continue;
+    }
+    const double ref = ref_cycles(j, L.df, L.tref);
+    load_sums<R>(a, L, pidx, j, W, lane);
+    assemble_poly(W, H, lane);
+    double rmax = 0.0, mumax = 0.0, etamax = 0.0;
+    for (int d = lane; d <= K; d += 64) rmax = fmax(rmax, sqrt(cabs2(W.r[d])));
+    for (int e = lane; e <= 2 * H; e += 64) mumax = fmax(mumax, sqrt(cabs2(W.mu[e])));
+    for (int k = lane; k <= H; k += 64) etamax = fmax(etamax, sqrt(cabs2(W.eta[k])));
+    rmax = wave_max(rmax);
+    mumax = wave_max(mumax);
+    etamax = wave_max(etamax);
+    const double rscale = mumax * etamax * (6.0 * H) * (2.0 * H + 1.0);
+    const bool constant = !(rmax > 64.0 * kEps * rscale);
+    double phi0 = 0.0;
+    if (!constant) {
+      double Rv = -1.0, dR;
+      if (lane < 16) {
+        eval_R(W, H, kTwoPi * lane / 16.0 + kPi, Rv, dR);
+        Rv = fabs(Rv);
+      }
+      const double rm = wave_max(Rv);
+      const unsigned long long mask = __ballot(lane < 16 && Rv == rm);
+      phi0 = kTwoPi * (__ffsll((long long)mask) - 1) / 16.0;
+      // f(x) = sum_j rho_{j-K} u^j v^{2K-j}, u = 1 + i x, v = 1 - i x,
+      // rho_d = r_d e^{i d phi0}; homogeneous Horner h_l = u h_{l-1} + rho_{K-l} v^l
+      for (int c = lane; c <= D; c += 64) {
+        double sn, cs;
+        sincos(K * phi0, &sn, &cs);
+        S.hb[0][c] = c == 0 ? cmul(W.r[K], make_double2(cs, sn)) : make_double2(0.0, 0.0);
+        S.vb[0][c] = c == 0 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+      }
+      wave_sync();
+      for (int l = 1; l <= D; ++l) {
+        const int d = K - l;
+        const double2 rd = d >= 0 ? W.r[d] : cconj(W.r[-d]);
+        double sn, cs;
+        sincos(d * phi0, &sn, &cs);
+        const double2 rho = cmul(rd, make_double2(cs, sn));
+        const double2* hsrc = (l & 1) ? S.hb[0] : S.hb[1];
+        const double2* vsrc = (l & 1) ? S.vb[0] : S.vb[1];
+        double2* hdst = (l & 1) ? S.hb[1] : S.hb[0];
+        double2* vdst = (l & 1) ? S.vb[1] : S.vb[0];
+        for (int c = lane; c <= D; c += 64) {
+          const double2 vprev = c > 0 ? vsrc[c - 1] : make_double2(0.0, 0.0);
+          const double2 hprev = c > 0 ? hsrc[c - 1] : make_double2(0.0, 0.0);
+          const double2 vnew = make_double2(vsrc[c].x + vprev.y, vsrc[c].y - vprev.x);
+          const double2 hnew = make_double2(hsrc[c].x - hprev.y, hsrc[c].y + hprev.x);
+          vdst[c] = vnew;
+          hdst[c] = cadd(hnew, cmul(rho, vnew));
+        }
+        wave_sync();
+      }
+      const double2* hfin = (D & 1) ? S.hb[1] : S.hb[0];
+      for (int c = lane; c <= D; c += 64) Rr[RL.f + c] = hfin[c].x;
+    }
+    for (int d = lane; d <= K; d += 64) { Rr[RL.r + 2 * d] = W.r[d].x; Rr[RL.r + 2 * d + 1] = W.r[d].y; }
+    for (int e = lane; e <= 2 * H; e += 64) { Rr[RL.mu + 2 * e] = W.mu[e].x; Rr[RL.mu + 2 * e + 1] = W.mu[e].y; }
+    for (int k = lane; k < H; k += 64) {
+      Rr[RL.eta + 2 * k] = W.eta[k + 1].x;
+      Rr[RL.eta + 2 * k + 1] = W.eta[k + 1].y;
+      Rr[RL.zw + 2 * k] = W.Z[k + 1].x;
+      Rr[RL.zw + 2 * k + 1] = W.Z[k + 1].y;
+    }
+    if (lane == 0) {
+      Rr[RL.meta + 0] = phi0;
+      Rr[RL.meta + 1] = ref;
+      Rr[RL.meta + 2] = constant ? (double)ST_CONSTANT : (double)ST_OK;
+      Rr[RL.meta + 3] = (double)lc;
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------- score
 
 // Best-candidate selection across the wave: max P; near ties (1e-12 relative)
 // prefer theta_1 > 0, then the smallest absolute theta_2.
@@ -209,7 +397,6 @@ __device__ __forceinline__ Best select_best(double P, double th_rel, double th_a
   const double pv = valid ? P : -1.0;
   const double pmax = wave_max(pv);
   const bool near = valid && pv >= pmax - 1e-12 * fmax(pmax, 1e-300);
-  // key: (theta1 > 0 ? 0 : 1) * 8 + theta_abs  (theta_abs in [0, 2 pi))
   double key = near ? ((ym > 0.0 ? 0.0 : 8.0) + th_abs) : 1e30;
   double kmin = key;
   for (int o = 32; o > 0; o >>= 1) kmin = fmin(kmin, __shfl_xor(kmin, o));
@@ -230,22 +417,6 @@ __device__ __forceinline__ double wrap_2pi(double x) {
   return x;
 }
 
-// Writes the outputs for one frequency given the chosen relative phase.
-__device__ __forceinline__ void write_outputs(const SolveArgs& a, const LcInfo& L, const FreqWork& W,
-                                              int64_t pidx, double th_rel, double ref, uint8_t st) {
-  const Cand c = eval_candidate(W, a.H, th_rel);
-  const double sq = sqrt(L.yy);
-  double P = c.P, amp = c.MM > 0.0 ? c.YM / c.MM * sq : 0.0;
-  double off = L.ybar - c.Mbar * amp;
-  double th_abs = wrap_2pi(th_rel + kTwoPi * ref);
-  if (st == ST_DEGENERATE) { P = 0.0; amp = 0.0; off = L.ybar; th_abs = 0.0; }
-  a.power[pidx] = P;
-  a.phase[pidx] = th_abs;
-  a.amp[pidx] = amp;
-  a.offset[pidx] = off;
-  if (a.status) a.status[pidx] = st;
-}
-
 // Degeneracy threshold: MM <= tau sum |alpha|^2 at every candidate, with tau
 // set by the precision of the sums (exact sums 1e-14, FP64 NFFT 1e-9, FP32
 // NFFT 1e-5: a few hundred times the sums' error relative to sum|g|).
@@ -255,188 +426,101 @@ __device__ __forceinline__ double mm_floor(const FreqWork& W, int H, double tau)
   return tau * s;
 }
 
-// Scores the candidate set {theta_c} spread over lanes, polishes the best and
-// writes outputs.  `valid` marks lanes holding a candidate.
-__device__ __forceinline__ void finish_frequency(const SolveArgs& a, const LcInfo& L, const FreqWork& W,
-                                                 int64_t pidx, double ref, double th, bool valid, uint8_t st0,
-                                                 int lane) {
-  const int H = a.H;
-  Cand c = eval_candidate(W, H, th);
-  const double floor_mm = mm_floor(W, H, a.mm_tau);
-  const double mmmax = wave_max(valid ? c.MM : -1.0);
-  uint8_t st = st0;
-  if (mmmax <= floor_mm) st = ST_DEGENERATE;
-  const bool ok = valid && c.MM > floor_mm;
-  const double th_abs = wrap_2pi(th + kTwoPi * ref);
-  Best b = select_best(c.P, th, th_abs, c.YM, ok || (valid && st == ST_DEGENERATE), lane);
-  double best_th = b.th_rel;
-  if (st != ST_DEGENERATE && st != ST_CONSTANT) {
-    // Newton polish on R(theta) (all lanes redundantly); keep only if P holds
-    double cur = best_th;
-    double curP = eval_candidate(W, H, cur).P;
-    for (int it = 0; it < 3; ++it) {
-      double R, dR;
-      eval_R(W, H, cur, R, dR);
-      if (!(dR != 0.0) || !isfinite(R / dR)) break;
-      const double nt = cur - R / dR;
-      if (fabs(nt - cur) > 1e-3) break;
-      const double nP = eval_candidate(W, H, nt).P;
-      if (!(nP >= curP)) break;
-      cur = nt;
-      curP = nP;
-    }
-    best_th = cur;
-  }
-  if (lane == 0) write_outputs(a, L, W, pidx, best_th, ref, st);
+__host__ __device__ inline size_t score_lds_bytes(int H) {
+  const int K = 3 * H - 1;
+  return (size_t)(2 * ((3 * H + 1) + (2 * H + 1) + (H + 1) + (K + 1) + H)) * sizeof(double);
 }
 
-template <typename R>
-__global__ __launch_bounds__(64) void k_solve_plain(SolveArgs a) {
-  extern __shared__ double sm[];
+// Scores all candidates of pairs [p0, p0 + np) and writes the outputs.
+__global__ __launch_bounds__(64) void k_score(SolveArgs a, const double* rec, int64_t p0, int64_t np) {
+  extern __shared__ double sms[];
   const int lane = wave_lane();
-  const int H = a.H, K = 3 * H - 1, D = 2 * K, n = D, ld = n + 1;
-  SolveLayout S = make_layout(sm, H);
-  const FreqWork& W = S.W;
-  for (int q = lane; q < H; q += 64) S.W.al[q] = a.alpha[q];
-  __syncthreads();
-  int64_t total = a.total;
-  if (a.list_count) total = (int64_t)*a.list_count < total ? (int64_t)*a.list_count : total;
-  unsigned long long sweeps_acc = 0;
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-    const int64_t pidx = a.list ? a.list[w] : w;
-    const int64_t lc = find_seg(a.freq_off, a.n_lc, pidx);
+  const int H = a.H, K = 3 * H - 1, D = 2 * K;
+  const RecLayout RL(H);
+  FreqWork W;
+  {
+    double2* q = reinterpret_cast<double2*>(sms);
+    W.Z = q; q += 3 * H + 1;
+    W.mu = q; q += 2 * H + 1;
+    W.eta = q; q += H + 1;
+    W.r = q; q += K + 1;
+    W.al = q;
+  }
+  for (int q = lane; q < H; q += 64) W.al[q] = a.alpha[q];
+  wave_sync();
+  const double floor_mm = mm_floor(W, H, a.mm_tau);
+  for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
+    const int64_t pidx = p0 + w;
+    const double* Rr = rec + w * (int64_t)RL.stride;
+    const int st = (int)Rr[RL.meta + 2];
+    const int64_t lc = (int64_t)Rr[RL.meta + 3];
     const LcInfo& L = a.lcs[lc];
-    const int64_t j = pidx - a.freq_off[lc] + 1;
-    if (L.status != 0) {
+    if (st == ST_BAD_LC) {
       if (lane == 0) {
         a.power[pidx] = 0.0; a.phase[pidx] = 0.0; a.amp[pidx] = 0.0; a.offset[pidx] = 0.0;
         if (a.status) a.status[pidx] = ST_BAD_LC;
       }
       continue;
     }
-    const double ref = ref_cycles(j, L.df, L.tref);
-    load_sums<R>(a, L, pidx, j, W, lane);
-    assemble_poly(W, H, lane);
-    // p == 0 (R constant in theta) check
-    double rmax = 0.0, mumax = 0.0, etamax = 0.0;
-    for (int d = lane; d <= K; d += 64) rmax = fmax(rmax, sqrt(cabs2(W.r[d])));
-    for (int e = lane; e <= 2 * H; e += 64) mumax = fmax(mumax, sqrt(cabs2(W.mu[e])));
-    for (int k = lane; k <= H; k += 64) etamax = fmax(etamax, sqrt(cabs2(W.eta[k])));
-    rmax = wave_max(rmax); mumax = wave_max(mumax); etamax = wave_max(etamax);
-    const double rscale = mumax * etamax * (6.0 * H) * (2.0 * H + 1.0);
-    if (!(rmax > 64.0 * kEps * rscale)) {
+    const double ref = Rr[RL.meta + 1];
+    for (int d = lane; d <= K; d += 64) W.r[d] = make_double2(Rr[RL.r + 2 * d], Rr[RL.r + 2 * d + 1]);
+    for (int e = lane; e <= 2 * H; e += 64) W.mu[e] = make_double2(Rr[RL.mu + 2 * e], Rr[RL.mu + 2 * e + 1]);
+    for (int k = lane; k < H; k += 64) {
+      W.eta[k + 1] = make_double2(Rr[RL.eta + 2 * k], Rr[RL.eta + 2 * k + 1]);
+      W.Z[k + 1] = make_double2(Rr[RL.zw + 2 * k], Rr[RL.zw + 2 * k + 1]);
+    }
+    if (lane == 0) W.eta[0] = make_double2(0.0, 0.0);
+    wave_sync();
+    double th = 0.0;
+    bool valid = false;
+    if (st == ST_CONSTANT) {
       // P does not depend on the phase: score theta_2 = 0 (absolute)
-      const double th = -kTwoPi * ref;
-      finish_frequency(a, L, W, pidx, ref, th, lane == 0, ST_CONSTANT, lane);
-      __syncthreads();
-      continue;
+      th = -kTwoPi * ref;
+      valid = lane == 0;
+    } else if (lane < D) {
+      th = Rr[RL.cand + lane];
+      valid = !isnan(th);
+      if (!valid) th = 0.0;
     }
-    // rotation: maximise |R(phi0 + pi)| over 16 candidates
-    double phi0 = 0.0;
-    {
-      double Rv = -1.0, dR;
-      if (lane < 16) {
-        eval_R(W, H, kTwoPi * lane / 16.0 + kPi, Rv, dR);
-        Rv = fabs(Rv);
+    const Cand c = eval_candidate(W, H, th);
+    const double mmmax = wave_max(valid ? c.MM : -1.0);
+    int stout = st;
+    if (mmmax <= floor_mm) stout = ST_DEGENERATE;
+    const bool ok = valid && (c.MM > floor_mm || stout == ST_DEGENERATE);
+    Best b = select_best(c.P, th, wrap_2pi(th + kTwoPi * ref), c.YM, ok, lane);
+    double best_th = b.th_rel;
+    if (stout != ST_DEGENERATE && stout != ST_CONSTANT) {
+      double cur = best_th;
+      double curP = eval_candidate(W, H, cur).P;
+      for (int it = 0; it < 3; ++it) {
+        double Rv, dR;
+        eval_R(W, H, cur, Rv, dR);
+        if (!(dR != 0.0) || !isfinite(Rv / dR)) break;
+        const double nt = cur - Rv / dR;
+        if (fabs(nt - cur) > 1e-3) break;
+        const double nP = eval_candidate(W, H, nt).P;
+        if (!(nP >= curP)) break;
+        cur = nt;
+        curP = nP;
       }
-      const double rm = wave_max(Rv);
-      const unsigned long long mask = __ballot(lane < 16 && Rv == rm);
-      const int bl = __ffsll((long long)mask) - 1;
-      phi0 = kTwoPi * bl / 16.0;
+      best_th = cur;
     }
-    // f(x) = sum_j rho_{j-K} u^j v^{2K-j}, u = 1 + i x, v = 1 - i x, rho_d = r_d e^{i d phi0};
-    // homogeneous Horner h_l = u h_{l-1} + rho_{K-l} v^l.
-    for (int c = lane; c <= D; c += 64) {
-      double2 rk = W.r[K];
-      double sn, cs;
-      sincos(K * phi0, &sn, &cs);
-      S.hb[0][c] = c == 0 ? cmul(rk, make_double2(cs, sn)) : make_double2(0.0, 0.0);
-      S.vb[0][c] = c == 0 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+    if (lane == 0) {
+      const Cand cb = eval_candidate(W, H, best_th);
+      const double sq = sqrt(L.yy);
+      double P = cb.P, amp = cb.MM > 0.0 ? cb.YM / cb.MM * sq : 0.0;
+      double off = L.ybar - cb.Mbar * amp;
+      double th_abs = wrap_2pi(best_th + kTwoPi * ref);
+      if (stout == ST_DEGENERATE) { P = 0.0; amp = 0.0; off = L.ybar; th_abs = 0.0; }
+      a.power[pidx] = P;
+      a.phase[pidx] = th_abs;
+      a.amp[pidx] = amp;
+      a.offset[pidx] = off;
+      if (a.status) a.status[pidx] = (uint8_t)stout;
     }
-    __syncthreads();
-    int cur = 0;
-    for (int l = 1; l <= D; ++l) {
-      const int d = K - l;
-      double2 rho;
-      {
-        const double2 rd = d >= 0 ? W.r[d] : cconj(W.r[-d]);
-        double sn, cs;
-        sincos(d * phi0, &sn, &cs);
-        rho = cmul(rd, make_double2(cs, sn));
-      }
-      for (int c = lane; c <= D; c += 64) {
-        const double2 vprev = c > 0 ? S.vb[cur][c - 1] : make_double2(0.0, 0.0);
-        const double2 hprev = c > 0 ? S.hb[cur][c - 1] : make_double2(0.0, 0.0);
-        const double2 vnew = make_double2(S.vb[cur][c].x + vprev.y, S.vb[cur][c].y - vprev.x);
-        const double2 hnew = make_double2(S.hb[cur][c].x - hprev.y, S.hb[cur][c].y + hprev.x);
-        S.vb[cur ^ 1][c] = vnew;
-        S.hb[cur ^ 1][c] = cadd(hnew, cmul(rho, vnew));
-      }
-      __syncthreads();
-      cur ^= 1;
-    }
-    for (int c = lane; c <= D; c += 64) S.f[c] = S.hb[cur][c].x;
-    __syncthreads();
-    // companion matrix (upper Hessenberg): row 0 = -f_{D-1-j}/f_D, subdiagonal ones
-    const double lead = S.f[D];
-    for (int i = lane; i < n; i += 64) {
-      for (int jj = 0; jj < n; ++jj) S.A[i * ld + jj] = 0.0;
-      if (i > 0) S.A[i * ld + i - 1] = 1.0;
-    }
-    __syncthreads();
-    for (int jj = lane; jj < n; jj += 64) S.A[jj] = -S.f[D - 1 - jj] / lead;
-    __syncthreads();
-    const int sw = hqr_wave(S.A, n, ld, S.wr, S.wi, lane);
-    uint8_t st0 = ST_OK;
-    if (sw < 0) st0 = ST_NO_CONVERGE; else sweeps_acc += (unsigned long long)sw;
-    // candidates: one per real eigenvalue and per complex pair (wi > 0)
-    bool any = false;
-    for (int base = 0; base < n; base += 64) {
-      const int i = base + lane;
-      double th = 0.0;
-      bool valid = false;
-      if (i < n) {
-        const double xr = S.wr[i], xi = S.wi[i];
-        if (xi >= 0.0 && isfinite(xr) && isfinite(xi)) {
-          th = phi0 + atan2(xr, 1.0 - xi) + atan2(xr, 1.0 + xi);
-          valid = true;
-        }
-      }
-      (void)any;
-      if (base == 0 && n <= 64) {
-        finish_frequency(a, L, W, pidx, ref, th, valid, st0, lane);
-      }
-    }
-    if (n > 64) {
-      // more candidates than lanes: score in two rounds, keep the best
-      double bestP = -1.0, bestTh = 0.0, bestAbs = 1e30, bestYm = 0.0;
-      for (int base = 0; base < n; base += 64) {
-        const int i = base + lane;
-        double th = 0.0;
-        bool valid = false;
-        if (i < n) {
-          const double xr = S.wr[i], xi = S.wi[i];
-          if (xi >= 0.0 && isfinite(xr) && isfinite(xi)) {
-            th = phi0 + atan2(xr, 1.0 - xi) + atan2(xr, 1.0 + xi);
-            valid = true;
-          }
-        }
-        const Cand c = eval_candidate(W, H, th);
-        const double thabs = wrap_2pi(th + kTwoPi * ref);
-        Best b = select_best(c.P, th, thabs, c.YM, valid && c.MM > mm_floor(W, H, a.mm_tau), lane);
-        const bool better = b.P > bestP * (1.0 + 1e-12) ||
-                            (b.P >= bestP * (1.0 - 1e-12) &&
-                             ((b.amp_sign > 0.0 && bestYm <= 0.0) ||
-                              ((b.amp_sign > 0.0) == (bestYm > 0.0) && b.th_abs < bestAbs)));
-        if (better) { bestP = b.P; bestTh = b.th_rel; bestAbs = b.th_abs; bestYm = b.amp_sign; }
-      }
-      finish_frequency(a, L, W, pidx, ref, bestTh, lane == 0, st0, lane);
-    }
-    __syncthreads();
+    wave_sync();
   }
-  if (a.counters && lane == 0) atomicAdd(&a.counters->qr_sweeps, sweeps_acc);
 }
-
 
 // Writes the deconvolved sums of every pair (3H complex per pair: Z_w(k j),
 // k = 1..2H, then Z_y(k j), k = 1..H with the 1/sqrt(YY) normalisation undone).
@@ -470,10 +554,61 @@ __global__ void k_export_stats(const LcInfo* lcs, double* out) {
   }
 }
 
-template __global__ void k_gather_sums<float>(SolveArgs, double*);
-template __global__ void k_gather_sums<double>(SolveArgs, double*);
+// ------------------------------------------------------------ launchers
 
-template __global__ void k_solve_plain<float>(SolveArgs);
-template __global__ void k_solve_plain<double>(SolveArgs);
+template <int N>
+static hipError_t launch_qr_n(double* rec, int stride, int64_t np, const int64_t* list,
+                              const unsigned* list_count, SolveCounters* counters, int waves, hipStream_t st) {
+  hipLaunchKernelGGL(k_qr<N>, dim3((unsigned)waves), dim3(64), qr_lds_bytes(N), st, rec, stride, np, list,
+                     list_count, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr(int H, double* rec, int stride, int64_t np, const int64_t* list, const unsigned* list_count,
+                     SolveCounters* counters, int waves, hipStream_t st) {
+  switch (H) {
+    case 1: return launch_qr_n<4>(rec, stride, np, list, list_count, counters, waves, st);
+    case 2: return launch_qr_n<10>(rec, stride, np, list, list_count, counters, waves, st);
+    case 3: return launch_qr_n<16>(rec, stride, np, list, list_count, counters, waves, st);
+    case 4: return launch_qr_n<22>(rec, stride, np, list, list_count, counters, waves, st);
+    case 5: return launch_qr_n<28>(rec, stride, np, list, list_count, counters, waves, st);
+    case 6: return launch_qr_n<34>(rec, stride, np, list, list_count, counters, waves, st);
+    case 7: return launch_qr_n<40>(rec, stride, np, list, list_count, counters, waves, st);
+    case 8: return launch_qr_n<46>(rec, stride, np, list, list_count, counters, waves, st);
+    case 9: return launch_qr_n<52>(rec, stride, np, list, list_count, counters, waves, st);
+    case 10: return launch_qr_n<58>(rec, stride, np, list, list_count, counters, waves, st);
+    case 11: return launch_qr_n<64>(rec, stride, np, list, list_count, counters, waves, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64_t p0, int64_t np, int waves,
+                           hipStream_t st) {
+  const size_t lds = asm_lds_bytes(a.H);
+  if (precision == 1)
+    hipLaunchKernelGGL(k_assemble<double>, dim3((unsigned)waves), dim3(64), lds, st, a, rec, p0, np);
+  else
+    hipLaunchKernelGGL(k_assemble<float>, dim3((unsigned)waves), dim3(64), lds, st, a, rec, p0, np);
+  return hipGetLastError();
+}
+
+hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_score, dim3((unsigned)waves), dim3(64), score_lds_bytes(a.H), st, a, rec, p0, np);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_sums(int precision, const SolveArgs& a, double* out, int blocks, hipStream_t st) {
+  if (precision == 1)
+    hipLaunchKernelGGL(k_gather_sums<double>, dim3((unsigned)blocks), dim3(64), 0, st, a, out);
+  else
+    hipLaunchKernelGGL(k_gather_sums<float>, dim3((unsigned)blocks), dim3(64), 0, st, a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_stats(const LcInfo* lcs, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_export_stats, dim3(1), dim3(64), 0, st, lcs, out);
+  return hipGetLastError();
+}
 
 }  // namespace ftp

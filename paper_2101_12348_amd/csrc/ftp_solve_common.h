@@ -36,21 +36,47 @@ struct SolveArgs {
 
 constexpr double kEps = 2.220446049250313e-16;
 
-// Shared-memory size (bytes) of one wave's per-frequency working set.
+// Shared-memory size (bytes) of one wave's per-frequency working set.  The
+// Cayley-Horner buffers (4 (D+1) complex) alias the companion matrix, which is
+// only built after them.
+__host__ __device__ inline size_t solve_region_a(int H) {
+  const size_t D = 6 * H - 2;
+  const size_t mat = D * (D + 1), hor = 8 * (D + 1);
+  return ((mat > hor ? mat : hor) + 1) & ~(size_t)1;
+}
 __host__ __device__ inline size_t solve_lds_bytes(int H) {
-  const int K = 3 * H - 1, D = 2 * K, n = D, ld = n + 1;
-  size_t nd = 0;
-  nd += ((size_t)n * ld + 1) & ~(size_t)1;          // Hessenberg matrix
+  const int K = 3 * H - 1, D = 2 * K, n = D;
+  size_t nd = solve_region_a(H);                    // Hessenberg matrix / Horner buffers
   nd += 2 * (((size_t)n + 1) & ~(size_t)1);         // eigenvalues (re, im)
   nd += 2 * (3 * H + 1);                            // Z
   nd += 2 * (2 * H + 1);                            // mu
   nd += 2 * (H + 1);                                // eta
   nd += 2 * (K + 1);                                // r
-  nd += 2 * 4 * (D + 1);                            // Horner buffers
   nd += ((size_t)D + 2) & ~(size_t)1;               // f
   nd += 2 * H;                                      // alpha
   return nd * sizeof(double);
 }
+// Per-pair record in HBM passed between the assemble, root and score kernels
+// (doubles): r_d (d = 0..K, complex), mu_e (e = 0..2H, complex), eta_k and
+// Z_w(k) (k = 1..H, complex), meta {phi0, ref cycles, status, unused},
+// f_c (c = 0..D, the Cayley polynomial) and D root candidates theta (NaN =
+// none).
+struct RecLayout {
+  int K, D, r, mu, eta, zw, meta, f, cand, stride;
+  __host__ __device__ explicit RecLayout(int H) {
+    K = 3 * H - 1;
+    D = 2 * K;
+    r = 0;
+    mu = r + 2 * (K + 1);
+    eta = mu + 2 * (2 * H + 1);
+    zw = eta + 2 * H;
+    meta = zw + 2 * H;
+    f = meta + 4;
+    cand = f + D + 1;
+    stride = (cand + D + 3) & ~3;
+  }
+};
+
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
@@ -166,7 +192,7 @@ __device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane
   for (int k = lane; k <= H; k += 64) {
     W.eta[k] = k == 0 ? make_double2(0.0, 0.0) : cmul(W.al[k - 1], cconj(W.Z[2 * H + k]));
   }
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier();
   for (int d = lane; d <= K; d += 64) {
     double2 acc = make_double2(0.0, 0.0);
     for (int k = -H; k <= H; ++k) {
@@ -179,7 +205,7 @@ __device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane
     }
     W.r[d] = make_double2(-acc.y, acc.x);  // multiply by i
   }
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier();
 }
 
 // Candidate evaluation at relative phase theta: returns P (normalised,
