@@ -170,6 +170,48 @@ int ftp_solve_sums(ftp_plan* plan, const double* sums, const double* lc_stats, d
  */
 int ftp_plan_load_mlp(ftp_plan* plan, const float* weights, int64_t n_floats, int width);
 
+/* ------------------------------------------------------------------
+ * Root-proposal network (learned solver; a project addition to the method).
+ * An MLP d_in -> W -> W -> W -> d_out with ReLU, bf16 weights and activations
+ * and FP32 accumulation on the matrix cores; parameters W1, b1, ..., W4, b4
+ * with W stored (out, in) row-major: n = d_in W + W + 2 (W^2 + W) + d_out W +
+ * d_out.  For a plan with H harmonics d_in = 2 (6H - 1) (the normalised
+ * coefficients p_k, k = 0..6H-2, of Eq. finalpoly as (Re, Im) pairs, rotated so
+ * that the first trig coefficient of R(theta) is real) and d_out = 4H (2H seed
+ * directions (u, v); seed = atan2(v, u) in that rotated frame).
+ * Inputs X are bf16 bit patterns (uint16), row-major B x d_in, device.
+ * Training labels: up to R real-root phases per sample in the same frame
+ * (device B x R floats) and their counts (device B ints).  Loss: Chamfer
+ * distance on the circle between seed vectors and root unit vectors,
+ *   L = mean_b [ (1/n_b) sum_j min_k |e_k - r_j|^2 + lam (1/K) sum_k min_j |e_k - r_j|^2 ].
+ * ------------------------------------------------------------------ */
+typedef struct ftp_mlp ftp_mlp;
+
+/* Create a network; weights: host FP32 array of n values, or NULL for
+ * He-uniform weights and zero biases drawn from `seed`.
+ * Errors: FTP_E_NULL, FTP_E_SIZE (dimensions out of range), FTP_E_HIP. */
+int ftp_mlp_create(ftp_mlp** out, int d_in, int width, int d_out, const float* weights, uint64_t seed);
+int ftp_mlp_destroy(ftp_mlp* net);
+int ftp_mlp_num_params(const ftp_mlp* net, int64_t* n);
+/* FP32 master weights to host (synchronises the device). */
+int ftp_mlp_get_weights(ftp_mlp* net, float* host, int64_t n);
+/* out (device, B x d_out FP32) = network(X). */
+int ftp_mlp_forward(ftp_mlp* net, const uint16_t* X, int64_t B, float* out, void* stream);
+/* Per-sample loss (device B floats, nullable) and the loss gradient w.r.t.
+ * every parameter (device n floats, nullable), without updating. */
+int ftp_mlp_loss_grad(ftp_mlp* net, const uint16_t* X, int64_t B, const float* roots, const int* nroots, int R,
+                      float lam, float* loss, float* grads, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 masters with
+ * learning rate lr; the bf16 copies follow.  loss: as above. */
+int ftp_mlp_train_step(ftp_mlp* net, const uint16_t* X, int64_t B, const float* roots, const int* nroots, int R,
+                       float lam, float lr, float* loss, void* stream);
+/* Training samples from one lightcurve: runs the periodogram with the
+ * companion solve and writes, per frequency j = 1..n_f, the network features
+ * (X, device n_f x 2(6H-1) bf16) and the real roots of the phase polynomial in
+ * the feature frame (roots, device n_f x R; nroots, device n_f, capped at R). */
+int ftp_learned_dataset(ftp_plan* plan, const double* t, const double* y, const double* sigma, int64_t n_obs,
+                        double df, int64_t n_f, uint16_t* X, float* roots, int* nroots, int R, void* stream);
+
 /* Statistics accumulated over the plan's calls since the previous
  * ftp_last_stats (or plan creation); resets the accumulation.  Synchronises
  * `stream`, which must be the stream the calls were made on. */

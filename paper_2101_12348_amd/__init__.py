@@ -29,6 +29,8 @@ EXPORTED = [
     "ftp_options_default", "ftp_plan_create", "ftp_plan_destroy", "ftp_periodogram",
     "ftp_periodogram_batch", "ftp_nfft_sums", "ftp_solve_sums", "ftp_plan_load_mlp",
     "ftp_last_stats", "ftp_status_string", "ftp_last_error",
+    "ftp_mlp_create", "ftp_mlp_destroy", "ftp_mlp_num_params", "ftp_mlp_get_weights", "ftp_mlp_forward",
+    "ftp_mlp_loss_grad", "ftp_mlp_train_step", "ftp_learned_dataset",
 ]
 
 
@@ -70,6 +72,14 @@ def load_library(path: Optional[str] = None):
     lib.ftp_solve_sums.argtypes = [vp, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp]
     lib.ftp_plan_load_mlp.argtypes = [vp, vp, i64, ip]
     lib.ftp_last_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
+    lib.ftp_mlp_create.argtypes = [ctypes.POINTER(vp), ip, ip, ip, vp, ctypes.c_uint64]
+    lib.ftp_mlp_destroy.argtypes = [vp]
+    lib.ftp_mlp_num_params.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.ftp_mlp_get_weights.argtypes = [vp, vp, i64]
+    lib.ftp_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    lib.ftp_mlp_loss_grad.argtypes = [vp, vp, i64, vp, vp, ip, ctypes.c_float, vp, vp, vp]
+    lib.ftp_mlp_train_step.argtypes = [vp, vp, i64, vp, vp, ip, ctypes.c_float, ctypes.c_float, vp, vp]
+    lib.ftp_learned_dataset.argtypes = [vp, vp, vp, vp, i64, dbl, i64, vp, vp, vp, ip, vp]
     lib.ftp_status_string.argtypes = [ip]
     lib.ftp_status_string.restype = ctypes.c_char_p
     lib.ftp_last_error.restype = ctypes.c_char_p
@@ -232,3 +242,85 @@ class Plan:
         st = Stats()
         _check(self.lib.ftp_last_stats(self.handle, ctypes.byref(st), _stream_ptr(stream)))
         return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+
+    def learned_dataset(self, t, y, sigma, df: float, n_f: int, R: int = 32, device="cuda", stream=None):
+        """(X bf16 (n_f, d_in), roots float32 (n_f, R), nroots int32 (n_f,)) from one lightcurve."""
+        torch = _torch()
+        t = _dev(t, torch.float64, device)
+        y = _dev(y, torch.float64, device)
+        sigma = _dev(sigma, torch.float64, device)
+        din = 2 * (6 * self.H - 1)
+        X = torch.empty((n_f, din), dtype=torch.bfloat16, device=t.device)
+        roots = torch.zeros((n_f, R), dtype=torch.float32, device=t.device)
+        nroots = torch.zeros(n_f, dtype=torch.int32, device=t.device)
+        _check(self.lib.ftp_learned_dataset(self.handle, _ptr(t), _ptr(y), _ptr(sigma), t.numel(), float(df),
+                                            int(n_f), _ptr(X), _ptr(roots), _ptr(nroots), int(R),
+                                            _stream_ptr(stream)))
+        return X, roots, nroots
+
+
+def mlp_param_count(d_in: int, width: int, d_out: int) -> int:
+    return d_in * width + width + 2 * (width * width + width) + d_out * width + d_out
+
+
+class Mlp:
+    """The root-proposal network on the device (see include/ftp.h)."""
+
+    def __init__(self, d_in: int, width: int, d_out: int, weights=None, seed: int = 0):
+        import numpy as np
+        self.lib = load_library()
+        self.d_in, self.width, self.d_out = d_in, width, d_out
+        h = ctypes.c_void_p()
+        wp = ctypes.c_void_p(0)
+        if weights is not None:
+            self._w = np.ascontiguousarray(weights, dtype=np.float32)
+            if self._w.size != mlp_param_count(d_in, width, d_out):
+                raise ValueError("weight array has the wrong size")
+            wp = self._w.ctypes.data_as(ctypes.c_void_p)
+        _check(self.lib.ftp_mlp_create(ctypes.byref(h), d_in, width, d_out, wp, ctypes.c_uint64(seed)))
+        self.handle = h
+        n = ctypes.c_int64()
+        _check(self.lib.ftp_mlp_num_params(h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.ftp_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self):
+        import numpy as np
+        w = np.empty(self.n_params, dtype=np.float32)
+        _check(self.lib.ftp_mlp_get_weights(self.handle, w.ctypes.data_as(ctypes.c_void_p), self.n_params))
+        return w
+
+    def forward(self, X, stream=None):
+        torch = _torch()
+        X = X.contiguous()
+        assert X.dtype == torch.bfloat16 and X.shape[1] == self.d_in
+        out = torch.empty((X.shape[0], self.d_out), dtype=torch.float32, device=X.device)
+        _check(self.lib.ftp_mlp_forward(self.handle, _ptr(X), X.shape[0], _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def loss_grad(self, X, roots, nroots, lam: float = 0.5, stream=None):
+        torch = _torch()
+        X, roots, nroots = X.contiguous(), roots.contiguous(), nroots.contiguous()
+        B, R = roots.shape
+        loss = torch.empty(B, dtype=torch.float32, device=X.device)
+        grads = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
+        _check(self.lib.ftp_mlp_loss_grad(self.handle, _ptr(X), B, _ptr(roots), _ptr(nroots), R, float(lam),
+                                          _ptr(loss), _ptr(grads), _stream_ptr(stream)))
+        return loss, grads
+
+    def train_step(self, X, roots, nroots, lr: float, lam: float = 0.5, stream=None, loss=None):
+        B, R = roots.shape
+        _check(self.lib.ftp_mlp_train_step(self.handle, _ptr(X), B, _ptr(roots), _ptr(nroots), R, float(lam),
+                                           float(lr), _ptr(loss) if loss is not None else ctypes.c_void_p(0),
+                                           _stream_ptr(stream)))

@@ -44,6 +44,35 @@ hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64
                         hipStream_t st);
 hipError_t launch_gather_sums(int precision, const SolveArgs& a, double* out, int blocks, hipStream_t st);
 hipError_t launch_export_stats(const LcInfo* lcs, double* out, hipStream_t st);
+struct GemmArgs {
+  const uint16_t* A; int64_t a_m, a_k;
+  const uint16_t* B; int64_t b_k, b_n;
+  int64_t M; int N, K;
+  const float* bias;
+  const uint16_t* mask; int64_t ld_mask;
+  int relu;
+  float* Cf; int64_t ld_cf;
+  uint16_t* Cb; int64_t ld_cb;
+};
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
+hipError_t launch_colsum(const float* G, int64_t M, int N, int64_t ld, float* out, hipStream_t st);
+hipError_t launch_chamfer(const float* out, int64_t B, int Kseeds, const float* roots, const int* nroots, int R,
+                          float lam, float* loss_b, float* dout, uint16_t* dout_bf, hipStream_t st);
+hipError_t launch_adam(float* w, uint16_t* wb, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t st);
+hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t st);
+hipError_t launch_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx, int waves, hipStream_t st);
+hipError_t launch_labels(const double* rec, int H, int64_t np, float* roots, int* nroots, int Rmax, int waves,
+                         hipStream_t st);
+struct LearnArgs {
+  double* rec;
+  int64_t np;
+  const float* seeds_out;
+  int64_t* fb_list;
+  unsigned int* fb_count;
+  unsigned flags;
+};
+hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st);
 }  // namespace ftp
 
 using namespace ftp;
@@ -90,6 +119,145 @@ int ilog2_ceil(int64_t v) {
 
 }  // namespace
 
+
+// Root-proposal network: parameters W1, b1, ..., W4, b4 (W stored (out, in)
+// row-major) as FP32 masters with bf16 copies, Adam moments, and the
+// activation buffers of the last batch.
+struct MlpNet {
+  int din = 0, width = 0, dout = 0;
+  int64_t n_params = 0;
+  int64_t oW[4], ob[4];
+  int nin[4], nout[4];
+  DevBuf w32, wbf, grad, am, av, loss;
+  DevBuf xbf, h[3], outf, dout_f, dout_b, dz_f, dz_b[2];
+  int64_t cap_batch = 0;
+  int64_t step = 0;
+
+  void layout() {
+    nin[0] = din; nout[0] = width;
+    nin[1] = width; nout[1] = width;
+    nin[2] = width; nout[2] = width;
+    nin[3] = width; nout[3] = dout;
+    int64_t o = 0;
+    for (int l = 0; l < 4; ++l) {
+      oW[l] = o; o += (int64_t)nin[l] * nout[l];
+      ob[l] = o; o += nout[l];
+    }
+    n_params = o;
+  }
+  int ensure_batch(int64_t B) {
+    if (B <= cap_batch) return FTP_OK;
+    int rc;
+    if ((rc = xbf.ensure(sizeof(uint16_t) * B * din))) return rc;
+    for (int l = 0; l < 3; ++l)
+      if ((rc = h[l].ensure(sizeof(uint16_t) * B * width))) return rc;
+    if ((rc = outf.ensure(sizeof(float) * B * dout))) return rc;
+    if ((rc = dout_f.ensure(sizeof(float) * B * dout))) return rc;
+    if ((rc = dout_b.ensure(sizeof(uint16_t) * B * dout))) return rc;
+    if ((rc = dz_f.ensure(sizeof(float) * B * width))) return rc;
+    for (int l = 0; l < 2; ++l)
+      if ((rc = dz_b[l].ensure(sizeof(uint16_t) * B * width))) return rc;
+    if ((rc = loss.ensure(sizeof(float) * B))) return rc;
+    cap_batch = B;
+    return FTP_OK;
+  }
+  void release() {
+    DevBuf* bs[] = {&w32, &wbf, &grad, &am, &av, &loss, &xbf, &h[0], &h[1], &h[2], &outf, &dout_f, &dout_b,
+                    &dz_f, &dz_b[0], &dz_b[1]};
+    for (DevBuf* b : bs) b->release();
+  }
+};
+
+uint16_t host_f2bf(float x) {
+  unsigned u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Copies FP32 parameters (host) into the net and refreshes the bf16 copies.
+int mlp_set_weights(MlpNet* N, const float* w) {
+  int rc;
+  if ((rc = N->w32.ensure(sizeof(float) * N->n_params))) return rc;
+  if ((rc = N->wbf.ensure(sizeof(uint16_t) * N->n_params))) return rc;
+  std::vector<uint16_t> b(N->n_params);
+  for (int64_t i = 0; i < N->n_params; ++i) b[i] = host_f2bf(w[i]);
+  HIP_TRY(hipMemcpy(N->w32.p, w, sizeof(float) * N->n_params, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(N->wbf.p, b.data(), sizeof(uint16_t) * N->n_params, hipMemcpyHostToDevice));
+  return FTP_OK;
+}
+
+// Forward pass on bf16 inputs X (B x din, row stride din): hidden activations
+// into N->h[0..2] (bf16), output (FP32) into out (row stride dout).
+int mlp_forward(MlpNet* N, const uint16_t* X, int64_t B, float* out, hipStream_t st) {
+  const uint16_t* wb = N->wbf.as<uint16_t>();
+  const float* w32 = N->w32.as<float>();
+  const uint16_t* in = X;
+  int64_t ldin = N->din;
+  for (int l = 0; l < 4; ++l) {
+    GemmArgs g{};
+    g.A = in; g.a_m = ldin; g.a_k = 1;
+    g.B = wb + N->oW[l]; g.b_k = 1; g.b_n = N->nin[l];
+    g.M = B; g.N = N->nout[l]; g.K = N->nin[l];
+    g.bias = w32 + N->ob[l];
+    if (l < 3) {
+      g.relu = 1;
+      g.Cb = N->h[l].as<uint16_t>(); g.ld_cb = N->width;
+    } else {
+      g.Cf = out; g.ld_cf = N->dout;
+    }
+    HIP_TRY(launch_gemm(g, st));
+    if (l < 3) { in = N->h[l].as<uint16_t>(); ldin = N->width; }
+  }
+  return FTP_OK;
+}
+
+// Loss and gradients (into N->grad) for a batch; forward pass included.
+int mlp_loss_grad(MlpNet* N, const uint16_t* X, int64_t B, const float* roots, const int* nroots, int R, float lam,
+                  hipStream_t st) {
+  int rc;
+  if ((rc = N->ensure_batch(B))) return rc;
+  if ((rc = N->grad.ensure(sizeof(float) * N->n_params))) return rc;
+  if ((rc = mlp_forward(N, X, B, N->outf.as<float>(), st))) return rc;
+  HIP_TRY(launch_chamfer(N->outf.as<float>(), B, N->dout / 2, roots, nroots, R, lam, N->loss.as<float>(),
+                         N->dout_f.as<float>(), N->dout_b.as<uint16_t>(), st));
+  const uint16_t* wb = N->wbf.as<uint16_t>();
+  float* gr = N->grad.as<float>();
+  // the upstream gradient of layer l: fp32 (for the bias) and bf16 (for the GEMMs)
+  const float* gf = N->dout_f.as<float>();
+  const uint16_t* gb = N->dout_b.as<uint16_t>();
+  int64_t ldg = N->dout;
+  int cur = 0;
+  for (int l = 3; l >= 0; --l) {
+    const uint16_t* in = l == 0 ? X : N->h[l - 1].as<uint16_t>();
+    const int64_t ldin = l == 0 ? N->din : N->width;
+    // dW_l[o, i] = sum_b g[b, o] in[b, i]
+    GemmArgs gw{};
+    gw.A = gb; gw.a_m = 1; gw.a_k = ldg;
+    gw.B = in; gw.b_k = ldin; gw.b_n = 1;
+    gw.M = N->nout[l]; gw.N = N->nin[l]; gw.K = (int)B;
+    gw.Cf = gr + N->oW[l]; gw.ld_cf = N->nin[l];
+    HIP_TRY(launch_gemm(gw, st));
+    HIP_TRY(launch_colsum(gf, B, N->nout[l], ldg, gr + N->ob[l], st));
+    if (l == 0) break;
+    // g_{l-1}[b, i] = (sum_o g[b, o] W_l[o, i]) * (h_{l-1}[b, i] > 0)
+    GemmArgs gd{};
+    gd.A = gb; gd.a_m = ldg; gd.a_k = 1;
+    gd.B = wb + N->oW[l]; gd.b_k = N->nin[l]; gd.b_n = 1;
+    gd.M = B; gd.N = N->nin[l]; gd.K = N->nout[l];
+    gd.mask = N->h[l - 1].as<uint16_t>(); gd.ld_mask = N->width;
+    gd.Cf = N->dz_f.as<float>(); gd.ld_cf = N->width;
+    gd.Cb = N->dz_b[cur].as<uint16_t>(); gd.ld_cb = N->width;
+    HIP_TRY(launch_gemm(gd, st));
+    gf = N->dz_f.as<float>();
+    gb = N->dz_b[cur].as<uint16_t>();
+    ldg = N->width;
+    cur ^= 1;
+  }
+  return FTP_OK;
+}
+
 struct ftp_plan {
   int H = 0;
   ftp_options opt{};
@@ -115,9 +283,14 @@ struct ftp_plan {
   std::vector<hipEvent_t> ev, evr;
   int ev_used = 0, evr_used = 0;
   // learned
-  DevBuf mlp;
-  int mlp_width = 0;
+  MlpNet net;
   bool mlp_loaded = false;
+  // training-set extraction (ftp_learned_dataset): features and real-root labels
+  uint16_t* ds_X = nullptr;
+  float* ds_roots = nullptr;
+  int* ds_nroots = nullptr;
+  int ds_R = 0;
+  DevBuf xfeat, seeds, fb_list, fb_count;
 };
 
 namespace {
@@ -346,7 +519,9 @@ int solve_grid_waves(ftp_plan* P) {
   return P->n_cu * 16;
 }
 
-// Per-frequency stage over pair chunks: assemble -> companion QR -> score.
+// Per-frequency stage over pair chunks: assemble -> roots -> score.  Roots:
+// companion QR (plain) or network features -> MLP -> Newton + Sturm with the
+// companion QR on the fallback list (learned / uniform-seed ablation).
 int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) {
   if (n_pairs <= 0) return FTP_OK;
   const RecLayout RL(P->H);
@@ -355,16 +530,54 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
   if ((rc = P->rec.ensure(sizeof(double) * (size_t)chunk * RL.stride))) return rc;
   double* rec = P->rec.as<double>();
   const int waves = solve_grid_waves(P);
+  const bool dataset = P->ds_X != nullptr;
+  const int solver = dataset ? FTP_SOLVER_PLAIN : P->opt.solver;
+  if (solver != FTP_SOLVER_PLAIN) {
+    if ((rc = P->fb_list.ensure(sizeof(int64_t) * chunk))) return rc;
+    if ((rc = P->fb_count.ensure(sizeof(unsigned)))) return rc;
+    if (solver == FTP_SOLVER_LEARNED) {
+      if ((rc = P->xfeat.ensure(sizeof(uint16_t) * chunk * P->net.din))) return rc;
+      if ((rc = P->seeds.ensure(sizeof(float) * chunk * P->net.dout))) return rc;
+      if ((rc = P->net.ensure_batch(chunk))) return rc;
+    }
+  }
   for (int64_t p0 = 0; p0 < n_pairs; p0 += chunk) {
     const int64_t np = std::min<int64_t>(chunk, n_pairs - p0);
     const int w = (int)std::min<int64_t>(np, waves);
-    HIP_TRY(launch_assemble(P->opt.precision, a, rec, p0, np, (int)std::min<int64_t>(np, 2 * waves), st));
+    const int w2 = (int)std::min<int64_t>(np, 2 * waves);
+    HIP_TRY(launch_assemble(P->opt.precision, a, rec, p0, np, w2, st));
     hipEvent_t r0 = next_root_event(P);
     if (r0) HIP_TRY(hipEventRecord(r0, st));
-    HIP_TRY(launch_qr(P->H, rec, RL.stride, np, nullptr, nullptr, P->counters.as<SolveCounters>(), w, st));
+    if (solver == FTP_SOLVER_PLAIN) {
+      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, nullptr, nullptr, P->counters.as<SolveCounters>(), w, st));
+    } else {
+      const float* seeds = nullptr;
+      if (solver == FTP_SOLVER_LEARNED) {
+        HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), P->net.din, w2, st));
+        if ((rc = mlp_forward(&P->net, P->xfeat.as<uint16_t>(), np, P->seeds.as<float>(), st))) return rc;
+        seeds = P->seeds.as<float>();
+      }
+      HIP_TRY(hipMemsetAsync(P->fb_count.p, 0, sizeof(unsigned), st));
+      LearnArgs L{};
+      L.rec = rec;
+      L.np = np;
+      L.seeds_out = seeds;
+      L.fb_list = P->fb_list.as<int64_t>();
+      L.fb_count = P->fb_count.as<unsigned>();
+      L.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
+      HIP_TRY(launch_newton_sturm(a, L, w2, st));
+      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, P->fb_list.as<int64_t>(), P->fb_count.as<unsigned>(),
+                        P->counters.as<SolveCounters>(), w, st));
+    }
     hipEvent_t r1 = next_root_event(P);
     if (r1) HIP_TRY(hipEventRecord(r1, st));
-    HIP_TRY(launch_score(a, rec, p0, np, (int)std::min<int64_t>(np, 2 * waves), st));
+    if (dataset) {
+      HIP_TRY(launch_features(rec, P->H, np, P->ds_X + p0 * (int64_t)(2 * (6 * P->H - 1)), 2 * (6 * P->H - 1), w2,
+                              st));
+      HIP_TRY(launch_labels(rec, P->H, np, P->ds_roots + p0 * (int64_t)P->ds_R, P->ds_nroots + p0, P->ds_R, w2, st));
+    } else {
+      HIP_TRY(launch_score(a, rec, p0, np, w2, st));
+    }
   }
   return FTP_OK;
 }
@@ -424,6 +637,7 @@ int run_batch(ftp_plan* P, int64_t n_lc, const int64_t* obs_off, const double* t
               const double* sigma, const double* df, const int64_t* freq_off, double* power, double* phase,
               double* amp, double* offset, uint8_t* status, double* sums_out, hipStream_t st) {
   int rc;
+  if (P->opt.solver == FTP_SOLVER_LEARNED && !P->mlp_loaded && !P->ds_X) return FTP_E_NO_MODEL;
   // chunk by grid memory
   const size_t esz = P->opt.precision == FTP_FP64 ? 16 : 8;
   int64_t lc0 = 0;
@@ -529,7 +743,9 @@ int ftp_plan_destroy(ftp_plan* P) {
   DevBuf* bufs[] = {&P->alpha, &P->twiddle32, &P->twiddle64, &P->lcinfo, &P->obs_off, &P->freq_off,
                     &P->grid_tile_base, &P->pw, &P->py, &P->tile_count, &P->tile_off, &P->cursor,
                     &P->block_sums, &P->total, &P->bucket, &P->grids, &P->fft_tab, &P->fft_items,
-                    &P->counters, &P->stats_out, &P->mlp, &P->rec};
+                    &P->counters, &P->stats_out, &P->rec, &P->xfeat, &P->seeds, &P->fb_list,
+                    &P->fb_count};
+  P->net.release();
   for (DevBuf* b : bufs) b->release();
   if (P->upload_done) (void)hipEventDestroy(P->upload_done);
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
@@ -589,6 +805,7 @@ int ftp_solve_sums(ftp_plan* P, const double* sums, const double* lc_stats, doub
   if (n_f < 1) return FTP_E_NF;
   if (!(lc_stats[2] > 0.0) || !std::isfinite(lc_stats[0]) || !std::isfinite(lc_stats[1])) return FTP_E_OPTION;
   int rc;
+  if (P->opt.solver == FTP_SOLVER_LEARNED && !P->mlp_loaded) return FTP_E_NO_MODEL;
   if ((rc = wait_uploads(P))) return rc;
   hipStream_t st = (hipStream_t)stream;
   P->h_lc.assign(1, LcInfo{});
@@ -620,16 +837,151 @@ int ftp_solve_sums(ftp_plan* P, const double* sums, const double* lc_stats, doub
 
 int ftp_plan_load_mlp(ftp_plan* P, const float* weights, int64_t n_floats, int width) {
   if (!P || !weights) return FTP_E_NULL;
-  const int64_t din = 2 * (6 * P->H - 1), dout = 4 * P->H;
   if (width < 16 || width > 1024 || width % 16) return FTP_E_SIZE;
-  const int64_t need = din * width + width + 2 * (width * width + width) + dout * width + dout;
-  if (n_floats != need) return FTP_E_SIZE;
-  int rc = P->mlp.ensure(sizeof(float) * need);
+  MlpNet& N = P->net;
+  N.din = 2 * (6 * P->H - 1);
+  N.width = width;
+  N.dout = 4 * P->H;
+  N.layout();
+  if (n_floats != N.n_params) return FTP_E_SIZE;
+  int rc = mlp_set_weights(&N, weights);
   if (rc) return rc;
-  HIP_TRY(hipMemcpy(P->mlp.p, weights, sizeof(float) * need, hipMemcpyHostToDevice));
-  P->mlp_width = width;
   P->mlp_loaded = true;
   return FTP_OK;
+}
+
+
+struct ftp_mlp {
+  MlpNet net;
+};
+
+int ftp_mlp_create(ftp_mlp** out, int d_in, int width, int d_out, const float* weights, uint64_t seed) {
+  if (!out) return FTP_E_NULL;
+  *out = nullptr;
+  if (d_in < 1 || d_in > 4096 || width < 16 || width > 1024 || width % 16 || d_out < 2 || d_out > 48 ||
+      d_out % 2)
+    return FTP_E_SIZE;
+  ftp_mlp* M = new ftp_mlp();
+  MlpNet& N = M->net;
+  N.din = d_in;
+  N.width = width;
+  N.dout = d_out;
+  N.layout();
+  std::vector<float> w(N.n_params, 0.f);
+  if (weights) {
+    std::memcpy(w.data(), weights, sizeof(float) * N.n_params);
+  } else {
+    // He-uniform weights, zero biases (splitmix64 stream)
+    uint64_t x = seed;
+    auto next = [&x]() {
+      x += 0x9e3779b97f4a7c15ull;
+      uint64_t z = x;
+      z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+      z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+      return z ^ (z >> 31);
+    };
+    for (int l = 0; l < 4; ++l) {
+      const double lim = std::sqrt(6.0 / N.nin[l]);
+      for (int64_t i = 0; i < (int64_t)N.nin[l] * N.nout[l]; ++i) {
+        const double u = (double)(next() >> 11) * (1.0 / 9007199254740992.0);
+        w[N.oW[l] + i] = (float)((2.0 * u - 1.0) * lim);
+      }
+    }
+  }
+  int rc = mlp_set_weights(&N, w.data());
+  if (!rc) rc = N.am.ensure(sizeof(float) * N.n_params);
+  if (!rc) rc = N.av.ensure(sizeof(float) * N.n_params);
+  if (!rc) rc = N.grad.ensure(sizeof(float) * N.n_params);
+  if (!rc && (hipMemset(N.am.p, 0, sizeof(float) * N.n_params) != hipSuccess ||
+              hipMemset(N.av.p, 0, sizeof(float) * N.n_params) != hipSuccess))
+    rc = FTP_E_HIP;
+  if (rc) {
+    N.release();
+    delete M;
+    return rc;
+  }
+  *out = M;
+  return FTP_OK;
+}
+
+int ftp_mlp_destroy(ftp_mlp* M) {
+  if (!M) return FTP_E_NULL;
+  (void)hipDeviceSynchronize();
+  M->net.release();
+  delete M;
+  return FTP_OK;
+}
+
+int ftp_mlp_num_params(const ftp_mlp* M, int64_t* n) {
+  if (!M || !n) return FTP_E_NULL;
+  *n = M->net.n_params;
+  return FTP_OK;
+}
+
+int ftp_mlp_get_weights(ftp_mlp* M, float* host, int64_t n) {
+  if (!M || !host) return FTP_E_NULL;
+  if (n != M->net.n_params) return FTP_E_SIZE;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(host, M->net.w32.p, sizeof(float) * n, hipMemcpyDeviceToHost));
+  return FTP_OK;
+}
+
+int ftp_mlp_forward(ftp_mlp* M, const uint16_t* X, int64_t B, float* out, void* stream) {
+  if (!M || !X || !out) return FTP_E_NULL;
+  if (B < 1) return FTP_E_SIZE;
+  int rc = M->net.ensure_batch(B);
+  if (rc) return rc;
+  return mlp_forward(&M->net, X, B, out, (hipStream_t)stream);
+}
+
+int ftp_mlp_loss_grad(ftp_mlp* M, const uint16_t* X, int64_t B, const float* roots, const int* nroots, int R,
+                      float lam, float* loss, float* grads, void* stream) {
+  if (!M || !X || !roots || !nroots) return FTP_E_NULL;
+  if (B < 1 || R < 1) return FTP_E_SIZE;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = mlp_loss_grad(&M->net, X, B, roots, nroots, R, lam, st);
+  if (rc) return rc;
+  if (loss) HIP_TRY(hipMemcpyAsync(loss, M->net.loss.p, sizeof(float) * B, hipMemcpyDeviceToDevice, st));
+  if (grads)
+    HIP_TRY(hipMemcpyAsync(grads, M->net.grad.p, sizeof(float) * M->net.n_params, hipMemcpyDeviceToDevice, st));
+  return FTP_OK;
+}
+
+int ftp_mlp_train_step(ftp_mlp* M, const uint16_t* X, int64_t B, const float* roots, const int* nroots, int R,
+                       float lam, float lr, float* loss, void* stream) {
+  if (!M || !X || !roots || !nroots) return FTP_E_NULL;
+  if (B < 1 || R < 1 || !(lr > 0.f)) return FTP_E_SIZE;
+  hipStream_t st = (hipStream_t)stream;
+  MlpNet& N = M->net;
+  int rc = mlp_loss_grad(&N, X, B, roots, nroots, R, lam, st);
+  if (rc) return rc;
+  N.step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)N.step), c2 = 1.f - std::pow(b2, (float)N.step);
+  HIP_TRY(launch_adam(N.w32.as<float>(), N.wbf.as<uint16_t>(), N.grad.as<float>(), N.am.as<float>(),
+                      N.av.as<float>(), N.n_params, lr, b1, b2, 1e-8f, c1, c2, st));
+  if (loss) HIP_TRY(hipMemcpyAsync(loss, N.loss.p, sizeof(float) * B, hipMemcpyDeviceToDevice, st));
+  return FTP_OK;
+}
+
+int ftp_learned_dataset(ftp_plan* P, const double* t, const double* y, const double* sigma, int64_t n_obs,
+                        double df, int64_t n_f, uint16_t* X, float* roots, int* nroots, int R, void* stream) {
+  if (!P || !t || !y || !sigma || !X || !roots || !nroots) return FTP_E_NULL;
+  int rc = validate_scalars(df, n_f, n_obs);
+  if (rc) return rc;
+  if (R < 1 || R > 64) return FTP_E_SIZE;
+  const int64_t obs_off[2] = {0, n_obs};
+  const int64_t freq_off[2] = {0, n_f};
+  P->ds_X = X;
+  P->ds_roots = roots;
+  P->ds_nroots = nroots;
+  P->ds_R = R;
+  rc = run_batch(P, 1, obs_off, t, y, sigma, &df, freq_off, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                 (hipStream_t)stream);
+  P->ds_X = nullptr;
+  P->ds_roots = nullptr;
+  P->ds_nroots = nullptr;
+  return rc;
 }
 
 int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {

@@ -1,0 +1,231 @@
+// Learned root proposal (a project addition to the method): Newton on the
+// real phase polynomial from network seeds, verified by a Sturm count.
+//
+// For each frequency (one wavefront):
+//   * 2H seeds (network output, or evenly spaced for the ablation) are
+//     refined by FP64 Newton on R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta
+//     (Eq. theta2cond written as R(theta) = i e^{-i K theta} p(e^{i theta}));
+//   * converged roots closer than 1e-8 rad are merged;
+//   * the number of distinct real roots of R is counted with Sturm sequences
+//     of the Cayley polynomial f(x) (theta = phi0 + 2 atan x) on two half
+//     circles: x in (-1, 1] for f and for x^D f(-1/x) (the map rotated by pi);
+//   * if the Sturm sequence is well determined and the counts agree, the
+//     Newton roots are the candidate set; otherwise the frequency goes to the
+//     companion-matrix solve through a device work list.
+#include "ftp_solve_common.h"
+
+namespace ftp {
+
+__device__ __forceinline__ void lwave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ double lrdlane(double v, int src) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), src);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+// Distinct real roots of the degree-D polynomial g (LDS, coefficients c =
+// 0..D, g[D] != 0) in (-1, 1] by a Sturm sequence evaluated at x = -1 and
+// x = 1.  Buffers b0, b1, b2 hold D + 1 doubles each.  Returns -1 when the
+// sequence ends in a non-constant gcd (repeated or nearly repeated roots) or a
+// step loses its leading term, i.e. when the count is not trustworthy.
+__device__ int sturm_count_unit(const double* g, int D, double* b0, double* b1, double* b2, int lane) {
+  double* A = b0;
+  double* B = b1;
+  double* C = b2;
+  // A = g / max|g|, B = g' / max|g'|
+  double ma = 0.0, mb = 0.0;
+  for (int c = lane; c <= D; c += 64) {
+    ma = fmax(ma, fabs(g[c]));
+    if (c < D) mb = fmax(mb, fabs((c + 1) * g[c + 1]));
+  }
+  ma = wave_max(ma);
+  mb = wave_max(mb);
+  if (!(ma > 0.0) || !(mb > 0.0)) return -1;
+  for (int c = lane; c <= D; c += 64) {
+    A[c] = g[c] / ma;
+    if (c < D) B[c] = (c + 1) * g[c + 1] / mb;
+  }
+  lwave_sync();
+  int da = D, db = D - 1;
+  // sign changes at x = -1 and x = +1
+  double pm = 0.0, pp = 0.0;     // previous non-zero signs
+  int vm = 0, vp = 0;
+  auto push = [&](const double* Pp, int deg) {
+    double s1 = 0.0, sm1 = 0.0;
+    for (int c = lane; c <= deg; c += 64) {
+      s1 += Pp[c];
+      sm1 += (c & 1) ? -Pp[c] : Pp[c];
+    }
+    s1 = sgn(wave_sum(s1));
+    sm1 = sgn(wave_sum(sm1));
+    if (s1 != 0.0) { if (pp != 0.0 && s1 != pp) ++vp; pp = s1; }
+    if (sm1 != 0.0) { if (pm != 0.0 && sm1 != pm) ++vm; pm = sm1; }
+  };
+  push(A, da);
+  push(B, db);
+  while (db > 0) {
+    // C = A mod B by long division, then negate
+    for (int c = lane; c <= da; c += 64) C[c] = A[c];
+    lwave_sync();
+    const double bl = B[db];
+    for (int i = da - db; i >= 0; --i) {
+      const double q = C[db + i] / bl;
+      for (int c = lane; c <= db; c += 64) C[c + i] -= q * B[c];
+      lwave_sync();
+    }
+    double mr = 0.0;
+    for (int c = lane; c < db; c += 64) mr = fmax(mr, fabs(C[c]));
+    mr = wave_max(mr);
+    if (!(mr > 1e-12)) return -1;   // remainder vanishes: gcd of positive degree
+    // degree of the remainder: highest c < db with |C[c]| > 1e-13 mr
+    int dc = -1;
+    for (int base = 0; base < db; base += 64) {
+      const int c = base + lane;
+      const bool nz = c < db && fabs(C[c]) > 1e-13 * mr;
+      const unsigned long long m = __ballot(nz);
+      if (m) dc = base + 63 - __clzll(m);
+    }
+    // a generic remainder has degree db - 1; a lost leading term means the
+    // sequence is ill-determined in floating point
+    if (dc != db - 1) return -1;
+    const double inv = -1.0 / mr;
+    for (int c = lane; c <= dc; c += 64) C[c] *= inv;
+    lwave_sync();
+    push(C, dc);
+    double* t = A;
+    A = B;
+    B = C;
+    C = t;
+    da = db;
+    db = dc;
+  }
+  return vm - vp;
+}
+
+struct LearnArgs {
+  double* rec;
+  int64_t np;
+  const float* seeds_out;   // network output, np x 4H (u, v pairs); nullptr = uniform seeds
+  int64_t* fb_list;
+  unsigned int* fb_count;
+  unsigned flags;
+};
+
+__host__ __device__ inline size_t learn_lds_bytes(int H) {
+  const int K = 3 * H - 1, D = 2 * K;
+  return (size_t)(2 * (K + 1) + 5 * (D + 1) + 8) * sizeof(double);
+}
+
+__global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
+  extern __shared__ double sml[];
+  const int lane = threadIdx.x & 63;
+  const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H;
+  const RecLayout RL(H);
+  FreqWork W;
+  W.r = reinterpret_cast<double2*>(sml);
+  double* g2 = sml + 2 * (K + 1);        // reflected polynomial x^D f(-1/x)
+  double* b0 = g2 + (D + 1);
+  double* b1 = b0 + (D + 1);
+  double* b2 = b1 + (D + 1);
+  double* fl = b2 + (D + 1);             // f copied to LDS
+  unsigned long long iters_acc = 0, roots_acc = 0, fb_acc = 0;
+  for (int64_t w = blockIdx.x; w < L.np; w += gridDim.x) {
+    double* R = L.rec + w * (int64_t)RL.stride;
+    const int st = (int)R[RL.meta + M_STATUS];
+    if (st == ST_BAD_LC || st == ST_CONSTANT) continue;
+    if (L.flags & 1u) {   // forced fallback
+      if (lane == 0) {
+        const unsigned slot = atomicAdd(L.fb_count, 1u);
+        L.fb_list[slot] = w;
+        R[RL.meta + M_FALLBACK] = 1.0;
+      }
+      ++fb_acc;
+      continue;
+    }
+    for (int d = lane; d <= K; d += 64) W.r[d] = make_double2(R[RL.r + 2 * d], R[RL.r + 2 * d + 1]);
+    for (int c = lane; c <= D; c += 64) {
+      const double fc = R[RL.f + c];
+      fl[c] = fc;
+      g2[D - c] = (c & 1) ? -fc : fc;
+    }
+    lwave_sync();
+    // Newton from the seeds (lane k < 2H)
+    double th = 0.0;
+    bool conv = false;
+    int its = 0;
+    if (lane < S) {
+      if (L.seeds_out) {
+        const float* o = L.seeds_out + w * 2 * S;
+        th = atan2((double)o[2 * lane + 1], (double)o[2 * lane]) - R[RL.meta + M_CANON];
+      } else {
+        th = kTwoPi * (lane + 0.5) / S;
+      }
+      for (its = 0; its < 16; ++its) {
+        double Rv, dR;
+        eval_R(W, H, th, Rv, dR);
+        if (!(dR != 0.0)) break;
+        double step = Rv / dR;
+        if (!isfinite(step)) break;
+        step = fmax(-0.5, fmin(0.5, step));
+        th -= step;
+        if (fabs(step) < 1e-12) { conv = true; break; }
+      }
+      th = fmod(th, kTwoPi);
+      if (th < 0.0) th += kTwoPi;
+    }
+    iters_acc += (unsigned long long)wave_sum((double)(lane < S ? its : 0));
+    // merge roots closer than 1e-8 rad (keep the lowest lane)
+    bool uniq = conv;
+    for (int j = 0; j < S; ++j) {
+      const double tj = lrdlane(th, j);
+      const bool cj = __builtin_amdgcn_readlane((int)conv, j) != 0;
+      double dd = fabs(tj - th);
+      dd = fmin(dd, kTwoPi - dd);
+      if (cj && j < lane && dd < 1e-8) uniq = false;
+    }
+    const unsigned long long um = __ballot(uniq && lane < S);
+    const int nu = __popcll(um);
+    // Sturm counts on the two half circles
+    const int c1 = sturm_count_unit(fl, D, b0, b1, b2, lane);
+    int cnt = -1;
+    if (c1 >= 0) {
+      const int c2 = sturm_count_unit(g2, D, b0, b1, b2, lane);
+      if (c2 >= 0) cnt = c1 + c2;
+    }
+    if (cnt >= 0 && cnt == nu) {
+      const int pos = __popcll(um & ((1ull << lane) - 1ull));
+      double* cand = R + RL.cand;
+      for (int c = lane; c < D; c += 64) cand[c] = __longlong_as_double(0x7ff8000000000000ll);
+      lwave_sync();
+      if (uniq && lane < S) cand[pos] = th;
+      roots_acc += (unsigned long long)nu;
+    } else {
+      if (lane == 0) {
+        const unsigned slot = atomicAdd(L.fb_count, 1u);
+        L.fb_list[slot] = w;
+        R[RL.meta + M_FALLBACK] = 1.0;
+      }
+      ++fb_acc;
+    }
+    lwave_sync();
+  }
+  if (lane == 0 && a.counters) {
+    if (iters_acc) atomicAdd(&a.counters->newton_iters, iters_acc);
+    if (roots_acc) atomicAdd(&a.counters->roots_found, roots_acc);
+    if (fb_acc) atomicAdd(&a.counters->fallback, fb_acc);
+  }
+}
+
+hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st) {
+  hipLaunchKernelGGL(k_newton_sturm, dim3((unsigned)waves), dim3(64), learn_lds_bytes(a.H), st, a, L);
+  return hipGetLastError();
+}
+
+}  // namespace ftp

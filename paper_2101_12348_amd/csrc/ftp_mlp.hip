@@ -1,0 +1,319 @@
+// Root-proposal network of the learned solve (a project addition to the
+// method): an MLP d_in -> W -> W -> W -> 4H with ReLU, BF16 weights and
+// activations, FP32 accumulation on the gfx950 matrix cores
+// (v_mfma_f32_16x16x32_bf16), trained on the device by its own forward and
+// backward kernels with Adam on FP32 master weights.
+//
+// Input features of a frequency: the coefficients p_k, k = 0..D, of the phase
+// polynomial (Eq. finalpoly), rotated to a canonical phase (r_1 real and
+// positive, where p(e^{i theta}) = -i e^{i K theta} sum_d r_d e^{i d theta}) and
+// scaled to max |p_k| = 1, as (Re, Im) pairs: d_in = 2 (D + 1).
+// Output: 2H (u, v) pairs; seed k is atan2(v_k, u_k) in the canonical frame.
+#include "ftp_solve_common.h"
+
+namespace ftp {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__host__ __device__ inline uint16_t f2bf(float x) {
+  unsigned u;
+  memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(uint16_t b) {
+  unsigned u = (unsigned)b << 16;
+  float x;
+  memcpy(&x, &u, 4);
+  return x;
+}
+
+// ------------------------------------------------------------------ GEMM
+
+// C[m, n] = sum_k A[m, k] B[k, n] with A, B in bf16 at arbitrary strides and
+// FP32 accumulation.  Epilogue: + bias[n], optional ReLU, optional ReLU mask
+// (C *= (maskB[m, n] > 0) with maskB bf16), FP32 and/or bf16 stores.
+struct GemmArgs {
+  const uint16_t* A; int64_t a_m, a_k;
+  const uint16_t* B; int64_t b_k, b_n;
+  int64_t M; int N, K;
+  const float* bias;
+  const uint16_t* mask; int64_t ld_mask;
+  int relu;
+  float* Cf; int64_t ld_cf;
+  uint16_t* Cb; int64_t ld_cb;
+};
+
+constexpr int kGT = 64;   // output tile (M and N) per workgroup
+constexpr int kGK = 32;   // K step (one MFMA)
+constexpr int kGP = 40;   // padded LDS row (bf16 elements)
+
+// 256 threads = 4 waves; wave w owns the 32 x 32 quadrant (w / 2, w % 2) of
+// the 64 x 64 tile as 2 x 2 MFMA 16 x 16 x 32 blocks.  Operand fragments (lane
+// l): A rows l % 16 with k = 8 (l / 16) .. + 7; B columns l % 16, same k; result
+// rows 4 (l / 16) + v, column l % 16 (v = 0..3).
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  __shared__ uint16_t As[kGT * kGP];
+  __shared__ uint16_t Bs[kGT * kGP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * kGT;
+  const int n0 = blockIdx.y * kGT;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4_t acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid >> 2, lk = (tid & 3) * 8;   // loader: row 0..63, k 0/8/16/24
+  for (int k0 = 0; k0 < g.K; k0 += kGK) {
+    {
+      const int64_t m = m0 + lr;
+      uint16_t* dst = As + lr * kGP + lk;
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + lk + q;
+        dst[q] = (m < g.M && k < g.K) ? g.A[m * g.a_m + (int64_t)k * g.a_k] : (uint16_t)0;
+      }
+      const int n = n0 + lr;
+      uint16_t* dstb = Bs + lr * kGP + lk;
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + lk + q;
+        dstb[q] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.b_k + (int64_t)n * g.b_n] : (uint16_t)0;
+      }
+    }
+    __syncthreads();
+    for (int i = 0; i < 2; ++i) {
+      const uint16_t* ap = As + (wm + i * 16 + (lane & 15)) * kGP + 8 * (lane >> 4);
+      bf16x8_t af;
+      memcpy(&af, ap, 16);
+      for (int j = 0; j < 2; ++j) {
+        const uint16_t* bp = Bs + (wn + j * 16 + (lane & 15)) * kGP + 8 * (lane >> 4);
+        bf16x8_t bfv;
+        memcpy(&bfv, bp, 16);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfv, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i) {
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn + j * 16 + (lane & 15);
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
+        if (m >= g.M || n >= g.N) continue;
+        float x = acc[i][j][v];
+        if (g.bias) x += g.bias[n];
+        if (g.relu) x = fmaxf(x, 0.f);
+        if (g.mask) {
+          const uint16_t mb = g.mask[m * g.ld_mask + n];
+          if ((mb & 0x8000u) || (mb & 0x7fffu) == 0) x = 0.f;
+        }
+        if (g.Cf) g.Cf[m * g.ld_cf + n] = x;
+        if (g.Cb) g.Cb[m * g.ld_cb + n] = f2bf(x);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------- small kernels
+
+// db[n] = sum_m G[m, n] (G fp32, row stride ld)
+__global__ __launch_bounds__(256) void k_colsum(const float* G, int64_t M, int N, int64_t ld, float* out) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int64_t m = 0; m < M; ++m) s += G[m * ld + n];
+  out[n] = s;
+}
+
+// Chamfer loss on the circle between seed vectors e_k = (u_k, v_k) and root
+// unit vectors r_j = (cos, sin) (one thread per sample):
+//   L_b = (1/n) sum_j min_k |e_k - r_j|^2 + lam (1/K) sum_k min_j |e_k - r_j|^2,
+// loss = mean_b L_b; dout = dL/dout (fp32 and bf16).
+__global__ __launch_bounds__(256) void k_chamfer(const float* out, int64_t B, int Kseeds, const float* roots,
+                                                 const int* nroots, int R, float lam, float* loss_b, float* dout,
+                                                 uint16_t* dout_bf) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  const float* o = out + b * 2 * Kseeds;
+  float g[2 * 24];
+  for (int q = 0; q < 2 * Kseeds; ++q) g[q] = 0.f;
+  const int n = nroots[b] < R ? nroots[b] : R;
+  float L = 0.f;
+  const float invB = 1.f / (float)B;
+  if (n > 0) {
+    for (int jr = 0; jr < n; ++jr) {
+      float sn, cs;
+      sincosf(roots[b * R + jr], &sn, &cs);
+      int kb = 0;
+      float db = 3.4e38f;
+      for (int k = 0; k < Kseeds; ++k) {
+        const float du = o[2 * k] - cs, dv = o[2 * k + 1] - sn;
+        const float d2 = du * du + dv * dv;
+        if (d2 < db) { db = d2; kb = k; }
+      }
+      L += db / n;
+      g[2 * kb] += 2.f * (o[2 * kb] - cs) / n;
+      g[2 * kb + 1] += 2.f * (o[2 * kb + 1] - sn) / n;
+    }
+    for (int k = 0; k < Kseeds; ++k) {
+      float db = 3.4e38f, bu = 0.f, bv = 0.f;
+      for (int jr = 0; jr < n; ++jr) {
+        float sn, cs;
+        sincosf(roots[b * R + jr], &sn, &cs);
+        const float du = o[2 * k] - cs, dv = o[2 * k + 1] - sn;
+        const float d2 = du * du + dv * dv;
+        if (d2 < db) { db = d2; bu = du; bv = dv; }
+      }
+      L += lam * db / Kseeds;
+      g[2 * k] += lam * 2.f * bu / Kseeds;
+      g[2 * k + 1] += lam * 2.f * bv / Kseeds;
+    }
+  }
+  loss_b[b] = L;
+  for (int q = 0; q < 2 * Kseeds; ++q) {
+    const float v = g[q] * invB;
+    dout[b * 2 * Kseeds + q] = v;
+    dout_bf[b * 2 * Kseeds + q] = f2bf(v);
+  }
+}
+
+// Adam (Kingma & Ba 2015) on FP32 master weights; writes the bf16 copy.
+__global__ __launch_bounds__(256) void k_adam(float* w, uint16_t* wb, const float* g, float* m, float* v,
+                                              int64_t n, float lr, float b1, float b2, float eps, float c1,
+                                              float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  wb[i] = f2bf(wi);
+}
+
+__global__ __launch_bounds__(256) void k_f32_to_bf16(const float* x, uint16_t* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+// Network features of pairs [0, np) of a record chunk: canonical rotation
+// (stored in the record) and normalised coefficients of p as bf16.
+__global__ __launch_bounds__(64) void k_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx) {
+  const RecLayout RL(H);
+  const int K = RL.K, D = RL.D;
+  const int lane = threadIdx.x & 63;
+  for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
+    double* R = rec + w * (int64_t)RL.stride;
+    const int st = (int)R[RL.meta + M_STATUS];
+    uint16_t* x = X + w * ldx;
+    if (st == ST_BAD_LC || st == ST_CONSTANT) {
+      for (int q = lane; q < 2 * (D + 1); q += 64) x[q] = 0;
+      continue;
+    }
+    const double2 r1 = make_double2(R[RL.r + 2], R[RL.r + 3]);
+    const double canon = (r1.x == 0.0 && r1.y == 0.0) ? 0.0 : atan2(r1.y, r1.x);
+    // p_{K+d} = -i r'_d with r'_d = r_d e^{-i d canon}, r'_{-d} = conj(r'_d)
+    double re = 0.0, im = 0.0, amax = 0.0;
+    for (int k = lane; k <= D; k += 64) {
+      const int d = k - K;
+      const int ad = d < 0 ? -d : d;
+      double2 rd = make_double2(R[RL.r + 2 * ad], R[RL.r + 2 * ad + 1]);
+      double sn, cs;
+      sincos(-(double)ad * canon, &sn, &cs);
+      rd = cmul(rd, make_double2(cs, sn));
+      if (d < 0) rd = cconj(rd);
+      re = rd.y;      // -i (a + i b) = b - i a
+      im = -rd.x;
+      amax = fmax(amax, sqrt(re * re + im * im));
+    }
+    amax = wave_max(amax);
+    const double sc = amax > 0.0 ? 1.0 / amax : 0.0;
+    for (int k = lane; k <= D; k += 64) {
+      const int d = k - K;
+      const int ad = d < 0 ? -d : d;
+      double2 rd = make_double2(R[RL.r + 2 * ad], R[RL.r + 2 * ad + 1]);
+      double sn, cs;
+      sincos(-(double)ad * canon, &sn, &cs);
+      rd = cmul(rd, make_double2(cs, sn));
+      if (d < 0) rd = cconj(rd);
+      x[2 * k] = f2bf((float)(rd.y * sc));
+      x[2 * k + 1] = f2bf((float)(-rd.x * sc));
+    }
+    if (lane == 0) R[RL.meta + M_CANON] = canon;
+  }
+}
+
+// Training labels: the real roots found by the companion solve, in the
+// canonical frame (theta + canon, wrapped to [0, 2 pi)), up to Rmax per pair.
+__global__ __launch_bounds__(64) void k_labels(const double* rec, int H, int64_t np, float* roots, int* nroots,
+                                               int Rmax) {
+  const RecLayout RL(H);
+  const int lane = threadIdx.x & 63;
+  for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
+    const double* R = rec + w * (int64_t)RL.stride;
+    const int st = (int)R[RL.meta + M_STATUS];
+    bool real = false;
+    double th = 0.0;
+    if (st == ST_OK && lane < RL.D) {
+      const unsigned lo = (unsigned)R[RL.meta + M_REAL_LO], hi = (unsigned)R[RL.meta + M_REAL_HI];
+      const unsigned long long msk = ((unsigned long long)hi << 32) | lo;
+      real = (msk >> lane) & 1ull;
+      th = R[RL.cand + lane] + R[RL.meta + M_CANON];
+      th = fmod(th, kTwoPi);
+      if (th < 0.0) th += kTwoPi;
+    }
+    const unsigned long long m = __ballot(real);
+    const int pos = __popcll(m & ((1ull << lane) - 1ull));
+    if (real && pos < Rmax) roots[w * Rmax + pos] = (float)th;
+    if (lane == 0) nroots[w] = __popcll(m) < Rmax ? __popcll(m) : Rmax;
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  dim3 grid((unsigned)((g.M + kGT - 1) / kGT), (unsigned)((g.N + kGT - 1) / kGT));
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* G, int64_t M, int N, int64_t ld, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, G, M, N, ld, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_chamfer(const float* out, int64_t B, int Kseeds, const float* roots, const int* nroots, int R,
+                          float lam, float* loss_b, float* dout, uint16_t* dout_bf, hipStream_t st) {
+  hipLaunchKernelGGL(k_chamfer, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, out, B, Kseeds, roots,
+                     nroots, R, lam, loss_b, dout, dout_bf);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* w, uint16_t* wb, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, wb, g, m, v, n, lr, b1, b2,
+                     eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx, int waves, hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3((unsigned)waves), dim3(64), 0, st, rec, H, np, X, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_labels(const double* rec, int H, int64_t np, float* roots, int* nroots, int Rmax, int waves,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_labels, dim3((unsigned)waves), dim3(64), 0, st, rec, H, np, roots, nroots, Rmax);
+  return hipGetLastError();
+}
+
+}  // namespace ftp

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, 
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
     const int64_t q = list ? list[w] : w;
     double* R = rec + q * (int64_t)stride;
-    const int st = (int)R[RL.meta + 2];
+    const int st = (int)R[RL.meta + M_STATUS];
     if (st == ST_BAD_LC || st == ST_CONSTANT) continue;
     const double* f = R + RL.f;
     const double lead = f[N];
@@ -228,16 +228,23 @@ __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, 
     wave_sync();
     const int sw = hqr_wave<N>(A, wr, wi, lane);
     if (sw < 0) {
-      if (lane == 0) R[RL.meta + 2] = (double)ST_NO_CONVERGE;
+      if (lane == 0) R[RL.meta + M_STATUS] = (double)ST_NO_CONVERGE;
     } else {
       sweeps_acc += (unsigned long long)sw;
     }
-    const double phi0 = R[RL.meta + 0];
+    const double phi0 = R[RL.meta + M_PHI0];
+    bool real = false;
     if (lane < N) {
       const double xr = wr[lane], xi = wi[lane];
       double th = __longlong_as_double(0x7ff8000000000000ll);
       if (xi >= 0.0 && isfinite(xr) && isfinite(xi)) th = phi0 + atan2(xr, 1.0 - xi) + atan2(xr, 1.0 + xi);
+      real = xi == 0.0 && isfinite(xr);
       R[RL.cand + lane] = th;
+    }
+    const unsigned long long rmask = __ballot(real);
+    if (lane == 0) {
+      R[RL.meta + M_REAL_LO] = (double)(unsigned)(rmask & 0xffffffffull);
+      R[RL.meta + M_REAL_HI] = (double)(unsigned)(rmask >> 32);
     }
     wave_sync();
   }
@@ -311,7 +318,11 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
     const LcInfo& L = a.lcs[lc];
     const int64_t j = pidx - a.freq_off[lc] + 1;
     if (L.status != 0) {
-      if (lane == 0) { Rr[RL.meta + 2] = (double)ST_BAD_LC; Rr[RL.meta + 3] = (double)lc; }
+      if (lane == 0) {
+        Rr[RL.meta + M_STATUS] = (double)ST_BAD_LC;
+        Rr[RL.meta + M_LC] = (double)lc;
+        Rr[RL.meta + M_FALLBACK] = 0.0;
+      }
       continue;
     }
     const double ref = ref_cycles(j, L.df, L.tref);
@@ -377,10 +388,11 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
       Rr[RL.zw + 2 * k + 1] = W.Z[k + 1].y;
     }
     if (lane == 0) {
-      Rr[RL.meta + 0] = phi0;
-      Rr[RL.meta + 1] = ref;
-      Rr[RL.meta + 2] = constant ? (double)ST_CONSTANT : (double)ST_OK;
-      Rr[RL.meta + 3] = (double)lc;
+      Rr[RL.meta + M_PHI0] = phi0;
+      Rr[RL.meta + M_REF] = ref;
+      Rr[RL.meta + M_STATUS] = constant ? (double)ST_CONSTANT : (double)ST_OK;
+      Rr[RL.meta + M_LC] = (double)lc;
+      Rr[RL.meta + M_FALLBACK] = 0.0;
     }
     wave_sync();
   }
@@ -452,8 +464,8 @@ __global__ __launch_bounds__(64) void k_score(SolveArgs a, const double* rec, in
   for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
     const int64_t pidx = p0 + w;
     const double* Rr = rec + w * (int64_t)RL.stride;
-    const int st = (int)Rr[RL.meta + 2];
-    const int64_t lc = (int64_t)Rr[RL.meta + 3];
+    const int st = (int)Rr[RL.meta + M_STATUS];
+    const int64_t lc = (int64_t)Rr[RL.meta + M_LC];
     const LcInfo& L = a.lcs[lc];
     if (st == ST_BAD_LC) {
       if (lane == 0) {
@@ -462,7 +474,7 @@ __global__ __launch_bounds__(64) void k_score(SolveArgs a, const double* rec, in
       }
       continue;
     }
-    const double ref = Rr[RL.meta + 1];
+    const double ref = Rr[RL.meta + M_REF];
     for (int d = lane; d <= K; d += 64) W.r[d] = make_double2(Rr[RL.r + 2 * d], Rr[RL.r + 2 * d + 1]);
     for (int e = lane; e <= 2 * H; e += 64) W.mu[e] = make_double2(Rr[RL.mu + 2 * e], Rr[RL.mu + 2 * e + 1]);
     for (int k = lane; k < H; k += 64) {
@@ -516,7 +528,7 @@ __global__ __launch_bounds__(64) void k_score(SolveArgs a, const double* rec, in
       a.phase[pidx] = th_abs;
       a.amp[pidx] = amp;
       a.offset[pidx] = off;
-      if (a.status) a.status[pidx] = (uint8_t)stout;
+      if (a.status) a.status[pidx] = (uint8_t)(stout | (Rr[RL.meta + M_FALLBACK] != 0.0 ? ST_FALLBACK : 0));
     }
     wave_sync();
   }

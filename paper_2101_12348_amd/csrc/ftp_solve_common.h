@@ -58,9 +58,19 @@ __host__ __device__ inline size_t solve_lds_bytes(int H) {
 }
 // Per-pair record in HBM passed between the assemble, root and score kernels
 // (doubles): r_d (d = 0..K, complex), mu_e (e = 0..2H, complex), eta_k and
-// Z_w(k) (k = 1..H, complex), meta {phi0, ref cycles, status, unused},
-// f_c (c = 0..D, the Cayley polynomial) and D root candidates theta (NaN =
-// none).
+// Z_w(k) (k = 1..H, complex), meta (see the M_* slots), f_c (c = 0..D, the
+// Cayley polynomial) and D root candidates theta (NaN = none).
+enum : int {
+  M_PHI0 = 0,      // Cayley rotation phi0
+  M_REF = 1,       // frac(f_j t_ref) in cycles
+  M_STATUS = 2,    // ST_* code driving the kernels
+  M_LC = 3,        // lightcurve index within the chunk
+  M_CANON = 4,     // canonical rotation of the network features (arg r_1)
+  M_REAL_LO = 5,   // bit mask of real companion eigenvalues (low / high 32 lanes)
+  M_REAL_HI = 6,
+  M_FALLBACK = 7,  // 1 if the learned proposal fell back to the companion solve
+  M_SLOTS = 8,
+};
 struct RecLayout {
   int K, D, r, mu, eta, zw, meta, f, cand, stride;
   __host__ __device__ explicit RecLayout(int H) {
@@ -71,7 +81,7 @@ struct RecLayout {
     eta = mu + 2 * (2 * H + 1);
     zw = eta + 2 * H;
     meta = zw + 2 * H;
-    f = meta + 4;
+    f = meta + M_SLOTS;
     cand = f + D + 1;
     stride = (cand + D + 3) & ~3;
   }

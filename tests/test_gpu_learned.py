@@ -1,0 +1,147 @@
+"""GPU checks of the learned root proposal.
+
+* The network's forward pass and gradients (bf16 MFMA, FP32 accumulation)
+  against the FP64 reference with the same bf16 rounding points.
+* Training lowers the loss.
+* The learned and uniform-seed solvers give the same periodogram as the
+  companion solve (every accepted frequency has all real roots, verified by the
+  Sturm count; the others fall back to the companion solve).
+* Forcing the fallback reproduces the companion solve bit for bit.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as MO
+from synthetic import single_long_case, tiny_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ftp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2101_12348_amd as F
+    F.load_library()
+    return F
+
+
+def _params_from_flat(w, din, width, dout):
+    dims = [din, width, width, width, dout]
+    p, o = {}, 0
+    for l in range(4):
+        n_in, n_out = dims[l], dims[l + 1]
+        p["W" + MO.LAYER_NAMES[l]] = w[o: o + n_in * n_out].reshape(n_out, n_in).astype(np.float64)
+        o += n_in * n_out
+        p["b" + MO.LAYER_NAMES[l]] = w[o: o + n_out].astype(np.float64)
+        o += n_out
+    return p
+
+
+def _flat(grads):
+    return np.concatenate([np.r_[grads["W" + k].ravel(), grads["b" + k].ravel()] for k in MO.LAYER_NAMES])
+
+
+@pytest.mark.parametrize("B,din,width,dout", [(37, 22, 32, 8), (300, 70, 256, 24)])
+def test_mlp_forward_and_gradients_match_reference(ftp, B, din, width, dout):
+    import torch
+    rng = np.random.default_rng(B)
+    w = np.concatenate([np.r_[rng.uniform(-1, 1, (n_out, n_in)).ravel() * np.sqrt(3.0 / n_in),
+                              0.1 * rng.standard_normal(n_out)]
+                        for n_in, n_out in [(din, width), (width, width), (width, width), (width, dout)]])
+    w = w.astype(np.float32)
+    net = ftp.Mlp(din, width, dout, weights=w)
+    X = rng.standard_normal((B, din)).astype(np.float32)
+    Xb = torch.as_tensor(X, device="cuda").to(torch.bfloat16)
+    R = 6
+    roots = rng.uniform(0, 2 * np.pi, (B, R)).astype(np.float32)
+    nroots = rng.integers(0, R + 1, B).astype(np.int32)
+    out = net.forward(Xb).cpu().numpy()
+    params = _params_from_flat(w.astype(np.float64), din, width, dout)
+    Xr = Xb.float().cpu().numpy().astype(np.float64)
+    ref, cache = MO.forward(params, Xr, emulate_bf16=True)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(out - ref)) <= 1e-2 * scale
+    loss, grads = net.loss_grad(Xb, torch.as_tensor(roots, device="cuda"),
+                                torch.as_tensor(nroots, device="cuda"), lam=0.5)
+    torch.cuda.synchronize()
+    # reference gradients at the GPU's own output (same rounding points)
+    L_ref, dout_ref = MO.chamfer_loss(out.astype(np.float64), roots.astype(np.float64), nroots, lam=0.5)
+    g_ref = _flat(MO.backward(params, cache, dout_ref, emulate_bf16=True))
+    g = grads.cpu().numpy().astype(np.float64)
+    # the per-sample losses average to the batch loss
+    assert abs(float(loss.mean().cpu()) - L_ref) <= 1e-4 * max(1.0, abs(L_ref))
+    o = 0
+    dims = [din, width, width, width, dout]
+    for l in range(4):
+        for n in (dims[l] * dims[l + 1], dims[l + 1]):
+            seg_g, seg_r = g[o: o + n], g_ref[o: o + n]
+            assert np.max(np.abs(seg_g - seg_r)) <= 3e-2 * max(np.max(np.abs(seg_r)), 1e-12), (l, n)
+            o += n
+
+
+def test_training_reduces_loss(ftp):
+    import torch
+    tmpl, lc = single_long_case(n_obs=1500)
+    plan = ftp.Plan(tmpl.c, tmpl.s)
+    X, roots, nroots = plan.learned_dataset(lc.t, lc.y, lc.sigma, lc.df, 6000, R=32)
+    assert int(nroots.min()) >= 0 and int(nroots.max()) <= 32
+    assert float(nroots.float().mean()) > 2.0
+    din = X.shape[1]
+    net = ftp.Mlp(din, 64, 4 * tmpl.H, seed=1)
+    l0, _ = net.loss_grad(X, roots, nroots)
+    loss = torch.empty(2048, dtype=torch.float32, device="cuda")
+    for it in range(300):
+        s = (it * 2048) % (X.shape[0] - 2048)
+        net.train_step(X[s: s + 2048], roots[s: s + 2048], nroots[s: s + 2048], lr=2e-3, loss=loss)
+    l1, _ = net.loss_grad(X, roots, nroots)
+    assert float(l1.mean()) < 0.8 * float(l0.mean())
+
+
+@pytest.mark.parametrize("solver", ["uniform", "learned"])
+def test_learned_and_uniform_match_companion(ftp, solver):
+    import torch
+    tmpl, lc = single_long_case(n_obs=3000)
+    n_f = 8000
+    plain = ftp.Plan(tmpl.c, tmpl.s)
+    a = {k: v.clone() for k, v in plain.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
+    if solver == "uniform":
+        p2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_UNIFORM)
+    else:
+        p2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED)
+        din, width, dout = 2 * (6 * tmpl.H - 1), 64, 4 * tmpl.H
+        w = np.random.default_rng(3).uniform(-0.2, 0.2, ftp.mlp_param_count(din, width, dout)).astype(np.float32)
+        p2.load_mlp(w, width)
+    p2.stats()
+    b = p2.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
+    st = p2.stats()
+    dP = float(torch.max(torch.abs(a["power"] - b["power"])))
+    assert dP <= 1e-10, dP
+    assert st["n_fallback"] < n_f
+    fb = (b["status"] & ftp.ST_FALLBACK) != 0
+    assert int(fb.sum()) == st["n_fallback"]
+    assert torch.equal(a["status"], b["status"] & (0xFF ^ ftp.ST_FALLBACK))
+
+
+def test_forced_fallback_is_the_companion_solve(ftp):
+    import torch
+    tmpl, lc = single_long_case(n_obs=2000)
+    n_f = 5000
+    plain = ftp.Plan(tmpl.c, tmpl.s)
+    a = {k: v.clone() for k, v in plain.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
+    p2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_UNIFORM, flags=ftp.FTP_FLAG_FORCE_FALLBACK)
+    p2.stats()
+    b = p2.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
+    st = p2.stats()
+    assert st["n_fallback"] == n_f
+    for k in ("power", "phase", "amp", "offset"):
+        assert torch.equal(a[k], b[k]), k
+    assert torch.all(b["status"] == (a["status"] | ftp.ST_FALLBACK))
+
+
+def test_learned_requires_a_network(ftp):
+    tmpl, lc = tiny_case(1, n_obs=50, H=3, n_f=20)
+    p = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED)
+    with pytest.raises(ftp.FtpError):
+        p.periodogram(lc.t, lc.y, lc.sigma, lc.df, lc.n_f)
