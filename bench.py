@@ -13,7 +13,11 @@ lightcurve: weights/statistics, spreading, FFTs, gather/deconvolution,
 polynomial assembly, root solve and scoring, all on the device.  Inputs are
 resident in HBM before the timed region starts.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solver plain|learned]
+The reported value is the learned-proposal path (network seeds, FP64 Newton,
+Sturm verification, companion-matrix fallback); the plain companion path is
+timed on the same input and reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solver learned|plain]
 """
 from __future__ import annotations
 
@@ -28,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 MFMA, published
 HBM_PEAK_GBS = 8000.0
 
 
@@ -58,12 +63,37 @@ def cpu_baseline(tmpl, lc, n_sample: int):
                        f"(N_obs={len(lc.t)}), {dt:.1f} s"), js, ref
 
 
+def run_solver(F, plan, t, y, s, lc, out, steps, warmup):
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.periodogram(t, y, s, lc.df, lc.n_f, out=out)
+    torch.cuda.synchronize()
+    plan.stats()   # reset the accumulation window
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.periodogram(t, y, s, lc.df, lc.n_f, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    ms_step = ev0.elapsed_time(ev1) / steps
+    per = {k: st[k] / steps for k in st}   # per periodogram call
+    return ms_step, per
+
+
+def mlp_flops(d_in, width, d_out):
+    return 2.0 * (d_in * width + 2 * width * width + width * d_out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--solver", default="plain", choices=["plain", "learned"])
+    ap.add_argument("--solver", default="learned", choices=["plain", "learned"])
     ap.add_argument("--cpu-sample", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -81,30 +111,24 @@ def main():
     dev = torch.device("cuda:0")
     tmpl, lc = single_long_case()
     H = tmpl.H
-    solver = F.FTP_SOLVER_PLAIN if args.solver == "plain" else F.FTP_SOLVER_LEARNED
-    plan = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=solver, flags=F.FTP_FLAG_TIME_STAGES)
+    K, D = 3 * H - 1, 6 * H - 2
     t = torch.as_tensor(lc.t, device=dev)
     y = torch.as_tensor(lc.y, device=dev)
     s = torch.as_tensor(lc.sigma, device=dev)
-    out = plan.alloc_outputs(lc.n_f, dev)
-    stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        plan.periodogram(t, y, s, lc.df, lc.n_f, out=out)
-    torch.cuda.synchronize()
-    plan.stats()   # reset the accumulation window
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.periodogram(t, y, s, lc.df, lc.n_f, out=out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_total = ev0.elapsed_time(ev1)
-    st = plan.stats()
-    ms_step = ms_total / args.steps
+    plain = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=F.FTP_SOLVER_PLAIN,
+                   flags=F.FTP_FLAG_TIME_STAGES)
+    out_p = plain.alloc_outputs(lc.n_f, dev)
+    ms_plain, st_plain = run_solver(F, plain, t, y, s, lc, out_p, args.steps, args.warmup)
+    if args.solver == "learned":
+        w, meta = F.load_model("single_long_h6")
+        plan = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=F.FTP_SOLVER_LEARNED,
+                      flags=F.FTP_FLAG_TIME_STAGES)
+        plan.load_mlp(w, meta["width"])
+        out = plan.alloc_outputs(lc.n_f, dev)
+        ms_step, st = run_solver(F, plan, t, y, s, lc, out, args.steps, args.warmup)
+    else:
+        plan, out, ms_step, st, meta = plain, out_p, ms_plain, st_plain, None
     pairs = lc.n_f
     value = pairs / (ms_step * 1e-3)
 
@@ -117,14 +141,34 @@ def main():
         dP = float(np.max(np.abs(P[js - 1] - ref["power"])))
         gate = dict(max_abs_dP=dP, n_checked=int(len(js)), pass_=bool(dP <= 1e-4))
     jbest = int(np.argmax(P)) + 1
+    dP_plain = float(torch.max(torch.abs(out["power"] - out_p["power"])))
 
-    ms_solve = st["ms_solve"] / args.steps
-    ms_nfft = st["ms_nfft"] / args.steps
-    ms_roots = st["ms_roots"] / args.steps
-    flops = qr_flops(H) * pairs
-    achieved = flops / (ms_roots * 1e-3) / 1e12 if ms_roots > 0 else None
+    # per-kernel work and rooflines
+    qr_plain = qr_flops(H) * pairs / (st_plain["ms_roots"] * 1e-3) / 1e12
+    stages = {"plain_qr": {"bound": "alu", "achieved": qr_plain, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": qr_plain / FP64_PEAK_TFLOPS, "ms": st_plain["ms_roots"],
+                           "flops_per_unit": qr_flops(H), "units": pairs}}
+    if args.solver == "learned":
+        nfb = st["n_fallback"]
+        fl_mlp = mlp_flops(meta["d_in"], meta["width"], meta["d_out"])
+        fl_verify = st["newton_iters"] * 10.0 * (K + 1) + pairs * 4.0 * D * D
+        for name, ms, fl, bound, peak in (
+                ("mlp_forward", st["ms_mlp"], fl_mlp * pairs, "mfma", BF16_PEAK_TFLOPS),
+                ("newton_sturm", st["ms_verify"], fl_verify, "alu", FP64_PEAK_TFLOPS),
+                ("fallback_qr", st["ms_fallback"], qr_flops(H) * nfb, "alu", FP64_PEAK_TFLOPS)):
+            ach = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+            stages[name] = {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                            "frac": ach / peak, "ms": ms}
+        dom = max(("mlp_forward", "newton_sturm", "fallback_qr"), key=lambda k: stages[k]["ms"])
+    else:
+        dom = "plain_qr"
+    kernel_names = {"plain_qr": "k_qr<34> (companion QR, FP64 vector)",
+                    "fallback_qr": "k_qr<34> on the fallback list (FP64 vector)",
+                    "newton_sturm": "k_newton_sturm (FP64 vector)",
+                    "mlp_forward": "k_gemm_bf16 (MFMA bf16)"}
+    d = stages[dom]
     line = {
-        "metric": "trial-freq x lightcurve pairs/sec at |dP|<=1e-4 vs FP64 oracle",
+        "metric": "trial-freq x lightcurve pairs/sec at |dP|<=1e-4 vs FP64 oracle; learned vs plain root solve",
         "value": value,
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -139,15 +183,19 @@ def main():
         "config": {"workload": "single long lightcurve: N_obs=1e4, T=1000 d nightly cadence, H=6, "
                                f"f_max=10/day, oversample 5, N_f={lc.n_f}, FP32 NFFT sums, FP64 solve",
                    "solver": args.solver, "H": H, "n_obs": int(len(lc.t)), "n_f": int(lc.n_f)},
-        "roofline": {"bound": "alu", "kernel": "k_qr<34> (companion QR, FP64 vector)",
-                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None, "traffic": None,
-                     "flops_per_pair": qr_flops(H), "ms_kernel": ms_roots, "ms_solve_stage": ms_solve,
-                     "ms_nfft_stage": ms_nfft},
+        "roofline": {"bound": d["bound"], "kernel": kernel_names[dom], "achieved": d["achieved"],
+                     "peak": d["peak"], "unit": d["unit"], "frac": d["frac"], "traffic": None,
+                     "ms_kernel": d["ms"]},
+        "stages": stages,
+        "plain": {"value": pairs / (ms_plain * 1e-3), "ms_per_step": ms_plain},
+        "speedup_vs_plain": ms_plain / ms_step,
+        "max_abs_dP_vs_plain": dP_plain,
+        "fallback_rate": (st["n_fallback"] / pairs) if args.solver == "learned" else None,
+        "ms_nfft_stage": st["ms_nfft"],
+        "ms_solve_stage": st["ms_solve"],
         "cpu_baseline": cpu,
         "accuracy": gate,
         "best_frequency": {"index": jbest, "f": jbest * lc.df, "injected_f": lc.f0},
-        "stats": {k: st[k] for k in ("n_pairs", "n_fallback", "qr_sweeps")},
     }
     print(json.dumps(line))
 

@@ -96,6 +96,9 @@ typedef struct {
   double ms_nfft;          /* device time of the NFFT stage (ms, 0 if not timed) */
   double ms_solve;         /* device time of the per-frequency stage (ms) */
   double ms_roots;         /* of which in the root-finding kernels (ms) */
+  double ms_mlp;           /* learned: features + network forward (ms) */
+  double ms_verify;        /* learned: Newton + Sturm verification (ms) */
+  double ms_fallback;      /* learned: companion solve of the fallback list (ms) */
 } ftp_stats;
 
 /* Fill `opt` with the defaults.  Returns FTP_E_NULL if opt is NULL. */

@@ -43,7 +43,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("n_pairs", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64), ("qr_sweeps", ctypes.c_uint64),
                 ("newton_iters", ctypes.c_uint64), ("roots_found", ctypes.c_uint64),
                 ("ms_nfft", ctypes.c_double), ("ms_solve", ctypes.c_double),
-                ("ms_roots", ctypes.c_double)]
+                ("ms_roots", ctypes.c_double), ("ms_mlp", ctypes.c_double), ("ms_verify", ctypes.c_double),
+                ("ms_fallback", ctypes.c_double)]
 
 
 class FtpError(RuntimeError):
@@ -258,6 +259,22 @@ class Plan:
                                             int(n_f), _ptr(X), _ptr(roots), _ptr(nroots), int(R),
                                             _stream_ptr(stream)))
         return X, roots, nroots
+
+
+MODELS = os.path.join(HERE, "models")
+
+
+def load_model(name: str = "single_long_h6"):
+    """(FP32 parameters, description) of a trained root-proposal network."""
+    import json
+    import numpy as np
+    base = os.path.join(MODELS, name)
+    with open(base + ".json") as fh:
+        meta = json.load(fh)
+    w = np.fromfile(base + ".f32", dtype=np.float32)
+    if w.size != mlp_param_count(meta["d_in"], meta["width"], meta["d_out"]):
+        raise FtpError(f"model {name}: parameter file has the wrong size")
+    return w, meta
 
 
 def mlp_param_count(d_in: int, width: int, d_out: int) -> int:

@@ -280,8 +280,8 @@ struct ftp_plan {
   ftp_stats last{};
   // stage timing (FTP_FLAG_TIME_STAGES): one event triple per lightcurve chunk
   // (NFFT start, NFFT end, solve end) and one pair per root-kernel launch
-  std::vector<hipEvent_t> ev, evr;
-  int ev_used = 0, evr_used = 0;
+  std::vector<hipEvent_t> ev, evr, evl;
+  int ev_used = 0, evr_used = 0, evl_used = 0;
   // learned
   MlpNet net;
   bool mlp_loaded = false;
@@ -336,6 +336,7 @@ hipEvent_t next_event_in(ftp_plan* P, std::vector<hipEvent_t>& pool, int& used) 
 }
 hipEvent_t next_event(ftp_plan* P) { return next_event_in(P, P->ev, P->ev_used); }
 hipEvent_t next_root_event(ftp_plan* P) { return next_event_in(P, P->evr, P->evr_used); }
+hipEvent_t next_learn_event(ftp_plan* P) { return next_event_in(P, P->evl, P->evl_used); }
 
 int wait_uploads(ftp_plan* P) {
   if (P->upload_pending) {
@@ -557,6 +558,8 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
         if ((rc = mlp_forward(&P->net, P->xfeat.as<uint16_t>(), np, P->seeds.as<float>(), st))) return rc;
         seeds = P->seeds.as<float>();
       }
+      hipEvent_t ra = next_learn_event(P);
+      if (ra) HIP_TRY(hipEventRecord(ra, st));
       HIP_TRY(hipMemsetAsync(P->fb_count.p, 0, sizeof(unsigned), st));
       LearnArgs L{};
       L.rec = rec;
@@ -566,6 +569,8 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       L.fb_count = P->fb_count.as<unsigned>();
       L.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
       HIP_TRY(launch_newton_sturm(a, L, w2, st));
+      hipEvent_t rb = next_learn_event(P);
+      if (rb) HIP_TRY(hipEventRecord(rb, st));
       HIP_TRY(launch_qr(P->H, rec, RL.stride, np, P->fb_list.as<int64_t>(), P->fb_count.as<unsigned>(),
                         P->counters.as<SolveCounters>(), w, st));
     }
@@ -750,6 +755,7 @@ int ftp_plan_destroy(ftp_plan* P) {
   if (P->upload_done) (void)hipEventDestroy(P->upload_done);
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : P->evr) (void)hipEventDestroy(e);
+  for (hipEvent_t e : P->evl) (void)hipEventDestroy(e);
   delete P;
   return FTP_OK;
 }
@@ -1000,10 +1006,20 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
     out->ms_nfft += a;
     out->ms_solve += b;
   }
+  out->ms_mlp = out->ms_verify = out->ms_fallback = 0.0;
   for (int k = 0; k + 2 <= P->evr_used; k += 2) {
     float a = 0.f;
     HIP_TRY(hipEventElapsedTime(&a, P->evr[k], P->evr[k + 1]));
     out->ms_roots += a;
+    if (k + 2 <= P->evl_used) {
+      float m = 0.f, v = 0.f, f = 0.f;
+      HIP_TRY(hipEventElapsedTime(&m, P->evr[k], P->evl[k]));
+      HIP_TRY(hipEventElapsedTime(&v, P->evl[k], P->evl[k + 1]));
+      HIP_TRY(hipEventElapsedTime(&f, P->evl[k + 1], P->evr[k + 1]));
+      out->ms_mlp += m;
+      out->ms_verify += v;
+      out->ms_fallback += f;
+    }
   }
   out->n_fallback = c.fallback;
   out->qr_sweeps = c.qr_sweeps;
@@ -1012,6 +1028,7 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
   // reset the accumulation window
   P->ev_used = 0;
   P->evr_used = 0;
+  P->evl_used = 0;
   P->last = ftp_stats{};
   HIP_TRY(hipMemsetAsync(P->counters.p, 0, sizeof(SolveCounters), (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));

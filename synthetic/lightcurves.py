@@ -26,7 +26,8 @@ __all__ = [
     "template_random_normal", "template_sawtooth", "template_eclipsing_binary",
     "eval_template", "cadence_uniform", "cadence_nightly",
     "frequency_grid", "small_fp64_case", "single_long_case", "ragged_batch_case",
-    "learned_train_lightcurves", "learned_heldout_lightcurves", "large_case",
+    "learned_train_lightcurves", "learned_heldout_lightcurves", "large_case", "single_long_template",
+    "learned_template",
     "tiny_case", "WORKLOADS",
 ]
 
@@ -242,22 +243,29 @@ def _learned_lc(seed: int, index: int, tmpl: Template, n_obs: int, baseline: flo
     return _signal_lc(rng, tmpl, t, 0.5, period, 10.0)
 
 
-def learned_template(seed: int = SEED0 + 3) -> Template:
+def single_long_template(seed: int = SEED0 + 1) -> Template:
+    """The H=6 template of the single long lightcurve workload."""
     return template_sawtooth(6, np.random.default_rng(seed))
+
+
+def learned_template() -> Template:
+    """Template of the learned-proposal workloads: the single long
+    lightcurve's, so a network trained here applies to that workload."""
+    return single_long_template()
 
 
 def learned_train_lightcurves(n_lc: int = 200, seed: int = SEED0 + 3, n_obs: int = 10_000,
                               baseline: float = 1000.0):
     """Lightcurves like the single long case (H=6) used to generate the
     polynomials the root-proposal network is trained on."""
-    tmpl = learned_template(seed)
+    tmpl = learned_template()
     return tmpl, [_learned_lc(seed + 1000, i, tmpl, n_obs, baseline) for i in range(n_lc)]
 
 
 def learned_heldout_lightcurves(n_lc: int = 1024, seed: int = SEED0 + 3, n_obs: int = 2000,
                                 baseline: float = 1000.0):
     """Held-out evaluation set (disjoint seed stream): N=2000, T=1000 d."""
-    tmpl = learned_template(seed)
+    tmpl = learned_template()
     return tmpl, [_learned_lc(seed + 2000, i, tmpl, n_obs, baseline) for i in range(n_lc)]
 
 
