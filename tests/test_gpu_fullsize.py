@@ -1,0 +1,69 @@
+"""Full-size workloads on the GPU, checked on sampled outputs against the
+oracle and against stored oracle results (tests/golden, written by
+tests/golden/make_golden.py from the oracle alone)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ftp_oracle as O
+from synthetic import single_long_case, large_case
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def ftp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2101_12348_amd as F
+    F.load_library()
+    return F
+
+
+@pytest.mark.parametrize("solver", ["plain", "learned"])
+def test_single_long_best_frequency_matches_oracle(ftp, solver):
+    path = os.path.join(GOLDEN, "single_long_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    gold = json.load(open(path))
+    tmpl, lc = single_long_case()
+    assert gold["n_f"] == lc.n_f
+    if solver == "plain":
+        plan = ftp.Plan(tmpl.c, tmpl.s)
+    else:
+        w, meta = ftp.load_model("single_long_h6")
+        plan = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED)
+        plan.load_mlp(w, meta["width"])
+    out = {k: v.cpu().numpy() for k, v in plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, lc.n_f).items()}
+    P = out["power"]
+    top = sorted(gold["top_peaks"], key=lambda d: -d["power"])
+    gap = top[0]["power"] - top[1]["power"]
+    assert gap > 1e-4  # the best index is unambiguous at the FP32-sum tolerance
+    assert int(np.argmax(P)) + 1 == gold["best_index"]
+    for pk in top:
+        assert abs(P[pk["index"] - 1] - pk["power"]) <= 1e-4
+
+
+def test_large_workload_sampled(ftp):
+    import torch
+    tmpl, lc = large_case()
+    assert lc.n_f > 2.5e5 and len(lc.t) == 100_000 and tmpl.H == 10
+    plain = ftp.Plan(tmpl.c, tmpl.s)
+    a = {k: v.clone() for k, v in plain.periodogram(lc.t, lc.y, lc.sigma, lc.df, lc.n_f).items()}
+    uni = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_UNIFORM)
+    uni.stats()
+    b = uni.periodogram(lc.t, lc.y, lc.sigma, lc.df, lc.n_f)
+    st = uni.stats()
+    assert float(torch.max(torch.abs(a["power"] - b["power"]))) <= 1e-10
+    assert st["n_fallback"] < lc.n_f
+    P = a["power"].cpu().numpy()
+    rng = np.random.default_rng(5)
+    jbest = int(np.argmax(P)) + 1
+    js = np.unique(np.r_[jbest, rng.integers(1, lc.n_f + 1, 20)])
+    ref = O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, freq_index=js, block=4)
+    assert np.max(np.abs(P[js - 1] - ref["power"])) <= 1e-4
+    assert abs(jbest * lc.df - lc.f0) <= 2 * lc.df or abs(jbest * lc.df - 2 * lc.f0) <= 2 * lc.df
