@@ -2,8 +2,9 @@
 // real phase polynomial from network seeds, verified by a Sturm count.
 //
 // For each frequency (one wavefront):
-//   * 2H seeds (network output, or evenly spaced for the ablation) are
-//     refined by FP64 Newton on R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta
+//   * 2H network seeds plus 2H evenly spaced starts (4H evenly spaced
+//     starts for the ablation without network) are refined by FP64 Newton on
+//     R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta
 //     (Eq. theta2cond written as R(theta) = i e^{-i K theta} p(e^{i theta}));
 //   * converged roots closer than 1e-8 rad are merged;
 //   * the number of distinct real roots of R is counted with Sturm sequences
@@ -32,14 +33,13 @@ __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.
 
 // Distinct real roots of the degree-D polynomial g (LDS, coefficients c =
 // 0..D, g[D] != 0) in (-1, 1] by a Sturm sequence evaluated at x = -1 and
-// x = 1.  Buffers b0, b1, b2 hold D + 1 doubles each.  Returns -1 when the
-// sequence ends in a non-constant gcd (repeated or nearly repeated roots) or a
-// step loses its leading term, i.e. when the count is not trustworthy.
-__device__ int sturm_count_unit(const double* g, int D, double* b0, double* b1, double* b2, int lane) {
-  double* A = b0;
-  double* B = b1;
-  double* C = b2;
-  // A = g / max|g|, B = g' / max|g'|
+// x = 1.  The sequence P_0 = g, P_1 = g', P_q = -rem(P_{q-2}, P_{q-1}) is
+// built in `ch` (polynomial q of degree D - q at offset q (D + 1) - q (q - 1) / 2,
+// (D + 1)(D + 2) / 2 doubles), each member scaled to max |coefficient| = 1;
+// `tmp` holds 2 (D + 1) doubles.  Returns -1 when a remainder vanishes (a
+// non-constant gcd: repeated or nearly repeated roots) or loses its leading
+// term, i.e. when the count is not trustworthy.
+__device__ int sturm_count_unit(const double* g, int D, double* ch, double* tmp, int lane) {
   double ma = 0.0, mb = 0.0;
   for (int c = lane; c <= D; c += 64) {
     ma = fmax(ma, fabs(g[c]));
@@ -48,63 +48,57 @@ __device__ int sturm_count_unit(const double* g, int D, double* b0, double* b1, 
   ma = wave_max(ma);
   mb = wave_max(mb);
   if (!(ma > 0.0) || !(mb > 0.0)) return -1;
+  double* P1 = ch + (D + 1);
   for (int c = lane; c <= D; c += 64) {
-    A[c] = g[c] / ma;
-    if (c < D) B[c] = (c + 1) * g[c + 1] / mb;
+    ch[c] = g[c] / ma;
+    if (c < D) P1[c] = (c + 1) * g[c + 1] / mb;
   }
   lwave_sync();
-  int da = D, db = D - 1;
-  // sign changes at x = -1 and x = +1
-  double pm = 0.0, pp = 0.0;     // previous non-zero signs
-  int vm = 0, vp = 0;
-  auto push = [&](const double* Pp, int deg) {
-    double s1 = 0.0, sm1 = 0.0;
-    for (int c = lane; c <= deg; c += 64) {
-      s1 += Pp[c];
-      sm1 += (c & 1) ? -Pp[c] : Pp[c];
-    }
-    s1 = sgn(wave_sum(s1));
-    sm1 = sgn(wave_sum(sm1));
-    if (s1 != 0.0) { if (pp != 0.0 && s1 != pp) ++vp; pp = s1; }
-    if (sm1 != 0.0) { if (pm != 0.0 && sm1 != pm) ++vm; pm = sm1; }
-  };
-  push(A, da);
-  push(B, db);
-  while (db > 0) {
-    // C = A mod B by long division, then negate
-    for (int c = lane; c <= da; c += 64) C[c] = A[c];
+  int nq = 2;   // members built
+  for (int q = 2; q <= D; ++q) {
+    const int da = D - q + 2, db = D - q + 1;
+    const double* A = ch + (int64_t)(q - 2) * (D + 1) - (int64_t)(q - 2) * (q - 3) / 2;
+    const double* B = ch + (int64_t)(q - 1) * (D + 1) - (int64_t)(q - 1) * (q - 2) / 2;
+    double* C = ch + (int64_t)q * (D + 1) - (int64_t)q * (q - 1) / 2;
+    for (int c = lane; c <= da; c += 64) tmp[c] = A[c];
     lwave_sync();
     const double bl = B[db];
     for (int i = da - db; i >= 0; --i) {
-      const double q = C[db + i] / bl;
-      for (int c = lane; c <= db; c += 64) C[c + i] -= q * B[c];
+      const double qt = tmp[db + i] / bl;
+      for (int c = lane; c <= db; c += 64) tmp[c + i] -= qt * B[c];
       lwave_sync();
     }
     double mr = 0.0;
-    for (int c = lane; c < db; c += 64) mr = fmax(mr, fabs(C[c]));
+    for (int c = lane; c < db; c += 64) mr = fmax(mr, fabs(tmp[c]));
     mr = wave_max(mr);
-    if (!(mr > 1e-12)) return -1;   // remainder vanishes: gcd of positive degree
-    // degree of the remainder: highest c < db with |C[c]| > 1e-13 mr
-    int dc = -1;
-    for (int base = 0; base < db; base += 64) {
-      const int c = base + lane;
-      const bool nz = c < db && fabs(C[c]) > 1e-13 * mr;
-      const unsigned long long m = __ballot(nz);
-      if (m) dc = base + 63 - __clzll(m);
-    }
-    // a generic remainder has degree db - 1; a lost leading term means the
-    // sequence is ill-determined in floating point
-    if (dc != db - 1) return -1;
+    // a vanishing remainder means a gcd of positive degree; a generic
+    // remainder keeps degree db - 1 (a lost leading term is ill-determined)
+    if (!(mr > 1e-12) || !(fabs(tmp[db - 1]) > 1e-13 * mr)) return -1;
     const double inv = -1.0 / mr;
-    for (int c = lane; c <= dc; c += 64) C[c] *= inv;
+    for (int c = lane; c < db; c += 64) C[c] = tmp[c] * inv;
     lwave_sync();
-    push(C, dc);
-    double* t = A;
-    A = B;
-    B = C;
-    C = t;
-    da = db;
-    db = dc;
+    nq = q + 1;
+  }
+  // signs of every member at x = 1 and x = -1 (lane q evaluates member q);
+  // tmp[q] and tmp[D + 1 + q] receive them
+  lwave_sync();
+  for (int q = lane; q < nq; q += 64) {
+    const double* Pq = ch + (int64_t)q * (D + 1) - (int64_t)q * (q - 1) / 2;
+    double a1 = 0.0, am = 0.0;
+    for (int c = 0; c <= D - q; ++c) {
+      a1 += Pq[c];
+      am += (c & 1) ? -Pq[c] : Pq[c];
+    }
+    tmp[q] = a1 > 0.0 ? 1.0 : (a1 < 0.0 ? -1.0 : 0.0);
+    tmp[D + 1 + q] = am > 0.0 ? 1.0 : (am < 0.0 ? -1.0 : 0.0);
+  }
+  lwave_sync();
+  int vp = 0, vm = 0;
+  double pp = 0.0, pm = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    const double a = tmp[q], b = tmp[D + 1 + q];
+    if (a != 0.0) { if (pp != 0.0 && a != pp) ++vp; pp = a; }
+    if (b != 0.0) { if (pm != 0.0 && b != pm) ++vm; pm = b; }
   }
   return vm - vp;
 }
@@ -120,21 +114,20 @@ struct LearnArgs {
 
 __host__ __device__ inline size_t learn_lds_bytes(int H) {
   const int K = 3 * H - 1, D = 2 * K;
-  return (size_t)(2 * (K + 1) + 5 * (D + 1) + 8) * sizeof(double);
+  return (size_t)(2 * (K + 1) + 4 * (D + 1) + (D + 1) * (D + 2) / 2 + 8) * sizeof(double);
 }
 
 __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
   extern __shared__ double sml[];
   const int lane = threadIdx.x & 63;
-  const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H;
+  const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = 2 * S;
   const RecLayout RL(H);
   FreqWork W;
   W.r = reinterpret_cast<double2*>(sml);
   double* g2 = sml + 2 * (K + 1);        // reflected polynomial x^D f(-1/x)
-  double* b0 = g2 + (D + 1);
-  double* b1 = b0 + (D + 1);
-  double* b2 = b1 + (D + 1);
-  double* fl = b2 + (D + 1);             // f copied to LDS
+  double* fl = g2 + (D + 1);             // f copied to LDS
+  double* tmp = fl + (D + 1);            // 2 (D + 1) scratch doubles
+  double* ch = tmp + 2 * (D + 1);        // Sturm sequence storage
   unsigned long long iters_acc = 0, roots_acc = 0, fb_acc = 0;
   for (int64_t w = blockIdx.x; w < L.np; w += gridDim.x) {
     double* R = L.rec + w * (int64_t)RL.stride;
@@ -156,18 +149,21 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
       g2[D - c] = (c & 1) ? -fc : fc;
     }
     lwave_sync();
-    // Newton from the seeds (lane k < 2H)
+    // Newton from 4H starts: lanes < 2H take the network seeds and lanes
+    // 2H..4H-1 evenly spaced phases (with no network, all 4H are evenly spaced)
     double th = 0.0;
     bool conv = false;
     int its = 0;
-    if (lane < S) {
-      if (L.seeds_out) {
+    if (lane < NS) {
+      if (L.seeds_out && lane < S) {
         const float* o = L.seeds_out + w * 2 * S;
         th = atan2((double)o[2 * lane + 1], (double)o[2 * lane]) - R[RL.meta + M_CANON];
+      } else if (L.seeds_out) {
+        th = kTwoPi * (lane - S + 0.5) / S;
       } else {
-        th = kTwoPi * (lane + 0.5) / S;
+        th = kTwoPi * (lane + 0.5) / NS;
       }
-      for (its = 0; its < 16; ++its) {
+      for (its = 0; its < 12; ++its) {
         double Rv, dR;
         eval_R(W, H, th, Rv, dR);
         if (!(dR != 0.0)) break;
@@ -180,23 +176,23 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
       th = fmod(th, kTwoPi);
       if (th < 0.0) th += kTwoPi;
     }
-    iters_acc += (unsigned long long)wave_sum((double)(lane < S ? its : 0));
+    iters_acc += (unsigned long long)wave_sum((double)(lane < NS ? its : 0));
     // merge roots closer than 1e-8 rad (keep the lowest lane)
     bool uniq = conv;
-    for (int j = 0; j < S; ++j) {
+    for (int j = 0; j < NS; ++j) {
       const double tj = lrdlane(th, j);
       const bool cj = __builtin_amdgcn_readlane((int)conv, j) != 0;
       double dd = fabs(tj - th);
       dd = fmin(dd, kTwoPi - dd);
       if (cj && j < lane && dd < 1e-8) uniq = false;
     }
-    const unsigned long long um = __ballot(uniq && lane < S);
+    const unsigned long long um = __ballot(uniq && lane < NS);
     const int nu = __popcll(um);
     // Sturm counts on the two half circles
-    const int c1 = sturm_count_unit(fl, D, b0, b1, b2, lane);
+    const int c1 = sturm_count_unit(fl, D, ch, tmp, lane);
     int cnt = -1;
     if (c1 >= 0) {
-      const int c2 = sturm_count_unit(g2, D, b0, b1, b2, lane);
+      const int c2 = sturm_count_unit(g2, D, ch, tmp, lane);
       if (c2 >= 0) cnt = c1 + c2;
     }
     if (cnt >= 0 && cnt == nu) {
@@ -204,7 +200,7 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
       double* cand = R + RL.cand;
       for (int c = lane; c < D; c += 64) cand[c] = __longlong_as_double(0x7ff8000000000000ll);
       lwave_sync();
-      if (uniq && lane < S) cand[pos] = th;
+      if (uniq && lane < NS) cand[pos] = th;
       roots_acc += (unsigned long long)nu;
     } else {
       if (lane == 0) {
