@@ -66,19 +66,37 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   const int lr = tid >> 2, lk = (tid & 3) * 8;   // loader: row 0..63, k 0/8/16/24
+  // 16-byte operand loads when k is contiguous, rows are 16-byte aligned and K
+  // is a multiple of the K step
+  const bool avec = g.a_k == 1 && (g.a_m & 7) == 0 && (g.K % kGK) == 0 &&
+                    ((reinterpret_cast<uintptr_t>(g.A) & 15) == 0);
+  const bool bvec = g.b_k == 1 && (g.b_n & 7) == 0 && (g.K % kGK) == 0 &&
+                    ((reinterpret_cast<uintptr_t>(g.B) & 15) == 0);
   for (int k0 = 0; k0 < g.K; k0 += kGK) {
     {
       const int64_t m = m0 + lr;
       uint16_t* dst = As + lr * kGP + lk;
-      for (int q = 0; q < 8; ++q) {
-        const int k = k0 + lk + q;
-        dst[q] = (m < g.M && k < g.K) ? g.A[m * g.a_m + (int64_t)k * g.a_k] : (uint16_t)0;
+      if (avec) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (m < g.M) v = *reinterpret_cast<const uint4*>(g.A + m * g.a_m + k0 + lk);
+        *reinterpret_cast<uint4*>(dst) = v;
+      } else {
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + lk + q;
+          dst[q] = (m < g.M && k < g.K) ? g.A[m * g.a_m + (int64_t)k * g.a_k] : (uint16_t)0;
+        }
       }
       const int n = n0 + lr;
       uint16_t* dstb = Bs + lr * kGP + lk;
-      for (int q = 0; q < 8; ++q) {
-        const int k = k0 + lk + q;
-        dstb[q] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.b_k + (int64_t)n * g.b_n] : (uint16_t)0;
+      if (bvec) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (n < g.N) v = *reinterpret_cast<const uint4*>(g.B + (int64_t)n * g.b_n + k0 + lk);
+        *reinterpret_cast<uint4*>(dstb) = v;
+      } else {
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + lk + q;
+          dstb[q] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.b_k + (int64_t)n * g.b_n] : (uint16_t)0;
+        }
       }
     }
     __syncthreads();

@@ -410,8 +410,7 @@ __device__ __forceinline__ Best select_best(double P, double th_rel, double th_a
   const double pmax = wave_max(pv);
   const bool near = valid && pv >= pmax - 1e-12 * fmax(pmax, 1e-300);
   double key = near ? ((ym > 0.0 ? 0.0 : 8.0) + th_abs) : 1e30;
-  double kmin = key;
-  for (int o = 32; o > 0; o >>= 1) kmin = fmin(kmin, __shfl_xor(kmin, o));
+  const double kmin = -wave_max(-key);
   const unsigned long long mask = __ballot(near && key == kmin);
   Best b;
   b.lane = mask ? __ffsll((long long)mask) - 1 : 0;
