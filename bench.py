@@ -14,10 +14,12 @@ polynomial assembly, root solve and scoring, all on the device.  Inputs are
 resident in HBM before the timed region starts.
 
 The reported value is the learned-proposal path (network seeds, FP64 Newton,
-Sturm verification, companion-matrix fallback); the plain companion path is
-timed on the same input and reported beside it.
+Sturm verification; unconfirmed frequencies go to the Aberth iteration, and
+what it leaves to the companion-matrix solve).  The plain companion path, the
+uniform-start ablation (no network) and the Aberth solver are timed on the
+same input and reported beside it under "solvers".
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solver learned|plain]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solver learned|plain|uniform|aberth]
 """
 from __future__ import annotations
 
@@ -84,6 +86,14 @@ def run_solver(F, plan, t, y, s, lc, out, steps, warmup):
     return ms_step, per
 
 
+def aberth_flops(H: int) -> float:
+    """FP64 work of one Aberth sweep over the D roots of a degree-D real
+    polynomial: per root, Horner for f and f' at a complex point (~16 D
+    flops) and the sum of 1/(z - z_j) over the other roots (~10 D flops)."""
+    D = 6 * H - 2
+    return 26.0 * D * D
+
+
 def mlp_flops(d_in, width, d_out):
     return 2.0 * (d_in * width + 2 * width * width + width * d_out)
 
@@ -93,7 +103,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--solver", default="learned", choices=["plain", "learned"])
+    ap.add_argument("--solver", default="learned", choices=["plain", "learned", "uniform", "aberth"])
     ap.add_argument("--cpu-sample", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -116,19 +126,20 @@ def main():
     y = torch.as_tensor(lc.y, device=dev)
     s = torch.as_tensor(lc.sigma, device=dev)
 
-    plain = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=F.FTP_SOLVER_PLAIN,
-                   flags=F.FTP_FLAG_TIME_STAGES)
-    out_p = plain.alloc_outputs(lc.n_f, dev)
-    ms_plain, st_plain = run_solver(F, plain, t, y, s, lc, out_p, args.steps, args.warmup)
-    if args.solver == "learned":
-        w, meta = F.load_model("single_long_h6")
-        plan = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=F.FTP_SOLVER_LEARNED,
-                      flags=F.FTP_FLAG_TIME_STAGES)
-        plan.load_mlp(w, meta["width"])
-        out = plan.alloc_outputs(lc.n_f, dev)
-        ms_step, st = run_solver(F, plan, t, y, s, lc, out, args.steps, args.warmup)
-    else:
-        plan, out, ms_step, st, meta = plain, out_p, ms_plain, st_plain, None
+    solver_ids = {"plain": F.FTP_SOLVER_PLAIN, "learned": F.FTP_SOLVER_LEARNED,
+                  "uniform": F.FTP_SOLVER_UNIFORM, "aberth": F.FTP_SOLVER_ABERTH}
+    w, meta = F.load_model("single_long_h6")
+    runs = {}
+    for name in ("plain", "learned", "uniform", "aberth"):
+        pl = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=solver_ids[name],
+                    flags=F.FTP_FLAG_TIME_STAGES)
+        if name == "learned":
+            pl.load_mlp(w, meta["width"])
+        o = pl.alloc_outputs(lc.n_f, dev)
+        ms, st = run_solver(F, pl, t, y, s, lc, o, args.steps, args.warmup)
+        runs[name] = (pl, o, ms, st)
+    plan, out, ms_step, st = runs[args.solver]
+    _, out_p, ms_plain, st_plain = runs["plain"]
     pairs = lc.n_f
     value = pairs / (ms_step * 1e-3)
 
@@ -141,31 +152,40 @@ def main():
         dP = float(np.max(np.abs(P[js - 1] - ref["power"])))
         gate = dict(max_abs_dP=dP, n_checked=int(len(js)), pass_=bool(dP <= 1e-4))
     jbest = int(np.argmax(P)) + 1
-    dP_plain = float(torch.max(torch.abs(out["power"] - out_p["power"])))
 
-    # per-kernel work and rooflines
-    qr_plain = qr_flops(H) * pairs / (st_plain["ms_roots"] * 1e-3) / 1e12
-    stages = {"plain_qr": {"bound": "alu", "achieved": qr_plain, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": qr_plain / FP64_PEAK_TFLOPS, "ms": st_plain["ms_roots"],
-                           "flops_per_unit": qr_flops(H), "units": pairs}}
-    if args.solver == "learned":
-        nfb = st["n_fallback"]
-        fl_mlp = mlp_flops(meta["d_in"], meta["width"], meta["d_out"])
-        fl_verify = st["newton_iters"] * 10.0 * (K + 1) + pairs * 4.0 * D * D
-        for name, ms, fl, bound, peak in (
-                ("mlp_forward", st["ms_mlp"], fl_mlp * pairs, "mfma", BF16_PEAK_TFLOPS),
-                ("newton_sturm", st["ms_verify"], fl_verify, "alu", FP64_PEAK_TFLOPS),
-                ("fallback_qr", st["ms_fallback"], qr_flops(H) * nfb, "alu", FP64_PEAK_TFLOPS)):
-            ach = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-            stages[name] = {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                            "frac": ach / peak, "ms": ms}
-        dom = max(("mlp_forward", "newton_sturm", "fallback_qr"), key=lambda k: stages[k]["ms"])
+    # per-kernel work and rooflines (FP64 flop counts of what each stage must do)
+    def stage(ms, fl, bound, peak, **kw):
+        ach = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        return dict(bound=bound, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak, ms=ms, **kw)
+
+    stages = {"plain_qr": stage(st_plain["ms_roots"], qr_flops(H) * pairs, "alu", FP64_PEAK_TFLOPS,
+                                flops_per_unit=qr_flops(H), units=pairs)}
+    if args.solver in ("learned", "uniform", "aberth"):
+        fl_verify = st["newton_iters"] * 10.0 * (K + 1) + (pairs - st["n_fallback"]) * 4.0 * D * D
+        if args.solver == "learned":
+            stages["mlp_forward"] = stage(st["ms_mlp"], mlp_flops(meta["d_in"], meta["width"], meta["d_out"]) * pairs,
+                                          "mfma", BF16_PEAK_TFLOPS)
+        if args.solver != "aberth":
+            stages["newton_sturm"] = stage(st["ms_verify"], fl_verify, "alu", FP64_PEAK_TFLOPS)
+        stages["aberth"] = stage(st["ms_aberth"], aberth_flops(H) * st["aberth_iters"], "alu", FP64_PEAK_TFLOPS,
+                                 flops_per_sweep=aberth_flops(H), sweeps=st["aberth_iters"])
+        stages["fallback_qr"] = stage(st["ms_fallback"], qr_flops(H) * st["n_fallback_qr"], "alu",
+                                      FP64_PEAK_TFLOPS)
+        dom = max((k for k in stages if k != "plain_qr"), key=lambda k: stages[k]["ms"])
     else:
         dom = "plain_qr"
-    kernel_names = {"plain_qr": "k_qr<34> (companion QR, FP64 vector)",
-                    "fallback_qr": "k_qr<34> on the fallback list (FP64 vector)",
+    kernel_names = {"plain_qr": f"k_qr<{D}> (companion QR, FP64 vector)",
+                    "fallback_qr": f"k_qr<{D}> on the Aberth tier's leftovers (FP64 vector)",
                     "newton_sturm": "k_newton_sturm (FP64 vector)",
+                    "aberth": "k_aberth (FP64 vector)",
                     "mlp_forward": "k_gemm_bf16 (MFMA bf16)"}
+    solvers = {}
+    for name, (_, o, ms, stn) in runs.items():
+        solvers[name] = {"value": pairs / (ms * 1e-3), "ms_per_step": ms,
+                         "max_abs_dP_vs_plain": float(torch.max(torch.abs(o["power"] - out_p["power"]))),
+                         "unconfirmed_rate": stn["n_fallback"] / pairs, "companion_rate": stn["n_fallback_qr"] / pairs,
+                         "ms_roots": stn["ms_roots"], "ms_mlp": stn["ms_mlp"], "ms_verify": stn["ms_verify"],
+                         "ms_aberth": stn["ms_aberth"], "ms_fallback_qr": stn["ms_fallback"]}
     d = stages[dom]
     line = {
         "metric": "trial-freq x lightcurve pairs/sec at |dP|<=1e-4 vs FP64 oracle; learned vs plain root solve",
@@ -187,10 +207,8 @@ def main():
                      "peak": d["peak"], "unit": d["unit"], "frac": d["frac"], "traffic": None,
                      "ms_kernel": d["ms"]},
         "stages": stages,
-        "plain": {"value": pairs / (ms_plain * 1e-3), "ms_per_step": ms_plain},
+        "solvers": solvers,
         "speedup_vs_plain": ms_plain / ms_step,
-        "max_abs_dP_vs_plain": dP_plain,
-        "fallback_rate": (st["n_fallback"] / pairs) if args.solver == "learned" else None,
         "ms_nfft_stage": st["ms_nfft"],
         "ms_solve_stage": st["ms_solve"],
         "cpu_baseline": cpu,

@@ -57,7 +57,11 @@ extern "C" {
 #define FTP_ST_CONSTANT 2      /* the phase polynomial vanishes: P does not depend on theta_2 */
 #define FTP_ST_NO_CONVERGE 3   /* companion QR hit its iteration limit */
 #define FTP_ST_BAD_LC 4        /* the lightcurve was rejected (see above) */
-#define FTP_ST_FALLBACK 8      /* bit: learned proposal fell back to the companion solve */
+#define FTP_ST_FALLBACK 8      /* bit: the solver's first method did not settle the frequency
+                                  (learned / uniform: Newton roots not confirmed by the Sturm
+                                  count; the roots came from Aberth or the companion solve) */
+#define FTP_ST_FALLBACK_QR 16  /* bit: the roots came from the companion solve after the
+                                  Aberth iteration did not converge (learned / uniform / Aberth) */
 
 #define FTP_MAX_H 11   /* D = 6H - 2 <= 64: one wavefront lane per companion row */
 
@@ -68,11 +72,15 @@ extern "C" {
 
 /* root solver */
 #define FTP_SOLVER_PLAIN 0     /* companion-matrix eigenvalues (Section 2) */
-#define FTP_SOLVER_LEARNED 1   /* MLP seeds + Newton + Sturm check, companion fallback */
-#define FTP_SOLVER_UNIFORM 2   /* as LEARNED but with 2H uniform seeds (ablation) */
+#define FTP_SOLVER_LEARNED 1   /* 2H MLP seeds + 2H evenly spaced starts, Newton, Sturm check;
+                                  unconfirmed frequencies go to Aberth, then the companion solve */
+#define FTP_SOLVER_UNIFORM 2   /* as LEARNED with 4H evenly spaced starts (ablation: no network) */
+#define FTP_SOLVER_ABERTH 3    /* Aberth-Ehrlich iteration on every frequency; companion solve
+                                  where it does not converge */
 
 /* option flags */
-#define FTP_FLAG_FORCE_FALLBACK 1u  /* learned path: send every frequency to the companion solve */
+#define FTP_FLAG_FORCE_FALLBACK 1u  /* learned / uniform / Aberth solvers: send every frequency to
+                                       the companion solve */
 #define FTP_FLAG_TIME_STAGES 2u     /* record HIP events around the NFFT and per-frequency stages
                                        (read back by ftp_last_stats) */
 
@@ -89,16 +97,20 @@ typedef struct {
 
 typedef struct {
   uint64_t n_pairs;        /* frequencies solved by the last call */
-  uint64_t n_fallback;     /* of which went to the companion solve (learned path) */
+  uint64_t n_fallback;     /* learned / uniform: frequencies whose Newton roots the Sturm
+                              count did not confirm (solved by the Aberth tier) */
+  uint64_t n_fallback_qr;  /* frequencies left to the companion solve by the Aberth tier */
   uint64_t qr_sweeps;      /* Francis double-shift sweeps performed */
   uint64_t newton_iters;   /* Newton iterations performed (learned path) */
   uint64_t roots_found;    /* distinct real roots accepted (learned path) */
+  uint64_t aberth_iters;   /* Aberth sweeps, summed over the frequencies it solved */
   double ms_nfft;          /* device time of the NFFT stage (ms, 0 if not timed) */
   double ms_solve;         /* device time of the per-frequency stage (ms) */
   double ms_roots;         /* of which in the root-finding kernels (ms) */
   double ms_mlp;           /* learned: features + network forward (ms) */
   double ms_verify;        /* learned: Newton + Sturm verification (ms) */
-  double ms_fallback;      /* learned: companion solve of the fallback list (ms) */
+  double ms_aberth;        /* learned / uniform / Aberth: the Aberth kernel (ms) */
+  double ms_fallback;      /* learned / uniform / Aberth: companion solve of what is left (ms) */
 } ftp_stats;
 
 /* Fill `opt` with the defaults.  Returns FTP_E_NULL if opt is NULL. */

@@ -19,11 +19,12 @@ FTP_FP64 = 1
 FTP_SOLVER_PLAIN = 0
 FTP_SOLVER_LEARNED = 1
 FTP_SOLVER_UNIFORM = 2
+FTP_SOLVER_ABERTH = 3
 FTP_FLAG_FORCE_FALLBACK = 1
 FTP_FLAG_TIME_STAGES = 2
 MAX_H = 11
 
-ST_OK, ST_DEGENERATE, ST_CONSTANT, ST_NO_CONVERGE, ST_BAD_LC, ST_FALLBACK = 0, 1, 2, 3, 4, 8
+ST_OK, ST_DEGENERATE, ST_CONSTANT, ST_NO_CONVERGE, ST_BAD_LC, ST_FALLBACK, ST_FALLBACK_QR = 0, 1, 2, 3, 4, 8, 16
 
 EXPORTED = [
     "ftp_options_default", "ftp_plan_create", "ftp_plan_destroy", "ftp_periodogram",
@@ -40,11 +41,11 @@ class Options(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("n_pairs", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64), ("qr_sweeps", ctypes.c_uint64),
-                ("newton_iters", ctypes.c_uint64), ("roots_found", ctypes.c_uint64),
-                ("ms_nfft", ctypes.c_double), ("ms_solve", ctypes.c_double),
+    _fields_ = [("n_pairs", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64), ("n_fallback_qr", ctypes.c_uint64),
+                ("qr_sweeps", ctypes.c_uint64), ("newton_iters", ctypes.c_uint64), ("roots_found", ctypes.c_uint64),
+                ("aberth_iters", ctypes.c_uint64), ("ms_nfft", ctypes.c_double), ("ms_solve", ctypes.c_double),
                 ("ms_roots", ctypes.c_double), ("ms_mlp", ctypes.c_double), ("ms_verify", ctypes.c_double),
-                ("ms_fallback", ctypes.c_double)]
+                ("ms_aberth", ctypes.c_double), ("ms_fallback", ctypes.c_double)]
 
 
 class FtpError(RuntimeError):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libftp.so")
-SOURCES = ["ftp_nfft.hip", "ftp_solve.hip", "ftp_learned.hip", "ftp_mlp.hip", "ftp_capi.hip"]
+SOURCES = ["ftp_nfft.hip", "ftp_solve.hip", "ftp_learned.hip", "ftp_aberth.hip", "ftp_mlp.hip", "ftp_capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

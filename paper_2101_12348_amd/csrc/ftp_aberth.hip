@@ -1,0 +1,205 @@
+// All roots of the Cayley polynomial f by the Aberth-Ehrlich simultaneous
+// iteration (O. Aberth, Math. Comp. 27 (1973); L. W. Ehrlich, Comm. ACM 10
+// (1967)), one root per lane of a wavefront.  A project addition to the
+// method: the paper takes the roots of the phase polynomial (Eq. finalpoly)
+// from a companion-matrix eigensolver; this kernel reaches the same root set
+// by a different iteration and feeds the same candidate scoring.
+//
+// Used as the second tier of the learned solve (frequencies whose Newton
+// roots the Sturm count did not confirm) and as a solver of its own over all
+// frequencies.  Stopping rule: a lane stops when its correction is at the
+// rounding level of |z| or when |f(z)| is within 4 D u of sum |f_k| |z|^k (the
+// root is exact for a polynomial perturbed at rounding level, the backward
+// error test of Bini and Fiorentino's MPSolve).  Frequencies whose roots do
+// not all stop within kAberthMaxIt sweeps go to the companion-matrix solve.
+//
+// Candidates: each root x maps back to the phase
+//   theta = phi0 + atan2(Re x, 1 - Im x) + atan2(Re x, 1 + Im x),
+// the argument of psi = e^{i phi0} (1 + i x) / (1 - i x), i.e. the projection
+// of psi onto the unit circle (Section 2.2); a conjugate pair gives the same
+// phase twice.
+#include "ftp_solve_common.h"
+
+namespace ftp {
+
+constexpr int kAberthMaxIt = 60;
+
+struct AberthArgs {
+  double* rec;
+  int64_t np;
+  const int64_t* list;       // pairs to solve; nullptr = every pair of the chunk
+  const unsigned* count;     // length of `list`
+  int64_t* qr_list;          // pairs left to the companion-matrix solve
+  unsigned* qr_count;
+  SolveCounters* counters;
+  int H;
+  double mark;               // M_FALLBACK value written for pairs sent on
+  unsigned flags;            // bit 0: send every pair on (companion solve only)
+};
+
+__host__ __device__ inline size_t aberth_lds_bytes(int H) {
+  const int D = 6 * H - 2;
+  return (size_t)((D + 2) + 2 * D) * sizeof(double);
+}
+
+__device__ __forceinline__ void awave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(64) void k_aberth(AberthArgs A) {
+  extern __shared__ double sab[];
+  const int lane = threadIdx.x & 63;
+  const int H = A.H, D = 6 * H - 2;
+  const RecLayout RL(H);
+  double* fc = sab;                                         // D + 1 coefficients
+  double2* zs = reinterpret_cast<double2*>(sab + (D + 2));  // D roots (16-byte aligned: D even)
+  const int64_t n = A.list ? (int64_t)(*A.count) : A.np;
+  constexpr double u = 1.1102230246251565e-16;
+  unsigned long long its_acc = 0, qr_acc = 0;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int64_t w = A.list ? A.list[i] : i;
+    double* R = A.rec + w * (int64_t)RL.stride;
+    if (!A.list) {
+      const int st = (int)R[RL.meta + M_STATUS];
+      if (st == ST_BAD_LC || st == ST_CONSTANT) continue;
+    }
+    if (A.flags & 1u) {
+      if (lane == 0) {
+        const unsigned slot = atomicAdd(A.qr_count, 1u);
+        A.qr_list[slot] = w;
+        R[RL.meta + M_FALLBACK] = A.mark;
+        ++qr_acc;
+      }
+      continue;
+    }
+    double fmaxabs = 0.0;
+    for (int c = lane; c <= D; c += 64) fmaxabs = fmax(fmaxabs, fabs(R[RL.f + c]));
+    fmaxabs = wave_max(fmaxabs);
+    const double fs = fmaxabs > 0.0 ? 1.0 / fmaxabs : 1.0;
+    for (int c = lane; c <= D; c += 64) fc[c] = R[RL.f + c] * fs;
+    awave_sync();
+    const double f0 = fc[0], fD = fc[D];
+    double rho = pow(fabs(f0 / fD), 1.0 / D);
+    if (!(rho > 1e-8 && rho < 1e8)) rho = 1.0;
+    const bool act = lane < D;
+    double zr = 0.0, zi = 0.0;
+    if (act) {
+      double sn, cs;
+      sincos(kTwoPi * (lane + 0.25) / D, &sn, &cs);
+      zr = rho * cs;
+      zi = rho * sn;
+    }
+    bool done = !act;
+    int it = 0;
+    for (; it < kAberthMaxIt; ++it) {
+      if (act) zs[lane] = make_double2(zr, zi);
+      awave_sync();
+      if (!done) {
+        const double az = sqrt(zr * zr + zi * zi);
+        double rr, ri;   // f'(z) / f(z)
+        bool exact = false;
+        if (az <= 1.0) {
+          double pr = fc[D], pi = 0.0, dr = 0.0, di = 0.0, ab = fabs(fc[D]);
+          for (int k = D - 1; k >= 0; --k) {
+            const double tr = dr * zr - di * zi + pr;
+            di = dr * zi + di * zr + pi;
+            dr = tr;
+            const double qr = pr * zr - pi * zi + fc[k];
+            pi = pr * zi + pi * zr;
+            pr = qr;
+            ab = ab * az + fabs(fc[k]);
+          }
+          const double pm2 = pr * pr + pi * pi;
+          exact = !(sqrt(pm2) > 4.0 * D * u * ab);
+          if (!exact) {
+            const double inv = 1.0 / pm2;
+            rr = (dr * pr + di * pi) * inv;
+            ri = (di * pr - dr * pi) * inv;
+          }
+        } else {
+          // reversed polynomial in y = 1/z: f(z) = z^D g(y), f'/f = y (D - y g'/g)
+          const double iz2 = 1.0 / (az * az);
+          const double yr = zr * iz2, yi = -zi * iz2, ay = 1.0 / az;
+          double gr = fc[0], gi = 0.0, dr = 0.0, di = 0.0, ab = fabs(fc[0]);
+          for (int k = 1; k <= D; ++k) {
+            const double tr = dr * yr - di * yi + gr;
+            di = dr * yi + di * yr + gi;
+            dr = tr;
+            const double qr = gr * yr - gi * yi + fc[k];
+            gi = gr * yi + gi * yr;
+            gr = qr;
+            ab = ab * ay + fabs(fc[k]);
+          }
+          const double gm2 = gr * gr + gi * gi;
+          exact = !(sqrt(gm2) > 4.0 * D * u * ab);
+          if (!exact) {
+            const double inv = 1.0 / gm2;
+            const double qr = (dr * gr + di * gi) * inv, qi = (di * gr - dr * gi) * inv;   // g'/g
+            const double sr = D - (yr * qr - yi * qi), si = -(yr * qi + yi * qr);       // D - y g'/g
+            rr = yr * sr - yi * si;
+            ri = yr * si + yi * sr;
+          }
+        }
+        if (exact) {
+          done = true;
+        } else {
+          double sr = 0.0, si = 0.0;   // sum_{j != lane} 1 / (z - z_j)
+          for (int j = 0; j < D; ++j) {
+            if (j == lane) continue;
+            const double2 zj = zs[j];
+            const double er = zr - zj.x, ei = zi - zj.y;
+            const double inv = 1.0 / (er * er + ei * ei);
+            sr += er * inv;
+            si -= ei * inv;
+          }
+          const double br = rr - sr, bi = ri - si;
+          const double inv = 1.0 / (br * br + bi * bi);
+          const double cr = br * inv, ci = -bi * inv;   // correction 1 / (f'/f - S)
+          if (isfinite(cr) && isfinite(ci)) {
+            zr -= cr;
+            zi -= ci;
+            if (sqrt(cr * cr + ci * ci) <= 4.0 * u * sqrt(zr * zr + zi * zi)) done = true;
+          } else {
+            done = true;   // coincident estimates: leave to the verdict below
+          }
+        }
+      }
+      awave_sync();
+      if (__ballot(!done) == 0ull) break;
+    }
+    // verdict: every lane stopped with a finite root, and the roots add up to
+    // -f_{D-1} / f_D (Vieta), which two estimates stuck on one root would break
+    const bool finite = !act || (isfinite(zr) && isfinite(zi));
+    double sx = act ? zr : 0.0, sy = act ? zi : 0.0, sa = act ? sqrt(zr * zr + zi * zi) : 0.0;
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    sa = wave_sum(sa);
+    const double ex = sx + fc[D - 1] / fD;
+    const bool vieta = sqrt(ex * ex + sy * sy) <= 1e-8 * (sa + fabs(fc[D - 1] / fD)) + 1e-12;
+    const bool ok = it < kAberthMaxIt && __ballot(!finite) == 0ull && vieta;
+    its_acc += (unsigned long long)(it < kAberthMaxIt ? it + 1 : it);
+    if (ok) {
+      const double phi0 = R[RL.meta + M_PHI0];
+      double* cand = R + RL.cand;
+      if (act) cand[lane] = phi0 + atan2(zr, 1.0 - zi) + atan2(zr, 1.0 + zi);
+    } else if (lane == 0) {
+      const unsigned slot = atomicAdd(A.qr_count, 1u);
+      A.qr_list[slot] = w;
+      R[RL.meta + M_FALLBACK] = A.mark;
+      ++qr_acc;
+    }
+    awave_sync();
+  }
+  if (lane == 0 && A.counters) {
+    if (its_acc) atomicAdd(&A.counters->aberth_iters, its_acc);
+    if (qr_acc) atomicAdd(&A.counters->fallback_qr, qr_acc);
+  }
+}
+
+hipError_t launch_aberth(const AberthArgs& A, int waves, hipStream_t st) {
+  hipLaunchKernelGGL(k_aberth, dim3((unsigned)waves), dim3(64), aberth_lds_bytes(A.H), st, A);
+  return hipGetLastError();
+}
+
+}  // namespace ftp

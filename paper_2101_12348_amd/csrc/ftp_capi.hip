@@ -73,6 +73,20 @@ struct LearnArgs {
   unsigned flags;
 };
 hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st);
+struct AberthArgs {
+  double* rec;
+  int64_t np;
+  const int64_t* list;
+  const unsigned* count;
+  int64_t* qr_list;
+  unsigned* qr_count;
+  SolveCounters* counters;
+  int H;
+  double mark;
+  unsigned flags;
+};
+hipError_t launch_aberth(const AberthArgs& A, int waves, hipStream_t st);
+hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st);
 }  // namespace ftp
 
 using namespace ftp;
@@ -290,7 +304,9 @@ struct ftp_plan {
   float* ds_roots = nullptr;
   int* ds_nroots = nullptr;
   int ds_R = 0;
-  DevBuf xfeat, seeds, fb_list, fb_count;
+  // work lists: Newton -> Aberth (fb_list, count fb_count[0]) and
+  // Aberth -> companion solve (fb2_list, count fb_count[1])
+  DevBuf xfeat, seeds, fb_list, fb2_list, fb_count;
 };
 
 namespace {
@@ -427,8 +443,8 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
   if ((rc = P->grids.ensure(sizeof(C) * n_grid))) return rc;
   LcInfo* dl = P->lcinfo.as<LcInfo>();
   hipLaunchKernelGGL(k_prep_stats, dim3((unsigned)n_lc), dim3(256), 0, st, dl, t, y, sigma);
-  HIP_TRY(hipMemsetAsync(P->tile_count.p, 0, sizeof(unsigned) * n_tiles, st));
-  HIP_TRY(hipMemsetAsync(P->cursor.p, 0, sizeof(unsigned) * n_tiles, st));
+  HIP_TRY(launch_zero_u32(P->tile_count.as<unsigned>(), n_tiles, st));
+  HIP_TRY(launch_zero_u32(P->cursor.as<unsigned>(), n_tiles, st));
   const unsigned pblocks = (unsigned)((n_pts + 255) / 256);
   hipLaunchKernelGGL(k_prep_points<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc,
                      P->obs_off.as<int64_t>(), n_pts, t, y, sigma, P->pw.as<PointRec<R>>(),
@@ -535,7 +551,8 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
   const int solver = dataset ? FTP_SOLVER_PLAIN : P->opt.solver;
   if (solver != FTP_SOLVER_PLAIN) {
     if ((rc = P->fb_list.ensure(sizeof(int64_t) * chunk))) return rc;
-    if ((rc = P->fb_count.ensure(sizeof(unsigned)))) return rc;
+    if ((rc = P->fb2_list.ensure(sizeof(int64_t) * chunk))) return rc;
+    if ((rc = P->fb_count.ensure(2 * sizeof(unsigned)))) return rc;
     if (solver == FTP_SOLVER_LEARNED) {
       if ((rc = P->xfeat.ensure(sizeof(uint16_t) * chunk * P->net.din))) return rc;
       if ((rc = P->seeds.ensure(sizeof(float) * chunk * P->net.dout))) return rc;
@@ -552,6 +569,11 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
     if (solver == FTP_SOLVER_PLAIN) {
       HIP_TRY(launch_qr(P->H, rec, RL.stride, np, nullptr, nullptr, P->counters.as<SolveCounters>(), w, st));
     } else {
+      // learned / uniform: [features, MLP] -> Newton + Sturm -> Aberth on the
+      // unconfirmed pairs -> companion QR on what Aberth leaves;
+      // Aberth solver: Aberth on every pair -> companion QR on what it leaves
+      unsigned* counts = P->fb_count.as<unsigned>();
+      HIP_TRY(launch_zero_u32(counts, 2, st));
       const float* seeds = nullptr;
       if (solver == FTP_SOLVER_LEARNED) {
         HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), P->net.din, w2, st));
@@ -560,18 +582,33 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       }
       hipEvent_t ra = next_learn_event(P);
       if (ra) HIP_TRY(hipEventRecord(ra, st));
-      HIP_TRY(hipMemsetAsync(P->fb_count.p, 0, sizeof(unsigned), st));
-      LearnArgs L{};
-      L.rec = rec;
-      L.np = np;
-      L.seeds_out = seeds;
-      L.fb_list = P->fb_list.as<int64_t>();
-      L.fb_count = P->fb_count.as<unsigned>();
-      L.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
-      HIP_TRY(launch_newton_sturm(a, L, w2, st));
+      if (solver != FTP_SOLVER_ABERTH) {
+        LearnArgs L{};
+        L.rec = rec;
+        L.np = np;
+        L.seeds_out = seeds;
+        L.fb_list = P->fb_list.as<int64_t>();
+        L.fb_count = counts;
+        L.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
+        HIP_TRY(launch_newton_sturm(a, L, w2, st));
+      }
       hipEvent_t rb = next_learn_event(P);
       if (rb) HIP_TRY(hipEventRecord(rb, st));
-      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, P->fb_list.as<int64_t>(), P->fb_count.as<unsigned>(),
+      AberthArgs A{};
+      A.rec = rec;
+      A.np = np;
+      A.list = solver == FTP_SOLVER_ABERTH ? nullptr : P->fb_list.as<int64_t>();
+      A.count = counts;
+      A.qr_list = P->fb2_list.as<int64_t>();
+      A.qr_count = counts + 1;
+      A.counters = P->counters.as<SolveCounters>();
+      A.H = P->H;
+      A.mark = 2.0;
+      A.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
+      HIP_TRY(launch_aberth(A, solver == FTP_SOLVER_ABERTH ? w2 : w, st));
+      hipEvent_t rc2 = next_learn_event(P);
+      if (rc2) HIP_TRY(hipEventRecord(rc2, st));
+      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, P->fb2_list.as<int64_t>(), counts + 1,
                         P->counters.as<SolveCounters>(), w, st));
     }
     hipEvent_t r1 = next_root_event(P);
@@ -700,7 +737,7 @@ int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, con
   ftp_options o;
   if (opt) o = *opt; else ftp_options_default(&o);
   if (o.precision != FTP_FP32_SUMS && o.precision != FTP_FP64) return FTP_E_OPTION;
-  if (o.solver < FTP_SOLVER_PLAIN || o.solver > FTP_SOLVER_UNIFORM) return FTP_E_OPTION;
+  if (o.solver < FTP_SOLVER_PLAIN || o.solver > FTP_SOLVER_ABERTH) return FTP_E_OPTION;
   if (o.nfft_R != 0.0 && !(o.nfft_R >= 1.5 && o.nfft_R <= 16.0)) return FTP_E_OPTION;
   if (o.nfft_msp < 0 || o.nfft_msp > 24) return FTP_E_OPTION;
   if (o.solve_waves < 0) return FTP_E_OPTION;
@@ -1006,22 +1043,29 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
     out->ms_nfft += a;
     out->ms_solve += b;
   }
-  out->ms_mlp = out->ms_verify = out->ms_fallback = 0.0;
+  out->ms_mlp = out->ms_verify = out->ms_aberth = out->ms_fallback = 0.0;
+  // per chunk: root events (start, end); learned-stage events (after the
+  // network, after Newton + Sturm, after Aberth) when the solver has them
   for (int k = 0; k + 2 <= P->evr_used; k += 2) {
     float a = 0.f;
     HIP_TRY(hipEventElapsedTime(&a, P->evr[k], P->evr[k + 1]));
     out->ms_roots += a;
-    if (k + 2 <= P->evl_used) {
-      float m = 0.f, v = 0.f, f = 0.f;
-      HIP_TRY(hipEventElapsedTime(&m, P->evr[k], P->evl[k]));
-      HIP_TRY(hipEventElapsedTime(&v, P->evl[k], P->evl[k + 1]));
-      HIP_TRY(hipEventElapsedTime(&f, P->evl[k + 1], P->evr[k + 1]));
+    const int l = 3 * (k / 2);
+    if (l + 3 <= P->evl_used) {
+      float m = 0.f, v = 0.f, b = 0.f, f = 0.f;
+      HIP_TRY(hipEventElapsedTime(&m, P->evr[k], P->evl[l]));
+      HIP_TRY(hipEventElapsedTime(&v, P->evl[l], P->evl[l + 1]));
+      HIP_TRY(hipEventElapsedTime(&b, P->evl[l + 1], P->evl[l + 2]));
+      HIP_TRY(hipEventElapsedTime(&f, P->evl[l + 2], P->evr[k + 1]));
       out->ms_mlp += m;
       out->ms_verify += v;
+      out->ms_aberth += b;
       out->ms_fallback += f;
     }
   }
   out->n_fallback = c.fallback;
+  out->n_fallback_qr = c.fallback_qr;
+  out->aberth_iters = c.aberth_iters;
   out->qr_sweeps = c.qr_sweeps;
   out->newton_iters = c.newton_iters;
   out->roots_found = c.roots_found;
@@ -1052,7 +1096,8 @@ const char* ftp_status_string(int code) {
     case FTP_ST_CONSTANT: return "phase polynomial vanishes (P constant in phase)";
     case FTP_ST_NO_CONVERGE: return "companion QR did not converge";
     case FTP_ST_BAD_LC: return "lightcurve rejected (NaN/Inf, sigma < 0, mixed zero sigma or Var(y) = 0)";
-    case FTP_ST_FALLBACK: return "learned proposal fell back to the companion solve";
+    case FTP_ST_FALLBACK: return "the solver's first method did not settle the frequency (Aberth tier used)";
+    case FTP_ST_FALLBACK_QR: return "roots from the companion solve after the Aberth tier";
     default: return "unknown code";
   }
 }

@@ -48,7 +48,8 @@ enum : uint8_t {
   ST_CONSTANT = 2,         // p == 0: P independent of phase; theta_2 = 0 scored
   ST_NO_CONVERGE = 3,      // QR iteration limit hit (best of what was found)
   ST_BAD_LC = 4,           // the lightcurve's input was rejected
-  ST_FALLBACK = 8,         // learned proposal fell back to the companion solve (bit)
+  ST_FALLBACK = 8,         // bit: the first method of the solver did not settle the pair
+  ST_FALLBACK_QR = 16,     // bit: roots from the companion solve after the Aberth tier
 };
 
 template <typename R> struct PointRec;
@@ -67,10 +68,12 @@ struct FftGridPass {
 };
 
 struct SolveCounters {
-  unsigned long long fallback;   // frequencies sent to the companion solve
+  unsigned long long fallback;   // frequencies the learned / uniform Newton solve did not confirm
   unsigned long long newton_iters;
   unsigned long long roots_found;
   unsigned long long qr_sweeps;
+  unsigned long long aberth_iters;   // Aberth sweeps summed over solved pairs
+  unsigned long long fallback_qr;    // pairs left to the companion solve after Aberth
 };
 
 }  // namespace ftp

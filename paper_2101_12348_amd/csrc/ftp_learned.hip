@@ -12,7 +12,12 @@
 //     circles: x in (-1, 1] for f and for x^D f(-1/x) (the map rotated by pi);
 //   * if the Sturm sequence is well determined and the counts agree, the
 //     Newton roots are the candidate set; otherwise the frequency goes to the
-//     companion-matrix solve through a device work list.
+//     Aberth iteration (then, if that does not converge, to the
+//     companion-matrix solve) through device work lists.
+// For D + 1 <= 64 the Sturm remainders are formed in registers (lane c holds
+// coefficient c; the shift by one power of x is a DPP lane shift); the chain is
+// written to LDS only for the final sign evaluation.  D = 64 (H = 11) uses the
+// LDS form.
 #include "ftp_solve_common.h"
 
 namespace ftp {
@@ -103,6 +108,80 @@ __device__ int sturm_count_unit(const double* g, int D, double* ch, double* tmp,
   return vm - vp;
 }
 
+// v from lane (lane - 1); lane 0 receives 0 (DPP wave_shr:1, all lanes active)
+__device__ __forceinline__ double lane_shr1(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x138, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// v from lane (lane + 1); lane 63 receives 0 (DPP wave_shl:1)
+__device__ __forceinline__ double lane_shl1(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x130, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sign changes of the member values s_q, q = 0..nq-1 (lane q holds s_q; zeros
+// are skipped, as in the Sturm count).
+__device__ __forceinline__ int sign_changes(double v, int nq, int lane) {
+  const bool in = lane < nq;
+  const unsigned long long pos = __ballot(in && v > 0.0), neg = __ballot(in && v < 0.0);
+  unsigned long long nz = pos | neg;
+  const unsigned long long full = nq >= 64 ? ~0ull : ((1ull << nq) - 1ull);
+  if (nz == full) return __popcll((pos ^ (pos >> 1)) & (full >> 1));
+  int changes = 0, prev = -1;
+  while (nz) {
+    const int b = __ffsll((long long)nz) - 1;
+    const int sgnb = (int)((pos >> b) & 1ull);
+    if (prev >= 0 && sgnb != prev) ++changes;
+    prev = sgnb;
+    nz &= nz - 1ull;
+  }
+  return changes;
+}
+
+// sturm_count_unit with the remainder sequence in registers (D + 1 <= 64, all
+// 64 lanes active; same members, scaling and ill-determination tests).
+__device__ int sturm_count_reg(const double* g, int D, double* ch, int lane) {
+  const double gv = lane <= D ? g[lane] : 0.0;
+  const double gnext = lane_shl1(gv);   // g[lane + 1], taken with every lane active
+  const double dv = lane < D ? (lane + 1) * gnext : 0.0;
+  const double ma = wave_max(fabs(gv)), mb = wave_max(fabs(dv));
+  if (!(ma > 0.0) || !(mb > 0.0)) return -1;
+  double A = gv / ma, B = dv / mb;
+  if (lane <= D) ch[lane] = A;
+  if (lane < D) ch[(D + 1) + lane] = B;
+  int nq = 2;
+  for (int q = 2; q <= D; ++q) {
+    const int da = D - q + 2, db = D - q + 1;
+    const double bl = lrdlane(B, db);
+    const double q1 = lrdlane(A, da) / bl;
+    double t = A - q1 * lane_shr1(B);
+    const double q0 = lrdlane(t, db) / bl;
+    t = lane < db ? t - q0 * B : 0.0;
+    const double mr = wave_max(fabs(t));
+    const double lead = lrdlane(t, db - 1);
+    if (!(mr > 1e-12) || !(fabs(lead) > 1e-13 * mr)) return -1;
+    const double C = t * (-1.0 / mr);
+    if (lane < db) ch[q * (D + 1) - q * (q - 1) / 2 + lane] = C;
+    A = B;
+    B = C;
+    nq = q + 1;
+  }
+  lwave_sync();
+  double a1 = 0.0, am = 0.0;
+  if (lane < nq) {
+    const double* Pq = ch + lane * (D + 1) - lane * (lane - 1) / 2;
+    for (int c = 0; c <= D - lane; ++c) {
+      a1 += Pq[c];
+      am += (c & 1) ? -Pq[c] : Pq[c];
+    }
+  }
+  return sign_changes(am, nq, lane) - sign_changes(a1, nq, lane);
+}
+
 struct LearnArgs {
   double* rec;
   int64_t np;
@@ -189,11 +268,19 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
     const unsigned long long um = __ballot(uniq && lane < NS);
     const int nu = __popcll(um);
     // Sturm counts on the two half circles
-    const int c1 = sturm_count_unit(fl, D, ch, tmp, lane);
     int cnt = -1;
-    if (c1 >= 0) {
-      const int c2 = sturm_count_unit(g2, D, ch, tmp, lane);
-      if (c2 >= 0) cnt = c1 + c2;
+    if (D < 64) {
+      const int c1 = sturm_count_reg(fl, D, ch, lane);
+      if (c1 >= 0) {
+        const int c2 = sturm_count_reg(g2, D, ch, lane);
+        if (c2 >= 0) cnt = c1 + c2;
+      }
+    } else {
+      const int c1 = sturm_count_unit(fl, D, ch, tmp, lane);
+      if (c1 >= 0) {
+        const int c2 = sturm_count_unit(g2, D, ch, tmp, lane);
+        if (c2 >= 0) cnt = c1 + c2;
+      }
     }
     if (cnt >= 0 && cnt == nu) {
       const int pos = __popcll(um & ((1ull << lane) - 1ull));

@@ -193,6 +193,41 @@ __device__ __forceinline__ int hqr_wave(double* A, double* wr, double* wi, const
   return sweeps;
 }
 
+// Balancing (Parlett & Reinsch, Numer. Math. 13 (1969); LAPACK gebal): a
+// diagonal similarity by powers of 2, exact in floating point, that brings the
+// off-diagonal 1-norms of each row and column within a factor of 2.  The
+// companion matrix of the Cayley polynomial has entries spread over many
+// orders of magnitude (binomial growth with D), and without this step the QR
+// iteration loses the roots' accuracy relative to the matrix norm.
+template <int N>
+__device__ __forceinline__ void balance_wave(double* A, const int lane) {
+  constexpr int ld = N + 1;
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    bool done = true;
+    for (int i = 0; i < N; ++i) {
+      const bool off = lane < N && lane != i;
+      double c = wave_sum(off ? fabs(A[lane * ld + i]) : 0.0);
+      const double r = wave_sum(off ? fabs(A[i * ld + lane]) : 0.0);
+      if (!(c > 0.0) || !(r > 0.0) || !isfinite(c) || !isfinite(r)) continue;   // (also ends the loops below)
+      const double s = c + r;
+      double f = 1.0, g = 0.5 * r;
+      while (c < g) { f *= 2.0; c *= 4.0; }
+      g = 2.0 * r;
+      while (c >= g) { f *= 0.5; c *= 0.25; }
+      if ((c + r) / f < 0.95 * s) {
+        done = false;
+        const double fi = 1.0 / f;
+        if (lane < N) {
+          A[i * ld + lane] *= fi;
+          A[lane * ld + i] *= f;
+        }
+        wave_sync();
+      }
+    }
+    if (done) break;
+  }
+}
+
 __host__ __device__ inline size_t qr_lds_bytes(int D) {
   return ((size_t)D * (D + 1) + 2 * (size_t)D + 2) * sizeof(double);
 }
@@ -226,6 +261,7 @@ __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, 
     wave_sync();
     if (lane < N) A[lane] = -f[N - 1 - lane] / lead;
     wave_sync();
+    balance_wave<N>(A, lane);
     const int sw = hqr_wave<N>(A, wr, wi, lane);
     if (sw < 0) {
       if (lane == 0) R[RL.meta + M_STATUS] = (double)ST_NO_CONVERGE;
@@ -311,6 +347,10 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
   const FreqWork& W = S.W;
   for (int q = lane; q < H; q += 64) S.W.al[q] = a.alpha[q];
   wave_sync();
+  // e^{2 pi i m / 16}, m = lane mod 16: the rotation phases d phi0 are
+  // multiples of 2 pi / 16, read from here by lane index
+  double tab_c, tab_s;
+  sincos(kTwoPi * (lane & 15) / 16.0, &tab_s, &tab_c);
   for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
     const int64_t pidx = p0 + w;
     double* Rr = rec + w * (int64_t)RL.stride;
@@ -346,22 +386,21 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
       }
       const double rm = wave_max(Rv);
       const unsigned long long mask = __ballot(lane < 16 && Rv == rm);
-      phi0 = kTwoPi * (__ffsll((long long)mask) - 1) / 16.0;
+      const int k0 = __ffsll((long long)mask) - 1;
+      phi0 = kTwoPi * k0 / 16.0;
       // f(x) = sum_j rho_{j-K} u^j v^{2K-j}, u = 1 + i x, v = 1 - i x,
       // rho_d = r_d e^{i d phi0}; homogeneous Horner h_l = u h_{l-1} + rho_{K-l} v^l
+      const double cK = rdlane(tab_c, (K * k0) & 15), sK = rdlane(tab_s, (K * k0) & 15);
       for (int c = lane; c <= D; c += 64) {
-        double sn, cs;
-        sincos(K * phi0, &sn, &cs);
-        S.hb[0][c] = c == 0 ? cmul(W.r[K], make_double2(cs, sn)) : make_double2(0.0, 0.0);
+        S.hb[0][c] = c == 0 ? cmul(W.r[K], make_double2(cK, sK)) : make_double2(0.0, 0.0);
         S.vb[0][c] = c == 0 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
       }
       wave_sync();
       for (int l = 1; l <= D; ++l) {
         const int d = K - l;
         const double2 rd = d >= 0 ? W.r[d] : cconj(W.r[-d]);
-        double sn, cs;
-        sincos(d * phi0, &sn, &cs);
-        const double2 rho = cmul(rd, make_double2(cs, sn));
+        const int m = (d * k0) & 15;
+        const double2 rho = cmul(rd, make_double2(rdlane(tab_c, m), rdlane(tab_s, m)));
         const double2* hsrc = (l & 1) ? S.hb[0] : S.hb[1];
         const double2* vsrc = (l & 1) ? S.vb[0] : S.vb[1];
         double2* hdst = (l & 1) ? S.hb[1] : S.hb[0];
@@ -527,7 +566,9 @@ __global__ __launch_bounds__(64) void k_score(SolveArgs a, const double* rec, in
       a.phase[pidx] = th_abs;
       a.amp[pidx] = amp;
       a.offset[pidx] = off;
-      if (a.status) a.status[pidx] = (uint8_t)(stout | (Rr[RL.meta + M_FALLBACK] != 0.0 ? ST_FALLBACK : 0));
+      const double fb = Rr[RL.meta + M_FALLBACK];
+      const int fbits = fb >= 2.0 ? (ST_FALLBACK | ST_FALLBACK_QR) : (fb != 0.0 ? ST_FALLBACK : 0);
+      if (a.status) a.status[pidx] = (uint8_t)(stout | fbits);
     }
     wave_sync();
   }
@@ -553,6 +594,12 @@ __global__ __launch_bounds__(64) void k_gather_sums(SolveArgs a, double* out) {
       out[(pidx * 3 * H + q) * 2 + 1] = v.y;
     }
   }
+}
+
+// Clears n counters (a kernel rather than a memset node, so that captured
+// graphs replay it like any other launch).
+__global__ __launch_bounds__(256) void k_zero_u32(unsigned* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
 }
 
 // lc_stats[0..3] = t_ref, ybar, YY, status bits of the first lightcurve.
@@ -614,6 +661,13 @@ hipError_t launch_gather_sums(int precision, const SolveArgs& a, double* out, in
     hipLaunchKernelGGL(k_gather_sums<double>, dim3((unsigned)blocks), dim3(64), 0, st, a, out);
   else
     hipLaunchKernelGGL(k_gather_sums<float>, dim3((unsigned)blocks), dim3(64), 0, st, a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -68,7 +68,7 @@ enum : int {
   M_CANON = 4,     // canonical rotation of the network features (arg r_1)
   M_REAL_LO = 5,   // bit mask of real companion eigenvalues (low / high 32 lanes)
   M_REAL_HI = 6,
-  M_FALLBACK = 7,  // 1 if the learned proposal fell back to the companion solve
+  M_FALLBACK = 7,  // 0: first method; 1: Aberth tier; 2: companion solve after Aberth
   M_SLOTS = 8,
 };
 struct RecLayout {

@@ -33,6 +33,10 @@ def test_header_constants_match_binding():
     assert int(consts["FTP_FP32_SUMS"]) == F.FTP_FP32_SUMS
     assert int(consts["FTP_FP64"]) == F.FTP_FP64
     assert int(consts["FTP_SOLVER_LEARNED"]) == F.FTP_SOLVER_LEARNED
+    assert int(consts["FTP_SOLVER_UNIFORM"]) == F.FTP_SOLVER_UNIFORM
+    assert int(consts["FTP_SOLVER_ABERTH"]) == F.FTP_SOLVER_ABERTH
+    assert int(consts["FTP_ST_FALLBACK"]) == F.ST_FALLBACK
+    assert int(consts["FTP_ST_FALLBACK_QR"]) == F.ST_FALLBACK_QR
     assert int(consts["FTP_ST_BAD_LC"]) == F.ST_BAD_LC
     assert int(consts["FTP_MAX_H"]) == F.MAX_H
 
@@ -41,7 +45,7 @@ def test_status_strings_and_option_defaults():
     import ctypes
     import paper_2101_12348_amd as F
     lib = F.load_library()
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, 1, 2, 3, 4, 8):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, 1, 2, 3, 4, 8, 16):
         s = lib.ftp_status_string(code).decode()
         assert s and s != "unknown code", code
     opt = F.Options()

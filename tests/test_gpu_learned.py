@@ -3,9 +3,10 @@
 * The network's forward pass and gradients (bf16 MFMA, FP32 accumulation)
   against the FP64 reference with the same bf16 rounding points.
 * Training lowers the loss.
-* The learned and uniform-seed solvers give the same periodogram as the
-  companion solve (every accepted frequency has all real roots, verified by the
-  Sturm count; the others fall back to the companion solve).
+* The learned, uniform-seed and Aberth solvers give the same periodogram as
+  the companion solve (every accepted frequency has all real roots, verified
+  by the Sturm count; the others go to the Aberth tier, and what it leaves to
+  the companion solve).
 * Forcing the fallback reproduces the companion solve bit for bit.
 """
 import numpy as np
@@ -99,7 +100,7 @@ def test_training_reduces_loss(ftp):
     assert float(l1.mean()) < 0.8 * float(l0.mean())
 
 
-@pytest.mark.parametrize("solver", ["uniform", "learned"])
+@pytest.mark.parametrize("solver", ["uniform", "learned", "aberth"])
 def test_learned_and_uniform_match_companion(ftp, solver):
     import torch
     tmpl, lc = single_long_case(n_obs=3000)
@@ -108,6 +109,8 @@ def test_learned_and_uniform_match_companion(ftp, solver):
     a = {k: v.clone() for k, v in plain.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
     if solver == "uniform":
         p2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_UNIFORM)
+    elif solver == "aberth":
+        p2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_ABERTH)
     else:
         p2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED)
         din, width, dout = 2 * (6 * tmpl.H - 1), 64, 4 * tmpl.H
@@ -118,10 +121,21 @@ def test_learned_and_uniform_match_companion(ftp, solver):
     st = p2.stats()
     dP = float(torch.max(torch.abs(a["power"] - b["power"])))
     assert dP <= 1e-10, dP
-    assert st["n_fallback"] < n_f
     fb = (b["status"] & ftp.ST_FALLBACK) != 0
-    assert int(fb.sum()) == st["n_fallback"]
-    assert torch.equal(a["status"], b["status"] & (0xFF ^ ftp.ST_FALLBACK))
+    fbq = (b["status"] & ftp.ST_FALLBACK_QR) != 0
+    assert int(fbq.sum()) == st["n_fallback_qr"]
+    if solver == "aberth":
+        assert st["n_fallback"] == 0 and st["newton_iters"] == 0
+        assert int(fb.sum()) == st["n_fallback_qr"]
+        assert st["aberth_iters"] > 0
+    else:
+        assert st["n_fallback"] < n_f
+        assert int(fb.sum()) == st["n_fallback"]
+        assert st["n_fallback_qr"] <= st["n_fallback"]
+        if solver == "learned":
+            # an untrained network leaves roots unconfirmed: the Aberth tier runs
+            assert st["n_fallback"] > 0 and st["aberth_iters"] > 0
+    assert torch.equal(a["status"], b["status"] & (0xFF ^ (ftp.ST_FALLBACK | ftp.ST_FALLBACK_QR)))
 
 
 def test_forced_fallback_is_the_companion_solve(ftp):
@@ -130,14 +144,16 @@ def test_forced_fallback_is_the_companion_solve(ftp):
     n_f = 5000
     plain = ftp.Plan(tmpl.c, tmpl.s)
     a = {k: v.clone() for k, v in plain.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
-    p2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_UNIFORM, flags=ftp.FTP_FLAG_FORCE_FALLBACK)
-    p2.stats()
-    b = p2.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
-    st = p2.stats()
-    assert st["n_fallback"] == n_f
-    for k in ("power", "phase", "amp", "offset"):
-        assert torch.equal(a[k], b[k]), k
-    assert torch.all(b["status"] == (a["status"] | ftp.ST_FALLBACK))
+    for solver in (ftp.FTP_SOLVER_UNIFORM, ftp.FTP_SOLVER_ABERTH):
+        p2 = ftp.Plan(tmpl.c, tmpl.s, solver=solver, flags=ftp.FTP_FLAG_FORCE_FALLBACK)
+        p2.stats()
+        b = p2.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
+        st = p2.stats()
+        assert st["n_fallback_qr"] == n_f
+        assert st["n_fallback"] == (n_f if solver == ftp.FTP_SOLVER_UNIFORM else 0)
+        for k in ("power", "phase", "amp", "offset"):
+            assert torch.equal(a[k], b[k]), k
+        assert torch.all(b["status"] == (a["status"] | ftp.ST_FALLBACK | ftp.ST_FALLBACK_QR))
 
 
 def test_learned_requires_a_network(ftp):

@@ -59,6 +59,28 @@ def test_solve_stage_from_exact_sums(ftp, seed, H):
     _check_phase_fit(tmpl, lc, js, g, 1e-12, 1e-8)
 
 
+@pytest.mark.parametrize("solver", ["plain", "uniform", "aberth"])
+@pytest.mark.parametrize("seed,H", [(5, 1), (6, 3), (7, 6), (8, 10), (9, 11)])
+def test_root_solvers_from_exact_sums(ftp, solver, seed, H):
+    """Every root solver (companion QR; Newton from evenly spaced starts with
+    the Sturm check and the Aberth / companion tiers behind it; Aberth on
+    every frequency) reproduces the oracle from exact sums, up to H = 11
+    (D = 64: all lanes of a wavefront, the LDS form of the Sturm chain)."""
+    tmpl, lc = tiny_case(seed, n_obs=80, H=H, n_f=60, cadence="nightly")
+    js = np.arange(1, lc.n_f + 1)
+    tref = 0.5 * (lc.t.min() + lc.t.max())
+    Zw, Zy, ybar, YY = O.raw_sums(lc.t, lc.y, lc.sigma, lc.df, js, 2 * H, H, t_ref=tref)
+    sums = np.concatenate([Zw, Zy], axis=1)
+    sv = {"plain": ftp.FTP_SOLVER_PLAIN, "uniform": ftp.FTP_SOLVER_UNIFORM, "aberth": ftp.FTP_SOLVER_ABERTH}[solver]
+    plan = ftp.Plan(tmpl.c, tmpl.s, precision=ftp.FTP_FP64, solver=sv)
+    out = plan.solve_sums(sums, tref, ybar, YY, lc.df)
+    g = {k: _np(v) for k, v in out.items()}
+    ref = O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, lc.n_f)
+    assert np.all((g["status"] & 0x7) == 0)
+    assert np.max(np.abs(g["power"] - ref["power"])) <= 1e-12
+    _check_phase_fit(tmpl, lc, js, g, 1e-12, 1e-8)
+
+
 @pytest.mark.parametrize("precision,tol", [(1, 5e-12), (0, 5e-7)])
 def test_nfft_sums_against_direct_sums(ftp, precision, tol):
     tmpl, lc = single_long_case(n_obs=3000)
