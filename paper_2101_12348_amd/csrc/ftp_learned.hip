@@ -8,16 +8,16 @@
 //     (Eq. theta2cond written as R(theta) = i e^{-i K theta} p(e^{i theta}));
 //   * converged roots closer than 1e-8 rad are merged;
 //   * the number of distinct real roots of R is counted with Sturm sequences
-//     of the Cayley polynomial f(x) (theta = phi0 + 2 atan x) on two half
-//     circles: x in (-1, 1] for f and for x^D f(-1/x) (the map rotated by pi);
+//     of the Cayley polynomial f(x) (theta = phi0 + 2 atan x): over the whole
+//     real line, or on two half circles, x in (-1, 1] for f and for
+//     x^D f(-1/x) (the map rotated by pi);
 //   * if the Sturm sequence is well determined and the counts agree, the
 //     Newton roots are the candidate set; otherwise the frequency goes to the
 //     Aberth iteration (then, if that does not converge, to the
 //     companion-matrix solve) through device work lists.
-// For D + 1 <= 64 the Sturm remainders are formed in registers (lane c holds
-// coefficient c; the shift by one power of x is a DPP lane shift); the chain is
-// written to LDS only for the final sign evaluation.  D = 64 (H = 11) uses the
-// LDS form.
+// For D + 1 <= 64 a single Sturm sequence of f over the whole real line is
+// formed in registers (sturm_count_line_reg); D = 64 (H = 11) uses the LDS
+// form on the two half circles.
 #include "ftp_solve_common.h"
 
 namespace ftp {
@@ -123,37 +123,34 @@ __device__ __forceinline__ double lane_shl1(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Sign changes of the member values s_q, q = 0..nq-1 (lane q holds s_q; zeros
-// are skipped, as in the Sturm count).
-__device__ __forceinline__ int sign_changes(double v, int nq, int lane) {
-  const bool in = lane < nq;
-  const unsigned long long pos = __ballot(in && v > 0.0), neg = __ballot(in && v < 0.0);
-  unsigned long long nz = pos | neg;
-  const unsigned long long full = nq >= 64 ? ~0ull : ((1ull << nq) - 1ull);
-  if (nz == full) return __popcll((pos ^ (pos >> 1)) & (full >> 1));
-  int changes = 0, prev = -1;
-  while (nz) {
-    const int b = __ffsll((long long)nz) - 1;
-    const int sgnb = (int)((pos >> b) & 1ull);
-    if (prev >= 0 && sgnb != prev) ++changes;
-    prev = sgnb;
-    nz &= nz - 1ull;
-  }
-  return changes;
-}
-
-// sturm_count_unit with the remainder sequence in registers (D + 1 <= 64, all
-// 64 lanes active; same members, scaling and ill-determination tests).
-__device__ int sturm_count_reg(const double* g, int D, double* ch, int lane) {
+// Distinct real roots of the degree-D polynomial g (LDS, g[D] != 0) on the
+// whole real line, D + 1 <= 64: the Sturm sequence P_0 = g, P_1 = g',
+// P_q = -rem(P_{q-2}, P_{q-1}) (each scaled to max |coefficient| = 1) is formed
+// in registers, lane c holding coefficient c, the shift by one power of x
+// being a DPP lane shift.  Every member of a generic sequence has degree
+// D - q, so its signs at +inf and -inf are those of its leading coefficient
+// (times (-1)^(D - q) at -inf) and the count V(-inf) - V(+inf) accumulates as
+// the members are formed.  Returns -1 under the same ill-determination tests
+// as the LDS form (vanishing remainder, or a leading term lost to cancellation).
+__device__ int sturm_count_line_reg(const double* g, int D, int lane) {
   const double gv = lane <= D ? g[lane] : 0.0;
   const double gnext = lane_shl1(gv);   // g[lane + 1], taken with every lane active
   const double dv = lane < D ? (lane + 1) * gnext : 0.0;
   const double ma = wave_max(fabs(gv)), mb = wave_max(fabs(dv));
   if (!(ma > 0.0) || !(mb > 0.0)) return -1;
   double A = gv / ma, B = dv / mb;
-  if (lane <= D) ch[lane] = A;
-  if (lane < D) ch[(D + 1) + lane] = B;
-  int nq = 2;
+  // signs of P_0 and P_1 at +inf (sp) and -inf (sm)
+  int sp = lrdlane(A, D) > 0.0 ? 1 : -1;
+  int sm = (D & 1) ? -sp : sp;
+  int vp = 0, vm = 0;
+  {
+    const int tp = lrdlane(B, D - 1) > 0.0 ? 1 : -1;
+    const int tm = ((D - 1) & 1) ? -tp : tp;
+    vp += tp != sp;
+    vm += tm != sm;
+    sp = tp;
+    sm = tm;
+  }
   for (int q = 2; q <= D; ++q) {
     const int da = D - q + 2, db = D - q + 1;
     const double bl = lrdlane(B, db);
@@ -164,22 +161,17 @@ __device__ int sturm_count_reg(const double* g, int D, double* ch, int lane) {
     const double mr = wave_max(fabs(t));
     const double lead = lrdlane(t, db - 1);
     if (!(mr > 1e-12) || !(fabs(lead) > 1e-13 * mr)) return -1;
-    const double C = t * (-1.0 / mr);
-    if (lane < db) ch[q * (D + 1) - q * (q - 1) / 2 + lane] = C;
+    // P_q = -t / mr: leading sign -sgn(lead), degree D - q
+    const int tp = lead > 0.0 ? -1 : 1;
+    const int tm = ((D - q) & 1) ? -tp : tp;
+    vp += tp != sp;
+    vm += tm != sm;
+    sp = tp;
+    sm = tm;
     A = B;
-    B = C;
-    nq = q + 1;
+    B = t * (-1.0 / mr);
   }
-  lwave_sync();
-  double a1 = 0.0, am = 0.0;
-  if (lane < nq) {
-    const double* Pq = ch + lane * (D + 1) - lane * (lane - 1) / 2;
-    for (int c = 0; c <= D - lane; ++c) {
-      a1 += Pq[c];
-      am += (c & 1) ? -Pq[c] : Pq[c];
-    }
-  }
-  return sign_changes(am, nq, lane) - sign_changes(a1, nq, lane);
+  return vm - vp;
 }
 
 struct LearnArgs {
@@ -270,11 +262,9 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
     // Sturm counts on the two half circles
     int cnt = -1;
     if (D < 64) {
-      const int c1 = sturm_count_reg(fl, D, ch, lane);
-      if (c1 >= 0) {
-        const int c2 = sturm_count_reg(g2, D, ch, lane);
-        if (c2 >= 0) cnt = c1 + c2;
-      }
+      // real roots of f on the whole line = real phases other than phi0 + pi,
+      // where R does not vanish (f has full degree D)
+      cnt = sturm_count_line_reg(fl, D, lane);
     } else {
       const int c1 = sturm_count_unit(fl, D, ch, tmp, lane);
       if (c1 >= 0) {
