@@ -106,6 +106,11 @@ def main():
     ap.add_argument("--solver", default="learned", choices=["plain", "learned", "uniform", "aberth"])
     ap.add_argument("--cpu-sample", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solvers", default="plain,learned,uniform,aberth",
+                    help="solvers to time (comma separated; plain and the reported solver are always timed)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device-to-device copy before the bench (reference kernel for "
+                         "the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -129,8 +134,15 @@ def main():
     solver_ids = {"plain": F.FTP_SOLVER_PLAIN, "learned": F.FTP_SOLVER_LEARNED,
                   "uniform": F.FTP_SOLVER_UNIFORM, "aberth": F.FTP_SOLVER_ABERTH}
     w, meta = F.load_model("single_long_h6")
+    if args.copy_calibration:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    wanted = set(x for x in args.solvers.split(",") if x) | {"plain", args.solver}
     runs = {}
-    for name in ("plain", "learned", "uniform", "aberth"):
+    for name in [n for n in ("plain", "learned", "uniform", "aberth") if n in wanted]:
         pl = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=solver_ids[name],
                     flags=F.FTP_FLAG_TIME_STAGES)
         if name == "learned":

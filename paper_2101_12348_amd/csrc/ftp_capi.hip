@@ -25,6 +25,8 @@ template <typename R>
 __global__ void k_prep_points(const LcInfo*, int64_t, const int64_t*, int64_t, const double*, const double*,
                               const double*, PointRec<R>*, PointRec<R>*, unsigned int*);
 __global__ void k_scan_blocks(const unsigned int*, int64_t, int64_t*, int64_t*);
+__global__ void k_scan_single(const unsigned int*, int64_t, int64_t*, int64_t*);
+constexpr int64_t kScanSingleMax = 1024 * 8;
 __global__ void k_scan_sums(int64_t*, int64_t);
 __global__ void k_scan_add(int64_t*, int64_t, const int64_t*, const unsigned int*, int64_t*);
 template <typename R>
@@ -442,18 +444,23 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
   if ((rc = P->bucket.ensure(sizeof(int) * std::max<int64_t>(4 * n_pts, 1)))) return rc;
   if ((rc = P->grids.ensure(sizeof(C) * n_grid))) return rc;
   LcInfo* dl = P->lcinfo.as<LcInfo>();
-  hipLaunchKernelGGL(k_prep_stats, dim3((unsigned)n_lc), dim3(256), 0, st, dl, t, y, sigma);
+  hipLaunchKernelGGL(k_prep_stats, dim3((unsigned)n_lc), dim3(1024), 0, st, dl, t, y, sigma);
   HIP_TRY(launch_zero_u32(P->tile_count.as<unsigned>(), n_tiles, st));
   HIP_TRY(launch_zero_u32(P->cursor.as<unsigned>(), n_tiles, st));
   const unsigned pblocks = (unsigned)((n_pts + 255) / 256);
   hipLaunchKernelGGL(k_prep_points<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc,
                      P->obs_off.as<int64_t>(), n_pts, t, y, sigma, P->pw.as<PointRec<R>>(),
                      P->py.as<PointRec<R>>(), P->tile_count.as<unsigned>());
-  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, st, P->tile_count.as<unsigned>(),
-                     n_tiles, P->tile_off.as<int64_t>(), P->block_sums.as<int64_t>());
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, st, P->block_sums.as<int64_t>(), nsb);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, P->tile_off.as<int64_t>(), n_tiles,
-                     P->block_sums.as<int64_t>(), P->tile_count.as<unsigned>(), P->total.as<int64_t>());
+  if (n_tiles <= kScanSingleMax) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, P->tile_count.as<unsigned>(), n_tiles,
+                       P->tile_off.as<int64_t>(), P->total.as<int64_t>());
+  } else {
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, st, P->tile_count.as<unsigned>(),
+                       n_tiles, P->tile_off.as<int64_t>(), P->block_sums.as<int64_t>());
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, st, P->block_sums.as<int64_t>(), nsb);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, P->tile_off.as<int64_t>(), n_tiles,
+                       P->block_sums.as<int64_t>(), P->tile_count.as<unsigned>(), P->total.as<int64_t>());
+  }
   hipLaunchKernelGGL(k_bin_fill<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc, P->obs_off.as<int64_t>(),
                      n_pts, P->pw.as<PointRec<R>>(), P->py.as<PointRec<R>>(), P->tile_off.as<int64_t>(),
                      P->cursor.as<unsigned>(), P->bucket.as<int>());

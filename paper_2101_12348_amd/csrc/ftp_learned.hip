@@ -108,21 +108,6 @@ __device__ int sturm_count_unit(const double* g, int D, double* ch, double* tmp,
   return vm - vp;
 }
 
-// v from lane (lane - 1); lane 0 receives 0 (DPP wave_shr:1, all lanes active)
-__device__ __forceinline__ double lane_shr1(double v) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x138, 0xf, 0xf, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-// v from lane (lane + 1); lane 63 receives 0 (DPP wave_shl:1)
-__device__ __forceinline__ double lane_shl1(double v) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), 0x130, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x130, 0xf, 0xf, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
 // Distinct real roots of the degree-D polynomial g (LDS, g[D] != 0) on the
 // whole real line, D + 1 <= 64: the Sturm sequence P_0 = g, P_1 = g',
 // P_q = -rem(P_{q-2}, P_{q-1}) (each scaled to max |coefficient| = 1) is formed

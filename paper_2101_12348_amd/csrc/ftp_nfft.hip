@@ -45,30 +45,6 @@ __device__ __forceinline__ void dd_wrap_half(double& hi, double& lo) {
   hi = h; lo = l;
 }
 
-template <typename T>
-__device__ __forceinline__ T block_sum(T v, T* sh) {
-  // 256-thread block reduction (4 waves)
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  T r = sh[0] + sh[1] + sh[2] + sh[3];
-  __syncthreads();
-  return r;
-}
-
-__device__ __forceinline__ double block_min(double v, double* sh) {
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double r = fmin(fmin(sh[0], sh[1]), fmin(sh[2], sh[3]));
-  __syncthreads();
-  return r;
-}
-
 __device__ __forceinline__ int64_t find_segment(const int64_t* off, int64_t n, int64_t x) {
   // largest s in [0, n) with off[s] <= x
   int64_t lo = 0, hi = n - 1;
@@ -81,60 +57,91 @@ __device__ __forceinline__ int64_t find_segment(const int64_t* off, int64_t n, i
 
 // ------------------------------------------------------------ prep
 
-// One 256-thread workgroup per lightcurve: weights (Section 1: w ~ sigma^-2,
-// sum w = 1; all sigma = 0 -> uniform), ybar, YY = chi^2_0, t_ref.
-__global__ __launch_bounds__(256) void k_prep_stats(LcInfo* lcs, const double* __restrict__ t,
-                                                    const double* __restrict__ y,
-                                                    const double* __restrict__ sigma) {
-  __shared__ double shd[4];
-  __shared__ int shi[4];
+template <typename T, int NW>
+__device__ __forceinline__ T block_sum_w(T v, T* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  T r = sh[0];
+  for (int k = 1; k < NW; ++k) r += sh[k];
+  __syncthreads();
+  return r;
+}
+
+template <int NW>
+__device__ __forceinline__ double block_min_w(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int k = 1; k < NW; ++k) r = fmin(r, sh[k]);
+  __syncthreads();
+  return r;
+}
+
+// One 1024-thread workgroup per lightcurve: weights (Section 1: w ~ sigma^-2,
+// sum w = 1; all sigma = 0 -> uniform), ybar, YY = chi^2_0, t_ref.  Two passes
+// over the observations: the first gathers the extremes, sum sigma^-2 and
+// sum y sigma^-2 (ybar), the second YY around ybar.
+constexpr int kStatThreads = 1024;
+__global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const double* __restrict__ t,
+                                                             const double* __restrict__ y,
+                                                             const double* __restrict__ sigma) {
+  constexpr int NW = kStatThreads / 64;
+  __shared__ double shd[NW];
+  __shared__ int shi[NW];
   LcInfo& L = lcs[blockIdx.x];
   const int64_t b = L.obs_off, n = L.n_obs;
-  double sinv = 0.0, tmin = INFINITY, tmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+  double sinv = 0.0, swy = 0.0, sy0 = 0.0, tmin = INFINITY, tmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
   int nzero = 0, bad = 0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    double ti = t[b + i], yi = y[b + i], si = sigma[b + i];
+#pragma unroll 4
+  for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
+    const double ti = t[b + i], yi = y[b + i], si = sigma[b + i];
     if (!isfinite(ti) || !isfinite(yi) || !isfinite(si) || si < 0.0) bad = 1;
-    if (si == 0.0) nzero++;
-    else sinv += 1.0 / (si * si);
+    if (si == 0.0) {
+      nzero++;
+      sy0 += yi;
+    } else {
+      const double iw = 1.0 / (si * si);
+      sinv += iw;
+      swy += iw * yi;
+    }
     tmin = fmin(tmin, ti);
     tmax = fmax(tmax, ti);
     ymin = fmin(ymin, yi);
     ymax = fmax(ymax, yi);
   }
-  sinv = block_sum(sinv, shd);
-  tmin = block_min(tmin, shd);
-  tmax = -block_min(-tmax, shd);
-  ymin = block_min(ymin, shd);
-  ymax = -block_min(-ymax, shd);
-  nzero = block_sum(nzero, shi);
-  bad = block_sum(bad, shi);
+  sinv = block_sum_w<double, NW>(sinv, shd);
+  swy = block_sum_w<double, NW>(swy, shd);
+  sy0 = block_sum_w<double, NW>(sy0, shd);
+  tmin = block_min_w<NW>(tmin, shd);
+  tmax = -block_min_w<NW>(-tmax, shd);
+  ymin = block_min_w<NW>(ymin, shd);
+  ymax = -block_min_w<NW>(-ymax, shd);
+  nzero = block_sum_w<int, NW>(nzero, shi);
+  bad = block_sum_w<int, NW>(bad, shi);
   int status = 0;
   int wmode = 0;
-  double winv = 0.0;
+  double winv = 0.0, ybar = 0.0;
   if (bad) status |= LC_BAD_INPUT;
-  if (nzero == n) { wmode = 1; winv = 1.0 / (double)n; }
+  if (nzero == n) { wmode = 1; winv = 1.0 / (double)n; ybar = sy0 * winv; }
   else if (nzero > 0) status |= LC_MIXED_SIGMA;
-  else winv = 1.0 / sinv;
-  double sy = 0.0;
-  if (status == 0) {
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-      double si = sigma[b + i];
-      double w = (wmode ? 1.0 : 1.0 / (si * si)) * winv;
-      sy += w * y[b + i];
-    }
-  }
-  double ybar = block_sum(sy, shd);
+  else { winv = 1.0 / sinv; ybar = swy * winv; }
   double syy = 0.0;
   if (status == 0) {
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-      double si = sigma[b + i];
-      double w = (wmode ? 1.0 : 1.0 / (si * si)) * winv;
-      double d = y[b + i] - ybar;
+#pragma unroll 4
+    for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
+      const double si = sigma[b + i];
+      const double w = (wmode ? 1.0 : 1.0 / (si * si)) * winv;
+      const double d = y[b + i] - ybar;
       syy += w * d * d;
     }
   }
-  double yy = block_sum(syy, shd);
+  const double yy = block_sum_w<double, NW>(syy, shd);
   // Var(y) = 0 means every y_i is equal (rounding may leave yy slightly > 0)
   if (status == 0 && (!(yy > 0.0 && isfinite(yy)) || ymin == ymax)) status |= LC_ZERO_VAR;
   if (threadIdx.x == 0) {
@@ -153,8 +160,8 @@ __device__ __forceinline__ void tile_span(int cell, int msp, int log2n, int& t0,
   const int ntile = n / kTileCells;
   int lo = cell - msp + 1;
   int hi = cell + msp;
-  lo = (lo % n + n) % n;
-  hi = (hi % n + n) % n;
+  lo &= n - 1;   // n is a power of two
+  hi &= n - 1;
   t0 = lo / kTileCells;
   t1 = hi / kTileCells;
   if (t1 == t0) t1 = -1;
@@ -204,7 +211,7 @@ __global__ __launch_bounds__(256) void k_prep_points(const LcInfo* __restrict__ 
     if (fr >= 1.0) { fr -= 1.0; c += 1.0; }
     long long ci = (long long)c;
     const long long n = 1LL << log2n;
-    ci = ((ci % n) + n) % n;
+    ci &= n - 1;   // n is a power of two
     // modulation phase frac(m_c x)
     double ph, pl;
     const double mc = (double)L.mc[g];
@@ -225,6 +232,38 @@ __global__ __launch_bounds__(256) void k_prep_points(const LcInfo* __restrict__ 
   }
   pw[i] = recs[0];
   py[i] = recs[1];
+}
+
+// Exclusive scan of 32-bit counts into 64-bit offsets, one workgroup for up
+// to kScanSingleMax counts: thread k scans a contiguous run of
+// ceil(n / 1024) counts; the run totals are scanned across the workgroup.
+// out[n] and *total receive the sum.
+constexpr int64_t kScanSingleMax = 1024 * 8;
+__global__ __launch_bounds__(1024) void k_scan_single(const unsigned int* __restrict__ in, int64_t n,
+                                                      int64_t* __restrict__ out, int64_t* __restrict__ total) {
+  __shared__ int64_t sh[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b = tid * per, e = b + per < n ? b + per : n;
+  int64_t s = 0;
+  for (int64_t k = b; k < e; ++k) s += in[k];
+  sh[tid] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t a = tid >= o ? sh[tid - o] : 0;
+    __syncthreads();
+    sh[tid] += a;
+    __syncthreads();
+  }
+  int64_t run = sh[tid] - s;
+  for (int64_t k = b; k < e; ++k) {
+    out[k] = run;
+    run += in[k];
+  }
+  if (tid == 1023) {
+    out[n] = sh[1023];
+    *total = sh[1023];
+  }
 }
 
 // Exclusive scan of 32-bit counts into 64-bit offsets: three kernels.

@@ -391,32 +391,50 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
       // f(x) = sum_j rho_{j-K} u^j v^{2K-j}, u = 1 + i x, v = 1 - i x,
       // rho_d = r_d e^{i d phi0}; homogeneous Horner h_l = u h_{l-1} + rho_{K-l} v^l
       const double cK = rdlane(tab_c, (K * k0) & 15), sK = rdlane(tab_s, (K * k0) & 15);
-      for (int c = lane; c <= D; c += 64) {
-        S.hb[0][c] = c == 0 ? cmul(W.r[K], make_double2(cK, sK)) : make_double2(0.0, 0.0);
-        S.vb[0][c] = c == 0 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
-      }
-      wave_sync();
-      for (int l = 1; l <= D; ++l) {
-        const int d = K - l;
-        const double2 rd = d >= 0 ? W.r[d] : cconj(W.r[-d]);
-        const int m = (d * k0) & 15;
-        const double2 rho = cmul(rd, make_double2(rdlane(tab_c, m), rdlane(tab_s, m)));
-        const double2* hsrc = (l & 1) ? S.hb[0] : S.hb[1];
-        const double2* vsrc = (l & 1) ? S.vb[0] : S.vb[1];
-        double2* hdst = (l & 1) ? S.hb[1] : S.hb[0];
-        double2* vdst = (l & 1) ? S.vb[1] : S.vb[0];
+      if (D < 64) {
+        // lane c holds coefficient c of h and v; multiplying by (1 + i x) or
+        // (1 - i x) takes the coefficient below from the next lower lane
+        double2 h = lane == 0 ? cmul(W.r[K], make_double2(cK, sK)) : make_double2(0.0, 0.0);
+        double2 v = lane == 0 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+        for (int l = 1; l <= D; ++l) {
+          const int d = K - l;
+          const double2 rd = d >= 0 ? W.r[d] : cconj(W.r[-d]);
+          const int m = (d * k0) & 15;
+          const double2 rho = cmul(rd, make_double2(rdlane(tab_c, m), rdlane(tab_s, m)));
+          const double vpx = lane_shr1(v.x), vpy = lane_shr1(v.y);
+          const double hpx = lane_shr1(h.x), hpy = lane_shr1(h.y);
+          v = make_double2(v.x + vpy, v.y - vpx);
+          h = cadd(make_double2(h.x - hpy, h.y + hpx), cmul(rho, v));
+        }
+        if (lane <= D) Rr[RL.f + lane] = h.x;
+      } else {
         for (int c = lane; c <= D; c += 64) {
-          const double2 vprev = c > 0 ? vsrc[c - 1] : make_double2(0.0, 0.0);
-          const double2 hprev = c > 0 ? hsrc[c - 1] : make_double2(0.0, 0.0);
-          const double2 vnew = make_double2(vsrc[c].x + vprev.y, vsrc[c].y - vprev.x);
-          const double2 hnew = make_double2(hsrc[c].x - hprev.y, hsrc[c].y + hprev.x);
-          vdst[c] = vnew;
-          hdst[c] = cadd(hnew, cmul(rho, vnew));
+          S.hb[0][c] = c == 0 ? cmul(W.r[K], make_double2(cK, sK)) : make_double2(0.0, 0.0);
+          S.vb[0][c] = c == 0 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
         }
         wave_sync();
+        for (int l = 1; l <= D; ++l) {
+          const int d = K - l;
+          const double2 rd = d >= 0 ? W.r[d] : cconj(W.r[-d]);
+          const int m = (d * k0) & 15;
+          const double2 rho = cmul(rd, make_double2(rdlane(tab_c, m), rdlane(tab_s, m)));
+          const double2* hsrc = (l & 1) ? S.hb[0] : S.hb[1];
+          const double2* vsrc = (l & 1) ? S.vb[0] : S.vb[1];
+          double2* hdst = (l & 1) ? S.hb[1] : S.hb[0];
+          double2* vdst = (l & 1) ? S.vb[1] : S.vb[0];
+          for (int c = lane; c <= D; c += 64) {
+            const double2 vprev = c > 0 ? vsrc[c - 1] : make_double2(0.0, 0.0);
+            const double2 hprev = c > 0 ? hsrc[c - 1] : make_double2(0.0, 0.0);
+            const double2 vnew = make_double2(vsrc[c].x + vprev.y, vsrc[c].y - vprev.x);
+            const double2 hnew = make_double2(hsrc[c].x - hprev.y, hsrc[c].y + hprev.x);
+            vdst[c] = vnew;
+            hdst[c] = cadd(hnew, cmul(rho, vnew));
+          }
+          wave_sync();
+        }
+        const double2* hfin = (D & 1) ? S.hb[1] : S.hb[0];
+        for (int c = lane; c <= D; c += 64) Rr[RL.f + c] = hfin[c].x;
       }
-      const double2* hfin = (D & 1) ? S.hb[1] : S.hb[0];
-      for (int c = lane; c <= D; c += 64) Rr[RL.f + c] = hfin[c].x;
     }
     for (int d = lane; d <= K; d += 64) { Rr[RL.r + 2 * d] = W.r[d].x; Rr[RL.r + 2 * d + 1] = W.r[d].y; }
     for (int e = lane; e <= 2 * H; e += 64) { Rr[RL.mu + 2 * e] = W.mu[e].x; Rr[RL.mu + 2 * e + 1] = W.mu[e].y; }
@@ -538,25 +556,26 @@ __global__ __launch_bounds__(64) void k_score(SolveArgs a, const double* rec, in
     if (mmmax <= floor_mm) stout = ST_DEGENERATE;
     const bool ok = valid && (c.MM > floor_mm || stout == ST_DEGENERATE);
     Best b = select_best(c.P, th, wrap_2pi(th + kTwoPi * ref), c.YM, ok, lane);
+    // Newton polish of the winner on R(theta) (Eq. theta2cond): a step is
+    // kept only if it is small and P does not drop; a step below 1e-13 rad
+    // changes P by O(1e-26) and ends the polish without re-scoring
     double best_th = b.th_rel;
+    Cand cb = {__shfl(c.P, b.lane), __shfl(c.YM, b.lane), __shfl(c.MM, b.lane), __shfl(c.Mbar, b.lane)};
     if (stout != ST_DEGENERATE && stout != ST_CONSTANT) {
-      double cur = best_th;
-      double curP = eval_candidate(W, H, cur).P;
       for (int it = 0; it < 3; ++it) {
         double Rv, dR;
-        eval_R(W, H, cur, Rv, dR);
+        eval_R(W, H, best_th, Rv, dR);
         if (!(dR != 0.0) || !isfinite(Rv / dR)) break;
-        const double nt = cur - Rv / dR;
-        if (fabs(nt - cur) > 1e-3) break;
-        const double nP = eval_candidate(W, H, nt).P;
-        if (!(nP >= curP)) break;
-        cur = nt;
-        curP = nP;
+        const double step = Rv / dR;
+        if (fabs(step) > 1e-3 || fabs(step) < 1e-13) break;
+        const double nt = best_th - step;
+        const Cand nc = eval_candidate(W, H, nt);
+        if (!(nc.P >= cb.P)) break;
+        best_th = nt;
+        cb = nc;
       }
-      best_th = cur;
     }
     if (lane == 0) {
-      const Cand cb = eval_candidate(W, H, best_th);
       const double sq = sqrt(L.yy);
       double P = cb.P, amp = cb.MM > 0.0 ? cb.YM / cb.MM * sq : 0.0;
       double off = L.ybar - cb.Mbar * amp;
