@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solvers", default="plain,learned,uniform,aberth",
                     help="solvers to time (comma separated; plain and the reported solver are always timed)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of tuning them before the timed steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy before the bench (reference kernel for "
                          "the HBM byte counters)")
@@ -148,6 +150,8 @@ def main():
         if name == "learned":
             pl.load_mlp(w, meta["width"])
         o = pl.alloc_outputs(lc.n_f, dev)
+        if not args.no_autotune:   # launch shapes tuned on this workload (outside the timed region)
+            pl.autotune(t, y, s, lc.df, lc.n_f)
         ms, st = run_solver(F, pl, t, y, s, lc, o, args.steps, args.warmup)
         runs[name] = (pl, o, ms, st)
     plan, out, ms_step, st = runs[args.solver]
@@ -193,7 +197,7 @@ def main():
                     "mlp_forward": "k_gemm_bf16 (MFMA bf16)"}
     solvers = {}
     for name, (_, o, ms, stn) in runs.items():
-        solvers[name] = {"value": pairs / (ms * 1e-3), "ms_per_step": ms,
+        solvers[name] = {"value": pairs / (ms * 1e-3), "ms_per_step": ms, "launch_shapes": runs[name][0].tuning(),
                          "max_abs_dP_vs_plain": float(torch.max(torch.abs(o["power"] - out_p["power"]))),
                          "unconfirmed_rate": stn["n_fallback"] / pairs, "companion_rate": stn["n_fallback_qr"] / pairs,
                          "ms_roots": stn["ms_roots"], "ms_mlp": stn["ms_mlp"], "ms_verify": stn["ms_verify"],

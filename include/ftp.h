@@ -50,6 +50,7 @@ extern "C" {
 #define FTP_E_HIP -8           /* a HIP runtime call failed (see ftp_last_error) */
 #define FTP_E_OPTION -9        /* an option value is invalid */
 #define FTP_E_NO_MODEL -10     /* learned solver requested but no network loaded */
+#define FTP_E_IO -11           /* a file could not be read or written (tuning cache) */
 
 /* per-frequency status values (uint8) */
 #define FTP_ST_OK 0
@@ -112,6 +113,22 @@ typedef struct {
   double ms_aberth;        /* learned / uniform / Aberth: the Aberth kernel (ms) */
   double ms_fallback;      /* learned / uniform / Aberth: companion solve of what is left (ms) */
 } ftp_stats;
+
+/* Launch shapes of the per-frequency kernels, in wavefronts per compute
+ * unit (1..256).  They change timing only: every frequency is computed by one
+ * wavefront whatever the grid, so results are identical for every setting.
+ * The companion-QR and Aberth kernels, whose work per frequency varies with
+ * their iteration counts, take frequencies from a work queue; assembly,
+ * Newton + Sturm and scoring stride over them. */
+typedef struct {
+  int assemble_wpc;     /* assembly (and network features) */
+  int newton_wpc;       /* Newton + Sturm (learned / uniform) */
+  int aberth_wpc;       /* Aberth */
+  int qr_wpc;           /* companion QR */
+  int score_wpc;        /* scoring */
+} ftp_tuning;
+
+#define FTP_TUNE_FORCE 1u   /* ftp_autotune: measure even if the cache holds an entry */
 
 /* Fill `opt` with the defaults.  Returns FTP_E_NULL if opt is NULL. */
 int ftp_options_default(ftp_options* opt);
@@ -226,6 +243,43 @@ int ftp_mlp_train_step(ftp_mlp* net, const uint16_t* X, int64_t B, const float* 
  * the feature frame (roots, device n_f x R; nroots, device n_f, capped at R). */
 int ftp_learned_dataset(ftp_plan* plan, const double* t, const double* y, const double* sigma, int64_t n_obs,
                         double df, int64_t n_f, uint16_t* X, float* roots, int* nroots, int R, void* stream);
+
+/* Current launch shapes of the plan (defaults until set or tuned). */
+int ftp_plan_get_tuning(const ftp_plan* plan, ftp_tuning* out);
+
+/* Set the launch shapes.  FTP_E_OPTION if a field is outside 1..256. */
+int ftp_plan_set_tuning(ftp_plan* plan, const ftp_tuning* tuning);
+
+/*
+ * Autotuner of the launch shapes (the schedule of the ragged-batch path): on
+ * the given lightcurve (same arguments as ftp_periodogram; device arrays),
+ * each shape that matters for the plan's solver is swept over 4..64 waves per
+ * compute unit, one at a time, keeping the fastest whole periodogram call
+ * (best of two, HIP events on `stream`).  The result is applied to the plan
+ * and written to *out.
+ * cache_path (nullable): a text file of "key assemble newton aberth qr score"
+ * lines; the key (ftp_plan_tune_key) names the device, its compute units, H,
+ * precision and solver.  An entry found there is applied without measuring
+ * (unless flags has FTP_TUNE_FORCE); a measured result is stored there.
+ * Returns 1 when the cache supplied the shapes, 0 when they were measured, or
+ * an error (FTP_E_*; the plan's shapes are then unchanged).  Allocates
+ * scratch outputs of n_f frequencies; synchronises `stream`; the timing calls
+ * count in the ftp_last_stats window like any other call.
+ */
+int ftp_autotune(ftp_plan* plan, const double* t, const double* y, const double* sigma, int64_t n_obs, double df,
+                 int64_t n_f, const char* cache_path, unsigned flags, ftp_tuning* out, void* stream);
+
+/* Cache key of the plan ("<arch>/<CUs>cu/H<H>/p<precision>/s<solver>") into
+ * buf (len bytes, NUL terminated).  FTP_E_SIZE if it does not fit. */
+int ftp_plan_tune_key(const ftp_plan* plan, char* buf, int len);
+
+/* Tuning-cache file access (host only, no device use).  lookup: 1 and *out
+ * filled when `key` has a well-formed entry, 0 when it has none (or the file
+ * does not exist); store: replaces or appends the entry, rewriting the file
+ * through a temporary and a rename.  Errors: FTP_E_NULL, FTP_E_OPTION (empty
+ * key, white space in it, or a field outside 1..256), FTP_E_IO. */
+int ftp_tune_cache_lookup(const char* path, const char* key, ftp_tuning* out);
+int ftp_tune_cache_store(const char* path, const char* key, const ftp_tuning* tuning);
 
 /* Statistics accumulated over the plan's calls since the previous
  * ftp_last_stats (or plan creation); resets the accumulation.  Synchronises

@@ -32,7 +32,12 @@ EXPORTED = [
     "ftp_last_stats", "ftp_status_string", "ftp_last_error",
     "ftp_mlp_create", "ftp_mlp_destroy", "ftp_mlp_num_params", "ftp_mlp_get_weights", "ftp_mlp_forward",
     "ftp_mlp_loss_grad", "ftp_mlp_train_step", "ftp_learned_dataset",
+    "ftp_plan_get_tuning", "ftp_plan_set_tuning", "ftp_autotune", "ftp_plan_tune_key",
+    "ftp_tune_cache_lookup", "ftp_tune_cache_store",
 ]
+
+FTP_TUNE_FORCE = 1
+FTP_E_IO = -11
 
 
 class Options(ctypes.Structure):
@@ -46,6 +51,15 @@ class Stats(ctypes.Structure):
                 ("aberth_iters", ctypes.c_uint64), ("ms_nfft", ctypes.c_double), ("ms_solve", ctypes.c_double),
                 ("ms_roots", ctypes.c_double), ("ms_mlp", ctypes.c_double), ("ms_verify", ctypes.c_double),
                 ("ms_aberth", ctypes.c_double), ("ms_fallback", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    """Launch shapes of the per-frequency kernels (waves per compute unit)."""
+    _fields_ = [("assemble_wpc", ctypes.c_int), ("newton_wpc", ctypes.c_int), ("aberth_wpc", ctypes.c_int),
+                ("qr_wpc", ctypes.c_int), ("score_wpc", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class FtpError(RuntimeError):
@@ -83,6 +97,13 @@ def load_library(path: Optional[str] = None):
     lib.ftp_mlp_train_step.argtypes = [vp, vp, i64, vp, vp, ip, ctypes.c_float, ctypes.c_float, vp, vp]
     lib.ftp_learned_dataset.argtypes = [vp, vp, vp, vp, i64, dbl, i64, vp, vp, vp, ip, vp]
     lib.ftp_status_string.argtypes = [ip]
+    lib.ftp_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.ftp_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.ftp_autotune.argtypes = [vp, vp, vp, vp, i64, dbl, i64, ctypes.c_char_p, ctypes.c_uint,
+                                 ctypes.POINTER(Tuning), vp]
+    lib.ftp_plan_tune_key.argtypes = [vp, ctypes.c_char_p, ip]
+    lib.ftp_tune_cache_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(Tuning)]
+    lib.ftp_tune_cache_store.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(Tuning)]
     lib.ftp_status_string.restype = ctypes.c_char_p
     lib.ftp_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -240,6 +261,38 @@ class Plan:
         w = np.ascontiguousarray(weights, dtype=np.float32)
         _check(self.lib.ftp_plan_load_mlp(self.handle, w.ctypes.data_as(ctypes.c_void_p), w.size, int(width)))
 
+    def tuning(self) -> dict:
+        tu = Tuning()
+        _check(self.lib.ftp_plan_get_tuning(self.handle, ctypes.byref(tu)))
+        return tu.as_dict()
+
+    def set_tuning(self, **kw):
+        tu = Tuning()
+        _check(self.lib.ftp_plan_get_tuning(self.handle, ctypes.byref(tu)))
+        for k, v in kw.items():
+            setattr(tu, k, int(v))
+        _check(self.lib.ftp_plan_set_tuning(self.handle, ctypes.byref(tu)))
+
+    def tune_key(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        _check(self.lib.ftp_plan_tune_key(self.handle, buf, 256))
+        return buf.value.decode()
+
+    def autotune(self, t, y, sigma, df: float, n_f: int, cache_path: Optional[str] = None, force: bool = False,
+                 device="cuda", stream=None):
+        """Tune the launch shapes on one lightcurve; returns (shapes, from_cache)."""
+        torch = _torch()
+        t = _dev(t, torch.float64, device)
+        y = _dev(y, torch.float64, device)
+        sigma = _dev(sigma, torch.float64, device)
+        tu = Tuning()
+        rc = self.lib.ftp_autotune(self.handle, _ptr(t), _ptr(y), _ptr(sigma), t.numel(), float(df), int(n_f),
+                                   cache_path.encode() if cache_path else None, FTP_TUNE_FORCE if force else 0,
+                                   ctypes.byref(tu), _stream_ptr(stream))
+        if rc < 0:
+            _check(rc)
+        return tu.as_dict(), rc == 1
+
     def stats(self, stream=None) -> dict:
         st = Stats()
         _check(self.lib.ftp_last_stats(self.handle, ctypes.byref(st), _stream_ptr(stream)))
@@ -342,3 +395,19 @@ class Mlp:
         _check(self.lib.ftp_mlp_train_step(self.handle, _ptr(X), B, _ptr(roots), _ptr(nroots), R, float(lam),
                                            float(lr), _ptr(loss) if loss is not None else ctypes.c_void_p(0),
                                            _stream_ptr(stream)))
+
+
+def tune_cache_lookup(path: str, key: str):
+    """The cached launch shapes for `key` (dict), or None."""
+    lib = load_library()
+    tu = Tuning()
+    rc = lib.ftp_tune_cache_lookup(path.encode(), key.encode(), ctypes.byref(tu))
+    if rc < 0:
+        _check(rc)
+    return tu.as_dict() if rc == 1 else None
+
+
+def tune_cache_store(path: str, key: str, **shapes):
+    lib = load_library()
+    tu = Tuning(**{k: int(v) for k, v in shapes.items()})
+    _check(lib.ftp_tune_cache_store(path.encode(), key.encode(), ctypes.byref(tu)))

@@ -35,6 +35,7 @@ struct AberthArgs {
   int H;
   double mark;               // M_FALLBACK value written for pairs sent on
   unsigned flags;            // bit 0: send every pair on (companion solve only)
+  unsigned* queue;           // work counter (zeroed), or nullptr for grid striding
 };
 
 __host__ __device__ inline size_t aberth_lds_bytes(int H) {
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(64) void k_aberth(AberthArgs A) {
   const int64_t n = A.list ? (int64_t)(*A.count) : A.np;
   constexpr double u = 1.1102230246251565e-16;
   unsigned long long its_acc = 0, qr_acc = 0;
-  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+  for (int64_t i = first_item(A.queue, lane); i < n; i = next_item(A.queue, lane, i)) {
     const int64_t w = A.list ? A.list[i] : i;
     double* R = A.rec + w * (int64_t)RL.stride;
     if (!A.list) {

@@ -8,9 +8,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cctype>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -39,7 +42,7 @@ template <typename R>
 __global__ void k_fft_pass(const FftGridPass*, int64_t, const int64_t*, const typename Cplx<R>::T*,
                            typename Cplx<R>::T*);
 hipError_t launch_qr(int H, double* rec, int stride, int64_t np, const int64_t* list, const unsigned* list_count,
-                     SolveCounters* counters, int waves, hipStream_t st);
+                     SolveCounters* counters, unsigned* queue, int waves, hipStream_t st);
 hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64_t p0, int64_t np, int waves,
                            hipStream_t st);
 hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves,
@@ -73,6 +76,7 @@ struct LearnArgs {
   int64_t* fb_list;
   unsigned int* fb_count;
   unsigned flags;
+  unsigned* queue;
 };
 hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st);
 struct AberthArgs {
@@ -86,6 +90,7 @@ struct AberthArgs {
   int H;
   double mark;
   unsigned flags;
+  unsigned* queue;
 };
 hipError_t launch_aberth(const AberthArgs& A, int waves, hipStream_t st);
 hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st);
@@ -280,6 +285,7 @@ struct ftp_plan {
   std::vector<double> c, s;
   int device = 0;
   int n_cu = 256;
+  std::string arch = "unknown";
   size_t grid_budget = (size_t)8 << 30;   // bytes of NFFT grids per chunk
   // device buffers
   DevBuf alpha, twiddle32, twiddle64;
@@ -306,9 +312,14 @@ struct ftp_plan {
   float* ds_roots = nullptr;
   int* ds_nroots = nullptr;
   int ds_R = 0;
-  // work lists: Newton -> Aberth (fb_list, count fb_count[0]) and
-  // Aberth -> companion solve (fb2_list, count fb_count[1])
-  DevBuf xfeat, seeds, fb_list, fb2_list, fb_count;
+  // work lists: Newton -> Aberth (fb_list, count work_ctr[0]) and
+  // Aberth -> companion solve (fb2_list, count work_ctr[1]); work_ctr[2..4]
+  // are the queue counters of the Newton, Aberth and QR kernels
+  DevBuf xfeat, seeds, fb_list, fb2_list, work_ctr;
+  // launch shapes (waves per compute unit), set by ftp_plan_set_tuning or
+  // ftp_autotune
+  ftp_tuning tune{32, 32, 16, 16, 32};
+  DevBuf tune_out;
 };
 
 namespace {
@@ -538,52 +549,58 @@ int upload_tables(ftp_plan* P, int64_t n_lc, hipStream_t st) {
   return FTP_OK;
 }
 
-int solve_grid_waves(ftp_plan* P) {
-  if (P->opt.solve_waves > 0) return P->opt.solve_waves;
-  return P->n_cu * 16;
+// Grid of a per-frequency kernel: the option override, else the tuned waves
+// per compute unit; never more waves than pairs.
+int64_t grid_waves(const ftp_plan* P, int wpc, int64_t np) {
+  const int64_t w = P->opt.solve_waves > 0 ? (int64_t)P->opt.solve_waves : (int64_t)wpc * P->n_cu;
+  return std::max<int64_t>(1, std::min<int64_t>(w, np));
 }
 
 // Per-frequency stage over pair chunks: assemble -> roots -> score.  Roots:
-// companion QR (plain) or network features -> MLP -> Newton + Sturm with the
-// companion QR on the fallback list (learned / uniform-seed ablation).
+// companion QR (plain); network features -> MLP -> Newton + Sturm -> Aberth
+// on the unconfirmed pairs -> companion QR on what Aberth leaves (learned,
+// and the uniform-start ablation without the network); Aberth on every pair
+// -> companion QR on what it leaves (Aberth).  The root kernels take their
+// pairs from queue counters.
 int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) {
   if (n_pairs <= 0) return FTP_OK;
   const RecLayout RL(P->H);
   const int64_t chunk = std::min<int64_t>(n_pairs, P->pair_chunk);
   int rc;
   if ((rc = P->rec.ensure(sizeof(double) * (size_t)chunk * RL.stride))) return rc;
+  if ((rc = P->work_ctr.ensure(8 * sizeof(unsigned)))) return rc;
   double* rec = P->rec.as<double>();
-  const int waves = solve_grid_waves(P);
+  unsigned* ctr = P->work_ctr.as<unsigned>();
   const bool dataset = P->ds_X != nullptr;
   const int solver = dataset ? FTP_SOLVER_PLAIN : P->opt.solver;
   if (solver != FTP_SOLVER_PLAIN) {
     if ((rc = P->fb_list.ensure(sizeof(int64_t) * chunk))) return rc;
     if ((rc = P->fb2_list.ensure(sizeof(int64_t) * chunk))) return rc;
-    if ((rc = P->fb_count.ensure(2 * sizeof(unsigned)))) return rc;
     if (solver == FTP_SOLVER_LEARNED) {
       if ((rc = P->xfeat.ensure(sizeof(uint16_t) * chunk * P->net.din))) return rc;
       if ((rc = P->seeds.ensure(sizeof(float) * chunk * P->net.dout))) return rc;
       if ((rc = P->net.ensure_batch(chunk))) return rc;
     }
   }
+  const ftp_tuning& T = P->tune;
   for (int64_t p0 = 0; p0 < n_pairs; p0 += chunk) {
     const int64_t np = std::min<int64_t>(chunk, n_pairs - p0);
-    const int w = (int)std::min<int64_t>(np, waves);
-    const int w2 = (int)std::min<int64_t>(np, 2 * waves);
-    HIP_TRY(launch_assemble(P->opt.precision, a, rec, p0, np, w2, st));
+    const int w_asm = (int)grid_waves(P, T.assemble_wpc, np);
+    const int w_qr = (int)grid_waves(P, T.qr_wpc, np);
+    const int w_nt = (int)grid_waves(P, T.newton_wpc, np);
+    const int w_ab = (int)grid_waves(P, T.aberth_wpc, np);
+    const int w_sc = (int)grid_waves(P, T.score_wpc, np);
+    HIP_TRY(launch_assemble(P->opt.precision, a, rec, p0, np, w_asm, st));
+    HIP_TRY(launch_zero_u32(ctr, 8, st));
     hipEvent_t r0 = next_root_event(P);
     if (r0) HIP_TRY(hipEventRecord(r0, st));
     if (solver == FTP_SOLVER_PLAIN) {
-      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, nullptr, nullptr, P->counters.as<SolveCounters>(), w, st));
+      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, nullptr, nullptr, P->counters.as<SolveCounters>(), ctr + 4, w_qr,
+                        st));
     } else {
-      // learned / uniform: [features, MLP] -> Newton + Sturm -> Aberth on the
-      // unconfirmed pairs -> companion QR on what Aberth leaves;
-      // Aberth solver: Aberth on every pair -> companion QR on what it leaves
-      unsigned* counts = P->fb_count.as<unsigned>();
-      HIP_TRY(launch_zero_u32(counts, 2, st));
       const float* seeds = nullptr;
       if (solver == FTP_SOLVER_LEARNED) {
-        HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), P->net.din, w2, st));
+        HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), P->net.din, w_asm, st));
         if ((rc = mlp_forward(&P->net, P->xfeat.as<uint16_t>(), np, P->seeds.as<float>(), st))) return rc;
         seeds = P->seeds.as<float>();
       }
@@ -595,9 +612,10 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
         L.np = np;
         L.seeds_out = seeds;
         L.fb_list = P->fb_list.as<int64_t>();
-        L.fb_count = counts;
+        L.fb_count = ctr;
         L.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
-        HIP_TRY(launch_newton_sturm(a, L, w2, st));
+        L.queue = nullptr;   // uniform work per pair: grid striding (a queue costs more than it balances)
+        HIP_TRY(launch_newton_sturm(a, L, w_nt, st));
       }
       hipEvent_t rb = next_learn_event(P);
       if (rb) HIP_TRY(hipEventRecord(rb, st));
@@ -605,27 +623,29 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       A.rec = rec;
       A.np = np;
       A.list = solver == FTP_SOLVER_ABERTH ? nullptr : P->fb_list.as<int64_t>();
-      A.count = counts;
+      A.count = ctr;
       A.qr_list = P->fb2_list.as<int64_t>();
-      A.qr_count = counts + 1;
+      A.qr_count = ctr + 1;
       A.counters = P->counters.as<SolveCounters>();
       A.H = P->H;
       A.mark = 2.0;
       A.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
-      HIP_TRY(launch_aberth(A, solver == FTP_SOLVER_ABERTH ? w2 : w, st));
+      A.queue = ctr + 3;
+      HIP_TRY(launch_aberth(A, w_ab, st));
       hipEvent_t rc2 = next_learn_event(P);
       if (rc2) HIP_TRY(hipEventRecord(rc2, st));
-      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, P->fb2_list.as<int64_t>(), counts + 1,
-                        P->counters.as<SolveCounters>(), w, st));
+      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, P->fb2_list.as<int64_t>(), ctr + 1,
+                        P->counters.as<SolveCounters>(), ctr + 4, w_qr, st));
     }
     hipEvent_t r1 = next_root_event(P);
     if (r1) HIP_TRY(hipEventRecord(r1, st));
     if (dataset) {
-      HIP_TRY(launch_features(rec, P->H, np, P->ds_X + p0 * (int64_t)(2 * (6 * P->H - 1)), 2 * (6 * P->H - 1), w2,
-                              st));
-      HIP_TRY(launch_labels(rec, P->H, np, P->ds_roots + p0 * (int64_t)P->ds_R, P->ds_nroots + p0, P->ds_R, w2, st));
+      HIP_TRY(launch_features(rec, P->H, np, P->ds_X + p0 * (int64_t)(2 * (6 * P->H - 1)), 2 * (6 * P->H - 1),
+                              w_asm, st));
+      HIP_TRY(launch_labels(rec, P->H, np, P->ds_roots + p0 * (int64_t)P->ds_R, P->ds_nroots + p0, P->ds_R, w_asm,
+                            st));
     } else {
-      HIP_TRY(launch_score(a, rec, p0, np, w2, st));
+      HIP_TRY(launch_score(a, rec, p0, np, w_sc, st));
     }
   }
   return FTP_OK;
@@ -718,6 +738,43 @@ int run_batch(ftp_plan* P, int64_t n_lc, const int64_t* obs_off, const double* t
   return FTP_OK;
 }
 
+bool tuning_valid(const ftp_tuning& t) {
+  const int v[5] = {t.assemble_wpc, t.newton_wpc, t.aberth_wpc, t.qr_wpc, t.score_wpc};
+  for (int x : v)
+    if (x < 1 || x > 256) return false;
+  return true;
+}
+
+bool key_valid(const char* key) {
+  if (!key || !*key) return false;
+  for (const char* c = key; *c; ++c)
+    if (std::isspace((unsigned char)*c)) return false;
+  return true;
+}
+
+// Device time of one periodogram call (ms) on stream st.
+int time_call(ftp_plan* P, const double* t, const double* y, const double* sigma, int64_t n_obs, double df,
+              int64_t n_f, hipStream_t st, float* ms) {
+  double* out = P->tune_out.as<double>();
+  uint8_t* status = reinterpret_cast<uint8_t*>(out + 4 * n_f);
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  const int64_t obs_off[2] = {0, n_obs};
+  const int64_t freq_off[2] = {0, n_f};
+  HIP_TRY(hipEventRecord(a, st));
+  int rc = run_batch(P, 1, obs_off, t, y, sigma, &df, freq_off, out, out + n_f, out + 2 * n_f, out + 3 * n_f,
+                     status, nullptr, st);
+  if (rc == FTP_OK) {
+    HIP_TRY(hipEventRecord(b, st));
+    HIP_TRY(hipEventSynchronize(b));
+    HIP_TRY(hipEventElapsedTime(ms, a, b));
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -756,7 +813,12 @@ int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, con
   hipError_t e = hipGetDevice(&P->device);
   if (e == hipSuccess) {
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) P->n_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) {
+      P->n_cu = prop.multiProcessorCount;
+      P->arch = prop.gcnArchName;
+      const size_t colon = P->arch.find(':');
+      if (colon != std::string::npos) P->arch.resize(colon);
+    }
   }
   if (e != hipSuccess) { g_last_error = hipGetErrorString(e); delete P; return FTP_E_HIP; }
   std::vector<double2> al(H);
@@ -793,7 +855,7 @@ int ftp_plan_destroy(ftp_plan* P) {
                     &P->grid_tile_base, &P->pw, &P->py, &P->tile_count, &P->tile_off, &P->cursor,
                     &P->block_sums, &P->total, &P->bucket, &P->grids, &P->fft_tab, &P->fft_items,
                     &P->counters, &P->stats_out, &P->rec, &P->xfeat, &P->seeds, &P->fb_list,
-                    &P->fb_count};
+                    &P->fb2_list, &P->work_ctr, &P->tune_out};
   P->net.release();
   for (DevBuf* b : bufs) b->release();
   if (P->upload_done) (void)hipEventDestroy(P->upload_done);
@@ -1034,6 +1096,161 @@ int ftp_learned_dataset(ftp_plan* P, const double* t, const double* y, const dou
   return rc;
 }
 
+int ftp_plan_get_tuning(const ftp_plan* P, ftp_tuning* out) {
+  if (!P || !out) return FTP_E_NULL;
+  *out = P->tune;
+  return FTP_OK;
+}
+
+int ftp_plan_set_tuning(ftp_plan* P, const ftp_tuning* t) {
+  if (!P || !t) return FTP_E_NULL;
+  if (!tuning_valid(*t)) return FTP_E_OPTION;
+  P->tune = *t;
+  return FTP_OK;
+}
+
+int ftp_plan_tune_key(const ftp_plan* P, char* buf, int len) {
+  if (!P || !buf) return FTP_E_NULL;
+  const int n = std::snprintf(buf, len > 0 ? (size_t)len : 0, "%s/%dcu/H%d/p%d/s%d", P->arch.c_str(), P->n_cu,
+                              P->H, P->opt.precision, P->opt.solver);
+  if (n < 0 || n >= len) return FTP_E_SIZE;
+  return FTP_OK;
+}
+
+int ftp_tune_cache_lookup(const char* path, const char* key, ftp_tuning* out) {
+  if (!path || !out) return FTP_E_NULL;
+  if (!key_valid(key)) return FTP_E_OPTION;
+  std::ifstream in(path);
+  if (!in) return 0;
+  std::string line;
+  int found = 0;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::string k;
+    ftp_tuning t{};
+    if (!(ls >> k) || k != key) continue;
+    if (!(ls >> t.assemble_wpc >> t.newton_wpc >> t.aberth_wpc >> t.qr_wpc >> t.score_wpc)) continue;
+    if (!tuning_valid(t)) continue;
+    *out = t;
+    found = 1;   // the last well-formed entry wins
+  }
+  return found;
+}
+
+int ftp_tune_cache_store(const char* path, const char* key, const ftp_tuning* t) {
+  if (!path || !t) return FTP_E_NULL;
+  if (!key_valid(key) || !tuning_valid(*t)) return FTP_E_OPTION;
+  std::vector<std::string> keep;
+  {
+    std::ifstream in(path);
+    std::string line;
+    while (in && std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      if ((ls >> k) && k == key) continue;
+      if (!line.empty()) keep.push_back(line);
+    }
+  }
+  char entry[512];
+  std::snprintf(entry, sizeof(entry), "%s %d %d %d %d %d", key, t->assemble_wpc, t->newton_wpc, t->aberth_wpc,
+                t->qr_wpc, t->score_wpc);
+  keep.push_back(entry);
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out) return FTP_E_IO;
+    for (const std::string& l : keep) out << l << "\n";
+    out.flush();
+    if (!out) return FTP_E_IO;
+  }
+  if (std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return FTP_E_IO;
+  }
+  return FTP_OK;
+}
+
+int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* sigma, int64_t n_obs, double df,
+                 int64_t n_f, const char* cache_path, unsigned flags, ftp_tuning* out, void* stream) {
+  if (!P || !t || !y || !sigma) return FTP_E_NULL;
+  int rc = validate_scalars(df, n_f, n_obs);
+  if (rc) return rc;
+  if (P->opt.solver == FTP_SOLVER_LEARNED && !P->mlp_loaded) return FTP_E_NO_MODEL;
+  char key[256];
+  if ((rc = ftp_plan_tune_key(P, key, (int)sizeof(key)))) return rc;
+  if (cache_path && !(flags & FTP_TUNE_FORCE)) {
+    ftp_tuning c{};
+    rc = ftp_tune_cache_lookup(cache_path, key, &c);
+    if (rc < 0) return rc;
+    if (rc == 1) {
+      P->tune = c;
+      if (out) *out = c;
+      return 1;
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = P->tune_out.ensure((size_t)n_f * (4 * sizeof(double) + 1)))) return rc;
+  const ftp_tuning saved = P->tune;
+  const unsigned saved_flags = P->opt.flags;
+  P->opt.flags &= ~FTP_FLAG_TIME_STAGES;
+  ftp_tuning cur = P->tune;
+  float ms = 0.f;
+  // the knobs that matter for the solver; the QR knob also for the others
+  // (it then only serves the companion fallback, but is cheap to sweep)
+  int* knobs[5];
+  int nk = 0;
+  if (P->opt.solver == FTP_SOLVER_PLAIN) {
+    knobs[nk++] = &cur.qr_wpc;
+  } else {
+    if (P->opt.solver != FTP_SOLVER_ABERTH) knobs[nk++] = &cur.newton_wpc;
+    knobs[nk++] = &cur.aberth_wpc;
+  }
+  knobs[nk++] = &cur.assemble_wpc;
+  knobs[nk++] = &cur.score_wpc;
+  const int cand[] = {4, 8, 12, 16, 24, 32, 48, 64};
+  auto measure = [&](float* best) -> int {
+    P->tune = cur;
+    float m0 = 0.f, m1 = 0.f;
+    int r = time_call(P, t, y, sigma, n_obs, df, n_f, st, &m0);
+    if (r) return r;
+    r = time_call(P, t, y, sigma, n_obs, df, n_f, st, &m1);
+    if (r) return r;
+    *best = std::min(m0, m1);
+    return FTP_OK;
+  };
+  rc = time_call(P, t, y, sigma, n_obs, df, n_f, st, &ms);   // warm-up
+  for (int k = 0; rc == FTP_OK && k < nk; ++k) {
+    int best_v = *knobs[k];
+    float best_ms = 0.f;
+    if ((rc = measure(&best_ms))) break;
+    for (int v : cand) {
+      if (v == best_v) continue;
+      const int keep = *knobs[k];
+      *knobs[k] = v;
+      float m = 0.f;
+      if ((rc = measure(&m))) break;
+      if (m < 0.98f * best_ms) {
+        best_ms = m;
+        best_v = v;
+      }
+      *knobs[k] = keep;
+    }
+    *knobs[k] = best_v;
+  }
+  P->opt.flags = saved_flags;
+  if (rc != FTP_OK) {
+    P->tune = saved;
+    return rc;
+  }
+  P->tune = cur;
+  if (out) *out = cur;
+  if (cache_path) {
+    const int wr = ftp_tune_cache_store(cache_path, key, &cur);
+    if (wr < 0) return wr;
+  }
+  return 0;
+}
+
 int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
   if (!P || !out) return FTP_E_NULL;
   SolveCounters c{};
@@ -1099,6 +1316,7 @@ const char* ftp_status_string(int code) {
     case FTP_E_HIP: return "HIP runtime error";
     case FTP_E_OPTION: return "invalid option";
     case FTP_E_NO_MODEL: return "learned solver requested but no network is loaded";
+    case FTP_E_IO: return "file could not be read or written";
     case FTP_ST_DEGENERATE: return "degenerate frequency (MM ~ 0)";
     case FTP_ST_CONSTANT: return "phase polynomial vanishes (P constant in phase)";
     case FTP_ST_NO_CONVERGE: return "companion QR did not converge";

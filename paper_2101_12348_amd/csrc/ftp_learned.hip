@@ -166,6 +166,7 @@ struct LearnArgs {
   int64_t* fb_list;
   unsigned int* fb_count;
   unsigned flags;
+  unsigned* queue;          // work counter (zeroed), or nullptr for grid striding
 };
 
 __host__ __device__ inline size_t learn_lds_bytes(int H) {
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
   double* tmp = fl + (D + 1);            // 2 (D + 1) scratch doubles
   double* ch = tmp + 2 * (D + 1);        // Sturm sequence storage
   unsigned long long iters_acc = 0, roots_acc = 0, fb_acc = 0;
-  for (int64_t w = blockIdx.x; w < L.np; w += gridDim.x) {
+  for (int64_t w = first_item(L.queue, lane); w < L.np; w = next_item(L.queue, lane, w)) {
     double* R = L.rec + w * (int64_t)RL.stride;
     const int st = (int)R[RL.meta + M_STATUS];
     if (st == ST_BAD_LC || st == ST_CONSTANT) continue;

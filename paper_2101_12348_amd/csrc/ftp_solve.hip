@@ -236,7 +236,8 @@ __host__ __device__ inline size_t qr_lds_bytes(int D) {
 // Candidates theta_rel (relative to t_ref) go to rec.cand; NaN marks none.
 template <int N>
 __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, const int64_t* list,
-                                           const unsigned int* list_count, SolveCounters* counters) {
+                                           const unsigned int* list_count, SolveCounters* counters,
+                                           unsigned* queue) {
   extern __shared__ double smq[];
   constexpr int ld = N + 1;
   double* A = smq;
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, 
   int64_t total = np;
   if (list) total = (int64_t)*list_count;
   unsigned long long sweeps_acc = 0;
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int64_t w = first_item(queue, lane); w < total; w = next_item(queue, lane, w)) {
     const int64_t q = list ? list[w] : w;
     double* R = rec + q * (int64_t)stride;
     const int st = (int)R[RL.meta + M_STATUS];
@@ -635,26 +636,27 @@ __global__ void k_export_stats(const LcInfo* lcs, double* out) {
 
 template <int N>
 static hipError_t launch_qr_n(double* rec, int stride, int64_t np, const int64_t* list,
-                              const unsigned* list_count, SolveCounters* counters, int waves, hipStream_t st) {
+                              const unsigned* list_count, SolveCounters* counters, unsigned* queue, int waves,
+                              hipStream_t st) {
   hipLaunchKernelGGL(k_qr<N>, dim3((unsigned)waves), dim3(64), qr_lds_bytes(N), st, rec, stride, np, list,
-                     list_count, counters);
+                     list_count, counters, queue);
   return hipGetLastError();
 }
 
 hipError_t launch_qr(int H, double* rec, int stride, int64_t np, const int64_t* list, const unsigned* list_count,
-                     SolveCounters* counters, int waves, hipStream_t st) {
+                     SolveCounters* counters, unsigned* queue, int waves, hipStream_t st) {
   switch (H) {
-    case 1: return launch_qr_n<4>(rec, stride, np, list, list_count, counters, waves, st);
-    case 2: return launch_qr_n<10>(rec, stride, np, list, list_count, counters, waves, st);
-    case 3: return launch_qr_n<16>(rec, stride, np, list, list_count, counters, waves, st);
-    case 4: return launch_qr_n<22>(rec, stride, np, list, list_count, counters, waves, st);
-    case 5: return launch_qr_n<28>(rec, stride, np, list, list_count, counters, waves, st);
-    case 6: return launch_qr_n<34>(rec, stride, np, list, list_count, counters, waves, st);
-    case 7: return launch_qr_n<40>(rec, stride, np, list, list_count, counters, waves, st);
-    case 8: return launch_qr_n<46>(rec, stride, np, list, list_count, counters, waves, st);
-    case 9: return launch_qr_n<52>(rec, stride, np, list, list_count, counters, waves, st);
-    case 10: return launch_qr_n<58>(rec, stride, np, list, list_count, counters, waves, st);
-    case 11: return launch_qr_n<64>(rec, stride, np, list, list_count, counters, waves, st);
+    case 1: return launch_qr_n<4>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 2: return launch_qr_n<10>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 3: return launch_qr_n<16>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 4: return launch_qr_n<22>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 5: return launch_qr_n<28>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 6: return launch_qr_n<34>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 7: return launch_qr_n<40>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 8: return launch_qr_n<46>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 9: return launch_qr_n<52>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 10: return launch_qr_n<58>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 11: return launch_qr_n<64>(rec, stride, np, list, list_count, counters, queue, waves, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -256,6 +256,22 @@ __device__ __forceinline__ double lane_shl1(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// Work distribution of the persistent root kernels: wavefront b starts on
+// item b; with a queue counter (zeroed before the launch) it then takes item
+// gridDim.x + ticket when it is done, lane 0 taking the ticket with a vector
+// atomic and the wave reading it from lane 0, so waves without work leave
+// without touching the counter; without a counter, items are strided by the
+// grid.
+__device__ __forceinline__ int64_t take_ticket(unsigned* q, int lane) {
+  unsigned v = 0u;
+  if (lane == 0) v = atomicAdd(q, 1u);
+  return (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ int64_t first_item(unsigned*, int) { return (int64_t)blockIdx.x; }
+__device__ __forceinline__ int64_t next_item(unsigned* q, int lane, int64_t w) {
+  return q ? (int64_t)gridDim.x + take_ticket(q, lane) : w + (int64_t)gridDim.x;
+}
+
 // Candidate evaluation at relative phase theta: returns P (normalised,
 // YY = 1), YM, MM and Mbar.
 struct Cand { double P, YM, MM, Mbar; };

@@ -80,3 +80,34 @@ def test_host_validation_without_device():
     assert lib.ftp_plan_create(ctypes.byref(h), 3, vp(c), vp(s), ctypes.byref(opt)) == -9
     assert lib.ftp_periodogram(None, None, None, None, 10, 0.1, 10, None, None, None, None, None, None) == -1
     assert lib.ftp_plan_destroy(None) == -1
+
+
+def test_tuning_cache_file_round_trip(tmp_path):
+    """The autotuner's cache file: lookup of a missing file or key, replace
+    and append, malformed and out-of-range lines ignored, bad keys and shapes
+    rejected, an unwritable path reported (host code only)."""
+    import paper_2101_12348_amd as F
+    F.load_library()
+    p = str(tmp_path / "tune.txt")
+    key = "gfx950/256cu/H6/p0/s1"
+    assert F.tune_cache_lookup(p, key) is None
+    shapes = dict(assemble_wpc=32, newton_wpc=16, aberth_wpc=8, qr_wpc=16, score_wpc=24)
+    F.tune_cache_store(p, key, **shapes)
+    F.tune_cache_store(p, "gfx950/256cu/H4/p0/s0", **{k: 4 for k in shapes})
+    assert F.tune_cache_lookup(p, key) == shapes
+    shapes2 = dict(shapes, qr_wpc=48)
+    F.tune_cache_store(p, key, **shapes2)
+    lines = open(p).read().splitlines()
+    assert sum(1 for l in lines if l.split()[0] == key) == 1 and len(lines) == 2
+    assert F.tune_cache_lookup(p, key) == shapes2
+    with open(p, "a") as fh:
+        fh.write("garbage line\n" + key + " 1 2 3\n" + "gfx950/256cu/H3/p0/s0 0 4 4 4 4\n")
+    assert F.tune_cache_lookup(p, key) == shapes2
+    assert F.tune_cache_lookup(p, "gfx950/256cu/H3/p0/s0") is None
+    for bad_key in ("", "has space"):
+        with pytest.raises(F.FtpError):
+            F.tune_cache_store(p, bad_key, **shapes)
+    with pytest.raises(F.FtpError):
+        F.tune_cache_store(p, key, **dict(shapes, score_wpc=0))
+    with pytest.raises(F.FtpError):
+        F.tune_cache_store(str(tmp_path / "missing_dir" / "tune.txt"), key, **shapes)

@@ -1,0 +1,69 @@
+"""Launch shapes and the autotuner (the schedule of the per-frequency stage).
+
+* Every frequency is computed by one wavefront whatever the grid and the
+  queue order, so outputs are bit-identical across launch shapes.
+* The autotuner returns valid shapes, applies them, stores them in its cache
+  and serves the next request for the same key from there.
+"""
+import numpy as np
+import pytest
+
+from synthetic import single_long_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ftp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2101_12348_amd as F
+    F.load_library()
+    return F
+
+
+@pytest.mark.parametrize("solver", [0, 2, 3])
+def test_outputs_do_not_depend_on_launch_shapes(ftp, solver):
+    import torch
+    tmpl, lc = single_long_case(n_obs=2000)
+    n_f = 6000
+    plan = ftp.Plan(tmpl.c, tmpl.s, solver=solver)
+    ref = {k: v.clone() for k, v in plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
+    for wpc in (1, 3, 64):
+        plan.set_tuning(assemble_wpc=wpc, newton_wpc=wpc, aberth_wpc=wpc, qr_wpc=wpc, score_wpc=wpc)
+        out = plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
+        for k in ref:
+            assert torch.equal(ref[k], out[k]), (wpc, k)
+
+
+def test_set_tuning_rejects_bad_shapes(ftp):
+    tmpl, _ = single_long_case(n_obs=500)
+    plan = ftp.Plan(tmpl.c, tmpl.s)
+    before = plan.tuning()
+    for bad in (0, 257, -3):
+        with pytest.raises(ftp.FtpError):
+            plan.set_tuning(qr_wpc=bad)
+    assert plan.tuning() == before
+
+
+def test_autotune_and_cache(ftp, tmp_path):
+    import torch
+    tmpl, lc = single_long_case(n_obs=2000)
+    n_f = 6000
+    plan = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_UNIFORM)
+    ref = {k: v.clone() for k, v in plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
+    cache = str(tmp_path / "tune.txt")
+    shapes, cached = plan.autotune(lc.t, lc.y, lc.sigma, lc.df, n_f, cache_path=cache)
+    assert not cached
+    assert all(1 <= v <= 256 for v in shapes.values())
+    assert plan.tuning() == shapes
+    assert ftp.tune_cache_lookup(cache, plan.tune_key()) == shapes
+    out = plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
+    for k in ref:
+        assert torch.equal(ref[k], out[k]), k
+    plan2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_UNIFORM)
+    shapes2, cached2 = plan2.autotune(lc.t, lc.y, lc.sigma, lc.df, n_f, cache_path=cache)
+    assert cached2 and shapes2 == shapes and plan2.tuning() == shapes
+    key = plan.tune_key()
+    assert key.endswith("/H6/p0/s2") and "cu/" in key
