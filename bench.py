@@ -86,6 +86,35 @@ def run_solver(F, plan, t, y, s, lc, out, steps, warmup):
     return ms_step, per
 
 
+KERNEL_OF_STAGE = {"plain_qr": "k_qr", "fallback_qr": "k_qr", "newton_sturm": "k_newton_sturm",
+                   "aberth": "k_aberth", "mlp_forward": "k_gemm_bf16"}
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/<kernel>_<workload>_hbm.txt (FETCH_SIZE and WRITE_SIZE scaled by a
+    256 MiB copy), or None when there is none or the kernel's sources changed
+    since the counters were taken (sha256 over the listed sources)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for src in fields["sources"].split():
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != fields["sources_sha256"]:
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def aberth_flops(H: int) -> float:
     """FP64 work of one Aberth sweep over the D roots of a degree-D real
     polynomial: per root, Horner for f and f' at a complex point (~16 D
@@ -109,7 +138,11 @@ def main():
     ap.add_argument("--solvers", default="plain,learned,uniform,aberth",
                     help="solvers to time (comma separated; plain and the reported solver are always timed)")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default launch shapes instead of tuning them before the timed steps")
+                    help="keep the default launch shapes instead of the tuned ones")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2101_12348_amd", "tuning_cache.txt"),
+                    help="launch-shape cache read (and, on a miss, written) by the autotuner")
+    ap.add_argument("--retune", action="store_true",
+                    help="measure the launch shapes even when the cache has them (and store the result)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy before the bench (reference kernel for "
                          "the HBM byte counters)")
@@ -150,8 +183,8 @@ def main():
         if name == "learned":
             pl.load_mlp(w, meta["width"])
         o = pl.alloc_outputs(lc.n_f, dev)
-        if not args.no_autotune:   # launch shapes tuned on this workload (outside the timed region)
-            pl.autotune(t, y, s, lc.df, lc.n_f)
+        if not args.no_autotune:   # launch shapes for this workload, outside the timed region
+            pl.autotune(t, y, s, lc.df, lc.n_f, cache_path=args.tune_cache, force=args.retune)
         ms, st = run_solver(F, pl, t, y, s, lc, o, args.steps, args.warmup)
         runs[name] = (pl, o, ms, st)
     plan, out, ms_step, st = runs[args.solver]
@@ -220,7 +253,8 @@ def main():
                                f"f_max=10/day, oversample 5, N_f={lc.n_f}, FP32 NFFT sums, FP64 solve",
                    "solver": args.solver, "H": H, "n_obs": int(len(lc.t)), "n_f": int(lc.n_f)},
         "roofline": {"bound": d["bound"], "kernel": kernel_names[dom], "achieved": d["achieved"],
-                     "peak": d["peak"], "unit": d["unit"], "frac": d["frac"], "traffic": None,
+                     "peak": d["peak"], "unit": d["unit"], "frac": d["frac"],
+                     "traffic": measured_traffic(KERNEL_OF_STAGE[dom], "single_long_h6"),
                      "ms_kernel": d["ms"]},
         "stages": stages,
         "solvers": solvers,

@@ -138,10 +138,10 @@ __device__ int sturm_count_line_reg(const double* g, int D, int lane) {
   }
   for (int q = 2; q <= D; ++q) {
     const int da = D - q + 2, db = D - q + 1;
-    const double bl = lrdlane(B, db);
-    const double q1 = lrdlane(A, da) / bl;
+    const double ibl = 1.0 / lrdlane(B, db);
+    const double q1 = lrdlane(A, da) * ibl;
     double t = A - q1 * lane_shr1(B);
-    const double q0 = lrdlane(t, db) / bl;
+    const double q0 = lrdlane(t, db) * ibl;
     t = lane < db ? t - q0 * B : 0.0;
     const double mr = wave_max(fabs(t));
     const double lead = lrdlane(t, db - 1);
