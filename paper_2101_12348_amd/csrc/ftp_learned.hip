@@ -2,19 +2,19 @@
 // real phase polynomial from network seeds, verified by a Sturm count.
 //
 // For each frequency (one wavefront):
-//   * 2H network seeds plus 2H evenly spaced starts (4H evenly spaced
-//     starts for the ablation without network) are refined by FP64 Newton on
-//     R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta
-//     (Eq. theta2cond written as R(theta) = i e^{-i K theta} p(e^{i theta}));
-//   * converged roots closer than 1e-8 rad are merged;
 //   * the number of distinct real roots of R is counted with Sturm sequences
 //     of the Cayley polynomial f(x) (theta = phi0 + 2 atan x): over the whole
 //     real line, or on two half circles, x in (-1, 1] for f and for
 //     x^D f(-1/x) (the map rotated by pi);
-//   * if the Sturm sequence is well determined and the counts agree, the
-//     Newton roots are the candidate set; otherwise the frequency goes to the
-//     Aberth iteration (then, if that does not converge, to the
-//     companion-matrix solve) through device work lists.
+//   * if the count is well determined, 2H network seeds plus 2H evenly spaced
+//     starts (4H evenly spaced starts for the ablation without network) are
+//     refined by FP64 Newton on R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta
+//     (Eq. theta2cond written as R(theta) = i e^{-i K theta} p(e^{i theta}));
+//     converged roots closer than 1e-8 rad are merged after iterations 4-8, 10
+//     and 12, and Newton stops once the merged roots reach the count;
+//   * if they do, the Newton roots are the candidate set; otherwise the
+//     frequency goes to the Aberth iteration (then, if that does not
+//     converge, to the companion-matrix solve) through device work lists.
 // For D + 1 <= 64 a single Sturm sequence of f over the whole real line is
 // formed in registers (sturm_count_line_reg); D = 64 (H = 11) uses the LDS
 // form on the two half circles.
@@ -206,46 +206,10 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
       g2[D - c] = (c & 1) ? -fc : fc;
     }
     lwave_sync();
-    // Newton from 4H starts: lanes < 2H take the network seeds and lanes
-    // 2H..4H-1 evenly spaced phases (with no network, all 4H are evenly spaced)
-    double th = 0.0;
-    bool conv = false;
-    int its = 0;
-    if (lane < NS) {
-      if (L.seeds_out && lane < S) {
-        const float* o = L.seeds_out + w * 2 * S;
-        th = atan2((double)o[2 * lane + 1], (double)o[2 * lane]) - R[RL.meta + M_CANON];
-      } else if (L.seeds_out) {
-        th = kTwoPi * (lane - S + 0.5) / S;
-      } else {
-        th = kTwoPi * (lane + 0.5) / NS;
-      }
-      for (its = 0; its < 12; ++its) {
-        double Rv, dR;
-        eval_R(W, H, th, Rv, dR);
-        if (!(dR != 0.0)) break;
-        double step = Rv / dR;
-        if (!isfinite(step)) break;
-        step = fmax(-0.5, fmin(0.5, step));
-        th -= step;
-        if (fabs(step) < 1e-12) { conv = true; break; }
-      }
-      th = fmod(th, kTwoPi);
-      if (th < 0.0) th += kTwoPi;
-    }
-    iters_acc += (unsigned long long)wave_sum((double)(lane < NS ? its : 0));
-    // merge roots closer than 1e-8 rad (keep the lowest lane)
-    bool uniq = conv;
-    for (int j = 0; j < NS; ++j) {
-      const double tj = lrdlane(th, j);
-      const bool cj = __builtin_amdgcn_readlane((int)conv, j) != 0;
-      double dd = fabs(tj - th);
-      dd = fmin(dd, kTwoPi - dd);
-      if (cj && j < lane && dd < 1e-8) uniq = false;
-    }
-    const unsigned long long um = __ballot(uniq && lane < NS);
-    const int nu = __popcll(um);
-    // Sturm counts on the two half circles
+    // Sturm count first.  An ill-determined count (or fewer than the two
+    // real roots every non-constant P has: its maximum and minimum) sends the
+    // frequency on without Newton; otherwise Newton stops as soon as it has
+    // found that many distinct real roots.
     int cnt = -1;
     if (D < 64) {
       // real roots of f on the whole line = real phases other than phi0 + pi,
@@ -258,12 +222,67 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
         if (c2 >= 0) cnt = c1 + c2;
       }
     }
+    if (cnt < 2) cnt = -1;
+    // Newton from 4H starts: lanes < 2H take the network seeds and lanes
+    // 2H..4H-1 evenly spaced phases (with no network, all 4H are evenly spaced)
+    double thw = 0.0;   // root in [0, 2 pi)
+    bool uniq = false;
+    int nu = -1;
+    unsigned long long um = 0ull;
+    if (cnt >= 0) {
+      double th = 0.0;
+      bool conv = false, live = lane < NS;
+      int its = 0;
+      if (live) {
+        if (L.seeds_out && lane < S) {
+          const float* o = L.seeds_out + w * 2 * S;
+          th = atan2((double)o[2 * lane + 1], (double)o[2 * lane]) - R[RL.meta + M_CANON];
+        } else if (L.seeds_out) {
+          th = kTwoPi * (lane - S + 0.5) / S;
+        } else {
+          th = kTwoPi * (lane + 0.5) / NS;
+        }
+      }
+      for (int it = 1; it <= 12; ++it) {
+        if (live && !conv) {
+          double Rv, dR;
+          eval_R(W, H, th, Rv, dR);
+          const double step = Rv / dR;
+          if (!(dR != 0.0) || !isfinite(step)) {
+            live = false;
+          } else {
+            const double sc = fmax(-0.5, fmin(0.5, step));
+            th -= sc;
+            ++its;
+            if (fabs(sc) < 1e-12) conv = true;
+          }
+        }
+        if ((it >= 4 && it <= 8) || it == 10 || it == 12) {
+          // distinct converged roots: merge those closer than 1e-8 rad,
+          // keeping the lowest lane
+          thw = fmod(th, kTwoPi);
+          if (thw < 0.0) thw += kTwoPi;
+          const unsigned long long cm = __ballot(conv);
+          uniq = conv;
+          for (int jj = 0; jj < NS; ++jj) {
+            const double tj = lrdlane(thw, jj);
+            double dd = fabs(tj - thw);
+            dd = fmin(dd, kTwoPi - dd);
+            if (((cm >> jj) & 1ull) && jj < lane && dd < 1e-8) uniq = false;
+          }
+          um = __ballot(uniq && lane < NS);
+          nu = __popcll(um);
+          if (nu == cnt) break;
+        }
+      }
+      iters_acc += (unsigned long long)wave_sum((double)(lane < NS ? its : 0));
+    }
     if (cnt >= 0 && cnt == nu) {
       const int pos = __popcll(um & ((1ull << lane) - 1ull));
       double* cand = R + RL.cand;
       for (int c = lane; c < D; c += 64) cand[c] = __longlong_as_double(0x7ff8000000000000ll);
       lwave_sync();
-      if (uniq && lane < NS) cand[pos] = th;
+      if (uniq && lane < NS) cand[pos] = thw;
       roots_acc += (unsigned long long)nu;
     } else {
       if (lane == 0) {
