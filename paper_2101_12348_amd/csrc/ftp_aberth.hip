@@ -43,16 +43,6 @@ __host__ __device__ inline size_t aberth_lds_bytes(int H) {
   return (size_t)((D + 2) + 2 * D) * sizeof(double);
 }
 
-// 1/d from the hardware estimate refined by two Newton steps (a few ulp: the
-// iteration needs a correction, not a correctly rounded quotient)
-__device__ __forceinline__ double arcp(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-d, r, 1.0);
-  return fma(r, e, r);
-}
-
 __device__ __forceinline__ void awave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -162,12 +152,12 @@ __global__ __launch_bounds__(64) void k_aberth(AberthArgs A) {
           for (int j = 0; j < D; ++j) {
             const double2 zj = zs[j];
             const double er = zr - zj.x, ei = zi - zj.y;
-            const double inv = j == lane ? 0.0 : arcp(er * er + ei * ei);
+            const double inv = j == lane ? 0.0 : fast_rcp_d(er * er + ei * ei);
             sr += er * inv;
             si -= ei * inv;
           }
           const double br = rr - sr, bi = ri - si;
-          const double inv = arcp(br * br + bi * bi);
+          const double inv = fast_rcp_d(br * br + bi * bi);
           const double cr = br * inv, ci = -bi * inv;   // correction 1 / (f'/f - S)
           if (isfinite(cr) && isfinite(ci)) {
             zr -= cr;

@@ -123,13 +123,17 @@ __device__ int sturm_count_line_reg(const double* g, int D, int lane) {
   const double dv = lane < D ? (lane + 1) * gnext : 0.0;
   const double ma = wave_max(fabs(gv)), mb = wave_max(fabs(dv));
   if (!(ma > 0.0) || !(mb > 0.0)) return -1;
-  double A = gv / ma, B = dv / mb;
+  const double ima = 1.0 / ma, imb = 1.0 / mb;
+  double A = gv * ima, B = dv * imb;
+  // leading coefficients of A and B, carried as scalars from step to step
+  double al = lrdlane(gv, D) * ima;
+  double bl = lrdlane(dv, D - 1) * imb;
   // signs of P_0 and P_1 at +inf (sp) and -inf (sm)
-  int sp = lrdlane(A, D) > 0.0 ? 1 : -1;
+  int sp = al > 0.0 ? 1 : -1;
   int sm = (D & 1) ? -sp : sp;
   int vp = 0, vm = 0;
   {
-    const int tp = lrdlane(B, D - 1) > 0.0 ? 1 : -1;
+    const int tp = bl > 0.0 ? 1 : -1;
     const int tm = ((D - 1) & 1) ? -tp : tp;
     vp += tp != sp;
     vm += tm != sm;
@@ -137,9 +141,9 @@ __device__ int sturm_count_line_reg(const double* g, int D, int lane) {
     sm = tm;
   }
   for (int q = 2; q <= D; ++q) {
-    const int da = D - q + 2, db = D - q + 1;
-    const double ibl = 1.0 / lrdlane(B, db);
-    const double q1 = lrdlane(A, da) * ibl;
+    const int db = D - q + 1;
+    const double ibl = fast_rcp_d(bl);
+    const double q1 = al * ibl;
     double t = A - q1 * lane_shr1(B);
     const double q0 = lrdlane(t, db) * ibl;
     t = lane < db ? t - q0 * B : 0.0;
@@ -153,8 +157,11 @@ __device__ int sturm_count_line_reg(const double* g, int D, int lane) {
     vm += tm != sm;
     sp = tp;
     sm = tm;
+    const double inv = -fast_rcp_d(mr);
     A = B;
-    B = t * (-1.0 / mr);
+    al = bl;
+    B = t * inv;
+    bl = lead * inv;
   }
   return vm - vp;
 }

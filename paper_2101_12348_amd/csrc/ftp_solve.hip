@@ -41,15 +41,8 @@ __device__ __forceinline__ double rdlane(double v, int src) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// 1/d and 1/sqrt(s) from the hardware estimates refined by two Newton steps
-// (a few ulp; the Householder step is backward stable to that level).
-__device__ __forceinline__ double fast_rcp(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-d, r, 1.0);
-  return fma(r, e, r);
-}
+// 1/sqrt(s) from the hardware estimate refined by two Newton steps (a few
+// ulp; the Householder step is backward stable to that level).
 __device__ __forceinline__ double fast_rsq(double s) {
   double y = __builtin_amdgcn_rsq(s);
   const double h = 0.5 * s;
@@ -143,7 +136,7 @@ __device__ __forceinline__ int hqr_wave(double* A, double* wr, double* wi, const
         const double alpha = -copysign(nrm, x);
         const double ax = fabs(x);
         const double tau = 1.0 + ax * inv;                         // (alpha - x) / alpha
-        const double rv = copysign(fast_rcp(ax + nrm), x);        // 1 / (x - alpha)
+        const double rv = copysign(fast_rcp_d(ax + nrm), x);        // 1 / (x - alpha)
         const double v1 = y * rv, v2 = z * rv;
         // row update: rows k..k+2, columns k..m (lane = column); the bulge
         // column k-1 becomes (alpha, 0, 0)

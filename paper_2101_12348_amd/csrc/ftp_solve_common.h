@@ -256,6 +256,15 @@ __device__ __forceinline__ double lane_shl1(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// 1/d from the hardware estimate refined by two Newton steps (a few ulp).
+__device__ __forceinline__ double fast_rcp_d(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Work distribution of the persistent root kernels: wavefront b starts on
 // item b; with a queue counter (zeroed before the launch) it then takes item
 // gridDim.x + ticket when it is done, lane 0 taking the ticket with a vector
