@@ -84,10 +84,17 @@ __global__ __launch_bounds__(64) void k_aberth(AberthArgs A) {
     double rho = pow(fabs(f0 / fD), 1.0 / D);
     if (!(rho > 1e-8 && rho < 1e8)) rho = 1.0;
     const bool act = lane < D;
+    // starting points: the real roots a Newton tier already found
+    // (x = tan((theta - phi0) / 2)), the others on a circle of radius rho
+    const int nw = A.list ? (int)R[RL.meta + M_WARM] : 0;
+    const double phi0s = R[RL.meta + M_PHI0];
     double zr = 0.0, zi = 0.0;
-    if (act) {
+    if (act && lane < nw) {
+      zr = tan(0.5 * (R[RL.cand + lane] - phi0s));
+      if (!isfinite(zr)) zr = 1e8;
+    } else if (act) {
       double sn, cs;
-      sincos(kTwoPi * (lane + 0.25) / D, &sn, &cs);
+      sincos(kTwoPi * (lane - nw + 0.25) / (D - nw), &sn, &cs);
       zr = rho * cs;
       zi = rho * sn;
     }

@@ -292,10 +292,14 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
       if (uniq && lane < NS) cand[pos] = thw;
       roots_acc += (unsigned long long)nu;
     } else {
+      // the distinct roots Newton did find start the Aberth iteration
+      const int nw = nu > 0 ? nu : 0;
+      if (nw > 0 && uniq && lane < NS) R[RL.cand + __popcll(um & ((1ull << lane) - 1ull))] = thw;
       if (lane == 0) {
+        R[RL.meta + M_WARM] = (double)nw;
+        R[RL.meta + M_FALLBACK] = 1.0;
         const unsigned slot = atomicAdd(L.fb_count, 1u);
         L.fb_list[slot] = w;
-        R[RL.meta + M_FALLBACK] = 1.0;
       }
       ++fb_acc;
     }

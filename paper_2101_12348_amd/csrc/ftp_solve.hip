@@ -356,6 +356,7 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
         Rr[RL.meta + M_STATUS] = (double)ST_BAD_LC;
         Rr[RL.meta + M_LC] = (double)lc;
         Rr[RL.meta + M_FALLBACK] = 0.0;
+        Rr[RL.meta + M_WARM] = 0.0;
       }
       continue;
     }
@@ -444,6 +445,7 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
       Rr[RL.meta + M_STATUS] = constant ? (double)ST_CONSTANT : (double)ST_OK;
       Rr[RL.meta + M_LC] = (double)lc;
       Rr[RL.meta + M_FALLBACK] = 0.0;
+      Rr[RL.meta + M_WARM] = 0.0;
     }
     wave_sync();
   }

@@ -69,7 +69,8 @@ enum : int {
   M_REAL_LO = 5,   // bit mask of real companion eigenvalues (low / high 32 lanes)
   M_REAL_HI = 6,
   M_FALLBACK = 7,  // 0: first method; 1: Aberth tier; 2: companion solve after Aberth
-  M_SLOTS = 8,
+  M_WARM = 8,      // Newton roots left in the candidate slots for the Aberth tier
+  M_SLOTS = 9,
 };
 struct RecLayout {
   int K, D, r, mu, eta, zw, meta, f, cand, stride;
