@@ -115,7 +115,7 @@ typedef struct {
 } ftp_stats;
 
 /* Launch shapes of the per-frequency kernels, in wavefronts per compute
- * unit (1..256).  They change timing only: every frequency is computed by one
+ * unit (1..256), and the implementation of the network's forward pass.  They change timing only: every frequency is computed by one
  * wavefront whatever the grid, so results are identical for every setting.
  * The companion-QR and Aberth kernels, whose work per frequency varies with
  * their iteration counts, take frequencies from a work queue; assembly,
@@ -126,6 +126,9 @@ typedef struct {
   int aberth_wpc;       /* Aberth */
   int qr_wpc;           /* companion QR */
   int score_wpc;        /* scoring */
+  int mlp_fused;        /* learned: 1 = one kernel for the four network layers (LDS-staged
+                           weights, activations kept per wavefront), 0 = four GEMM
+                           launches; identical results */
 } ftp_tuning;
 
 #define FTP_TUNE_FORCE 1u   /* ftp_autotune: measure even if the cache holds an entry */
@@ -247,18 +250,20 @@ int ftp_learned_dataset(ftp_plan* plan, const double* t, const double* y, const 
 /* Current launch shapes of the plan (defaults until set or tuned). */
 int ftp_plan_get_tuning(const ftp_plan* plan, ftp_tuning* out);
 
-/* Set the launch shapes.  FTP_E_OPTION if a field is outside 1..256. */
+/* Set the launch shapes.  FTP_E_OPTION if a shape is outside 1..256 or
+ * mlp_fused is not 0 or 1. */
 int ftp_plan_set_tuning(ftp_plan* plan, const ftp_tuning* tuning);
 
 /*
  * Autotuner of the launch shapes (the schedule of the ragged-batch path): on
  * the given lightcurve (same arguments as ftp_periodogram; device arrays),
  * each shape that matters for the plan's solver is swept over 4..64 waves per
- * compute unit, one at a time, keeping the fastest whole periodogram call
+ * compute unit (and, for the learned solver, both network implementations),
+ * one at a time, keeping the fastest whole periodogram call
  * (best of two, HIP events on `stream`).  The result is applied to the plan
  * and written to *out.
- * cache_path (nullable): a text file of "key assemble newton aberth qr score"
- * lines; the key (ftp_plan_tune_key) names the device, its compute units, H,
+ * cache_path (nullable): a text file of "key assemble newton aberth qr score
+ * mlp_fused" lines; the key (ftp_plan_tune_key) names the device, its compute units, H,
  * precision and solver.  An entry found there is applied without measuring
  * (unless flags has FTP_TUNE_FORCE); a measured result is stored there.
  * Returns 1 when the cache supplied the shapes, 0 when they were measured, or
@@ -277,7 +282,8 @@ int ftp_plan_tune_key(const ftp_plan* plan, char* buf, int len);
  * filled when `key` has a well-formed entry, 0 when it has none (or the file
  * does not exist); store: replaces or appends the entry, rewriting the file
  * through a temporary and a rename.  Errors: FTP_E_NULL, FTP_E_OPTION (empty
- * key, white space in it, or a field outside 1..256), FTP_E_IO. */
+ * key, white space in it, a shape outside 1..256 or mlp_fused not 0 / 1),
+ * FTP_E_IO. */
 int ftp_tune_cache_lookup(const char* path, const char* key, ftp_tuning* out);
 int ftp_tune_cache_store(const char* path, const char* key, const ftp_tuning* tuning);
 

@@ -56,7 +56,7 @@ class Stats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """Launch shapes of the per-frequency kernels (waves per compute unit)."""
     _fields_ = [("assemble_wpc", ctypes.c_int), ("newton_wpc", ctypes.c_int), ("aberth_wpc", ctypes.c_int),
-                ("qr_wpc", ctypes.c_int), ("score_wpc", ctypes.c_int)]
+                ("qr_wpc", ctypes.c_int), ("score_wpc", ctypes.c_int), ("mlp_fused", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

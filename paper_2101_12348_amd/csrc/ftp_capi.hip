@@ -93,6 +93,17 @@ struct AberthArgs {
   unsigned* queue;
 };
 hipError_t launch_aberth(const AberthArgs& A, int waves, hipStream_t st);
+struct FusedMlpArgs {
+  const uint16_t* X;
+  int64_t np;
+  const uint16_t* wb;
+  const float* w32;
+  int64_t oW[4], ob[4];
+  int nin[4], nout[4];
+  float* out;
+};
+bool mlp_fused_ok(const int* nin, const int* nout);
+hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st);
 hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st);
 }  // namespace ftp
 
@@ -318,7 +329,7 @@ struct ftp_plan {
   DevBuf xfeat, seeds, fb_list, fb2_list, work_ctr;
   // launch shapes (waves per compute unit), set by ftp_plan_set_tuning or
   // ftp_autotune
-  ftp_tuning tune{32, 32, 16, 16, 32};
+  ftp_tuning tune{32, 32, 16, 16, 32, 0};
   DevBuf tune_out;
 };
 
@@ -583,6 +594,11 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
     }
   }
   const ftp_tuning& T = P->tune;
+  // learned solver with a fusable network: features in rows of dinp bf16
+  // (zero padded), then one kernel for the four layers
+  const bool fused = solver == FTP_SOLVER_LEARNED && P->tune.mlp_fused && mlp_fused_ok(P->net.nin, P->net.nout);
+  const int dinp = (P->net.din + 31) & ~31;
+  if (fused && (rc = P->xfeat.ensure(sizeof(uint16_t) * chunk * dinp))) return rc;
   for (int64_t p0 = 0; p0 < n_pairs; p0 += chunk) {
     const int64_t np = std::min<int64_t>(chunk, n_pairs - p0);
     const int w_asm = (int)grid_waves(P, T.assemble_wpc, np);
@@ -600,8 +616,26 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
     } else {
       const float* seeds = nullptr;
       if (solver == FTP_SOLVER_LEARNED) {
-        HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), P->net.din, w_asm, st));
-        if ((rc = mlp_forward(&P->net, P->xfeat.as<uint16_t>(), np, P->seeds.as<float>(), st))) return rc;
+        MlpNet& N = P->net;
+        if (fused) {
+          HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), dinp, w_asm, st));
+          FusedMlpArgs fa{};
+          fa.X = P->xfeat.as<uint16_t>();
+          fa.np = np;
+          fa.wb = N.wbf.as<uint16_t>();
+          fa.w32 = N.w32.as<float>();
+          for (int l = 0; l < 4; ++l) {
+            fa.oW[l] = N.oW[l];
+            fa.ob[l] = N.ob[l];
+            fa.nin[l] = N.nin[l];
+            fa.nout[l] = N.nout[l];
+          }
+          fa.out = P->seeds.as<float>();
+          HIP_TRY(launch_mlp_fused(fa, st));
+        } else {
+          HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), N.din, w_asm, st));
+          if ((rc = mlp_forward(&N, P->xfeat.as<uint16_t>(), np, P->seeds.as<float>(), st))) return rc;
+        }
         seeds = P->seeds.as<float>();
       }
       hipEvent_t ra = next_learn_event(P);
@@ -742,7 +776,7 @@ bool tuning_valid(const ftp_tuning& t) {
   const int v[5] = {t.assemble_wpc, t.newton_wpc, t.aberth_wpc, t.qr_wpc, t.score_wpc};
   for (int x : v)
     if (x < 1 || x > 256) return false;
-  return true;
+  return t.mlp_fused == 0 || t.mlp_fused == 1;
 }
 
 bool key_valid(const char* key) {
@@ -1129,7 +1163,7 @@ int ftp_tune_cache_lookup(const char* path, const char* key, ftp_tuning* out) {
     std::string k;
     ftp_tuning t{};
     if (!(ls >> k) || k != key) continue;
-    if (!(ls >> t.assemble_wpc >> t.newton_wpc >> t.aberth_wpc >> t.qr_wpc >> t.score_wpc)) continue;
+    if (!(ls >> t.assemble_wpc >> t.newton_wpc >> t.aberth_wpc >> t.qr_wpc >> t.score_wpc >> t.mlp_fused)) continue;
     if (!tuning_valid(t)) continue;
     *out = t;
     found = 1;   // the last well-formed entry wins
@@ -1152,8 +1186,8 @@ int ftp_tune_cache_store(const char* path, const char* key, const ftp_tuning* t)
     }
   }
   char entry[512];
-  std::snprintf(entry, sizeof(entry), "%s %d %d %d %d %d", key, t->assemble_wpc, t->newton_wpc, t->aberth_wpc,
-                t->qr_wpc, t->score_wpc);
+  std::snprintf(entry, sizeof(entry), "%s %d %d %d %d %d %d", key, t->assemble_wpc, t->newton_wpc, t->aberth_wpc,
+                t->qr_wpc, t->score_wpc, t->mlp_fused);
   keep.push_back(entry);
   const std::string tmp = std::string(path) + ".tmp";
   {
@@ -1197,7 +1231,7 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
   float ms = 0.f;
   // the knobs that matter for the solver; the QR knob also for the others
   // (it then only serves the companion fallback, but is cheap to sweep)
-  int* knobs[5];
+  int* knobs[6];
   int nk = 0;
   if (P->opt.solver == FTP_SOLVER_PLAIN) {
     knobs[nk++] = &cur.qr_wpc;
@@ -1207,7 +1241,10 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
   }
   knobs[nk++] = &cur.assemble_wpc;
   knobs[nk++] = &cur.score_wpc;
+  const bool tune_mlp = P->opt.solver == FTP_SOLVER_LEARNED && mlp_fused_ok(P->net.nin, P->net.nout);
+  if (tune_mlp) knobs[nk++] = &cur.mlp_fused;
   const int cand[] = {4, 8, 12, 16, 24, 32, 48, 64};
+  const int cand01[] = {0, 1};
   auto measure = [&](float* best) -> int {
     P->tune = cur;
     float m0 = 0.f, m1 = 0.f;
@@ -1223,7 +1260,11 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
     int best_v = *knobs[k];
     float best_ms = 0.f;
     if ((rc = measure(&best_ms))) break;
-    for (int v : cand) {
+    const bool binary = knobs[k] == &cur.mlp_fused;
+    const int* cv = binary ? cand01 : cand;
+    const int ncv = binary ? 2 : 8;
+    for (int ci = 0; ci < ncv; ++ci) {
+      const int v = cv[ci];
       if (v == best_v) continue;
       const int keep = *knobs[k];
       *knobs[k] = v;

@@ -16,21 +16,6 @@ namespace ftp {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 
-// float -> bfloat16 bits, round to nearest even (finite inputs)
-__host__ __device__ inline uint16_t f2bf(float x) {
-  unsigned u;
-  memcpy(&u, &x, 4);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__host__ __device__ inline float bf2f(uint16_t b) {
-  unsigned u = (unsigned)b << 16;
-  float x;
-  memcpy(&x, &u, 4);
-  return x;
-}
-
 // ------------------------------------------------------------------ GEMM
 
 // C[m, n] = sum_k A[m, k] B[k, n] with A, B in bf16 at arbitrary strides and
@@ -56,8 +41,8 @@ constexpr int kGP = 40;   // padded LDS row (bf16 elements)
 // l): A rows l % 16 with k = 8 (l / 16) .. + 7; B columns l % 16, same k; result
 // rows 4 (l / 16) + v, column l % 16 (v = 0..3).
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-  __shared__ uint16_t As[kGT * kGP];
-  __shared__ uint16_t Bs[kGT * kGP];
+  __shared__ __align__(16) uint16_t As[kGT * kGP];
+  __shared__ __align__(16) uint16_t Bs[kGT * kGP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t m0 = (int64_t)blockIdx.x * kGT;
   const int n0 = blockIdx.y * kGT;
@@ -217,50 +202,135 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(const float* x, uint16_t* y
   if (i < n) y[i] = f2bf(x[i]);
 }
 
-// Network features of pairs [0, np) of a record chunk: canonical rotation
-// (stored in the record) and normalised coefficients of p as bf16.
+// Network features of pairs [0, np) of a record chunk (one wavefront per
+// pair), written to X (row stride ldx >= 2 (D + 1), the rest of the row
+// zeroed); the canonical rotation goes to the record for the Newton kernel.
 __global__ __launch_bounds__(64) void k_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx) {
   const RecLayout RL(H);
-  const int K = RL.K, D = RL.D;
+  const int D = RL.D;
   const int lane = threadIdx.x & 63;
   for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
     double* R = rec + w * (int64_t)RL.stride;
     const int st = (int)R[RL.meta + M_STATUS];
     uint16_t* x = X + w * ldx;
+    for (int q = 2 * (D + 1) + lane; q < ldx; q += 64) x[q] = 0;
     if (st == ST_BAD_LC || st == ST_CONSTANT) {
       for (int q = lane; q < 2 * (D + 1); q += 64) x[q] = 0;
       continue;
     }
-    const double2 r1 = make_double2(R[RL.r + 2], R[RL.r + 3]);
-    const double canon = (r1.x == 0.0 && r1.y == 0.0) ? 0.0 : atan2(r1.y, r1.x);
-    // p_{K+d} = -i r'_d with r'_d = r_d e^{-i d canon}, r'_{-d} = conj(r'_d)
-    double re = 0.0, im = 0.0, amax = 0.0;
-    for (int k = lane; k <= D; k += 64) {
-      const int d = k - K;
-      const int ad = d < 0 ? -d : d;
-      double2 rd = make_double2(R[RL.r + 2 * ad], R[RL.r + 2 * ad + 1]);
-      double sn, cs;
-      sincos(-(double)ad * canon, &sn, &cs);
-      rd = cmul(rd, make_double2(cs, sn));
-      if (d < 0) rd = cconj(rd);
-      re = rd.y;      // -i (a + i b) = b - i a
-      im = -rd.x;
-      amax = fmax(amax, sqrt(re * re + im * im));
-    }
-    amax = wave_max(amax);
-    const double sc = amax > 0.0 ? 1.0 / amax : 0.0;
-    for (int k = lane; k <= D; k += 64) {
-      const int d = k - K;
-      const int ad = d < 0 ? -d : d;
-      double2 rd = make_double2(R[RL.r + 2 * ad], R[RL.r + 2 * ad + 1]);
-      double sn, cs;
-      sincos(-(double)ad * canon, &sn, &cs);
-      rd = cmul(rd, make_double2(cs, sn));
-      if (d < 0) rd = cconj(rd);
-      x[2 * k] = f2bf((float)(rd.y * sc));
-      x[2 * k + 1] = f2bf((float)(-rd.x * sc));
-    }
+    const double canon = pair_features(reinterpret_cast<const double2*>(R + RL.r), RL.K, lane, x);
     if (lane == 0) R[RL.meta + M_CANON] = canon;
+  }
+}
+
+// ------------------------------------------------------- fused inference
+
+// The four layers of the network for 64 pairs per workgroup:
+// wave w owns pairs 16 w .. 16 w + 15 of the workgroup's tile and keeps their
+// activations in its own LDS rows (the output of a layer becomes the A operand
+// of the next); the weights of each 32-wide K step are staged once per
+// workgroup in LDS (double-buffered) and shared by the four waves.  Each wave
+// computes all N tiles of its 16 rows with v_mfma_f32_16x16x32_bf16 (FP32
+// accumulation); bias and ReLU are applied in the epilogue, which rounds the
+// hidden activations to bf16 (the same rounding points as k_gemm_bf16).
+// Requirements (checked on the host): width a multiple of 32 up to 256,
+// d_in and d_out up to 256.
+struct FusedMlpArgs {
+  const uint16_t* X;     // np x dinp bf16 features (dinp = d_in rounded up to 32)
+  int64_t np;
+  const uint16_t* wb;    // bf16 weights, layer l at wb + oW[l], (out, in) row-major
+  const float* w32;      // FP32 parameters (biases at w32 + ob[l])
+  int64_t oW[4], ob[4];
+  int nin[4], nout[4];
+  float* out;            // np x nout[3]
+};
+
+constexpr int kFRows = 64;           // pairs per workgroup
+constexpr int kActLd = 256 + 8;      // LDS row of one pair's activations (bf16)
+constexpr int kWLd = 32 + 8;         // LDS row of one output unit's K slice (bf16)
+constexpr int kWMaxN = 256;
+
+__global__ __launch_bounds__(256) void k_mlp_fused(FusedMlpArgs a) {
+  __shared__ __align__(16) uint16_t act[kFRows * kActLd];
+  __shared__ __align__(16) uint16_t wst[2][kWMaxN * kWLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * kFRows;
+  uint16_t* myact = act + wave * 16 * kActLd;
+  // features of this wave's 16 pairs (rows of X, stride dinp, zero padded;
+  // zero rows past the end)
+  const int din = a.nin[0];
+  const int dinp = (din + 31) & ~31;
+  for (int q = lane; q < 16 * (dinp / 8); q += 64) {
+    const int i = q / (dinp / 8), c = (q % (dinp / 8)) * 8;
+    const int64_t w = row0 + wave * 16 + i;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (w < a.np) v = *reinterpret_cast<const uint4*>(a.X + w * dinp + c);
+    *reinterpret_cast<uint4*>(myact + i * kActLd + c) = v;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int mrow = lane & 15, kq = 8 * (lane >> 4);
+  for (int l = 0; l < 4; ++l) {
+    const int nin = a.nin[l], nout = a.nout[l];
+    const int K = l == 0 ? dinp : nin;
+    const int nt = (nout + 15) >> 4;
+    const uint16_t* W = a.wb + a.oW[l];
+    f32x4_t acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    // stage the K slice [k0, k0 + 32) of rows n < 16 nt into buffer b
+    auto stage = [&](int b, int k0) {
+      for (int c = tid; c < nt * 16 * 4; c += 256) {
+        const int n = c >> 2, kk = (c & 3) * 8;
+        uint16_t* dst = &wst[b][n * kWLd + kk];
+        const int64_t off = (int64_t)n * nin + k0 + kk;
+        if (n < nout && k0 + kk + 8 <= nin && ((a.oW[l] + off) & 7) == 0) {
+          *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(W + off);
+        } else {
+          for (int e = 0; e < 8; ++e)
+            dst[e] = (n < nout && k0 + kk + e < nin) ? W[off + e] : (uint16_t)0;
+        }
+      }
+    };
+    stage(0, 0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      if (k0 + 32 < K) stage(buf ^ 1, k0 + 32);
+      bf16x8_t af;
+      memcpy(&af, myact + mrow * kActLd + k0 + kq, 16);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (j < nt) {
+          bf16x8_t bfv;
+          memcpy(&bfv, &wst[buf][(16 * j + mrow) * kWLd + kq], 16);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfv, acc[j], 0, 0, 0);
+        }
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
+    // epilogue: rows 4 (lane / 16) + v, column 16 j + lane % 16
+    const float* bias = a.w32 + a.ob[l];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j >= nt) continue;
+      const int n = 16 * j + mrow;
+      if (n >= nout) continue;
+      const float bn = bias[n];
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * (lane >> 4) + v;
+        float xv = acc[j][v] + bn;
+        if (l < 3) {
+          myact[r * kActLd + n] = f2bf(fmaxf(xv, 0.f));
+        } else {
+          const int64_t w = row0 + wave * 16 + r;
+          if (w < a.np) a.out[w * nout + n] = xv;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -320,6 +390,20 @@ hipError_t launch_adam(float* w, uint16_t* wb, const float* g, float* m, float* 
 
 hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, n);
+  return hipGetLastError();
+}
+
+bool mlp_fused_ok(const int* nin, const int* nout) {
+  if (nin[0] > 256 || nout[3] < 1 || nout[3] > 256) return false;
+  for (int l = 0; l < 3; ++l)
+    if (nout[l] % 32 != 0 || nout[l] > 256) return false;
+  return nin[1] == nout[0] && nin[2] == nout[1] && nin[3] == nout[2];
+}
+
+hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st) {
+  if (fa.np <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((fa.np + kFRows - 1) / kFRows);
+  hipLaunchKernelGGL(k_mlp_fused, dim3(blocks), dim3(256), 0, st, fa);
   return hipGetLastError();
 }
 

@@ -11,9 +11,7 @@ struct SolveArgs {
   const LcInfo* lcs;
   int64_t n_lc;
   const int64_t* freq_off;       // device, n_lc + 1 (prefix of n_f)
-  int64_t total;                 // number of work entries (pairs or list capacity)
-  const int64_t* list;           // optional pair indices (nullptr: identity)
-  const unsigned int* list_count;  // optional device count for list
+  int64_t total;                 // number of pairs
   const void* grids;             // float2 or double2 grids
   const double* sums_in;         // optional: per pair 3H complex sums (see gather)
   const double2* alpha;          // template alpha_n, n = 1..H
@@ -26,12 +24,6 @@ struct SolveArgs {
   double* offset;
   uint8_t* status;
   SolveCounters* counters;
-  // learned path
-  const float* seeds;            // per pair 2H seed angles (nullptr for plain)
-  int64_t* fallback_list;
-  unsigned int* fallback_count;
-  double* poly_out;              // per pair K+1 complex r_d (learned assemble)
-  uint16_t* feat_out;            // per pair bf16 features
 };
 
 constexpr double kEps = 2.220446049250313e-16;
@@ -264,6 +256,65 @@ __device__ __forceinline__ double fast_rcp_d(double d) {
   r = fma(r, e, r);
   e = fma(-d, r, 1.0);
   return fma(r, e, r);
+}
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__host__ __device__ inline uint16_t f2bf(float x) {
+  unsigned u;
+  memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(uint16_t b) {
+  unsigned u = (unsigned)b << 16;
+  float x;
+  memcpy(&x, &u, 4);
+  return x;
+}
+
+// Network features of one pair (all 64 lanes; r: the K + 1 coefficients r_d
+// of R, in LDS or global memory): the coefficients p_k,
+// k = 0..D, of the phase polynomial rotated to the canonical phase (r_1 real
+// and positive) and scaled to max |p_k| = 1, as (Re, Im) bf16 pairs written
+// to x[2k], x[2k + 1].  p_{K+d} = -i r'_d with r'_d = r_d u^d, r'_{-d} =
+// conj(r'_d) and u = e^{-i canon} = conj(r_1) / |r_1|, u^|d| by repeated
+// squaring.  Returns canon = arg r_1 (0 when r_1 = 0).
+__device__ __forceinline__ double pair_features(const double2* r, int K, int lane, uint16_t* x) {
+  const int D = 2 * K;
+  const double2 r1 = r[1];
+  const double m1 = sqrt(r1.x * r1.x + r1.y * r1.y);
+  const double canon = m1 > 0.0 ? atan2(r1.y, r1.x) : 0.0;
+  const double2 u = m1 > 0.0 ? make_double2(r1.x / m1, -r1.y / m1) : make_double2(1.0, 0.0);
+  double2 v[2];
+  double amax = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    const int k = lane + 64 * s;
+    v[s] = make_double2(0.0, 0.0);
+    if (k > D) continue;
+    const int d = k - K;
+    int ad = d < 0 ? -d : d;
+    double2 rd = r[ad];
+    double2 pw = make_double2(1.0, 0.0), b = u;
+    while (ad) {
+      if (ad & 1) pw = cmul(pw, b);
+      b = cmul(b, b);
+      ad >>= 1;
+    }
+    rd = cmul(rd, pw);
+    if (d < 0) rd = cconj(rd);
+    v[s] = make_double2(rd.y, -rd.x);   // -i (a + i b) = b - i a
+    amax = fmax(amax, sqrt(v[s].x * v[s].x + v[s].y * v[s].y));
+  }
+  amax = wave_max(amax);
+  const double sc = amax > 0.0 ? 1.0 / amax : 0.0;
+  for (int s = 0; s < 2; ++s) {
+    const int k = lane + 64 * s;
+    if (k > D) continue;
+    x[2 * k] = f2bf((float)(v[s].x * sc));
+    x[2 * k + 1] = f2bf((float)(v[s].y * sc));
+  }
+  return canon;
 }
 
 // Work distribution of the persistent root kernels: wavefront b starts on

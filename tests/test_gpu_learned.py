@@ -161,3 +161,32 @@ def test_learned_requires_a_network(ftp):
     p = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED)
     with pytest.raises(ftp.FtpError):
         p.periodogram(lc.t, lc.y, lc.sigma, lc.df, lc.n_f)
+
+
+@pytest.mark.parametrize("width", [256, 64, 48])
+def test_fused_network_kernel_equals_unfused(ftp, width):
+    """The fused features + four-layer kernel reproduces the separate features
+    kernel and GEMM launches bit for bit (same bf16 rounding points, same
+    K order of the MFMA accumulation); width 48 is not fused (not a multiple
+    of 32) and takes the separate kernels either way."""
+    import torch
+    tmpl, lc = single_long_case(n_obs=3000)
+    n_f = 8000
+    din, dout = 2 * (6 * tmpl.H - 1), 4 * tmpl.H
+    if width == 256:
+        w, meta = ftp.load_model("single_long_h6")
+    else:
+        w = np.random.default_rng(width).uniform(-0.2, 0.2, ftp.mlp_param_count(din, width, dout)).astype(np.float32)
+    res = []
+    for fused in (1, 0):
+        p = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED)
+        p.set_tuning(mlp_fused=fused)
+        p.load_mlp(w, width)
+        p.stats()
+        out = {k: v.clone() for k, v in p.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
+        res.append((out, p.stats()))
+    (a, sa), (b, sb) = res
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    for k in ("n_fallback", "newton_iters", "roots_found"):
+        assert sa[k] == sb[k], k

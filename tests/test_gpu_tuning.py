@@ -44,6 +44,8 @@ def test_set_tuning_rejects_bad_shapes(ftp):
     for bad in (0, 257, -3):
         with pytest.raises(ftp.FtpError):
             plan.set_tuning(qr_wpc=bad)
+    with pytest.raises(ftp.FtpError):
+        plan.set_tuning(mlp_fused=2)
     assert plan.tuning() == before
 
 
@@ -56,7 +58,7 @@ def test_autotune_and_cache(ftp, tmp_path):
     cache = str(tmp_path / "tune.txt")
     shapes, cached = plan.autotune(lc.t, lc.y, lc.sigma, lc.df, n_f, cache_path=cache)
     assert not cached
-    assert all(1 <= v <= 256 for v in shapes.values())
+    assert all(1 <= v <= 256 for k, v in shapes.items() if k != "mlp_fused") and shapes["mlp_fused"] in (0, 1)
     assert plan.tuning() == shapes
     assert ftp.tune_cache_lookup(cache, plan.tune_key()) == shapes
     out = plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
