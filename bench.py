@@ -127,6 +127,94 @@ def mlp_flops(d_in, width, d_out):
     return 2.0 * (d_in * width + 2 * width * width + width * d_out)
 
 
+def _time_calls(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_ragged(args):
+    """The ragged batch (4096 lightcurves, H = 4, ~1.6e8 pairs) through
+    ftp_periodogram_batch for the solvers that need no network (the bundled
+    network is trained for the H = 6 template); sampled members checked
+    against the oracle."""
+    import numpy as np
+    import torch
+    import paper_2101_12348_amd as F
+    from synthetic import ragged_batch_case
+    batch = ragged_batch_case()
+    lcs = batch.lcs
+    dev = torch.device("cuda:0")
+    obs_off = np.concatenate([[0], np.cumsum([len(lc.t) for lc in lcs])]).astype(np.int64)
+    freq_off = np.concatenate([[0], np.cumsum([lc.n_f for lc in lcs])]).astype(np.int64)
+    t = torch.as_tensor(np.concatenate([lc.t for lc in lcs]), device=dev)
+    y = torch.as_tensor(np.concatenate([lc.y for lc in lcs]), device=dev)
+    s = torch.as_tensor(np.concatenate([lc.sigma for lc in lcs]), device=dev)
+    df = np.array([lc.df for lc in lcs])
+    pairs = int(freq_off[-1])
+    big = max(range(len(lcs)), key=lambda i: lcs[i].n_f)
+    res = {}
+    for name, sv in (("uniform", F.FTP_SOLVER_UNIFORM), ("aberth", F.FTP_SOLVER_ABERTH), ("plain", F.FTP_SOLVER_PLAIN)):
+        pl = F.Plan(batch.template.c, batch.template.s, solver=sv)
+        if not args.no_autotune:
+            lb = lcs[big]
+            pl.autotune(lb.t, lb.y, lb.sigma, lb.df, lb.n_f, cache_path=args.tune_cache, force=args.retune)
+        out = pl.alloc_outputs(pairs, dev)
+        ms = _time_calls(lambda: pl.periodogram_batch(obs_off, t, y, s, df, freq_off, out=out),
+                         max(1, min(args.steps, 3)), 1)
+        P = out["power"].cpu().numpy()
+        rng = np.random.default_rng(7)
+        dmax = 0.0
+        if not args.no_cpu_baseline:
+            from oracle import ftp_oracle as O
+            for b in rng.choice(len(lcs), 8, replace=False):
+                lc = lcs[b]
+                js = np.unique(rng.integers(1, lc.n_f + 1, 6))
+                ref = O.periodogram(lc.t, lc.y, lc.sigma, batch.template.c, batch.template.s, lc.df, freq_index=js)
+                dmax = max(dmax, float(np.max(np.abs(P[freq_off[b] + js - 1] - ref["power"]))))
+        res[name] = {"value": pairs / (ms * 1e-3), "ms_per_call": ms, "max_abs_dP_sampled": dmax,
+                     "launch_shapes": pl.tuning()}
+        pl.close()
+    print(json.dumps({"workload": "ragged batch: 4096 lightcurves, N_obs log-U[50, 5000], T U(30, 1500) d, H=4",
+                      "pairs": pairs, "unit": "pairs/s", "solvers": res}))
+
+
+def bench_h_sweep(args):
+    """H = 1..11 at N_f ~ 5e4 (one single-long-like lightcurve per H): time
+    per periodogram for the plain, uniform-start and Aberth solvers."""
+    import torch
+    import paper_2101_12348_amd as F
+    from synthetic import h_sweep_case
+    dev = torch.device("cuda:0")
+    rows = []
+    for H in range(1, F.MAX_H + 1):
+        tmpl, lc = h_sweep_case(H)
+        t = torch.as_tensor(lc.t, device=dev)
+        y = torch.as_tensor(lc.y, device=dev)
+        s = torch.as_tensor(lc.sigma, device=dev)
+        row = {"H": H, "D": 6 * H - 2, "n_f": int(lc.n_f)}
+        for name, sv in (("plain", F.FTP_SOLVER_PLAIN), ("uniform", F.FTP_SOLVER_UNIFORM),
+                         ("aberth", F.FTP_SOLVER_ABERTH)):
+            pl = F.Plan(tmpl.c, tmpl.s, solver=sv)
+            out = pl.alloc_outputs(lc.n_f, dev)
+            ms = _time_calls(lambda: pl.periodogram(t, y, s, lc.df, lc.n_f, out=out), 5, 2)
+            row[name] = {"ms": ms, "pairs_per_s": lc.n_f / (ms * 1e-3)}
+            pl.close()
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "H sweep: N_obs=1e4, T=1000 d, f_max=10/day, sawtooth-like templates",
+                      "rows": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +231,9 @@ def main():
                     help="launch-shape cache read (and, on a miss, written) by the autotuner")
     ap.add_argument("--retune", action="store_true",
                     help="measure the launch shapes even when the cache has them (and store the result)")
+    ap.add_argument("--workload", default="single_long", choices=["single_long", "ragged", "h_sweep"],
+                    help="single_long: the reported line; ragged: the 4096-lightcurve batch (H = 4); "
+                         "h_sweep: H = 1..11 at N_f ~ 5e4 (extra measurements, one JSON line each)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy before the bench (reference kernel for "
                          "the HBM byte counters)")
@@ -157,6 +248,11 @@ def main():
     import torch
     import paper_2101_12348_amd as F
     from synthetic import single_long_case
+
+    if args.workload == "ragged":
+        return bench_ragged(args)
+    if args.workload == "h_sweep":
+        return bench_h_sweep(args)
 
     dev = torch.device("cuda:0")
     tmpl, lc = single_long_case()

@@ -27,7 +27,7 @@ __all__ = [
     "eval_template", "cadence_uniform", "cadence_nightly",
     "frequency_grid", "small_fp64_case", "single_long_case", "ragged_batch_case",
     "learned_train_lightcurves", "learned_heldout_lightcurves", "large_case", "single_long_template",
-    "learned_template",
+    "learned_template", "h_sweep_case",
     "tiny_case", "WORKLOADS",
 ]
 
@@ -280,9 +280,21 @@ def large_case(seed: int = SEED0 + 4, n_obs: int = 100_000):
     return tmpl, _signal_lc(rng, tmpl, t, 0.5, period, 20.0)
 
 
+def h_sweep_case(H: int, seed: int = SEED0 + 5, n_obs: int = 10_000):
+    """Single-long-like lightcurve (N=1e4 over 1000 d, nightly cadence,
+    f_max = 10/day) carrying a signal of an H-harmonic sawtooth-like
+    template; one template and lightcurve per H (seed stream seed + H)."""
+    rng = np.random.default_rng(seed * 100 + H)
+    tmpl = template_sawtooth(H, rng)
+    t = cadence_nightly(rng, n_obs, 1000.0)
+    period = float(np.exp(rng.uniform(np.log(0.2), np.log(50.0))))
+    return tmpl, _signal_lc(rng, tmpl, t, 0.5, period, 10.0)
+
+
 WORKLOADS = {
     "small_fp64": small_fp64_case,
     "single_long": single_long_case,
     "ragged_batch": ragged_batch_case,
     "large": large_case,
+    "h_sweep": h_sweep_case,
 }
