@@ -250,12 +250,20 @@ def _best_candidate(cands):
 
 
 def periodogram(t, y, sigma, c, s, df, n_f=None, freq_index=None, block=256,
-                return_details=False):
+                return_details=False, positive_amplitude=False):
     """Template periodogram at f_j = j df.  Evaluate either j = 1..n_f or the
     explicit 1-based indices ``freq_index``.  Returns dict with power, phase
     (theta_2 in [0, 2 pi), relative to t = 0), amp (theta_1), offset
     (theta_3), flag (1 = degenerate MM) and, if asked, per-frequency p and
-    candidate lists."""
+    candidate lists.
+
+    positive_amplitude: the fit constrained to theta_1 > 0 (Section 2.2 names
+    it as a remedy for negative-amplitude solutions).  theta_1 = YM/MM with
+    MM > 0, so the constraint is YM > 0; P = YM^2/(YY MM) vanishes where YM = 0,
+    so the constrained maximum is attained at a stationary point inside
+    {YM > 0}: the best candidate with theta_1 > 0.  With no such candidate
+    (YM vanishing at every candidate) the result is P = 0, theta_1 = 0,
+    theta_3 = ybar, theta_2 = 0."""
     t = np.asarray(t, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     if len(t) < 3 or len(y) != len(t) or len(sigma) != len(t):
@@ -306,7 +314,8 @@ def periodogram(t, y, sigma, c, s, df, n_f=None, freq_index=None, block=256,
                 th2 = float(np.angle(psi)) % (2.0 * np.pi)
                 cands.append((P, th1, th3, th2))
                 allmm.append(MM)
-            best = _best_candidate(cands)
+            pool = [cd for cd in cands if cd[1] > 0] if positive_amplitude else cands
+            best = _best_candidate(pool) if pool else (0.0, 0.0, ybar, 0.0)
             k = b0 + q
             degenerate = max(allmm) <= MM_DEGENERATE * np.sum(np.abs(alpha) ** 2)
             if degenerate:

@@ -270,3 +270,55 @@ def test_direct_fit_at_phase_matches_candidate():
         assert abs(P - r["power"][j - 1]) < 1e-12
         assert abs(a - r["amp"][j - 1]) < 1e-9 * max(1, abs(a))
         assert abs(b - r["offset"][j - 1]) < 1e-9 * max(1, abs(b))
+
+
+def _constrained_grid_max(lc, tmpl, f, th):
+    """max over theta_2 on the grid of observation-level P restricted to a
+    positive least-squares amplitude: P = Cov_w(y, M)^2 / (Var_w(y) Var_w(M)),
+    the amplitude's sign being that of Cov_w(y, M) (weighted least squares on
+    [M, 1], Section 1 definition of P)."""
+    w = 1.0 / lc.sigma ** 2
+    w = w / w.sum()
+    yc = lc.y - np.dot(w, lc.y)
+    M = O.template_values(tmpl.c, tmpl.s, 2 * np.pi * f * lc.t[None, :] - th[:, None])
+    Mc = M - (M @ w)[:, None]
+    cov = Mc @ (w * yc)
+    var = (Mc ** 2) @ w
+    P = cov ** 2 / (var * np.dot(w, yc ** 2))
+    P = np.where(cov > 0, P, -1.0)
+    return P.max()
+
+
+@pytest.mark.parametrize("seed,H", [(4, 2), (5, 3), (6, 5)])
+def test_positive_amplitude_brute_force(seed, H):
+    """The theta_1 > 0 variant (Section 2.2's constrained remedy) against a
+    dense theta_2 grid restricted to positive amplitudes; it never exceeds
+    the unconstrained power and reports a positive amplitude."""
+    tmpl, lc = tiny_case(seed, n_obs=45, H=H, n_f=25)
+    r = _run(tmpl, lc, positive_amplitude=True)
+    u = _run(tmpl, lc)
+    th = np.linspace(0.0, 2 * np.pi, 40_001)[:-1]
+    for j in range(1, lc.n_f + 1):
+        f = j * lc.df
+        Pg = _constrained_grid_max(lc, tmpl, f, th)
+        Pc = r["power"][j - 1]
+        assert Pc <= u["power"][j - 1] + 1e-15
+        assert Pc >= Pg - 1e-13
+        assert Pc - Pg < 1e-5   # grid step 1.6e-4 rad
+        assert r["amp"][j - 1] > 0
+        Pd, a, _ = O.direct_fit_at_phase(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, f, r["phase"][j - 1])
+        assert a > 0 and abs(Pd - Pc) < 1e-12
+
+
+def test_positive_amplitude_on_a_flipped_signal():
+    """A noiseless flipped copy of an asymmetric template: unconstrained,
+    theta_1 = -1.5 and P = 1; constrained to theta_1 > 0, P < 1."""
+    rng = np.random.default_rng(9)
+    tm = Template(np.array([1.0, 0.6, 0.3]), np.array([0.0, 0.5, -0.4]))
+    t = np.sort(rng.uniform(0, 10, 60))
+    df = 1.0 / (5 * (t.max() - t.min()))
+    y = -1.5 * eval_template(tm, 2 * np.pi * 20 * df * t - 0.5)
+    u = O.periodogram(t, y, np.ones(60), tm.c, tm.s, df, freq_index=[20])
+    p = O.periodogram(t, y, np.ones(60), tm.c, tm.s, df, freq_index=[20], positive_amplitude=True)
+    assert abs(u["power"][0] - 1.0) < 1e-10 and u["amp"][0] < 0
+    assert p["amp"][0] > 0 and p["power"][0] < 0.99
