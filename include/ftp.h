@@ -84,6 +84,11 @@ extern "C" {
                                        the companion solve */
 #define FTP_FLAG_TIME_STAGES 2u     /* record HIP events around the NFFT and per-frequency stages
                                        (read back by ftp_last_stats) */
+#define FTP_FLAG_POSITIVE_AMP 8u    /* fit constrained to theta_1 > 0 (Section 2.2): the best
+                                       candidate with YM > 0 (P = YM^2/(YY MM) vanishes on YM = 0,
+                                       so the constrained maximum is one of the same stationary
+                                       points); none: P = 0, theta_1 = 0, theta_3 = ybar,
+                                       theta_2 = 0 */
 
 typedef struct ftp_plan ftp_plan;
 

@@ -22,6 +22,7 @@ FTP_SOLVER_UNIFORM = 2
 FTP_SOLVER_ABERTH = 3
 FTP_FLAG_FORCE_FALLBACK = 1
 FTP_FLAG_TIME_STAGES = 2
+FTP_FLAG_POSITIVE_AMP = 8
 MAX_H = 11
 
 ST_OK, ST_DEGENERATE, ST_CONSTANT, ST_NO_CONVERGE, ST_BAD_LC, ST_FALLBACK, ST_FALLBACK_QR = 0, 1, 2, 3, 4, 8, 16

@@ -108,6 +108,7 @@ hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st);
 }  // namespace ftp
 
 using namespace ftp;
+static_assert(kFlagPositiveAmp == FTP_FLAG_POSITIVE_AMP, "flag values must agree");
 
 static thread_local std::string g_last_error;
 

@@ -42,6 +42,9 @@ enum : int {
 };
 
 // Per-frequency status codes written to the caller's status array.
+// option bit the per-frequency kernels read (same value as FTP_FLAG_POSITIVE_AMP)
+constexpr unsigned kFlagPositiveAmp = 8u;
+
 enum : uint8_t {
   ST_OK = 0,
   ST_DEGENERATE = 1,       // MM ~ 0 at every candidate: P = 0

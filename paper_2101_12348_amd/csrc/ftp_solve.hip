@@ -550,14 +550,17 @@ __global__ __launch_bounds__(64) void k_score(SolveArgs a, const double* rec, in
     const double mmmax = wave_max(valid ? c.MM : -1.0);
     int stout = st;
     if (mmmax <= floor_mm) stout = ST_DEGENERATE;
-    const bool ok = valid && (c.MM > floor_mm || stout == ST_DEGENERATE);
+    // positive-amplitude variant: only candidates with theta_1 = YM/MM > 0
+    const bool pos = (a.flags & kFlagPositiveAmp) != 0u;
+    const bool ok = valid && (c.MM > floor_mm || stout == ST_DEGENERATE) && (!pos || c.YM > 0.0);
+    const bool none = pos && stout != ST_DEGENERATE && __ballot(ok) == 0ull;
     Best b = select_best(c.P, th, wrap_2pi(th + kTwoPi * ref), c.YM, ok, lane);
     // Newton polish of the winner on R(theta) (Eq. theta2cond): a step is
     // kept only if it is small and P does not drop; a step below 1e-13 rad
     // changes P by O(1e-26) and ends the polish without re-scoring
     double best_th = b.th_rel;
     Cand cb = {__shfl(c.P, b.lane), __shfl(c.YM, b.lane), __shfl(c.MM, b.lane), __shfl(c.Mbar, b.lane)};
-    if (stout != ST_DEGENERATE && stout != ST_CONSTANT) {
+    if (stout != ST_DEGENERATE && stout != ST_CONSTANT && !none) {
       for (int it = 0; it < 3; ++it) {
         double Rv, dR;
         eval_R(W, H, best_th, Rv, dR);
@@ -576,7 +579,7 @@ __global__ __launch_bounds__(64) void k_score(SolveArgs a, const double* rec, in
       double P = cb.P, amp = cb.MM > 0.0 ? cb.YM / cb.MM * sq : 0.0;
       double off = L.ybar - cb.Mbar * amp;
       double th_abs = wrap_2pi(best_th + kTwoPi * ref);
-      if (stout == ST_DEGENERATE) { P = 0.0; amp = 0.0; off = L.ybar; th_abs = 0.0; }
+      if (stout == ST_DEGENERATE || none) { P = 0.0; amp = 0.0; off = L.ybar; th_abs = 0.0; }
       a.power[pidx] = P;
       a.phase[pidx] = th_abs;
       a.amp[pidx] = amp;

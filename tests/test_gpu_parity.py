@@ -81,6 +81,38 @@ def test_root_solvers_from_exact_sums(ftp, solver, seed, H):
     _check_phase_fit(tmpl, lc, js, g, 1e-12, 1e-8)
 
 
+@pytest.mark.parametrize("solver", ["plain", "uniform", "aberth"])
+@pytest.mark.parametrize("seed,H", [(10, 2), (11, 3), (12, 6)])
+def test_positive_amplitude_from_exact_sums(ftp, solver, seed, H):
+    """The theta_1 > 0 variant (FTP_FLAG_POSITIVE_AMP) against the oracle's
+    constrained fit, from exact sums."""
+    tmpl, lc = tiny_case(seed, n_obs=80, H=H, n_f=60, cadence="nightly")
+    js = np.arange(1, lc.n_f + 1)
+    tref = 0.5 * (lc.t.min() + lc.t.max())
+    Zw, Zy, ybar, YY = O.raw_sums(lc.t, lc.y, lc.sigma, lc.df, js, 2 * H, H, t_ref=tref)
+    sums = np.concatenate([Zw, Zy], axis=1)
+    sv = {"plain": ftp.FTP_SOLVER_PLAIN, "uniform": ftp.FTP_SOLVER_UNIFORM, "aberth": ftp.FTP_SOLVER_ABERTH}[solver]
+    plan = ftp.Plan(tmpl.c, tmpl.s, precision=ftp.FTP_FP64, solver=sv, flags=ftp.FTP_FLAG_POSITIVE_AMP)
+    g = {k: _np(v) for k, v in plan.solve_sums(sums, tref, ybar, YY, lc.df).items()}
+    ref = O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, lc.n_f, positive_amplitude=True)
+    unc = O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, lc.n_f)
+    assert np.max(np.abs(g["power"] - ref["power"])) <= 1e-12
+    assert np.all(g["amp"][g["power"] > 0] > 0)
+    assert np.any(unc["amp"] < 0)   # the constraint is active somewhere on this grid
+    _check_phase_fit(tmpl, lc, js, g, 1e-12, 1e-8)
+
+
+def test_positive_amplitude_end_to_end_fp32(ftp):
+    tmpl, lc = single_long_case(n_obs=3000)
+    n_f = 6000
+    plan = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_UNIFORM, flags=ftp.FTP_FLAG_POSITIVE_AMP)
+    g = {k: _np(v) for k, v in plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
+    js = np.unique(np.random.default_rng(4).integers(1, n_f + 1, 120))
+    ref = O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, freq_index=js, positive_amplitude=True)
+    assert np.max(np.abs(g["power"][js - 1] - ref["power"])) <= 1e-4
+    assert np.all(g["amp"][g["power"] > 0] > 0)
+
+
 @pytest.mark.parametrize("precision,tol", [(1, 5e-12), (0, 5e-7)])
 def test_nfft_sums_against_direct_sums(ftp, precision, tol):
     tmpl, lc = single_long_case(n_obs=3000)
