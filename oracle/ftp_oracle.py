@@ -332,6 +332,37 @@ def periodogram(t, y, sigma, c, s, df, n_f=None, freq_index=None, block=256,
     return out
 
 
+# ---------------------------------------------------- Section 2.3 multi-band
+
+def chi2_0(y, sigma):
+    """The weighted sum of squared residuals of one band about its weighted
+    mean, sum (y - ybar)^2 / sigma^2 (Section 2.3); unit weights when every
+    sigma is 0 (Section 2)."""
+    y = np.asarray(y, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    wr = np.ones_like(y) if np.all(sigma == 0) else 1.0 / sigma ** 2
+    ybar = np.sum(wr * y) / np.sum(wr)
+    return float(np.sum(wr * (y - ybar) ** 2))
+
+
+def multiband_periodogram(bands, c, s, df, n_f=None, freq_index=None, positive_amplitude=False):
+    """Multi-phase multi-band periodogram (Section 2.3, Eq.
+    multibandmultiphase): P = sum_k chi2_0,k P_k / sum_k chi2_0,k over bands
+    k = 1..K, each band (t, y, sigma) with its own periodogram P_k (its own
+    phase, amplitude and offset) on the common grid f_j = j df.  Returns
+    (P, per-band powers (K, F), chi2_0 (K,))."""
+    Pk = []
+    c0 = []
+    for (t, y, sig) in bands:
+        r = periodogram(t, y, sig, c, s, df, n_f=n_f, freq_index=freq_index,
+                        positive_amplitude=positive_amplitude)
+        Pk.append(r["power"])
+        c0.append(chi2_0(y, sig))
+    Pk = np.array(Pk)
+    c0 = np.array(c0)
+    return (c0[:, None] * Pk).sum(axis=0) / c0.sum(), Pk, c0
+
+
 # ----------------------------------------------------- direct definitions
 
 def template_values(c, s, x):

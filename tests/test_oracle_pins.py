@@ -322,3 +322,59 @@ def test_positive_amplitude_on_a_flipped_signal():
     p = O.periodogram(t, y, np.ones(60), tm.c, tm.s, df, freq_index=[20], positive_amplitude=True)
     assert abs(u["power"][0] - 1.0) < 1e-10 and u["amp"][0] < 0
     assert p["amp"][0] > 0 and p["power"][0] < 0.99
+
+
+def _band(seed, n, tmpl, f0, amp, phase):
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.uniform(0, 12, n))
+    sig = rng.uniform(0.3, 1.0, n)
+    y = amp * eval_template(tmpl, 2 * np.pi * f0 * t - phase) + 0.7 + sig * rng.standard_normal(n)
+    return t, y, sig
+
+
+def test_multiband_against_per_band_least_squares():
+    """Multi-phase multi-band power (Section 2.3) against its definition:
+    every band fitted on its own (amplitude, phase, offset) by brute force
+    over theta_2, P = 1 - sum_k chi2_k / sum_k chi2_0,k with chi2 summed over
+    the residuals directly."""
+    tm = Template(np.array([1.0, 0.4]), np.array([0.2, -0.3]))
+    df = 1.0 / 60.0
+    bands = [_band(30, 40, tm, 9 * df, 1.0, 0.4), _band(31, 35, tm, 9 * df, 0.6, 1.1),
+             _band(32, 50, tm, 9 * df, 0.3, 2.0)]
+    js = np.array([3, 9, 14])
+    P, Pk, c0 = O.multiband_periodogram(bands, tm.c, tm.s, df, freq_index=js)
+    th = np.linspace(0.0, 2 * np.pi, 20_001)[:-1]
+    dth = th[1] - th[0]
+    g = (math.sqrt(5) - 1) / 2
+    for q, j in enumerate(js):
+        f = j * df
+        chi_fit, chi_0 = 0.0, 0.0
+        for (t, y, sig) in bands:
+            Pg = O.direct_power_at_phase(t, y, sig, tm.c, tm.s, f, th)
+            k = int(np.argmax(Pg))
+            a, b = th[k] - dth, th[k] + dth
+            for _ in range(60):
+                x1, x2 = b - g * (b - a), a + g * (b - a)
+                if O.direct_power_at_phase(t, y, sig, tm.c, tm.s, f, x1) > \
+                   O.direct_power_at_phase(t, y, sig, tm.c, tm.s, f, x2):
+                    b = x2
+                else:
+                    a = x1
+            _, amp, off = O.direct_fit_at_phase(t, y, sig, tm.c, tm.s, f, 0.5 * (a + b))
+            model = amp * O.template_values(tm.c, tm.s, 2 * np.pi * f * t - 0.5 * (a + b)) + off
+            chi_fit += np.sum((y - model) ** 2 / sig ** 2)
+            ybar = np.sum(y / sig ** 2) / np.sum(1 / sig ** 2)
+            chi_0 += np.sum((y - ybar) ** 2 / sig ** 2)
+        assert abs(P[q] - (1.0 - chi_fit / chi_0)) < 1e-9
+
+
+def test_multiband_special_cases():
+    """One band is the single-band periodogram; identical bands give it too."""
+    tm = Template(np.array([0.8, 0.1, 0.3]), np.array([0.0, 0.5, -0.2]))
+    df = 1.0 / 60.0
+    b = _band(33, 45, tm, 11 * df, 0.9, 0.3)
+    P1, _, _ = O.multiband_periodogram([b], tm.c, tm.s, df, n_f=20)
+    r = O.periodogram(*b, tm.c, tm.s, df, 20)
+    assert np.max(np.abs(P1 - r["power"])) < 1e-15
+    P3, Pk, c0 = O.multiband_periodogram([b, b, b], tm.c, tm.s, df, n_f=20)
+    assert np.max(np.abs(P3 - r["power"])) < 1e-15 and np.allclose(c0, c0[0])
