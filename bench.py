@@ -188,6 +188,36 @@ def bench_ragged(args):
                       "pairs": pairs, "unit": "pairs/s", "solvers": res}))
 
 
+def bench_multiband(args):
+    """Multi-phase multi-band periodogram (Section 2.3) of a five-band object
+    (2000 observations per band, N_f ~ 5e4): (band x trial frequency) pairs
+    per second, sampled against the oracle's combination."""
+    import numpy as np
+    import torch
+    import paper_2101_12348_amd as F
+    from synthetic import multiband_case
+    tmpl, bands, df, n_f, f0 = multiband_case()
+    res = {}
+    for name, sv in (("uniform", F.FTP_SOLVER_UNIFORM), ("plain", F.FTP_SOLVER_PLAIN)):
+        pl = F.Plan(tmpl.c, tmpl.s, solver=sv)
+        if not args.no_autotune:
+            pl.autotune(*bands[0], df, n_f, cache_path=args.tune_cache, force=args.retune)
+        holder = {}
+        ms = _time_calls(lambda: holder.update(o=pl.periodogram_multiband(bands, df, n_f)), args.steps, args.warmup)
+        g = holder["o"]["power"].cpu().numpy()
+        d = None
+        if not args.no_cpu_baseline:
+            from oracle import ftp_oracle as O
+            js = np.unique(np.linspace(1, n_f, 40).astype(np.int64))
+            P, _, _ = O.multiband_periodogram(bands, tmpl.c, tmpl.s, df, freq_index=js)
+            d = float(np.max(np.abs(g[js - 1] - P)))
+        res[name] = {"value": len(bands) * n_f / (ms * 1e-3), "ms_per_call": ms, "max_abs_dP_sampled": d,
+                     "best_f": (int(np.argmax(g)) + 1) * df}
+        pl.close()
+    print(json.dumps({"workload": f"multi-band: {len(bands)} bands x 2000 obs, T=1000 d, H={tmpl.H}, N_f={n_f}",
+                      "unit": "band x frequency pairs/s", "injected_f": f0, "solvers": res}))
+
+
 def bench_h_sweep(args):
     """H = 1..11 at N_f ~ 5e4 (one single-long-like lightcurve per H): time
     per periodogram for the plain, uniform-start and Aberth solvers."""
@@ -231,7 +261,7 @@ def main():
                     help="launch-shape cache read (and, on a miss, written) by the autotuner")
     ap.add_argument("--retune", action="store_true",
                     help="measure the launch shapes even when the cache has them (and store the result)")
-    ap.add_argument("--workload", default="single_long", choices=["single_long", "ragged", "h_sweep"],
+    ap.add_argument("--workload", default="single_long", choices=["single_long", "ragged", "h_sweep", "multiband"],
                     help="single_long: the reported line; ragged: the 4096-lightcurve batch (H = 4); "
                          "h_sweep: H = 1..11 at N_f ~ 5e4 (extra measurements, one JSON line each)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -253,6 +283,8 @@ def main():
         return bench_ragged(args)
     if args.workload == "h_sweep":
         return bench_h_sweep(args)
+    if args.workload == "multiband":
+        return bench_multiband(args)
 
     dev = torch.device("cuda:0")
     tmpl, lc = single_long_case()

@@ -180,6 +180,25 @@ int ftp_periodogram_batch(ftp_plan* plan, int64_t n_lc, const int64_t* obs_off, 
                           void* stream);
 
 /*
+ * Multi-phase multi-band periodogram (Section 2.3, Eq. multibandmultiphase):
+ * n_band bands of one object, each with its own phase, amplitude and offset,
+ * the plan's template for all of them, on the common grid f_j = j df,
+ * j = 1..n_f:  power[j] = sum_k chi2_0,k P_k[j] / sum_k chi2_0,k with
+ * chi2_0,k = sum over band k of (y - ybar_k)^2 / sigma^2 (unit weights when
+ * every sigma of the band is 0).  Runs the bands as a ragged batch.
+ *   obs_off : host, n_band + 1 offsets of the bands in t, y, sigma (device).
+ *   power   : device, n_f FP64.
+ *   band_power (nullable): device, n_band x n_f FP64, the band periodograms.
+ *   chi2_0  (nullable): device, n_band FP64 (0 for a rejected band, which
+ *             then does not count; all rejected: power = 0).
+ * Errors: as ftp_periodogram_batch.  Plan scratch grows to n_band n_f
+ * records of 33 bytes.
+ */
+int ftp_periodogram_multiband(ftp_plan* plan, int64_t n_band, const int64_t* obs_off, const double* t,
+                              const double* y, const double* sigma, double df, int64_t n_f, double* power,
+                              double* band_power, double* chi2_0, void* stream);
+
+/*
  * NFFT stage alone (for checking the sums): writes, per frequency j = 1..n_f,
  * 3H complex FP64 values to `sums` (device, n_f * 6H doubles, interleaved
  * re/im): Z_w(k j), k = 1..2H, then Z_y(k j), k = 1..H, where

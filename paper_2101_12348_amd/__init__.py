@@ -34,7 +34,7 @@ EXPORTED = [
     "ftp_mlp_create", "ftp_mlp_destroy", "ftp_mlp_num_params", "ftp_mlp_get_weights", "ftp_mlp_forward",
     "ftp_mlp_loss_grad", "ftp_mlp_train_step", "ftp_learned_dataset",
     "ftp_plan_get_tuning", "ftp_plan_set_tuning", "ftp_autotune", "ftp_plan_tune_key",
-    "ftp_tune_cache_lookup", "ftp_tune_cache_store",
+    "ftp_tune_cache_lookup", "ftp_tune_cache_store", "ftp_periodogram_multiband",
 ]
 
 FTP_TUNE_FORCE = 1
@@ -98,6 +98,7 @@ def load_library(path: Optional[str] = None):
     lib.ftp_mlp_train_step.argtypes = [vp, vp, i64, vp, vp, ip, ctypes.c_float, ctypes.c_float, vp, vp]
     lib.ftp_learned_dataset.argtypes = [vp, vp, vp, vp, i64, dbl, i64, vp, vp, vp, ip, vp]
     lib.ftp_status_string.argtypes = [ip]
+    lib.ftp_periodogram_multiband.argtypes = [vp, i64, vp, vp, vp, vp, dbl, i64, vp, vp, vp, vp]
     lib.ftp_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.ftp_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.ftp_autotune.argtypes = [vp, vp, vp, vp, i64, dbl, i64, ctypes.c_char_p, ctypes.c_uint,
@@ -261,6 +262,25 @@ class Plan:
         import numpy as np
         w = np.ascontiguousarray(weights, dtype=np.float32)
         _check(self.lib.ftp_plan_load_mlp(self.handle, w.ctypes.data_as(ctypes.c_void_p), w.size, int(width)))
+
+    def periodogram_multiband(self, bands, df: float, n_f: int, device="cuda", stream=None):
+        """Multi-phase multi-band periodogram of bands [(t, y, sigma), ...]
+        sharing the plan's template: dict(power (n_f,), band_power
+        (n_band, n_f), chi2_0 (n_band,))."""
+        import numpy as np
+        torch = _torch()
+        obs_off = np.concatenate([[0], np.cumsum([len(b[0]) for b in bands])]).astype(np.int64)
+        t = _dev(np.concatenate([np.asarray(b[0], dtype=np.float64) for b in bands]), torch.float64, device)
+        y = _dev(np.concatenate([np.asarray(b[1], dtype=np.float64) for b in bands]), torch.float64, device)
+        s = _dev(np.concatenate([np.asarray(b[2], dtype=np.float64) for b in bands]), torch.float64, device)
+        nb = len(bands)
+        power = torch.empty(n_f, dtype=torch.float64, device=t.device)
+        bp = torch.empty((nb, n_f), dtype=torch.float64, device=t.device)
+        c2 = torch.empty(nb, dtype=torch.float64, device=t.device)
+        _check(self.lib.ftp_periodogram_multiband(self.handle, nb, obs_off.ctypes.data_as(ctypes.c_void_p), _ptr(t),
+                                                  _ptr(y), _ptr(s), float(df), int(n_f), _ptr(power), _ptr(bp),
+                                                  _ptr(c2), _stream_ptr(stream)))
+        return dict(power=power, band_power=bp, chi2_0=c2)
 
     def tuning(self) -> dict:
         tu = Tuning()

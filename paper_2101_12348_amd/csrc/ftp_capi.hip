@@ -105,6 +105,9 @@ struct FusedMlpArgs {
 bool mlp_fused_ok(const int* nin, const int* nout);
 hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st);
 hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st);
+hipError_t launch_lc_chi2(const LcInfo* lcs, int64_t n_lc, double* out, hipStream_t st);
+hipError_t launch_mb_combine(const double* bp, int64_t n_band, int64_t n_f, const double* chi2, double* power,
+                             hipStream_t st);
 }  // namespace ftp
 
 using namespace ftp;
@@ -332,6 +335,10 @@ struct ftp_plan {
   // ftp_autotune
   ftp_tuning tune{32, 32, 16, 16, 32, 0};
   DevBuf tune_out;
+  // multi-band calls: chi^2_0 of every lightcurve of the batch (device, set
+  // for the duration of the call) and the band outputs' scratch
+  double* lc_chi2_out = nullptr;
+  DevBuf mb_out, mb_chi2;
 };
 
 namespace {
@@ -718,6 +725,7 @@ int run_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, con
   if ((rc = run_nfft<R>(P, n_lc, n_pts, n_grid, n_tiles, t + o0, y + o0, sigma + o0, st))) return rc;
   hipEvent_t e1 = next_event(P);
   if (e1) HIP_TRY(hipEventRecord(e1, st));
+  if (P->lc_chi2_out) HIP_TRY(launch_lc_chi2(P->lcinfo.as<LcInfo>(), n_lc, P->lc_chi2_out + lc0, st));
   SolveArgs a = base_args(P, n_lc, n_pairs);
   if (sums_out) {
     const int64_t blocks = std::min<int64_t>(n_pairs, 65536);
@@ -890,7 +898,7 @@ int ftp_plan_destroy(ftp_plan* P) {
                     &P->grid_tile_base, &P->pw, &P->py, &P->tile_count, &P->tile_off, &P->cursor,
                     &P->block_sums, &P->total, &P->bucket, &P->grids, &P->fft_tab, &P->fft_items,
                     &P->counters, &P->stats_out, &P->rec, &P->xfeat, &P->seeds, &P->fb_list,
-                    &P->fb2_list, &P->work_ctr, &P->tune_out};
+                    &P->fb2_list, &P->work_ctr, &P->tune_out, &P->mb_out, &P->mb_chi2};
   P->net.release();
   for (DevBuf* b : bufs) b->release();
   if (P->upload_done) (void)hipEventDestroy(P->upload_done);
@@ -928,6 +936,40 @@ int ftp_periodogram_batch(ftp_plan* P, int64_t n_lc, const int64_t* obs_off, con
   if (obs_off[n_lc] > ((int64_t)1 << 30)) return FTP_E_SIZE;
   return run_batch(P, n_lc, obs_off, t, y, sigma, df, freq_off, power, phase, amp, offset, status, nullptr,
                    (hipStream_t)stream);
+}
+
+int ftp_periodogram_multiband(ftp_plan* P, int64_t n_band, const int64_t* obs_off, const double* t, const double* y,
+                              const double* sigma, double df, int64_t n_f, double* power, double* band_power,
+                              double* chi2_0, void* stream) {
+  if (!P || !obs_off || !t || !y || !sigma || !power) return FTP_E_NULL;
+  if (n_band < 1) return FTP_E_OFFSETS;
+  if (obs_off[0] != 0) return FTP_E_OFFSETS;
+  for (int64_t b = 0; b < n_band; ++b) {
+    if (obs_off[b + 1] < obs_off[b]) return FTP_E_OFFSETS;
+    int rc = validate_scalars(df, n_f, obs_off[b + 1] - obs_off[b]);
+    if (rc) return rc;
+  }
+  if (obs_off[n_band] > ((int64_t)1 << 30)) return FTP_E_SIZE;
+  if (n_f > (((int64_t)1 << 40) / n_band)) return FTP_E_SIZE;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t np = n_band * n_f;
+  int rc;
+  // band outputs: power (caller's band_power or scratch), phase, amp, offset, status
+  if ((rc = P->mb_out.ensure((size_t)np * (4 * sizeof(double) + 1)))) return rc;
+  if ((rc = P->mb_chi2.ensure(sizeof(double) * n_band))) return rc;
+  double* scr = P->mb_out.as<double>();
+  double* bp = band_power ? band_power : scr;
+  double* c2 = chi2_0 ? chi2_0 : P->mb_chi2.as<double>();
+  std::vector<int64_t> freq_off(n_band + 1);
+  std::vector<double> dfs(n_band, df);
+  for (int64_t b = 0; b <= n_band; ++b) freq_off[b] = b * n_f;
+  P->lc_chi2_out = c2;
+  rc = run_batch(P, n_band, obs_off, t, y, sigma, dfs.data(), freq_off.data(), bp, scr + np, scr + 2 * np,
+                 scr + 3 * np, reinterpret_cast<uint8_t*>(scr + 4 * np), nullptr, st);
+  P->lc_chi2_out = nullptr;
+  if (rc) return rc;
+  HIP_TRY(launch_mb_combine(bp, n_band, n_f, c2, power, st));
+  return FTP_OK;
 }
 
 int ftp_nfft_sums(ftp_plan* P, const double* t, const double* y, const double* sigma, int64_t n_obs, double df,

@@ -614,6 +614,29 @@ __global__ __launch_bounds__(64) void k_gather_sums(SolveArgs a, double* out) {
   }
 }
 
+// chi^2_0 of each lightcurve of a chunk (Section 2.3): sum (y - ybar)^2 /
+// sigma^2 = YY / w_inv with YY = sum w (y - ybar)^2, sum w = 1 (unit weights:
+// w_inv = 1/N); 0 for a rejected lightcurve.
+__global__ __launch_bounds__(256) void k_lc_chi2(const LcInfo* lcs, int64_t n_lc, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n_lc) out[i] = lcs[i].status == 0 ? lcs[i].yy / lcs[i].winv : 0.0;
+}
+
+// Multi-phase multi-band combination (Section 2.3, Eq.
+// multibandmultiphase): power[j] = sum_k chi2[k] P_k[j] / sum_k chi2[k] over
+// the band periodograms P_k = bp[k n_f + j]; 0 when every band was rejected.
+__global__ __launch_bounds__(256) void k_mb_combine(const double* bp, int64_t n_band, int64_t n_f,
+                                                    const double* chi2, double* power) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n_f) return;
+  double num = 0.0, den = 0.0;
+  for (int64_t k = 0; k < n_band; ++k) {
+    num += chi2[k] * bp[k * n_f + j];
+    den += chi2[k];
+  }
+  power[j] = den > 0.0 ? num / den : 0.0;
+}
+
 // Clears n counters (a kernel rather than a memset node, so that captured
 // graphs replay it like any other launch).
 __global__ __launch_bounds__(256) void k_zero_u32(unsigned* p, int64_t n) {
@@ -680,6 +703,18 @@ hipError_t launch_gather_sums(int precision, const SolveArgs& a, double* out, in
     hipLaunchKernelGGL(k_gather_sums<double>, dim3((unsigned)blocks), dim3(64), 0, st, a, out);
   else
     hipLaunchKernelGGL(k_gather_sums<float>, dim3((unsigned)blocks), dim3(64), 0, st, a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_lc_chi2(const LcInfo* lcs, int64_t n_lc, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_lc_chi2, dim3((unsigned)((n_lc + 255) / 256)), dim3(256), 0, st, lcs, n_lc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mb_combine(const double* bp, int64_t n_band, int64_t n_f, const double* chi2, double* power,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_mb_combine, dim3((unsigned)((n_f + 255) / 256)), dim3(256), 0, st, bp, n_band, n_f, chi2,
+                     power);
   return hipGetLastError();
 }
 

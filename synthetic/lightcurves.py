@@ -27,7 +27,7 @@ __all__ = [
     "eval_template", "cadence_uniform", "cadence_nightly",
     "frequency_grid", "small_fp64_case", "single_long_case", "ragged_batch_case",
     "learned_train_lightcurves", "learned_heldout_lightcurves", "large_case", "single_long_template",
-    "learned_template", "h_sweep_case",
+    "learned_template", "h_sweep_case", "multiband_case",
     "tiny_case", "WORKLOADS",
 ]
 
@@ -278,6 +278,31 @@ def large_case(seed: int = SEED0 + 4, n_obs: int = 100_000):
     t = cadence_nightly(rng, n_obs, 3000.0, season_len=243.0)
     period = float(np.exp(rng.uniform(np.log(0.2), np.log(50.0))))
     return tmpl, _signal_lc(rng, tmpl, t, 0.5, period, 20.0)
+
+
+def multiband_case(seed: int = SEED0 + 6, n_band: int = 5, n_obs: int = 2000, baseline: float = 1000.0,
+                   H: int = 6):
+    """One variable observed in n_band bands (u, g, r, i, z-like): the same
+    period and phase in every band, band amplitudes 0.5, 0.4, 0.35, 0.3, 0.25
+    (cycled), per-band noise sigma ~ U(0.05, 0.2) times 1.0, 0.6, 0.5, 0.6,
+    0.9 (cycled), each band on its own nightly cadence over the baseline;
+    df from the longest band span, f_max = 10/day.  Returns (template, bands
+    [(t, y, sigma)], df, n_f, f0)."""
+    rng = np.random.default_rng(seed)
+    tmpl = template_sawtooth(H, rng)
+    period = float(np.exp(rng.uniform(np.log(0.2), np.log(50.0))))
+    phi = float(rng.uniform(0.0, 2.0 * np.pi))
+    amps = [0.5, 0.4, 0.35, 0.3, 0.25]
+    noise = [1.0, 0.6, 0.5, 0.6, 0.9]
+    bands = []
+    for k in range(n_band):
+        t = cadence_nightly(rng, n_obs, baseline)
+        sigma = rng.uniform(0.05, 0.2, n_obs) * noise[k % 5]
+        y = amps[k % 5] * eval_template(tmpl, 2 * np.pi * t / period - phi) + 0.1 * k + sigma * rng.standard_normal(n_obs)
+        bands.append((t, y, sigma))
+    t_all = np.concatenate([b[0] for b in bands])
+    df, n_f = frequency_grid(t_all, 10.0)
+    return tmpl, bands, df, n_f, 1.0 / period
 
 
 def h_sweep_case(H: int, seed: int = SEED0 + 5, n_obs: int = 10_000):
