@@ -168,8 +168,40 @@ __device__ __forceinline__ void tile_span(int cell, int msp, int log2n, int& t0,
   (void)ntile;
 }
 
+// Per-workgroup aggregation of tile counts: an LDS open-addressing table keyed
+// by global tile index.  A 256-point workgroup touches at most 1024 tiles (two
+// grids, at most two tiles per point), so 2048 slots always leave room and a
+// probe sequence ends within the table.  Counting in LDS first turns one
+// global atomic per (point, tile) into one per (workgroup, tile); points in
+// time order touch few tiles per workgroup.
+constexpr int kTileHash = 2048;
+struct TileTable {
+  int key[kTileHash];
+  unsigned cnt[kTileHash];
+  unsigned base[kTileHash];
+};
+
+__device__ __forceinline__ void tile_table_clear(TileTable& T) {
+  for (int h = threadIdx.x; h < kTileHash; h += blockDim.x) {
+    T.key[h] = -1;
+    T.cnt[h] = 0u;
+  }
+}
+
+// Slot of `tile` (inserted if new).
+__device__ __forceinline__ int tile_slot(TileTable& T, int tile) {
+  unsigned h = ((unsigned)tile * 2654435761u) >> 21;   // 11-bit multiplicative hash
+  for (int probe = 0; probe < kTileHash; ++probe) {
+    const int old = atomicCAS(&T.key[h], -1, tile);
+    if (old == -1 || old == tile) return (int)h;
+    h = (h + 1u) & (kTileHash - 1);
+  }
+  return -1;   // not reached: the table holds at most 1024 keys
+}
+
 // Per point and grid: cell, fractional offset and modulated strength, and the
-// tile histogram (global atomic counts; the counts do not depend on order).
+// tile histogram (counts per workgroup in LDS, then added to the global
+// counts; the counts do not depend on order).
 template <typename R>
 __global__ __launch_bounds__(256) void k_prep_points(const LcInfo* __restrict__ lcs, int64_t n_lc,
                                                      const int64_t* __restrict__ obs_off,
@@ -179,59 +211,64 @@ __global__ __launch_bounds__(256) void k_prep_points(const LcInfo* __restrict__ 
                                                      PointRec<R>* __restrict__ pw,
                                                      PointRec<R>* __restrict__ py,
                                                      unsigned int* __restrict__ tile_count) {
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n_total) return;
-  const int64_t lc = find_segment(obs_off, n_lc, i);
-  const LcInfo& L = lcs[lc];
-  PointRec<R> recs[2];
-  if (L.status != 0) {
-    for (int g = 0; g < 2; ++g) { recs[g].cell = -1; recs[g].frac = 0; recs[g].g.x = 0; recs[g].g.y = 0; }
+  __shared__ TileTable T;
+  tile_table_clear(T);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n_total) {
+    const int64_t lc = find_segment(obs_off, n_lc, i);
+    const LcInfo& L = lcs[lc];
+    PointRec<R> recs[2];
+    if (L.status != 0) {
+      for (int g = 0; g < 2; ++g) { recs[g].cell = -1; recs[g].frac = 0; recs[g].g.x = 0; recs[g].g.y = 0; }
+    } else {
+      const double si = sigma[i];
+      const double w = (L.wmode ? 1.0 : 1.0 / (si * si)) * L.winv;
+      const double gval[2] = {w, w * (y[i] - L.ybar) * L.inv_sqrt_yy};
+      // x = df (t - tref) in double-double, reduced mod 1
+      double dh, dl;
+      two_sum(t[i], -L.tref, dh, dl);
+      double xh, xl;
+      two_prod(L.df, dh, xh, xl);
+      xl = fma(L.df, dl, xl);
+      dd_wrap_half(xh, xl);
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const int log2n = L.log2n[g];
+        const double nn = (double)(1 << log2n);
+        double uh = xh * nn, ul = xl * nn;   // exact scaling by a power of two
+        double c = floor(uh);
+        double fr = (uh - c) + ul;
+        if (fr < 0.0) { fr += 1.0; c -= 1.0; }
+        if (fr >= 1.0) { fr -= 1.0; c += 1.0; }
+        long long ci = (long long)c;
+        const long long n = 1LL << log2n;
+        ci &= n - 1;   // n is a power of two
+        // modulation phase frac(m_c x)
+        double ph, pl;
+        const double mc = (double)L.mc[g];
+        two_prod(mc, xh, ph, pl);
+        pl = fma(mc, xl, pl);
+        dd_wrap_half(ph, pl);
+        double phase = ph + pl;
+        double sn, cs;
+        sincospi(2.0 * phase, &sn, &cs);
+        recs[g].cell = (int)ci;
+        recs[g].frac = (R)fr;
+        recs[g].g.x = (R)(gval[g] * cs);
+        recs[g].g.y = (R)(gval[g] * sn);
+        int t0, t1;
+        tile_span((int)ci, L.msp, log2n, t0, t1);
+        atomicAdd(&T.cnt[tile_slot(T, (int)(L.tile_base[g] + t0))], 1u);
+        if (t1 >= 0) atomicAdd(&T.cnt[tile_slot(T, (int)(L.tile_base[g] + t1))], 1u);
+      }
+    }
     pw[i] = recs[0];
     py[i] = recs[1];
-    return;
   }
-  const double si = sigma[i];
-  const double w = (L.wmode ? 1.0 : 1.0 / (si * si)) * L.winv;
-  const double gval[2] = {w, w * (y[i] - L.ybar) * L.inv_sqrt_yy};
-  // x = df (t - tref) in double-double, reduced mod 1
-  double dh, dl;
-  two_sum(t[i], -L.tref, dh, dl);
-  double xh, xl;
-  two_prod(L.df, dh, xh, xl);
-  xl = fma(L.df, dl, xl);
-  dd_wrap_half(xh, xl);
-#pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    const int log2n = L.log2n[g];
-    const double nn = (double)(1 << log2n);
-    double uh = xh * nn, ul = xl * nn;   // exact scaling by a power of two
-    double c = floor(uh);
-    double fr = (uh - c) + ul;
-    if (fr < 0.0) { fr += 1.0; c -= 1.0; }
-    if (fr >= 1.0) { fr -= 1.0; c += 1.0; }
-    long long ci = (long long)c;
-    const long long n = 1LL << log2n;
-    ci &= n - 1;   // n is a power of two
-    // modulation phase frac(m_c x)
-    double ph, pl;
-    const double mc = (double)L.mc[g];
-    two_prod(mc, xh, ph, pl);
-    pl = fma(mc, xl, pl);
-    dd_wrap_half(ph, pl);
-    double phase = ph + pl;
-    double sn, cs;
-    sincospi(2.0 * phase, &sn, &cs);
-    recs[g].cell = (int)ci;
-    recs[g].frac = (R)fr;
-    recs[g].g.x = (R)(gval[g] * cs);
-    recs[g].g.y = (R)(gval[g] * sn);
-    int t0, t1;
-    tile_span((int)ci, L.msp, log2n, t0, t1);
-    atomicAdd(&tile_count[L.tile_base[g] + t0], 1u);
-    if (t1 >= 0) atomicAdd(&tile_count[L.tile_base[g] + t1], 1u);
-  }
-  pw[i] = recs[0];
-  py[i] = recs[1];
+  __syncthreads();
+  for (int h = threadIdx.x; h < kTileHash; h += 256)
+    if (T.key[h] >= 0) atomicAdd(&tile_count[T.key[h]], T.cnt[h]);
 }
 
 // Exclusive scan of 32-bit counts into 64-bit offsets, one workgroup for up
@@ -336,8 +373,11 @@ __global__ __launch_bounds__(256) void k_scan_add(int64_t* __restrict__ out, int
   }
 }
 
-// Bucket fill: the slot inside a bucket comes from an atomic cursor.  The
-// spread result does not depend on this order (exact integer accumulation).
+// Bucket fill: each workgroup counts its entries per tile in LDS (the entry's
+// rank there comes from the LDS atomic), reserves one range per tile with a
+// global atomic on the tile's cursor, and writes every entry at range start +
+// rank.  The spread result does not depend on this order (exact integer
+// accumulation).
 template <typename R>
 __global__ __launch_bounds__(256) void k_bin_fill(const LcInfo* __restrict__ lcs, int64_t n_lc,
                                                   const int64_t* __restrict__ obs_off, int64_t n_total,
@@ -346,23 +386,39 @@ __global__ __launch_bounds__(256) void k_bin_fill(const LcInfo* __restrict__ lcs
                                                   const int64_t* __restrict__ tile_off,
                                                   unsigned int* __restrict__ cursor,
                                                   int* __restrict__ bucket) {
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n_total) return;
-  const int64_t lc = find_segment(obs_off, n_lc, i);
-  const LcInfo& L = lcs[lc];
-  for (int g = 0; g < 2; ++g) {
-    int cell = g == 0 ? pw[i].cell : py[i].cell;
-    if (cell < 0) continue;
-    int t0, t1;
-    tile_span(cell, L.msp, L.log2n[g], t0, t1);
-    int64_t tt = L.tile_base[g] + t0;
-    unsigned int slot = atomicAdd(&cursor[tt], 1u);
-    bucket[tile_off[tt] + slot] = (int)((i << 1) | g) ;
-    if (t1 >= 0) {
-      tt = L.tile_base[g] + t1;
-      slot = atomicAdd(&cursor[tt], 1u);
-      bucket[tile_off[tt] + slot] = (int)((i << 1) | g);
+  __shared__ TileTable T;
+  tile_table_clear(T);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int slot[4], rank[4];
+  int ne = 0;
+  if (i < n_total) {
+    const int64_t lc = find_segment(obs_off, n_lc, i);
+    const LcInfo& L = lcs[lc];
+    for (int g = 0; g < 2; ++g) {
+      const int cell = g == 0 ? pw[i].cell : py[i].cell;
+      if (cell < 0) continue;
+      int t0, t1;
+      tile_span(cell, L.msp, L.log2n[g], t0, t1);
+      const int ts[2] = {t0, t1};
+      for (int e = 0; e < 2; ++e) {
+        if (ts[e] < 0) continue;
+        const int h = tile_slot(T, (int)(L.tile_base[g] + ts[e]));
+        slot[ne] = h;
+        rank[ne] = (int)atomicAdd(&T.cnt[h], 1u) | (g << 30);
+        ++ne;
+      }
     }
+  }
+  __syncthreads();
+  for (int h = threadIdx.x; h < kTileHash; h += 256)
+    if (T.key[h] >= 0) T.base[h] = atomicAdd(&cursor[T.key[h]], T.cnt[h]);
+  __syncthreads();
+  for (int e = 0; e < ne; ++e) {
+    const int h = slot[e];
+    const int g = rank[e] >> 30;
+    const unsigned r = (unsigned)(rank[e] & 0x3fffffff);
+    bucket[tile_off[T.key[h]] + T.base[h] + r] = (int)((i << 1) | g);
   }
 }
 
