@@ -304,7 +304,7 @@ struct ftp_plan {
   size_t grid_budget = (size_t)8 << 30;   // bytes of NFFT grids per chunk
   // device buffers
   DevBuf alpha, twiddle32, twiddle64;
-  DevBuf lcinfo, obs_off, freq_off, grid_tile_base, pw, py, tile_count, tile_off, cursor, block_sums,
+  DevBuf pw, py, tile_count, tile_off, cursor, block_sums,
       total, bucket, grids, fft_tab, fft_items, counters, stats_out, rec;
   int64_t pair_chunk = (int64_t)1 << 20;  // pairs per assemble/root/score round
   // host staging (kept alive until the uploads completed)
@@ -312,6 +312,16 @@ struct ftp_plan {
   std::vector<int64_t> h_obs_off, h_freq_off, h_gtb;
   std::vector<FftGridPass> h_fft;
   std::vector<int64_t> h_items;
+  std::vector<int64_t> fft_round_tab_off, fft_round_n, fft_round_items;
+  // per-chunk tables (lightcurve plans, offsets, FFT passes) packed into one
+  // pinned host buffer and sent with one copy; the d_* pointers point into
+  // d_stage
+  unsigned char* h_stage = nullptr;
+  size_t h_stage_cap = 0;
+  DevBuf d_stage;
+  LcInfo* d_lc = nullptr;
+  int64_t *d_obs_off = nullptr, *d_freq_off = nullptr, *d_gtb = nullptr, *d_items = nullptr;
+  FftGridPass* d_fft = nullptr;
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
   ftp_stats last{};
@@ -473,13 +483,13 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
   if ((rc = P->total.ensure(sizeof(int64_t)))) return rc;
   if ((rc = P->bucket.ensure(sizeof(int) * std::max<int64_t>(4 * n_pts, 1)))) return rc;
   if ((rc = P->grids.ensure(sizeof(C) * n_grid))) return rc;
-  LcInfo* dl = P->lcinfo.as<LcInfo>();
+  LcInfo* dl = P->d_lc;
   hipLaunchKernelGGL(k_prep_stats, dim3((unsigned)n_lc), dim3(1024), 0, st, dl, t, y, sigma);
   HIP_TRY(launch_zero_u32(P->tile_count.as<unsigned>(), n_tiles, st));
   HIP_TRY(launch_zero_u32(P->cursor.as<unsigned>(), n_tiles, st));
   const unsigned pblocks = (unsigned)((n_pts + 255) / 256);
   hipLaunchKernelGGL(k_prep_points<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc,
-                     P->obs_off.as<int64_t>(), n_pts, t, y, sigma, P->pw.as<PointRec<R>>(),
+                     P->d_obs_off, n_pts, t, y, sigma, P->pw.as<PointRec<R>>(),
                      P->py.as<PointRec<R>>(), P->tile_count.as<unsigned>());
   if (n_tiles <= kScanSingleMax) {
     hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, P->tile_count.as<unsigned>(), n_tiles,
@@ -491,22 +501,38 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, st, P->tile_off.as<int64_t>(), n_tiles,
                        P->block_sums.as<int64_t>(), P->tile_count.as<unsigned>(), P->total.as<int64_t>());
   }
-  hipLaunchKernelGGL(k_bin_fill<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc, P->obs_off.as<int64_t>(),
+  hipLaunchKernelGGL(k_bin_fill<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc, P->d_obs_off,
                      n_pts, P->pw.as<PointRec<R>>(), P->py.as<PointRec<R>>(), P->tile_off.as<int64_t>(),
                      P->cursor.as<unsigned>(), P->bucket.as<int>());
   hipLaunchKernelGGL(k_spread<R>, dim3((unsigned)n_tiles), dim3(256), 0, st, dl, 2 * n_lc,
-                     P->grid_tile_base.as<int64_t>(), P->pw.as<PointRec<R>>(), P->py.as<PointRec<R>>(),
+                     P->d_gtb, P->pw.as<PointRec<R>>(), P->py.as<PointRec<R>>(),
                      P->tile_off.as<int64_t>(), P->bucket.as<int>(), P->grids.as<C>());
-  // FFT rounds
+  const C* tw = reinterpret_cast<const C*>(P->opt.precision == FTP_FP64 ? P->twiddle64.p : P->twiddle32.p);
+  int64_t item_base = 0;
+  for (size_t r = 0; r < P->fft_round_n.size(); ++r) {
+    hipLaunchKernelGGL(k_fft_pass<R>, dim3((unsigned)P->fft_round_items[r]), dim3(256), 32768, st,
+                       P->d_fft + P->fft_round_tab_off[r], P->fft_round_n[r], P->d_items + item_base, tw,
+                       P->grids.as<C>());
+    item_base += P->fft_round_n[r] + 1;
+  }
+  HIP_TRY(hipGetLastError());
+  return FTP_OK;
+}
+
+// FFT passes of the chunk's grids (host): per round, one FftGridPass per grid
+// that still has a pass, and the item offsets of each round.
+void build_fft_tables(ftp_plan* P) {
   int max_pass = 0;
   for (const LcInfo& L : P->h_lc) max_pass = std::max({max_pass, L.npass[0], L.npass[1]});
   std::vector<FftGridPass>& tab = P->h_fft;
   std::vector<int64_t>& items = P->h_items;
   tab.clear();
   items.clear();
-  std::vector<int64_t> round_tab_off, round_n, round_items;
+  P->fft_round_tab_off.clear();
+  P->fft_round_n.clear();
+  P->fft_round_items.clear();
   for (int r = 0; r < max_pass; ++r) {
-    round_tab_off.push_back((int64_t)tab.size());
+    P->fft_round_tab_off.push_back((int64_t)tab.size());
     int64_t it = 0;
     int64_t cnt = 0;
     for (const LcInfo& L : P->h_lc) {
@@ -527,44 +553,58 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
         ++cnt;
       }
     }
-    round_n.push_back(cnt);
-    round_items.push_back(it);
+    P->fft_round_n.push_back(cnt);
+    P->fft_round_items.push_back(it);
   }
   // item_begin arrays per round, laid out after each other (with sentinel)
   for (int r = 0; r < max_pass; ++r) {
-    for (int64_t q = 0; q < round_n[r]; ++q) items.push_back(tab[round_tab_off[r] + q].item_begin);
-    items.push_back(round_items[r]);
+    for (int64_t q = 0; q < P->fft_round_n[r]; ++q) items.push_back(tab[P->fft_round_tab_off[r] + q].item_begin);
+    items.push_back(P->fft_round_items[r]);
   }
-  if ((rc = P->fft_tab.ensure(sizeof(FftGridPass) * std::max<size_t>(tab.size(), 1)))) return rc;
-  if ((rc = P->fft_items.ensure(sizeof(int64_t) * std::max<size_t>(items.size(), 1)))) return rc;
-  HIP_TRY(hipMemcpyAsync(P->fft_tab.p, tab.data(), sizeof(FftGridPass) * tab.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(P->fft_items.p, items.data(), sizeof(int64_t) * items.size(), hipMemcpyHostToDevice,
-                         st));
-  const C* tw = reinterpret_cast<const C*>(P->opt.precision == FTP_FP64 ? P->twiddle64.p : P->twiddle32.p);
-  int64_t item_base = 0;
-  for (int r = 0; r < max_pass; ++r) {
-    hipLaunchKernelGGL(k_fft_pass<R>, dim3((unsigned)round_items[r]), dim3(256), 32768, st,
-                       P->fft_tab.as<FftGridPass>() + round_tab_off[r], round_n[r],
-                       P->fft_items.as<int64_t>() + item_base, tw, P->grids.as<C>());
-    item_base += round_n[r] + 1;
-  }
-  HIP_TRY(hipGetLastError());
-  return FTP_OK;
 }
 
-int upload_tables(ftp_plan* P, int64_t n_lc, hipStream_t st) {
+// Sends the chunk's tables (and, with_fft, its FFT passes) in one copy from
+// pinned staging.  The staging is reused once this copy has completed
+// (upload_done, waited for by the next call).
+int upload_tables(ftp_plan* P, int64_t n_lc, hipStream_t st, bool with_fft) {
   int rc;
-  if ((rc = P->lcinfo.ensure(sizeof(LcInfo) * n_lc))) return rc;
-  if ((rc = P->obs_off.ensure(sizeof(int64_t) * (n_lc + 1)))) return rc;
-  if ((rc = P->freq_off.ensure(sizeof(int64_t) * (n_lc + 1)))) return rc;
-  if ((rc = P->grid_tile_base.ensure(sizeof(int64_t) * (2 * n_lc + 1)))) return rc;
-  HIP_TRY(hipMemcpyAsync(P->lcinfo.p, P->h_lc.data(), sizeof(LcInfo) * n_lc, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(P->obs_off.p, P->h_obs_off.data(), sizeof(int64_t) * (n_lc + 1),
-                         hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(P->freq_off.p, P->h_freq_off.data(), sizeof(int64_t) * (n_lc + 1),
-                         hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(P->grid_tile_base.p, P->h_gtb.data(), sizeof(int64_t) * (2 * n_lc + 1),
-                         hipMemcpyHostToDevice, st));
+  if ((rc = wait_uploads(P))) return rc;
+  if (with_fft) build_fft_tables(P);
+  else {
+    P->h_fft.clear();
+    P->h_items.clear();
+  }
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t s_lc = sizeof(LcInfo) * n_lc, s_off = sizeof(int64_t) * (n_lc + 1),
+               s_gtb = sizeof(int64_t) * (2 * n_lc + 1), s_fft = sizeof(FftGridPass) * P->h_fft.size(),
+               s_it = sizeof(int64_t) * P->h_items.size();
+  const size_t o_lc = 0, o_obs = al(o_lc + s_lc), o_freq = al(o_obs + s_off), o_gtb = al(o_freq + s_off),
+               o_fft = al(o_gtb + s_gtb), o_it = al(o_fft + s_fft), total = al(o_it + s_it);
+  if (total > P->h_stage_cap) {
+    if (P->h_stage) HIP_TRY(hipHostFree(P->h_stage));
+    P->h_stage = nullptr;
+    P->h_stage_cap = 0;
+    HIP_TRY(hipHostMalloc((void**)&P->h_stage, total, hipHostMallocDefault));
+    P->h_stage_cap = total;
+  }
+  unsigned char* h = P->h_stage;
+  std::memcpy(h + o_lc, P->h_lc.data(), s_lc);
+  std::memcpy(h + o_obs, P->h_obs_off.data(), s_off);
+  std::memcpy(h + o_freq, P->h_freq_off.data(), s_off);
+  std::memcpy(h + o_gtb, P->h_gtb.data(), s_gtb);
+  if (s_fft) std::memcpy(h + o_fft, P->h_fft.data(), s_fft);
+  if (s_it) std::memcpy(h + o_it, P->h_items.data(), s_it);
+  if ((rc = P->d_stage.ensure(total))) return rc;
+  HIP_TRY(hipMemcpyAsync(P->d_stage.p, h, total, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(P->upload_done, st));
+  P->upload_pending = true;
+  unsigned char* d = P->d_stage.as<unsigned char>();
+  P->d_lc = reinterpret_cast<LcInfo*>(d + o_lc);
+  P->d_obs_off = reinterpret_cast<int64_t*>(d + o_obs);
+  P->d_freq_off = reinterpret_cast<int64_t*>(d + o_freq);
+  P->d_gtb = reinterpret_cast<int64_t*>(d + o_gtb);
+  P->d_fft = reinterpret_cast<FftGridPass*>(d + o_fft);
+  P->d_items = reinterpret_cast<int64_t*>(d + o_it);
   return FTP_OK;
 }
 
@@ -695,9 +735,9 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
 
 SolveArgs base_args(ftp_plan* P, int64_t n_lc, int64_t n_pairs) {
   SolveArgs a{};
-  a.lcs = P->lcinfo.as<LcInfo>();
+  a.lcs = P->d_lc;
   a.n_lc = n_lc;
-  a.freq_off = P->freq_off.as<int64_t>();
+  a.freq_off = P->d_freq_off;
   a.total = n_pairs;
   a.grids = P->grids.p;
   a.alpha = P->alpha.as<double2>();
@@ -717,7 +757,7 @@ int run_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, con
   int64_t n_grid = 0, n_tiles = 0;
   if ((rc = plan_chunk(P, lc0, lc1, obs_off, df, freq_off, &n_grid, &n_tiles))) return rc;
   const int64_t n_lc = lc1 - lc0;
-  if ((rc = upload_tables(P, n_lc, st))) return rc;
+  if ((rc = upload_tables(P, n_lc, st, true))) return rc;
   const int64_t o0 = obs_off[lc0], n_pts = obs_off[lc1] - o0;
   const int64_t f0 = freq_off[lc0], n_pairs = freq_off[lc1] - f0;
   hipEvent_t e0 = next_event(P);
@@ -725,7 +765,7 @@ int run_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, con
   if ((rc = run_nfft<R>(P, n_lc, n_pts, n_grid, n_tiles, t + o0, y + o0, sigma + o0, st))) return rc;
   hipEvent_t e1 = next_event(P);
   if (e1) HIP_TRY(hipEventRecord(e1, st));
-  if (P->lc_chi2_out) HIP_TRY(launch_lc_chi2(P->lcinfo.as<LcInfo>(), n_lc, P->lc_chi2_out + lc0, st));
+  if (P->lc_chi2_out) HIP_TRY(launch_lc_chi2(P->d_lc, n_lc, P->lc_chi2_out + lc0, st));
   SolveArgs a = base_args(P, n_lc, n_pairs);
   if (sums_out) {
     const int64_t blocks = std::min<int64_t>(n_pairs, 65536);
@@ -740,8 +780,6 @@ int run_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, con
   }
   hipEvent_t e2 = next_event(P);
   if (e2) HIP_TRY(hipEventRecord(e2, st));
-  HIP_TRY(hipEventRecord(P->upload_done, st));
-  P->upload_pending = true;
   return FTP_OK;
 }
 
@@ -894,14 +932,15 @@ int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, con
 int ftp_plan_destroy(ftp_plan* P) {
   if (!P) return FTP_E_NULL;
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&P->alpha, &P->twiddle32, &P->twiddle64, &P->lcinfo, &P->obs_off, &P->freq_off,
-                    &P->grid_tile_base, &P->pw, &P->py, &P->tile_count, &P->tile_off, &P->cursor,
-                    &P->block_sums, &P->total, &P->bucket, &P->grids, &P->fft_tab, &P->fft_items,
+  DevBuf* bufs[] = {&P->alpha, &P->twiddle32, &P->twiddle64, &P->d_stage,
+                    &P->pw, &P->py, &P->tile_count, &P->tile_off, &P->cursor,
+                    &P->block_sums, &P->total, &P->bucket, &P->grids,
                     &P->counters, &P->stats_out, &P->rec, &P->xfeat, &P->seeds, &P->fb_list,
                     &P->fb2_list, &P->work_ctr, &P->tune_out, &P->mb_out, &P->mb_chi2};
   P->net.release();
   for (DevBuf* b : bufs) b->release();
   if (P->upload_done) (void)hipEventDestroy(P->upload_done);
+  if (P->h_stage) (void)hipHostFree(P->h_stage);
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : P->evr) (void)hipEventDestroy(e);
   for (hipEvent_t e : P->evl) (void)hipEventDestroy(e);
@@ -983,7 +1022,7 @@ int ftp_nfft_sums(ftp_plan* P, const double* t, const double* y, const double* s
                  (hipStream_t)stream);
   if (rc) return rc;
   // lc_stats: tref, ybar, yy, status bits
-  HIP_TRY(launch_export_stats(P->lcinfo.as<LcInfo>(), lc_stats, (hipStream_t)stream));
+  HIP_TRY(launch_export_stats(P->d_lc, lc_stats, (hipStream_t)stream));
   return FTP_OK;
 }
 
@@ -1008,7 +1047,7 @@ int ftp_solve_sums(ftp_plan* P, const double* sums, const double* lc_stats, doub
   P->h_obs_off.assign(2, 0);
   P->h_freq_off = {0, n_f};
   P->h_gtb.assign(3, 0);
-  if ((rc = upload_tables(P, 1, st))) return rc;
+  if ((rc = upload_tables(P, 1, st, false))) return rc;
   SolveArgs a = base_args(P, 1, n_f);
   a.sums_in = sums;
   a.mm_tau = 1e-14;
@@ -1018,8 +1057,6 @@ int ftp_solve_sums(ftp_plan* P, const double* sums, const double* lc_stats, doub
   a.offset = offset;
   a.status = status;
   if ((rc = run_solve(P, a, n_f, st))) return rc;
-  HIP_TRY(hipEventRecord(P->upload_done, st));
-  P->upload_pending = true;
   P->last.n_pairs += (uint64_t)n_f;
   return FTP_OK;
 }

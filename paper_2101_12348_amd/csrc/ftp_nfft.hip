@@ -98,7 +98,6 @@ __global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const 
   const int64_t b = L.obs_off, n = L.n_obs;
   double sinv = 0.0, swy = 0.0, sy0 = 0.0, tmin = INFINITY, tmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
   int nzero = 0, bad = 0;
-#pragma unroll 4
   for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
     const double ti = t[b + i], yi = y[b + i], si = sigma[b + i];
     if (!isfinite(ti) || !isfinite(yi) || !isfinite(si) || si < 0.0) bad = 1;
@@ -133,7 +132,6 @@ __global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const 
   else { winv = 1.0 / sinv; ybar = swy * winv; }
   double syy = 0.0;
   if (status == 0) {
-#pragma unroll 4
     for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
       const double si = sigma[b + i];
       const double w = (wmode ? 1.0 : 1.0 / (si * si)) * winv;
