@@ -57,32 +57,6 @@ __device__ __forceinline__ int64_t find_segment(const int64_t* off, int64_t n, i
 
 // ------------------------------------------------------------ prep
 
-template <typename T, int NW>
-__device__ __forceinline__ T block_sum_w(T v, T* sh) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  T r = sh[0];
-  for (int k = 1; k < NW; ++k) r += sh[k];
-  __syncthreads();
-  return r;
-}
-
-template <int NW>
-__device__ __forceinline__ double block_min_w(double v, double* sh) {
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double r = sh[0];
-  for (int k = 1; k < NW; ++k) r = fmin(r, sh[k]);
-  __syncthreads();
-  return r;
-}
-
 // One 1024-thread workgroup per lightcurve: weights (Section 1: w ~ sigma^-2,
 // sum w = 1; all sigma = 0 -> uniform), ybar, YY = chi^2_0, t_ref.  Two passes
 // over the observations: the first gathers the extremes, sum sigma^-2 and
@@ -92,12 +66,11 @@ __global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const 
                                                              const double* __restrict__ y,
                                                              const double* __restrict__ sigma) {
   constexpr int NW = kStatThreads / 64;
-  __shared__ double shd[NW];
-  __shared__ int shi[NW];
   LcInfo& L = lcs[blockIdx.x];
   const int64_t b = L.obs_off, n = L.n_obs;
   double sinv = 0.0, swy = 0.0, sy0 = 0.0, tmin = INFINITY, tmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
   int nzero = 0, bad = 0;
+#pragma unroll 1
   for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
     const double ti = t[b + i], yi = y[b + i], si = sigma[b + i];
     if (!isfinite(ti) || !isfinite(yi) || !isfinite(si) || si < 0.0) bad = 1;
@@ -114,15 +87,48 @@ __global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const 
     ymin = fmin(ymin, yi);
     ymax = fmax(ymax, yi);
   }
-  sinv = block_sum_w<double, NW>(sinv, shd);
-  swy = block_sum_w<double, NW>(swy, shd);
-  sy0 = block_sum_w<double, NW>(sy0, shd);
-  tmin = block_min_w<NW>(tmin, shd);
-  tmax = -block_min_w<NW>(-tmax, shd);
-  ymin = block_min_w<NW>(ymin, shd);
-  ymax = -block_min_w<NW>(-ymax, shd);
-  nzero = block_sum_w<int, NW>(nzero, shi);
-  bad = block_sum_w<int, NW>(bad, shi);
+  // the nine reductions together: wave-level shuffles, one LDS exchange
+  double v[7] = {sinv, swy, sy0, tmin, -tmax, ymin, -ymax};
+  int iv[2] = {nzero, bad};
+  for (int o = 32; o > 0; o >>= 1) {
+    for (int q = 0; q < 3; ++q) v[q] += __shfl_xor(v[q], o);
+    for (int q = 3; q < 7; ++q) v[q] = fmin(v[q], __shfl_xor(v[q], o));
+    for (int q = 0; q < 2; ++q) iv[q] += __shfl_xor(iv[q], o);
+  }
+  __shared__ double shv[NW][7];
+  __shared__ int shiv[NW][2];
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    for (int q = 0; q < 7; ++q) shv[wid][q] = v[q];
+    for (int q = 0; q < 2; ++q) shiv[wid][q] = iv[q];
+  }
+  __syncthreads();
+  // thread q < 9 reduces column q over the waves; everyone reads the results
+  __shared__ double resv[7];
+  __shared__ int resi[2];
+  if (threadIdx.x < 7) {
+    const int q = threadIdx.x;
+    double r = shv[0][q];
+    for (int k = 1; k < NW; ++k) r = q < 3 ? r + shv[k][q] : fmin(r, shv[k][q]);
+    resv[q] = r;
+  } else if (threadIdx.x < 9) {
+    const int q = threadIdx.x - 7;
+    int r = shiv[0][q];
+    for (int k = 1; k < NW; ++k) r += shiv[k][q];
+    resi[q] = r;
+  }
+  __syncthreads();
+  for (int q = 0; q < 7; ++q) v[q] = resv[q];
+  for (int q = 0; q < 2; ++q) iv[q] = resi[q];
+  sinv = v[0];
+  swy = v[1];
+  sy0 = v[2];
+  tmin = v[3];
+  tmax = -v[4];
+  ymin = v[5];
+  ymax = -v[6];
+  nzero = iv[0];
+  bad = iv[1];
   int status = 0;
   int wmode = 0;
   double winv = 0.0, ybar = 0.0;
@@ -132,14 +138,20 @@ __global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const 
   else { winv = 1.0 / sinv; ybar = swy * winv; }
   double syy = 0.0;
   if (status == 0) {
-    for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
+  #pragma unroll 1
+  for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
       const double si = sigma[b + i];
       const double w = (wmode ? 1.0 : 1.0 / (si * si)) * winv;
       const double d = y[b + i] - ybar;
       syy += w * d * d;
     }
   }
-  const double yy = block_sum_w<double, NW>(syy, shd);
+  for (int o = 32; o > 0; o >>= 1) syy += __shfl_xor(syy, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) shv[wid][0] = syy;
+  __syncthreads();
+  double yy = shv[0][0];
+  for (int k = 1; k < NW; ++k) yy += shv[k][0];
   // Var(y) = 0 means every y_i is equal (rounding may leave yy slightly > 0)
   if (status == 0 && (!(yy > 0.0 && isfinite(yy)) || ymin == ymax)) status |= LC_ZERO_VAR;
   if (threadIdx.x == 0) {
