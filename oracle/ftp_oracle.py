@@ -363,6 +363,100 @@ def multiband_periodogram(bands, c, s, df, n_f=None, freq_index=None, positive_a
     return (c0[:, None] * Pk).sum(axis=0) / c0.sum(), Pk, c0
 
 
+# ------------------------------------------ Appendix A shared-phase multi-band
+
+def shared_phase_periodogram(bands, templates, df, n_f=None, freq_index=None, offsets=None):
+    """Shared-phase multi-band template periodogram (Appendix A): bands k with
+    templates M^(k) (c^(k), s^(k)) share theta_1, theta_2, theta_3,
+    y^(k) ~ theta_1 M^(k)(w t - theta_2) + theta_3 + lambda_k with fixed
+    relative offsets lambda_k (``offsets``, subtracted first); weights
+    sigma^-2 normalised over all observations (Section 2 rules).  Following
+    Appendix A: psi^2H MM^ = sum_i w_i (psi^H M_i)^2 and psi^H Mbar =
+    sum_i w_i psi^H M_i give MM' = psi^2H MM^ - (psi^H Mbar)^2, and
+    YM' = sum_i w_i y_i psi^H M_i - ybar psi^H Mbar; then Eq. finalpoly, its
+    roots and the single-band scoring with the global ybar and YY.  Templates
+    with fewer harmonics are padded with zeros to the largest H.  Returns dict
+    with power, phase, amp, offset, flag, ybar, YY."""
+    K = len(bands)
+    if K < 1 or len(templates) != K:
+        raise OracleError("need one template per band")
+    H = max(len(np.atleast_1d(c)) for c, _ in templates)
+    alphas = np.zeros((K, H), dtype=np.complex128)
+    for k, (c, sv) in enumerate(templates):
+        a = alpha_from_template(c, sv)
+        alphas[k, : len(a)] = a
+    if np.all(alphas == 0):
+        raise OracleError("templates must have a non-zero coefficient")
+    lam = np.zeros(K) if offsets is None else np.asarray(offsets, dtype=np.float64)
+    t_all = np.concatenate([np.asarray(b[0], dtype=np.float64) for b in bands])
+    y_all = np.concatenate([np.asarray(b[1], dtype=np.float64) - lam[k] for k, b in enumerate(bands)])
+    sig_all = np.concatenate([np.asarray(b[2], dtype=np.float64) for b in bands])
+    band = np.concatenate([np.full(len(b[0]), k) for k, b in enumerate(bands)])
+    if len(t_all) < 3 or not (np.all(np.isfinite(t_all)) and np.all(np.isfinite(y_all))):
+        raise OracleError("need at least 3 finite observations")
+    if not (np.isfinite(df) and df > 0):
+        raise OracleError("df must be positive")
+    w = weights(sig_all)
+    ybar, YY = moments(y_all, w)
+    A = alphas[band]                                   # (N, H) template of each observation
+    scale = float(np.sum(w * np.sum(np.abs(A) ** 2, axis=1)))
+    if freq_index is None:
+        if n_f is None or n_f < 1:
+            raise OracleError("n_f must be >= 1")
+        idx = np.arange(1, n_f + 1)
+    else:
+        idx = np.asarray(freq_index, dtype=np.int64)
+    F = len(idx)
+    out = dict(power=np.zeros(F), phase=np.zeros(F), amp=np.zeros(F), offset=np.zeros(F),
+               flag=np.zeros(F, dtype=np.int8))
+    Pn = np.polynomial.polynomial
+    for q, j in enumerate(idx):
+        z = _unit_phasors(t_all, np.array([np.longdouble(j) * np.longdouble(df)]))[:, 0]   # e^{i w t}
+        zn = np.empty((len(t_all), H), dtype=np.complex128)
+        zn[:, 0] = z
+        for n in range(1, H):
+            zn[:, n] = zn[:, n - 1] * z
+        # psi^H M_i(w t_i - theta): coefficient of psi^{H+n} is alpha_n e^{-i n w t},
+        # of psi^{H-n} conj(alpha_n) e^{i n w t}
+        Q = np.zeros((len(t_all), 2 * H + 1), dtype=np.complex128)
+        Q[:, H + 1:] = A * np.conj(zn)
+        Q[:, H - 1:: -1] = np.conj(A) * zn
+        Mbarp = w @ Q
+        MMhatp = np.zeros(4 * H + 1, dtype=np.complex128)
+        for a_ in range(2 * H + 1):
+            for b_ in range(2 * H + 1):
+                MMhatp[a_ + b_] += np.sum(w * Q[:, a_] * Q[:, b_])
+        MMp = MMhatp - Pn.polymul(Mbarp, Mbarp)
+        YMp = (w * y_all) @ Q - ybar * Mbarp
+        p_raw = final_poly(MMp, YMp)
+        p, _ = trim_poly(p_raw)
+        if len(p) >= 2:
+            roots = poly_roots(p)
+            roots = roots[np.isfinite(roots) & (np.abs(roots) > 1e-8)]
+        else:
+            roots = np.zeros(0, dtype=np.complex128)
+        psis = list(roots / np.abs(roots)) if len(roots) else [1.0 + 0j]
+        cands, allmm = [], []
+        for psi in psis:
+            YM = np.real(psi ** (-H) * Pn.polyval(psi, YMp))
+            MM = np.real(psi ** (-2 * H) * Pn.polyval(psi, MMp))
+            Mb = np.real(psi ** (-H) * Pn.polyval(psi, Mbarp))
+            allmm.append(MM)
+            if MM <= MM_DEGENERATE * scale:
+                cands.append((0.0, 0.0, ybar, float(np.angle(psi)) % (2 * np.pi)))
+                continue
+            th1 = YM / MM
+            cands.append((YM * YM / (YY * MM), th1, ybar - Mb * th1, float(np.angle(psi)) % (2 * np.pi)))
+        best = _best_candidate(cands)
+        if max(allmm) <= MM_DEGENERATE * scale:
+            out["power"][q], out["amp"][q], out["offset"][q], out["phase"][q] = 0.0, 0.0, ybar, 0.0
+            out["flag"][q] = 1
+        else:
+            out["power"][q], out["amp"][q], out["offset"][q], out["phase"][q] = best
+    out["ybar"], out["YY"] = ybar, YY
+    return out
+
+
 # ----------------------------------------------------- direct definitions
 
 def template_values(c, s, x):

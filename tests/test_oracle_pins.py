@@ -378,3 +378,83 @@ def test_multiband_special_cases():
     assert np.max(np.abs(P1 - r["power"])) < 1e-15
     P3, Pk, c0 = O.multiband_periodogram([b, b, b], tm.c, tm.s, df, n_f=20)
     assert np.max(np.abs(P3 - r["power"])) < 1e-15 and np.allclose(c0, c0[0])
+
+
+def _sp_bands(seed, ns, templates, f0, A, phi, B, lam, noise=0.3):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, n in enumerate(ns):
+        t = np.sort(rng.uniform(0, 12, n))
+        sig = rng.uniform(0.2, 0.6, n) * noise / 0.3
+        y = A * eval_template(templates[k], 2 * np.pi * f0 * t - phi) + B + lam[k] + sig * rng.standard_normal(n)
+        out.append((t, y, sig))
+    return out
+
+
+def _sp_direct(bands, templates, lam, f, th):
+    """Observation-level P(theta_2) of the shared-phase model: the weighted
+    correlation of y - lambda with the per-observation template, weights
+    sigma^-2 normalised over all bands (Appendix A)."""
+    w = np.concatenate([1.0 / b[2] ** 2 for b in bands])
+    w = w / w.sum()
+    y = np.concatenate([b[1] - lam[k] for k, b in enumerate(bands)])
+    M = np.concatenate([O.template_values(templates[k].c, templates[k].s,
+                                          2 * np.pi * f * b[0][None, :] - np.atleast_1d(th)[:, None])
+                        for k, b in enumerate(bands)], axis=1)
+    yc = y - np.dot(w, y)
+    Mc = M - (M @ w)[:, None]
+    cov = Mc @ (w * yc)
+    return cov ** 2 / (((Mc ** 2) @ w) * np.dot(w, yc ** 2)), cov / ((Mc ** 2) @ w)
+
+
+def test_shared_phase_brute_force():
+    """Shared-phase multi-band (Appendix A) against a dense theta_2 grid of the
+    observation-level definition with per-band templates and offsets."""
+    tms = [Template(np.array([1.0, 0.4, 0.1]), np.array([0.2, -0.3, 0.2])),
+           Template(np.array([0.7, 0.5]), np.array([-0.1, 0.3])),
+           Template(np.array([1.2, 0.2, -0.2]), np.array([0.0, 0.1, 0.3]))]
+    df = 1.0 / 60.0
+    lam = np.array([0.0, 0.8, -0.5])
+    bands = _sp_bands(50, (40, 30, 45), tms, 9 * df, 1.3, 0.7, 0.2, lam)
+    js = np.array([2, 9, 13, 21])
+    r = O.shared_phase_periodogram(bands, [(tm.c, tm.s) for tm in tms], df, freq_index=js, offsets=lam)
+    th = np.linspace(0.0, 2 * np.pi, 20_001)[:-1]
+    dth = th[1] - th[0]
+    g = (math.sqrt(5) - 1) / 2
+    for q, j in enumerate(js):
+        f = j * df
+        Pg, _ = _sp_direct(bands, tms, lam, f, th)
+        k = int(np.argmax(Pg))
+        a, b = th[k] - dth, th[k] + dth
+        for _ in range(60):
+            x1, x2 = b - g * (b - a), a + g * (b - a)
+            if _sp_direct(bands, tms, lam, f, x1)[0][0] > _sp_direct(bands, tms, lam, f, x2)[0][0]:
+                b = x2
+            else:
+                a = x1
+        Pref = _sp_direct(bands, tms, lam, f, 0.5 * (a + b))[0][0]
+        assert r["power"][q] >= Pg.max() - 1e-13
+        assert abs(r["power"][q] - max(Pref, Pg.max())) < 1e-10
+        Pd, amp = _sp_direct(bands, tms, lam, f, r["phase"][q])
+        assert abs(Pd[0] - r["power"][q]) < 1e-12 and abs(amp[0] - r["amp"][q]) < 1e-9 * max(1, abs(amp[0]))
+
+
+def test_shared_phase_special_cases():
+    """One band, or bands sharing one template with no offsets, reduce to the
+    single-band periodogram of the (concatenated) data; relative offsets
+    given back through ``offsets`` cancel."""
+    tm = Template(np.array([0.8, 0.1, 0.3]), np.array([0.0, 0.5, -0.2]))
+    df = 1.0 / 60.0
+    bands = _sp_bands(51, (40, 35), [tm, tm], 11 * df, 0.9, 0.3, 0.1, [0.0, 0.0])
+    r1 = O.shared_phase_periodogram(bands[:1], [(tm.c, tm.s)], df, n_f=20)
+    s1 = O.periodogram(*bands[0], tm.c, tm.s, df, 20)
+    assert np.max(np.abs(r1["power"] - s1["power"])) < 1e-12
+    cat = tuple(np.concatenate([b[i] for b in bands]) for i in range(3))
+    r2 = O.shared_phase_periodogram(bands, [(tm.c, tm.s)] * 2, df, n_f=20)
+    s2 = O.periodogram(*cat, tm.c, tm.s, df, 20)
+    assert np.max(np.abs(r2["power"] - s2["power"])) < 1e-12
+    assert np.max(np.abs(r2["amp"] - s2["amp"])) < 1e-9 and np.max(np.abs(r2["offset"] - s2["offset"])) < 1e-9
+    lam = np.array([0.4, -1.1])
+    shifted = [(b[0], b[1] + lam[k], b[2]) for k, b in enumerate(bands)]
+    r3 = O.shared_phase_periodogram(shifted, [(tm.c, tm.s)] * 2, df, n_f=20, offsets=lam)
+    assert np.max(np.abs(r3["power"] - r2["power"])) < 1e-12
