@@ -148,6 +148,19 @@ int ftp_options_default(ftp_options* opt);
  */
 int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, const ftp_options* opt);
 
+/*
+ * Create a plan for the shared-phase multi-band model (Appendix A): one
+ * template per band, c and s host arrays of n_band x H values, band-major
+ * (band k's c_n at c[k H + n - 1]); a band with fewer harmonics is padded
+ * with zeros, a band whose template is all zero is allowed as long as one
+ * band's is not.  1 <= n_band <= 16.  Such a plan serves only
+ * ftp_periodogram_shared_phase (ftp_last_stats, tuning and destroy as any
+ * plan); the other periodogram calls return FTP_E_OPTION on it.
+ * Errors: FTP_E_NULL, FTP_E_H, FTP_E_OPTION (n_band out of range), FTP_E_HIP.
+ */
+int ftp_plan_create_bands(ftp_plan** out, int n_band, int H, const double* c, const double* s,
+                          const ftp_options* opt);
+
 /* Release a plan and its device scratch (synchronises the device). */
 int ftp_plan_destroy(ftp_plan* plan);
 
@@ -197,6 +210,33 @@ int ftp_periodogram_batch(ftp_plan* plan, int64_t n_lc, const int64_t* obs_off, 
 int ftp_periodogram_multiband(ftp_plan* plan, int64_t n_band, const int64_t* obs_off, const double* t,
                               const double* y, const double* sigma, double df, int64_t n_f, double* power,
                               double* band_power, double* chi2_0, void* stream);
+
+/*
+ * Shared-phase multi-band periodogram (Appendix A) of one object observed in
+ * the plan's n_band bands: band k's observations are t, y, sigma[obs_off[k]
+ * .. obs_off[k+1]) (device arrays; obs_off on the host, n_band + 1 entries,
+ * obs_off[0] = 0, every band non-empty).  The bands share amplitude theta_1,
+ * phase theta_2 and offset theta_3; band k's data are modelled as
+ * theta_1 M_k(omega t - theta_2) + theta_3 + offsets[k] with fixed offsets
+ * (host, n_band values; NULL = all zero), subtracted before anything else.
+ * Weights sigma^-2 are normalised over all observations (all sigma zero in
+ * every band: unit weights); ybar and YY = chi^2_0 are those of all bands
+ * together.  Per frequency j df, j = 1..n_f, the sums of every band give
+ * MM = psi^2H MMhat - (psi^H Mbar)^2 and YM = sum w y psi^H M - ybar psi^H Mbar,
+ * whose polynomial (Eq. finalpoly) is solved and scored exactly as in the
+ * single-band call; outputs as ftp_periodogram (device, n_f each): power,
+ * phase (theta_2), amp (theta_1), offset (theta_3, the common offset before
+ * the band offsets are added back), status.  FTP_FLAG_POSITIVE_AMP applies.
+ * All bands' grids are resident together (no chunking).
+ * Errors: FTP_E_NULL, FTP_E_OPTION (not a bands plan, non-finite offset),
+ * FTP_E_OFFSETS, FTP_E_NOBS (an empty band), FTP_E_DF, FTP_E_NF, FTP_E_SIZE,
+ * FTP_E_NO_MODEL, FTP_E_HIP.  Mixed unit and sigma weights across bands, or
+ * non-finite input, give status FTP_ST_BAD_LC for every frequency.
+ */
+int ftp_periodogram_shared_phase(ftp_plan* plan, const int64_t* obs_off, const double* t, const double* y,
+                                 const double* sigma, const double* offsets, double df, int64_t n_f,
+                                 double* power, double* phase, double* amp, double* offset, uint8_t* status,
+                                 void* stream);
 
 /*
  * NFFT stage alone (for checking the sums): writes, per frequency j = 1..n_f,

@@ -35,6 +35,7 @@ EXPORTED = [
     "ftp_mlp_loss_grad", "ftp_mlp_train_step", "ftp_learned_dataset",
     "ftp_plan_get_tuning", "ftp_plan_set_tuning", "ftp_autotune", "ftp_plan_tune_key",
     "ftp_tune_cache_lookup", "ftp_tune_cache_store", "ftp_periodogram_multiband",
+    "ftp_plan_create_bands", "ftp_periodogram_shared_phase",
 ]
 
 FTP_TUNE_FORCE = 1
@@ -82,6 +83,8 @@ def load_library(path: Optional[str] = None):
     vp, i64, dbl, ip = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     lib.ftp_options_default.argtypes = [ctypes.POINTER(Options)]
     lib.ftp_plan_create.argtypes = [ctypes.POINTER(vp), ip, vp, vp, ctypes.POINTER(Options)]
+    lib.ftp_plan_create_bands.argtypes = [ctypes.POINTER(vp), ip, ip, vp, vp, ctypes.POINTER(Options)]
+    lib.ftp_periodogram_shared_phase.argtypes = [vp, vp, vp, vp, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp]
     lib.ftp_plan_destroy.argtypes = [vp]
     lib.ftp_periodogram.argtypes = [vp, vp, vp, vp, i64, dbl, i64, vp, vp, vp, vp, vp, vp]
     lib.ftp_periodogram_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -163,15 +166,18 @@ class Plan:
             raise ValueError("c and s must be 1-D arrays of equal length")
         self.H = len(c)
         self.c, self.s = c, s
+        self.options = self._options(precision, solver, nfft_R, nfft_msp, solve_waves, flags)
+        h = ctypes.c_void_p()
+        _check(self.lib.ftp_plan_create(ctypes.byref(h), self.H, c.ctypes.data_as(ctypes.c_void_p),
+                                         s.ctypes.data_as(ctypes.c_void_p), ctypes.byref(self.options)))
+        self.handle = h
+
+    def _options(self, precision, solver, nfft_R, nfft_msp, solve_waves, flags):
         opt = Options()
         self.lib.ftp_options_default(ctypes.byref(opt))
         opt.precision, opt.solver, opt.nfft_R = precision, solver, nfft_R
         opt.nfft_msp, opt.solve_waves, opt.flags = nfft_msp, solve_waves, flags
-        self.options = opt
-        h = ctypes.c_void_p()
-        _check(self.lib.ftp_plan_create(ctypes.byref(h), self.H, c.ctypes.data_as(ctypes.c_void_p),
-                                         s.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opt)))
-        self.handle = h
+        return opt
 
     def close(self):
         if getattr(self, "handle", None):
@@ -355,6 +361,57 @@ def load_model(name: str = "single_long_h6"):
 def mlp_param_count(d_in: int, width: int, d_out: int) -> int:
     return d_in * width + width + 2 * (width * width + width) + d_out * width + d_out
 
+
+
+class BandsPlan(Plan):
+    """A plan for the shared-phase multi-band model (Appendix A): one template
+    (c_n, s_n) per band, padded with zeros to the largest H."""
+
+    def __init__(self, templates, precision: int = FTP_FP32_SUMS, solver: int = FTP_SOLVER_PLAIN,
+                 nfft_R: float = 2.0, nfft_msp: int = 0, solve_waves: int = 0, flags: int = 0):
+        import numpy as np
+        self.lib = load_library()
+        nb = len(templates)
+        H = max(len(np.atleast_1d(c)) for c, _ in templates) if nb else 0
+        c = np.zeros((max(nb, 1), max(H, 1)), dtype=np.float64)
+        s = np.zeros_like(c)
+        for k, (ck, sk) in enumerate(templates):
+            ck, sk = np.atleast_1d(np.asarray(ck, dtype=np.float64)), np.atleast_1d(np.asarray(sk, dtype=np.float64))
+            if ck.shape != sk.shape or ck.ndim != 1:
+                raise ValueError("each template needs 1-D c and s of equal length")
+            c[k, : len(ck)], s[k, : len(sk)] = ck, sk
+        self.H, self.n_band = H, nb
+        self.c, self.s = c, s
+        self.options = self._options(precision, solver, nfft_R, nfft_msp, solve_waves, flags)
+        h = ctypes.c_void_p()
+        _check(self.lib.ftp_plan_create_bands(ctypes.byref(h), nb, H, c.ctypes.data_as(ctypes.c_void_p),
+                                               s.ctypes.data_as(ctypes.c_void_p), ctypes.byref(self.options)))
+        self.handle = h
+
+    def periodogram_shared_phase(self, bands, df: float, n_f: int, offsets=None, device="cuda", stream=None,
+                                 out=None):
+        """Shared-phase periodogram of bands [(t, y, sigma), ...] (one per
+        template, in order), with fixed band offsets (None = zero); returns
+        the outputs of Plan.periodogram."""
+        import numpy as np
+        torch = _torch()
+        obs_off = np.concatenate([[0], np.cumsum([len(b[0]) for b in bands])]).astype(np.int64)
+        t = _dev(np.concatenate([np.asarray(b[0], dtype=np.float64) for b in bands]), torch.float64, device)
+        y = _dev(np.concatenate([np.asarray(b[1], dtype=np.float64) for b in bands]), torch.float64, device)
+        sg = _dev(np.concatenate([np.asarray(b[2], dtype=np.float64) for b in bands]), torch.float64, device)
+        if len(bands) != self.n_band:
+            raise ValueError("one band of data per template")
+        off = None if offsets is None else np.ascontiguousarray(offsets, dtype=np.float64)
+        if off is not None and off.shape != (self.n_band,):
+            raise ValueError("one offset per band")
+        if out is None:
+            out = self.alloc_outputs(n_f, t.device)
+        _check(self.lib.ftp_periodogram_shared_phase(
+            self.handle, obs_off.ctypes.data_as(ctypes.c_void_p), _ptr(t), _ptr(y), _ptr(sg),
+            off.ctypes.data_as(ctypes.c_void_p) if off is not None else ctypes.c_void_p(0), float(df), int(n_f),
+            _ptr(out["power"]), _ptr(out["phase"]), _ptr(out["amp"]), _ptr(out["offset"]), _ptr(out["status"]),
+            _stream_ptr(stream)))
+        return out
 
 class Mlp:
     """The root-proposal network on the device (see include/ftp.h)."""

@@ -24,6 +24,7 @@
 namespace ftp {
 // kernels (defined in the other translation units)
 __global__ void k_prep_stats(LcInfo*, const double*, const double*, const double*);
+__global__ void k_sp_combine(LcInfo*, int, const double2*, int);
 template <typename R>
 __global__ void k_prep_points(const LcInfo*, int64_t, const int64_t*, int64_t, const double*, const double*,
                               const double*, PointRec<R>*, PointRec<R>*, unsigned int*);
@@ -307,6 +308,7 @@ struct ftp_plan {
   DevBuf pw, py, tile_count, tile_off, cursor, block_sums,
       total, bucket, grids, fft_tab, fft_items, counters, stats_out, rec;
   int64_t pair_chunk = (int64_t)1 << 20;  // pairs per assemble/root/score round
+  int n_band = 0;                          // > 0: band templates for shared-phase calls
   // host staging (kept alive until the uploads completed)
   std::vector<LcInfo> h_lc;
   std::vector<int64_t> h_obs_off, h_freq_off, h_gtb;
@@ -469,7 +471,7 @@ int plan_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, co
 }
 
 template <typename R>
-int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n_tiles, const double* t,
+int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n_tiles, int shared_bands, const double* t,
              const double* y, const double* sigma, hipStream_t st) {
   using C = typename Cplx<R>::T;
   int rc;
@@ -485,6 +487,8 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
   if ((rc = P->grids.ensure(sizeof(C) * n_grid))) return rc;
   LcInfo* dl = P->d_lc;
   hipLaunchKernelGGL(k_prep_stats, dim3((unsigned)n_lc), dim3(1024), 0, st, dl, t, y, sigma);
+  if (shared_bands > 0)
+    hipLaunchKernelGGL(k_sp_combine, dim3(1), dim3(64), 0, st, dl, shared_bands, P->alpha.as<double2>(), P->H);
   HIP_TRY(launch_zero_u32(P->tile_count.as<unsigned>(), n_tiles, st));
   HIP_TRY(launch_zero_u32(P->cursor.as<unsigned>(), n_tiles, st));
   const unsigned pblocks = (unsigned)((n_pts + 255) / 256);
@@ -762,7 +766,7 @@ int run_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, con
   const int64_t f0 = freq_off[lc0], n_pairs = freq_off[lc1] - f0;
   hipEvent_t e0 = next_event(P);
   if (e0) HIP_TRY(hipEventRecord(e0, st));
-  if ((rc = run_nfft<R>(P, n_lc, n_pts, n_grid, n_tiles, t + o0, y + o0, sigma + o0, st))) return rc;
+  if ((rc = run_nfft<R>(P, n_lc, n_pts, n_grid, n_tiles, 0, t + o0, y + o0, sigma + o0, st))) return rc;
   hipEvent_t e1 = next_event(P);
   if (e1) HIP_TRY(hipEventRecord(e1, st));
   if (P->lc_chi2_out) HIP_TRY(launch_lc_chi2(P->d_lc, n_lc, P->lc_chi2_out + lc0, st));
@@ -788,6 +792,7 @@ int run_batch(ftp_plan* P, int64_t n_lc, const int64_t* obs_off, const double* t
               double* amp, double* offset, uint8_t* status, double* sums_out, hipStream_t st) {
   int rc;
   if (P->opt.solver == FTP_SOLVER_LEARNED && !P->mlp_loaded && !P->ds_X) return FTP_E_NO_MODEL;
+  if (P->n_band) return FTP_E_OPTION;   // band templates: shared-phase calls only
   // chunk by grid memory
   const size_t esz = P->opt.precision == FTP_FP64 ? 16 : 8;
   int64_t lc0 = 0;
@@ -874,11 +879,27 @@ int ftp_options_default(ftp_options* opt) {
   return FTP_OK;
 }
 
-int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, const ftp_options* opt) {
+}  // extern "C"
+
+namespace {
+// Plan for one template (n_band = 0) or for n_band band templates (c, s of
+// n_band x H, band-major; shared-phase calls).
+int plan_create_impl(ftp_plan** out, int n_band, int H, const double* c, const double* s, const ftp_options* opt) {
   if (!out) return FTP_E_NULL;
   *out = nullptr;
-  int rc = validate_template(H, c, s);
-  if (rc) return rc;
+  int rc;
+  const int nt = n_band > 0 ? n_band : 1;
+  if (!c || !s) return FTP_E_NULL;
+  bool any = false;
+  for (int b = 0; b < nt; ++b) {
+    rc = validate_template(H, c + b * H, s + b * H);
+    if (rc == FTP_OK) any = true;
+    else if (rc != FTP_E_H || n_band == 0) return rc;
+    for (int n = 0; n < H; ++n)
+      if (!std::isfinite(c[b * H + n]) || !std::isfinite(s[b * H + n])) return FTP_E_H;
+  }
+  if (!any) return FTP_E_H;
+  if (H < 1 || H > FTP_MAX_H) return FTP_E_H;
   ftp_options o;
   if (opt) o = *opt; else ftp_options_default(&o);
   if (o.precision != FTP_FP32_SUMS && o.precision != FTP_FP64) return FTP_E_OPTION;
@@ -888,9 +909,10 @@ int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, con
   if (o.solve_waves < 0) return FTP_E_OPTION;
   ftp_plan* P = new ftp_plan();
   P->H = H;
+  P->n_band = n_band;
   P->opt = o;
-  P->c.assign(c, c + H);
-  P->s.assign(s, s + H);
+  P->c.assign(c, c + nt * H);
+  P->s.assign(s, s + nt * H);
   hipError_t e = hipGetDevice(&P->device);
   if (e == hipSuccess) {
     hipDeviceProp_t prop;
@@ -902,8 +924,8 @@ int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, con
     }
   }
   if (e != hipSuccess) { g_last_error = hipGetErrorString(e); delete P; return FTP_E_HIP; }
-  std::vector<double2> al(H);
-  for (int n = 0; n < H; ++n) al[n] = make_double2(0.5 * c[n], 0.5 * s[n]);
+  std::vector<double2> al(nt * H);
+  for (int n = 0; n < nt * H; ++n) al[n] = make_double2(0.5 * c[n], 0.5 * s[n]);
   std::vector<float2> tw32(kTwiddleN);
   std::vector<double2> tw64(kTwiddleN);
   for (int k = 0; k < kTwiddleN; ++k) {
@@ -911,12 +933,12 @@ int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, con
     tw64[k] = make_double2((double)cosl(ang), (double)sinl(ang));
     tw32[k] = make_float2((float)tw64[k].x, (float)tw64[k].y);
   }
-  if ((rc = P->alpha.ensure(sizeof(double2) * H)) || (rc = P->twiddle32.ensure(sizeof(float2) * kTwiddleN)) ||
+  if ((rc = P->alpha.ensure(sizeof(double2) * nt * H)) || (rc = P->twiddle32.ensure(sizeof(float2) * kTwiddleN)) ||
       (rc = P->twiddle64.ensure(sizeof(double2) * kTwiddleN)) || (rc = P->counters.ensure(sizeof(SolveCounters)))) {
     delete P;
     return rc;
   }
-  if (hipMemcpy(P->alpha.p, al.data(), sizeof(double2) * H, hipMemcpyHostToDevice) != hipSuccess ||
+  if (hipMemcpy(P->alpha.p, al.data(), sizeof(double2) * nt * H, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(P->twiddle32.p, tw32.data(), sizeof(float2) * kTwiddleN, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(P->twiddle64.p, tw64.data(), sizeof(double2) * kTwiddleN, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(P->counters.p, 0, sizeof(SolveCounters)) != hipSuccess ||
@@ -927,6 +949,25 @@ int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, con
   }
   *out = P;
   return FTP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ftp_plan_create(ftp_plan** out, int H, const double* c, const double* s, const ftp_options* opt) {
+  if (!out) return FTP_E_NULL;
+  *out = nullptr;
+  int rc = validate_template(H, c, s);
+  if (rc) return rc;
+  return plan_create_impl(out, 0, H, c, s, opt);
+}
+
+int ftp_plan_create_bands(ftp_plan** out, int n_band, int H, const double* c, const double* s,
+                          const ftp_options* opt) {
+  if (!out) return FTP_E_NULL;
+  *out = nullptr;
+  if (n_band < 1 || n_band > kMaxBands) return FTP_E_OPTION;
+  return plan_create_impl(out, n_band, H, c, s, opt);
 }
 
 int ftp_plan_destroy(ftp_plan* P) {
@@ -1011,6 +1052,55 @@ int ftp_periodogram_multiband(ftp_plan* P, int64_t n_band, const int64_t* obs_of
   return FTP_OK;
 }
 
+int ftp_periodogram_shared_phase(ftp_plan* P, const int64_t* obs_off, const double* t, const double* y,
+                                 const double* sigma, const double* offsets, double df, int64_t n_f, double* power,
+                                 double* phase, double* amp, double* offset, uint8_t* status, void* stream) {
+  if (!P || !obs_off || !t || !y || !sigma || !power || !phase || !amp || !offset) return FTP_E_NULL;
+  const int nb = P->n_band;
+  if (nb < 1) return FTP_E_OPTION;
+  if (obs_off[0] != 0) return FTP_E_OFFSETS;
+  for (int b = 0; b < nb; ++b) {
+    if (obs_off[b + 1] < obs_off[b]) return FTP_E_OFFSETS;
+    if (obs_off[b + 1] == obs_off[b]) return FTP_E_NOBS;
+    if (offsets && !std::isfinite(offsets[b])) return FTP_E_OPTION;
+  }
+  int rc = validate_scalars(df, n_f, obs_off[nb]);
+  if (rc) return rc;
+  if (obs_off[nb] > ((int64_t)1 << 30)) return FTP_E_SIZE;
+  if (P->opt.solver == FTP_SOLVER_LEARNED && !P->mlp_loaded) return FTP_E_NO_MODEL;
+  if (n_f > (((int64_t)1 << 40) / nb)) return FTP_E_SIZE;
+  if ((rc = wait_uploads(P))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int64_t> freq_off(nb + 1);
+  std::vector<double> dfs(nb, df);
+  for (int b = 0; b <= nb; ++b) freq_off[b] = (int64_t)b * n_f;
+  int64_t n_grid = 0, n_tiles = 0;
+  if ((rc = plan_chunk(P, 0, nb, obs_off, dfs.data(), freq_off.data(), &n_grid, &n_tiles))) return rc;
+  for (int b = 0; b < nb; ++b) P->h_lc[b].yoff = offsets ? offsets[b] : 0.0;
+  if ((rc = upload_tables(P, nb, st, true))) return rc;
+  hipEvent_t e0 = next_event(P);
+  if (e0) HIP_TRY(hipEventRecord(e0, st));
+  if (P->opt.precision == FTP_FP64)
+    rc = run_nfft<double>(P, nb, obs_off[nb], n_grid, n_tiles, nb, t, y, sigma, st);
+  else
+    rc = run_nfft<float>(P, nb, obs_off[nb], n_grid, n_tiles, nb, t, y, sigma, st);
+  if (rc) return rc;
+  hipEvent_t e1 = next_event(P);
+  if (e1) HIP_TRY(hipEventRecord(e1, st));
+  SolveArgs a = base_args(P, 1, n_f);
+  a.n_band = nb;
+  a.power = power;
+  a.phase = phase;
+  a.amp = amp;
+  a.offset = offset;
+  a.status = status;
+  if ((rc = run_solve(P, a, n_f, st))) return rc;
+  hipEvent_t e2 = next_event(P);
+  if (e2) HIP_TRY(hipEventRecord(e2, st));
+  P->last.n_pairs += (uint64_t)n_f;
+  return FTP_OK;
+}
+
 int ftp_nfft_sums(ftp_plan* P, const double* t, const double* y, const double* sigma, int64_t n_obs, double df,
                   int64_t n_f, double* sums, double* lc_stats, void* stream) {
   if (!P || !t || !y || !sigma || !sums || !lc_stats) return FTP_E_NULL;
@@ -1034,6 +1124,7 @@ int ftp_solve_sums(ftp_plan* P, const double* sums, const double* lc_stats, doub
   if (!(lc_stats[2] > 0.0) || !std::isfinite(lc_stats[0]) || !std::isfinite(lc_stats[1])) return FTP_E_OPTION;
   int rc;
   if (P->opt.solver == FTP_SOLVER_LEARNED && !P->mlp_loaded) return FTP_E_NO_MODEL;
+  if (P->n_band) return FTP_E_OPTION;
   if ((rc = wait_uploads(P))) return rc;
   hipStream_t st = (hipStream_t)stream;
   P->h_lc.assign(1, LcInfo{});
@@ -1196,6 +1287,7 @@ int ftp_learned_dataset(ftp_plan* P, const double* t, const double* y, const dou
   int rc = validate_scalars(df, n_f, n_obs);
   if (rc) return rc;
   if (R < 1 || R > 64) return FTP_E_SIZE;
+  if (P->n_band) return FTP_E_OPTION;
   const int64_t obs_off[2] = {0, n_obs};
   const int64_t freq_off[2] = {0, n_f};
   P->ds_X = X;
@@ -1290,6 +1382,7 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
   int rc = validate_scalars(df, n_f, n_obs);
   if (rc) return rc;
   if (P->opt.solver == FTP_SOLVER_LEARNED && !P->mlp_loaded) return FTP_E_NO_MODEL;
+  if (P->n_band) return FTP_E_OPTION;
   char key[256];
   if ((rc = ftp_plan_tune_key(P, key, (int)sizeof(key)))) return rc;
   if (cache_path && !(flags & FTP_TUNE_FORCE)) {

@@ -28,11 +28,17 @@ struct LcInfo {
   int lp[2][kMaxPasses];   // log2 sizes of the FFT passes (largest stride first)
   int msp;                 // kernel half-width in cells
   int pad0;
+  double yoff;             // fixed offset subtracted from y (shared-phase bands)
   // filled on the device
   double tref, ybar, yy, inv_sqrt_yy, winv;
+  double tmin, tmax;
+  double wsum;             // sum of this lightcurve's normalised weights (1, or a band's share)
+  double mm_scale;         // shared-phase: sum_k wsum_k sum_n |alpha^(k)_n|^2 (0 otherwise)
   int wmode;               // 0: sigma^-2 weights, 1: uniform (all sigma = 0)
   int status;              // FTP_LC_* bits
 };
+
+constexpr int kMaxBands = 16;         // bands of a shared-phase plan
 
 // Per-lightcurve status bits (device side).
 enum : int {

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const 
   int nzero = 0, bad = 0;
 #pragma unroll 1
   for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
-    const double ti = t[b + i], yi = y[b + i], si = sigma[b + i];
+    const double ti = t[b + i], yi = y[b + i] - L.yoff, si = sigma[b + i];
     if (!isfinite(ti) || !isfinite(yi) || !isfinite(si) || si < 0.0) bad = 1;
     if (si == 0.0) {
       nzero++;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const 
   for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
       const double si = sigma[b + i];
       const double w = (wmode ? 1.0 : 1.0 / (si * si)) * winv;
-      const double d = y[b + i] - ybar;
+      const double d = y[b + i] - L.yoff - ybar;
       syy += w * d * d;
     }
   }
@@ -156,6 +156,10 @@ __global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const 
   if (status == 0 && (!(yy > 0.0 && isfinite(yy)) || ymin == ymax)) status |= LC_ZERO_VAR;
   if (threadIdx.x == 0) {
     L.tref = 0.5 * (tmin + tmax);
+    L.tmin = tmin;
+    L.tmax = tmax;
+    L.wsum = 1.0;
+    L.mm_scale = 0.0;
     L.ybar = ybar;
     L.yy = yy;
     L.inv_sqrt_yy = (status == 0) ? 1.0 / sqrt(yy) : 0.0;
@@ -176,6 +180,57 @@ __device__ __forceinline__ void tile_span(int cell, int msp, int log2n, int& t0,
   t1 = hi / kTileCells;
   if (t1 == t0) t1 = -1;
   (void)ntile;
+}
+
+// Shared-phase bands (Appendix A): the per-band statistics of k_prep_stats
+// combined into the object's, written back to every band so that the grids
+// carry weights normalised over all bands, the common weighted mean and
+// variance, and one reference time.  Band k's share of the weights is
+// S_k / S with S_k = sum sigma^-2 over the band (its count with unit
+// weights); ybar = sum S_k ybar_k / S; YY = sum (S_k / S)(YY_k + (ybar_k -
+// ybar)^2).  A band with bad input, or bands mixing unit and sigma weights,
+// reject the object; a band of constant y is fine on its own.  Band 0 also
+// receives mm_scale = sum_k (S_k / S) sum_n |alpha^(k)_n|^2, the scale of the
+// degeneracy test.  One thread.
+__global__ void k_sp_combine(LcInfo* lcs, int n_band, const double2* alpha, int H) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int bad = 0;
+  double S = 0.0, sy = 0.0, tmin = INFINITY, tmax = -INFINITY;
+  for (int k = 0; k < n_band; ++k) {
+    const LcInfo& L = lcs[k];
+    if (L.status & (LC_BAD_INPUT | LC_MIXED_SIGMA)) bad = 1;
+    if (L.wmode != lcs[0].wmode) bad = 1;
+    const double Sk = 1.0 / L.winv;
+    S += Sk;
+    sy += Sk * L.ybar;
+    tmin = fmin(tmin, L.tmin);
+    tmax = fmax(tmax, L.tmax);
+  }
+  const double ybar = sy / S;
+  double yy = 0.0, msc = 0.0;
+  for (int k = 0; k < n_band; ++k) {
+    const LcInfo& L = lcs[k];
+    const double f = (1.0 / L.winv) / S;
+    const double d = L.ybar - ybar;
+    yy += f * (L.yy + d * d);
+    double a2 = 0.0;
+    for (int n = 0; n < H; ++n) a2 += alpha[k * H + n].x * alpha[k * H + n].x + alpha[k * H + n].y * alpha[k * H + n].y;
+    msc += f * a2;
+  }
+  int status = bad ? LC_BAD_INPUT : 0;
+  if (!bad && !(yy > 0.0 && isfinite(yy))) status = LC_ZERO_VAR;
+  for (int k = 0; k < n_band; ++k) {
+    LcInfo& L = lcs[k];
+    const double f = (1.0 / L.winv) / S;
+    L.wsum = f;
+    L.winv = 1.0 / S;
+    L.ybar = ybar;
+    L.yy = yy;
+    L.inv_sqrt_yy = status == 0 ? 1.0 / sqrt(yy) : 0.0;
+    L.tref = 0.5 * (tmin + tmax);
+    L.status = status;
+    L.mm_scale = k == 0 ? msc : 0.0;
+  }
 }
 
 // Per-workgroup aggregation of tile counts: an LDS open-addressing table keyed
@@ -234,7 +289,7 @@ __global__ __launch_bounds__(256) void k_prep_points(const LcInfo* __restrict__ 
     } else {
       const double si = sigma[i];
       const double w = (L.wmode ? 1.0 : 1.0 / (si * si)) * L.winv;
-      const double gval[2] = {w, w * (y[i] - L.ybar) * L.inv_sqrt_yy};
+      const double gval[2] = {w, w * (y[i] - L.yoff - L.ybar) * L.inv_sqrt_yy};
       // x = df (t - tref) in double-double, reduced mod 1
       double dh, dl;
       two_sum(t[i], -L.tref, dh, dl);

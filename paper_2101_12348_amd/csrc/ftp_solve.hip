@@ -283,14 +283,18 @@ __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, 
 
 // ------------------------------------------------------------- assemble
 
-__host__ __device__ inline size_t asm_lds_bytes(int H) {
+__host__ __device__ inline size_t asm_lds_bytes(int H, int nb) {
   const int K = 3 * H - 1, D = 2 * K;
-  return (size_t)(2 * ((3 * H + 1) + (2 * H + 1) + (H + 1) + (K + 1) + 4 * (D + 1) + H)) * sizeof(double);
+  return (size_t)(2 * ((3 * H + 1) + (2 * H + 1) + (H + 1) + (K + 1) + 4 * (D + 1) + H)) * sizeof(double) +
+         (size_t)nb * (3 * H + (2 * H + 1) + H + 1) * sizeof(double2);
 }
 
-struct AsmLayout { FreqWork W; double2* hb[2]; double2* vb[2]; };
+// W: per-pair work arrays; hb, vb: Horner buffers; shared phase: Zb (band
+// sums, nb x 3H), T (template products, nb x (2H + 1)), alb (templates,
+// nb x H), wsb (the bands' weight shares, nb).
+struct AsmLayout { FreqWork W; double2* hb[2]; double2* vb[2]; double2* Zb; double2* T; double2* alb; double2* wsb; };
 
-__device__ __forceinline__ AsmLayout asm_layout(double* sm, int H) {
+__device__ __forceinline__ AsmLayout asm_layout(double* sm, int H, int nb) {
   const int K = 3 * H - 1, D = 2 * K;
   AsmLayout s;
   double2* q = reinterpret_cast<double2*>(sm);
@@ -302,8 +306,57 @@ __device__ __forceinline__ AsmLayout asm_layout(double* sm, int H) {
   s.hb[1] = q; q += D + 1;
   s.vb[0] = q; q += D + 1;
   s.vb[1] = q; q += D + 1;
-  s.W.al = q;
+  s.W.al = q; q += H;
+  s.Zb = q; q += nb * 3 * H;
+  s.T = q; q += nb * (2 * H + 1);
+  s.alb = q; q += nb * H;
+  s.wsb = q;
   return s;
+}
+
+// Shared-phase bands (Appendix A): trig coefficients of MM and YM from the
+// sums of every band.  With Z^b_n (weights normalised over all bands, Z^b_0 =
+// W_b the band's share) and Zy^b_n:
+//   B_n = sum_b alpha^b_n conj(Z^b_n)            (psi^n coefficient of Mbar),
+//   eta_n = sum_b alpha^b_n conj(Zy^b_n),
+//   mu_e = sum_b conj(Z^b_e) T^b_e - C_e,
+// T^b_e = sum_{n+m=e} alpha^b_n alpha^b_m + 2 sum_{n-m=e} alpha^b_n conj(alpha^b_m)
+// (T^b_0 = 2 sum_n |alpha^b_n|^2) the band's sum of M^2, and C_e the same
+// products of B (Mbar^2).  One band reduces to assemble_poly.  W.Z[1..H]
+// receive conj(B_n), which the scoring uses with unit alpha for Mbar.
+__device__ __forceinline__ void assemble_shared(const AsmLayout& S, int nb, int H, int lane) {
+  const FreqWork& W = S.W;
+  for (int q = lane; q < 2 * H; q += 64) {
+    const int n = (q % H) + 1;
+    const bool isy = q >= H;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int b = 0; b < nb; ++b) {
+      const double2 z = S.Zb[b * 3 * H + (isy ? 2 * H + n - 1 : n - 1)];
+      acc = cadd(acc, cmul(S.alb[b * H + n - 1], cconj(z)));
+    }
+    if (isy) W.eta[n] = acc;
+    else W.Z[n] = cconj(acc);
+  }
+  if (lane == 0) W.eta[0] = make_double2(0.0, 0.0);
+  wave_sync();
+  for (int e = lane; e <= 2 * H; e += 64) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int b = 0; b < nb; ++b) {
+      const double2 ze = e == 0 ? S.wsb[b] : S.Zb[b * 3 * H + e - 1];
+      acc = cadd(acc, cmul(cconj(ze), S.T[b * (2 * H + 1) + e]));
+    }
+    double2 c = make_double2(0.0, 0.0);
+    if (e == 0) {
+      for (int n = 1; n <= H; ++n) c.x += 2.0 * cabs2(W.Z[n]);
+    } else {
+      const int nlo = e - H > 1 ? e - H : 1;
+      const int nhi = e - 1 < H ? e - 1 : H;
+      for (int n = nlo; n <= nhi; ++n) c = cadd(c, cmul(cconj(W.Z[n]), cconj(W.Z[e - n])));
+      for (int n = e + 1; n <= H; ++n) c = cadd(c, cscale(cmul(cconj(W.Z[n]), W.Z[n - e]), 2.0));
+    }
+    W.mu[e] = csub(acc, c);
+  }
+  wave_sync();
 }
 
 // Load the 3H sums of pair pidx (frequency index j of lightcurve L) into W.Z.
@@ -337,9 +390,30 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
   const int lane = wave_lane();
   const int H = a.H, K = 3 * H - 1, D = 2 * K;
   const RecLayout RL(H);
-  AsmLayout S = asm_layout(sma, H);
+  const int nb = a.n_band;
+  AsmLayout S = asm_layout(sma, H, nb);
   const FreqWork& W = S.W;
-  for (int q = lane; q < H; q += 64) S.W.al[q] = a.alpha[q];
+  if (nb == 0) {
+    for (int q = lane; q < H; q += 64) S.W.al[q] = a.alpha[q];
+  } else {
+    for (int q = lane; q < nb * H; q += 64) S.alb[q] = a.alpha[q];
+    for (int b = lane; b < nb; b += 64) S.wsb[b] = make_double2(a.lcs[b].wsum, 0.0);
+    wave_sync();
+    for (int q = lane; q < nb * (2 * H + 1); q += 64) {
+      const int b = q / (2 * H + 1), e = q % (2 * H + 1);
+      const double2* al = S.alb + b * H;
+      double2 acc = make_double2(0.0, 0.0);
+      if (e == 0) {
+        for (int n = 0; n < H; ++n) acc.x += 2.0 * cabs2(al[n]);
+      } else {
+        const int nlo = e - H > 1 ? e - H : 1;
+        const int nhi = e - 1 < H ? e - 1 : H;
+        for (int n = nlo; n <= nhi; ++n) acc = cadd(acc, cmul(al[n - 1], al[e - n - 1]));
+        for (int n = e + 1; n <= H; ++n) acc = cadd(acc, cscale(cmul(al[n - 1], cconj(al[n - e - 1])), 2.0));
+      }
+      S.T[q] = acc;
+    }
+  }
   wave_sync();
   // e^{2 pi i m / 16}, m = lane mod 16: the rotation phases d phi0 are
   // multiples of 2 pi / 16, read from here by lane index
@@ -361,8 +435,22 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
       continue;
     }
     const double ref = ref_cycles(j, L.df, L.tref);
-    load_sums<R>(a, L, pidx, j, W, lane);
-    assemble_poly(W, H, lane);
+    if (nb == 0) {
+      load_sums<R>(a, L, pidx, j, W, lane);
+      assemble_poly(W, H, lane);
+    } else {
+      // every band's sums of this frequency (grids of lightcurves 0..nb-1)
+      const typename Cplx<R>::T* grids = reinterpret_cast<const typename Cplx<R>::T*>(a.grids);
+      for (int q = lane; q < nb * 3 * H; q += 64) {
+        const int b = q / (3 * H), qq = q % (3 * H);
+        const int g = qq < 2 * H ? 0 : 1;
+        const int k = g == 0 ? qq + 1 : qq - 2 * H + 1;
+        S.Zb[q] = gather_mode<R>(a.lcs[b], g, (int64_t)k * j, grids);
+      }
+      wave_sync();
+      assemble_shared(S, nb, H, lane);
+      assemble_r(W, H, lane);
+    }
     double rmax = 0.0, mumax = 0.0, etamax = 0.0;
     for (int d = lane; d <= K; d += 64) rmax = fmax(rmax, sqrt(cabs2(W.r[d])));
     for (int e = lane; e <= 2 * H; e += 64) mumax = fmax(mumax, sqrt(cabs2(W.mu[e])));
@@ -510,9 +598,11 @@ __global__ __launch_bounds__(64) void k_score(SolveArgs a, const double* rec, in
     W.r = q; q += K + 1;
     W.al = q;
   }
-  for (int q = lane; q < H; q += 64) W.al[q] = a.alpha[q];
+  // shared phase: the record holds conj(B_n) in place of Z_n, so unit alpha
+  // gives Mbar; the degeneracy scale comes from the bands' templates
+  for (int q = lane; q < H; q += 64) W.al[q] = a.n_band ? make_double2(1.0, 0.0) : a.alpha[q];
   wave_sync();
-  const double floor_mm = mm_floor(W, H, a.mm_tau);
+  const double floor_mm = a.n_band ? a.mm_tau * a.lcs[0].mm_scale : mm_floor(W, H, a.mm_tau);
   for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
     const int64_t pidx = p0 + w;
     const double* Rr = rec + w * (int64_t)RL.stride;
@@ -684,7 +774,7 @@ hipError_t launch_qr(int H, double* rec, int stride, int64_t np, const int64_t* 
 
 hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64_t p0, int64_t np, int waves,
                            hipStream_t st) {
-  const size_t lds = asm_lds_bytes(a.H);
+  const size_t lds = asm_lds_bytes(a.H, a.n_band);
   if (precision == 1)
     hipLaunchKernelGGL(k_assemble<double>, dim3((unsigned)waves), dim3(64), lds, st, a, rec, p0, np);
   else

@@ -14,7 +14,8 @@ struct SolveArgs {
   int64_t total;                 // number of pairs
   const void* grids;             // float2 or double2 grids
   const double* sums_in;         // optional: per pair 3H complex sums (see gather)
-  const double2* alpha;          // template alpha_n, n = 1..H
+  const double2* alpha;          // template alpha_n, n = 1..H (shared phase: n_band x H, band-major)
+  int n_band;                    // 0: single band; > 0: shared-phase bands (lcs[0..n_band))
   int H;
   int flags;
   double mm_tau;                 // degenerate if MM <= mm_tau * sum|alpha|^2 at every candidate
@@ -191,6 +192,8 @@ struct FreqWork {
 //   YM(psi) = sum_k a_k conj(Zy_k) psi^k + c.c.   (YC~_k = conj(Zy_k)),
 //   R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta = sum_d r_d psi^d,
 //   r_d = i sum_k (3k - d) mu_{d-k} eta_k   (Eq. finalpoly with p = -i psi^K R).
+__device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane);
+
 __device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane) {
   const int K = 3 * H - 1;
   for (int e = lane; e <= 2 * H; e += 64) {
@@ -219,6 +222,13 @@ __device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane
     W.eta[k] = k == 0 ? make_double2(0.0, 0.0) : cmul(W.al[k - 1], cconj(W.Z[2 * H + k]));
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier();
+  assemble_r(W, H, lane);
+}
+
+// r_d, d = 0..K, of R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta from the trig
+// coefficients mu_e of MM and eta_k of YM (Eq. finalpoly as a trig polynomial).
+__device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane) {
+  const int K = 3 * H - 1;
   for (int d = lane; d <= K; d += 64) {
     double2 acc = make_double2(0.0, 0.0);
     for (int k = -H; k <= H; ++k) {

@@ -27,7 +27,7 @@ __all__ = [
     "eval_template", "cadence_uniform", "cadence_nightly",
     "frequency_grid", "small_fp64_case", "single_long_case", "ragged_batch_case",
     "learned_train_lightcurves", "learned_heldout_lightcurves", "large_case", "single_long_template",
-    "learned_template", "h_sweep_case", "multiband_case",
+    "learned_template", "h_sweep_case", "multiband_case", "shared_phase_case",
     "tiny_case", "WORKLOADS",
 ]
 
@@ -303,6 +303,33 @@ def multiband_case(seed: int = SEED0 + 6, n_band: int = 5, n_obs: int = 2000, ba
     t_all = np.concatenate([b[0] for b in bands])
     df, n_f = frequency_grid(t_all, 10.0)
     return tmpl, bands, df, n_f, 1.0 / period
+
+
+def shared_phase_case(seed: int = SEED0 + 7, n_band: int = 5, n_obs: int = 2000, baseline: float = 1000.0,
+                      H: int = 6):
+    """One variable in n_band bands whose shapes differ per band (the model of
+    the shared-phase multi-band periodogram, Appendix A): a sawtooth-like
+    template per band (own harmonic phases), one period, phase and amplitude
+    for all bands, band offsets lambda_k = 0.3 k - 0.5, per-band noise sigma ~
+    U(0.05, 0.2) times 1.0, 0.6, 0.5, 0.6, 0.9 (cycled), nightly cadences over
+    the baseline, df from the longest band span and f_max = 10/day.  Returns
+    (templates, bands [(t, y, sigma)], offsets, df, n_f, f0)."""
+    rng = np.random.default_rng(seed)
+    templates = [template_sawtooth(H, rng) for _ in range(n_band)]
+    period = float(np.exp(rng.uniform(np.log(0.2), np.log(50.0))))
+    phi = float(rng.uniform(0.0, 2.0 * np.pi))
+    lam = 0.3 * np.arange(n_band) - 0.5
+    noise = [1.0, 0.6, 0.5, 0.6, 0.9]
+    bands = []
+    for k in range(n_band):
+        t = cadence_nightly(rng, n_obs, baseline)
+        sigma = rng.uniform(0.05, 0.2, n_obs) * noise[k % 5]
+        y = 0.4 * eval_template(templates[k], 2 * np.pi * t / period - phi) + 0.2 + lam[k] + \
+            sigma * rng.standard_normal(n_obs)
+        bands.append((t, y, sigma))
+    t_all = np.concatenate([b[0] for b in bands])
+    df, n_f = frequency_grid(t_all, 10.0)
+    return templates, bands, lam, df, n_f, 1.0 / period
 
 
 def h_sweep_case(H: int, seed: int = SEED0 + 5, n_obs: int = 10_000):

@@ -80,6 +80,15 @@ def test_host_validation_without_device():
     assert lib.ftp_plan_create(ctypes.byref(h), 3, vp(c), vp(s), ctypes.byref(opt)) == -9
     assert lib.ftp_periodogram(None, None, None, None, 10, 0.1, 10, None, None, None, None, None, None) == -1
     assert lib.ftp_plan_destroy(None) == -1
+    # bands plans: band count, all-zero or non-finite templates
+    cb, sb = np.zeros((2, 3)), np.zeros((2, 3))
+    assert lib.ftp_plan_create_bands(ctypes.byref(h), 0, 3, vp(cb), vp(sb), None) == -9
+    assert lib.ftp_plan_create_bands(ctypes.byref(h), 17, 3, vp(np.ones(51)), vp(np.ones(51)), None) == -9
+    assert lib.ftp_plan_create_bands(ctypes.byref(h), 2, 3, vp(cb), vp(sb), None) == -2
+    cb[1, 0] = np.inf
+    assert lib.ftp_plan_create_bands(ctypes.byref(h), 2, 3, vp(cb), vp(sb), None) == -2
+    assert lib.ftp_periodogram_shared_phase(None, None, None, None, None, None, 0.1, 10, None, None, None,
+                                            None, None, None) == -1
 
 
 def test_tuning_cache_file_round_trip(tmp_path):
