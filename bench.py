@@ -218,6 +218,44 @@ def bench_multiband(args):
                       "unit": "band x frequency pairs/s", "injected_f": f0, "solvers": res}))
 
 
+def bench_shared_phase(args):
+    """Shared-phase multi-band periodogram (Appendix A) of a five-band object
+    with a template per band (2000 observations per band, N_f ~ 5e4):
+    frequencies per second (each frequency one root solve over all bands),
+    sampled against the oracle."""
+    import numpy as np
+    import paper_2101_12348_amd as F
+    from synthetic import shared_phase_case
+    tms, bands, lam, df, n_f, f0 = shared_phase_case()
+    H = max(len(tm.c) for tm in tms)
+    res = {}
+    for name, sv in (("uniform", F.FTP_SOLVER_UNIFORM), ("aberth", F.FTP_SOLVER_ABERTH),
+                     ("plain", F.FTP_SOLVER_PLAIN)):
+        pl = F.BandsPlan([(tm.c, tm.s) for tm in tms], solver=sv)
+        if not args.no_autotune:
+            # launch shapes of a single-band plan of the same H and solver
+            sp = F.Plan(tms[0].c, tms[0].s, solver=sv)
+            shapes, _ = sp.autotune(*bands[0], df, n_f, cache_path=args.tune_cache, force=args.retune)
+            sp.close()
+            pl.set_tuning(**shapes)
+        holder = {}
+        ms = _time_calls(lambda: holder.update(o=pl.periodogram_shared_phase(bands, df, n_f, offsets=lam)),
+                         args.steps, args.warmup)
+        g = holder["o"]["power"].cpu().numpy()
+        d = None
+        if not args.no_cpu_baseline:
+            from oracle import ftp_oracle as O
+            js = np.unique(np.linspace(1, n_f, 40).astype(np.int64))
+            r = O.shared_phase_periodogram(bands, [(tm.c, tm.s) for tm in tms], df, freq_index=js, offsets=lam)
+            d = float(np.max(np.abs(g[js - 1] - r["power"])))
+        res[name] = {"value": n_f / (ms * 1e-3), "band_pairs_per_s": len(bands) * n_f / (ms * 1e-3),
+                     "ms_per_call": ms, "max_abs_dP_sampled": d, "best_f": (int(np.argmax(g)) + 1) * df}
+        pl.close()
+    print(json.dumps({"workload": f"shared-phase multi-band: {len(bands)} bands x 2000 obs, a template per band, "
+                                  f"T=1000 d, H={H}, N_f={n_f}",
+                      "unit": "frequencies/s", "injected_f": f0, "solvers": res}))
+
+
 def bench_h_sweep(args):
     """H = 1..11 at N_f ~ 5e4 (one single-long-like lightcurve per H): time
     per periodogram for the plain, uniform-start and Aberth solvers."""
@@ -261,7 +299,8 @@ def main():
                     help="launch-shape cache read (and, on a miss, written) by the autotuner")
     ap.add_argument("--retune", action="store_true",
                     help="measure the launch shapes even when the cache has them (and store the result)")
-    ap.add_argument("--workload", default="single_long", choices=["single_long", "ragged", "h_sweep", "multiband"],
+    ap.add_argument("--workload", default="single_long", choices=["single_long", "ragged", "h_sweep", "multiband",
+                                                               "shared_phase"],
                     help="single_long: the reported line; ragged: the 4096-lightcurve batch (H = 4); "
                          "h_sweep: H = 1..11 at N_f ~ 5e4 (extra measurements, one JSON line each)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -270,7 +309,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(lightcurves and frequency slices shard without communication; see the design notes).",
+              "(lightcurves and frequency slices shard without communication).",
               file=sys.stderr)
         sys.exit(2)
 
@@ -285,6 +324,8 @@ def main():
         return bench_h_sweep(args)
     if args.workload == "multiband":
         return bench_multiband(args)
+    if args.workload == "shared_phase":
+        return bench_shared_phase(args)
 
     dev = torch.device("cuda:0")
     tmpl, lc = single_long_case()

@@ -108,62 +108,106 @@ __device__ int sturm_count_unit(const double* g, int D, double* ch, double* tmp,
   return vm - vp;
 }
 
-// Distinct real roots of the degree-D polynomial g (LDS, g[D] != 0) on the
-// whole real line, D + 1 <= 64: the Sturm sequence P_0 = g, P_1 = g',
-// P_q = -rem(P_{q-2}, P_{q-1}) (each scaled to max |coefficient| = 1) is formed
-// in registers, lane c holding coefficient c, the shift by one power of x
-// being a DPP lane shift.  Every member of a generic sequence has degree
-// D - q, so its signs at +inf and -inf are those of its leading coefficient
-// (times (-1)^(D - q) at -inf) and the count V(-inf) - V(+inf) accumulates as
-// the members are formed.  Returns -1 under the same ill-determination tests
-// as the LDS form (vanishing remainder, or a leading term lost to cancellation).
-__device__ int sturm_count_line_reg(const double* g, int D, int lane) {
-  const double gv = lane <= D ? g[lane] : 0.0;
+// max |v| over the wavefront from the high words (sign cleared) of the
+// doubles: the high word of |v| orders like |v|, so this is the maximum with
+// its low word cleared (relative error below 2^-20, never above the maximum).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) { return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false); }
+__device__ __forceinline__ double wave_max_abs_hi(double v) {
+  int h = (int)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffff;
+  h = max(h, dpp_i<0xB1>(h));
+  h = max(h, dpp_i<0x4E>(h));
+  h = max(h, dpp_i<0x141>(h));
+  h = max(h, dpp_i<0x140>(h));
+  h = max(max(__builtin_amdgcn_readlane(h, 0), __builtin_amdgcn_readlane(h, 16)),
+          max(__builtin_amdgcn_readlane(h, 32), __builtin_amdgcn_readlane(h, 48)));
+  return __longlong_as_double((long long)((unsigned long long)(unsigned)h << 32));
+}
+
+// Sturm sequence of a degree-D polynomial g over the whole real line, D + 1
+// <= 64, in registers: P_0 = g, P_1 = g', P_q = -rem(P_{q-2}, P_{q-1}), each
+// member scaled to max |coefficient| ~ 1, lane c holding coefficient c (the
+// shift by one power of x is a DPP lane shift).  Every member of a generic
+// sequence has degree D - q, so its signs at +inf and -inf are those of its
+// leading coefficient (times (-1)^(D - q) at -inf), and the count V(-inf) -
+// V(+inf) accumulates as the members are formed.  `ok` drops when a remainder
+// vanishes (a gcd of positive degree: repeated or nearly repeated roots) or
+// loses its leading term to cancellation: the count is then not trusted.
+// A, B: the last two members; al, bl: their leading coefficients (uniform).
+struct SturmChain {
+  double A, B, al, bl;
+  int sp, sm, vp, vm;
+  bool ok;
+};
+
+__device__ __forceinline__ SturmChain sturm_begin(double gv, int D, int lane) {
+  SturmChain c;
   const double gnext = lane_shl1(gv);   // g[lane + 1], taken with every lane active
   const double dv = lane < D ? (lane + 1) * gnext : 0.0;
   const double ma = wave_max(fabs(gv)), mb = wave_max(fabs(dv));
-  if (!(ma > 0.0) || !(mb > 0.0)) return -1;
+  c.ok = ma > 0.0 && mb > 0.0;
   const double ima = 1.0 / ma, imb = 1.0 / mb;
-  double A = gv * ima, B = dv * imb;
-  // leading coefficients of A and B, carried as scalars from step to step
-  double al = lrdlane(gv, D) * ima;
-  double bl = lrdlane(dv, D - 1) * imb;
-  // signs of P_0 and P_1 at +inf (sp) and -inf (sm)
-  int sp = al > 0.0 ? 1 : -1;
-  int sm = (D & 1) ? -sp : sp;
-  int vp = 0, vm = 0;
-  {
-    const int tp = bl > 0.0 ? 1 : -1;
-    const int tm = ((D - 1) & 1) ? -tp : tp;
-    vp += tp != sp;
-    vm += tm != sm;
-    sp = tp;
-    sm = tm;
+  c.A = gv * ima;
+  c.B = dv * imb;
+  c.al = lrdlane(gv, D) * ima;
+  c.bl = lrdlane(dv, D - 1) * imb;
+  c.sp = c.al > 0.0 ? 1 : -1;
+  c.sm = (D & 1) ? -c.sp : c.sp;
+  c.vp = 0;
+  c.vm = 0;
+  const int tp = c.bl > 0.0 ? 1 : -1;
+  const int tm = ((D - 1) & 1) ? -tp : tp;
+  c.vp += tp != c.sp;
+  c.vm += tm != c.sm;
+  c.sp = tp;
+  c.sm = tm;
+  return c;
+}
+
+// Member q (2 <= q <= D) from the last two.  Branch-free, so that two chains
+// stepped side by side interleave; a chain that is no longer ok keeps
+// stepping on values that are then ignored.
+__device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane) {
+  const int db = D - q + 1;
+  const double ibl = fast_rcp_d(c.bl);
+  const double q1 = c.al * ibl;
+  double t = c.A - q1 * lane_shr1(c.B);
+  const double q0 = lrdlane(t, db) * ibl;
+  t = lane < db ? t - q0 * c.B : 0.0;
+  const double mr = wave_max_abs_hi(t);
+  const double lead = lrdlane(t, db - 1);
+  c.ok = c.ok && mr > 1e-12 && fabs(lead) > 1e-13 * mr;
+  // P_q = -t / mr: leading sign -sgn(lead), degree D - q
+  const int tp = lead > 0.0 ? -1 : 1;
+  const int tm = ((D - q) & 1) ? -tp : tp;
+  c.vp += tp != c.sp;
+  c.vm += tm != c.sm;
+  c.sp = tp;
+  c.sm = tm;
+  const double inv = -fast_rcp_d(mr);
+  c.A = c.B;
+  c.al = c.bl;
+  c.B = t * inv;
+  c.bl = lead * inv;
+}
+
+// Distinct real roots of g (coefficient `gv` in lane c, g[D] != 0), or -1.
+__device__ int sturm_count_line_reg(double gv, int D, int lane) {
+  SturmChain c = sturm_begin(gv, D, lane);
+  for (int q = 2; q <= D && c.ok; ++q) sturm_step(c, D, q, lane);
+  return c.ok ? c.vm - c.vp : -1;
+}
+
+// The same for two polynomials at once (two frequencies of one wavefront).
+__device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int& ca, int& cb) {
+  SturmChain a = sturm_begin(ga, D, lane);
+  SturmChain b = sturm_begin(gb, D, lane);
+  for (int q = 2; q <= D && (a.ok || b.ok); ++q) {
+    sturm_step(a, D, q, lane);
+    sturm_step(b, D, q, lane);
   }
-  for (int q = 2; q <= D; ++q) {
-    const int db = D - q + 1;
-    const double ibl = fast_rcp_d(bl);
-    const double q1 = al * ibl;
-    double t = A - q1 * lane_shr1(B);
-    const double q0 = lrdlane(t, db) * ibl;
-    t = lane < db ? t - q0 * B : 0.0;
-    const double mr = wave_max(fabs(t));
-    const double lead = lrdlane(t, db - 1);
-    if (!(mr > 1e-12) || !(fabs(lead) > 1e-13 * mr)) return -1;
-    // P_q = -t / mr: leading sign -sgn(lead), degree D - q
-    const int tp = lead > 0.0 ? -1 : 1;
-    const int tm = ((D - q) & 1) ? -tp : tp;
-    vp += tp != sp;
-    vm += tm != sm;
-    sp = tp;
-    sm = tm;
-    const double inv = -fast_rcp_d(mr);
-    A = B;
-    al = bl;
-    B = t * inv;
-    bl = lead * inv;
-  }
-  return vm - vp;
+  ca = a.ok ? a.vm - a.vp : -1;
+  cb = b.ok ? b.vm - b.vp : -1;
 }
 
 struct LearnArgs {
@@ -221,7 +265,7 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
     if (D < 64) {
       // real roots of f on the whole line = real phases other than phi0 + pi,
       // where R does not vanish (f has full degree D)
-      cnt = sturm_count_line_reg(fl, D, lane);
+      cnt = sturm_count_line_reg(lane <= D ? fl[lane] : 0.0, D, lane);
     } else {
       const int c1 = sturm_count_unit(fl, D, ch, tmp, lane);
       if (c1 >= 0) {
@@ -265,17 +309,21 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
           }
         }
         if ((it >= 4 && it <= 8) || it == 10 || it == 12) {
+          const unsigned long long cm = __ballot(conv);
+          // fewer converged lanes than the count cannot reach it (the last
+          // check always runs: its roots seed the fallback)
+          if (it < 12 && __popcll(cm) < cnt) continue;
           // distinct converged roots: merge those closer than 1e-8 rad,
           // keeping the lowest lane
           thw = fmod(th, kTwoPi);
           if (thw < 0.0) thw += kTwoPi;
-          const unsigned long long cm = __ballot(conv);
           uniq = conv;
-          for (int jj = 0; jj < NS; ++jj) {
+          for (unsigned long long m = cm; m; m &= m - 1ull) {
+            const int jj = __builtin_ctzll(m);
             const double tj = lrdlane(thw, jj);
             double dd = fabs(tj - thw);
             dd = fmin(dd, kTwoPi - dd);
-            if (((cm >> jj) & 1ull) && jj < lane && dd < 1e-8) uniq = false;
+            if (jj < lane && dd < 1e-8) uniq = false;
           }
           um = __ballot(uniq && lane < NS);
           nu = __popcll(um);
@@ -312,8 +360,153 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
   }
 }
 
+// Two frequencies per wavefront (4H <= 32 starts, D < 64): frequencies 2b and
+// 2b + 1 of the list.  Their two Sturm chains are stepped side by side (the
+// chains are serial, so a second independent one fills the latency of the
+// first), then Newton runs on both at once, lanes 0..31 for the first and
+// 32..63 for the second, each half with the starts, merge and stop rule of the
+// one-frequency kernel; a half that has reached its count is frozen while the
+// other goes on.
+__global__ __launch_bounds__(64) void k_newton_sturm2(SolveArgs a, LearnArgs L) {
+  extern __shared__ double sml[];
+  const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
+  const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = 2 * S;
+  const RecLayout RL(H);
+  double2* rr = reinterpret_cast<double2*>(sml);   // r_d of both frequencies
+  FreqWork W;
+  W.r = rr + half * (K + 1);
+  const unsigned long long lo32 = 0xffffffffull;
+  const unsigned long long hmask = half ? ~lo32 : lo32;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  unsigned long long iters_acc = 0, roots_acc = 0, fb_acc = 0;
+  for (int64_t w0 = 2 * (int64_t)blockIdx.x; w0 < L.np; w0 += 2 * (int64_t)gridDim.x) {
+    const bool hasB = w0 + 1 < L.np;
+    double* RA = L.rec + w0 * (int64_t)RL.stride;
+    double* RB = hasB ? RA + RL.stride : RA;
+    const int stA = (int)RA[RL.meta + M_STATUS];
+    const int stB = hasB ? (int)RB[RL.meta + M_STATUS] : ST_BAD_LC;
+    const bool actA = stA != ST_BAD_LC && stA != ST_CONSTANT;
+    const bool actB = stB != ST_BAD_LC && stB != ST_CONSTANT;
+    if (!actA && !actB) continue;
+    double* Rh = half ? RB : RA;            // this lane's frequency
+    const int64_t wh = w0 + half;
+    const bool acth = half ? actB : actA;
+    if (L.flags & 1u) {   // forced fallback
+      if (hl == 0 && acth) {
+        const unsigned slot = atomicAdd(L.fb_count, 1u);
+        L.fb_list[slot] = wh;
+        Rh[RL.meta + M_FALLBACK] = 1.0;
+      }
+      fb_acc += (unsigned long long)actA + (unsigned long long)actB;
+      continue;
+    }
+    for (int d = lane; d < 2 * (K + 1); d += 64) {
+      const int h = d > K ? 1 : 0, dd = d - h * (K + 1);
+      const double* Rs = h ? RB : RA;
+      rr[d] = make_double2(Rs[RL.r + 2 * dd], Rs[RL.r + 2 * dd + 1]);
+    }
+    const double fA = lane <= D ? RA[RL.f + lane] : 0.0;
+    const double fB = lane <= D ? RB[RL.f + lane] : 0.0;
+    lwave_sync();
+    // counts: -2 inactive (no output), -1 ill-determined or below two (to the
+    // fallback without Newton), else the number of distinct real roots
+    int cA, cB;
+    sturm_count_line_reg2(fA, fB, D, lane, cA, cB);
+    if (cA < 2) cA = -1;
+    if (cB < 2) cB = -1;
+    if (!actA) cA = -2;
+    if (!actB) cB = -2;
+    const int cnt = half ? cB : cA;
+    double th = 0.0, thw = 0.0;
+    bool conv = false, uniq = false, live = cnt >= 0 && hl < NS;
+    int its = 0;
+    if (live) {
+      if (L.seeds_out && hl < S) {
+        const float* o = L.seeds_out + wh * 2 * S;
+        th = atan2((double)o[2 * hl + 1], (double)o[2 * hl]) - Rh[RL.meta + M_CANON];
+      } else if (L.seeds_out) {
+        th = kTwoPi * (hl - S + 0.5) / S;
+      } else {
+        th = kTwoPi * (hl + 0.5) / NS;
+      }
+    }
+    bool doneA = cA < 0, doneB = cB < 0;
+    unsigned long long um = 0ull;
+    for (int it = 1; it <= 12 && !(doneA && doneB); ++it) {
+      if (live && !conv) {
+        double Rv, dR;
+        eval_R(W, H, th, Rv, dR);
+        const double step = Rv / dR;
+        if (!(dR != 0.0) || !isfinite(step)) {
+          live = false;
+        } else {
+          const double sc = fmax(-0.5, fmin(0.5, step));
+          th -= sc;
+          ++its;
+          if (fabs(sc) < 1e-12) conv = true;
+        }
+      }
+      if ((it >= 4 && it <= 8) || it == 10 || it == 12) {
+        const unsigned long long cm = __ballot(conv);
+        const bool needA = !doneA && __popcll(cm & lo32) >= cA;
+        const bool needB = !doneB && __popcll(cm >> 32) >= cB;
+        if (!needA && !needB && it < 12) continue;
+        // distinct converged roots of each half (merge closer than 1e-8 rad,
+        // keeping the lowest lane)
+        thw = fmod(th, kTwoPi);
+        if (thw < 0.0) thw += kTwoPi;
+        uniq = conv;
+        for (unsigned long long m = cm; m; m &= m - 1ull) {
+          const int jj = __builtin_ctzll(m);
+          const double tj = lrdlane(thw, jj);
+          double dd = fabs(tj - thw);
+          dd = fmin(dd, kTwoPi - dd);
+          if ((jj >> 5) == half && jj < lane && dd < 1e-8) uniq = false;
+        }
+        um = __ballot(uniq && hl < NS);
+        if (__popcll(um & lo32) == cA) doneA = true;
+        if (__popcll(um >> 32) == cB) doneB = true;
+        if (half ? doneB : doneA) live = false;
+      }
+    }
+    iters_acc += (unsigned long long)wave_sum((double)its);
+    const int nuA = __popcll(um & lo32), nuB = __popcll(um >> 32);
+    const bool okA = cA >= 0 && nuA == cA, okB = cB >= 0 && nuB == cB;
+    const bool ok = half ? okB : okA;
+    const int nu = half ? nuB : nuA;
+    double* cand = Rh + RL.cand;
+    if (cnt != -2 && ok)
+      for (int c = hl; c < D; c += 32) cand[c] = __longlong_as_double(0x7ff8000000000000ll);
+    lwave_sync();
+    // confirmed roots, or the distinct roots found, which start the Aberth
+    // iteration of a fallback frequency
+    if (cnt != -2 && uniq && hl < NS) cand[__popcll(um & hmask & below)] = thw;
+    if (cnt != -2 && !ok && hl == 0) {
+      Rh[RL.meta + M_WARM] = (double)nu;
+      Rh[RL.meta + M_FALLBACK] = 1.0;
+      const unsigned slot = atomicAdd(L.fb_count, 1u);
+      L.fb_list[slot] = wh;
+    }
+    roots_acc += (unsigned long long)((okA ? nuA : 0) + (okB ? nuB : 0));
+    fb_acc += (unsigned long long)((actA && !okA) + (actB && !okB));
+    lwave_sync();
+  }
+  if (lane == 0 && a.counters) {
+    if (iters_acc) atomicAdd(&a.counters->newton_iters, iters_acc);
+    if (roots_acc) atomicAdd(&a.counters->roots_found, roots_acc);
+    if (fb_acc) atomicAdd(&a.counters->fallback, fb_acc);
+  }
+}
+
+bool newton_two_per_wave(int H) { return 4 * H <= 32 && 6 * H - 2 < 64; }
+
 hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st) {
-  hipLaunchKernelGGL(k_newton_sturm, dim3((unsigned)waves), dim3(64), learn_lds_bytes(a.H), st, a, L);
+  if (newton_two_per_wave(a.H)) {
+    const size_t lds = (size_t)4 * (3 * a.H) * sizeof(double);
+    hipLaunchKernelGGL(k_newton_sturm2, dim3((unsigned)waves), dim3(64), lds, st, a, L);
+  } else {
+    hipLaunchKernelGGL(k_newton_sturm, dim3((unsigned)waves), dim3(64), learn_lds_bytes(a.H), st, a, L);
+  }
   return hipGetLastError();
 }
 
