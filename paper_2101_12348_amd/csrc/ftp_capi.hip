@@ -304,7 +304,7 @@ struct ftp_plan {
   std::string arch = "unknown";
   size_t grid_budget = (size_t)8 << 30;   // bytes of NFFT grids per chunk
   // device buffers
-  DevBuf alpha, twiddle32, twiddle64;
+  DevBuf alpha, twiddle32, twiddle64, ctab;
   DevBuf pw, py, tile_count, tile_off, cursor, block_sums,
       total, bucket, grids, fft_tab, fft_items, counters, stats_out, rec;
   int64_t pair_chunk = (int64_t)1 << 20;  // pairs per assemble/root/score round
@@ -454,6 +454,8 @@ int plan_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, co
       L.log2n[g] = log2n;
       L.mc[g] = mmax / 2;
       L.beta[g] = M_PI * (Reff - 0.5) / (msp * Reff);
+      L.dec_a[g] = std::sqrt(L.beta[g] / M_PI);
+      L.dec_b[g] = M_PI * M_PI / ((double)nn * (double)nn * L.beta[g]);
       fft_plan(log2n, P->opt.precision, &L.npass[g], L.lp[g]);
       L.grid_off[g] = goff;
       goff += nn;
@@ -745,6 +747,7 @@ SolveArgs base_args(ftp_plan* P, int64_t n_lc, int64_t n_pairs) {
   a.total = n_pairs;
   a.grids = P->grids.p;
   a.alpha = P->alpha.as<double2>();
+  a.ctab = P->ctab.as<double>();
   a.H = P->H;
   a.flags = (int)P->opt.flags;
   a.mm_tau = P->opt.precision == FTP_FP64 ? 1e-9 : 1e-5;
@@ -882,6 +885,34 @@ int ftp_options_default(ftp_options* opt) {
 }  // extern "C"
 
 namespace {
+// Table of the Cayley map theta = phi0 + 2 atan x for degree D < 64: with
+// u = 1 + i x, v = 1 - i x, the coefficient of x^c in u^j v^(D-j) is i^c N_c(j),
+// N_c(j) = sum_a (-1)^(c-a) C(j, a) C(D-j, c-a) (an integer, |N_c(j)| <= C(D, c)),
+// so f_c = Re(i^c sum_j rho_{j-K} N_c(j)) is rho.x (c even) or rho.y (c odd)
+// against N_c, with the sign of i^c's real or imaginary part.  Stored as
+// T[j (D + 1) + c] = s_c N_c(j), s_c = +1 for c = 0, 3 mod 4 and -1 for 1, 2.
+// Exact integers up to D = 52; the entries of larger D round to doubles.
+std::vector<double> cayley_table(int D) {
+  std::vector<std::vector<int64_t>> C(D + 1, std::vector<int64_t>(D + 1, 0));
+  for (int n = 0; n <= D; ++n) {
+    C[n][0] = 1;
+    for (int k = 1; k <= n; ++k) C[n][k] = C[n - 1][k - 1] + (k <= n - 1 ? C[n - 1][k] : 0);
+  }
+  std::vector<double> T((size_t)(D + 1) * (D + 1));
+  for (int j = 0; j <= D; ++j)
+    for (int c = 0; c <= D; ++c) {
+      int64_t acc = 0;
+      const int a0 = c - (D - j) > 0 ? c - (D - j) : 0, a1 = j < c ? j : c;
+      for (int a = a0; a <= a1; ++a) {
+        const int64_t t = C[j][a] * C[D - j][c - a];
+        acc += ((c - a) & 1) ? -t : t;
+      }
+      const double sgn = (c % 4 == 0 || c % 4 == 3) ? 1.0 : -1.0;
+      T[(size_t)j * (D + 1) + c] = sgn * (double)acc;
+    }
+  return T;
+}
+
 // Plan for one template (n_band = 0) or for n_band band templates (c, s of
 // n_band x H, band-major; shared-phase calls).
 int plan_create_impl(ftp_plan** out, int n_band, int H, const double* c, const double* s, const ftp_options* opt) {
@@ -947,6 +978,19 @@ int plan_create_impl(ftp_plan** out, int n_band, int H, const double* c, const d
     delete P;
     return FTP_E_HIP;
   }
+  const int D = 6 * H - 2;
+  if (D < 64) {
+    std::vector<double> ct = cayley_table(D);
+    if ((rc = P->ctab.ensure(sizeof(double) * ct.size()))) {
+      delete P;
+      return rc;
+    }
+    if (hipMemcpy(P->ctab.p, ct.data(), sizeof(double) * ct.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      g_last_error = "plan setup copy failed";
+      delete P;
+      return FTP_E_HIP;
+    }
+  }
   *out = P;
   return FTP_OK;
 }
@@ -973,7 +1017,7 @@ int ftp_plan_create_bands(ftp_plan** out, int n_band, int H, const double* c, co
 int ftp_plan_destroy(ftp_plan* P) {
   if (!P) return FTP_E_NULL;
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&P->alpha, &P->twiddle32, &P->twiddle64, &P->d_stage,
+  DevBuf* bufs[] = {&P->alpha, &P->twiddle32, &P->twiddle64, &P->ctab, &P->d_stage,
                     &P->pw, &P->py, &P->tile_count, &P->tile_off, &P->cursor,
                     &P->block_sums, &P->total, &P->bucket, &P->grids,
                     &P->counters, &P->stats_out, &P->rec, &P->xfeat, &P->seeds, &P->fb_list,

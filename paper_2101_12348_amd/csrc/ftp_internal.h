@@ -23,6 +23,8 @@ struct LcInfo {
   int64_t tile_base[2];    // first global tile index of each grid
   int64_t mc[2];           // centre mode of each grid
   double beta[2];          // Gaussian exponent per cell^2 of each grid
+  double dec_a[2];         // deconvolution of mode m: dec_a exp(dec_b (m - mc)^2),
+  double dec_b[2];         //   dec_a = sqrt(beta / pi), dec_b = pi^2 / (n^2 beta)
   int log2n[2];
   int npass[2];
   int lp[2][kMaxPasses];   // log2 sizes of the FFT passes (largest stride first)

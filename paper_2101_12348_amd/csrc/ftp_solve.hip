@@ -475,21 +475,33 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
       // rho_d = r_d e^{i d phi0}; homogeneous Horner h_l = u h_{l-1} + rho_{K-l} v^l
       const double cK = rdlane(tab_c, (K * k0) & 15), sK = rdlane(tab_s, (K * k0) & 15);
       if (D < 64) {
-        // lane c holds coefficient c of h and v; multiplying by (1 + i x) or
-        // (1 - i x) takes the coefficient below from the next lower lane
-        double2 h = lane == 0 ? cmul(W.r[K], make_double2(cK, sK)) : make_double2(0.0, 0.0);
-        double2 v = lane == 0 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
-        for (int l = 1; l <= D; ++l) {
-          const int d = K - l;
-          const double2 rd = d >= 0 ? W.r[d] : cconj(W.r[-d]);
-          const int m = (d * k0) & 15;
-          const double2 rho = cmul(rd, make_double2(rdlane(tab_c, m), rdlane(tab_s, m)));
-          const double vpx = lane_shr1(v.x), vpy = lane_shr1(v.y);
-          const double hpx = lane_shr1(h.x), hpy = lane_shr1(h.y);
-          v = make_double2(v.x + vpy, v.y - vpx);
-          h = cadd(make_double2(h.x - hpy, h.y + hpx), cmul(rho, v));
+        // f_c = sum_j (rho_{j-K}.x or .y) T[j][c] with the Cayley-map table
+        // (coefficient c of u^j v^(D-j), u = 1 + i x, v = 1 - i x, divided by
+        // i^c); lane j forms rho_{j-K}, lane c the dot product of column c
+        double* rx = reinterpret_cast<double*>(S.hb[0]);
+        double* ry = rx + (D + 1);
+        {
+          const int d = lane - K;
+          const double ec = __shfl(tab_c, (d * k0) & 15), es = __shfl(tab_s, (d * k0) & 15);
+          if (lane <= D) {
+            const double2 rho = cmul(d >= 0 ? W.r[d] : cconj(W.r[-d]), make_double2(ec, es));
+            rx[lane] = rho.x;
+            ry[lane] = rho.y;
+          }
         }
-        if (lane <= D) Rr[RL.f + lane] = h.x;
+        wave_sync();
+        if (lane <= D) {
+          const double* rc = (lane & 1) ? ry : rx;
+          const double* col = a.ctab + lane;
+          double acc0 = 0.0, acc1 = 0.0;
+          int jx = 0;
+          for (; jx + 1 <= D; jx += 2) {
+            acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
+            acc1 = fma(rc[jx + 1], col[(jx + 1) * (D + 1)], acc1);
+          }
+          if (jx <= D) acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
+          Rr[RL.f + lane] = acc0 + acc1;
+        }
       } else {
         for (int c = lane; c <= D; c += 64) {
           S.hb[0][c] = c == 0 ? cmul(W.r[K], make_double2(cK, sK)) : make_double2(0.0, 0.0);
@@ -583,8 +595,10 @@ __host__ __device__ inline size_t score_lds_bytes(int H) {
   return (size_t)(2 * ((3 * H + 1) + (2 * H + 1) + (H + 1) + (K + 1) + H)) * sizeof(double);
 }
 
-// Scores all candidates of pairs [p0, p0 + np) and writes the outputs.
-__global__ __launch_bounds__(64) void k_score(SolveArgs a, const double* rec, int64_t p0, int64_t np) {
+// Scores all candidates of pairs [p0, p0 + np) and writes the outputs.  Five
+// waves per SIMD (at most 96 VGPRs): latency-bound per-frequency work gains more
+// from the extra wave than it loses to the few spilled registers.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_score(SolveArgs a, const double* rec, int64_t p0, int64_t np) {
   extern __shared__ double sms[];
   const int lane = wave_lane();
   const int H = a.H, K = 3 * H - 1, D = 2 * K;

@@ -15,6 +15,7 @@ struct SolveArgs {
   const void* grids;             // float2 or double2 grids
   const double* sums_in;         // optional: per pair 3H complex sums (see gather)
   const double2* alpha;          // template alpha_n, n = 1..H (shared phase: n_band x H, band-major)
+  const double* ctab;            // Cayley-map table, (D + 1)^2 doubles, D < 64 (see k_assemble)
   int n_band;                    // 0: single band; > 0: shared-phase bands (lcs[0..n_band))
   int H;
   int flags;
@@ -153,14 +154,11 @@ __device__ __forceinline__ int64_t fft_pos(int64_t q, const LcInfo& L, int g) {
 template <typename R>
 __device__ __forceinline__ double2 gather_mode(const LcInfo& L, int g, int64_t m,
                                                const typename Cplx<R>::T* grids) {
-  const int log2n = L.log2n[g];
-  const int64_t n = 1LL << log2n;
+  const int64_t n = 1LL << L.log2n[g];
   const int64_t mp = m - L.mc[g];
-  const int64_t q = ((mp % n) + n) % n;
+  const int64_t q = mp & (n - 1);   // mp mod n (n a power of two)
   const typename Cplx<R>::T v = grids[L.grid_off[g] + fft_pos(q, L, g)];
-  const double beta = L.beta[g];
-  const double nn = (double)n;
-  const double fac = sqrt(beta / kPi) * exp(kPi * kPi * (double)mp * (double)mp / (nn * nn * beta));
+  const double fac = L.dec_a[g] * exp(L.dec_b[g] * (double)mp * (double)mp);
   return make_double2((double)v.x * fac, (double)v.y * fac);
 }
 
