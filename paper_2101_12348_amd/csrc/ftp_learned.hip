@@ -6,8 +6,8 @@
 //     of the Cayley polynomial f(x) (theta = phi0 + 2 atan x): over the whole
 //     real line, or on two half circles, x in (-1, 1] for f and for
 //     x^D f(-1/x) (the map rotated by pi);
-//   * if the count is well determined, 2H network seeds plus 2H evenly spaced
-//     starts (4H evenly spaced starts for the ablation without network) are
+//   * if the count is well determined, 2H network seeds plus evenly spaced
+//     starts (only evenly spaced starts for the ablation without network) are
 //     refined by FP64 Newton on R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta
 //     (Eq. theta2cond written as R(theta) = i e^{-i K theta} p(e^{i theta}));
 //     converged roots closer than 1e-8 rad are merged after iterations 4-8, 10
@@ -15,9 +15,11 @@
 //   * if they do, the Newton roots are the candidate set; otherwise the
 //     frequency goes to the Aberth iteration (then, if that does not
 //     converge, to the companion-matrix solve) through device work lists.
-// For D + 1 <= 64 a single Sturm sequence of f over the whole real line is
-// formed in registers (sturm_count_line_reg); D = 64 (H = 11) uses the LDS
-// form on the two half circles.
+// For H <= 8 a wavefront takes two frequencies (k_newton_sturm2, 32 starts
+// each, at most D); for H = 9..11 one (k_newton_sturm, 4H starts).  For
+// D + 1 <= 64 a single Sturm sequence of f over the whole real line is formed
+// in registers (sturm_count_line_reg); D = 64 (H = 11) uses the LDS form on
+// the two half circles.
 #include "ftp_solve_common.h"
 
 namespace ftp {
@@ -360,17 +362,20 @@ __global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
   }
 }
 
-// Two frequencies per wavefront (4H <= 32 starts, D < 64): frequencies 2b and
-// 2b + 1 of the list.  Their two Sturm chains are stepped side by side (the
-// chains are serial, so a second independent one fills the latency of the
-// first), then Newton runs on both at once, lanes 0..31 for the first and
-// 32..63 for the second, each half with the starts, merge and stop rule of the
-// one-frequency kernel; a half that has reached its count is frozen while the
-// other goes on.
+// Two frequencies per wavefront (H <= 8): frequencies 2b and 2b + 1 of the
+// list.  Their two Sturm chains are stepped side by side (the chains are
+// serial, so a second independent one fills the latency of the first), then
+// Newton runs on both at once, lanes 0..31 for the first and 32..63 for the
+// second, each half with the merge and stop rule of the one-frequency kernel
+// and min(32, D) starts: the 2H network seeds and min(32, D) - 2H evenly
+// spaced phases (all evenly spaced without network).  A half that has reached
+// its count is frozen while the other goes on.
 __global__ __launch_bounds__(64) void k_newton_sturm2(SolveArgs a, LearnArgs L) {
   extern __shared__ double sml[];
   const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
-  const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = 2 * S;
+  // starts per frequency: every lane of the half (at most D: no more real
+  // roots exist, and the candidate slots hold D)
+  const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = D < 32 ? D : 32;
   const RecLayout RL(H);
   double2* rr = reinterpret_cast<double2*>(sml);   // r_d of both frequencies
   FreqWork W;
@@ -425,7 +430,7 @@ __global__ __launch_bounds__(64) void k_newton_sturm2(SolveArgs a, LearnArgs L) 
         const float* o = L.seeds_out + wh * 2 * S;
         th = atan2((double)o[2 * hl + 1], (double)o[2 * hl]) - Rh[RL.meta + M_CANON];
       } else if (L.seeds_out) {
-        th = kTwoPi * (hl - S + 0.5) / S;
+        th = kTwoPi * (hl - S + 0.5) / (NS - S);
       } else {
         th = kTwoPi * (hl + 0.5) / NS;
       }
