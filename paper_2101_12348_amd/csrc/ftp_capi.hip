@@ -61,6 +61,8 @@ struct GemmArgs {
   uint16_t* Cb; int64_t ld_cb;
 };
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
+hipError_t launch_dense(const uint16_t* A, int64_t lda, const uint16_t* W, int ldw, const float* bias, int64_t M,
+                        int N, int Kp, int relu, uint16_t* Yb, float* Yf, int64_t ldy, hipStream_t st);
 hipError_t launch_colsum(const float* G, int64_t M, int N, int64_t ld, float* out, hipStream_t st);
 hipError_t launch_chamfer(const float* out, int64_t B, int Kseeds, const float* roots, const int* nroots, int R,
                           float lam, float* loss_b, float* dout, uint16_t* dout_bf, hipStream_t st);
@@ -166,6 +168,13 @@ struct MlpNet {
   int64_t oW[4], ob[4];
   int nin[4], nout[4];
   DevBuf w32, wbf, grad, am, av, loss;
+  // inference copy of the bf16 weights with each layer's rows zero-padded to
+  // kp[l] (a multiple of 32) for the dense-layer kernel; built when a plan
+  // loads a network whose width is a multiple of 32
+  DevBuf winf;
+  int kp[4] = {0, 0, 0, 0};
+  int64_t oWi[4] = {0, 0, 0, 0};
+  bool dense = false;
   DevBuf xbf, h[3], outf, dout_f, dout_b, dz_f, dz_b[2];
   int64_t cap_batch = 0;
   int64_t step = 0;
@@ -199,7 +208,7 @@ struct MlpNet {
     return FTP_OK;
   }
   void release() {
-    DevBuf* bs[] = {&w32, &wbf, &grad, &am, &av, &loss, &xbf, &h[0], &h[1], &h[2], &outf, &dout_f, &dout_b,
+    DevBuf* bs[] = {&winf, &w32, &wbf, &grad, &am, &av, &loss, &xbf, &h[0], &h[1], &h[2], &outf, &dout_f, &dout_b,
                     &dz_f, &dz_b[0], &dz_b[1]};
     for (DevBuf* b : bs) b->release();
   }
@@ -222,6 +231,45 @@ int mlp_set_weights(MlpNet* N, const float* w) {
   for (int64_t i = 0; i < N->n_params; ++i) b[i] = host_f2bf(w[i]);
   HIP_TRY(hipMemcpy(N->w32.p, w, sizeof(float) * N->n_params, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(N->wbf.p, b.data(), sizeof(uint16_t) * N->n_params, hipMemcpyHostToDevice));
+  return FTP_OK;
+}
+
+// Padded inference weights (see MlpNet::winf) from host FP32 parameters.
+int mlp_build_inference(MlpNet* N, const float* w) {
+  N->dense = N->width % 32 == 0;
+  if (!N->dense) return FTP_OK;
+  int64_t o = 0;
+  for (int l = 0; l < 4; ++l) {
+    N->kp[l] = (N->nin[l] + 31) & ~31;
+    N->oWi[l] = o;
+    o += (int64_t)N->nout[l] * N->kp[l];
+  }
+  std::vector<uint16_t> b((size_t)o, 0);
+  for (int l = 0; l < 4; ++l)
+    for (int n = 0; n < N->nout[l]; ++n)
+      for (int k = 0; k < N->nin[l]; ++k)
+        b[N->oWi[l] + (int64_t)n * N->kp[l] + k] = host_f2bf(w[N->oW[l] + (int64_t)n * N->nin[l] + k]);
+  int rc;
+  if ((rc = N->winf.ensure(sizeof(uint16_t) * (size_t)o))) return rc;
+  HIP_TRY(hipMemcpy(N->winf.p, b.data(), sizeof(uint16_t) * (size_t)o, hipMemcpyHostToDevice));
+  return FTP_OK;
+}
+
+// Inference forward pass with the dense-layer kernel: X (B x kp[0] bf16, row
+// stride ldx, zero-padded), hidden activations into N->h[0..2], FP32 output
+// (row stride dout).  Same rounding points and K order as mlp_forward.
+int mlp_forward_dense(MlpNet* N, const uint16_t* X, int64_t ldx, int64_t B, float* out, hipStream_t st) {
+  const uint16_t* wi = N->winf.as<uint16_t>();
+  const float* w32 = N->w32.as<float>();
+  const uint16_t* in = X;
+  int64_t ldin = ldx;
+  for (int l = 0; l < 4; ++l) {
+    const bool last = l == 3;
+    HIP_TRY(launch_dense(in, ldin, wi + N->oWi[l], N->kp[l], w32 + N->ob[l], B, N->nout[l], N->kp[l], last ? 0 : 1,
+                         last ? nullptr : N->h[l].as<uint16_t>(), last ? out : nullptr,
+                         last ? (int64_t)N->dout : (int64_t)N->width, st));
+    if (!last) { in = N->h[l].as<uint16_t>(); ldin = N->width; }
+  }
   return FTP_OK;
 }
 
@@ -652,7 +700,7 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
   // (zero padded), then one kernel for the four layers
   const bool fused = solver == FTP_SOLVER_LEARNED && P->tune.mlp_fused && mlp_fused_ok(P->net.nin, P->net.nout);
   const int dinp = (P->net.din + 31) & ~31;
-  if (fused && (rc = P->xfeat.ensure(sizeof(uint16_t) * chunk * dinp))) return rc;
+  if ((fused || P->net.dense) && (rc = P->xfeat.ensure(sizeof(uint16_t) * chunk * dinp))) return rc;
   for (int64_t p0 = 0; p0 < n_pairs; p0 += chunk) {
     const int64_t np = std::min<int64_t>(chunk, n_pairs - p0);
     const int w_asm = (int)grid_waves(P, T.assemble_wpc, np);
@@ -686,6 +734,9 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
           }
           fa.out = P->seeds.as<float>();
           HIP_TRY(launch_mlp_fused(fa, st));
+        } else if (N.dense) {
+          HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), dinp, w_asm, st));
+          if ((rc = mlp_forward_dense(&N, P->xfeat.as<uint16_t>(), dinp, np, P->seeds.as<float>(), st))) return rc;
         } else {
           HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), N.din, w_asm, st));
           if ((rc = mlp_forward(&N, P->xfeat.as<uint16_t>(), np, P->seeds.as<float>(), st))) return rc;
@@ -1207,6 +1258,7 @@ int ftp_plan_load_mlp(ftp_plan* P, const float* weights, int64_t n_floats, int w
   if (n_floats != N.n_params) return FTP_E_SIZE;
   int rc = mlp_set_weights(&N, weights);
   if (rc) return rc;
+  if ((rc = mlp_build_inference(&N, weights))) return rc;
   P->mlp_loaded = true;
   return FTP_OK;
 }

@@ -118,6 +118,130 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   }
 }
 
+// ------------------------------------------------- inference dense layer
+
+// Y = act(A W^T + b) for inference: A (M x Kp bf16, row stride lda), W (N x Kp
+// bf16 row-major), Kp a multiple of 32 (rows zero-padded), 16-byte aligned rows.
+// A workgroup of RW x 4 waves owns 64 RW rows and 256 columns (column block
+// blockIdx.y); wave (r, c) computes rows 64 r .. + 63 and columns 64 c .. + 63
+// of the block as 4 x 4 MFMA 16 x 16 x 32 tiles (64 FP32 accumulators per
+// lane).  The K loop stages 32-wide slices of A and W in LDS, double-buffered:
+// the global loads of the next slice are issued before the MFMAs of the
+// current one; one W slice serves all 64 RW rows.  bf16 outputs leave through
+// LDS so that each lane stores 16 contiguous bytes; FP32 outputs (the last
+// layer, few columns) are stored directly.
+struct DenseArgs {
+  const uint16_t* A; int64_t lda;
+  const uint16_t* W; int ldw;
+  const float* bias;
+  int64_t M; int N, Kp;
+  int relu;
+  uint16_t* Yb; float* Yf; int64_t ldy;
+};
+
+constexpr int kDC = 256;   // columns per workgroup
+constexpr int kDP = 40;    // padded LDS row (bf16): 80 bytes, rows on distinct banks
+#ifndef FTP_DENSE_RW
+#define FTP_DENSE_RW 2
+#endif
+constexpr int kDRW = FTP_DENSE_RW;   // row waves per workgroup
+
+template <int RW>
+__global__ __launch_bounds__(256 * RW) void k_dense_bf16(DenseArgs d) {
+  constexpr int BM = 64 * RW, NT = 256 * RW;
+  __shared__ __align__(16) uint16_t As[2][BM * kDP];
+  __shared__ __align__(16) uint16_t Ws[2][kDC * kDP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int c0 = blockIdx.y * kDC;
+  const int lr = tid >> 2, lk = (tid & 3) * 8;   // loader: row 0..BM-1, k 0/8/16/24
+  constexpr int WQ = kDC / (NT / 4);             // W rows per loader thread
+  const bool wave_on = c0 + 64 * wc < d.N;
+  f32x4_t acc[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  uint4 ra, rw[WQ];
+  auto load = [&](int k0) {
+    const int64_t m = m0 + lr;
+    ra = m < d.M ? *reinterpret_cast<const uint4*>(d.A + m * d.lda + k0 + lk) : make_uint4(0u, 0u, 0u, 0u);
+    for (int q = 0; q < WQ; ++q) {
+      const int n = c0 + lr + BM * q;
+      rw[q] = n < d.N ? *reinterpret_cast<const uint4*>(d.W + (int64_t)n * d.ldw + k0 + lk)
+                      : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto stage = [&](int b) {
+    *reinterpret_cast<uint4*>(&As[b][lr * kDP + lk]) = ra;
+    for (int q = 0; q < WQ; ++q) *reinterpret_cast<uint4*>(&Ws[b][(lr + BM * q) * kDP + lk]) = rw[q];
+  };
+  const int nk = d.Kp / 32;
+  load(0);
+  stage(0);
+  __syncthreads();
+  for (int ks = 0; ks < nk; ++ks) {
+    const int b = ks & 1;
+    if (ks + 1 < nk) load(32 * (ks + 1));
+    if (wave_on) {
+      bf16x8_t af[4], wf[4];
+      for (int i = 0; i < 4; ++i)
+        memcpy(&af[i], &As[b][(64 * wr + 16 * i + (lane & 15)) * kDP + 8 * (lane >> 4)], 16);
+      for (int j = 0; j < 4; ++j)
+        memcpy(&wf[j], &Ws[b][(64 * wc + 16 * j + (lane & 15)) * kDP + 8 * (lane >> 4)], 16);
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], wf[j], acc[i][j], 0, 0, 0);
+    }
+    if (ks + 1 < nk) stage(b ^ 1);
+    __syncthreads();
+  }
+  // lane holds rows 64 wr + 16 i + 4 (lane / 16) + v, column 64 wc + 16 j + lane % 16
+  if (d.Yf) {
+    if (!wave_on) return;
+    for (int j = 0; j < 4; ++j) {
+      const int n = c0 + 64 * wc + 16 * j + (lane & 15);
+      if (n >= d.N) continue;
+      const float bn = d.bias ? d.bias[n] : 0.f;
+      for (int i = 0; i < 4; ++i)
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = m0 + 64 * wr + 16 * i + 4 * (lane >> 4) + v;
+          if (m >= d.M) continue;
+          float x = acc[i][j][v] + bn;
+          if (d.relu) x = fmaxf(x, 0.f);
+          d.Yf[m * d.ldy + n] = x;
+        }
+    }
+    return;
+  }
+  // bf16: the tile (BM x 256) through LDS, in row slabs of 64 (one per row
+  // wave) held in the W buffers (2 x 256 x 40 >= 64 x 264 elements)
+  uint16_t* Ct = &Ws[0][0];
+  constexpr int kCP = kDC + 8;
+  const int ncols = d.N - c0 < kDC ? d.N - c0 : kDC;   // a multiple of 8
+  for (int r = 0; r < RW; ++r) {
+    if (wr == r && wave_on) {
+      for (int j = 0; j < 4; ++j) {
+        const int cl = 64 * wc + 16 * j + (lane & 15);
+        const float bn = (c0 + cl < d.N && d.bias) ? d.bias[c0 + cl] : 0.f;
+        for (int i = 0; i < 4; ++i)
+          for (int v = 0; v < 4; ++v) {
+            float x = acc[i][j][v] + bn;
+            if (d.relu) x = fmaxf(x, 0.f);
+            Ct[(16 * i + 4 * (lane >> 4) + v) * kCP + cl] = f2bf(x);
+          }
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < 64 * (kDC / 8); q += NT) {
+      const int rr = q / (kDC / 8), c8 = (q % (kDC / 8)) * 8;
+      const int64_t m = m0 + 64 * r + rr;
+      if (m >= d.M || c8 >= ncols) continue;
+      *reinterpret_cast<uint4*>(d.Yb + m * d.ldy + c0 + c8) = *reinterpret_cast<const uint4*>(&Ct[rr * kCP + c8]);
+    }
+    __syncthreads();
+  }
+}
+
 // --------------------------------------------------------- small kernels
 
 // db[n] = sum_m G[m, n] (G fp32, row stride ld)
@@ -361,6 +485,15 @@ __global__ __launch_bounds__(64) void k_labels(const double* rec, int H, int64_t
 }
 
 // ------------------------------------------------------------ launchers
+
+hipError_t launch_dense(const uint16_t* A, int64_t lda, const uint16_t* W, int ldw, const float* bias, int64_t M,
+                        int N, int Kp, int relu, uint16_t* Yb, float* Yf, int64_t ldy, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  DenseArgs d{A, lda, W, ldw, bias, M, N, Kp, relu, Yb, Yf, ldy};
+  dim3 grid((unsigned)((M + 64 * kDRW - 1) / (64 * kDRW)), (unsigned)((N + kDC - 1) / kDC));
+  hipLaunchKernelGGL(k_dense_bf16<kDRW>, grid, dim3(256 * kDRW), 0, st, d);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
