@@ -436,7 +436,7 @@ __global__ __launch_bounds__(64) void k_newton_sturm2(SolveArgs a, LearnArgs L) 
       }
     }
     bool doneA = cA < 0, doneB = cB < 0;
-    unsigned long long um = 0ull;
+    unsigned long long um = 0ull, merged = 0ull;
     for (int it = 1; it <= 12 && !(doneA && doneB); ++it) {
       if (live && !conv) {
         double Rv, dR;
@@ -456,18 +456,25 @@ __global__ __launch_bounds__(64) void k_newton_sturm2(SolveArgs a, LearnArgs L) 
         const bool needA = !doneA && __popcll(cm & lo32) >= cA;
         const bool needB = !doneB && __popcll(cm >> 32) >= cB;
         if (!needA && !needB && it < 12) continue;
-        // distinct converged roots of each half (merge closer than 1e-8 rad,
-        // keeping the lowest lane)
+        // distinct converged roots of each half: a converged lane is unique
+        // unless a lower converged lane of its half lies within 1e-8 rad.
+        // Converged lanes no longer move, so only the lanes converged since
+        // the last merge are compared (lowest first): each settles its own
+        // flag against the lower lanes and clears the flag of higher ones on
+        // the same root.
         thw = fmod(th, kTwoPi);
         if (thw < 0.0) thw += kTwoPi;
-        uniq = conv;
-        for (unsigned long long m = cm; m; m &= m - 1ull) {
+        for (unsigned long long m = cm & ~merged; m; m &= m - 1ull) {
           const int jj = __builtin_ctzll(m);
           const double tj = lrdlane(thw, jj);
           double dd = fabs(tj - thw);
           dd = fmin(dd, kTwoPi - dd);
-          if ((jj >> 5) == half && jj < lane && dd < 1e-8) uniq = false;
+          const bool same = conv && (jj >> 5) == half && dd < 1e-8;
+          const unsigned long long sm = __ballot(same);
+          if (lane == jj) uniq = (sm & ((1ull << jj) - 1ull)) == 0ull;
+          else if (lane > jj && same) uniq = false;
         }
+        merged = cm;
         um = __ballot(uniq && hl < NS);
         if (__popcll(um & lo32) == cA) doneA = true;
         if (__popcll(um >> 32) == cB) doneB = true;
