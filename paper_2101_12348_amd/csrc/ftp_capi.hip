@@ -784,7 +784,9 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       HIP_TRY(launch_labels(rec, P->H, np, P->ds_roots + p0 * (int64_t)P->ds_R, P->ds_nroots + p0, P->ds_R, w_asm,
                             st));
     } else {
-      HIP_TRY(launch_score(a, rec, p0, np, w_sc, st));
+      SolveArgs as = a;
+      as.newton_cands = solver == FTP_SOLVER_LEARNED || solver == FTP_SOLVER_UNIFORM;
+      HIP_TRY(launch_score(as, rec, p0, np, w_sc, st));
     }
   }
   return FTP_OK;

@@ -384,8 +384,10 @@ __device__ __forceinline__ void load_sums(const SolveArgs& a, const LcInfo& L, i
 }
 
 // Sums -> polynomial record for pairs [p0, p0 + np) of the chunk.
+// At least four waves per SIMD (at most 128 VGPRs): the kernel is bound by
+// VALU issue and latency, and the register count otherwise drifts just above 128.
 template <typename R>
-__global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64_t p0, int64_t np) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble(SolveArgs a, double* rec, int64_t p0, int64_t np) {
   extern __shared__ double sma[];
   const int lane = wave_lane();
   const int H = a.H, K = 3 * H - 1, D = 2 * K;
@@ -437,7 +439,7 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
     const double ref = ref_cycles(j, L.df, L.tref);
     if (nb == 0) {
       load_sums<R>(a, L, pidx, j, W, lane);
-      assemble_poly(W, H, lane);
+      assemble_poly(W, H, lane, S.hb[0]);
     } else {
       // every band's sums of this frequency (grids of lightcurves 0..nb-1)
       const typename Cplx<R>::T* grids = reinterpret_cast<const typename Cplx<R>::T*>(a.grids);
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(64) void k_assemble(SolveArgs a, double* rec, int64
       }
       wave_sync();
       assemble_shared(S, nb, H, lane);
-      assemble_r(W, H, lane);
+      assemble_r(W, H, lane, S.hb[0]);
     }
     double rmax = 0.0, mumax = 0.0, etamax = 0.0;
     for (int d = lane; d <= K; d += 64) rmax = fmax(rmax, sqrt(cabs2(W.r[d])));
@@ -635,7 +637,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
     for (int e = lane; e <= 2 * H; e += 64) W.mu[e] = make_double2(Rr[RL.mu + 2 * e], Rr[RL.mu + 2 * e + 1]);
     for (int k = lane; k < H; k += 64) {
       W.eta[k + 1] = make_double2(Rr[RL.eta + 2 * k], Rr[RL.eta + 2 * k + 1]);
-      W.Z[k + 1] = make_double2(Rr[RL.zw + 2 * k], Rr[RL.zw + 2 * k + 1]);
+      // the conjugated psi^k coefficient of Mbar, conj(alpha_k conj(Z_k))
+      const double2 z = make_double2(Rr[RL.zw + 2 * k], Rr[RL.zw + 2 * k + 1]);
+      W.Z[k + 1] = cconj(cmul(W.al[k], cconj(z)));
     }
     if (lane == 0) W.eta[0] = make_double2(0.0, 0.0);
     wave_sync();
@@ -664,7 +668,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
     // changes P by O(1e-26) and ends the polish without re-scoring
     double best_th = b.th_rel;
     Cand cb = {__shfl(c.P, b.lane), __shfl(c.YM, b.lane), __shfl(c.MM, b.lane), __shfl(c.Mbar, b.lane)};
-    if (stout != ST_DEGENERATE && stout != ST_CONSTANT && !none) {
+    // roots that Newton already converged (steps below 1e-12 rad, learned and
+    // uniform solvers) are not polished: the polish step would be rounding noise
+    const bool newton_root = a.newton_cands && Rr[RL.meta + M_FALLBACK] == 0.0;
+    if (stout != ST_DEGENERATE && stout != ST_CONSTANT && !none && !newton_root) {
       for (int it = 0; it < 3; ++it) {
         double Rv, dR;
         eval_R(W, H, best_th, Rv, dR);

@@ -17,6 +17,7 @@ struct SolveArgs {
   const double2* alpha;          // template alpha_n, n = 1..H (shared phase: n_band x H, band-major)
   const double* ctab;            // Cayley-map table, (D + 1)^2 doubles, D < 64 (see k_assemble)
   int n_band;                    // 0: single band; > 0: shared-phase bands (lcs[0..n_band))
+  int newton_cands;              // candidates of M_FALLBACK == 0 pairs are Newton-converged roots
   int H;
   int flags;
   double mm_tau;                 // degenerate if MM <= mm_tau * sum|alpha|^2 at every candidate
@@ -190,9 +191,10 @@ struct FreqWork {
 //   YM(psi) = sum_k a_k conj(Zy_k) psi^k + c.c.   (YC~_k = conj(Zy_k)),
 //   R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta = sum_d r_d psi^d,
 //   r_d = i sum_k (3k - d) mu_{d-k} eta_k   (Eq. finalpoly with p = -i psi^K R).
-__device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane);
+__device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane, double2* scr);
 
-__device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane) {
+// `scr`: LDS scratch of 8H + 2 complex values for assemble_r.
+__device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane, double2* scr) {
   const int K = 3 * H - 1;
   for (int e = lane; e <= 2 * H; e += 64) {
     double2 acc = make_double2(0.0, 0.0);
@@ -220,22 +222,34 @@ __device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane
     W.eta[k] = k == 0 ? make_double2(0.0, 0.0) : cmul(W.al[k - 1], cconj(W.Z[2 * H + k]));
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier();
-  assemble_r(W, H, lane);
+  assemble_r(W, H, lane, scr);
 }
 
 // r_d, d = 0..K, of R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta from the trig
 // coefficients mu_e of MM and eta_k of YM (Eq. finalpoly as a trig polynomial).
-__device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane) {
+// The coefficients are first laid out over their full index ranges (mu_e for
+// e = -2H..4H with mu_{-e} = conj mu_e and zero beyond 2H, eta_k for k = -H..H
+// with eta_0 = 0) so that the sum over k has no branches.
+__device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane, double2* scr) {
   const int K = 3 * H - 1;
+  double2* mf = scr;               // mf[e + 2H], e = -2H .. 4H
+  double2* ef = scr + 6 * H + 1;   // ef[k + H], k = -H .. H
+  for (int i = lane; i <= 6 * H; i += 64) {
+    const int e = i - 2 * H;
+    mf[i] = e < 0 ? cconj(W.mu[-e]) : (e <= 2 * H ? W.mu[e] : make_double2(0.0, 0.0));
+  }
+  for (int i = lane; i <= 2 * H; i += 64) {
+    const int k = i - H;
+    ef[i] = k < 0 ? cconj(W.eta[-k]) : W.eta[k];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier();
   for (int d = lane; d <= K; d += 64) {
     double2 acc = make_double2(0.0, 0.0);
-    for (int k = -H; k <= H; ++k) {
-      if (k == 0) continue;
-      const int e = d - k;
-      if (e > 2 * H || e < -2 * H) continue;
-      const double2 me = e >= 0 ? W.mu[e] : cconj(W.mu[-e]);
-      const double2 ek = k > 0 ? W.eta[k] : cconj(W.eta[-k]);
-      acc = cadd(acc, cscale(cmul(me, ek), (double)(3 * k - d)));
+    double s = (double)(-3 * H - d);   // 3k - d
+    for (int k = -H; k <= H; ++k, s += 3.0) {
+      const double2 t = cmul(mf[d - k + 2 * H], ef[k + H]);
+      acc.x = fma(s, t.x, acc.x);
+      acc.y = fma(s, t.y, acc.y);
     }
     W.r[d] = make_double2(-acc.y, acc.x);  // multiply by i
   }
@@ -345,25 +359,34 @@ __device__ __forceinline__ int64_t next_item(unsigned* q, int lane, int64_t w) {
 // YY = 1), YM, MM and Mbar.
 struct Cand { double P, YM, MM, Mbar; };
 
+// psi b + c (complex multiply-add, four FMAs)
+__device__ __forceinline__ double2 cfma(double2 b, double2 psi, double2 c) {
+  return make_double2(fma(b.x, psi.x, fma(-b.y, psi.y, c.x)), fma(b.x, psi.y, fma(b.y, psi.x, c.y)));
+}
+
+// MM, YM and Mbar at theta by Horner in psi = e^{i theta}:
+// MM = mu_0 + 2 Re sum_{k=1}^{2H} mu_k psi^k, YM = 2 Re sum_{k=1}^{H} eta_k psi^k,
+// Mbar = 2 Re sum_{k=1}^{H} conj(W.Z[k]) psi^k, where W.Z[k] must hold the
+// conjugated psi^k coefficient of Mbar, conj(alpha_k conj(Z_k)) (the scoring
+// kernel converts the sums before calling).
 __device__ __forceinline__ Cand eval_candidate(const FreqWork& W, int H, double theta) {
   double sn, cs;
   sincos(theta, &sn, &cs);
-  const double2 e1 = make_double2(cs, sn);
-  double2 pw = e1;
-  double YM = 0.0, MM = W.mu[0].x, Mb = 0.0;
-  for (int k = 1; k <= 2 * H; ++k) {
-    MM += 2.0 * (W.mu[k].x * pw.x - W.mu[k].y * pw.y);
-    if (k <= H) {
-      YM += 2.0 * (W.eta[k].x * pw.x - W.eta[k].y * pw.y);
-      const double2 t = cmul(cmul(W.al[k - 1], pw), cconj(W.Z[k]));
-      Mb += 2.0 * t.x;
-    }
-    pw = cmul(pw, e1);
+  const double2 psi = make_double2(cs, sn);
+  double2 m = W.mu[2 * H];
+  for (int k = 2 * H - 1; k >= 1; --k) m = cfma(m, psi, W.mu[k]);
+  double2 y = W.eta[H], b = cconj(W.Z[H]);
+  for (int k = H - 1; k >= 1; --k) {
+    y = cfma(y, psi, W.eta[k]);
+    b = cfma(b, psi, cconj(W.Z[k]));
   }
+  // the sums above stop at psi^1: one more factor psi
+  const double MM = W.mu[0].x + 2.0 * (m.x * psi.x - m.y * psi.y);
+  const double YM = 2.0 * (y.x * psi.x - y.y * psi.y);
   Cand c;
   c.YM = YM;
   c.MM = MM;
-  c.Mbar = Mb;
+  c.Mbar = 2.0 * (b.x * psi.x - b.y * psi.y);
   c.P = MM > 0.0 ? YM * YM / MM : 0.0;
   return c;
 }
@@ -373,17 +396,17 @@ __device__ __forceinline__ void eval_R(const FreqWork& W, int H, double theta, d
   const int K = 3 * H - 1;
   double sn, cs;
   sincos(theta, &sn, &cs);
-  const double2 e1 = make_double2(cs, sn);
-  double2 pw = e1;
-  R = W.r[0].x;
-  dR = 0.0;
-  for (int d = 1; d <= K; ++d) {
-    const double re = W.r[d].x * pw.x - W.r[d].y * pw.y;
-    const double im = W.r[d].x * pw.y + W.r[d].y * pw.x;
-    R += 2.0 * re;
-    dR += -2.0 * d * im;
-    pw = cmul(pw, e1);
+  const double2 psi = make_double2(cs, sn);
+  // q(psi) = sum_{d=1}^{K} r_d psi^{d-1} and q'(psi) by Horner; with
+  // p = psi q: R = r_0 + 2 Re p, dR/dtheta = -2 Im(psi p') = -2 Im(p + psi^2 q')
+  double2 q = W.r[K], dq = make_double2(0.0, 0.0);
+  for (int d = K - 1; d >= 1; --d) {
+    dq = cfma(dq, psi, q);
+    q = cfma(q, psi, W.r[d]);
   }
+  const double2 p = cmul(q, psi), psi2 = cmul(psi, psi);
+  R = W.r[0].x + 2.0 * p.x;
+  dR = -2.0 * (p.y + (dq.x * psi2.y + dq.y * psi2.x));
 }
 
 }  // namespace ftp
