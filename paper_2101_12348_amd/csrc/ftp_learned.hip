@@ -113,16 +113,23 @@ __device__ int sturm_count_unit(const double* g, int D, double* ch, double* tmp,
 // max |v| over the wavefront from the high words (sign cleared) of the
 // doubles: the high word of |v| orders like |v|, so this is the maximum with
 // its low word cleared (relative error below 2^-20, never above the maximum).
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v) { return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false); }
+// Row stages: quad_perm [1,0,3,2], [2,3,0,1], row_half_mirror, row_mirror
+// (every lane of a row ends with the row maximum); then row_bcast:15 into rows
+// 1 and 3 and row_bcast:31 into rows 2 and 3 leave the maximum in lane 63.
+// (DPP moves without an `old` value, so that each folds into its v_max; lanes
+// of rows a row mask leaves out hold unspecified values, which do not reach
+// lane 63.)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int v) { return __builtin_amdgcn_mov_dpp(v, CTRL, ROWS, 0xf, true); }
 __device__ __forceinline__ double wave_max_abs_hi(double v) {
   int h = (int)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffff;
-  h = max(h, dpp_i<0xB1>(h));
-  h = max(h, dpp_i<0x4E>(h));
-  h = max(h, dpp_i<0x141>(h));
-  h = max(h, dpp_i<0x140>(h));
-  h = max(max(__builtin_amdgcn_readlane(h, 0), __builtin_amdgcn_readlane(h, 16)),
-          max(__builtin_amdgcn_readlane(h, 32), __builtin_amdgcn_readlane(h, 48)));
+  h = max(h, dpp_i<0xB1, 0xf>(h));
+  h = max(h, dpp_i<0x4E, 0xf>(h));
+  h = max(h, dpp_i<0x141, 0xf>(h));
+  h = max(h, dpp_i<0x140, 0xf>(h));
+  h = max(h, dpp_i<0x142, 0xa>(h));
+  h = max(h, dpp_i<0x143, 0xc>(h));
+  h = __builtin_amdgcn_readlane(h, 63);
   return __longlong_as_double((long long)((unsigned long long)(unsigned)h << 32));
 }
 
@@ -137,7 +144,7 @@ __device__ __forceinline__ double wave_max_abs_hi(double v) {
 // loses its leading term to cancellation: the count is then not trusted.
 // A, B: the last two members; al, bl: their leading coefficients (uniform).
 struct SturmChain {
-  double A, B, al, bl;
+  double A, B, al, bl, ibl;   // ibl = 1 / bl
   int sp, sm, vp, vm;
   bool ok;
 };
@@ -153,6 +160,7 @@ __device__ __forceinline__ SturmChain sturm_begin(double gv, int D, int lane) {
   c.B = dv * imb;
   c.al = lrdlane(gv, D) * ima;
   c.bl = lrdlane(dv, D - 1) * imb;
+  c.ibl = fast_rcp_d(c.bl);
   c.sp = c.al > 0.0 ? 1 : -1;
   c.sm = (D & 1) ? -c.sp : c.sp;
   c.vp = 0;
@@ -171,7 +179,7 @@ __device__ __forceinline__ SturmChain sturm_begin(double gv, int D, int lane) {
 // stepping on values that are then ignored.
 __device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane) {
   const int db = D - q + 1;
-  const double ibl = fast_rcp_d(c.bl);
+  const double ibl = c.ibl;
   const double q1 = c.al * ibl;
   double t = c.A - q1 * lane_shr1(c.B);
   const double q0 = lrdlane(t, db) * ibl;
@@ -186,11 +194,15 @@ __device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane
   c.vm += tm != c.sm;
   c.sp = tp;
   c.sm = tm;
-  const double inv = -fast_rcp_d(mr);
+  // one reciprocal for both 1 / mr (the scaling) and 1 / bl of the next step:
+  // with u = 1 / (mr lead), 1 / mr = lead u and 1 / (-lead / mr) = -mr^2 u
+  const double u = fast_rcp_d(mr * lead);
+  const double inv = -lead * u;
   c.A = c.B;
   c.al = c.bl;
   c.B = t * inv;
   c.bl = lead * inv;
+  c.ibl = -(mr * mr) * u;
 }
 
 // Distinct real roots of g (coefficient `gv` in lane c, g[D] != 0), or -1.
@@ -227,7 +239,7 @@ __host__ __device__ inline size_t learn_lds_bytes(int H) {
   return (size_t)(2 * (K + 1) + 4 * (D + 1) + (D + 1) * (D + 2) / 2 + 8) * sizeof(double);
 }
 
-__global__ __launch_bounds__(64) void k_newton_sturm(SolveArgs a, LearnArgs L) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_sturm(SolveArgs a, LearnArgs L) {
   extern __shared__ double sml[];
   const int lane = threadIdx.x & 63;
   const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = 2 * S;

@@ -111,8 +111,9 @@ __device__ __forceinline__ int64_t find_seg(const int64_t* off, int64_t n, int64
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
   const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp((int)u, (int)u, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(u >> 32), (int)(u >> 32), CTRL, 0xf, 0xf, false);
+  // (every CTRL used here reads a lane of the same row: no lane is left without a source)
+  const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xf, 0xf, true);
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 __device__ __forceinline__ double lane_d(double v, int src) {
