@@ -417,9 +417,12 @@ int validate_template(int H, const double* c, const double* s) {
 int default_msp(int precision) { return precision == FTP_FP64 ? 12 : 7; }
 
 // FFT pass plan: passes (largest stride first) with in-LDS sizes.
+// log2 of the elements one FFT workgroup holds in LDS (64 KB)
+int fft_max_el(int precision) { return precision == FTP_FP64 ? 12 : 13; }
+
 void fft_plan(int L, int precision, int* npass, int* lp) {
-  const int last = precision == FTP_FP64 ? 11 : 12;
-  const int wide = last - 4;
+  const int last = precision == FTP_FP64 ? 11 : 12;   // largest single pass (twiddle table)
+  const int wide = fft_max_el(precision) - 4;         // earlier passes: 16 columns per workgroup
   if (L <= last) { *npass = 1; lp[0] = L; return; }
   const int rest = L - last;
   const int npre = (rest + wide - 1) / wide;
@@ -564,7 +567,8 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
   const C* tw = reinterpret_cast<const C*>(P->opt.precision == FTP_FP64 ? P->twiddle64.p : P->twiddle32.p);
   int64_t item_base = 0;
   for (size_t r = 0; r < P->fft_round_n.size(); ++r) {
-    hipLaunchKernelGGL(k_fft_pass<R>, dim3((unsigned)P->fft_round_items[r]), dim3(256), 32768, st,
+    hipLaunchKernelGGL(k_fft_pass<R>, dim3((unsigned)P->fft_round_items[r]), dim3(256),
+                       sizeof(C) << fft_max_el(P->opt.precision), st,
                        P->d_fft + P->fft_round_tab_off[r], P->fft_round_n[r], P->d_items + item_base, tw,
                        P->grids.as<C>());
     item_base += P->fft_round_n[r] + 1;
@@ -600,7 +604,7 @@ void build_fft_tables(ftp_plan* P) {
         int consumed = 0;
         for (int q = 0; q <= r; ++q) consumed += L.lp[g][q];
         fp.ls = fp.log2n - consumed;
-        const int maxel = P->opt.precision == FTP_FP64 ? 11 : 12;
+        const int maxel = fft_max_el(P->opt.precision);
         fp.lcols = std::min(fp.ls, std::min(4, maxel - fp.lp));
         tab.push_back(fp);
         it += 1LL << (fp.log2n - fp.lp - fp.lcols);
