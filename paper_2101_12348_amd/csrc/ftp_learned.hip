@@ -212,13 +212,80 @@ __device__ int sturm_count_line_reg(double gv, int D, int lane) {
   return c.ok ? c.vm - c.vp : -1;
 }
 
+// Per-half maximum of |v| from the high words (as wave_max_abs_hi): the row
+// stages, then row_bcast:15 into rows 1 and 3 leave the maximum of lanes
+// 0..31 in lane 31 and of lanes 32..63 in lane 63.
+__device__ __forceinline__ void half_max_abs_hi(double v, double& m_lo, double& m_hi) {
+  int h = (int)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffff;
+  h = max(h, dpp_i<0xB1, 0xf>(h));
+  h = max(h, dpp_i<0x4E, 0xf>(h));
+  h = max(h, dpp_i<0x141, 0xf>(h));
+  h = max(h, dpp_i<0x140, 0xf>(h));
+  h = max(h, dpp_i<0x142, 0xa>(h));
+  const int lo = __builtin_amdgcn_readlane(h, 31), hi = __builtin_amdgcn_readlane(h, 63);
+  m_lo = __longlong_as_double((long long)((unsigned long long)(unsigned)lo << 32));
+  m_hi = __longlong_as_double((long long)((unsigned long long)(unsigned)hi << 32));
+}
+
 // The same for two polynomials at once (two frequencies of one wavefront).
+// While a member still has more than 32 coefficients the two chains are
+// stepped side by side over the whole wave; from step D - 29 on, every
+// polynomial of both chains fits in 32 lanes, and the chains are packed into
+// the two half-waves (chain b's coefficient c in lane 32 + c) and stepped by
+// one instruction stream.  Coefficients above a member's degree are exact
+// zeros, so the shift by one power of x brings a zero into lane 32.  In the
+// packed form the per-chain scalars (al, bl, 1/bl) are held per lane, equal
+// within each half.
 __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int& ca, int& cb) {
   SturmChain a = sturm_begin(ga, D, lane);
   SturmChain b = sturm_begin(gb, D, lane);
-  for (int q = 2; q <= D && (a.ok || b.ok); ++q) {
+  const int qpack = D - 29 > 2 ? D - 29 : 2;
+  int q = 2;
+  for (; q < qpack && (a.ok || b.ok); ++q) {
     sturm_step(a, D, q, lane);
     sturm_step(b, D, q, lane);
+  }
+  if (q <= D && (a.ok || b.ok)) {
+    const int half = lane >> 5, hl = lane & 31;
+    const double bA = __shfl(b.A, hl), bB = __shfl(b.B, hl);   // all lanes active
+    double A = half ? bA : a.A, B = half ? bB : a.B;
+    double al = half ? b.al : a.al, bl = half ? b.bl : a.bl, ibl = half ? b.ibl : a.ibl;
+    for (; q <= D && (a.ok || b.ok); ++q) {
+      const int db = D - q + 1;
+      const double q1 = al * ibl;
+      double t = A - q1 * lane_shr1(B);
+      const double ta = lrdlane(t, db), tb = lrdlane(t, 32 + db);
+      const double q0 = (half ? tb : ta) * ibl;
+      t = hl < db ? t - q0 * B : 0.0;
+      double mra, mrb;
+      half_max_abs_hi(t, mra, mrb);
+      const double la = lrdlane(t, db - 1), lb = lrdlane(t, 32 + db - 1);
+      a.ok = a.ok && mra > 1e-12 && fabs(la) > 1e-13 * mra;
+      b.ok = b.ok && mrb > 1e-12 && fabs(lb) > 1e-13 * mrb;
+      // P_q = -t / mr: leading sign -sgn(lead), degree D - q
+      {
+        const int tp = la > 0.0 ? -1 : 1, tm = ((D - q) & 1) ? -tp : tp;
+        a.vp += tp != a.sp;
+        a.vm += tm != a.sm;
+        a.sp = tp;
+        a.sm = tm;
+      }
+      {
+        const int tp = lb > 0.0 ? -1 : 1, tm = ((D - q) & 1) ? -tp : tp;
+        b.vp += tp != b.sp;
+        b.vm += tm != b.sm;
+        b.sp = tp;
+        b.sm = tm;
+      }
+      const double mr = half ? mrb : mra, lead = half ? lb : la;
+      const double u = fast_rcp_d(mr * lead);
+      const double inv = -lead * u;
+      A = B;
+      al = bl;
+      B = t * inv;
+      bl = lead * inv;
+      ibl = -(mr * mr) * u;
+    }
   }
   ca = a.ok ? a.vm - a.vp : -1;
   cb = b.ok ? b.vm - b.vp : -1;
