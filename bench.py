@@ -86,8 +86,10 @@ def run_solver(F, plan, t, y, s, lc, out, steps, warmup):
     return ms_step, per
 
 
-KERNEL_OF_STAGE = {"plain_qr": "k_qr", "fallback_qr": "k_qr", "newton_sturm": "k_newton_sturm",
-                   "aberth": "k_aberth", "mlp_forward": "k_gemm_bf16"}
+# kernels behind each stage for H <= 8 (two frequencies per wavefront in the
+# Newton + Sturm kernel; the one-frequency k_newton_sturm serves H = 9..11)
+KERNEL_OF_STAGE = {"plain_qr": "k_qr", "fallback_qr": "k_qr", "newton_sturm": "k_newton_sturm2",
+                   "aberth": "k_aberth", "mlp_forward": "k_dense_bf16"}
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -430,9 +432,9 @@ def main():
         dom = "plain_qr"
     kernel_names = {"plain_qr": f"k_qr<{D}> (companion QR, FP64 vector)",
                     "fallback_qr": f"k_qr<{D}> on the Aberth tier's leftovers (FP64 vector)",
-                    "newton_sturm": "k_newton_sturm (FP64 vector)",
+                    "newton_sturm": ("k_newton_sturm2" if H <= 8 else "k_newton_sturm") + " (FP64 vector)",
                     "aberth": "k_aberth (FP64 vector)",
-                    "mlp_forward": "k_gemm_bf16 (MFMA bf16)"}
+                    "mlp_forward": "k_dense_bf16 (MFMA bf16)"}
     solvers = {}
     for name, (_, o, ms, stn) in runs.items():
         solvers[name] = {"value": pairs / (ms * 1e-3), "ms_per_step": ms, "launch_shapes": runs[name][0].tuning(),
