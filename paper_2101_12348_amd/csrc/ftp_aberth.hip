@@ -105,48 +105,42 @@ __global__ __launch_bounds__(64) void k_aberth(AberthArgs A) {
       awave_sync();
       if (!done) {
         const double az = sqrt(zr * zr + zi * zi);
-        double rr, ri;   // f'(z) / f(z)
-        bool exact = false;
-        if (az <= 1.0) {
-          double pr = fc[D], pi = 0.0, dr = 0.0, di = 0.0, ab = fabs(fc[D]);
-          for (int k = D - 1; k >= 0; --k) {
-            const double tr = dr * zr - di * zi + pr;
-            di = dr * zi + di * zr + pi;
-            dr = tr;
-            const double qr = pr * zr - pi * zi + fc[k];
-            pi = pr * zi + pi * zr;
-            pr = qr;
-            ab = ab * az + fabs(fc[k]);
-          }
-          const double pm2 = pr * pr + pi * pi;
-          exact = !(sqrt(pm2) > 4.0 * D * u * ab);
-          if (!exact) {
-            const double inv = 1.0 / pm2;
-            rr = (dr * pr + di * pi) * inv;
-            ri = (di * pr - dr * pi) * inv;
-          }
-        } else {
-          // reversed polynomial in y = 1/z: f(z) = z^D g(y), f'/f = y (D - y g'/g)
+        double rr = 0.0, ri = 0.0;   // f'(z) / f(z)
+        // one Horner loop for every lane (no divergent branches): inside the
+        // unit circle f at x = z; outside, the reversed polynomial
+        // g(y) = y^D f(1/y) at x = y = 1/z, with f'/f = y (D - y g'/g)
+        const bool inside = az <= 1.0;
+        double xr = zr, xi = zi, ax = az;
+        if (!inside) {
           const double iz2 = 1.0 / (az * az);
-          const double yr = zr * iz2, yi = -zi * iz2, ay = 1.0 / az;
-          double gr = fc[0], gi = 0.0, dr = 0.0, di = 0.0, ab = fabs(fc[0]);
-          for (int k = 1; k <= D; ++k) {
-            const double tr = dr * yr - di * yi + gr;
-            di = dr * yi + di * yr + gi;
-            dr = tr;
-            const double qr = gr * yr - gi * yi + fc[k];
-            gi = gr * yi + gi * yr;
-            gr = qr;
-            ab = ab * ay + fabs(fc[k]);
-          }
-          const double gm2 = gr * gr + gi * gi;
-          exact = !(sqrt(gm2) > 4.0 * D * u * ab);
-          if (!exact) {
-            const double inv = 1.0 / gm2;
-            const double qr = (dr * gr + di * gi) * inv, qi = (di * gr - dr * gi) * inv;   // g'/g
-            const double sr = D - (yr * qr - yi * qi), si = -(yr * qi + yi * qr);       // D - y g'/g
-            rr = yr * sr - yi * si;
-            ri = yr * si + yi * sr;
+          xr = zr * iz2;
+          xi = -zi * iz2;
+          ax = 1.0 / az;
+        }
+        const int c0 = inside ? D : 0, cs = inside ? -1 : 1;   // coefficient of x^D, then step
+        double pr = fc[c0], pi = 0.0, dr = 0.0, di = 0.0, ab = fabs(fc[c0]);
+        for (int k = 1; k <= D; ++k) {
+          const double c = fc[c0 + cs * k];
+          const double tr = dr * xr - di * xi + pr;
+          di = dr * xi + di * xr + pi;
+          dr = tr;
+          const double qr = pr * xr - pi * xi + c;
+          pi = pr * xi + pi * xr;
+          pr = qr;
+          ab = ab * ax + fabs(c);
+        }
+        const double pm2 = pr * pr + pi * pi;
+        const bool exact = !(sqrt(pm2) > 4.0 * D * u * ab);
+        if (!exact) {
+          const double inv = 1.0 / pm2;
+          const double qr = (dr * pr + di * pi) * inv, qi = (di * pr - dr * pi) * inv;   // p'/p at x
+          if (inside) {
+            rr = qr;
+            ri = qi;
+          } else {
+            const double sr = D - (xr * qr - xi * qi), si = -(xr * qi + xi * qr);       // D - y g'/g
+            rr = xr * sr - xi * si;
+            ri = xr * si + xi * sr;
           }
         }
         if (exact) {
