@@ -449,7 +449,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // and min(32, D) starts: the 2H network seeds and min(32, D) - 2H evenly
 // spaced phases (all evenly spaced without network).  A half that has reached
 // its count is frozen while the other goes on.
-__global__ __launch_bounds__(64) void k_newton_sturm2(SolveArgs a, LearnArgs L) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_sturm2(SolveArgs a, LearnArgs L) {
   extern __shared__ double sml[];
   const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
   // starts per frequency: every lane of the half (at most D: no more real

@@ -360,6 +360,42 @@ __device__ __forceinline__ int64_t next_item(unsigned* q, int lane, int64_t w) {
 // YY = 1), YM, MM and Mbar.
 struct Cand { double P, YM, MM, Mbar; };
 
+// sin and cos of a moderate angle (|x| < 2^30; every phase here is within a
+// few turns of [0, 2 pi)): Cody-Waite reduction by pi/2 in two parts
+// (k = rint(2x/pi), r = x - k pi/2 in [-pi/4, pi/4], the products exact in
+// FMA), the Taylor series of sin and cos to r^17 and r^18 (truncation below
+// 1e-19 on that interval; the coefficients are 1/n!), then the quadrant.
+__device__ __forceinline__ void sincos_small(double x, double& s, double& c) {
+  const double k = rint(x * 0.63661977236758134308);        // 2 / pi
+  double r = fma(-k, 1.5707963267948966192, x);             // pi/2, leading double
+  r = fma(-k, 6.1232339957367660359e-17, r);                // pi/2 - leading double
+  const double z = r * r;
+  double ps = 2.8114572543455207632e-15;                    // 1/17!
+  ps = fma(ps, z, -7.6471637318198164759e-13);              // -1/15!
+  ps = fma(ps, z, 1.6059043836821614599e-10);               // 1/13!
+  ps = fma(ps, z, -2.5052108385441718775e-08);              // -1/11!
+  ps = fma(ps, z, 2.7557319223985890653e-06);               // 1/9!
+  ps = fma(ps, z, -1.9841269841269841270e-04);              // -1/7!
+  ps = fma(ps, z, 8.3333333333333333333e-03);               // 1/5!
+  ps = fma(ps, z, -1.6666666666666666667e-01);              // -1/3!
+  const double sr = fma(ps * z, r, r);
+  double pc = 1.5619206968586225271e-16;                    // 1/18!
+  pc = fma(pc, z, -4.7794773323873852974e-14);              // -1/16!
+  pc = fma(pc, z, 1.1470745597729724714e-11);               // 1/14!
+  pc = fma(pc, z, -2.0876756987868098979e-09);              // -1/12!
+  pc = fma(pc, z, 2.7557319223985890653e-07);               // 1/10!
+  pc = fma(pc, z, -2.4801587301587301587e-05);              // -1/8!
+  pc = fma(pc, z, 1.3888888888888888889e-03);               // 1/6!
+  pc = fma(pc, z, -4.1666666666666666667e-02);              // -1/4!
+  pc = fma(pc, z, 0.5);
+  const double cr = fma(-pc, z, 1.0);
+  const int q = (int)k & 3;
+  const double ss = (q & 1) ? cr : sr;
+  const double cc = (q & 1) ? sr : cr;
+  s = (q & 2) ? -ss : ss;
+  c = ((q + 1) & 2) ? -cc : cc;
+}
+
 // psi b + c (complex multiply-add, four FMAs)
 __device__ __forceinline__ double2 cfma(double2 b, double2 psi, double2 c) {
   return make_double2(fma(b.x, psi.x, fma(-b.y, psi.y, c.x)), fma(b.x, psi.y, fma(b.y, psi.x, c.y)));
@@ -372,7 +408,7 @@ __device__ __forceinline__ double2 cfma(double2 b, double2 psi, double2 c) {
 // kernel converts the sums before calling).
 __device__ __forceinline__ Cand eval_candidate(const FreqWork& W, int H, double theta) {
   double sn, cs;
-  sincos(theta, &sn, &cs);
+  sincos_small(theta, sn, cs);
   const double2 psi = make_double2(cs, sn);
   double2 m = W.mu[2 * H];
   for (int k = 2 * H - 1; k >= 1; --k) m = cfma(m, psi, W.mu[k]);
@@ -396,7 +432,7 @@ __device__ __forceinline__ Cand eval_candidate(const FreqWork& W, int H, double 
 __device__ __forceinline__ void eval_R(const FreqWork& W, int H, double theta, double& R, double& dR) {
   const int K = 3 * H - 1;
   double sn, cs;
-  sincos(theta, &sn, &cs);
+  sincos_small(theta, sn, cs);
   const double2 psi = make_double2(cs, sn);
   // q(psi) = sum_{d=1}^{K} r_d psi^{d-1} and q'(psi) by Horner; with
   // p = psi q: R = r_0 + 2 Re p, dR/dtheta = -2 Im(psi p') = -2 Im(p + psi^2 q')
