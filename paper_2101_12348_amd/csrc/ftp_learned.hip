@@ -110,29 +110,6 @@ __device__ int sturm_count_unit(const double* g, int D, double* ch, double* tmp,
   return vm - vp;
 }
 
-// max |v| over the wavefront from the high words (sign cleared) of the
-// doubles: the high word of |v| orders like |v|, so this is the maximum with
-// its low word cleared (relative error below 2^-20, never above the maximum).
-// Row stages: quad_perm [1,0,3,2], [2,3,0,1], row_half_mirror, row_mirror
-// (every lane of a row ends with the row maximum); then row_bcast:15 into rows
-// 1 and 3 and row_bcast:31 into rows 2 and 3 leave the maximum in lane 63.
-// (DPP moves without an `old` value, so that each folds into its v_max; lanes
-// of rows a row mask leaves out hold unspecified values, which do not reach
-// lane 63.)
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_i(int v) { return __builtin_amdgcn_mov_dpp(v, CTRL, ROWS, 0xf, true); }
-__device__ __forceinline__ double wave_max_abs_hi(double v) {
-  int h = (int)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffff;
-  h = max(h, dpp_i<0xB1, 0xf>(h));
-  h = max(h, dpp_i<0x4E, 0xf>(h));
-  h = max(h, dpp_i<0x141, 0xf>(h));
-  h = max(h, dpp_i<0x140, 0xf>(h));
-  h = max(h, dpp_i<0x142, 0xa>(h));
-  h = max(h, dpp_i<0x143, 0xc>(h));
-  h = __builtin_amdgcn_readlane(h, 63);
-  return __longlong_as_double((long long)((unsigned long long)(unsigned)h << 32));
-}
-
 // Sturm sequence of a degree-D polynomial g over the whole real line, D + 1
 // <= 64, in registers: P_0 = g, P_1 = g', P_q = -rem(P_{q-2}, P_{q-1}), each
 // member scaled to max |coefficient| ~ 1, lane c holding coefficient c (the

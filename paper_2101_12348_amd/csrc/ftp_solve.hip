@@ -457,18 +457,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     for (int d = lane; d <= K; d += 64) rmax = fmax(rmax, sqrt(cabs2(W.r[d])));
     for (int e = lane; e <= 2 * H; e += 64) mumax = fmax(mumax, sqrt(cabs2(W.mu[e])));
     for (int k = lane; k <= H; k += 64) etamax = fmax(etamax, sqrt(cabs2(W.eta[k])));
-    rmax = wave_max(rmax);
-    mumax = wave_max(mumax);
-    etamax = wave_max(etamax);
+    // maxima from the doubles' high words (within 2^-20): the threshold
+    // below only separates R = 0 from rounding noise
+    rmax = wave_max_abs_hi(rmax);
+    mumax = wave_max_abs_hi(mumax);
+    etamax = wave_max_abs_hi(etamax);
     const double rscale = mumax * etamax * (6.0 * H) * (2.0 * H + 1.0);
     const bool constant = !(rmax > 64.0 * kEps * rscale);
     double phi0 = 0.0;
     if (!constant) {
-      double Rv = -1.0, dR;
-      if (lane < 16) {
-        eval_R(W, H, kTwoPi * lane / 16.0 + kPi, Rv, dR);
-        Rv = fabs(Rv);
-      }
+      double Rv = -1.0;
+      if (lane < 16) Rv = fabs(eval_R_value(W, H, kTwoPi * lane / 16.0 + kPi));
       const double rm = wave_max(Rv);
       const unsigned long long mask = __ballot(lane < 16 && Rv == rm);
       const int k0 = __ffsll((long long)mask) - 1;

@@ -137,6 +137,29 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
+// max |v| over the wavefront from the high words (sign cleared) of the
+// doubles: the high word of |v| orders like |v|, so this is the maximum with
+// its low word cleared (relative error below 2^-20, never above the maximum).
+// Row stages: quad_perm [1,0,3,2], [2,3,0,1], row_half_mirror, row_mirror
+// (every lane of a row ends with the row maximum); then row_bcast:15 into rows
+// 1 and 3 and row_bcast:31 into rows 2 and 3 leave the maximum in lane 63.
+// (DPP moves without an `old` value, so that each folds into its v_max; lanes
+// of rows a row mask leaves out hold unspecified values, which do not reach
+// lane 63.)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int v) { return __builtin_amdgcn_mov_dpp(v, CTRL, ROWS, 0xf, true); }
+__device__ __forceinline__ double wave_max_abs_hi(double v) {
+  int h = (int)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffff;
+  h = max(h, dpp_i<0xB1, 0xf>(h));
+  h = max(h, dpp_i<0x4E, 0xf>(h));
+  h = max(h, dpp_i<0x141, 0xf>(h));
+  h = max(h, dpp_i<0x140, 0xf>(h));
+  h = max(h, dpp_i<0x142, 0xa>(h));
+  h = max(h, dpp_i<0x143, 0xc>(h));
+  h = __builtin_amdgcn_readlane(h, 63);
+  return __longlong_as_double((long long)((unsigned long long)(unsigned)h << 32));
+}
+
 // Position of mode index q (0 <= q < n) in the digit-reversed FFT output.
 __device__ __forceinline__ int64_t fft_pos(int64_t q, const LcInfo& L, int g) {
   int64_t pos = 0;
@@ -426,6 +449,17 @@ __device__ __forceinline__ Cand eval_candidate(const FreqWork& W, int H, double 
   c.Mbar = 2.0 * (b.x * psi.x - b.y * psi.y);
   c.P = MM > 0.0 ? YM * YM / MM : 0.0;
   return c;
+}
+
+// R(theta) alone (Horner in psi).
+__device__ __forceinline__ double eval_R_value(const FreqWork& W, int H, double theta) {
+  const int K = 3 * H - 1;
+  double sn, cs;
+  sincos_small(theta, sn, cs);
+  const double2 psi = make_double2(cs, sn);
+  double2 q = W.r[K];
+  for (int d = K - 1; d >= 1; --d) q = cfma(q, psi, W.r[d]);
+  return W.r[0].x + 2.0 * (q.x * psi.x - q.y * psi.y);
 }
 
 // R(theta) and dR/dtheta from r_d.
