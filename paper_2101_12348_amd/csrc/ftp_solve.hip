@@ -596,10 +596,10 @@ __host__ __device__ inline size_t score_lds_bytes(int H) {
   return (size_t)(2 * ((3 * H + 1) + (2 * H + 1) + (H + 1) + (K + 1) + H)) * sizeof(double);
 }
 
-// Scores all candidates of pairs [p0, p0 + np) and writes the outputs.  Five
-// waves per SIMD (at most 96 VGPRs): latency-bound per-frequency work gains more
-// from the extra wave than it loses to the few spilled registers.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_score(SolveArgs a, const double* rec, int64_t p0, int64_t np) {
+// Scores all candidates of pairs [p0, p0 + np) and writes the outputs.  At
+// least four waves per SIMD (at most 128 VGPRs, no spills; measured faster
+// than five waves with spills, or than the uncapped allocation).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_score(SolveArgs a, const double* rec, int64_t p0, int64_t np) {
   extern __shared__ double sms[];
   const int lane = wave_lane();
   const int H = a.H, K = 3 * H - 1, D = 2 * K;
