@@ -107,7 +107,7 @@ struct FusedMlpArgs {
 };
 bool mlp_fused_ok(const int* nin, const int* nout);
 hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st);
-hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st);
+hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st, unsigned* p2 = nullptr);
 hipError_t launch_lc_chi2(const LcInfo* lcs, int64_t n_lc, double* out, hipStream_t st);
 hipError_t launch_mb_combine(const double* bp, int64_t n_band, int64_t n_f, const double* chi2, double* power,
                              hipStream_t st);
@@ -542,8 +542,7 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
   hipLaunchKernelGGL(k_prep_stats, dim3((unsigned)n_lc), dim3(1024), 0, st, dl, t, y, sigma);
   if (shared_bands > 0)
     hipLaunchKernelGGL(k_sp_combine, dim3(1), dim3(64), 0, st, dl, shared_bands, P->alpha.as<double2>(), P->H);
-  HIP_TRY(launch_zero_u32(P->tile_count.as<unsigned>(), n_tiles, st));
-  HIP_TRY(launch_zero_u32(P->cursor.as<unsigned>(), n_tiles, st));
+  HIP_TRY(launch_zero_u32(P->tile_count.as<unsigned>(), n_tiles, st, P->cursor.as<unsigned>()));
   const unsigned pblocks = (unsigned)((n_pts + 255) / 256);
   hipLaunchKernelGGL(k_prep_points<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc,
                      P->d_obs_off, n_pts, t, y, sigma, P->pw.as<PointRec<R>>(),
@@ -777,8 +776,10 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       HIP_TRY(launch_aberth(A, w_ab, st));
       hipEvent_t rc2 = next_learn_event(P);
       if (rc2) HIP_TRY(hipEventRecord(rc2, st));
+      // what the Aberth tier leaves is usually nothing or a few frequencies:
+      // a launch of four waves per CU serves it through the queue
       HIP_TRY(launch_qr(P->H, rec, RL.stride, np, P->fb2_list.as<int64_t>(), ctr + 1,
-                        P->counters.as<SolveCounters>(), ctr + 4, w_qr, st));
+                        P->counters.as<SolveCounters>(), ctr + 4, std::min(w_qr, (int)grid_waves(P, 4, np)), st));
     }
     hipEvent_t r1 = next_root_event(P);
     if (r1) HIP_TRY(hipEventRecord(r1, st));

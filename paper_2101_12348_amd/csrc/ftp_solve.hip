@@ -749,8 +749,11 @@ __global__ __launch_bounds__(256) void k_mb_combine(const double* bp, int64_t n_
 
 // Clears n counters (a kernel rather than a memset node, so that captured
 // graphs replay it like any other launch).
-__global__ __launch_bounds__(256) void k_zero_u32(unsigned* p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+__global__ __launch_bounds__(256) void k_zero_u32(unsigned* p, int64_t n, unsigned* p2) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    p[i] = 0u;
+    if (p2) p2[i] = 0u;
+  }
 }
 
 // lc_stats[0..3] = t_ref, ybar, YY, status bits of the first lightcurve.
@@ -828,10 +831,11 @@ hipError_t launch_mb_combine(const double* bp, int64_t n_band, int64_t n_f, cons
   return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st) {
+// Clears p[0..n) and, when given, p2[0..n) in one launch.
+hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st, unsigned* p2) {
   if (n <= 0) return hipSuccess;
   const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
-  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, p2);
   return hipGetLastError();
 }
 
