@@ -577,9 +577,51 @@ __global__ __launch_bounds__(256) void k_fft_pass(const FftGridPass* __restrict_
     buf[e] = g[(int64_t)m * s + c];
   }
   __syncthreads();
-  // in-place radix-2 decimation in frequency; output in bit-reversed order
+  // in-place radix-2 decimation in frequency; output in bit-reversed order.
+  // Pairs of stages (spans S and S/2) run as one radix-4 step per thread on
+  // x[i], x[i + S/2], x[i + S], x[i + 3S/2] (i = 2S-block base + r, r < S/2):
+  //   y0 = x0 + x2, y2 = (x0 - x2) w_{2S}^r, y1 = x1 + x3, y3 = (x1 - x3) w_{2S}^r i,
+  //   z0 = y0 + y1, z1 = (y0 - y1) w_S^r,   z2 = y2 + y3, z3 = (y2 - y3) w_S^r,
+  // exactly the two radix-2 stages (w_{2S}^{r + S/2} = w_{2S}^r i and
+  // w_S^r = (w_{2S}^r)^2 taken from the table), with one LDS round trip and one
+  // barrier instead of two; an odd stage count ends with one radix-2 stage.
   const int tstride = kTwiddleN >> lp;   // w_np^r = w_4096^{r * 4096/np}
-  for (int span = np >> 1, lspan = lp - 1; span >= 1; span >>= 1, --lspan) {
+  int span = np >> 1, lspan = lp - 1;
+  for (; span >= 2; span >>= 2, lspan -= 2) {
+    const int h = span >> 1;             // S/2
+    const int ng = (np >> 2) << lcols;   // radix-4 groups per step
+    for (int bi = threadIdx.x; bi < ng; bi += 256) {
+      const int c = bi & (cols - 1);
+      const int q = bi >> lcols;                 // 0 .. np/4 - 1
+      const int r = q & (h - 1);
+      const int i0 = ((q >> (lspan - 1)) << (lspan + 1)) + r;
+      C x0 = buf[i0 * cols + c], x1 = buf[(i0 + h) * cols + c];
+      C x2 = buf[(i0 + span) * cols + c], x3 = buf[(i0 + span + h) * cols + c];
+      const C w = twiddle[(r << (lp - 1 - lspan)) * tstride];        // w_{2S}^r
+      const C w2 = twiddle[(r << (lp - lspan)) * tstride];           // w_S^r
+      C y0, y1, y2, y3, d;
+      y0.x = x0.x + x2.x; y0.y = x0.y + x2.y;
+      d.x = x0.x - x2.x; d.y = x0.y - x2.y;
+      y2.x = d.x * w.x - d.y * w.y; y2.y = d.x * w.y + d.y * w.x;
+      y1.x = x1.x + x3.x; y1.y = x1.y + x3.y;
+      d.x = x1.x - x3.x; d.y = x1.y - x3.y;
+      // (d w) i
+      y3.x = -(d.x * w.y + d.y * w.x); y3.y = d.x * w.x - d.y * w.y;
+      C z0, z1, z2, z3;
+      z0.x = y0.x + y1.x; z0.y = y0.y + y1.y;
+      d.x = y0.x - y1.x; d.y = y0.y - y1.y;
+      z1.x = d.x * w2.x - d.y * w2.y; z1.y = d.x * w2.y + d.y * w2.x;
+      z2.x = y2.x + y3.x; z2.y = y2.y + y3.y;
+      d.x = y2.x - y3.x; d.y = y2.y - y3.y;
+      z3.x = d.x * w2.x - d.y * w2.y; z3.y = d.x * w2.y + d.y * w2.x;
+      buf[i0 * cols + c] = z0;
+      buf[(i0 + h) * cols + c] = z1;
+      buf[(i0 + span) * cols + c] = z2;
+      buf[(i0 + span + h) * cols + c] = z3;
+    }
+    __syncthreads();
+  }
+  for (; span >= 1; span >>= 1, --lspan) {
     const int nb = (np >> 1) << lcols;   // butterflies per stage
     for (int bi = threadIdx.x; bi < nb; bi += 256) {
       const int c = bi & (cols - 1);
