@@ -363,6 +363,7 @@ struct ftp_plan {
   std::vector<FftGridPass> h_fft;
   std::vector<int64_t> h_items;
   std::vector<int64_t> fft_round_tab_off, fft_round_n, fft_round_items;
+  std::vector<int> fft_round_el;   // log2 of the largest LDS block (elements) a round's passes use
   // per-chunk tables (lightcurve plans, offsets, FFT passes) packed into one
   // pinned host buffer and sent with one copy; the d_* pointers point into
   // d_stage
@@ -566,8 +567,9 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
   const C* tw = reinterpret_cast<const C*>(P->opt.precision == FTP_FP64 ? P->twiddle64.p : P->twiddle32.p);
   int64_t item_base = 0;
   for (size_t r = 0; r < P->fft_round_n.size(); ++r) {
+    // LDS for the round's largest block only (more workgroups per CU)
     hipLaunchKernelGGL(k_fft_pass<R>, dim3((unsigned)P->fft_round_items[r]), dim3(256),
-                       sizeof(C) << fft_max_el(P->opt.precision), st,
+                       sizeof(C) << P->fft_round_el[r], st,
                        P->d_fft + P->fft_round_tab_off[r], P->fft_round_n[r], P->d_items + item_base, tw,
                        P->grids.as<C>());
     item_base += P->fft_round_n[r] + 1;
@@ -588,10 +590,12 @@ void build_fft_tables(ftp_plan* P) {
   P->fft_round_tab_off.clear();
   P->fft_round_n.clear();
   P->fft_round_items.clear();
+  P->fft_round_el.clear();
   for (int r = 0; r < max_pass; ++r) {
     P->fft_round_tab_off.push_back((int64_t)tab.size());
     int64_t it = 0;
     int64_t cnt = 0;
+    int el = 0;
     for (const LcInfo& L : P->h_lc) {
       for (int g = 0; g < 2; ++g) {
         if (L.npass[g] <= r) continue;
@@ -605,6 +609,7 @@ void build_fft_tables(ftp_plan* P) {
         fp.ls = fp.log2n - consumed;
         const int maxel = fft_max_el(P->opt.precision);
         fp.lcols = std::min(fp.ls, std::min(4, maxel - fp.lp));
+        el = std::max(el, fp.lp + fp.lcols);
         tab.push_back(fp);
         it += 1LL << (fp.log2n - fp.lp - fp.lcols);
         ++cnt;
@@ -612,6 +617,7 @@ void build_fft_tables(ftp_plan* P) {
     }
     P->fft_round_n.push_back(cnt);
     P->fft_round_items.push_back(it);
+    P->fft_round_el.push_back(el);
   }
   // item_begin arrays per round, laid out after each other (with sentinel)
   for (int r = 0; r < max_pass; ++r) {

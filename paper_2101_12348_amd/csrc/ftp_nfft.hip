@@ -571,10 +571,24 @@ __global__ __launch_bounds__(256) void k_fft_pass(const FftGridPass* __restrict_
   const int64_t j0b = (local_item % groups_per_block) << lcols;
   C* g = grids + P.grid_off + blk * ((int64_t)np << ls) + j0b;
   const int total = np << lcols;
-  // load: element (m, c) -> buf[m * cols + c]
-  for (int e = threadIdx.x; e < total; e += 256) {
-    const int m = e >> lcols, c = e & (cols - 1);
-    buf[e] = g[(int64_t)m * s + c];
+  // load: element (m, c) -> buf[m * cols + c], eight loads in flight per
+  // thread (total is a multiple of 2048 whenever it exceeds it)
+  if (total >= 8 * 256) {
+    for (int e0 = threadIdx.x; e0 < total; e0 += 8 * 256) {
+      C v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256;
+        v[u] = g[(int64_t)(e >> lcols) * s + (e & (cols - 1))];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) buf[e0 + u * 256] = v[u];
+    }
+  } else {
+    for (int e = threadIdx.x; e < total; e += 256) {
+      const int m = e >> lcols, c = e & (cols - 1);
+      buf[e] = g[(int64_t)m * s + c];
+    }
   }
   __syncthreads();
   // in-place radix-2 decimation in frequency; output in bit-reversed order.
