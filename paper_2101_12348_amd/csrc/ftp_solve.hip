@@ -618,7 +618,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int q = lane; q < H; q += 64) W.al[q] = a.n_band ? make_double2(1.0, 0.0) : a.alpha[q];
   wave_sync();
   const double floor_mm = a.n_band ? a.mm_tau * a.lcs[0].mm_scale : mm_floor(W, H, a.mm_tau);
+  // the record fields each lane needs (lane d <= K: r_d; e <= 2H: mu_e;
+  // k < H: eta, Z_w; c < D: candidate c; D <= 64) are loaded one pair ahead,
+  // so their latency overlaps the scoring of the current pair
+  struct Fields { double2 r, mu, eta, zw; double cand; };
+  auto fetch = [&](int64_t w) {
+    Fields f;
+    f.r = f.mu = f.eta = f.zw = make_double2(0.0, 0.0);
+    f.cand = 0.0;
+    if (w < np) {
+      const double* R = rec + w * (int64_t)RL.stride;
+      if (lane <= K) f.r = make_double2(R[RL.r + 2 * lane], R[RL.r + 2 * lane + 1]);
+      if (lane <= 2 * H) f.mu = make_double2(R[RL.mu + 2 * lane], R[RL.mu + 2 * lane + 1]);
+      if (lane < H) {
+        f.eta = make_double2(R[RL.eta + 2 * lane], R[RL.eta + 2 * lane + 1]);
+        f.zw = make_double2(R[RL.zw + 2 * lane], R[RL.zw + 2 * lane + 1]);
+      }
+      if (lane < D) f.cand = R[RL.cand + lane];
+    }
+    return f;
+  };
+  Fields nxt = fetch(blockIdx.x);
   for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
+    const Fields cur = nxt;
+    nxt = fetch(w + gridDim.x);
     const int64_t pidx = p0 + w;
     const double* Rr = rec + w * (int64_t)RL.stride;
     const int st = (int)Rr[RL.meta + M_STATUS];
@@ -632,13 +655,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       continue;
     }
     const double ref = Rr[RL.meta + M_REF];
-    for (int d = lane; d <= K; d += 64) W.r[d] = make_double2(Rr[RL.r + 2 * d], Rr[RL.r + 2 * d + 1]);
-    for (int e = lane; e <= 2 * H; e += 64) W.mu[e] = make_double2(Rr[RL.mu + 2 * e], Rr[RL.mu + 2 * e + 1]);
-    for (int k = lane; k < H; k += 64) {
-      W.eta[k + 1] = make_double2(Rr[RL.eta + 2 * k], Rr[RL.eta + 2 * k + 1]);
+    if (lane <= K) W.r[lane] = cur.r;
+    if (lane <= 2 * H) W.mu[lane] = cur.mu;
+    if (lane < H) {
+      W.eta[lane + 1] = cur.eta;
       // the conjugated psi^k coefficient of Mbar, conj(alpha_k conj(Z_k))
-      const double2 z = make_double2(Rr[RL.zw + 2 * k], Rr[RL.zw + 2 * k + 1]);
-      W.Z[k + 1] = cconj(cmul(W.al[k], cconj(z)));
+      W.Z[lane + 1] = cconj(cmul(W.al[lane], cconj(cur.zw)));
     }
     if (lane == 0) W.eta[0] = make_double2(0.0, 0.0);
     wave_sync();
@@ -649,7 +671,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       th = -kTwoPi * ref;
       valid = lane == 0;
     } else if (lane < D) {
-      th = Rr[RL.cand + lane];
+      th = cur.cand;
       valid = !isnan(th);
       if (!valid) th = 0.0;
     }
