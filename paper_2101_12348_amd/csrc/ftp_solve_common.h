@@ -325,12 +325,14 @@ __host__ __device__ inline float bf2f(uint16_t b) {
 // and positive) and scaled to max |p_k| = 1, as (Re, Im) bf16 pairs written
 // to x[2k], x[2k + 1].  p_{K+d} = -i r'_d with r'_d = r_d u^d, r'_{-d} =
 // conj(r'_d) and u = e^{-i canon} = conj(r_1) / |r_1|, u^|d| by repeated
-// squaring.  Returns canon = arg r_1 (0 when r_1 = 0).
+// squaring.  Returns canon = arg r_1 to single precision (0 when r_1 = 0).
 __device__ __forceinline__ double pair_features(const double2* r, int K, int lane, uint16_t* x) {
   const int D = 2 * K;
   const double2 r1 = r[1];
   const double m1 = sqrt(r1.x * r1.x + r1.y * r1.y);
-  const double canon = m1 > 0.0 ? atan2(r1.y, r1.x) : 0.0;
+  // canon only maps network seeds (and training labels) between frames, where
+  // Newton refines whatever it is given: single precision is enough
+  const double canon = m1 > 0.0 ? (double)atan2f((float)r1.y, (float)r1.x) : 0.0;
   const double2 u = m1 > 0.0 ? make_double2(r1.x / m1, -r1.y / m1) : make_double2(1.0, 0.0);
   double2 v[2];
   double amax = 0.0;
