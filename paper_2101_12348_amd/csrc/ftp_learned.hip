@@ -189,21 +189,6 @@ __device__ int sturm_count_line_reg(double gv, int D, int lane) {
   return c.ok ? c.vm - c.vp : -1;
 }
 
-// Per-half maximum of |v| from the high words (as wave_max_abs_hi): the row
-// stages, then row_bcast:15 into rows 1 and 3 leave the maximum of lanes
-// 0..31 in lane 31 and of lanes 32..63 in lane 63.
-__device__ __forceinline__ void half_max_abs_hi(double v, double& m_lo, double& m_hi) {
-  int h = (int)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffff;
-  h = max(h, dpp_i<0xB1, 0xf>(h));
-  h = max(h, dpp_i<0x4E, 0xf>(h));
-  h = max(h, dpp_i<0x141, 0xf>(h));
-  h = max(h, dpp_i<0x140, 0xf>(h));
-  h = max(h, dpp_i<0x142, 0xa>(h));
-  const int lo = __builtin_amdgcn_readlane(h, 31), hi = __builtin_amdgcn_readlane(h, 63);
-  m_lo = __longlong_as_double((long long)((unsigned long long)(unsigned)lo << 32));
-  m_hi = __longlong_as_double((long long)((unsigned long long)(unsigned)hi << 32));
-}
-
 // The same for two polynomials at once (two frequencies of one wavefront).
 // While a member still has more than 32 coefficients the two chains are
 // stepped side by side over the whole wave; from step D - 29 on, every

@@ -552,6 +552,131 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
+// Two frequencies per wavefront (single band, sums from the grids, D < 64):
+// frequencies 2b and 2b + 1 of the chunk on lanes 0..31 and 32..63, each half
+// with its own LDS working set.  The assembly's per-frequency loops have 3H,
+// 2H + 1, K + 1 or 16 lanes of work, which a half-wave holds, so one
+// instruction stream serves two frequencies; the Cayley dot products (D + 1
+// columns) take two rounds of 32.  Maxima and the rotation argmax are reduced
+// per half (row broadcast into lanes 31 and 63).  A pair with status
+// "constant" or from a rejected lightcurve still runs the (cheap) rotation and
+// dot products of its half, whose results are not written.
+template <typename R>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble2(SolveArgs a, double* rec,
+                                                                                          int64_t p0, int64_t np) {
+  extern __shared__ double sma[];
+  const int lane = wave_lane(), half = lane >> 5, hl = lane & 31;
+  const int H = a.H, K = 3 * H - 1, D = 2 * K;
+  const RecLayout RL(H);
+  const size_t per = asm_lds_bytes(H, 0) / sizeof(double);
+  AsmLayout S = asm_layout(sma + half * per, H, 0);
+  const FreqWork& W = S.W;
+  for (int q = hl; q < H; q += 32) S.W.al[q] = a.alpha[q];
+  wave_sync();
+  double tab_c, tab_s;
+  sincos(kTwoPi * (lane & 15) / 16.0, &tab_s, &tab_c);
+  const typename Cplx<R>::T* grids = reinterpret_cast<const typename Cplx<R>::T*>(a.grids);
+  for (int64_t w0 = 2 * (int64_t)blockIdx.x; w0 < np; w0 += 2 * (int64_t)gridDim.x) {
+    const bool has = w0 + half < np;                    // an empty second half repeats the first
+    const int64_t w = has ? w0 + half : w0;
+    const int64_t pidx = p0 + w;
+    double* Rr = rec + w * (int64_t)RL.stride;
+    const int64_t lc = find_seg(a.freq_off, a.n_lc, pidx);
+    const LcInfo& L = a.lcs[lc];
+    const int64_t j = pidx - a.freq_off[lc] + 1;
+    const bool bad = L.status != 0;
+    if (hl == 0) W.Z[0] = make_double2(1.0, 0.0);
+    for (int q = hl; q < 3 * H; q += 32) {
+      const int g = q < 2 * H ? 0 : 1;
+      const int k = g == 0 ? q + 1 : q - 2 * H + 1;
+      W.Z[q + 1] = bad ? make_double2(0.0, 0.0) : gather_mode<R>(L, g, (int64_t)k * j, grids);
+    }
+    wave_sync();
+    assemble_poly(W, H, hl, S.hb[0], 32);
+    const double ref = ref_cycles(j, L.df, L.tref);
+    double rmax = 0.0, mumax = 0.0, etamax = 0.0;
+    for (int d = hl; d <= K; d += 32) rmax = fmax(rmax, sqrt(cabs2(W.r[d])));
+    for (int e = hl; e <= 2 * H; e += 32) mumax = fmax(mumax, sqrt(cabs2(W.mu[e])));
+    for (int k = hl; k <= H; k += 32) etamax = fmax(etamax, sqrt(cabs2(W.eta[k])));
+    {
+      double lo, hi;
+      half_max_abs_hi(rmax, lo, hi);
+      rmax = half ? hi : lo;
+      half_max_abs_hi(mumax, lo, hi);
+      mumax = half ? hi : lo;
+      half_max_abs_hi(etamax, lo, hi);
+      etamax = half ? hi : lo;
+    }
+    const double rscale = mumax * etamax * (6.0 * H) * (2.0 * H + 1.0);
+    const bool constant = !(rmax > 64.0 * kEps * rscale);
+    // rotation phi0: the 16 candidates of each half on its lanes 0..15
+    double Rv = -1.0;
+    if (hl < 16) Rv = fabs(eval_R_value(W, H, kTwoPi * hl / 16.0 + kPi));
+    double rm;
+    {
+      double lo, hi;
+      half_max_d(Rv, lo, hi);
+      rm = half ? hi : lo;
+    }
+    const unsigned long long mask = __ballot(hl < 16 && Rv == rm);
+    const unsigned hm = half ? (unsigned)(mask >> 32) : (unsigned)mask;
+    const int k0 = hm ? __ffs(hm) - 1 : 0;
+    const double phi0 = constant ? 0.0 : kTwoPi * k0 / 16.0;
+    // rho_j = r_{j-K} e^{i (j-K) phi0}, j = 0..D, in two rounds of 32 (every
+    // lane takes part in the table reads), then the dot products
+    double* rx = reinterpret_cast<double*>(S.hb[0]);
+    double* ry = rx + (D + 1);
+    for (int rr = 0; rr < 2; ++rr) {
+      const int jx = hl + 32 * rr, d = jx - K;
+      const int m = (d * k0) & 15;
+      const double ec = __shfl(tab_c, m), es = __shfl(tab_s, m);
+      if (jx <= D) {
+        const double2 rho = cmul(d >= 0 ? W.r[d] : cconj(W.r[d < 0 ? -d : 0]), make_double2(ec, es));
+        rx[jx] = rho.x;
+        ry[jx] = rho.y;
+      }
+    }
+    wave_sync();
+    const bool write = has && !bad;
+    for (int c = hl; c <= D; c += 32) {
+      const double* rc = (c & 1) ? ry : rx;
+      const double* col = a.ctab + c;
+      double acc0 = 0.0, acc1 = 0.0;
+      int jx = 0;
+      for (; jx + 1 <= D; jx += 2) {
+        acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
+        acc1 = fma(rc[jx + 1], col[(jx + 1) * (D + 1)], acc1);
+      }
+      if (jx <= D) acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
+      if (write && !constant) Rr[RL.f + c] = acc0 + acc1;
+    }
+    if (write) {
+      for (int d = hl; d <= K; d += 32) { Rr[RL.r + 2 * d] = W.r[d].x; Rr[RL.r + 2 * d + 1] = W.r[d].y; }
+      for (int e = hl; e <= 2 * H; e += 32) { Rr[RL.mu + 2 * e] = W.mu[e].x; Rr[RL.mu + 2 * e + 1] = W.mu[e].y; }
+      for (int k = hl; k < H; k += 32) {
+        Rr[RL.eta + 2 * k] = W.eta[k + 1].x;
+        Rr[RL.eta + 2 * k + 1] = W.eta[k + 1].y;
+        Rr[RL.zw + 2 * k] = W.Z[k + 1].x;
+        Rr[RL.zw + 2 * k + 1] = W.Z[k + 1].y;
+      }
+      if (hl == 0) {
+        Rr[RL.meta + M_PHI0] = phi0;
+        Rr[RL.meta + M_REF] = ref;
+        Rr[RL.meta + M_STATUS] = constant ? (double)ST_CONSTANT : (double)ST_OK;
+        Rr[RL.meta + M_LC] = (double)lc;
+        Rr[RL.meta + M_FALLBACK] = 0.0;
+        Rr[RL.meta + M_WARM] = 0.0;
+      }
+    } else if (has && hl == 0) {
+      Rr[RL.meta + M_STATUS] = (double)ST_BAD_LC;
+      Rr[RL.meta + M_LC] = (double)lc;
+      Rr[RL.meta + M_FALLBACK] = 0.0;
+      Rr[RL.meta + M_WARM] = 0.0;
+    }
+    wave_sync();
+  }
+}
+
 // ---------------------------------------------------------------- score
 
 // Best-candidate selection across the wave: max P; near ties (1e-12 relative)
@@ -819,6 +944,16 @@ hipError_t launch_qr(int H, double* rec, int stride, int64_t np, const int64_t* 
 
 hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64_t p0, int64_t np, int waves,
                            hipStream_t st) {
+  if (a.n_band == 0 && !a.sums_in && 6 * a.H - 2 < 64) {
+    // two frequencies per wavefront
+    const size_t lds2 = 2 * asm_lds_bytes(a.H, 0);
+    const int w2 = (int)std::max<int64_t>(1, std::min<int64_t>(waves, (np + 1) / 2));
+    if (precision == 1)
+      hipLaunchKernelGGL(k_assemble2<double>, dim3((unsigned)w2), dim3(64), lds2, st, a, rec, p0, np);
+    else
+      hipLaunchKernelGGL(k_assemble2<float>, dim3((unsigned)w2), dim3(64), lds2, st, a, rec, p0, np);
+    return hipGetLastError();
+  }
   const size_t lds = asm_lds_bytes(a.H, a.n_band);
   if (precision == 1)
     hipLaunchKernelGGL(k_assemble<double>, dim3((unsigned)waves), dim3(64), lds, st, a, rec, p0, np);

@@ -160,6 +160,37 @@ __device__ __forceinline__ double wave_max_abs_hi(double v) {
   return __longlong_as_double((long long)((unsigned long long)(unsigned)h << 32));
 }
 
+// Per-half maximum of |v| from the high words (as wave_max_abs_hi): the row
+// stages, then row_bcast:15 into rows 1 and 3 leave the maximum of lanes
+// 0..31 in lane 31 and of lanes 32..63 in lane 63.
+__device__ __forceinline__ void half_max_abs_hi(double v, double& m_lo, double& m_hi) {
+  int h = (int)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffff;
+  h = max(h, dpp_i<0xB1, 0xf>(h));
+  h = max(h, dpp_i<0x4E, 0xf>(h));
+  h = max(h, dpp_i<0x141, 0xf>(h));
+  h = max(h, dpp_i<0x140, 0xf>(h));
+  h = max(h, dpp_i<0x142, 0xa>(h));
+  const int lo = __builtin_amdgcn_readlane(h, 31), hi = __builtin_amdgcn_readlane(h, 63);
+  m_lo = __longlong_as_double((long long)((unsigned long long)(unsigned)lo << 32));
+  m_hi = __longlong_as_double((long long)((unsigned long long)(unsigned)hi << 32));
+}
+
+// Exact per-half maximum of doubles: row stages of wave_max, then
+// row_bcast:15 into rows 1 and 3; lane 31 holds the maximum of lanes 0..31,
+// lane 63 that of lanes 32..63 (rows 0 and 2 end with unspecified values).
+__device__ __forceinline__ void half_max_d(double v, double& m_lo, double& m_hi) {
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  v = fmax(v, dpp_d<0x140>(v));
+  const long long u = __double_as_longlong(v);
+  const int blo = __builtin_amdgcn_mov_dpp((int)u, 0x142, 0xa, 0xf, true);
+  const int bhi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0x142, 0xa, 0xf, true);
+  v = fmax(v, __longlong_as_double(((long long)bhi << 32) | (long long)(unsigned)blo));
+  m_lo = lane_d(v, 31);
+  m_hi = lane_d(v, 63);
+}
+
 // Position of mode index q (0 <= q < n) in the digit-reversed FFT output.
 __device__ __forceinline__ int64_t fft_pos(int64_t q, const LcInfo& L, int g) {
   int64_t pos = 0;
@@ -215,12 +246,15 @@ struct FreqWork {
 //   YM(psi) = sum_k a_k conj(Zy_k) psi^k + c.c.   (YC~_k = conj(Zy_k)),
 //   R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta = sum_d r_d psi^d,
 //   r_d = i sum_k (3k - d) mu_{d-k} eta_k   (Eq. finalpoly with p = -i psi^K R).
-__device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane, double2* scr);
+__device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane, double2* scr, int nl = 64);
 
-// `scr`: LDS scratch of 8H + 2 complex values for assemble_r.
-__device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane, double2* scr) {
+// `scr`: LDS scratch of 8H + 2 complex values for assemble_r.  `lane` counts
+// within a group of `nl` lanes working on one frequency (64: the wavefront; 32:
+// a half-wave, two frequencies per wavefront); every lane of the wavefront
+// calls this.
+__device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane, double2* scr, int nl = 64) {
   const int K = 3 * H - 1;
-  for (int e = lane; e <= 2 * H; e += 64) {
+  for (int e = lane; e <= 2 * H; e += nl) {
     double2 acc = make_double2(0.0, 0.0);
     if (e == 0) {
       double s = 0.0;
@@ -242,11 +276,11 @@ __device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane
     }
     W.mu[e] = acc;
   }
-  for (int k = lane; k <= H; k += 64) {
+  for (int k = lane; k <= H; k += nl) {
     W.eta[k] = k == 0 ? make_double2(0.0, 0.0) : cmul(W.al[k - 1], cconj(W.Z[2 * H + k]));
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier();
-  assemble_r(W, H, lane, scr);
+  assemble_r(W, H, lane, scr, nl);
 }
 
 // r_d, d = 0..K, of R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta from the trig
@@ -254,20 +288,20 @@ __device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane
 // The coefficients are first laid out over their full index ranges (mu_e for
 // e = -2H..4H with mu_{-e} = conj mu_e and zero beyond 2H, eta_k for k = -H..H
 // with eta_0 = 0) so that the sum over k has no branches.
-__device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane, double2* scr) {
+__device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane, double2* scr, int nl) {
   const int K = 3 * H - 1;
   double2* mf = scr;               // mf[e + 2H], e = -2H .. 4H
   double2* ef = scr + 6 * H + 1;   // ef[k + H], k = -H .. H
-  for (int i = lane; i <= 6 * H; i += 64) {
+  for (int i = lane; i <= 6 * H; i += nl) {
     const int e = i - 2 * H;
     mf[i] = e < 0 ? cconj(W.mu[-e]) : (e <= 2 * H ? W.mu[e] : make_double2(0.0, 0.0));
   }
-  for (int i = lane; i <= 2 * H; i += 64) {
+  for (int i = lane; i <= 2 * H; i += nl) {
     const int k = i - H;
     ef[i] = k < 0 ? cconj(W.eta[-k]) : W.eta[k];
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier();
-  for (int d = lane; d <= K; d += 64) {
+  for (int d = lane; d <= K; d += nl) {
     double2 acc = make_double2(0.0, 0.0);
     double s = (double)(-3 * H - d);   // 3k - d
     for (int k = -H; k <= H; ++k, s += 3.0) {
