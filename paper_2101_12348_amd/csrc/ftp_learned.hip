@@ -10,8 +10,10 @@
 //     starts (only evenly spaced starts for the ablation without network) are
 //     refined by FP64 Newton on R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta
 //     (Eq. theta2cond written as R(theta) = i e^{-i K theta} p(e^{i theta}));
-//     converged roots closer than 1e-8 rad are merged after iterations 4-8, 10
-//     and 12, and Newton stops once the merged roots reach the count;
+//     converged roots closer than 1e-8 rad are merged after every iteration
+//     from the fourth (two-frequency kernel; after iterations 4-8, 10 and 12
+//     in the one-frequency kernel), and Newton stops once the merged roots
+//     reach the count;
 //   * if they do, the Newton roots are the candidate set; otherwise the
 //     frequency goes to the Aberth iteration (then, if that does not
 //     converge, to the companion-matrix solve) through device work lists.
@@ -492,7 +494,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           if (fabs(sc) < 1e-12) conv = true;
         }
       }
-      if ((it >= 4 && it <= 8) || it == 10 || it == 12) {
+      if (it >= 4) {   // merges are incremental, so every iteration from the fourth checks
         const unsigned long long cm = __ballot(conv);
         const bool needA = !doneA && __popcll(cm & lo32) >= cA;
         const bool needB = !doneB && __popcll(cm >> 32) >= cB;
