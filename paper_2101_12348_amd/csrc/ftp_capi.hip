@@ -47,7 +47,8 @@ hipError_t launch_qr(int H, double* rec, int stride, int64_t np, const int64_t* 
 hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64_t p0, int64_t np, int waves,
                            hipStream_t st);
 hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves,
-                        hipStream_t st);
+                        hipStream_t st, const int64_t* list = nullptr, const unsigned* list_n = nullptr);
+hipError_t launch_score2(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves, hipStream_t st);
 hipError_t launch_gather_sums(int precision, const SolveArgs& a, double* out, int blocks, hipStream_t st);
 hipError_t launch_export_stats(const LcInfo* lcs, double* out, hipStream_t st);
 struct GemmArgs {
@@ -797,7 +798,13 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
     } else {
       SolveArgs as = a;
       as.newton_cands = solver == FTP_SOLVER_LEARNED || solver == FTP_SOLVER_UNIFORM;
-      HIP_TRY(launch_score(as, rec, p0, np, w_sc, st));
+      if (as.newton_cands && 4 * P->H <= 32) {
+        // Newton-root pairs two per wavefront, then the fallback list
+        HIP_TRY(launch_score2(as, rec, p0, np, w_sc, st));
+        HIP_TRY(launch_score(as, rec, p0, np, w_sc, st, P->fb_list.as<int64_t>(), ctr));
+      } else {
+        HIP_TRY(launch_score(as, rec, p0, np, w_sc, st));
+      }
     }
   }
   return FTP_OK;

@@ -724,7 +724,10 @@ __host__ __device__ inline size_t score_lds_bytes(int H) {
 // Scores all candidates of pairs [p0, p0 + np) and writes the outputs.  At
 // least four waves per SIMD (at most 128 VGPRs, no spills; measured faster
 // than five waves with spills, or than the uncapped allocation).
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_score(SolveArgs a, const double* rec, int64_t p0, int64_t np) {
+// `list` (device, *list_n entries): score only those pairs of the chunk.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_score(SolveArgs a, const double* rec, int64_t p0, int64_t np,
+                                                                                      const int64_t* list,
+                                                                                      const unsigned* list_n) {
   extern __shared__ double sms[];
   const int lane = wave_lane();
   const int H = a.H, K = 3 * H - 1, D = 2 * K;
@@ -747,12 +750,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   // k < H: eta, Z_w; c < D: candidate c; D <= 64) are loaded one pair ahead,
   // so their latency overlaps the scoring of the current pair
   struct Fields { double2 r, mu, eta, zw; double cand; };
-  auto fetch = [&](int64_t w) {
+  const int64_t n = list ? (int64_t)*list_n : np;
+  auto item = [&](int64_t i) { return list ? list[i] : i; };
+  auto fetch = [&](int64_t i) {
     Fields f;
     f.r = f.mu = f.eta = f.zw = make_double2(0.0, 0.0);
     f.cand = 0.0;
-    if (w < np) {
-      const double* R = rec + w * (int64_t)RL.stride;
+    if (i < n) {
+      const double* R = rec + item(i) * (int64_t)RL.stride;
       if (lane <= K) f.r = make_double2(R[RL.r + 2 * lane], R[RL.r + 2 * lane + 1]);
       if (lane <= 2 * H) f.mu = make_double2(R[RL.mu + 2 * lane], R[RL.mu + 2 * lane + 1]);
       if (lane < H) {
@@ -764,9 +769,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     return f;
   };
   Fields nxt = fetch(blockIdx.x);
-  for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
     const Fields cur = nxt;
-    nxt = fetch(w + gridDim.x);
+    nxt = fetch(i + gridDim.x);
+    const int64_t w = item(i);
     const int64_t pidx = p0 + w;
     const double* Rr = rec + w * (int64_t)RL.stride;
     const int st = (int)Rr[RL.meta + M_STATUS];
@@ -844,6 +850,116 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const double fb = Rr[RL.meta + M_FALLBACK];
       const int fbits = fb >= 2.0 ? (ST_FALLBACK | ST_FALLBACK_QR) : (fb != 0.0 ? ST_FALLBACK : 0);
       if (a.status) a.status[pidx] = (uint8_t)(stout | fbits);
+    }
+    wave_sync();
+  }
+}
+
+// select_best within each half-wave (the tie rule of select_best).
+__device__ __forceinline__ Best select_best_half(double P, double th_rel, double th_abs, double ym, bool valid,
+                                                 int lane) {
+  const int half = lane >> 5;
+  const double pv = valid ? P : -1.0;
+  double lo, hi;
+  half_max_d(pv, lo, hi);
+  const double pmax = half ? hi : lo;
+  const bool near = valid && pv >= pmax - 1e-12 * fmax(pmax, 1e-300);
+  const double key = near ? ((ym > 0.0 ? 0.0 : 8.0) + th_abs) : 1e30;
+  half_max_d(-key, lo, hi);
+  const double kmin = -(half ? hi : lo);
+  const unsigned long long mask = __ballot(near && key == kmin);
+  const unsigned hm = half ? (unsigned)(mask >> 32) : (unsigned)mask;
+  Best b;
+  b.lane = (hm ? __ffs(hm) - 1 : 0) + 32 * half;
+  b.P = __shfl(pv, b.lane);
+  b.th_rel = __shfl(th_rel, b.lane);
+  b.th_abs = __shfl(th_abs, b.lane);
+  b.amp_sign = __shfl(ym, b.lane);
+  return b;
+}
+
+// Scoring of the pairs whose candidates are Newton-converged roots (learned
+// and uniform solvers with two frequencies per Newton wavefront: at most 32
+// roots, in candidate slots 0..31), two pairs per wavefront: frequencies 2b
+// and 2b + 1 on the half-waves, each with its own LDS working set, candidates
+// one per lane, maxima and the best candidate per half.  These candidates need
+// no polish.  Pairs sent to a fallback tier (M_FALLBACK != 0) are left to
+// k_score over the fallback list.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_score2(SolveArgs a, const double* rec,
+                                                                                       int64_t p0, int64_t np) {
+  extern __shared__ double sms[];
+  const int lane = wave_lane(), half = lane >> 5, hl = lane & 31;
+  const int H = a.H, K = 3 * H - 1, D = 2 * K;
+  const RecLayout RL(H);
+  FreqWork W;
+  {
+    double2* q = reinterpret_cast<double2*>(sms + half * (score_lds_bytes(H) / sizeof(double)));
+    W.Z = q; q += 3 * H + 1;
+    W.mu = q; q += 2 * H + 1;
+    W.eta = q; q += H + 1;
+    W.r = q; q += K + 1;
+    W.al = q;
+  }
+  for (int q = hl; q < H; q += 32) W.al[q] = a.n_band ? make_double2(1.0, 0.0) : a.alpha[q];
+  wave_sync();
+  const double floor_mm = a.n_band ? a.mm_tau * a.lcs[0].mm_scale : mm_floor(W, H, a.mm_tau);
+  const bool pos = (a.flags & kFlagPositiveAmp) != 0u;
+  for (int64_t w0 = 2 * (int64_t)blockIdx.x; w0 < np; w0 += 2 * (int64_t)gridDim.x) {
+    const bool has = w0 + half < np;
+    const int64_t w = has ? w0 + half : w0;
+    const int64_t pidx = p0 + w;
+    const double* Rr = rec + w * (int64_t)RL.stride;
+    const int st = (int)Rr[RL.meta + M_STATUS];
+    const bool mine = has && Rr[RL.meta + M_FALLBACK] == 0.0;
+    const int64_t lc = (int64_t)Rr[RL.meta + M_LC];
+    const LcInfo& L = a.lcs[lc];
+    const double ref = Rr[RL.meta + M_REF];
+    if (hl <= K) W.r[hl] = make_double2(Rr[RL.r + 2 * hl], Rr[RL.r + 2 * hl + 1]);
+    if (hl <= 2 * H) W.mu[hl] = make_double2(Rr[RL.mu + 2 * hl], Rr[RL.mu + 2 * hl + 1]);
+    if (hl < H) {
+      W.eta[hl + 1] = make_double2(Rr[RL.eta + 2 * hl], Rr[RL.eta + 2 * hl + 1]);
+      const double2 z = make_double2(Rr[RL.zw + 2 * hl], Rr[RL.zw + 2 * hl + 1]);
+      W.Z[hl + 1] = cconj(cmul(W.al[hl], cconj(z)));
+    }
+    if (hl == 0) W.eta[0] = make_double2(0.0, 0.0);
+    wave_sync();
+    double th = 0.0;
+    bool valid = false;
+    if (st == ST_CONSTANT) {
+      th = -kTwoPi * ref;
+      valid = hl == 0;
+    } else if (st != ST_BAD_LC && hl < D) {
+      th = Rr[RL.cand + hl];
+      valid = !isnan(th);
+      if (!valid) th = 0.0;
+    }
+    const Cand c = eval_candidate(W, H, th);
+    double lo, hi;
+    half_max_d(valid ? c.MM : -1.0, lo, hi);
+    const double mmmax = half ? hi : lo;
+    int stout = st;
+    if (st != ST_BAD_LC && mmmax <= floor_mm) stout = ST_DEGENERATE;
+    const bool ok = valid && (c.MM > floor_mm || stout == ST_DEGENERATE) && (!pos || c.YM > 0.0);
+    const unsigned long long okm = __ballot(ok);
+    const bool none = pos && stout != ST_DEGENERATE && (half ? (okm >> 32) : (okm & 0xffffffffull)) == 0ull;
+    const Best b = select_best_half(c.P, th, wrap_2pi(th + kTwoPi * ref), c.YM, ok, lane);
+    const Cand cb = {__shfl(c.P, b.lane), __shfl(c.YM, b.lane), __shfl(c.MM, b.lane), __shfl(c.Mbar, b.lane)};
+    if (hl == 0 && mine) {
+      if (st == ST_BAD_LC) {
+        a.power[pidx] = 0.0; a.phase[pidx] = 0.0; a.amp[pidx] = 0.0; a.offset[pidx] = 0.0;
+        if (a.status) a.status[pidx] = ST_BAD_LC;
+      } else {
+        const double sq = sqrt(L.yy);
+        double P = cb.P, amp = cb.MM > 0.0 ? cb.YM / cb.MM * sq : 0.0;
+        double off = L.ybar - cb.Mbar * amp;
+        double th_abs = wrap_2pi(b.th_rel + kTwoPi * ref);
+        if (stout == ST_DEGENERATE || none) { P = 0.0; amp = 0.0; off = L.ybar; th_abs = 0.0; }
+        a.power[pidx] = P;
+        a.phase[pidx] = th_abs;
+        a.amp[pidx] = amp;
+        a.offset[pidx] = off;
+        if (a.status) a.status[pidx] = (uint8_t)stout;
+      }
     }
     wave_sync();
   }
@@ -963,8 +1079,16 @@ hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64
 }
 
 hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_score, dim3((unsigned)waves), dim3(64), score_lds_bytes(a.H), st, a, rec, p0, np);
+                        hipStream_t st, const int64_t* list, const unsigned* list_n) {
+  hipLaunchKernelGGL(k_score, dim3((unsigned)waves), dim3(64), score_lds_bytes(a.H), st, a, rec, p0, np, list,
+                     list_n);
+  return hipGetLastError();
+}
+
+// Newton-candidate pairs two per wavefront (see k_score2).
+hipError_t launch_score2(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves, hipStream_t st) {
+  const int w2 = (int)std::max<int64_t>(1, std::min<int64_t>(waves, (np + 1) / 2));
+  hipLaunchKernelGGL(k_score2, dim3((unsigned)w2), dim3(64), 2 * score_lds_bytes(a.H), st, a, rec, p0, np);
   return hipGetLastError();
 }
 
