@@ -784,9 +784,9 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       hipEvent_t rc2 = next_learn_event(P);
       if (rc2) HIP_TRY(hipEventRecord(rc2, st));
       // what the Aberth tier leaves is usually nothing or a few frequencies:
-      // a launch of four waves per CU serves it through the queue
+      // a launch of one wave per CU serves it through the queue
       HIP_TRY(launch_qr(P->H, rec, RL.stride, np, P->fb2_list.as<int64_t>(), ctr + 1,
-                        P->counters.as<SolveCounters>(), ctr + 4, std::min(w_qr, (int)grid_waves(P, 4, np)), st));
+                        P->counters.as<SolveCounters>(), ctr + 4, std::min(w_qr, (int)grid_waves(P, 1, np)), st));
     }
     hipEvent_t r1 = next_root_event(P);
     if (r1) HIP_TRY(hipEventRecord(r1, st));
@@ -801,7 +801,8 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       if (as.newton_cands && 4 * P->H <= 32) {
         // Newton-root pairs two per wavefront, then the fallback list
         HIP_TRY(launch_score2(as, rec, p0, np, w_sc, st));
-        HIP_TRY(launch_score(as, rec, p0, np, w_sc, st, P->fb_list.as<int64_t>(), ctr));
+        HIP_TRY(launch_score(as, rec, p0, np, std::min(w_sc, (int)grid_waves(P, 2, np)), st,
+                             P->fb_list.as<int64_t>(), ctr));
       } else {
         HIP_TRY(launch_score(as, rec, p0, np, w_sc, st));
       }
