@@ -347,6 +347,64 @@ __global__ __launch_bounds__(64) void k_features(double* rec, int H, int64_t np,
   }
 }
 
+// Two pairs per wavefront (D < 64): the same features, pair 2b on lanes
+// 0..31 and 2b + 1 on lanes 32..63, coefficients in two rounds of 32 and the
+// scale from a per-half maximum.  Every lane runs the arithmetic (the per-half
+// reduction needs the whole wavefront); rejected or constant pairs then write
+// zeros instead.
+__global__ __launch_bounds__(64) void k_features2(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx) {
+  const RecLayout RL(H);
+  const int D = RL.D, K = RL.K;
+  const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
+  for (int64_t w0 = 2 * (int64_t)blockIdx.x; w0 < np; w0 += 2 * (int64_t)gridDim.x) {
+    const bool has = w0 + half < np;
+    const int64_t w = has ? w0 + half : w0;
+    double* R = rec + w * (int64_t)RL.stride;
+    const int st = (int)R[RL.meta + M_STATUS];
+    const bool zero = st == ST_BAD_LC || st == ST_CONSTANT;
+    const double2* r = reinterpret_cast<const double2*>(R + RL.r);
+    const double2 r1 = r[1];
+    const double m1 = sqrt(r1.x * r1.x + r1.y * r1.y);
+    const double canon = m1 > 0.0 ? (double)atan2f((float)r1.y, (float)r1.x) : 0.0;
+    const double2 u = m1 > 0.0 ? make_double2(r1.x / m1, -r1.y / m1) : make_double2(1.0, 0.0);
+    double2 v[2];
+    double amax = 0.0;
+    for (int s = 0; s < 2; ++s) {
+      const int k = hl + 32 * s;
+      v[s] = make_double2(0.0, 0.0);
+      if (k > D) continue;
+      const int d = k - K;
+      int ad = d < 0 ? -d : d;
+      double2 rd = r[ad];
+      double2 pw = make_double2(1.0, 0.0), b = u;
+      while (ad) {
+        if (ad & 1) pw = cmul(pw, b);
+        b = cmul(b, b);
+        ad >>= 1;
+      }
+      rd = cmul(rd, pw);
+      if (d < 0) rd = cconj(rd);
+      v[s] = make_double2(rd.y, -rd.x);   // -i (a + i b) = b - i a
+      amax = fmax(amax, sqrt(v[s].x * v[s].x + v[s].y * v[s].y));
+    }
+    double lo, hi;
+    half_max_d(amax, lo, hi);
+    amax = half ? hi : lo;
+    const double sc = amax > 0.0 ? 1.0 / amax : 0.0;
+    if (has) {
+      uint16_t* x = X + w * ldx;
+      for (int64_t q = 2 * (D + 1) + hl; q < ldx; q += 32) x[q] = 0;
+      for (int s = 0; s < 2; ++s) {
+        const int k = hl + 32 * s;
+        if (k > D) continue;
+        x[2 * k] = zero ? (uint16_t)0 : f2bf((float)(v[s].x * sc));
+        x[2 * k + 1] = zero ? (uint16_t)0 : f2bf((float)(v[s].y * sc));
+      }
+      if (hl == 0 && !zero) R[RL.meta + M_CANON] = canon;
+    }
+  }
+}
+
 // ------------------------------------------------------- fused inference
 
 // The four layers of the network for 64 pairs per workgroup:
@@ -541,7 +599,12 @@ hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st) {
 }
 
 hipError_t launch_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx, int waves, hipStream_t st) {
-  hipLaunchKernelGGL(k_features, dim3((unsigned)waves), dim3(64), 0, st, rec, H, np, X, ldx);
+  if (6 * H - 2 < 64) {
+    const int w2 = (int)std::max<int64_t>(1, std::min<int64_t>(waves, (np + 1) / 2));
+    hipLaunchKernelGGL(k_features2, dim3((unsigned)w2), dim3(64), 0, st, rec, H, np, X, ldx);
+  } else {
+    hipLaunchKernelGGL(k_features, dim3((unsigned)waves), dim3(64), 0, st, rec, H, np, X, ldx);
+  }
   return hipGetLastError();
 }
 
