@@ -86,8 +86,8 @@ def run_solver(F, plan, t, y, s, lc, out, steps, warmup):
     return ms_step, per
 
 
-# kernels behind each stage for H <= 8 (two frequencies per wavefront in the
-# Newton + Sturm kernel; the one-frequency k_newton_sturm serves H = 9..11)
+# kernels behind each stage for H <= 10 (two frequencies per wavefront in the
+# Newton + Sturm kernel; the one-frequency k_newton_sturm serves H = 11)
 KERNEL_OF_STAGE = {"plain_qr": "k_qr", "fallback_qr": "k_qr", "newton_sturm": "k_newton_sturm2",
                    "aberth": "k_aberth", "mlp_forward": "k_dense_bf16"}
 
@@ -432,7 +432,7 @@ def main():
         dom = "plain_qr"
     kernel_names = {"plain_qr": f"k_qr<{D}> (companion QR, FP64 vector)",
                     "fallback_qr": f"k_qr<{D}> on the Aberth tier's leftovers (FP64 vector)",
-                    "newton_sturm": ("k_newton_sturm2" if H <= 8 else "k_newton_sturm") + " (FP64 vector)",
+                    "newton_sturm": ("k_newton_sturm2" if H <= 10 else "k_newton_sturm") + " (FP64 vector)",
                     "aberth": "k_aberth (FP64 vector)",
                     "mlp_forward": "k_dense_bf16 (MFMA bf16)"}
     solvers = {}

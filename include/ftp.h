@@ -74,7 +74,7 @@ extern "C" {
 /* root solver */
 #define FTP_SOLVER_PLAIN 0     /* companion-matrix eigenvalues (Section 2) */
 #define FTP_SOLVER_LEARNED 1   /* 2H MLP seeds + evenly spaced starts (min(32, 6H - 2) starts in
-                                  all for H <= 8, 4H for H > 8), Newton, Sturm check; unconfirmed
+                                  all for H <= 10, 4H for H = 11), Newton, Sturm check; unconfirmed
                                   frequencies go to Aberth, then the companion solve */
 #define FTP_SOLVER_UNIFORM 2   /* as LEARNED with evenly spaced starts only (ablation: no network) */
 #define FTP_SOLVER_ABERTH 3    /* Aberth-Ehrlich iteration on every frequency; companion solve

@@ -798,7 +798,7 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
     } else {
       SolveArgs as = a;
       as.newton_cands = solver == FTP_SOLVER_LEARNED || solver == FTP_SOLVER_UNIFORM;
-      if (as.newton_cands && 4 * P->H <= 32) {
+      if (as.newton_cands && 6 * P->H - 2 < 64) {
         // Newton-root pairs two per wavefront, then the fallback list
         HIP_TRY(launch_score2(as, rec, p0, np, w_sc, st));
         HIP_TRY(launch_score(as, rec, p0, np, std::min(w_sc, (int)grid_waves(P, 2, np)), st,

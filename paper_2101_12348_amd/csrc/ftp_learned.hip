@@ -17,8 +17,8 @@
 //   * if they do, the Newton roots are the candidate set; otherwise the
 //     frequency goes to the Aberth iteration (then, if that does not
 //     converge, to the companion-matrix solve) through device work lists.
-// For H <= 8 a wavefront takes two frequencies (k_newton_sturm2, 32 starts
-// each, at most D); for H = 9..11 one (k_newton_sturm, 4H starts).  For
+// For H <= 10 a wavefront takes two frequencies (k_newton_sturm2, 32 starts
+// each, at most D); for H = 11 one (k_newton_sturm, 4H starts).  For
 // D + 1 <= 64 a single Sturm sequence of f over the whole real line is formed
 // in registers (sturm_count_line_reg); D = 64 (H = 11) uses the LDS form on
 // the two half circles.
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
-// Two frequencies per wavefront (H <= 8): frequencies 2b and 2b + 1 of the
+// Two frequencies per wavefront (H <= 10, D < 64): frequencies 2b and 2b + 1 of the
 // list.  Their two Sturm chains are stepped side by side (the chains are
 // serial, so a second independent one fills the latency of the first), then
 // Newton runs on both at once, lanes 0..31 for the first and 32..63 for the
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
-bool newton_two_per_wave(int H) { return 4 * H <= 32 && 6 * H - 2 < 64; }
+bool newton_two_per_wave(int H) { return 6 * H - 2 < 64; }
 
 hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st) {
   if (newton_two_per_wave(a.H)) {
