@@ -2,10 +2,9 @@
 // real phase polynomial from network seeds, verified by a Sturm count.
 //
 // For each frequency (one wavefront):
-//   * the number of distinct real roots of R is counted with Sturm sequences
-//     of the Cayley polynomial f(x) (theta = phi0 + 2 atan x): over the whole
-//     real line, or on two half circles, x in (-1, 1] for f and for
-//     x^D f(-1/x) (the map rotated by pi);
+//   * the number of distinct real roots of R is counted with a Sturm sequence
+//     of the Cayley polynomial f(x) (theta = phi0 + 2 atan x) over the whole
+//     real line;
 //   * if the count is well determined, 2H network seeds plus evenly spaced
 //     starts (only evenly spaced starts for the ablation without network) are
 //     refined by FP64 Newton on R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta
@@ -18,10 +17,9 @@
 //     frequency goes to the Aberth iteration (then, if that does not
 //     converge, to the companion-matrix solve) through device work lists.
 // For H <= 10 a wavefront takes two frequencies (k_newton_sturm2, 32 starts
-// each, at most D); for H = 11 one (k_newton_sturm, 4H starts).  For
-// D + 1 <= 64 a single Sturm sequence of f over the whole real line is formed
-// in registers (sturm_count_line_reg); D = 64 (H = 11) uses the LDS form on
-// the two half circles.
+// each, at most D); for H = 11 one (k_newton_sturm, 4H starts).  The Sturm
+// sequence is formed in registers, one coefficient per lane (for D = 64 the
+// top coefficient is carried as a scalar; see sturm_begin).
 #include "ftp_solve_common.h"
 
 namespace ftp {
@@ -40,78 +38,6 @@ __device__ __forceinline__ double lrdlane(double v, int src) {
 
 __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
-// Distinct real roots of the degree-D polynomial g (LDS, coefficients c =
-// 0..D, g[D] != 0) in (-1, 1] by a Sturm sequence evaluated at x = -1 and
-// x = 1.  The sequence P_0 = g, P_1 = g', P_q = -rem(P_{q-2}, P_{q-1}) is
-// built in `ch` (polynomial q of degree D - q at offset q (D + 1) - q (q - 1) / 2,
-// (D + 1)(D + 2) / 2 doubles), each member scaled to max |coefficient| = 1;
-// `tmp` holds 2 (D + 1) doubles.  Returns -1 when a remainder vanishes (a
-// non-constant gcd: repeated or nearly repeated roots) or loses its leading
-// term, i.e. when the count is not trustworthy.
-__device__ int sturm_count_unit(const double* g, int D, double* ch, double* tmp, int lane) {
-  double ma = 0.0, mb = 0.0;
-  for (int c = lane; c <= D; c += 64) {
-    ma = fmax(ma, fabs(g[c]));
-    if (c < D) mb = fmax(mb, fabs((c + 1) * g[c + 1]));
-  }
-  ma = wave_max(ma);
-  mb = wave_max(mb);
-  if (!(ma > 0.0) || !(mb > 0.0)) return -1;
-  double* P1 = ch + (D + 1);
-  for (int c = lane; c <= D; c += 64) {
-    ch[c] = g[c] / ma;
-    if (c < D) P1[c] = (c + 1) * g[c + 1] / mb;
-  }
-  lwave_sync();
-  int nq = 2;   // members built
-  for (int q = 2; q <= D; ++q) {
-    const int da = D - q + 2, db = D - q + 1;
-    const double* A = ch + (int64_t)(q - 2) * (D + 1) - (int64_t)(q - 2) * (q - 3) / 2;
-    const double* B = ch + (int64_t)(q - 1) * (D + 1) - (int64_t)(q - 1) * (q - 2) / 2;
-    double* C = ch + (int64_t)q * (D + 1) - (int64_t)q * (q - 1) / 2;
-    for (int c = lane; c <= da; c += 64) tmp[c] = A[c];
-    lwave_sync();
-    const double bl = B[db];
-    for (int i = da - db; i >= 0; --i) {
-      const double qt = tmp[db + i] / bl;
-      for (int c = lane; c <= db; c += 64) tmp[c + i] -= qt * B[c];
-      lwave_sync();
-    }
-    double mr = 0.0;
-    for (int c = lane; c < db; c += 64) mr = fmax(mr, fabs(tmp[c]));
-    mr = wave_max(mr);
-    // a vanishing remainder means a gcd of positive degree; a generic
-    // remainder keeps degree db - 1 (a lost leading term is ill-determined)
-    if (!(mr > 1e-12) || !(fabs(tmp[db - 1]) > 1e-13 * mr)) return -1;
-    const double inv = -1.0 / mr;
-    for (int c = lane; c < db; c += 64) C[c] = tmp[c] * inv;
-    lwave_sync();
-    nq = q + 1;
-  }
-  // signs of every member at x = 1 and x = -1 (lane q evaluates member q);
-  // tmp[q] and tmp[D + 1 + q] receive them
-  lwave_sync();
-  for (int q = lane; q < nq; q += 64) {
-    const double* Pq = ch + (int64_t)q * (D + 1) - (int64_t)q * (q - 1) / 2;
-    double a1 = 0.0, am = 0.0;
-    for (int c = 0; c <= D - q; ++c) {
-      a1 += Pq[c];
-      am += (c & 1) ? -Pq[c] : Pq[c];
-    }
-    tmp[q] = a1 > 0.0 ? 1.0 : (a1 < 0.0 ? -1.0 : 0.0);
-    tmp[D + 1 + q] = am > 0.0 ? 1.0 : (am < 0.0 ? -1.0 : 0.0);
-  }
-  lwave_sync();
-  int vp = 0, vm = 0;
-  double pp = 0.0, pm = 0.0;
-  for (int q = 0; q < nq; ++q) {
-    const double a = tmp[q], b = tmp[D + 1 + q];
-    if (a != 0.0) { if (pp != 0.0 && a != pp) ++vp; pp = a; }
-    if (b != 0.0) { if (pm != 0.0 && b != pm) ++vm; pm = b; }
-  }
-  return vm - vp;
-}
-
 // Sturm sequence of a degree-D polynomial g over the whole real line, D + 1
 // <= 64, in registers: P_0 = g, P_1 = g', P_q = -rem(P_{q-2}, P_{q-1}), each
 // member scaled to max |coefficient| ~ 1, lane c holding coefficient c (the
@@ -128,16 +54,21 @@ struct SturmChain {
   bool ok;
 };
 
-__device__ __forceinline__ SturmChain sturm_begin(double gv, int D, int lane) {
+// gv: coefficient `lane` of g (lanes 0..min(D, 63)); gtop = g[D].  For D = 64
+// the top coefficient has no lane: it is carried as the scalar leading
+// coefficient only, which is all the chain needs of it (the first remainder
+// cancels it exactly and the shifted derivative reaches lane 63 at most).
+__device__ __forceinline__ SturmChain sturm_begin(double gv, double gtop, int D, int lane) {
   SturmChain c;
   const double gnext = lane_shl1(gv);   // g[lane + 1], taken with every lane active
-  const double dv = lane < D ? (lane + 1) * gnext : 0.0;
-  const double ma = wave_max(fabs(gv)), mb = wave_max(fabs(dv));
+  const double g1 = lane == 63 ? gtop : gnext;
+  const double dv = lane < D ? (lane + 1) * g1 : 0.0;
+  const double ma = fmax(wave_max(fabs(gv)), fabs(gtop)), mb = wave_max(fabs(dv));
   c.ok = ma > 0.0 && mb > 0.0;
   const double ima = 1.0 / ma, imb = 1.0 / mb;
   c.A = gv * ima;
   c.B = dv * imb;
-  c.al = lrdlane(gv, D) * ima;
+  c.al = gtop * ima;
   c.bl = lrdlane(dv, D - 1) * imb;
   c.ibl = fast_rcp_d(c.bl);
   c.sp = c.al > 0.0 ? 1 : -1;
@@ -184,9 +115,10 @@ __device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane
   c.ibl = -(mr * mr) * u;
 }
 
-// Distinct real roots of g (coefficient `gv` in lane c, g[D] != 0), or -1.
-__device__ int sturm_count_line_reg(double gv, int D, int lane) {
-  SturmChain c = sturm_begin(gv, D, lane);
+// Distinct real roots of g (coefficient `gv` in lane c, gtop = g[D] != 0,
+// D <= 64), or -1.
+__device__ int sturm_count_line_reg(double gv, double gtop, int D, int lane) {
+  SturmChain c = sturm_begin(gv, gtop, D, lane);
   for (int q = 2; q <= D && c.ok; ++q) sturm_step(c, D, q, lane);
   return c.ok ? c.vm - c.vp : -1;
 }
@@ -201,8 +133,8 @@ __device__ int sturm_count_line_reg(double gv, int D, int lane) {
 // packed form the per-chain scalars (al, bl, 1/bl) are held per lane, equal
 // within each half.
 __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int& ca, int& cb) {
-  SturmChain a = sturm_begin(ga, D, lane);
-  SturmChain b = sturm_begin(gb, D, lane);
+  SturmChain a = sturm_begin(ga, lrdlane(ga, D), D, lane);
+  SturmChain b = sturm_begin(gb, lrdlane(gb, D), D, lane);
   const int qpack = D - 29 > 2 ? D - 29 : 2;
   int q = 2;
   for (; q < qpack && (a.ok || b.ok); ++q) {
@@ -267,7 +199,7 @@ struct LearnArgs {
 
 __host__ __device__ inline size_t learn_lds_bytes(int H) {
   const int K = 3 * H - 1, D = 2 * K;
-  return (size_t)(2 * (K + 1) + 4 * (D + 1) + (D + 1) * (D + 2) / 2 + 8) * sizeof(double);
+  return (size_t)(2 * (K + 1) + (D + 2)) * sizeof(double);
 }
 
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_sturm(SolveArgs a, LearnArgs L) {
@@ -277,10 +209,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const RecLayout RL(H);
   FreqWork W;
   W.r = reinterpret_cast<double2*>(sml);
-  double* g2 = sml + 2 * (K + 1);        // reflected polynomial x^D f(-1/x)
-  double* fl = g2 + (D + 1);             // f copied to LDS
-  double* tmp = fl + (D + 1);            // 2 (D + 1) scratch doubles
-  double* ch = tmp + 2 * (D + 1);        // Sturm sequence storage
+  double* fl = sml + 2 * (K + 1);        // f copied to LDS
   unsigned long long iters_acc = 0, roots_acc = 0, fb_acc = 0;
   for (int64_t w = first_item(L.queue, lane); w < L.np; w = next_item(L.queue, lane, w)) {
     double* R = L.rec + w * (int64_t)RL.stride;
@@ -296,28 +225,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       continue;
     }
     for (int d = lane; d <= K; d += 64) W.r[d] = make_double2(R[RL.r + 2 * d], R[RL.r + 2 * d + 1]);
-    for (int c = lane; c <= D; c += 64) {
-      const double fc = R[RL.f + c];
-      fl[c] = fc;
-      g2[D - c] = (c & 1) ? -fc : fc;
-    }
+    for (int c = lane; c <= D; c += 64) fl[c] = R[RL.f + c];
     lwave_sync();
     // Sturm count first.  An ill-determined count (or fewer than the two
     // real roots every non-constant P has: its maximum and minimum) sends the
     // frequency on without Newton; otherwise Newton stops as soon as it has
     // found that many distinct real roots.
     int cnt = -1;
-    if (D < 64) {
-      // real roots of f on the whole line = real phases other than phi0 + pi,
-      // where R does not vanish (f has full degree D)
-      cnt = sturm_count_line_reg(lane <= D ? fl[lane] : 0.0, D, lane);
-    } else {
-      const int c1 = sturm_count_unit(fl, D, ch, tmp, lane);
-      if (c1 >= 0) {
-        const int c2 = sturm_count_unit(g2, D, ch, tmp, lane);
-        if (c2 >= 0) cnt = c1 + c2;
-      }
-    }
+    // real roots of f on the whole line = real phases other than phi0 + pi,
+    // where R does not vanish (f has full degree D)
+    cnt = sturm_count_line_reg(lane <= D ? fl[lane] : 0.0, fl[D], D, lane);
     if (cnt < 2) cnt = -1;
     // Newton from 4H starts: lanes < 2H take the network seeds and lanes
     // 2H..4H-1 evenly spaced phases (with no network, all 4H are evenly spaced)
