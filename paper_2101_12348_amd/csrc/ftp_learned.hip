@@ -48,9 +48,13 @@ __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.
 // vanishes (a gcd of positive degree: repeated or nearly repeated roots) or
 // loses its leading term to cancellation: the count is then not trusted.
 // A, B: the last two members; al, bl: their leading coefficients (uniform).
+// Signs: consecutive members differ in degree by one, so at -inf a sign
+// change occurs exactly where none occurs at +inf; with V(+inf) = vp over
+// the D transitions of a full chain, the count V(-inf) - V(+inf) is D - 2 vp.
 struct SturmChain {
   double A, B, al, bl, ibl;   // ibl = 1 / bl
-  int sp, sm, vp, vm;
+  bool sp;                    // last member positive at +inf
+  int vp;                     // sign changes at +inf so far
   bool ok;
 };
 
@@ -71,16 +75,9 @@ __device__ __forceinline__ SturmChain sturm_begin(double gv, double gtop, int D,
   c.al = gtop * ima;
   c.bl = lrdlane(dv, D - 1) * imb;
   c.ibl = fast_rcp_d(c.bl);
-  c.sp = c.al > 0.0 ? 1 : -1;
-  c.sm = (D & 1) ? -c.sp : c.sp;
-  c.vp = 0;
-  c.vm = 0;
-  const int tp = c.bl > 0.0 ? 1 : -1;
-  const int tm = ((D - 1) & 1) ? -tp : tp;
-  c.vp += tp != c.sp;
-  c.vm += tm != c.sm;
-  c.sp = tp;
-  c.sm = tm;
+  const bool p0 = c.al > 0.0, p1 = c.bl > 0.0;
+  c.vp = p0 != p1;
+  c.sp = p1;
   return c;
 }
 
@@ -97,13 +94,10 @@ __device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane
   const double mr = wave_max_abs_hi(t);
   const double lead = lrdlane(t, db - 1);
   c.ok = c.ok && mr > 1e-12 && fabs(lead) > 1e-13 * mr;
-  // P_q = -t / mr: leading sign -sgn(lead), degree D - q
-  const int tp = lead > 0.0 ? -1 : 1;
-  const int tm = ((D - q) & 1) ? -tp : tp;
+  // P_q = -t / mr: positive at +inf when lead < 0
+  const bool tp = lead < 0.0;
   c.vp += tp != c.sp;
-  c.vm += tm != c.sm;
   c.sp = tp;
-  c.sm = tm;
   // one reciprocal for both 1 / mr (the scaling) and 1 / bl of the next step:
   // with u = 1 / (mr lead), 1 / mr = lead u and 1 / (-lead / mr) = -mr^2 u
   const double u = fast_rcp_d(mr * lead);
@@ -120,7 +114,7 @@ __device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane
 __device__ int sturm_count_line_reg(double gv, double gtop, int D, int lane) {
   SturmChain c = sturm_begin(gv, gtop, D, lane);
   for (int q = 2; q <= D && c.ok; ++q) sturm_step(c, D, q, lane);
-  return c.ok ? c.vm - c.vp : -1;
+  return c.ok ? D - 2 * c.vp : -1;
 }
 
 // The same for two polynomials at once (two frequencies of one wavefront).
@@ -158,20 +152,16 @@ __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int
       const double la = lrdlane(t, db - 1), lb = lrdlane(t, 32 + db - 1);
       a.ok = a.ok && mra > 1e-12 && fabs(la) > 1e-13 * mra;
       b.ok = b.ok && mrb > 1e-12 && fabs(lb) > 1e-13 * mrb;
-      // P_q = -t / mr: leading sign -sgn(lead), degree D - q
+      // P_q = -t / mr: positive at +inf when lead < 0
       {
-        const int tp = la > 0.0 ? -1 : 1, tm = ((D - q) & 1) ? -tp : tp;
+        const bool tp = la < 0.0;
         a.vp += tp != a.sp;
-        a.vm += tm != a.sm;
         a.sp = tp;
-        a.sm = tm;
       }
       {
-        const int tp = lb > 0.0 ? -1 : 1, tm = ((D - q) & 1) ? -tp : tp;
+        const bool tp = lb < 0.0;
         b.vp += tp != b.sp;
-        b.vm += tm != b.sm;
         b.sp = tp;
-        b.sm = tm;
       }
       const double mr = half ? mrb : mra, lead = half ? lb : la;
       const double u = fast_rcp_d(mr * lead);
@@ -183,8 +173,8 @@ __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int
       ibl = -(mr * mr) * u;
     }
   }
-  ca = a.ok ? a.vm - a.vp : -1;
-  cb = b.ok ? b.vm - b.vp : -1;
+  ca = a.ok ? D - 2 * a.vp : -1;
+  cb = b.ok ? D - 2 * b.vp : -1;
 }
 
 struct LearnArgs {
