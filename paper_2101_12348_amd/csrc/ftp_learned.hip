@@ -9,6 +9,8 @@
 //     starts (only evenly spaced starts for the ablation without network) are
 //     refined by FP64 Newton on R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta
 //     (Eq. theta2cond written as R(theta) = i e^{-i K theta} p(e^{i theta}));
+//     for H <= 10 each step of R is evaluated on the Cayley polynomial f and
+//     the iterate kept as tan((theta - phi0) / 2) or its reciprocal;
 //     converged roots closer than 1e-8 rad are merged after every iteration
 //     from the fourth (two-frequency kernel; after iterations 4-8, 10 and 12
 //     in the one-frequency kernel), and Newton stops once the merged roots
@@ -39,20 +41,31 @@ __device__ __forceinline__ double lrdlane(double v, int src) {
 __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
 // Sturm sequence of a degree-D polynomial g over the whole real line, D + 1
-// <= 64, in registers: P_0 = g, P_1 = g', P_q = -rem(P_{q-2}, P_{q-1}), each
-// member scaled to max |coefficient| ~ 1, lane c holding coefficient c (the
-// shift by one power of x is a DPP lane shift).  Every member of a generic
-// sequence has degree D - q, so its signs at +inf and -inf are those of its
-// leading coefficient (times (-1)^(D - q) at -inf), and the count V(-inf) -
-// V(+inf) accumulates as the members are formed.  `ok` drops when a remainder
-// vanishes (a gcd of positive degree: repeated or nearly repeated roots) or
-// loses its leading term to cancellation: the count is then not trusted.
-// A, B: the last two members; al, bl: their leading coefficients (uniform).
-// Signs: consecutive members differ in degree by one, so at -inf a sign
-// change occurs exactly where none occurs at +inf; with V(+inf) = vp over
-// the D transitions of a full chain, the count V(-inf) - V(+inf) is D - 2 vp.
+// <= 64, in registers: P_0 = g, P_1 = g', P_q = -rem(P_{q-2}, P_{q-1}), lane c
+// holding coefficient c (the shift by one power of x is a DPP lane shift).
+// Each member is scaled by the reciprocal of its leading coefficient's
+// magnitude and that coefficient then set to exactly +-1: a positive scale
+// leaves the signs, and so the count, unchanged, the quotient of each
+// division is al bl x + (next coefficient) bl with no division, and the chain
+// from one member to the next holds no reduction over the lanes.  Every member
+// of a generic sequence has degree D - q, so its signs at +inf and -inf are
+// those of its leading coefficient (times (-1)^(D - q) at -inf), and the count
+// V(-inf) - V(+inf) accumulates as the members are formed; consecutive members
+// differ in degree by one, so at -inf a sign change occurs exactly where none
+// occurs at +inf, and with V(+inf) = vp over the D transitions of a full chain
+// the count is D - 2 vp.  `ok` drops when a remainder vanishes against the
+// members it comes from (max |coefficient| below 1e-12 of theirs: a gcd of
+// positive degree, repeated or nearly repeated roots) or loses its leading
+// term to cancellation (below 1e-13 of its largest coefficient): the count is
+// then not trusted.  The maxima feed only this test, so they are off the
+// chain's critical path.  The scale is bounded (leading magnitudes below
+// 1e-300 fail the test anyway) so that coefficients above a member's degree
+// stay exact zeros even in a failed chain: in the packed form they shift into
+// the other half-wave.
+// A, B: the last two members; al, bl: their leading coefficients (+-1);
+// MA, MB: their largest coefficient magnitudes.
 struct SturmChain {
-  double A, B, al, bl, ibl;   // ibl = 1 / bl
+  double A, B, al, bl, MA, MB;
   bool sp;                    // last member positive at +inf
   int vp;                     // sign changes at +inf so far
   bool ok;
@@ -67,17 +80,17 @@ __device__ __forceinline__ SturmChain sturm_begin(double gv, double gtop, int D,
   const double gnext = lane_shl1(gv);   // g[lane + 1], taken with every lane active
   const double g1 = lane == 63 ? gtop : gnext;
   const double dv = lane < D ? (lane + 1) * g1 : 0.0;
-  const double ma = fmax(wave_max(fabs(gv)), fabs(gtop)), mb = wave_max(fabs(dv));
-  c.ok = ma > 0.0 && mb > 0.0;
-  const double ima = 1.0 / ma, imb = 1.0 / mb;
-  c.A = gv * ima;
-  c.B = dv * imb;
-  c.al = gtop * ima;
-  c.bl = lrdlane(dv, D - 1) * imb;
-  c.ibl = fast_rcp_d(c.bl);
-  const bool p0 = c.al > 0.0, p1 = c.bl > 0.0;
-  c.vp = p0 != p1;
-  c.sp = p1;
+  const double ag = fabs(gtop), sgn = gtop > 0.0 ? 1.0 : -1.0;
+  const double sa = fast_rcp_d(fmax(ag, 1e-300)), sb = fast_rcp_d(fmax(D * ag, 1e-300));
+  c.ok = ag > 0.0 && ag < INFINITY;
+  c.A = lane == D ? sgn : gv * sa;
+  c.B = lane == D - 1 ? sgn : dv * sb;
+  c.MA = fmax(wave_max_abs_hi(gv), ag) * sa;
+  c.MB = wave_max_abs_hi(dv) * sb;
+  c.al = sgn;
+  c.bl = sgn;
+  c.vp = 0;
+  c.sp = gtop > 0.0;
   return c;
 }
 
@@ -86,34 +99,30 @@ __device__ __forceinline__ SturmChain sturm_begin(double gv, double gtop, int D,
 // stepping on values that are then ignored.
 __device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane) {
   const int db = D - q + 1;
-  const double ibl = c.ibl;
-  const double q1 = c.al * ibl;
-  double t = c.A - q1 * lane_shr1(c.B);
-  const double q0 = lrdlane(t, db) * ibl;
+  double t = c.A - (c.al * c.bl) * lane_shr1(c.B);
+  const double q0 = lrdlane(t, db) * c.bl;
   t = lane < db ? t - q0 * c.B : 0.0;
-  const double mr = wave_max_abs_hi(t);
   const double lead = lrdlane(t, db - 1);
-  c.ok = c.ok && mr > 1e-12 && fabs(lead) > 1e-13 * mr;
-  // P_q = -t / mr: positive at +inf when lead < 0
+  const double mr = wave_max_abs_hi(t);
+  c.ok = c.ok && mr > 1e-12 * fmax(c.MA, c.MB) && fabs(lead) > 1e-13 * mr;
+  // P_q = -t / |lead|: positive at +inf when lead < 0
   const bool tp = lead < 0.0;
   c.vp += tp != c.sp;
   c.sp = tp;
-  // one reciprocal for both 1 / mr (the scaling) and 1 / bl of the next step:
-  // with u = 1 / (mr lead), 1 / mr = lead u and 1 / (-lead / mr) = -mr^2 u
-  const double u = fast_rcp_d(mr * lead);
-  const double inv = -lead * u;
+  const double s = fast_rcp_d(fmax(fabs(lead), 1e-300)), nb = tp ? 1.0 : -1.0;
   c.A = c.B;
   c.al = c.bl;
-  c.B = t * inv;
-  c.bl = lead * inv;
-  c.ibl = -(mr * mr) * u;
+  c.MA = c.MB;
+  c.B = lane == db - 1 ? nb : -t * s;
+  c.bl = nb;
+  c.MB = mr * s;
 }
 
 // Distinct real roots of g (coefficient `gv` in lane c, gtop = g[D] != 0,
 // D <= 64), or -1.
 __device__ int sturm_count_line_reg(double gv, double gtop, int D, int lane) {
   SturmChain c = sturm_begin(gv, gtop, D, lane);
-  for (int q = 2; q <= D && c.ok; ++q) sturm_step(c, D, q, lane);
+  for (int q = 2; q <= D; ++q) sturm_step(c, D, q, lane);
   return c.ok ? D - 2 * c.vp : -1;
 }
 
@@ -124,57 +133,56 @@ __device__ int sturm_count_line_reg(double gv, double gtop, int D, int lane) {
 // the two half-waves (chain b's coefficient c in lane 32 + c) and stepped by
 // one instruction stream.  Coefficients above a member's degree are exact
 // zeros, so the shift by one power of x brings a zero into lane 32.  In the
-// packed form the per-chain scalars (al, bl, 1/bl) are held per lane, equal
-// within each half.
+// packed form the per-chain values (al, bl, MA, MB, the sign count and ok)
+// are held per lane, equal within each half.
 __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int& ca, int& cb) {
   SturmChain a = sturm_begin(ga, lrdlane(ga, D), D, lane);
   SturmChain b = sturm_begin(gb, lrdlane(gb, D), D, lane);
   const int qpack = D - 29 > 2 ? D - 29 : 2;
   int q = 2;
-  for (; q < qpack && (a.ok || b.ok); ++q) {
+  for (; q < qpack; ++q) {
     sturm_step(a, D, q, lane);
     sturm_step(b, D, q, lane);
   }
-  if (q <= D && (a.ok || b.ok)) {
-    const int half = lane >> 5, hl = lane & 31;
-    const double bA = __shfl(b.A, hl), bB = __shfl(b.B, hl);   // all lanes active
-    double A = half ? bA : a.A, B = half ? bB : a.B;
-    double al = half ? b.al : a.al, bl = half ? b.bl : a.bl, ibl = half ? b.ibl : a.ibl;
-    for (; q <= D && (a.ok || b.ok); ++q) {
-      const int db = D - q + 1;
-      const double q1 = al * ibl;
-      double t = A - q1 * lane_shr1(B);
-      const double ta = lrdlane(t, db), tb = lrdlane(t, 32 + db);
-      const double q0 = (half ? tb : ta) * ibl;
-      t = hl < db ? t - q0 * B : 0.0;
-      double mra, mrb;
-      half_max_abs_hi(t, mra, mrb);
-      const double la = lrdlane(t, db - 1), lb = lrdlane(t, 32 + db - 1);
-      a.ok = a.ok && mra > 1e-12 && fabs(la) > 1e-13 * mra;
-      b.ok = b.ok && mrb > 1e-12 && fabs(lb) > 1e-13 * mrb;
-      // P_q = -t / mr: positive at +inf when lead < 0
-      {
-        const bool tp = la < 0.0;
-        a.vp += tp != a.sp;
-        a.sp = tp;
-      }
-      {
-        const bool tp = lb < 0.0;
-        b.vp += tp != b.sp;
-        b.sp = tp;
-      }
-      const double mr = half ? mrb : mra, lead = half ? lb : la;
-      const double u = fast_rcp_d(mr * lead);
-      const double inv = -lead * u;
-      A = B;
-      al = bl;
-      B = t * inv;
-      bl = lead * inv;
-      ibl = -(mr * mr) * u;
-    }
+  const int half = lane >> 5, hl = lane & 31;
+  const double bA = __shfl(b.A, hl), bB = __shfl(b.B, hl);   // all lanes active
+  SturmChain c;
+  c.A = half ? bA : a.A;
+  c.B = half ? bB : a.B;
+  c.al = half ? b.al : a.al;
+  c.bl = half ? b.bl : a.bl;
+  c.MA = half ? b.MA : a.MA;
+  c.MB = half ? b.MB : a.MB;
+  c.sp = half ? b.sp : a.sp;
+  c.vp = half ? b.vp : a.vp;
+  c.ok = half ? b.ok : a.ok;
+  for (; q <= D; ++q) {
+    const int db = D - q + 1;
+    double t = c.A - (c.al * c.bl) * lane_shr1(c.B);
+    const double ta = lrdlane(t, db), tb = lrdlane(t, 32 + db);
+    const double q0 = (half ? tb : ta) * c.bl;
+    t = hl < db ? t - q0 * c.B : 0.0;
+    const double la = lrdlane(t, db - 1), lb = lrdlane(t, 32 + db - 1);
+    const double lead = half ? lb : la;
+    double mra, mrb;
+    half_max_abs_hi(t, mra, mrb);
+    const double mr = half ? mrb : mra;
+    c.ok = c.ok && mr > 1e-12 * fmax(c.MA, c.MB) && fabs(lead) > 1e-13 * mr;
+    // P_q = -t / |lead|: positive at +inf when lead < 0
+    const bool tp = lead < 0.0;
+    c.vp += tp != c.sp;
+    c.sp = tp;
+    const double s = fast_rcp_d(fmax(fabs(lead), 1e-300)), nb = tp ? 1.0 : -1.0;
+    c.A = c.B;
+    c.al = c.bl;
+    c.MA = c.MB;
+    c.B = hl == db - 1 ? nb : -t * s;
+    c.bl = nb;
+    c.MB = mr * s;
   }
-  ca = a.ok ? D - 2 * a.vp : -1;
-  cb = b.ok ? D - 2 * b.vp : -1;
+  const int cnt = c.ok ? D - 2 * c.vp : -1;
+  ca = __builtin_amdgcn_readlane(cnt, 0);
+  cb = __builtin_amdgcn_readlane(cnt, 32);
 }
 
 struct LearnArgs {
@@ -312,24 +320,99 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
+// Newton on R(theta) carried out on the Cayley polynomial.  With x = tan((theta
+// - phi0) / 2), f(x) = (1 + x^2)^K R(theta), so R'/R = ((1 + x^2) f'/f - 2 K x)
+// / 2 and the Newton step of R in theta is d = 2 f / ((1 + x^2) f' - 2 K x f).
+// For |x| > 1 the iterate is kept as y = 1 / x and the reversed polynomial
+// g(y) = y^D f(1 / y) = (1 + y^2)^K R(theta) serves the same way, with theta
+// decreasing in y, so the formula (in g, y) gives -d.  Either way the iterate u
+// = x or y has |u| <= 1, and the step (clamped to 0.5 rad as in theta) is
+// applied by the tangent addition formula u <- (u - t) / (1 + u t), t = tan(s
+// / 2) from its series to fifth order (the clamp bounds the relative error of
+// t by 1.3e-5 and it vanishes as the step does, so convergence stays quadratic);
+// if the result leaves [-1, 1] its reciprocal is taken and the representation
+// flips.  One Newton step costs a real Horner pass of degree D for f and f'
+// (2D multiply-adds) in place of K complex multiply-adds for R and R' plus a
+// sine and cosine.  cp: coefficients of f (sg > 0) or of g (sg < 0) in
+// ascending order.  Returns the signed step s (theta moves by sg * s, clamped);
+// ok drops on a zero or non-finite step.
+__device__ __forceinline__ double newton_u_step(const double* cp, int D, int K, double& u, int& sg, bool& ok) {
+  double F = cp[D], dF = 0.0;
+#pragma unroll 4
+  for (int c = D - 1; c >= 0; --c) {
+    dF = fma(dF, u, F);
+    F = fma(F, u, cp[c]);
+  }
+  const double den = fma(fma(u, u, 1.0), dF, -(2.0 * K) * u * F);
+  const double d = 2.0 * F * fast_rcp_d(den);
+  ok = den != 0.0 && isfinite(d);
+  const double sc = fmax(-0.5, fmin(0.5, d));
+  const double h = 0.5 * sc, h2 = h * h;
+  const double t = h * fma(h2, fma(h2, 0.13333333333333333333, 0.33333333333333333333), 1.0);
+  const double num = u - t, dd = fma(u, t, 1.0);
+  const bool flip = fabs(num) > fabs(dd);
+  u = (flip ? dd : num) * fast_rcp_d(flip ? num : dd);
+  sg = flip ? -sg : sg;
+  return sc;
+}
+
+// Iterate (u, sg) of the phase whose direction is (c, s) (any length r > 0)
+// relative to phi0: tan(alpha / 2) = s / (r + c), taken while c >= 0 (|u| <=
+// 1); otherwise its reciprocal, (r + c) / s = s / (r - c).
+__device__ __forceinline__ void u_from_dir(double c, double s, double& u, int& sg) {
+  const double r = sqrt(fma(c, c, s * s));
+  const bool in = c >= 0.0;
+  u = s * fast_rcp_d(fmax(in ? r + c : r - c, 1e-300));
+  sg = in ? 1 : -1;
+}
+
+// atan(u) for |u| <= 1.  Two halvings, atan(u) = 2 atan(u / (1 + sqrt(1 +
+// u^2))), bring the argument below tan(pi / 16) < 0.199, where the Taylor
+// series through z^23 leaves a remainder below 2e-17 of the result.
+__device__ __forceinline__ double atan_unit(double u) {
+  double z = u * fast_rcp_d(1.0 + sqrt(fma(u, u, 1.0)));
+  z = z * fast_rcp_d(1.0 + sqrt(fma(z, z, 1.0)));
+  const double z2 = z * z;
+  double p = -1.0 / 23.0;
+  p = fma(p, z2, 1.0 / 21.0);
+  p = fma(p, z2, -1.0 / 19.0);
+  p = fma(p, z2, 1.0 / 17.0);
+  p = fma(p, z2, -1.0 / 15.0);
+  p = fma(p, z2, 1.0 / 13.0);
+  p = fma(p, z2, -1.0 / 11.0);
+  p = fma(p, z2, 1.0 / 9.0);
+  p = fma(p, z2, -1.0 / 7.0);
+  p = fma(p, z2, 1.0 / 5.0);
+  p = fma(p, z2, -1.0 / 3.0);
+  return 4.0 * fma(p * z2, z, z);
+}
+
+// Phase in [0, 2 pi) of the iterate: phi0 + 2 atan u (sg > 0), phi0 + pi sign(u)
+// - 2 atan u (sg < 0).
+__device__ __forceinline__ double theta_from_u(double phi0, double u, int sg) {
+  const double au = 2.0 * atan_unit(u);
+  double th = sg > 0 ? phi0 + au : phi0 + copysign(kPi, u) - au;
+  th = fma(-floor(th * (1.0 / kTwoPi)), kTwoPi, th);
+  return th >= kTwoPi ? th - kTwoPi : (th < 0.0 ? th + kTwoPi : th);
+}
+
 // Two frequencies per wavefront (H <= 10, D < 64): frequencies 2b and 2b + 1 of the
 // list.  Their two Sturm chains are stepped side by side (the chains are
 // serial, so a second independent one fills the latency of the first), then
 // Newton runs on both at once, lanes 0..31 for the first and 32..63 for the
 // second, each half with the merge and stop rule of the one-frequency kernel
 // and min(32, D) starts: the 2H network seeds and min(32, D) - 2H evenly
-// spaced phases (all evenly spaced without network).  A half that has reached
-// its count is frozen while the other goes on.
+// spaced phases (all evenly spaced without network).  The Newton steps are
+// those of R in theta, evaluated on the Cayley polynomial (newton_u_step).  A
+// half that has reached its count is frozen while the other goes on.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_sturm2(SolveArgs a, LearnArgs L) {
   extern __shared__ double sml[];
   const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
   // starts per frequency: every lane of the half (at most D: no more real
   // roots exist, and the candidate slots hold D)
   const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = D < 32 ? D : 32;
+  const int FS = D + 2;   // f and its reversal for each half, 16-byte aligned
   const RecLayout RL(H);
-  double2* rr = reinterpret_cast<double2*>(sml);   // r_d of both frequencies
-  FreqWork W;
-  W.r = rr + half * (K + 1);
   const unsigned long long lo32 = 0xffffffffull;
   const unsigned long long hmask = half ? ~lo32 : lo32;
   const unsigned long long below = (1ull << lane) - 1ull;
@@ -355,13 +438,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       fb_acc += (unsigned long long)actA + (unsigned long long)actB;
       continue;
     }
-    for (int d = lane; d < 2 * (K + 1); d += 64) {
-      const int h = d > K ? 1 : 0, dd = d - h * (K + 1);
-      const double* Rs = h ? RB : RA;
-      rr[d] = make_double2(Rs[RL.r + 2 * dd], Rs[RL.r + 2 * dd + 1]);
-    }
     const double fA = lane <= D ? RA[RL.f + lane] : 0.0;
     const double fB = lane <= D ? RB[RL.f + lane] : 0.0;
+    if (lane <= D) {
+      sml[lane] = fA;
+      sml[FS + D - lane] = fA;
+      sml[2 * FS + lane] = fB;
+      sml[3 * FS + D - lane] = fB;
+    }
     lwave_sync();
     // counts: -2 inactive (no output), -1 ill-determined or below two (to the
     // fallback without Newton), else the number of distinct real roots
@@ -372,31 +456,39 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (!actA) cA = -2;
     if (!actB) cB = -2;
     const int cnt = half ? cB : cA;
-    double th = 0.0, thw = 0.0;
+    const double phi0 = Rh[RL.meta + M_PHI0];
+    double u = 0.0;
+    int sg = 1;
     bool conv = false, uniq = false, live = cnt >= 0 && hl < NS;
     int its = 0;
     if (live) {
-      if (L.seeds_out && hl < S) {
+      // start direction relative to phi0: a network seed (its output vector
+      // is the root's direction in the canonical frame, rotated here by
+      // -(canon + phi0)) or an evenly spaced phase less phi0
+      const bool seeded = L.seeds_out && hl < S;
+      double bc = 1.0, bs = 0.0, ang;
+      if (seeded) {
         const float* o = L.seeds_out + wh * 2 * S;
-        th = atan2((double)o[2 * hl + 1], (double)o[2 * hl]) - Rh[RL.meta + M_CANON];
-      } else if (L.seeds_out) {
-        th = kTwoPi * (hl - S + 0.5) / (NS - S);
+        bc = (double)o[2 * hl];
+        bs = (double)o[2 * hl + 1];
+        ang = -(Rh[RL.meta + M_CANON] + phi0);
       } else {
-        th = kTwoPi * (hl + 0.5) / NS;
+        ang = (L.seeds_out ? (hl - S + 0.5) * (kTwoPi / (NS - S)) : (hl + 0.5) * (kTwoPi / NS)) - phi0;
       }
+      double s1, c1;
+      sincos_small(ang, s1, c1);
+      u_from_dir(fma(bc, c1, -bs * s1), fma(bc, s1, bs * c1), u, sg);
     }
+    const double* fbase = sml + 2 * FS * half;
     bool doneA = cA < 0, doneB = cB < 0;
     unsigned long long um = 0ull, merged = 0ull;
     for (int it = 1; it <= 12 && !(doneA && doneB); ++it) {
       if (live && !conv) {
-        double Rv, dR;
-        eval_R(W, H, th, Rv, dR);
-        const double step = Rv / dR;
-        if (!(dR != 0.0) || !isfinite(step)) {
+        bool ok;
+        const double sc = newton_u_step(sg > 0 ? fbase : fbase + FS, D, K, u, sg, ok);
+        if (!ok) {
           live = false;
         } else {
-          const double sc = fmax(-0.5, fmin(0.5, step));
-          th -= sc;
           ++its;
           if (fabs(sc) < 1e-12) conv = true;
         }
@@ -407,19 +499,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const bool needB = !doneB && __popcll(cm >> 32) >= cB;
         if (!needA && !needB && it < 12) continue;
         // distinct converged roots of each half: a converged lane is unique
-        // unless a lower converged lane of its half lies within 1e-8 rad.
-        // Converged lanes no longer move, so only the lanes converged since
-        // the last merge are compared (lowest first): each settles its own
-        // flag against the lower lanes and clears the flag of higher ones on
-        // the same root.
-        thw = fmod(th, kTwoPi);
-        if (thw < 0.0) thw += kTwoPi;
+        // unless a lower converged lane of its half lies within 1e-8 rad
+        // (|du| < 0.5e-8 (1 + u^2) in one representation; across the two, x =
+        // 1 / y, only near |u| = 1).  Converged lanes no longer move, so only
+        // the lanes converged since the last merge are compared (lowest
+        // first): each settles its own flag against the lower lanes and
+        // clears the flag of higher ones on the same root.
+        const double tol = 0.5e-8 * fma(u, u, 1.0);
         for (unsigned long long m = cm & ~merged; m; m &= m - 1ull) {
           const int jj = __builtin_ctzll(m);
-          const double tj = lrdlane(thw, jj);
-          double dd = fabs(tj - thw);
-          dd = fmin(dd, kTwoPi - dd);
-          const bool same = conv && (jj >> 5) == half && dd < 1e-8;
+          const double uj = lrdlane(u, jj);
+          const int sj = __builtin_amdgcn_readlane(sg, jj);
+          const double dd = sg == sj ? u - uj : fma(u, uj, -1.0);
+          const bool same = conv && (jj >> 5) == half && fabs(dd) < tol;
           const unsigned long long sm = __ballot(same);
           if (lane == jj) uniq = (sm & ((1ull << jj) - 1ull)) == 0ull;
           else if (lane > jj && same) uniq = false;
@@ -432,6 +524,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       }
     }
     iters_acc += (unsigned long long)wave_sum((double)its);
+    const double thw = theta_from_u(phi0, u, sg);
     const int nuA = __popcll(um & lo32), nuB = __popcll(um >> 32);
     const bool okA = cA >= 0 && nuA == cA, okB = cB >= 0 && nuB == cB;
     const bool ok = half ? okB : okA;
@@ -464,7 +557,7 @@ bool newton_two_per_wave(int H) { return 6 * H - 2 < 64; }
 
 hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st) {
   if (newton_two_per_wave(a.H)) {
-    const size_t lds = (size_t)4 * (3 * a.H) * sizeof(double);
+    const size_t lds = (size_t)4 * (6 * a.H) * sizeof(double);   // 4 x (D + 2)
     hipLaunchKernelGGL(k_newton_sturm2, dim3((unsigned)waves), dim3(64), lds, st, a, L);
   } else {
     hipLaunchKernelGGL(k_newton_sturm, dim3((unsigned)waves), dim3(64), learn_lds_bytes(a.H), st, a, L);
