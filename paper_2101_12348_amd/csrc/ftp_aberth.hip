@@ -196,8 +196,8 @@ __global__ __launch_bounds__(64) void k_aberth(AberthArgs A) {
     awave_sync();
   }
   if (lane == 0 && A.counters) {
-    if (its_acc) atomicAdd(&A.counters->aberth_iters, its_acc);
-    if (qr_acc) atomicAdd(&A.counters->fallback_qr, qr_acc);
+    if (its_acc) atomicAdd(&counter_slot(A.counters)->aberth_iters, its_acc);
+    if (qr_acc) atomicAdd(&counter_slot(A.counters)->fallback_qr, qr_acc);
   }
 }
 

@@ -1037,14 +1037,14 @@ int plan_create_impl(ftp_plan** out, int n_band, int H, const double* c, const d
     tw32[k] = make_float2((float)tw64[k].x, (float)tw64[k].y);
   }
   if ((rc = P->alpha.ensure(sizeof(double2) * nt * H)) || (rc = P->twiddle32.ensure(sizeof(float2) * kTwiddleN)) ||
-      (rc = P->twiddle64.ensure(sizeof(double2) * kTwiddleN)) || (rc = P->counters.ensure(sizeof(SolveCounters)))) {
+      (rc = P->twiddle64.ensure(sizeof(double2) * kTwiddleN)) || (rc = P->counters.ensure(sizeof(SolveCounters) * kCounterSlots))) {
     delete P;
     return rc;
   }
   if (hipMemcpy(P->alpha.p, al.data(), sizeof(double2) * nt * H, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(P->twiddle32.p, tw32.data(), sizeof(float2) * kTwiddleN, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(P->twiddle64.p, tw64.data(), sizeof(double2) * kTwiddleN, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(P->counters.p, 0, sizeof(SolveCounters)) != hipSuccess ||
+      hipMemset(P->counters.p, 0, sizeof(SolveCounters) * kCounterSlots) != hipSuccess ||
       hipEventCreateWithFlags(&P->upload_done, hipEventDisableTiming) != hipSuccess) {
     g_last_error = "plan setup copy failed";
     delete P;
@@ -1584,9 +1584,18 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
 
 int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
   if (!P || !out) return FTP_E_NULL;
-  SolveCounters c{};
-  HIP_TRY(hipMemcpyAsync(&c, P->counters.p, sizeof(c), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  SolveCounters cs[kCounterSlots];
+  HIP_TRY(hipMemcpyAsync(cs, P->counters.p, sizeof(cs), hipMemcpyDeviceToHost, (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  SolveCounters c{};
+  for (const SolveCounters& x : cs) {
+    c.fallback += x.fallback;
+    c.newton_iters += x.newton_iters;
+    c.roots_found += x.roots_found;
+    c.qr_sweeps += x.qr_sweeps;
+    c.aberth_iters += x.aberth_iters;
+    c.fallback_qr += x.fallback_qr;
+  }
   *out = P->last;
   out->ms_nfft = 0.0;
   out->ms_solve = 0.0;
@@ -1629,7 +1638,7 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
   P->evr_used = 0;
   P->evl_used = 0;
   P->last = ftp_stats{};
-  HIP_TRY(hipMemsetAsync(P->counters.p, 0, sizeof(SolveCounters), (hipStream_t)stream));
+  HIP_TRY(hipMemsetAsync(P->counters.p, 0, sizeof(SolveCounters) * kCounterSlots, (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   return FTP_OK;
 }

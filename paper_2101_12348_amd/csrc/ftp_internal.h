@@ -78,6 +78,10 @@ struct FftGridPass {
   int log2n, lp, ls, lcols;  // log2 of size, pass size, stride, columns per item
 };
 
+// Solve statistics, in kCounterSlots copies: each wavefront adds to copy
+// (block index mod kCounterSlots), so that the per-wave additions of a large
+// grid do not all meet on one address; the host sums the copies.
+constexpr int kCounterSlots = 64;
 struct SolveCounters {
   unsigned long long fallback;   // frequencies the learned / uniform Newton solve did not confirm
   unsigned long long newton_iters;

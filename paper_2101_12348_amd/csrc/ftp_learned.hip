@@ -40,35 +40,53 @@ __device__ __forceinline__ double lrdlane(double v, int src) {
 
 __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
+__device__ __forceinline__ int hiword(double x) {
+  return (int)((unsigned long long)__double_as_longlong(x) >> 32);
+}
+__device__ __forceinline__ double from_hiword(int h) {
+  return __longlong_as_double((long long)((unsigned long long)(unsigned)h << 32));
+}
+
+// Thresholds of the Sturm test, applied to high words of positive doubles: a
+// difference of high words is 2^20 log2 of the ratio to within 0.09 (the
+// mantissa enters linearly), so "ratio above 1e-12" reads hi(x) - hi(y) >
+// hi(1) - hi(1e-12), to within 7% of the bound; "below 1e13" is hi(x) <
+// hi(1e13), to within 2^-20.  hi(NaN) and hi(inf) exceed hi(1e13).
+constexpr int kHiT12 = 0x3ff00000 - 0x3d719799;   // hi(1) - hi(1e-12)
+constexpr int kHi1e13 = 0x42a2309c;               // hi(1e13)
+
 // Sturm sequence of a degree-D polynomial g over the whole real line, D + 1
 // <= 64, in registers: P_0 = g, P_1 = g', P_q = -rem(P_{q-2}, P_{q-1}), lane c
 // holding coefficient c (the shift by one power of x is a DPP lane shift).
 // Each member is scaled by the reciprocal of its leading coefficient's
-// magnitude and that coefficient then set to exactly +-1: a positive scale
-// leaves the signs, and so the count, unchanged, the quotient of each
-// division is al bl x + (next coefficient) bl with no division, and the chain
-// from one member to the next holds no reduction over the lanes.  Every member
-// of a generic sequence has degree D - q, so its signs at +inf and -inf are
-// those of its leading coefficient (times (-1)^(D - q) at -inf), and the count
-// V(-inf) - V(+inf) accumulates as the members are formed; consecutive members
-// differ in degree by one, so at -inf a sign change occurs exactly where none
-// occurs at +inf, and with V(+inf) = vp over the D transitions of a full chain
-// the count is D - 2 vp.  `ok` drops when a remainder vanishes against the
-// members it comes from (max |coefficient| below 1e-12 of theirs: a gcd of
-// positive degree, repeated or nearly repeated roots) or loses its leading
-// term to cancellation (below 1e-13 of its largest coefficient): the count is
-// then not trusted.  The maxima feed only this test, so they are off the
-// chain's critical path.  The scale is bounded (leading magnitudes below
-// 1e-300 fail the test anyway) so that coefficients above a member's degree
-// stay exact zeros even in a failed chain: in the packed form they shift into
-// the other half-wave.
-// A, B: the last two members; al, bl: their leading coefficients (+-1);
-// MA, MB: their largest coefficient magnitudes.
+// magnitude (P_0 and P_1 with their leading lane set to +-1): a positive scale
+// leaves the signs, and so the count, unchanged, and the quotient of each
+// division is taken as al bl x + (next coefficient) bl with al, bl = +-1 and no
+// division (a member's leading coefficient is +-1 to within the reciprocal's
+// few ulp, which perturbs the quotient by as much: the size of the rounding
+// already present).  Every member of a generic sequence has degree D - q, so
+// its signs at +inf and -inf are those of its leading coefficient (times
+// (-1)^(D - q) at -inf), and the count V(-inf) - V(+inf) accumulates as the
+// members are formed; consecutive members differ in degree by one, so at -inf
+// a sign change occurs exactly where none occurs at +inf, and with V(+inf) =
+// vp over the D transitions of a full chain the count is D - 2 vp.
+// The count is trusted (sturm_finish) when, over the whole chain, every
+// scaled member has all coefficients below 1e13 (no remainder lost its
+// leading term to cancellation: that term is at least 1e-13 of the largest)
+// and every remainder's leading coefficient exceeds 1e-12 of the largest
+// coefficient of any member (no remainder vanished against the members it
+// comes from: a gcd of positive degree, repeated or nearly repeated roots).
+// This is stricter than the same two tests applied step by step, and needs no
+// reduction over the lanes until the end: each lane keeps the running maximum
+// of its coefficients' magnitudes and the running minimum of the leads'
+// (high words, see above).
 struct SturmChain {
-  double A, B, al, bl, MA, MB;
-  bool sp;                    // last member positive at +inf
-  int vp;                     // sign changes at +inf so far
-  bool ok;
+  double A, B, al, bl;  // the last two members and their leading coefficients (+-1)
+  int rmax;             // running max of hi(|coefficient|) in this lane
+  int rminl;            // running min of hi(|leading coefficient|) of the remainders
+  int sp;               // last member positive at +inf (0 / 1)
+  int vp;               // sign changes at +inf so far
+  int ok;               // g has a finite nonzero leading coefficient
 };
 
 // gv: coefficient `lane` of g (lanes 0..min(D, 63)); gtop = g[D].  For D = 64
@@ -81,41 +99,69 @@ __device__ __forceinline__ SturmChain sturm_begin(double gv, double gtop, int D,
   const double g1 = lane == 63 ? gtop : gnext;
   const double dv = lane < D ? (lane + 1) * g1 : 0.0;
   const double ag = fabs(gtop), sgn = gtop > 0.0 ? 1.0 : -1.0;
-  const double sa = fast_rcp_d(fmax(ag, 1e-300)), sb = fast_rcp_d(fmax(D * ag, 1e-300));
+  const double sa = fast_rcp_d(ag + 1e-300), sb = fast_rcp_d(D * ag + 1e-300);
   c.ok = ag > 0.0 && ag < INFINITY;
   c.A = lane == D ? sgn : gv * sa;
   c.B = lane == D - 1 ? sgn : dv * sb;
-  c.MA = fmax(wave_max_abs_hi(gv), ag) * sa;
-  c.MB = wave_max_abs_hi(dv) * sb;
   c.al = sgn;
   c.bl = sgn;
+  c.rmax = max(hiword(c.A) & 0x7fffffff, hiword(c.B) & 0x7fffffff);
+  c.rminl = 0x7fefffff;
   c.vp = 0;
-  c.sp = gtop > 0.0;
+  c.sp = gtop > 0.0 ? 1 : 0;
   return c;
 }
 
-// Member q (2 <= q <= D) from the last two.  Branch-free, so that two chains
-// stepped side by side interleave; a chain that is no longer ok keeps
-// stepping on values that are then ignored.
+// Member q (2 <= q <= D) from the last two (every lane holds one chain).
+// Branch-free, so that two chains stepped side by side interleave.
 __device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane) {
   const int db = D - q + 1;
   double t = c.A - (c.al * c.bl) * lane_shr1(c.B);
   const double q0 = lrdlane(t, db) * c.bl;
   t = lane < db ? t - q0 * c.B : 0.0;
   const double lead = lrdlane(t, db - 1);
-  const double mr = wave_max_abs_hi(t);
-  c.ok = c.ok && mr > 1e-12 * fmax(c.MA, c.MB) && fabs(lead) > 1e-13 * mr;
-  // P_q = -t / |lead|: positive at +inf when lead < 0
-  const bool tp = lead < 0.0;
-  c.vp += tp != c.sp;
+  const int hl = hiword(lead);
+  // P_q = -t / |lead|: positive at +inf when lead < 0 (sign bit of hl)
+  const int tp = (int)((unsigned)hl >> 31);
+  c.vp += tp ^ c.sp;
   c.sp = tp;
-  const double s = fast_rcp_d(fmax(fabs(lead), 1e-300)), nb = tp ? 1.0 : -1.0;
+  c.rminl = min(c.rminl, hl & 0x7fffffff);
+  const double s = fast_rcp_d(fabs(lead) + 1e-300);
   c.A = c.B;
   c.al = c.bl;
-  c.MA = c.MB;
-  c.B = lane == db - 1 ? nb : -t * s;
-  c.bl = nb;
-  c.MB = mr * s;
+  c.B = -t * s;
+  c.bl = from_hiword((hl & 0x80000000) ^ 0xbff00000);   // -sign(lead)
+  c.rmax = max(c.rmax, hiword(c.B) & 0x7fffffff);
+}
+
+// Maximum of an int over the wavefront (row stages, then row_bcast:15 and
+// row_bcast:31 into lane 63).
+__device__ __forceinline__ int wave_max_int(int h) {
+  h = max(h, dpp_i<0xB1, 0xf>(h));
+  h = max(h, dpp_i<0x4E, 0xf>(h));
+  h = max(h, dpp_i<0x141, 0xf>(h));
+  h = max(h, dpp_i<0x140, 0xf>(h));
+  h = max(h, dpp_i<0x142, 0xa>(h));
+  h = max(h, dpp_i<0x143, 0xc>(h));
+  return __builtin_amdgcn_readlane(h, 63);
+}
+
+// Maxima of an int over lanes 0..31 and 32..63 (row stages, then
+// row_bcast:15 into rows 1 and 3: lanes 31 and 63).
+__device__ __forceinline__ void half_max_hi_int(int h, int& h_lo, int& h_hi) {
+  h = max(h, dpp_i<0xB1, 0xf>(h));
+  h = max(h, dpp_i<0x4E, 0xf>(h));
+  h = max(h, dpp_i<0x141, 0xf>(h));
+  h = max(h, dpp_i<0x140, 0xf>(h));
+  h = max(h, dpp_i<0x142, 0xa>(h));
+  h_lo = __builtin_amdgcn_readlane(h, 31);
+  h_hi = __builtin_amdgcn_readlane(h, 63);
+}
+
+// The test of the whole chain (see SturmChain) from hmax = hi(largest |coefficient|)
+// and hminl = hi(smallest |leading coefficient| of a remainder).
+__device__ __forceinline__ bool sturm_trusted(int ok, int hmax, int hminl) {
+  return ok && hmax < kHi1e13 && hminl - hmax > -kHiT12;
 }
 
 // Distinct real roots of g (coefficient `gv` in lane c, gtop = g[D] != 0,
@@ -123,7 +169,15 @@ __device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane
 __device__ int sturm_count_line_reg(double gv, double gtop, int D, int lane) {
   SturmChain c = sturm_begin(gv, gtop, D, lane);
   for (int q = 2; q <= D; ++q) sturm_step(c, D, q, lane);
-  return c.ok ? D - 2 * c.vp : -1;
+  return sturm_trusted(c.ok, wave_max_int(c.rmax), c.rminl) ? D - 2 * c.vp : -1;
+}
+
+// v from lane addr / 4 (ds_bpermute, all lanes active)
+__device__ __forceinline__ double bperm_d(int addr, double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(u & 0xffffffffull));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 // The same for two polynomials at once (two frequencies of one wavefront).
@@ -132,9 +186,12 @@ __device__ int sturm_count_line_reg(double gv, double gtop, int D, int lane) {
 // polynomial of both chains fits in 32 lanes, and the chains are packed into
 // the two half-waves (chain b's coefficient c in lane 32 + c) and stepped by
 // one instruction stream.  Coefficients above a member's degree are exact
-// zeros, so the shift by one power of x brings a zero into lane 32.  In the
-// packed form the per-chain values (al, bl, MA, MB, the sign count and ok)
-// are held per lane, equal within each half.
+// zeros, so the shift by one power of x brings a zero into lane 32 (the
+// scale is kept finite for that: a zero times it stays zero).  In the packed
+// form the per-chain values (al bl, bl, the sign count, the running minimum
+// of the leads) are held per lane, equal within each half, and the two
+// coefficients a step needs from its own half (t_db for the quotient, the new
+// leading coefficient) come by ds_bpermute from lane 32 h + db (- 1).
 __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int& ca, int& cb) {
   SturmChain a = sturm_begin(ga, lrdlane(ga, D), D, lane);
   SturmChain b = sturm_begin(gb, lrdlane(gb, D), D, lane);
@@ -146,43 +203,36 @@ __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int
   }
   const int half = lane >> 5, hl = lane & 31;
   const double bA = __shfl(b.A, hl), bB = __shfl(b.B, hl);   // all lanes active
-  SturmChain c;
-  c.A = half ? bA : a.A;
-  c.B = half ? bB : a.B;
-  c.al = half ? b.al : a.al;
-  c.bl = half ? b.bl : a.bl;
-  c.MA = half ? b.MA : a.MA;
-  c.MB = half ? b.MB : a.MB;
-  c.sp = half ? b.sp : a.sp;
-  c.vp = half ? b.vp : a.vp;
-  c.ok = half ? b.ok : a.ok;
+  const int rma = wave_max_int(a.rmax), rmb = wave_max_int(b.rmax);
+  double A = half ? bA : a.A, B = half ? bB : a.B;
+  double bl = half ? b.bl : a.bl, ab = half ? b.al * b.bl : a.al * a.bl;
+  int rmax = half ? rmb : rma, rminl = half ? b.rminl : a.rminl;
+  int sp = half ? b.sp : a.sp, vp = half ? b.vp : a.vp;
+  const int pbase = (lane & 32) << 2;   // ds_bpermute byte address of the half's lane 0
   for (; q <= D; ++q) {
     const int db = D - q + 1;
-    double t = c.A - (c.al * c.bl) * lane_shr1(c.B);
-    const double ta = lrdlane(t, db), tb = lrdlane(t, 32 + db);
-    const double q0 = (half ? tb : ta) * c.bl;
-    t = hl < db ? t - q0 * c.B : 0.0;
-    const double la = lrdlane(t, db - 1), lb = lrdlane(t, 32 + db - 1);
-    const double lead = half ? lb : la;
-    double mra, mrb;
-    half_max_abs_hi(t, mra, mrb);
-    const double mr = half ? mrb : mra;
-    c.ok = c.ok && mr > 1e-12 * fmax(c.MA, c.MB) && fabs(lead) > 1e-13 * mr;
-    // P_q = -t / |lead|: positive at +inf when lead < 0
-    const bool tp = lead < 0.0;
-    c.vp += tp != c.sp;
-    c.sp = tp;
-    const double s = fast_rcp_d(fmax(fabs(lead), 1e-300)), nb = tp ? 1.0 : -1.0;
-    c.A = c.B;
-    c.al = c.bl;
-    c.MA = c.MB;
-    c.B = hl == db - 1 ? nb : -t * s;
-    c.bl = nb;
-    c.MB = mr * s;
+    double t = fma(-ab, lane_shr1(B), A);
+    const int pl = pbase + ((db - 1) << 2);
+    const double q0 = bperm_d(pl + 4, t) * bl;
+    t = hl < db ? fma(-q0, B, t) : 0.0;
+    const double lead = bperm_d(pl, t);
+    const int hlead = hiword(lead);
+    const int tp = (int)((unsigned)hlead >> 31);   // P_q positive at +inf
+    vp += tp ^ sp;
+    sp = tp;
+    rminl = min(rminl, hlead & 0x7fffffff);
+    const double s = fast_rcp_d(fabs(lead) + 1e-300);
+    const double nb = from_hiword((hlead & 0x80000000) ^ 0xbff00000);   // -sign(lead)
+    A = B;
+    B = -t * s;
+    rmax = max(rmax, hiword(B) & 0x7fffffff);
+    ab = bl * nb;
+    bl = nb;
   }
-  const int cnt = c.ok ? D - 2 * c.vp : -1;
-  ca = __builtin_amdgcn_readlane(cnt, 0);
-  cb = __builtin_amdgcn_readlane(cnt, 32);
+  int hma, hmb;
+  half_max_hi_int(rmax, hma, hmb);
+  ca = sturm_trusted(a.ok, hma, __builtin_amdgcn_readlane(rminl, 0)) ? D - 2 * __builtin_amdgcn_readlane(vp, 0) : -1;
+  cb = sturm_trusted(b.ok, hmb, __builtin_amdgcn_readlane(rminl, 32)) ? D - 2 * __builtin_amdgcn_readlane(vp, 32) : -1;
 }
 
 struct LearnArgs {
@@ -314,9 +364,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     lwave_sync();
   }
   if (lane == 0 && a.counters) {
-    if (iters_acc) atomicAdd(&a.counters->newton_iters, iters_acc);
-    if (roots_acc) atomicAdd(&a.counters->roots_found, roots_acc);
-    if (fb_acc) atomicAdd(&a.counters->fallback, fb_acc);
+    SolveCounters* c = counter_slot(a.counters);
+    if (iters_acc) atomicAdd(&c->newton_iters, iters_acc);
+    if (roots_acc) atomicAdd(&c->roots_found, roots_acc);
+    if (fb_acc) atomicAdd(&c->fallback, fb_acc);
   }
 }
 
@@ -459,7 +510,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const double phi0 = Rh[RL.meta + M_PHI0];
     double u = 0.0;
     int sg = 1;
-    bool conv = false, uniq = false, live = cnt >= 0 && hl < NS;
+    bool conv = false, live = cnt >= 0 && hl < NS;
     int its = 0;
     if (live) {
       // start direction relative to phi0: a network seed (its output vector
@@ -481,7 +532,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     const double* fbase = sml + 2 * FS * half;
     bool doneA = cA < 0, doneB = cB < 0;
-    unsigned long long um = 0ull, merged = 0ull;
+    unsigned long long um = 0ull, merged = 0ull, U = 0ull;   // U: unique converged lanes
     for (int it = 1; it <= 12 && !(doneA && doneB); ++it) {
       if (live && !conv) {
         bool ok;
@@ -499,25 +550,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const bool needB = !doneB && __popcll(cm >> 32) >= cB;
         if (!needA && !needB && it < 12) continue;
         // distinct converged roots of each half: a converged lane is unique
-        // unless a lower converged lane of its half lies within 1e-8 rad
-        // (|du| < 0.5e-8 (1 + u^2) in one representation; across the two, x =
-        // 1 / y, only near |u| = 1).  Converged lanes no longer move, so only
-        // the lanes converged since the last merge are compared (lowest
-        // first): each settles its own flag against the lower lanes and
-        // clears the flag of higher ones on the same root.
-        const double tol = 0.5e-8 * fma(u, u, 1.0);
-        for (unsigned long long m = cm & ~merged; m; m &= m - 1ull) {
-          const int jj = __builtin_ctzll(m);
-          const double uj = lrdlane(u, jj);
-          const int sj = __builtin_amdgcn_readlane(sg, jj);
-          const double dd = sg == sj ? u - uj : fma(u, uj, -1.0);
-          const bool same = conv && (jj >> 5) == half && fabs(dd) < tol;
-          const unsigned long long sm = __ballot(same);
-          if (lane == jj) uniq = (sm & ((1ull << jj) - 1ull)) == 0ull;
-          else if (lane > jj && same) uniq = false;
+        // unless a lower converged lane of its half lies within 1e-8 rad.
+        // Compared on key = u (sg > 0) or sign(u) 2 - u (sg < 0), which
+        // increases with theta - phi0 over (-pi, pi) and moves by |du| where
+        // theta moves by 2 |du| / (1 + u^2) (the cut at theta - phi0 = pi
+        // sits where R is largest, far from any root).  Converged lanes no
+        // longer move, so each check settles only the lanes converged since
+        // the last: one pass per root, from the lowest pending lane jj, marks
+        // every converged lane of its half within the tolerance of jj; jj is
+        // unique if none of them is lower, and the higher ones (also roots
+        // settled earlier) are not.
+        const double key = sg > 0 ? u : copysign(2.0, u) - u;
+        for (unsigned long long pend = cm & ~merged; pend;) {
+          const int jj = __builtin_ctzll(pend);
+          const double kj = lrdlane(key, jj), uj = lrdlane(u, jj);
+          const double tol = 0.5e-8 * fma(uj, uj, 1.0);
+          const unsigned long long bit = 1ull << jj;
+          const unsigned long long same = __ballot(fabs(key - kj) < tol) & cm & (jj < 32 ? lo32 : ~lo32);
+          const unsigned long long upto = (bit << 1) - 1ull;   // lanes 0..jj
+          U &= upto | ~same;
+          U = (same & (bit - 1ull)) ? (U & ~bit) : (U | bit);
+          pend &= ~(same | bit);
         }
         merged = cm;
-        um = __ballot(uniq && hl < NS);
+        um = U;
         if (__popcll(um & lo32) == cA) doneA = true;
         if (__popcll(um >> 32) == cB) doneB = true;
         if (half ? doneB : doneA) live = false;
@@ -535,7 +591,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     lwave_sync();
     // confirmed roots, or the distinct roots found, which start the Aberth
     // iteration of a fallback frequency
-    if (cnt != -2 && uniq && hl < NS) cand[__popcll(um & hmask & below)] = thw;
+    if (cnt != -2 && ((um >> lane) & 1ull)) cand[__popcll(um & hmask & below)] = thw;
     if (cnt != -2 && !ok && hl == 0) {
       Rh[RL.meta + M_WARM] = (double)nu;
       Rh[RL.meta + M_FALLBACK] = 1.0;
@@ -547,9 +603,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     lwave_sync();
   }
   if (lane == 0 && a.counters) {
-    if (iters_acc) atomicAdd(&a.counters->newton_iters, iters_acc);
-    if (roots_acc) atomicAdd(&a.counters->roots_found, roots_acc);
-    if (fb_acc) atomicAdd(&a.counters->fallback, fb_acc);
+    SolveCounters* c = counter_slot(a.counters);
+    if (iters_acc) atomicAdd(&c->newton_iters, iters_acc);
+    if (roots_acc) atomicAdd(&c->roots_found, roots_acc);
+    if (fb_acc) atomicAdd(&c->fallback, fb_acc);
   }
 }
 

@@ -278,7 +278,7 @@ __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, 
     }
     wave_sync();
   }
-  if (counters && lane == 0 && sweeps_acc) atomicAdd(&counters->qr_sweeps, sweeps_acc);
+  if (counters && lane == 0 && sweeps_acc) atomicAdd(&counter_slot(counters)->qr_sweeps, sweeps_acc);
 }
 
 // ------------------------------------------------------------- assemble

@@ -26,7 +26,7 @@ struct SolveArgs {
   double* amp;
   double* offset;
   uint8_t* status;
-  SolveCounters* counters;
+  SolveCounters* counters;   // kCounterSlots copies (counter_slot)
 };
 
 constexpr double kEps = 2.220446049250313e-16;
@@ -84,6 +84,11 @@ struct RecLayout {
 };
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// This wavefront's copy of the solve statistics.
+__device__ __forceinline__ SolveCounters* counter_slot(SolveCounters* c) {
+  return c + (blockIdx.x & (kCounterSlots - 1));
+}
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
