@@ -415,9 +415,10 @@ def main():
     stages = {"plain_qr": stage(st_plain["ms_roots"], qr_flops(H) * pairs, "alu", FP64_PEAK_TFLOPS,
                                 flops_per_unit=qr_flops(H), units=pairs)}
     if args.solver in ("learned", "uniform", "aberth"):
-        # Newton: ~10 (K + 1) flops per iteration (R and dR/dtheta); one Sturm
-        # chain: two multiply-adds per coefficient per remainder, ~2 D^2 per pair
-        fl_verify = st["newton_iters"] * 10.0 * (K + 1) + pairs * 2.0 * D * D
+        # Newton: f and f' by Horner at the iterate (2 D multiply-adds, 4 D
+        # flops) and ~20 flops for the step, per iteration; one Sturm chain:
+        # two multiply-adds per coefficient per remainder, ~2 D^2 per pair
+        fl_verify = st["newton_iters"] * (4.0 * D + 20.0) + pairs * 2.0 * D * D
         if args.solver == "learned":
             stages["mlp_forward"] = stage(st["ms_mlp"], mlp_flops(meta["d_in"], meta["width"], meta["d_out"]) * pairs,
                                           "mfma", BF16_PEAK_TFLOPS)

@@ -375,6 +375,11 @@ struct ftp_plan {
   int64_t *d_obs_off = nullptr, *d_freq_off = nullptr, *d_gtb = nullptr, *d_items = nullptr;
   FftGridPass* d_fft = nullptr;
   hipEvent_t upload_done = nullptr;
+  // side stream of the learned / uniform solve: the scoring of the pairs the
+  // Newton tier confirmed runs there, beside the Aberth tier (fork after
+  // Newton, join before the fallback pairs are scored)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   bool upload_pending = false;
   ftp_stats last{};
   // stage timing (FTP_FLAG_TIME_STAGES): one event triple per lightcurve chunk
@@ -706,6 +711,9 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
     }
   }
   const ftp_tuning& T = P->tune;
+  // scoring of the Newton-root pairs two per wavefront, on the side stream
+  const bool overlap_score =
+      !dataset && (solver == FTP_SOLVER_LEARNED || solver == FTP_SOLVER_UNIFORM) && 6 * P->H - 2 < 64;
   // learned solver with a fusable network: features in rows of dinp bf16
   // (zero padded), then one kernel for the four layers
   const bool fused = solver == FTP_SOLVER_LEARNED && P->tune.mlp_fused && mlp_fused_ok(P->net.nin, P->net.nout);
@@ -765,6 +773,16 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
         L.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
         L.queue = nullptr;   // uniform work per pair: grid striding (a queue costs more than it balances)
         HIP_TRY(launch_newton_sturm(a, L, w_nt, st));
+        if (overlap_score) {
+          // the Newton-root pairs are final now: score them on the side
+          // stream while the fallback tiers run on this one
+          SolveArgs as = a;
+          as.newton_cands = true;
+          HIP_TRY(hipEventRecord(P->fork_ev, st));
+          HIP_TRY(hipStreamWaitEvent(P->side, P->fork_ev, 0));
+          HIP_TRY(launch_score2(as, rec, p0, np, w_sc, P->side));
+          HIP_TRY(hipEventRecord(P->join_ev, P->side));
+        }
       }
       hipEvent_t rb = next_learn_event(P);
       if (rb) HIP_TRY(hipEventRecord(rb, st));
@@ -798,9 +816,10 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
     } else {
       SolveArgs as = a;
       as.newton_cands = solver == FTP_SOLVER_LEARNED || solver == FTP_SOLVER_UNIFORM;
-      if (as.newton_cands && 6 * P->H - 2 < 64) {
-        // Newton-root pairs two per wavefront, then the fallback list
-        HIP_TRY(launch_score2(as, rec, p0, np, w_sc, st));
+      if (overlap_score) {
+        // Newton-root pairs (two per wavefront, on the side stream), then the
+        // fallback list
+        HIP_TRY(hipStreamWaitEvent(st, P->join_ev, 0));
         HIP_TRY(launch_score(as, rec, p0, np, std::min(w_sc, (int)grid_waves(P, 2, np)), st,
                              P->fb_list.as<int64_t>(), ctr));
       } else {
@@ -1045,7 +1064,10 @@ int plan_create_impl(ftp_plan** out, int n_band, int H, const double* c, const d
       hipMemcpy(P->twiddle32.p, tw32.data(), sizeof(float2) * kTwiddleN, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(P->twiddle64.p, tw64.data(), sizeof(double2) * kTwiddleN, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(P->counters.p, 0, sizeof(SolveCounters) * kCounterSlots) != hipSuccess ||
-      hipEventCreateWithFlags(&P->upload_done, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&P->upload_done, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming) != hipSuccess) {
     g_last_error = "plan setup copy failed";
     delete P;
     return FTP_E_HIP;
@@ -1097,6 +1119,9 @@ int ftp_plan_destroy(ftp_plan* P) {
   P->net.release();
   for (DevBuf* b : bufs) b->release();
   if (P->upload_done) (void)hipEventDestroy(P->upload_done);
+  if (P->fork_ev) (void)hipEventDestroy(P->fork_ev);
+  if (P->join_ev) (void)hipEventDestroy(P->join_ev);
+  if (P->side) (void)hipStreamDestroy(P->side);
   if (P->h_stage) (void)hipHostFree(P->h_stage);
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : P->evr) (void)hipEventDestroy(e);
