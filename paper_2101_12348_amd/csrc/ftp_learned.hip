@@ -50,10 +50,48 @@ __device__ __forceinline__ double from_hiword(int h) {
 // Thresholds of the Sturm test, applied to high words of positive doubles: a
 // difference of high words is 2^20 log2 of the ratio to within 0.09 (the
 // mantissa enters linearly), so "ratio above 1e-12" reads hi(x) - hi(y) >
-// hi(1) - hi(1e-12), to within 7% of the bound; "below 1e13" is hi(x) <
-// hi(1e13), to within 2^-20.  hi(NaN) and hi(inf) exceed hi(1e13).
-constexpr int kHiT12 = 0x3ff00000 - 0x3d719799;   // hi(1) - hi(1e-12)
-constexpr int kHi1e13 = 0x42a2309c;               // hi(1e13)
+// hi(1) - hi(1e-12), to within 7% of the bound.  hi(NaN) and hi(inf) are at
+// least 0x7ff00000.
+constexpr int kHi1 = 0x3ff00000;
+constexpr int kHiT12 = kHi1 - 0x3d719799;   // hi(1) - hi(1e-12)
+constexpr int kHiT13 = kHi1 - 0x3d3c25c2;   // hi(1) - hi(1e-13)
+
+// Maximum of an int over the wavefront (row stages, then row_bcast:15 and
+// row_bcast:31 into lane 63).
+__device__ __forceinline__ int wave_max_int(int h) {
+  h = max(h, dpp_i<0xB1, 0xf>(h));
+  h = max(h, dpp_i<0x4E, 0xf>(h));
+  h = max(h, dpp_i<0x141, 0xf>(h));
+  h = max(h, dpp_i<0x140, 0xf>(h));
+  h = max(h, dpp_i<0x142, 0xa>(h));
+  h = max(h, dpp_i<0x143, 0xc>(h));
+  return __builtin_amdgcn_readlane(h, 63);
+}
+
+// Maxima of an int over lanes 0..31 and 32..63 (row stages, then
+// row_bcast:15 into rows 1 and 3: lanes 31 and 63).
+__device__ __forceinline__ void half_max_int(int h, int& h_lo, int& h_hi) {
+  h = max(h, dpp_i<0xB1, 0xf>(h));
+  h = max(h, dpp_i<0x4E, 0xf>(h));
+  h = max(h, dpp_i<0x141, 0xf>(h));
+  h = max(h, dpp_i<0x140, 0xf>(h));
+  h = max(h, dpp_i<0x142, 0xa>(h));
+  h_lo = __builtin_amdgcn_readlane(h, 31);
+  h_hi = __builtin_amdgcn_readlane(h, 63);
+}
+
+// The test of one Sturm step on high words: hr = hi(max |t|) of the
+// remainder, hl = hi(|leading coefficient of t|), hM = hi of the larger of
+// the two members' largest coefficient magnitudes.  The remainder must not
+// vanish against the members (max |t| above 1e-12 of theirs: else a gcd of
+// positive degree, repeated or nearly repeated roots) nor lose its leading
+// term to cancellation (above 1e-13 of max |t|), and must be finite.
+__device__ __forceinline__ bool sturm_step_ok(int hr, int hl, int hM) {
+  return (hr < 0x7ff00000) & (hr - hM > -kHiT12) & (hl - hr > -kHiT13);
+}
+// hi(max |P_q|) of the scaled member P_q = -t / |lead|: hr - hl + hi(1)
+// (bounded so that a failed chain's value stays an int)
+__device__ __forceinline__ int sturm_member_hi(int hr, int hl) { return min(hr - hl, 0x40000000) + kHi1; }
 
 // Sturm sequence of a degree-D polynomial g over the whole real line, D + 1
 // <= 64, in registers: P_0 = g, P_1 = g', P_q = -rem(P_{q-2}, P_{q-1}), lane c
@@ -69,24 +107,14 @@ constexpr int kHi1e13 = 0x42a2309c;               // hi(1e13)
 // (-1)^(D - q) at -inf), and the count V(-inf) - V(+inf) accumulates as the
 // members are formed; consecutive members differ in degree by one, so at -inf
 // a sign change occurs exactly where none occurs at +inf, and with V(+inf) =
-// vp over the D transitions of a full chain the count is D - 2 vp.
-// The count is trusted (sturm_finish) when, over the whole chain, every
-// scaled member has all coefficients below 1e13 (no remainder lost its
-// leading term to cancellation: that term is at least 1e-13 of the largest)
-// and every remainder's leading coefficient exceeds 1e-12 of the largest
-// coefficient of any member (no remainder vanished against the members it
-// comes from: a gcd of positive degree, repeated or nearly repeated roots).
-// This is stricter than the same two tests applied step by step, and needs no
-// reduction over the lanes until the end: each lane keeps the running maximum
-// of its coefficients' magnitudes and the running minimum of the leads'
-// (high words, see above).
+// vp over the D transitions of a full chain the count is D - 2 vp.  Each step
+// is tested (sturm_step_ok); a chain that fails is not trusted.
 struct SturmChain {
   double A, B, al, bl;  // the last two members and their leading coefficients (+-1)
-  int rmax;             // running max of hi(|coefficient|) in this lane
-  int rminl;            // running min of hi(|leading coefficient|) of the remainders
+  int hMA, hMB;         // hi(max |coefficient|) of A and B
   int sp;               // last member positive at +inf (0 / 1)
   int vp;               // sign changes at +inf so far
-  int ok;               // g has a finite nonzero leading coefficient
+  bool ok;
 };
 
 // gv: coefficient `lane` of g (lanes 0..min(D, 63)); gtop = g[D].  For D = 64
@@ -105,8 +133,8 @@ __device__ __forceinline__ SturmChain sturm_begin(double gv, double gtop, int D,
   c.B = lane == D - 1 ? sgn : dv * sb;
   c.al = sgn;
   c.bl = sgn;
-  c.rmax = max(hiword(c.A) & 0x7fffffff, hiword(c.B) & 0x7fffffff);
-  c.rminl = 0x7fefffff;
+  c.hMA = max(wave_max_int(hiword(c.A) & 0x7fffffff), kHi1);   // the top of A is +-1 (no lane at D = 64)
+  c.hMB = wave_max_int(hiword(c.B) & 0x7fffffff);
   c.vp = 0;
   c.sp = gtop > 0.0 ? 1 : 0;
   return c;
@@ -120,48 +148,20 @@ __device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane
   const double q0 = lrdlane(t, db) * c.bl;
   t = lane < db ? t - q0 * c.B : 0.0;
   const double lead = lrdlane(t, db - 1);
-  const int hl = hiword(lead);
+  const int hl = hiword(lead), hla = hl & 0x7fffffff;
+  const int hr = wave_max_int(hiword(t) & 0x7fffffff);
+  c.ok = c.ok && sturm_step_ok(hr, hla, max(c.hMA, c.hMB));
   // P_q = -t / |lead|: positive at +inf when lead < 0 (sign bit of hl)
   const int tp = (int)((unsigned)hl >> 31);
   c.vp += tp ^ c.sp;
   c.sp = tp;
-  c.rminl = min(c.rminl, hl & 0x7fffffff);
   const double s = fast_rcp_d(fabs(lead) + 1e-300);
   c.A = c.B;
   c.al = c.bl;
+  c.hMA = c.hMB;
   c.B = -t * s;
   c.bl = from_hiword((hl & 0x80000000) ^ 0xbff00000);   // -sign(lead)
-  c.rmax = max(c.rmax, hiword(c.B) & 0x7fffffff);
-}
-
-// Maximum of an int over the wavefront (row stages, then row_bcast:15 and
-// row_bcast:31 into lane 63).
-__device__ __forceinline__ int wave_max_int(int h) {
-  h = max(h, dpp_i<0xB1, 0xf>(h));
-  h = max(h, dpp_i<0x4E, 0xf>(h));
-  h = max(h, dpp_i<0x141, 0xf>(h));
-  h = max(h, dpp_i<0x140, 0xf>(h));
-  h = max(h, dpp_i<0x142, 0xa>(h));
-  h = max(h, dpp_i<0x143, 0xc>(h));
-  return __builtin_amdgcn_readlane(h, 63);
-}
-
-// Maxima of an int over lanes 0..31 and 32..63 (row stages, then
-// row_bcast:15 into rows 1 and 3: lanes 31 and 63).
-__device__ __forceinline__ void half_max_hi_int(int h, int& h_lo, int& h_hi) {
-  h = max(h, dpp_i<0xB1, 0xf>(h));
-  h = max(h, dpp_i<0x4E, 0xf>(h));
-  h = max(h, dpp_i<0x141, 0xf>(h));
-  h = max(h, dpp_i<0x140, 0xf>(h));
-  h = max(h, dpp_i<0x142, 0xa>(h));
-  h_lo = __builtin_amdgcn_readlane(h, 31);
-  h_hi = __builtin_amdgcn_readlane(h, 63);
-}
-
-// The test of the whole chain (see SturmChain) from hmax = hi(largest |coefficient|)
-// and hminl = hi(smallest |leading coefficient| of a remainder).
-__device__ __forceinline__ bool sturm_trusted(int ok, int hmax, int hminl) {
-  return ok && hmax < kHi1e13 && hminl - hmax > -kHiT12;
+  c.hMB = sturm_member_hi(hr, hla);
 }
 
 // Distinct real roots of g (coefficient `gv` in lane c, gtop = g[D] != 0,
@@ -169,7 +169,7 @@ __device__ __forceinline__ bool sturm_trusted(int ok, int hmax, int hminl) {
 __device__ int sturm_count_line_reg(double gv, double gtop, int D, int lane) {
   SturmChain c = sturm_begin(gv, gtop, D, lane);
   for (int q = 2; q <= D; ++q) sturm_step(c, D, q, lane);
-  return sturm_trusted(c.ok, wave_max_int(c.rmax), c.rminl) ? D - 2 * c.vp : -1;
+  return c.ok ? D - 2 * c.vp : -1;
 }
 
 // v from lane addr / 4 (ds_bpermute, all lanes active)
@@ -188,8 +188,8 @@ __device__ __forceinline__ double bperm_d(int addr, double v) {
 // one instruction stream.  Coefficients above a member's degree are exact
 // zeros, so the shift by one power of x brings a zero into lane 32 (the
 // scale is kept finite for that: a zero times it stays zero).  In the packed
-// form the per-chain values (al bl, bl, the sign count, the running minimum
-// of the leads) are held per lane, equal within each half, and the two
+// form the per-chain values (al bl, bl, the sign count, the members' largest
+// magnitudes, the test) are held per lane, equal within each half, and the two
 // coefficients a step needs from its own half (t_db for the quotient, the new
 // leading coefficient) come by ds_bpermute from lane 32 h + db (- 1).
 __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int& ca, int& cb) {
@@ -203,11 +203,11 @@ __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int
   }
   const int half = lane >> 5, hl = lane & 31;
   const double bA = __shfl(b.A, hl), bB = __shfl(b.B, hl);   // all lanes active
-  const int rma = wave_max_int(a.rmax), rmb = wave_max_int(b.rmax);
   double A = half ? bA : a.A, B = half ? bB : a.B;
   double bl = half ? b.bl : a.bl, ab = half ? b.al * b.bl : a.al * a.bl;
-  int rmax = half ? rmb : rma, rminl = half ? b.rminl : a.rminl;
+  int hMA = half ? b.hMA : a.hMA, hMB = half ? b.hMB : a.hMB;
   int sp = half ? b.sp : a.sp, vp = half ? b.vp : a.vp;
+  bool ok = half ? b.ok : a.ok;
   const int pbase = (lane & 32) << 2;   // ds_bpermute byte address of the half's lane 0
   for (; q <= D; ++q) {
     const int db = D - q + 1;
@@ -216,23 +216,26 @@ __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int
     const double q0 = bperm_d(pl + 4, t) * bl;
     t = hl < db ? fma(-q0, B, t) : 0.0;
     const double lead = bperm_d(pl, t);
-    const int hlead = hiword(lead);
+    const int hlead = hiword(lead), hla = hlead & 0x7fffffff;
+    int hra, hrb;
+    half_max_int(hiword(t) & 0x7fffffff, hra, hrb);
+    const int hr = half ? hrb : hra;
+    ok = ok & sturm_step_ok(hr, hla, max(hMA, hMB));
     const int tp = (int)((unsigned)hlead >> 31);   // P_q positive at +inf
     vp += tp ^ sp;
     sp = tp;
-    rminl = min(rminl, hlead & 0x7fffffff);
     const double s = fast_rcp_d(fabs(lead) + 1e-300);
     const double nb = from_hiword((hlead & 0x80000000) ^ 0xbff00000);   // -sign(lead)
     A = B;
     B = -t * s;
-    rmax = max(rmax, hiword(B) & 0x7fffffff);
+    hMA = hMB;
+    hMB = sturm_member_hi(hr, hla);
     ab = bl * nb;
     bl = nb;
   }
-  int hma, hmb;
-  half_max_hi_int(rmax, hma, hmb);
-  ca = sturm_trusted(a.ok, hma, __builtin_amdgcn_readlane(rminl, 0)) ? D - 2 * __builtin_amdgcn_readlane(vp, 0) : -1;
-  cb = sturm_trusted(b.ok, hmb, __builtin_amdgcn_readlane(rminl, 32)) ? D - 2 * __builtin_amdgcn_readlane(vp, 32) : -1;
+  const unsigned long long okm = __ballot(ok);
+  ca = (okm & 1ull) ? D - 2 * __builtin_amdgcn_readlane(vp, 0) : -1;
+  cb = (okm >> 32 & 1ull) ? D - 2 * __builtin_amdgcn_readlane(vp, 32) : -1;
 }
 
 struct LearnArgs {
