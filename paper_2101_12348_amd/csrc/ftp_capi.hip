@@ -983,14 +983,18 @@ namespace {
 // against N_c, with the sign of i^c's real or imaginary part.  Stored as
 // T[j (D + 1) + c] = s_c N_c(j), s_c = +1 for c = 0, 3 mod 4 and -1 for 1, 2.
 // Exact integers up to D = 52; the entries of larger D round to doubles.
+// Only rows j = 0..K (D = 2K) are kept: N_c(D - j) = (-1)^c N_c(j) (a -> c - a
+// in the sum), and rho_{D-j} = conj(rho_j) since R is real, so the terms j and
+// D - j of f_c are equal and f_c = sum_{j<K} 2 rho'_j T[j][c] + rho'_K T[K][c].
 std::vector<double> cayley_table(int D) {
   std::vector<std::vector<int64_t>> C(D + 1, std::vector<int64_t>(D + 1, 0));
   for (int n = 0; n <= D; ++n) {
     C[n][0] = 1;
     for (int k = 1; k <= n; ++k) C[n][k] = C[n - 1][k - 1] + (k <= n - 1 ? C[n - 1][k] : 0);
   }
-  std::vector<double> T((size_t)(D + 1) * (D + 1));
-  for (int j = 0; j <= D; ++j)
+  const int K = D / 2;
+  std::vector<double> T((size_t)(K + 1) * (D + 1));
+  for (int j = 0; j <= K; ++j)
     for (int c = 0; c <= D; ++c) {
       int64_t acc = 0;
       const int a0 = c - (D - j) > 0 ? c - (D - j) : 0, a1 = j < c ? j : c;

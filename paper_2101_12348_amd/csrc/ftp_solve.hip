@@ -478,16 +478,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       if (D < 64) {
         // f_c = sum_j (rho_{j-K}.x or .y) T[j][c] with the Cayley-map table
         // (coefficient c of u^j v^(D-j), u = 1 + i x, v = 1 - i x, divided by
-        // i^c); lane j forms rho_{j-K}, lane c the dot product of column c
+        // i^c), whose terms j and D - j are equal (the table keeps rows j <=
+        // K): f_c = sum_{j<K} 2 rho'_j T[j][c] + rho'_K T[K][c].  Lane j forms
+        // 2 rho_{j-K} (rho_0 once), lane c the dot product of column c.
         double* rx = reinterpret_cast<double*>(S.hb[0]);
-        double* ry = rx + (D + 1);
+        double* ry = rx + (K + 1);
         {
           const int d = lane - K;
           const double ec = __shfl(tab_c, (d * k0) & 15), es = __shfl(tab_s, (d * k0) & 15);
-          if (lane <= D) {
-            const double2 rho = cmul(d >= 0 ? W.r[d] : cconj(W.r[-d]), make_double2(ec, es));
-            rx[lane] = rho.x;
-            ry[lane] = rho.y;
+          if (lane <= K) {
+            const double2 rho = cmul(cconj(W.r[-d]), make_double2(ec, es));
+            const double wgt = lane < K ? 2.0 : 1.0;
+            rx[lane] = wgt * rho.x;
+            ry[lane] = wgt * rho.y;
           }
         }
         wave_sync();
@@ -496,11 +499,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           const double* col = a.ctab + lane;
           double acc0 = 0.0, acc1 = 0.0;
           int jx = 0;
-          for (; jx + 1 <= D; jx += 2) {
+          for (; jx + 1 <= K; jx += 2) {
             acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
             acc1 = fma(rc[jx + 1], col[(jx + 1) * (D + 1)], acc1);
           }
-          if (jx <= D) acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
+          if (jx <= K) acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
           Rr[RL.f + lane] = acc0 + acc1;
         }
       } else {
@@ -622,18 +625,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const unsigned hm = half ? (unsigned)(mask >> 32) : (unsigned)mask;
     const int k0 = hm ? __ffs(hm) - 1 : 0;
     const double phi0 = constant ? 0.0 : kTwoPi * k0 / 16.0;
-    // rho_j = r_{j-K} e^{i (j-K) phi0}, j = 0..D, in two rounds of 32 (every
-    // lane takes part in the table reads), then the dot products
+    // 2 rho_j = 2 r_{j-K} e^{i (j-K) phi0}, j = 0..K - 1, and rho_K (K + 1 <=
+    // 30 lanes: every lane takes part in the table reads), then the dot
+    // products over the table's rows j <= K (the terms j and D - j are equal)
     double* rx = reinterpret_cast<double*>(S.hb[0]);
-    double* ry = rx + (D + 1);
-    for (int rr = 0; rr < 2; ++rr) {
-      const int jx = hl + 32 * rr, d = jx - K;
+    double* ry = rx + (K + 1);
+    {
+      const int jx = hl, d = jx - K;
       const int m = (d * k0) & 15;
       const double ec = __shfl(tab_c, m), es = __shfl(tab_s, m);
-      if (jx <= D) {
-        const double2 rho = cmul(d >= 0 ? W.r[d] : cconj(W.r[d < 0 ? -d : 0]), make_double2(ec, es));
-        rx[jx] = rho.x;
-        ry[jx] = rho.y;
+      if (jx <= K) {
+        const double2 rho = cmul(cconj(W.r[-d]), make_double2(ec, es));
+        const double wgt = jx < K ? 2.0 : 1.0;
+        rx[jx] = wgt * rho.x;
+        ry[jx] = wgt * rho.y;
       }
     }
     wave_sync();
@@ -643,11 +648,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const double* col = a.ctab + c;
       double acc0 = 0.0, acc1 = 0.0;
       int jx = 0;
-      for (; jx + 1 <= D; jx += 2) {
+      for (; jx + 1 <= K; jx += 2) {
         acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
         acc1 = fma(rc[jx + 1], col[(jx + 1) * (D + 1)], acc1);
       }
-      if (jx <= D) acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
+      if (jx <= K) acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
       if (write && !constant) Rr[RL.f + c] = acc0 + acc1;
     }
     if (write) {

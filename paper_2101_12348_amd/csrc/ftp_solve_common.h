@@ -15,7 +15,7 @@ struct SolveArgs {
   const void* grids;             // float2 or double2 grids
   const double* sums_in;         // optional: per pair 3H complex sums (see gather)
   const double2* alpha;          // template alpha_n, n = 1..H (shared phase: n_band x H, band-major)
-  const double* ctab;            // Cayley-map table, (D + 1)^2 doubles, D < 64 (see k_assemble)
+  const double* ctab;            // Cayley-map table, rows j = 0..K of D + 1 doubles, D < 64 (see k_assemble)
   int n_band;                    // 0: single band; > 0: shared-phase bands (lcs[0..n_band))
   int newton_cands;              // candidates of M_FALLBACK == 0 pairs are Newton-converged roots
   int H;
