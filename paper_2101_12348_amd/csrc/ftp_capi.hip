@@ -100,10 +100,10 @@ hipError_t launch_aberth(const AberthArgs& A, int waves, hipStream_t st);
 struct FusedMlpArgs {
   const uint16_t* X;
   int64_t np;
-  const uint16_t* wb;
+  const uint16_t* wi;
   const float* w32;
-  int64_t oW[4], ob[4];
-  int nin[4], nout[4];
+  int64_t oWi[4], ob[4];
+  int kp[4], nout[4];
   float* out;
 };
 bool mlp_fused_ok(const int* nin, const int* nout);
@@ -170,7 +170,8 @@ struct MlpNet {
   int nin[4], nout[4];
   DevBuf w32, wbf, grad, am, av, loss;
   // inference copy of the bf16 weights with each layer's rows zero-padded to
-  // kp[l] (a multiple of 32) for the dense-layer kernel; built when a plan
+  // kp[l] (a multiple of 32) and their number to a multiple of 16, for the
+  // dense-layer and fused network kernels; built when a plan
   // loads a network whose width is a multiple of 32
   DevBuf winf;
   int kp[4] = {0, 0, 0, 0};
@@ -239,11 +240,13 @@ int mlp_set_weights(MlpNet* N, const float* w) {
 int mlp_build_inference(MlpNet* N, const float* w) {
   N->dense = N->width % 32 == 0;
   if (!N->dense) return FTP_OK;
+  // rows padded with zeros to a multiple of 16 (whole MFMA column tiles: the
+  // fused network kernel reads every row of a tile unconditionally)
   int64_t o = 0;
   for (int l = 0; l < 4; ++l) {
     N->kp[l] = (N->nin[l] + 31) & ~31;
     N->oWi[l] = o;
-    o += (int64_t)N->nout[l] * N->kp[l];
+    o += (int64_t)((N->nout[l] + 15) & ~15) * N->kp[l];
   }
   std::vector<uint16_t> b((size_t)o, 0);
   for (int l = 0; l < 4; ++l)
@@ -716,7 +719,8 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       !dataset && (solver == FTP_SOLVER_LEARNED || solver == FTP_SOLVER_UNIFORM) && 6 * P->H - 2 < 64;
   // learned solver with a fusable network: features in rows of dinp bf16
   // (zero padded), then one kernel for the four layers
-  const bool fused = solver == FTP_SOLVER_LEARNED && P->tune.mlp_fused && mlp_fused_ok(P->net.nin, P->net.nout);
+  const bool fused = solver == FTP_SOLVER_LEARNED && P->tune.mlp_fused && P->net.dense &&
+                     mlp_fused_ok(P->net.nin, P->net.nout);
   const int dinp = (P->net.din + 31) & ~31;
   if ((fused || P->net.dense) && (rc = P->xfeat.ensure(sizeof(uint16_t) * chunk * dinp))) return rc;
   for (int64_t p0 = 0; p0 < n_pairs; p0 += chunk) {
@@ -742,12 +746,12 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
           FusedMlpArgs fa{};
           fa.X = P->xfeat.as<uint16_t>();
           fa.np = np;
-          fa.wb = N.wbf.as<uint16_t>();
+          fa.wi = N.winf.as<uint16_t>();
           fa.w32 = N.w32.as<float>();
           for (int l = 0; l < 4; ++l) {
-            fa.oW[l] = N.oW[l];
+            fa.oWi[l] = N.oWi[l];
             fa.ob[l] = N.ob[l];
-            fa.nin[l] = N.nin[l];
+            fa.kp[l] = N.kp[l];
             fa.nout[l] = N.nout[l];
           }
           fa.out = P->seeds.as<float>();

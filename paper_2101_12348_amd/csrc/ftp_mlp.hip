@@ -14,6 +14,11 @@
 namespace ftp {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+
+// float -> bf16 bits by the hardware conversion (round to nearest even, one
+// instruction on gfx950; equal to f2bf for finite values), used by the
+// inference epilogues of k_dense_bf16 and k_mlp_fused alike
+__device__ __forceinline__ uint16_t bf16_rne(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 
 // ------------------------------------------------------------------ GEMM
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(256 * RW) void k_dense_bf16(DenseArgs d) {
           for (int v = 0; v < 4; ++v) {
             float x = acc[i][j][v] + bn;
             if (d.relu) x = fmaxf(x, 0.f);
-            Ct[(16 * i + 4 * (lane >> 4) + v) * kCP + cl] = f2bf(x);
+            Ct[(16 * i + 4 * (lane >> 4) + v) * kCP + cl] = bf16_rne(x);
           }
       }
     }
@@ -407,112 +412,145 @@ __global__ __launch_bounds__(64) void k_features2(double* rec, int H, int64_t np
 
 // ------------------------------------------------------- fused inference
 
-// The four layers of the network for 64 pairs per workgroup:
-// wave w owns pairs 16 w .. 16 w + 15 of the workgroup's tile and keeps their
-// activations in its own LDS rows (the output of a layer becomes the A operand
-// of the next); the weights of each 32-wide K step are staged once per
-// workgroup in LDS (double-buffered) and shared by the four waves.  Each wave
-// computes all N tiles of its 16 rows with v_mfma_f32_16x16x32_bf16 (FP32
-// accumulation); bias and ReLU are applied in the epilogue, which rounds the
-// hidden activations to bf16 (the same rounding points as k_gemm_bf16).
-// Requirements (checked on the host): width a multiple of 32 up to 256,
-// d_in and d_out up to 256.
+// The four layers of the network for 128 pairs per workgroup (four waves),
+// with the activations kept in LDS between layers: the output of a layer is
+// written over its input (after every wave has read it) and is the A operand
+// of the next.  Per layer, wave w computes all 128 rows of the column tiles
+// 4w .. 4w + 3 (64 columns) as 8 x 4 MFMA 16 x 16 x 32 tiles.  The weights
+// (about 300 KB for width 256, resident in L2) are read by each wave straight
+// into its B fragments, three K slices ahead, so the K loop has no barrier;
+// the LDS holds only the activations (67.5 KB: two workgroups per CU).
+// Weights: the inference copy with each layer's rows zero-padded to kp[l]
+// (multiples of 32, 16-byte aligned) and their number to a multiple of 16.
+// Same operands, K order, bias, ReLU and
+// bf16 rounding as k_dense_bf16, so the result equals the unfused launches
+// bit for bit.  Requirements (checked on the host): width a multiple of 32 up
+// to 256, kp[0] up to 256, d_out up to 64.
 struct FusedMlpArgs {
-  const uint16_t* X;     // np x dinp bf16 features (dinp = d_in rounded up to 32)
+  const uint16_t* X;     // np x kp[0] bf16 features (zero padded)
   int64_t np;
-  const uint16_t* wb;    // bf16 weights, layer l at wb + oW[l], (out, in) row-major
+  const uint16_t* wi;    // padded bf16 weights, layer l at wi + oWi[l], rows of kp[l]
   const float* w32;      // FP32 parameters (biases at w32 + ob[l])
-  int64_t oW[4], ob[4];
-  int nin[4], nout[4];
+  int64_t oWi[4], ob[4];
+  int kp[4], nout[4];
   float* out;            // np x nout[3]
 };
 
-constexpr int kFRows = 64;           // pairs per workgroup
+constexpr int kFRows = 128;          // pairs per workgroup
+constexpr int kFRT = kFRows / 16;    // row tiles
 constexpr int kActLd = 256 + 8;      // LDS row of one pair's activations (bf16)
-constexpr int kWLd = 32 + 8;         // LDS row of one output unit's K slice (bf16)
-constexpr int kWMaxN = 256;
+constexpr int kOutLd = 64 + 4;       // LDS row of one pair's outputs (FP32, d_out <= 64)
 
-__global__ __launch_bounds__(256) void k_mlp_fused(FusedMlpArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_fused(FusedMlpArgs a) {
   __shared__ __align__(16) uint16_t act[kFRows * kActLd];
-  __shared__ __align__(16) uint16_t wst[2][kWMaxN * kWLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * kFRows;
-  uint16_t* myact = act + wave * 16 * kActLd;
-  // features of this wave's 16 pairs (rows of X, stride dinp, zero padded;
-  // zero rows past the end)
-  const int din = a.nin[0];
-  const int dinp = (din + 31) & ~31;
-  for (int q = lane; q < 16 * (dinp / 8); q += 64) {
-    const int i = q / (dinp / 8), c = (q % (dinp / 8)) * 8;
-    const int64_t w = row0 + wave * 16 + i;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (w < a.np) v = *reinterpret_cast<const uint4*>(a.X + w * dinp + c);
-    *reinterpret_cast<uint4*>(myact + i * kActLd + c) = v;
+  // features of the 128 pairs (rows of X, stride kp[0]; zero rows past the end)
+  {
+    const int c8 = a.kp[0] / 8;
+    for (int q = tid; q < kFRows * c8; q += 256) {
+      const int i = q / c8, c = (q % c8) * 8;
+      const int64_t w = row0 + i;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (w < a.np) v = *reinterpret_cast<const uint4*>(a.X + w * a.kp[0] + c);
+      *reinterpret_cast<uint4*>(&act[i * kActLd + c]) = v;
+    }
   }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  __syncthreads();
   const int mrow = lane & 15, kq = 8 * (lane >> 4);
+#pragma unroll 1
   for (int l = 0; l < 4; ++l) {
-    const int nin = a.nin[l], nout = a.nout[l];
-    const int K = l == 0 ? dinp : nin;
-    const int nt = (nout + 15) >> 4;
-    const uint16_t* W = a.wb + a.oW[l];
-    f32x4_t acc[16];
+    const int K = a.kp[l], nout = a.nout[l];
+    const int nt = (nout + 15) >> 4;             // column tiles of the layer
+    const int j0 = 4 * wave;                     // this wave's first column tile
+    const bool on = j0 < nt;
+    const uint16_t* W = a.wi + a.oWi[l];
+    f32x4_t acc[kFRT][4];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    // stage the K slice [k0, k0 + 32) of rows n < 16 nt into buffer b
-    auto stage = [&](int b, int k0) {
-      for (int c = tid; c < nt * 16 * 4; c += 256) {
-        const int n = c >> 2, kk = (c & 3) * 8;
-        uint16_t* dst = &wst[b][n * kWLd + kk];
-        const int64_t off = (int64_t)n * nin + k0 + kk;
-        if (n < nout && k0 + kk + 8 <= nin && ((a.oW[l] + off) & 7) == 0) {
-          *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(W + off);
-        } else {
-          for (int e = 0; e < 8; ++e)
-            dst[e] = (n < nout && k0 + kk + e < nin) ? W[off + e] : (uint16_t)0;
+    for (int i = 0; i < kFRT; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    if (on) {
+      // B fragment of column tile j0 + j at K slice k0: weight row 16 (j0 + j)
+      // + lane % 16, k = k0 + 8 (lane / 16) .. + 7.  Loaded unconditionally
+      // (the rows are padded to whole tiles; a tile past the layer's last
+      // reads its last row, a slice past K the last slice: both unused)
+      const int npad = (nout + 15) & ~15;
+      auto loadB = [&](int k0, bf16x8_t (&f)[4]) {
+        const int kc = k0 < K ? k0 : K - 32;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = min(16 * (j0 + j) + mrow, npad - 1);
+          f[j] = *reinterpret_cast<const bf16x8_t*>(W + (int64_t)n * K + kc + kq);
+        }
+      };
+      bf16x8_t b0[4], b1[4], b2[4];
+      loadB(0, b0);
+      loadB(32, b1);
+      loadB(64, b2);
+#pragma unroll 1
+      for (int k0 = 0; k0 < K; k0 += 32) {
+        // the slice's eight A fragments first, then its 32 MFMAs
+        bf16x8_t af[kFRT];
+#pragma unroll
+        for (int i = 0; i < kFRT; ++i)
+          af[i] = *reinterpret_cast<const bf16x8_t*>(&act[(16 * i + mrow) * kActLd + k0 + kq]);
+#pragma unroll
+        for (int i = 0; i < kFRT; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], b0[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          b0[j] = b1[j];
+          b1[j] = b2[j];
+        }
+        loadB(k0 + 96, b2);
+      }
+    }
+    __syncthreads();   // every wave is done reading this layer's input
+    // epilogue: lane holds rows 16 i + 4 (lane / 16) + v, column 16 (j0 + j) +
+    // lane % 16; each column is written through one base address with the
+    // rows as constant offsets.  Hidden layers: bf16 over the input; the last
+    // layer: FP32 rows of kOutLd through the same LDS, then copied out
+    const float* bias = a.w32 + a.ob[l];
+    if (l < 3) {
+      if (on) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int n = 16 * (j0 + j) + mrow;
+          if (j0 + j >= nt || n >= nout) continue;
+          const float bn = bias[n];
+          uint16_t* base = act + 4 * (lane >> 4) * kActLd + n;
+#pragma unroll
+          for (int i = 0; i < kFRT; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) base[(16 * i + v) * kActLd] = bf16_rne(fmaxf(acc[i][j][v] + bn, 0.f));
         }
       }
-    };
-    stage(0, 0);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < K; k0 += 32) {
-      if (k0 + 32 < K) stage(buf ^ 1, k0 + 32);
-      bf16x8_t af;
-      memcpy(&af, myact + mrow * kActLd + k0 + kq, 16);
+      __syncthreads();   // the next layer reads these outputs
+    } else {
+      float* of = reinterpret_cast<float*>(act);
+      if (on) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        if (j < nt) {
-          bf16x8_t bfv;
-          memcpy(&bfv, &wst[buf][(16 * j + mrow) * kWLd + kq], 16);
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfv, acc[j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          const int n = 16 * (j0 + j) + mrow;
+          if (j0 + j >= nt || n >= nout) continue;
+          const float bn = bias[n];
+          float* base = of + 4 * (lane >> 4) * kOutLd + n;
+#pragma unroll
+          for (int i = 0; i < kFRT; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) base[(16 * i + v) * kOutLd] = acc[i][j][v] + bn;
         }
       }
       __syncthreads();
-      buf ^= 1;
-    }
-    // epilogue: rows 4 (lane / 16) + v, column 16 j + lane % 16
-    const float* bias = a.w32 + a.ob[l];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      if (j >= nt) continue;
-      const int n = 16 * j + mrow;
-      if (n >= nout) continue;
-      const float bn = bias[n];
-      for (int v = 0; v < 4; ++v) {
-        const int r = 4 * (lane >> 4) + v;
-        float xv = acc[j][v] + bn;
-        if (l < 3) {
-          myact[r * kActLd + n] = f2bf(fmaxf(xv, 0.f));
-        } else {
-          const int64_t w = row0 + wave * 16 + r;
-          if (w < a.np) a.out[w * nout + n] = xv;
-        }
+      for (int q = tid; q < kFRows * nout; q += 256) {
+        const int r = q / nout, c = q - r * nout;
+        const int64_t w = row0 + r;
+        if (w < a.np) a.out[w * nout + c] = of[r * kOutLd + c];
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -585,7 +623,7 @@ hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_
 }
 
 bool mlp_fused_ok(const int* nin, const int* nout) {
-  if (nin[0] > 256 || nout[3] < 1 || nout[3] > 256) return false;
+  if (((nin[0] + 31) & ~31) > 256 || nout[3] < 1 || nout[3] > 64) return false;
   for (int l = 0; l < 3; ++l)
     if (nout[l] % 32 != 0 || nout[l] > 256) return false;
   return nin[1] == nout[0] && nin[2] == nout[1] && nin[3] == nout[2];
