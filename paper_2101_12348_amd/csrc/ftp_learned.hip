@@ -188,28 +188,35 @@ __device__ __forceinline__ double bperm_d(int addr, double v) {
 // one instruction stream.  Coefficients above a member's degree are exact
 // zeros, so the shift by one power of x brings a zero into lane 32 (the
 // scale is kept finite for that: a zero times it stays zero).  In the packed
-// form the per-lane values al bl, bl and the sign count are equal within each
-// half, the test runs on scalar registers per chain, and the two
+// form the per-lane values al bl and bl are equal within each half, the test
+// and the sign count run on scalar registers per chain, and the two
 // coefficients a step needs from its own half (t_db for the quotient, the new
 // leading coefficient) come by ds_bpermute from lane 32 h + db (- 1).
 // One packed step (both chains, one per half-wave): the new member from A and
 // B into A (the caller swaps the roles of A and B on alternate steps, so that
 // the chain needs no register moves).  The step's test values go to scalar
-// registers per chain: hr (hi of max |t|), hl (hi of |lead|), and the signs.
+// registers per chain: hr (hi of max |t|) and hl (the signed high word of the
+// new leading coefficient), which also gives the sign count.
 struct PackedScalars {
-  int hMA, hMB;   // hi(max |coefficient|) of the two members, per chain
-  int m12, m13;   // smallest margins of the two tests so far, per chain
+  int hMA, hMB;   // hi(max |coefficient|) of the two members
+  int m12, m13;   // smallest margins of the two tests so far
   int hmax;       // largest hi(max |t|) so far (finiteness)
+  int sp, vp;     // last member positive at +inf (0 / 1); sign changes at +inf
 };
+// hr = hi(max |t|), hl = the high word of the new leading coefficient (signed)
 __device__ __forceinline__ void packed_scalars_step(PackedScalars& c, int hr, int hl) {
+  const int ha = hl & 0x7fffffff;
   c.m12 = min(c.m12, hr - max(c.hMA, c.hMB));
-  c.m13 = min(c.m13, hl - hr);
+  c.m13 = min(c.m13, ha - hr);
   c.hmax = max(c.hmax, hr);
   c.hMA = c.hMB;
-  c.hMB = sturm_member_hi(hr, hl);
+  c.hMB = sturm_member_hi(hr, ha);
+  const int tp = (int)((unsigned)hl >> 31);   // P_q = -t / |lead| positive at +inf
+  c.vp += tp ^ c.sp;
+  c.sp = tp;
 }
-__device__ __forceinline__ void sturm_packed_step(double& A, const double B, double& bl, double& ab, int& sp, int& vp,
-                                                  PackedScalars& sa, PackedScalars& sb, int db, int hl, int pbase) {
+__device__ __forceinline__ void sturm_packed_step(double& A, const double B, double& bl, double& ab, PackedScalars& sa,
+                                                  PackedScalars& sb, int db, int hl, int pbase) {
   double t = fma(-ab, lane_shr1(B), A);
   const int pl = pbase + ((db - 1) << 2);
   const double q0 = bperm_d(pl + 4, t) * bl;
@@ -218,11 +225,8 @@ __device__ __forceinline__ void sturm_packed_step(double& A, const double B, dou
   const int hlead = hiword(lead);
   int hra, hrb;
   half_max_int(hiword(t) & 0x7fffffff, hra, hrb);
-  packed_scalars_step(sa, hra, __builtin_amdgcn_readlane(hlead, 0) & 0x7fffffff);
-  packed_scalars_step(sb, hrb, __builtin_amdgcn_readlane(hlead, 32) & 0x7fffffff);
-  const int tp = (int)((unsigned)hlead >> 31);   // P_q positive at +inf
-  vp += tp ^ sp;
-  sp = tp;
+  packed_scalars_step(sa, hra, __builtin_amdgcn_readlane(hlead, 0));
+  packed_scalars_step(sb, hrb, __builtin_amdgcn_readlane(hlead, 32));
   const double s = fast_rcp_d(fabs(lead) + 1e-300);
   const double nb = from_hiword((hlead & 0x80000000) ^ 0xbff00000);   // -sign(lead)
   A = -t * s;
@@ -243,24 +247,23 @@ __device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int
   const double bA = __shfl(b.A, hl), bB = __shfl(b.B, hl);   // all lanes active
   double A = half ? bA : a.A, B = half ? bB : a.B;
   double bl = half ? b.bl : a.bl, ab = half ? b.al * b.bl : a.al * a.bl;
-  int sp = half ? b.sp : a.sp, vp = half ? b.vp : a.vp;
   // the steps' tests, kept as the smallest margins and checked at the end
-  // (the same as requiring every step to pass)
-  PackedScalars sa{a.hMA, a.hMB, 0x7fffffff, 0x7fffffff, 0};
-  PackedScalars sb{b.hMA, b.hMB, 0x7fffffff, 0x7fffffff, 0};
+  // (the same as requiring every step to pass), and the sign counts
+  PackedScalars sa{a.hMA, a.hMB, 0x7fffffff, 0x7fffffff, 0, a.sp, a.vp};
+  PackedScalars sb{b.hMA, b.hMB, 0x7fffffff, 0x7fffffff, 0, b.sp, b.vp};
   const int pbase = (lane & 32) << 2;   // ds_bpermute byte address of the half's lane 0
   // two steps per trip: the new member overwrites the older of the two
   for (; q + 1 <= D; q += 2) {
-    sturm_packed_step(A, B, bl, ab, sp, vp, sa, sb, D - q + 1, hl, pbase);
-    sturm_packed_step(B, A, bl, ab, sp, vp, sa, sb, D - q, hl, pbase);
+    sturm_packed_step(A, B, bl, ab, sa, sb, D - q + 1, hl, pbase);
+    sturm_packed_step(B, A, bl, ab, sa, sb, D - q, hl, pbase);
   }
   if (q <= D) {
-    sturm_packed_step(A, B, bl, ab, sp, vp, sa, sb, D - q + 1, hl, pbase);
+    sturm_packed_step(A, B, bl, ab, sa, sb, D - q + 1, hl, pbase);
   }
   const bool oka = a.ok && sa.hmax < 0x7ff00000 && sa.m12 > -kHiT12 && sa.m13 > -kHiT13;
   const bool okb = b.ok && sb.hmax < 0x7ff00000 && sb.m12 > -kHiT12 && sb.m13 > -kHiT13;
-  ca = oka ? D - 2 * __builtin_amdgcn_readlane(vp, 0) : -1;
-  cb = okb ? D - 2 * __builtin_amdgcn_readlane(vp, 32) : -1;
+  ca = oka ? D - 2 * sa.vp : -1;
+  cb = okb ? D - 2 * sb.vp : -1;
 }
 
 struct LearnArgs {

@@ -319,11 +319,13 @@ __device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane, d
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier();
 }
 
-// v from lane (lane - 1); lane 0 receives 0 (DPP wave_shr:1, all lanes active)
+// v from lane (lane - 1); lane 0 receives 0 (DPP wave_shr:1 with bound_ctrl:
+// a lane whose source is out of range reads 0, so no zeroed `old` operand is
+// needed; all lanes active)
 __device__ __forceinline__ double lane_shr1(double v) {
   const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x138, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffull), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x138, 0xf, 0xf, true);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 // v from lane (lane + 1); lane 63 receives 0 (DPP wave_shl:1)
