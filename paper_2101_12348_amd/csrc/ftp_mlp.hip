@@ -371,9 +371,10 @@ __global__ __launch_bounds__(64) void k_features2(double* rec, int H, int64_t np
     const double2 r1 = r[1];
     const double m1 = sqrt(r1.x * r1.x + r1.y * r1.y);
     const double canon = m1 > 0.0 ? (double)atan2f((float)r1.y, (float)r1.x) : 0.0;
-    const double2 u = m1 > 0.0 ? make_double2(r1.x / m1, -r1.y / m1) : make_double2(1.0, 0.0);
+    const double im1 = m1 > 0.0 ? 1.0 / m1 : 0.0;
+    const double2 u = m1 > 0.0 ? make_double2(r1.x * im1, -r1.y * im1) : make_double2(1.0, 0.0);
     double2 v[2];
-    double amax = 0.0;
+    double a2 = 0.0;   // largest |v|^2 of the half
     for (int s = 0; s < 2; ++s) {
       const int k = hl + 32 * s;
       v[s] = make_double2(0.0, 0.0);
@@ -390,20 +391,22 @@ __global__ __launch_bounds__(64) void k_features2(double* rec, int H, int64_t np
       rd = cmul(rd, pw);
       if (d < 0) rd = cconj(rd);
       v[s] = make_double2(rd.y, -rd.x);   // -i (a + i b) = b - i a
-      amax = fmax(amax, sqrt(v[s].x * v[s].x + v[s].y * v[s].y));
+      a2 = fmax(a2, v[s].x * v[s].x + v[s].y * v[s].y);
     }
     double lo, hi;
-    half_max_d(amax, lo, hi);
-    amax = half ? hi : lo;
+    half_max_d(a2, lo, hi);
+    const double amax = sqrt(half ? hi : lo);
     const double sc = amax > 0.0 ? 1.0 / amax : 0.0;
     if (has) {
-      uint16_t* x = X + w * ldx;
-      for (int64_t q = 2 * (D + 1) + hl; q < ldx; q += 32) x[q] = 0;
+      // (Re, Im) of coefficient k as one 32-bit store; the padding of the row
+      // (ldx and 2 (D + 1) even) likewise
+      unsigned* x = reinterpret_cast<unsigned*>(X + w * ldx);
+      for (int64_t q = (D + 1) + hl; q < ldx / 2; q += 32) x[q] = 0u;
       for (int s = 0; s < 2; ++s) {
         const int k = hl + 32 * s;
         if (k > D) continue;
-        x[2 * k] = zero ? (uint16_t)0 : f2bf((float)(v[s].x * sc));
-        x[2 * k + 1] = zero ? (uint16_t)0 : f2bf((float)(v[s].y * sc));
+        const unsigned re = zero ? 0u : f2bf((float)(v[s].x * sc)), im = zero ? 0u : f2bf((float)(v[s].y * sc));
+        x[k] = re | (im << 16);
       }
       if (hl == 0 && !zero) R[RL.meta + M_CANON] = canon;
     }
