@@ -8,13 +8,12 @@
 //   * if the count is well determined, 2H network seeds plus evenly spaced
 //     starts (only evenly spaced starts for the ablation without network) are
 //     refined by FP64 Newton on R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta
-//     (Eq. theta2cond written as R(theta) = i e^{-i K theta} p(e^{i theta}));
-//     for H <= 10 each step of R is evaluated on the Cayley polynomial f and
-//     the iterate kept as tan((theta - phi0) / 2) or its reciprocal;
-//     converged roots closer than 1e-8 rad are merged after every iteration
-//     from the fourth (two-frequency kernel; after iterations 4-8, 10 and 12
-//     in the one-frequency kernel), and Newton stops once the merged roots
-//     reach the count;
+//     (Eq. theta2cond written as R(theta) = i e^{-i K theta} p(e^{i theta})),
+//     each step evaluated on the Cayley polynomial f with the iterate kept as
+//     tan((theta - phi0) / 2) or its reciprocal (newton_u_step); converged
+//     roots closer than 1e-8 rad are merged, one root per pass, after every
+//     iteration from the fourth, and Newton stops once the merged roots reach
+//     the count;
 //   * if they do, the Newton roots are the candidate set; otherwise the
 //     frequency goes to the Aberth iteration (then, if that does not
 //     converge, to the companion-matrix solve) through device work lists.
@@ -276,132 +275,6 @@ struct LearnArgs {
   unsigned* queue;          // work counter (zeroed), or nullptr for grid striding
 };
 
-__host__ __device__ inline size_t learn_lds_bytes(int H) {
-  const int K = 3 * H - 1, D = 2 * K;
-  return (size_t)(2 * (K + 1) + (D + 2)) * sizeof(double);
-}
-
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_sturm(SolveArgs a, LearnArgs L) {
-  extern __shared__ double sml[];
-  const int lane = threadIdx.x & 63;
-  const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = 2 * S;
-  const RecLayout RL(H);
-  FreqWork W;
-  W.r = reinterpret_cast<double2*>(sml);
-  double* fl = sml + 2 * (K + 1);        // f copied to LDS
-  unsigned long long iters_acc = 0, roots_acc = 0, fb_acc = 0;
-  for (int64_t w = first_item(L.queue, lane); w < L.np; w = next_item(L.queue, lane, w)) {
-    double* R = L.rec + w * (int64_t)RL.stride;
-    const int st = (int)R[RL.meta + M_STATUS];
-    if (st == ST_BAD_LC || st == ST_CONSTANT) continue;
-    if (L.flags & 1u) {   // forced fallback
-      if (lane == 0) {
-        const unsigned slot = atomicAdd(L.fb_count, 1u);
-        L.fb_list[slot] = w;
-        R[RL.meta + M_FALLBACK] = 1.0;
-      }
-      ++fb_acc;
-      continue;
-    }
-    for (int d = lane; d <= K; d += 64) W.r[d] = make_double2(R[RL.r + 2 * d], R[RL.r + 2 * d + 1]);
-    for (int c = lane; c <= D; c += 64) fl[c] = R[RL.f + c];
-    lwave_sync();
-    // Sturm count first.  An ill-determined count (or fewer than the two
-    // real roots every non-constant P has: its maximum and minimum) sends the
-    // frequency on without Newton; otherwise Newton stops as soon as it has
-    // found that many distinct real roots.
-    int cnt = -1;
-    // real roots of f on the whole line = real phases other than phi0 + pi,
-    // where R does not vanish (f has full degree D)
-    cnt = sturm_count_line_reg(lane <= D ? fl[lane] : 0.0, fl[D], D, lane);
-    if (cnt < 2) cnt = -1;
-    // Newton from 4H starts: lanes < 2H take the network seeds and lanes
-    // 2H..4H-1 evenly spaced phases (with no network, all 4H are evenly spaced)
-    double thw = 0.0;   // root in [0, 2 pi)
-    bool uniq = false;
-    int nu = -1;
-    unsigned long long um = 0ull;
-    if (cnt >= 0) {
-      double th = 0.0;
-      bool conv = false, live = lane < NS;
-      int its = 0;
-      if (live) {
-        if (L.seeds_out && lane < S) {
-          const float* o = L.seeds_out + w * 2 * S;
-          th = atan2((double)o[2 * lane + 1], (double)o[2 * lane]) - R[RL.meta + M_CANON];
-        } else if (L.seeds_out) {
-          th = kTwoPi * (lane - S + 0.5) / S;
-        } else {
-          th = kTwoPi * (lane + 0.5) / NS;
-        }
-      }
-      for (int it = 1; it <= 12; ++it) {
-        if (live && !conv) {
-          double Rv, dR;
-          eval_R(W, H, th, Rv, dR);
-          const double step = Rv / dR;
-          if (!(dR != 0.0) || !isfinite(step)) {
-            live = false;
-          } else {
-            const double sc = fmax(-0.5, fmin(0.5, step));
-            th -= sc;
-            ++its;
-            if (fabs(sc) < 1e-12) conv = true;
-          }
-        }
-        if ((it >= 4 && it <= 8) || it == 10 || it == 12) {
-          const unsigned long long cm = __ballot(conv);
-          // fewer converged lanes than the count cannot reach it (the last
-          // check always runs: its roots seed the fallback)
-          if (it < 12 && __popcll(cm) < cnt) continue;
-          // distinct converged roots: merge those closer than 1e-8 rad,
-          // keeping the lowest lane
-          thw = fmod(th, kTwoPi);
-          if (thw < 0.0) thw += kTwoPi;
-          uniq = conv;
-          for (unsigned long long m = cm; m; m &= m - 1ull) {
-            const int jj = __builtin_ctzll(m);
-            const double tj = lrdlane(thw, jj);
-            double dd = fabs(tj - thw);
-            dd = fmin(dd, kTwoPi - dd);
-            if (jj < lane && dd < 1e-8) uniq = false;
-          }
-          um = __ballot(uniq && lane < NS);
-          nu = __popcll(um);
-          if (nu == cnt) break;
-        }
-      }
-      iters_acc += (unsigned long long)wave_sum((double)(lane < NS ? its : 0));
-    }
-    if (cnt >= 0 && cnt == nu) {
-      const int pos = __popcll(um & ((1ull << lane) - 1ull));
-      double* cand = R + RL.cand;
-      for (int c = lane; c < D; c += 64) cand[c] = __longlong_as_double(0x7ff8000000000000ll);
-      lwave_sync();
-      if (uniq && lane < NS) cand[pos] = thw;
-      roots_acc += (unsigned long long)nu;
-    } else {
-      // the distinct roots Newton did find start the Aberth iteration
-      const int nw = nu > 0 ? nu : 0;
-      if (nw > 0 && uniq && lane < NS) R[RL.cand + __popcll(um & ((1ull << lane) - 1ull))] = thw;
-      if (lane == 0) {
-        R[RL.meta + M_WARM] = (double)nw;
-        R[RL.meta + M_FALLBACK] = 1.0;
-        const unsigned slot = atomicAdd(L.fb_count, 1u);
-        L.fb_list[slot] = w;
-      }
-      ++fb_acc;
-    }
-    lwave_sync();
-  }
-  if (lane == 0 && a.counters) {
-    SolveCounters* c = counter_slot(a.counters);
-    if (iters_acc) atomicAdd(&c->newton_iters, iters_acc);
-    if (roots_acc) atomicAdd(&c->roots_found, roots_acc);
-    if (fb_acc) atomicAdd(&c->fallback, fb_acc);
-  }
-}
-
 // Newton on R(theta) carried out on the Cayley polynomial.  With x = tan((theta
 // - phi0) / 2), f(x) = (1 + x^2)^K R(theta), so R'/R = ((1 + x^2) f'/f - 2 K x)
 // / 2 and the Newton step of R in theta is d = 2 f / ((1 + x^2) f' - 2 K x f).
@@ -631,6 +504,138 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     roots_acc += (unsigned long long)((okA ? nuA : 0) + (okB ? nuB : 0));
     fb_acc += (unsigned long long)((actA && !okA) + (actB && !okB));
+    lwave_sync();
+  }
+  if (lane == 0 && a.counters) {
+    SolveCounters* c = counter_slot(a.counters);
+    if (iters_acc) atomicAdd(&c->newton_iters, iters_acc);
+    if (roots_acc) atomicAdd(&c->roots_found, roots_acc);
+    if (fb_acc) atomicAdd(&c->fallback, fb_acc);
+  }
+}
+
+// One frequency per wavefront (H = 11, D = 64): the Sturm chain of f in
+// registers (the degree-64 coefficient as a scalar), then Newton from 4H
+// starts (the 2H network seeds and 2H evenly spaced phases; all evenly spaced
+// without network), stepped on the Cayley polynomial and merged one root per
+// pass as in k_newton_sturm2, with the same stop rule.
+__host__ __device__ inline size_t learn_lds_bytes(int H) {
+  const int D = 6 * H - 2;
+  return (size_t)(2 * (D + 2)) * sizeof(double);   // f and its reversal
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_sturm(SolveArgs a, LearnArgs L) {
+  extern __shared__ double sml[];
+  const int lane = threadIdx.x & 63;
+  const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = 2 * S;
+  const int FS = D + 2;
+  const RecLayout RL(H);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  unsigned long long iters_acc = 0, roots_acc = 0, fb_acc = 0;
+  for (int64_t w = first_item(L.queue, lane); w < L.np; w = next_item(L.queue, lane, w)) {
+    double* R = L.rec + w * (int64_t)RL.stride;
+    const int st = (int)R[RL.meta + M_STATUS];
+    if (st == ST_BAD_LC || st == ST_CONSTANT) continue;
+    if (L.flags & 1u) {   // forced fallback
+      if (lane == 0) {
+        const unsigned slot = atomicAdd(L.fb_count, 1u);
+        L.fb_list[slot] = w;
+        R[RL.meta + M_FALLBACK] = 1.0;
+      }
+      ++fb_acc;
+      continue;
+    }
+    for (int c = lane; c <= D; c += 64) {
+      const double fc = R[RL.f + c];
+      sml[c] = fc;
+      sml[FS + D - c] = fc;
+    }
+    const double gv = lane <= D ? R[RL.f + lane] : 0.0;
+    const double gtop = R[RL.f + D];
+    lwave_sync();
+    // Sturm count first: an ill-determined count (or fewer than the two real
+    // roots every non-constant P has) sends the frequency on without Newton
+    int cnt = sturm_count_line_reg(gv, gtop, D, lane);
+    if (cnt < 2) cnt = -1;
+    const double phi0 = R[RL.meta + M_PHI0];
+    double u = 0.0;
+    int sg = 1;
+    bool conv = false, live = cnt >= 0 && lane < NS;
+    int its = 0;
+    if (live) {
+      const bool seeded = L.seeds_out && lane < S;
+      double bc = 1.0, bs = 0.0, ang;
+      if (seeded) {
+        const float* o = L.seeds_out + w * 2 * S;
+        bc = (double)o[2 * lane];
+        bs = (double)o[2 * lane + 1];
+        ang = -(R[RL.meta + M_CANON] + phi0);
+      } else {
+        ang = (L.seeds_out ? (lane - S + 0.5) * (kTwoPi / (NS - S)) : (lane + 0.5) * (kTwoPi / NS)) - phi0;
+      }
+      double s1, c1;
+      sincos_small(ang, s1, c1);
+      u_from_dir(fma(bc, c1, -bs * s1), fma(bc, s1, bs * c1), u, sg);
+    }
+    bool done = cnt < 0;
+    unsigned long long um = 0ull, merged = 0ull, U = 0ull;
+    for (int it = 1; it <= 12 && !done; ++it) {
+      if (live && !conv) {
+        bool ok;
+        const double sc = newton_u_step(sg > 0 ? sml : sml + FS, D, K, u, sg, ok);
+        if (!ok) {
+          live = false;
+        } else {
+          ++its;
+          if (fabs(sc) < 1e-12) conv = true;
+        }
+      }
+      if (it >= 4) {
+        const unsigned long long cm = __ballot(conv);
+        // fewer converged lanes than the count cannot reach it (the last
+        // check always runs: its roots seed the fallback)
+        if (__popcll(cm) < cnt && it < 12) continue;
+        const double key = sg > 0 ? u : copysign(2.0, u) - u;
+        for (unsigned long long pend = cm & ~merged; pend;) {
+          const int jj = __builtin_ctzll(pend);
+          const double kj = lrdlane(key, jj), uj = lrdlane(u, jj);
+          const double tol = 0.5e-8 * fma(uj, uj, 1.0);
+          const unsigned long long bit = 1ull << jj;
+          const unsigned long long same = __ballot(fabs(key - kj) < tol) & cm;
+          const unsigned long long upto = (bit << 1) - 1ull;
+          U &= upto | ~same;
+          U = (same & (bit - 1ull)) ? (U & ~bit) : (U | bit);
+          pend &= ~(same | bit);
+        }
+        merged = cm;
+        um = U;
+        if (__popcll(um) == cnt) {
+          done = true;
+          live = false;
+        }
+      }
+    }
+    iters_acc += (unsigned long long)wave_sum((double)(lane < NS ? its : 0));
+    const double thw = theta_from_u(phi0, u, sg);
+    const int nu = __popcll(um);
+    const bool uniq = (um >> lane) & 1ull;
+    if (cnt >= 0 && cnt == nu) {
+      double* cand = R + RL.cand;
+      for (int c = lane; c < D; c += 64) cand[c] = __longlong_as_double(0x7ff8000000000000ll);
+      lwave_sync();
+      if (uniq) cand[__popcll(um & below)] = thw;
+      roots_acc += (unsigned long long)nu;
+    } else {
+      // the distinct roots Newton did find start the Aberth iteration
+      if (uniq) R[RL.cand + __popcll(um & below)] = thw;
+      if (lane == 0) {
+        R[RL.meta + M_WARM] = (double)nu;
+        R[RL.meta + M_FALLBACK] = 1.0;
+        const unsigned slot = atomicAdd(L.fb_count, 1u);
+        L.fb_list[slot] = w;
+      }
+      ++fb_acc;
+    }
     lwave_sync();
   }
   if (lane == 0 && a.counters) {
