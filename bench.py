@@ -348,20 +348,29 @@ def main():
         del src, dst
     wanted = set(x for x in args.solvers.split(",") if x) | {"plain", args.solver}
     runs = {}
+    ms_staged = {}
     for name in [n for n in ("plain", "learned", "uniform", "aberth") if n in wanted]:
-        pl = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=solver_ids[name],
+        # the timed plan records no per-stage events (they are instrumentation:
+        # each one is a queue marker with a gap around it); a second plan with
+        # the same launch shapes and FTP_FLAG_TIME_STAGES gives the per-stage
+        # durations and counters, from a timed region of its own
+        pl = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=solver_ids[name])
+        ps = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=solver_ids[name],
                     flags=F.FTP_FLAG_TIME_STAGES)
         if name == "learned":
             pl.load_mlp(w, meta["width"])
+            ps.load_mlp(w, meta["width"])
         o = pl.alloc_outputs(lc.n_f, dev)
         if not args.no_autotune:   # launch shapes for this workload, outside the timed region
             pl.autotune(t, y, s, lc.df, lc.n_f, cache_path=args.tune_cache, force=args.retune)
-        ms, st = run_solver(F, pl, t, y, s, lc, o, args.steps, args.warmup)
+        ps.set_tuning(**pl.tuning())
+        ms, _ = run_solver(F, pl, t, y, s, lc, o, args.steps, args.warmup)
+        ms_staged[name], st = run_solver(F, ps, t, y, s, lc, ps.alloc_outputs(lc.n_f, dev), args.steps, args.warmup)
         runs[name] = (pl, o, ms, st)
     plan, out, ms_step, st = runs[args.solver]
     # positive-amplitude variant (theta_1 > 0, Section 2.2) of the reported solver
     pv = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=solver_ids[args.solver],
-                flags=F.FTP_FLAG_TIME_STAGES | F.FTP_FLAG_POSITIVE_AMP)
+                flags=F.FTP_FLAG_POSITIVE_AMP)
     if args.solver == "learned":
         pv.load_mlp(w, meta["width"])
     if not args.no_autotune:
@@ -438,7 +447,8 @@ def main():
                     "mlp_forward": "k_dense_bf16 (MFMA bf16)"}
     solvers = {}
     for name, (_, o, ms, stn) in runs.items():
-        solvers[name] = {"value": pairs / (ms * 1e-3), "ms_per_step": ms, "launch_shapes": runs[name][0].tuning(),
+        solvers[name] = {"value": pairs / (ms * 1e-3), "ms_per_step": ms, "ms_per_step_stage_events": ms_staged[name],
+                         "launch_shapes": runs[name][0].tuning(),
                          "max_abs_dP_vs_plain": float(torch.max(torch.abs(o["power"] - out_p["power"]))),
                          "unconfirmed_rate": stn["n_fallback"] / pairs, "companion_rate": stn["n_fallback_qr"] / pairs,
                          "ms_roots": stn["ms_roots"], "ms_mlp": stn["ms_mlp"], "ms_verify": stn["ms_verify"],
