@@ -292,12 +292,22 @@ struct LearnArgs {
 // ascending order.  Returns the signed step s (theta moves by sg * s, clamped);
 // ok drops on a zero or non-finite step.
 __device__ __forceinline__ double newton_u_step(const double* cp, int D, int K, double& u, int& sg, bool& ok) {
-  double F = cp[D], dF = 0.0;
-#pragma unroll 4
-  for (int c = D - 1; c >= 0; --c) {
-    dF = fma(dF, u, F);
-    F = fma(F, u, cp[c]);
+  // f = E(v) + u O(v), v = u^2 (D even: E has the even powers up to D, O the
+  // odd ones up to D - 1), f' = 2u E'(v) + O(v) + 2v O'(v): four independent
+  // Horner chains of D/2 steps in place of two of D
+  const double v = u * u;
+  double E = cp[D], dE = 0.0, O = cp[D - 1], dO = 0.0;
+#pragma unroll 2
+  for (int c = D - 2; c >= 2; c -= 2) {
+    dE = fma(dE, v, E);
+    E = fma(E, v, cp[c]);
+    dO = fma(dO, v, O);
+    O = fma(O, v, cp[c - 1]);
   }
+  dE = fma(dE, v, E);
+  E = fma(E, v, cp[0]);
+  const double F = fma(u, O, E);
+  const double dF = fma(2.0 * u, dE, fma(2.0 * v, dO, O));
   const double den = fma(fma(u, u, 1.0), dF, -(2.0 * K) * u * F);
   const double d = 2.0 * F * fast_rcp_d(den);
   ok = den != 0.0 && isfinite(d);
