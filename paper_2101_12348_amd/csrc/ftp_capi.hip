@@ -23,7 +23,7 @@
 
 namespace ftp {
 // kernels (defined in the other translation units)
-__global__ void k_prep_stats(LcInfo*, const double*, const double*, const double*);
+__global__ void k_prep_stats(LcInfo*, const double*, const double*, const double*, double*, unsigned*);
 __global__ void k_sp_combine(LcInfo*, int, const double2*, int);
 template <typename R>
 __global__ void k_prep_points(const LcInfo*, int64_t, const int64_t*, int64_t, const double*, const double*,
@@ -359,6 +359,9 @@ struct ftp_plan {
   DevBuf alpha, twiddle32, twiddle64, ctab;
   DevBuf pw, py, tile_count, tile_off, cursor, block_sums,
       total, bucket, grids, fft_tab, fft_items, counters, stats_out, rec;
+  DevBuf stat_part, stat_ticket;   // statistics kernel: partials per workgroup, ticket per lightcurve
+  int64_t stat_slots = 0;          // workgroups of the statistics kernel in this chunk
+  int stat_nby = 1;                // the most workgroups of one lightcurve
   int64_t pair_chunk = (int64_t)1 << 20;  // pairs per assemble/root/score round
   int n_band = 0;                          // > 0: band templates for shared-phase calls
   // host staging (kept alive until the uploads completed)
@@ -492,7 +495,8 @@ int plan_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, co
   P->h_obs_off.assign(n + 1, 0);
   P->h_freq_off.assign(n + 1, 0);
   P->h_gtb.assign(2 * n + 1, 0);
-  int64_t goff = 0, tbase = 0;
+  int64_t goff = 0, tbase = 0, stat_slots = 0;
+  P->stat_nby = 1;
   for (int64_t b = 0; b < n; ++b) {
     LcInfo& L = P->h_lc[b];
     const int64_t gb = lc0 + b;
@@ -502,6 +506,12 @@ int plan_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, co
     L.n_f = freq_off[gb + 1] - freq_off[gb];
     L.df = df[gb];
     L.msp = msp;
+    // the statistics kernel's workgroups depend on n_obs alone, so a lightcurve
+    // is reduced in the same order alone and inside a batch
+    L.stat_nb = (int)std::min<int64_t>(kStatMaxBlocks, std::max<int64_t>(1, (L.n_obs + 511) / 512));
+    L.stat_off = stat_slots;
+    stat_slots += L.stat_nb;
+    P->stat_nby = std::max(P->stat_nby, L.stat_nb);
     P->h_obs_off[b] = L.obs_off;
     P->h_freq_off[b] = L.freq_off;
     for (int g = 0; g < 2; ++g) {
@@ -525,6 +535,7 @@ int plan_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, co
       tbase += nn / kTileCells;
     }
   }
+  P->stat_slots = stat_slots;
   P->h_obs_off[n] = obs_off[lc1] - obs_off[lc0];
   P->h_freq_off[n] = freq_off[lc1] - freq_off[lc0];
   P->h_gtb[2 * n] = tbase;
@@ -549,7 +560,17 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
   if ((rc = P->bucket.ensure(sizeof(int) * std::max<int64_t>(4 * n_pts, 1)))) return rc;
   if ((rc = P->grids.ensure(sizeof(C) * n_grid))) return rc;
   LcInfo* dl = P->d_lc;
-  hipLaunchKernelGGL(k_prep_stats, dim3((unsigned)n_lc), dim3(1024), 0, st, dl, t, y, sigma);
+  // statistics: stat_nb workgroups per lightcurve, combined by the last of
+  // them; the tickets start at 0 and every call leaves them at 0
+  if ((rc = P->stat_part.ensure(sizeof(double) * kStatVals * P->stat_slots))) return rc;
+  {
+    const size_t cap0 = P->stat_ticket.cap;
+    if ((rc = P->stat_ticket.ensure(sizeof(unsigned) * n_lc))) return rc;
+    if (P->stat_ticket.cap != cap0)
+      HIP_TRY(launch_zero_u32(P->stat_ticket.as<unsigned>(), (int64_t)(P->stat_ticket.cap / sizeof(unsigned)), st));
+  }
+  hipLaunchKernelGGL(k_prep_stats, dim3((unsigned)n_lc, (unsigned)P->stat_nby), dim3(kStatThreads), 0, st, dl, t, y,
+                     sigma, P->stat_part.as<double>(), P->stat_ticket.as<unsigned>());
   if (shared_bands > 0)
     hipLaunchKernelGGL(k_sp_combine, dim3(1), dim3(64), 0, st, dl, shared_bands, P->alpha.as<double2>(), P->H);
   HIP_TRY(launch_zero_u32(P->tile_count.as<unsigned>(), n_tiles, st, P->cursor.as<unsigned>()));
@@ -1122,7 +1143,7 @@ int ftp_plan_destroy(ftp_plan* P) {
   DevBuf* bufs[] = {&P->alpha, &P->twiddle32, &P->twiddle64, &P->ctab, &P->d_stage,
                     &P->pw, &P->py, &P->tile_count, &P->tile_off, &P->cursor,
                     &P->block_sums, &P->total, &P->bucket, &P->grids,
-                    &P->counters, &P->stats_out, &P->rec, &P->xfeat, &P->seeds, &P->fb_list,
+                    &P->counters, &P->stats_out, &P->rec, &P->stat_part, &P->stat_ticket, &P->xfeat, &P->seeds, &P->fb_list,
                     &P->fb2_list, &P->work_ctr, &P->tune_out, &P->mb_out, &P->mb_chi2};
   P->net.release();
   for (DevBuf* b : bufs) b->release();

@@ -29,8 +29,9 @@ struct LcInfo {
   int npass[2];
   int lp[2][kMaxPasses];   // log2 sizes of the FFT passes (largest stride first)
   int msp;                 // kernel half-width in cells
-  int pad0;
+  int stat_nb;             // workgroups of the statistics kernel for this lightcurve
   double yoff;             // fixed offset subtracted from y (shared-phase bands)
+  int64_t stat_off;        // slot of its first workgroup's partials
   // filled on the device
   double tref, ybar, yy, inv_sqrt_yy, winv;
   double tmin, tmax;
@@ -41,6 +42,12 @@ struct LcInfo {
 };
 
 constexpr int kMaxBands = 16;         // bands of a shared-phase plan
+
+// Statistics kernel: threads per workgroup, doubles of partials per workgroup,
+// most workgroups per lightcurve.
+constexpr int kStatThreads = 256;
+constexpr int kStatVals = 11;
+constexpr int kStatMaxBlocks = 64;
 
 // Per-lightcurve status bits (device side).
 enum : int {

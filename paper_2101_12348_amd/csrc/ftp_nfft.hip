@@ -57,116 +57,136 @@ __device__ __forceinline__ int64_t find_segment(const int64_t* off, int64_t n, i
 
 // ------------------------------------------------------------ prep
 
-// One 1024-thread workgroup per lightcurve: weights (Section 1: w ~ sigma^-2,
-// sum w = 1; all sigma = 0 -> uniform), ybar, YY = chi^2_0, t_ref.  Two passes
-// over the observations: the first gathers the extremes, sum sigma^-2 and
-// sum y sigma^-2 (ybar), the second YY around ybar.
-constexpr int kStatThreads = 1024;
+// Per-lightcurve statistics: the weights (Section 1: w ~ sigma^-2 with
+// sum w = 1; all sigma = 0 gives uniform weights, a mix is rejected), ybar,
+// YY = chi^2_0, t_ref and the input checks. Lightcurve blockIdx.x takes
+// stat_nb workgroups (blockIdx.y), a count set by its n_obs alone, so it is
+// reduced in the same order alone and in a batch. Each workgroup makes two
+// passes over its share of the observations: the first for the extremes, the
+// counts and the sums of s and s y (s = sigma^-2; over sigma = 0 the same with
+// unit weights), the second for M2_b = sum s (y - m_b)^2 around its own mean
+// m_b. It writes these partials and takes a ticket. The last workgroup
+// combines them in workgroup order by the pairwise update of Chan, Golub and
+// LeVeque (M2 = sum_b [M2_b + W_b (m_b - m)^2]), so YY = M2 / W carries no
+// one-pass cancellation. It then fills the LcInfo and resets the ticket for the
+// next call.
+
+// Block-wide sums of v[0..NS) and minima of v[NS..NS+NM) in a fixed order
+// (wave shuffles, then the waves in turn); every thread receives the result.
+template <int NS, int NM>
+__device__ __forceinline__ void block_reduce(double* v) {
+  constexpr int N = NS + NM, NW = kStatThreads / 64;
+  for (int o = 32; o > 0; o >>= 1) {
+    for (int q = 0; q < NS; ++q) v[q] += __shfl_xor(v[q], o);
+    for (int q = NS; q < N; ++q) v[q] = fmin(v[q], __shfl_xor(v[q], o));
+  }
+  __shared__ double sh[NW][N];
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < N; ++q) sh[wid][q] = v[q];
+  __syncthreads();
+  for (int q = 0; q < N; ++q) {
+    double r = sh[0][q];
+    for (int k = 1; k < NW; ++k) r = q < NS ? r + sh[k][q] : fmin(r, sh[k][q]);
+    v[q] = r;
+  }
+  __syncthreads();   // the exchange array may be reused
+}
+
 __global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const double* __restrict__ t,
-                                                             const double* __restrict__ y,
-                                                             const double* __restrict__ sigma) {
-  constexpr int NW = kStatThreads / 64;
+                                                            const double* __restrict__ y,
+                                                            const double* __restrict__ sigma, double* part,
+                                                            unsigned* tickets) {
   LcInfo& L = lcs[blockIdx.x];
+  const int nb = L.stat_nb;
+  if ((int)blockIdx.y >= nb) return;
+  unsigned* ticket = tickets + blockIdx.x;
   const int64_t b = L.obs_off, n = L.n_obs;
-  double sinv = 0.0, swy = 0.0, sy0 = 0.0, tmin = INFINITY, tmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
-  int nzero = 0, bad = 0;
+  const int64_t i0 = (int64_t)blockIdx.y * kStatThreads + threadIdx.x, stride = (int64_t)nb * kStatThreads;
+  // W (sigma > 0), sum s y, count (sigma = 0), sum y (sigma = 0), bad; tmin, -tmax, ymin, -ymax
+  double v[9] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY, INFINITY, INFINITY};
 #pragma unroll 1
-  for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
+  for (int64_t i = i0; i < n; i += stride) {
     const double ti = t[b + i], yi = y[b + i] - L.yoff, si = sigma[b + i];
-    if (!isfinite(ti) || !isfinite(yi) || !isfinite(si) || si < 0.0) bad = 1;
+    if (!isfinite(ti) || !isfinite(yi) || !isfinite(si) || si < 0.0) v[4] = 1.0;
     if (si == 0.0) {
-      nzero++;
-      sy0 += yi;
+      v[2] += 1.0;
+      v[3] += yi;
     } else {
       const double iw = 1.0 / (si * si);
-      sinv += iw;
-      swy += iw * yi;
+      v[0] += iw;
+      v[1] += iw * yi;
     }
-    tmin = fmin(tmin, ti);
-    tmax = fmax(tmax, ti);
-    ymin = fmin(ymin, yi);
-    ymax = fmax(ymax, yi);
+    v[5] = fmin(v[5], ti);
+    v[6] = fmin(v[6], -ti);
+    v[7] = fmin(v[7], yi);
+    v[8] = fmin(v[8], -yi);
   }
-  // the nine reductions together: wave-level shuffles, one LDS exchange
-  double v[7] = {sinv, swy, sy0, tmin, -tmax, ymin, -ymax};
-  int iv[2] = {nzero, bad};
-  for (int o = 32; o > 0; o >>= 1) {
-    for (int q = 0; q < 3; ++q) v[q] += __shfl_xor(v[q], o);
-    for (int q = 3; q < 7; ++q) v[q] = fmin(v[q], __shfl_xor(v[q], o));
-    for (int q = 0; q < 2; ++q) iv[q] += __shfl_xor(iv[q], o);
+  block_reduce<5, 4>(v);
+  const double mw = v[0] > 0.0 ? v[1] / v[0] : 0.0, mu = v[2] > 0.0 ? v[3] / v[2] : 0.0;
+  double m2[2] = {0.0, 0.0};
+#pragma unroll 1
+  for (int64_t i = i0; i < n; i += stride) {
+    const double yi = y[b + i] - L.yoff, si = sigma[b + i];
+    if (si == 0.0) {
+      m2[1] += (yi - mu) * (yi - mu);
+    } else {
+      m2[0] += (yi - mw) * (yi - mw) / (si * si);
+    }
   }
-  __shared__ double shv[NW][7];
-  __shared__ int shiv[NW][2];
-  const int wid = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    for (int q = 0; q < 7; ++q) shv[wid][q] = v[q];
-    for (int q = 0; q < 2; ++q) shiv[wid][q] = iv[q];
-  }
-  __syncthreads();
-  // thread q < 9 reduces column q over the waves; everyone reads the results
-  __shared__ double resv[7];
-  __shared__ int resi[2];
-  if (threadIdx.x < 7) {
-    const int q = threadIdx.x;
-    double r = shv[0][q];
-    for (int k = 1; k < NW; ++k) r = q < 3 ? r + shv[k][q] : fmin(r, shv[k][q]);
-    resv[q] = r;
-  } else if (threadIdx.x < 9) {
-    const int q = threadIdx.x - 7;
-    int r = shiv[0][q];
-    for (int k = 1; k < NW; ++k) r += shiv[k][q];
-    resi[q] = r;
+  block_reduce<2, 0>(m2);
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    double* pb = part + (L.stat_off + blockIdx.y) * kStatVals;
+    for (int q = 0; q < 9; ++q) pb[q] = v[q];
+    pb[9] = m2[0];
+    pb[10] = m2[1];
+    __threadfence();
+    last = atomicAdd(ticket, 1u) == (unsigned)nb - 1u;
   }
   __syncthreads();
-  for (int q = 0; q < 7; ++q) v[q] = resv[q];
-  for (int q = 0; q < 2; ++q) iv[q] = resi[q];
-  sinv = v[0];
-  swy = v[1];
-  sy0 = v[2];
-  tmin = v[3];
-  tmax = -v[4];
-  ymin = v[5];
-  ymax = -v[6];
-  nzero = iv[0];
-  bad = iv[1];
-  int status = 0;
-  int wmode = 0;
+  if (!last) return;
+  __threadfence();
+  // the workgroups' partials, workgroup k on thread k (nb <= kStatMaxBlocks <= kStatThreads)
+  double w[9] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY, INFINITY, INFINITY};
+  double bm2[2] = {0.0, 0.0};
+  if ((int)threadIdx.x < nb) {
+    const double* pb = part + (L.stat_off + threadIdx.x) * kStatVals;
+    for (int q = 0; q < 9; ++q) w[q] = pb[q];
+    bm2[0] = pb[9];
+    bm2[1] = pb[10];
+  }
+  double mine[4] = {w[0], w[1], w[2], w[3]};
+  block_reduce<5, 4>(w);
+  const double tmin = w[5], tmax = -w[6], ymin = w[7], ymax = -w[8];
+  const int64_t nzero = (int64_t)w[2];
+  int status = 0, wmode = 0;
   double winv = 0.0, ybar = 0.0;
-  if (bad) status |= LC_BAD_INPUT;
-  if (nzero == n) { wmode = 1; winv = 1.0 / (double)n; ybar = sy0 * winv; }
+  if (w[4] != 0.0) status |= LC_BAD_INPUT;
+  if (nzero == n) { wmode = 1; winv = 1.0 / (double)n; ybar = w[3] * winv; }
   else if (nzero > 0) status |= LC_MIXED_SIGMA;
-  else { winv = 1.0 / sinv; ybar = swy * winv; }
-  double syy = 0.0;
-  if (status == 0) {
-  #pragma unroll 1
-  for (int64_t i = threadIdx.x; i < n; i += kStatThreads) {
-      const double si = sigma[b + i];
-      const double w = (wmode ? 1.0 : 1.0 / (si * si)) * winv;
-      const double d = y[b + i] - L.yoff - ybar;
-      syy += w * d * d;
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) syy += __shfl_xor(syy, o);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) shv[wid][0] = syy;
-  __syncthreads();
-  double yy = shv[0][0];
-  for (int k = 1; k < NW; ++k) yy += shv[k][0];
+  else { winv = 1.0 / w[0]; ybar = w[1] * winv; }
+  // this workgroup's share of M2 about the whole mean
+  const double wb = wmode ? mine[2] : mine[0], sb = wmode ? mine[3] : mine[1];
+  const double db = wb > 0.0 ? sb / wb - ybar : 0.0;
+  double m2t[1] = {status == 0 ? (wmode ? bm2[1] : bm2[0]) + wb * db * db : 0.0};
+  block_reduce<1, 0>(m2t);
+  if (threadIdx.x != 0) return;
+  *ticket = 0u;
+  const double yy = m2t[0] * winv;
   // Var(y) = 0 means every y_i is equal (rounding may leave yy slightly > 0)
   if (status == 0 && (!(yy > 0.0 && isfinite(yy)) || ymin == ymax)) status |= LC_ZERO_VAR;
-  if (threadIdx.x == 0) {
-    L.tref = 0.5 * (tmin + tmax);
-    L.tmin = tmin;
-    L.tmax = tmax;
-    L.wsum = 1.0;
-    L.mm_scale = 0.0;
-    L.ybar = ybar;
-    L.yy = yy;
-    L.inv_sqrt_yy = (status == 0) ? 1.0 / sqrt(yy) : 0.0;
-    L.winv = winv;
-    L.wmode = wmode;
-    L.status = status;
-  }
+  L.tref = 0.5 * (tmin + tmax);
+  L.tmin = tmin;
+  L.tmax = tmax;
+  L.wsum = 1.0;
+  L.mm_scale = 0.0;
+  L.ybar = ybar;
+  L.yy = yy;
+  L.inv_sqrt_yy = (status == 0) ? 1.0 / sqrt(yy) : 0.0;
+  L.winv = winv;
+  L.wmode = wmode;
+  L.status = status;
 }
 
 __device__ __forceinline__ void tile_span(int cell, int msp, int log2n, int& t0, int& t1) {

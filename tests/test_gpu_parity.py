@@ -231,3 +231,30 @@ def test_noiseless_injection_gpu(ftp):
     assert abs(g["amp"][j0 - 1] - A) < 1e-7 and abs(g["offset"][j0 - 1] - B) < 1e-7
     d = (g["phase"][j0 - 1] - phi + np.pi) % (2 * np.pi) - np.pi
     assert abs(d) < 1e-7
+
+
+@pytest.mark.parametrize("n_obs", [2047, 2048, 5000, 300_000])
+def test_long_lightcurve_statistics(ftp, n_obs):
+    # weighted mean and YY of one long lightcurve (Section 2): the many-workgroup
+    # reduction against the oracle, with weights, with uniform weights, with a
+    # mean far above the scatter, and the rejected inputs
+    tmpl, lc = single_long_case(n_obs=min(n_obs, 10_000))
+    rng = np.random.default_rng(n_obs)
+    t = np.sort(rng.uniform(0.0, 1000.0, n_obs)) if n_obs > 10_000 else lc.t
+    y = rng.standard_normal(n_obs) if n_obs > 10_000 else lc.y
+    sig = rng.uniform(0.05, 0.2, n_obs) if n_obs > 10_000 else lc.sigma
+    plan = ftp.Plan(tmpl.c, tmpl.s, precision=ftp.FTP_FP64)
+    js = np.array([1, 7])
+    for yy_in, ss in ((y, sig), (y + 1e6, sig), (y, np.zeros(n_obs))):
+        _, st = plan.nfft_sums(t, yy_in, ss, lc.df, 8)
+        st = _np(st)
+        _, _, ybar, YY = O.raw_sums(t, yy_in, ss, lc.df, js, 2 * tmpl.H, tmpl.H, t_ref=st[0])
+        assert st[3] == 0
+        assert st[0] == 0.5 * (t.min() + t.max())
+        assert abs(st[1] - ybar) <= 1e-12 * max(1.0, abs(ybar)), (st[1], ybar)
+        assert abs(st[2] - YY) <= 1e-9 * YY, (st[2], YY)
+    mixed = sig.copy(); mixed[n_obs // 2] = 0.0
+    nan_y = y.copy(); nan_y[-1] = np.nan
+    for yy_in, ss in ((y, mixed), (nan_y, sig), (np.full(n_obs, 3.0), sig)):
+        _, st = plan.nfft_sums(t, yy_in, ss, lc.df, 8)
+        assert _np(st)[3] != 0
