@@ -842,11 +842,14 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       SolveArgs as = a;
       as.newton_cands = solver == FTP_SOLVER_LEARNED || solver == FTP_SOLVER_UNIFORM;
       if (overlap_score) {
-        // Newton-root pairs (two per wavefront, on the side stream), then the
-        // fallback list
-        HIP_TRY(hipStreamWaitEvent(st, P->join_ev, 0));
+        // the fallback list here, while the Newton-root pairs (M_FALLBACK = 0,
+        // a disjoint set: neither kernel reads what the other writes) may
+        // still be scored on the side stream; the join then orders the side
+        // stream's outputs before whatever follows on this one (the next
+        // chunk's assembly rewrites the records)
         HIP_TRY(launch_score(as, rec, p0, np, std::min(w_sc, (int)grid_waves(P, 2, np)), st,
                              P->fb_list.as<int64_t>(), ctr));
+        HIP_TRY(hipStreamWaitEvent(st, P->join_ev, 0));
       } else {
         HIP_TRY(launch_score(as, rec, p0, np, w_sc, st));
       }
