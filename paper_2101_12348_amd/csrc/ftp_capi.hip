@@ -23,7 +23,8 @@
 
 namespace ftp {
 // kernels (defined in the other translation units)
-__global__ void k_prep_stats(LcInfo*, const double*, const double*, const double*, double*, unsigned*);
+__global__ void k_prep_stats(LcInfo*, const double*, const double*, const double*, double*, unsigned*, unsigned*,
+                             unsigned*, int64_t);
 __global__ void k_sp_combine(LcInfo*, int, const double2*, int);
 template <typename R>
 __global__ void k_prep_points(const LcInfo*, int64_t, const int64_t*, int64_t, const double*, const double*,
@@ -569,11 +570,12 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
     if (P->stat_ticket.cap != cap0)
       HIP_TRY(launch_zero_u32(P->stat_ticket.as<unsigned>(), (int64_t)(P->stat_ticket.cap / sizeof(unsigned)), st));
   }
+  // (it also clears the tile histogram and the binning cursors)
   hipLaunchKernelGGL(k_prep_stats, dim3((unsigned)n_lc, (unsigned)P->stat_nby), dim3(kStatThreads), 0, st, dl, t, y,
-                     sigma, P->stat_part.as<double>(), P->stat_ticket.as<unsigned>());
+                     sigma, P->stat_part.as<double>(), P->stat_ticket.as<unsigned>(), P->tile_count.as<unsigned>(),
+                     P->cursor.as<unsigned>(), n_tiles);
   if (shared_bands > 0)
     hipLaunchKernelGGL(k_sp_combine, dim3(1), dim3(64), 0, st, dl, shared_bands, P->alpha.as<double2>(), P->H);
-  HIP_TRY(launch_zero_u32(P->tile_count.as<unsigned>(), n_tiles, st, P->cursor.as<unsigned>()));
   const unsigned pblocks = (unsigned)((n_pts + 255) / 256);
   hipLaunchKernelGGL(k_prep_points<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc,
                      P->d_obs_off, n_pts, t, y, sigma, P->pw.as<PointRec<R>>(),
@@ -751,8 +753,13 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
     const int w_nt = (int)grid_waves(P, T.newton_wpc, np);
     const int w_ab = (int)grid_waves(P, T.aberth_wpc, np);
     const int w_sc = (int)grid_waves(P, T.score_wpc, np);
-    HIP_TRY(launch_assemble(P->opt.precision, a, rec, p0, np, w_asm, st));
-    HIP_TRY(launch_zero_u32(ctr, 8, st));
+    {
+      // the assembly also clears the chunk's counters (no kernel of the
+      // previous chunk reads them once its scoring has run)
+      SolveArgs aa = a;
+      aa.clear8 = ctr;
+      HIP_TRY(launch_assemble(P->opt.precision, aa, rec, p0, np, w_asm, st));
+    }
     hipEvent_t r0 = next_root_event(P);
     if (r0) HIP_TRY(hipEventRecord(r0, st));
     if (solver == FTP_SOLVER_PLAIN) {

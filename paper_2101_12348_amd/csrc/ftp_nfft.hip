@@ -96,7 +96,15 @@ __device__ __forceinline__ void block_reduce(double* v) {
 __global__ __launch_bounds__(kStatThreads) void k_prep_stats(LcInfo* lcs, const double* __restrict__ t,
                                                             const double* __restrict__ y,
                                                             const double* __restrict__ sigma, double* part,
-                                                            unsigned* tickets) {
+                                                            unsigned* tickets, unsigned* zero_a, unsigned* zero_b,
+                                                            int64_t n_zero) {
+  // zero_a[0..n_zero) and zero_b[0..n_zero) are cleared on the way, by the
+  // whole grid
+  for (int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kStatThreads + threadIdx.x; i < n_zero;
+       i += (int64_t)gridDim.x * gridDim.y * kStatThreads) {
+    zero_a[i] = 0u;
+    zero_b[i] = 0u;
+  }
   LcInfo& L = lcs[blockIdx.x];
   const int nb = L.stat_nb;
   if ((int)blockIdx.y >= nb) return;

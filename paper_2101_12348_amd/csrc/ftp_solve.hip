@@ -390,6 +390,7 @@ template <typename R>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble(SolveArgs a, double* rec, int64_t p0, int64_t np) {
   extern __shared__ double sma[];
   const int lane = wave_lane();
+  if (a.clear8 && blockIdx.x == 0 && lane < 8) a.clear8[lane] = 0u;
   const int H = a.H, K = 3 * H - 1, D = 2 * K;
   const RecLayout RL(H);
   const int nb = a.n_band;
@@ -569,6 +570,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                                                           int64_t p0, int64_t np) {
   extern __shared__ double sma[];
   const int lane = wave_lane(), half = lane >> 5, hl = lane & 31;
+  if (a.clear8 && blockIdx.x == 0 && lane < 8) a.clear8[lane] = 0u;
   const int H = a.H, K = 3 * H - 1, D = 2 * K;
   const RecLayout RL(H);
   const size_t per = asm_lds_bytes(H, 0) / sizeof(double);

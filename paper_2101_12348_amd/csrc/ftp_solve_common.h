@@ -27,6 +27,7 @@ struct SolveArgs {
   double* offset;
   uint8_t* status;
   SolveCounters* counters;   // kCounterSlots copies (counter_slot)
+  unsigned* clear8;          // non-null: the assembly sets these 8 words (a chunk's queue and list counters) to 0
 };
 
 constexpr double kEps = 2.220446049250313e-16;
