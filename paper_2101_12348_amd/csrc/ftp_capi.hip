@@ -388,6 +388,7 @@ struct ftp_plan {
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   bool upload_pending = false;
+  size_t stage_sizes[6] = {0, 0, 0, 0, 0, 0};   // piece sizes of the tables last sent (all 0: none)
   ftp_stats last{};
   // stage timing (FTP_FLAG_TIME_STAGES): one event triple per lightcurve chunk
   // (NFFT start, NFFT end, solve end) and one pair per root-kernel launch
@@ -676,6 +677,7 @@ int upload_tables(ftp_plan* P, int64_t n_lc, hipStream_t st, bool with_fft) {
   const size_t o_lc = 0, o_obs = al(o_lc + s_lc), o_freq = al(o_obs + s_off), o_gtb = al(o_freq + s_off),
                o_fft = al(o_gtb + s_gtb), o_it = al(o_fft + s_fft), total = al(o_it + s_it);
   if (total > P->h_stage_cap) {
+    for (int k = 0; k < 6; ++k) P->stage_sizes[k] = 0;
     if (P->h_stage) HIP_TRY(hipHostFree(P->h_stage));
     P->h_stage = nullptr;
     P->h_stage_cap = 0;
@@ -683,16 +685,26 @@ int upload_tables(ftp_plan* P, int64_t n_lc, hipStream_t st, bool with_fft) {
     P->h_stage_cap = total;
   }
   unsigned char* h = P->h_stage;
-  std::memcpy(h + o_lc, P->h_lc.data(), s_lc);
-  std::memcpy(h + o_obs, P->h_obs_off.data(), s_off);
-  std::memcpy(h + o_freq, P->h_freq_off.data(), s_off);
-  std::memcpy(h + o_gtb, P->h_gtb.data(), s_gtb);
-  if (s_fft) std::memcpy(h + o_fft, P->h_fft.data(), s_fft);
-  if (s_it) std::memcpy(h + o_it, P->h_items.data(), s_it);
-  if ((rc = P->d_stage.ensure(total))) return rc;
-  HIP_TRY(hipMemcpyAsync(P->d_stage.p, h, total, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipEventRecord(P->upload_done, st));
-  P->upload_pending = true;
+  // the staging still holds the tables last sent, and the device copy is
+  // complete (waited for above); the kernels rewrite only the fields the
+  // device fills, which the host leaves 0. Tables equal to those need no copy.
+  const size_t sizes[6] = {s_lc, s_off, s_off, s_gtb, s_fft, s_it};
+  const void* src[6] = {P->h_lc.data(), P->h_obs_off.data(), P->h_freq_off.data(), P->h_gtb.data(),
+                        P->h_fft.data(), P->h_items.data()};
+  const size_t offs[6] = {o_lc, o_obs, o_freq, o_gtb, o_fft, o_it};
+  bool same = P->d_stage.p != nullptr && P->d_stage.cap >= total;
+  for (int k = 0; k < 6 && same; ++k)
+    same = sizes[k] == P->stage_sizes[k] && (sizes[k] == 0 || std::memcmp(h + offs[k], src[k], sizes[k]) == 0);
+  if (!same) {
+    for (int k = 0; k < 6; ++k) P->stage_sizes[k] = 0;
+    for (int k = 0; k < 6; ++k)
+      if (sizes[k]) std::memcpy(h + offs[k], src[k], sizes[k]);
+    if ((rc = P->d_stage.ensure(total))) return rc;
+    HIP_TRY(hipMemcpyAsync(P->d_stage.p, h, total, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(P->upload_done, st));
+    P->upload_pending = true;
+    for (int k = 0; k < 6; ++k) P->stage_sizes[k] = sizes[k];
+  }
   unsigned char* d = P->d_stage.as<unsigned char>();
   P->d_lc = reinterpret_cast<LcInfo*>(d + o_lc);
   P->d_obs_off = reinterpret_cast<int64_t*>(d + o_obs);

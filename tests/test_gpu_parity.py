@@ -258,3 +258,30 @@ def test_long_lightcurve_statistics(ftp, n_obs):
     for yy_in, ss in ((y, mixed), (nan_y, sig), (np.full(n_obs, 3.0), sig)):
         _, st = plan.nfft_sums(t, yy_in, ss, lc.df, 8)
         assert _np(st)[3] != 0
+
+
+def test_plan_reuse_across_inputs(ftp):
+    # one plan serving lightcurves of different sizes, a batch and the
+    # solve-from-sums entry in turn gives, on every call, what a fresh plan
+    # gives (the plan's tables are re-sent only when they change)
+    import torch
+    tmpl, a = single_long_case(n_obs=2500)
+    _, b = single_long_case(n_obs=400)
+    n_f = 3000
+    fresh = {}
+    for name, lc in (("a", a), ("b", b)):
+        p = ftp.Plan(tmpl.c, tmpl.s)
+        fresh[name] = {k: v.clone() for k, v in p.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
+    plan = ftp.Plan(tmpl.c, tmpl.s)
+    sums, st = plan.nfft_sums(a.t, a.y, a.sigma, a.df, n_f)
+    stats = [float(x) for x in st.cpu()[:3]]
+    ref_ss = {k: v.clone() for k, v in plan.solve_sums(sums, *stats, a.df).items()}
+    for name, lc in (("a", a), ("a", a), ("b", b), ("a", a), ("b", b), ("b", b)):
+        out = plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
+        for k in ("power", "phase", "amp", "offset", "status"):
+            assert torch.equal(out[k], fresh[name][k]), (name, k)
+        s2, st2 = plan.nfft_sums(a.t, a.y, a.sigma, a.df, n_f)
+        assert torch.equal(s2, sums) and torch.equal(st2, st)
+        ss = plan.solve_sums(sums, *stats, a.df)
+        for k in ("power", "phase", "amp", "offset", "status"):
+            assert torch.equal(ss[k], ref_ss[k]), ("sums", k)
