@@ -49,7 +49,8 @@ hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64
                            hipStream_t st);
 hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves,
                         hipStream_t st, const int64_t* list = nullptr, const unsigned* list_n = nullptr);
-hipError_t launch_score2(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves, hipStream_t st);
+hipError_t launch_score2(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves, hipStream_t st,
+                         hipEvent_t done = nullptr);
 hipError_t launch_gather_sums(int precision, const SolveArgs& a, double* out, int blocks, hipStream_t st);
 hipError_t launch_export_stats(const LcInfo* lcs, double* out, hipStream_t st);
 struct GemmArgs {
@@ -83,7 +84,8 @@ struct LearnArgs {
   unsigned flags;
   unsigned* queue;
 };
-hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st);
+hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st,
+                               hipEvent_t done = nullptr);
 struct AberthArgs {
   double* rec;
   int64_t np;
@@ -816,16 +818,16 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
         L.fb_count = ctr;
         L.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
         L.queue = nullptr;   // uniform work per pair: grid striding (a queue costs more than it balances)
-        HIP_TRY(launch_newton_sturm(a, L, w_nt, st));
+        // with the side stream, the Newton launch and the side scoring launch
+        // record the fork and join events themselves
+        HIP_TRY(launch_newton_sturm(a, L, w_nt, st, overlap_score ? P->fork_ev : nullptr));
         if (overlap_score) {
           // the Newton-root pairs are final now: score them on the side
           // stream while the fallback tiers run on this one
           SolveArgs as = a;
           as.newton_cands = true;
-          HIP_TRY(hipEventRecord(P->fork_ev, st));
           HIP_TRY(hipStreamWaitEvent(P->side, P->fork_ev, 0));
-          HIP_TRY(launch_score2(as, rec, p0, np, w_sc, P->side));
-          HIP_TRY(hipEventRecord(P->join_ev, P->side));
+          HIP_TRY(launch_score2(as, rec, p0, np, w_sc, P->side, P->join_ev));
         }
       }
       hipEvent_t rb = next_learn_event(P);
@@ -1117,8 +1119,7 @@ int plan_create_impl(ftp_plan** out, int n_band, int H, const double* c, const d
       hipMemset(P->counters.p, 0, sizeof(SolveCounters) * kCounterSlots) != hipSuccess ||
       hipEventCreateWithFlags(&P->upload_done, hipEventDisableTiming) != hipSuccess ||
       hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreate(&P->fork_ev) != hipSuccess || hipEventCreate(&P->join_ev) != hipSuccess) {
     g_last_error = "plan setup copy failed";
     delete P;
     return FTP_E_HIP;

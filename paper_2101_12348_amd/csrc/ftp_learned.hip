@@ -21,6 +21,7 @@
 // each, at most D); for H = 11 one (k_newton_sturm, 4H starts).  The Sturm
 // sequence is formed in registers, one coefficient per lane (for D = 64 the
 // top coefficient is carried as a scalar; see sturm_begin).
+#include <hip/hip_ext.h>
 #include "ftp_solve_common.h"
 
 namespace ftp {
@@ -658,12 +659,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 bool newton_two_per_wave(int H) { return 6 * H - 2 < 64; }
 
-hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st) {
+// `done` (nullable): an event the launch itself records at the kernel's end
+// (no marker packet of its own on the stream).
+hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st, hipEvent_t done) {
   if (newton_two_per_wave(a.H)) {
     const size_t lds = (size_t)4 * (6 * a.H) * sizeof(double);   // 4 x (D + 2)
-    hipLaunchKernelGGL(k_newton_sturm2, dim3((unsigned)waves), dim3(64), lds, st, a, L);
+    hipExtLaunchKernelGGL(k_newton_sturm2, dim3((unsigned)waves), dim3(64), lds, st, nullptr, done, 0, a, L);
   } else {
-    hipLaunchKernelGGL(k_newton_sturm, dim3((unsigned)waves), dim3(64), learn_lds_bytes(a.H), st, a, L);
+    hipExtLaunchKernelGGL(k_newton_sturm, dim3((unsigned)waves), dim3(64), learn_lds_bytes(a.H), st, nullptr, done, 0,
+                          a, L);
   }
   return hipGetLastError();
 }

@@ -19,6 +19,7 @@
 //   k_score    : P = YM^2 / (YY MM) at every candidate, best by P with the
 //                documented tie rule, Newton polish on R(theta) kept only if P
 //                does not drop, outputs theta_2, theta_1, theta_3.
+#include <hip/hip_ext.h>
 #include "ftp_solve_common.h"
 
 namespace ftp {
@@ -1092,10 +1093,13 @@ hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64
   return hipGetLastError();
 }
 
-// Newton-candidate pairs two per wavefront (see k_score2).
-hipError_t launch_score2(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves, hipStream_t st) {
+// Newton-candidate pairs two per wavefront (see k_score2); `done` (nullable):
+// an event the launch itself records at the kernel's end.
+hipError_t launch_score2(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves, hipStream_t st,
+                         hipEvent_t done) {
   const int w2 = (int)std::max<int64_t>(1, std::min<int64_t>(waves, (np + 1) / 2));
-  hipLaunchKernelGGL(k_score2, dim3((unsigned)w2), dim3(64), 2 * score_lds_bytes(a.H), st, a, rec, p0, np);
+  hipExtLaunchKernelGGL(k_score2, dim3((unsigned)w2), dim3(64), 2 * score_lds_bytes(a.H), st, nullptr, done, 0, a, rec,
+                        p0, np);
   return hipGetLastError();
 }
 
