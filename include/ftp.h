@@ -85,7 +85,7 @@ extern "C" {
                                        the companion solve */
 #define FTP_FLAG_TIME_STAGES 2u     /* record HIP events around the NFFT and per-frequency stages
                                        (read back by ftp_last_stats) */
-#define FTP_FLAG_POSITIVE_AMP 8u    /* fit constrained to theta_1 > 0 (Section 2.2): the best
+#define FTP_FLAG_POSITIVE_AMP 8u    /* fit constrained to theta_1 > 0 (Section 2.1): the best
                                        candidate with YM > 0 (P = YM^2/(YY MM) vanishes on YM = 0,
                                        so the constrained maximum is one of the same stationary
                                        points); none: P = 0, theta_1 = 0, theta_3 = ybar,
@@ -194,7 +194,7 @@ int ftp_periodogram_batch(ftp_plan* plan, int64_t n_lc, const int64_t* obs_off, 
                           void* stream);
 
 /*
- * Multi-phase multi-band periodogram (Section 2.3, Eq. multibandmultiphase):
+ * Multi-phase multi-band periodogram (Section 2.2, Eq. multibandmultiphase):
  * n_band bands of one object, each with its own phase, amplitude and offset,
  * the plan's template for all of them, on the common grid f_j = j df,
  * j = 1..n_f:  power[j] = sum_k chi2_0,k P_k[j] / sum_k chi2_0,k with
@@ -261,6 +261,29 @@ int ftp_nfft_sums(ftp_plan* plan, const double* t, const double* y, const double
 int ftp_solve_sums(ftp_plan* plan, const double* sums, const double* lc_stats, double df, int64_t n_f,
                    double* power, double* phase, double* amp, double* offset, uint8_t* status,
                    void* stream);
+
+/*
+ * Root counts of the per-frequency phase polynomials (a check of the count
+ * the learned and uniform solvers rely on), from given sums in the layout
+ * ftp_nfft_sums writes (device `sums`; t_ref, ybar, YY on the host in
+ * `lc_stats`, 3 doubles).  Per frequency j = 1..n_f (device int32 arrays of
+ * n_f values):
+ *   sturm_count[j-1]    : distinct real roots of R(theta) (the real-phase
+ *                         solutions of Eq. theta2cond, Section 2) from the
+ *                         Sturm sequence of the solvers' Cayley polynomial, as
+ *                         the learned / uniform solvers compute it; -1 when the
+ *                         sequence fails its conditioning test (the solvers then
+ *                         fall back), -2 for a frequency the solvers skip (P
+ *                         constant in theta_2);
+ *   companion_real[j-1] : real eigenvalues of that polynomial's companion
+ *                         matrix by the plain solver's QR (the unit-circle roots
+ *                         psi of Eq. finalpoly); -1 if the QR did not converge,
+ *                         -2 as above.
+ * Errors: FTP_E_NULL, FTP_E_DF, FTP_E_NF, FTP_E_OPTION (bands plan, invalid
+ * lc_stats), FTP_E_HIP.
+ */
+int ftp_root_counts(ftp_plan* plan, const double* sums, const double* lc_stats, double df, int64_t n_f,
+                    int32_t* sturm_count, int32_t* companion_real, void* stream);
 
 /*
  * Load the root-proposal network (learned solver): `weights` is a host FP32

@@ -23,7 +23,7 @@ notation:
 Readings where the paper is silent or inexact:
 * the psi^{6H-1} coefficient of p cancels identically (the leading terms of
   2 MM' dYM' and YM' dMM' are both 4H a b), so the degree is 6H-2, not the
-  6H-1 stated in Section 2.4; coefficients at or below 64 eps max|p| are
+  6H-1 stated in Section 2.3; coefficients at or below 64 eps max|p| are
   trimmed from both ends and zero roots are discarded;
 * every projected root is scored, not only those already on the unit
   circle (Section 2 scores all solutions of the phase condition);
@@ -257,7 +257,7 @@ def periodogram(t, y, sigma, c, s, df, n_f=None, freq_index=None, block=256,
     (theta_3), flag (1 = degenerate MM) and, if asked, per-frequency p and
     candidate lists.
 
-    positive_amplitude: the fit constrained to theta_1 > 0 (Section 2.2 names
+    positive_amplitude: the fit constrained to theta_1 > 0 (Section 2.1 names
     it as a remedy for negative-amplitude solutions).  theta_1 = YM/MM with
     MM > 0, so the constraint is YM > 0; P = YM^2/(YY MM) vanishes where YM = 0,
     so the constrained maximum is attained at a stationary point inside
@@ -332,11 +332,11 @@ def periodogram(t, y, sigma, c, s, df, n_f=None, freq_index=None, block=256,
     return out
 
 
-# ---------------------------------------------------- Section 2.3 multi-band
+# ---------------------------------------------------- Section 2.2 multi-band
 
 def chi2_0(y, sigma):
     """The weighted sum of squared residuals of one band about its weighted
-    mean, sum (y - ybar)^2 / sigma^2 (Section 2.3); unit weights when every
+    mean, sum (y - ybar)^2 / sigma^2 (Section 2.2); unit weights when every
     sigma is 0 (Section 2)."""
     y = np.asarray(y, dtype=np.float64)
     sigma = np.asarray(sigma, dtype=np.float64)
@@ -346,7 +346,7 @@ def chi2_0(y, sigma):
 
 
 def multiband_periodogram(bands, c, s, df, n_f=None, freq_index=None, positive_amplitude=False):
-    """Multi-phase multi-band periodogram (Section 2.3, Eq.
+    """Multi-phase multi-band periodogram (Section 2.2, Eq.
     multibandmultiphase): P = sum_k chi2_0,k P_k / sum_k chi2_0,k over bands
     k = 1..K, each band (t, y, sigma) with its own periodogram P_k (its own
     phase, amplitude and offset) on the common grid f_j = j df.  Returns

@@ -35,7 +35,7 @@ EXPORTED = [
     "ftp_mlp_loss_grad", "ftp_mlp_train_step", "ftp_learned_dataset",
     "ftp_plan_get_tuning", "ftp_plan_set_tuning", "ftp_autotune", "ftp_plan_tune_key",
     "ftp_tune_cache_lookup", "ftp_tune_cache_store", "ftp_periodogram_multiband",
-    "ftp_plan_create_bands", "ftp_periodogram_shared_phase",
+    "ftp_plan_create_bands", "ftp_periodogram_shared_phase", "ftp_root_counts",
 ]
 
 FTP_TUNE_FORCE = 1
@@ -90,6 +90,7 @@ def load_library(path: Optional[str] = None):
     lib.ftp_periodogram_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.ftp_nfft_sums.argtypes = [vp, vp, vp, vp, i64, dbl, i64, vp, vp, vp]
     lib.ftp_solve_sums.argtypes = [vp, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp]
+    lib.ftp_root_counts.argtypes = [vp, vp, vp, dbl, i64, vp, vp, vp]
     lib.ftp_plan_load_mlp.argtypes = [vp, vp, i64, ip]
     lib.ftp_last_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
     lib.ftp_mlp_create.argtypes = [ctypes.POINTER(vp), ip, ip, ip, vp, ctypes.c_uint64]
@@ -263,6 +264,25 @@ class Plan:
                                        _ptr(out["amp"]), _ptr(out["offset"]), _ptr(out["status"]),
                                        _stream_ptr(stream)))
         return out
+
+    def root_counts(self, sums, tref: float, ybar: float, yy: float, df: float, device="cuda", stream=None):
+        """(Sturm count, real companion eigenvalues) per frequency, int32
+        tensors, from sums in the layout of nfft_sums (see ftp_root_counts)."""
+        import numpy as np
+        torch = _torch()
+        sums = torch.as_tensor(sums, device=device)
+        if sums.is_complex():
+            sums = torch.view_as_real(sums.to(torch.complex128).contiguous())
+        sums = sums.to(torch.float64).contiguous()
+        n_f = sums.shape[0]
+        if sums.shape[1] != 3 * self.H:
+            raise ValueError("sums must have 3H columns")
+        stats = np.array([tref, ybar, yy], dtype=np.float64)
+        sc = torch.empty(n_f, dtype=torch.int32, device=sums.device)
+        cr = torch.empty(n_f, dtype=torch.int32, device=sums.device)
+        _check(self.lib.ftp_root_counts(self.handle, _ptr(sums), stats.ctypes.data_as(ctypes.c_void_p), float(df),
+                                        int(n_f), _ptr(sc), _ptr(cr), _stream_ptr(stream)))
+        return sc, cr
 
     def load_mlp(self, weights, width: int):
         import numpy as np

@@ -16,7 +16,7 @@
 // Candidates: each root x maps back to the phase
 //   theta = phi0 + atan2(Re x, 1 - Im x) + atan2(Re x, 1 + Im x),
 // the argument of psi = e^{i phi0} (1 + i x) / (1 - i x), i.e. the projection
-// of psi onto the unit circle (Section 2.2); a conjugate pair gives the same
+// of psi onto the unit circle (Section 2, after Eq. finalpoly); a conjugate pair gives the same
 // phase twice.
 #include "ftp_solve_common.h"
 

@@ -84,6 +84,8 @@ struct LearnArgs {
   unsigned flags;
   unsigned* queue;
 };
+hipError_t launch_root_counts(const double* rec, int H, int64_t np, int* sturm, int* real, int waves,
+                              hipStream_t st);
 hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st,
                                hipEvent_t done = nullptr);
 struct AberthArgs {
@@ -1342,6 +1344,50 @@ int ftp_solve_sums(ftp_plan* P, const double* sums, const double* lc_stats, doub
   a.status = status;
   if ((rc = run_solve(P, a, n_f, st))) return rc;
   P->last.n_pairs += (uint64_t)n_f;
+  return FTP_OK;
+}
+
+int ftp_root_counts(ftp_plan* P, const double* sums, const double* lc_stats, double df, int64_t n_f,
+                    int32_t* sturm_count, int32_t* companion_real, void* stream) {
+  if (!P || !sums || !lc_stats || !sturm_count || !companion_real) return FTP_E_NULL;
+  if (!(std::isfinite(df) && df > 0.0)) return FTP_E_DF;
+  if (n_f < 1) return FTP_E_NF;
+  if (!(lc_stats[2] > 0.0) || !std::isfinite(lc_stats[0]) || !std::isfinite(lc_stats[1])) return FTP_E_OPTION;
+  if (P->n_band) return FTP_E_OPTION;
+  int rc;
+  if ((rc = wait_uploads(P))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  P->h_lc.assign(1, LcInfo{});
+  LcInfo& L = P->h_lc[0];
+  L.n_f = n_f;
+  L.df = df;
+  L.tref = lc_stats[0];
+  L.ybar = lc_stats[1];
+  L.yy = lc_stats[2];
+  L.inv_sqrt_yy = 1.0 / std::sqrt(lc_stats[2]);
+  P->h_obs_off.assign(2, 0);
+  P->h_freq_off = {0, n_f};
+  P->h_gtb.assign(3, 0);
+  if ((rc = upload_tables(P, 1, st, false))) return rc;
+  SolveArgs a = base_args(P, 1, n_f);
+  a.sums_in = sums;
+  a.mm_tau = 1e-14;
+  const RecLayout RL(P->H);
+  const int64_t chunk = std::min<int64_t>(n_f, P->pair_chunk);
+  if ((rc = P->rec.ensure(sizeof(double) * (size_t)chunk * RL.stride))) return rc;
+  if ((rc = P->work_ctr.ensure(8 * sizeof(unsigned)))) return rc;
+  double* rec = P->rec.as<double>();
+  unsigned* ctr = P->work_ctr.as<unsigned>();
+  for (int64_t p0 = 0; p0 < n_f; p0 += chunk) {
+    const int64_t np = std::min<int64_t>(chunk, n_f - p0);
+    SolveArgs aa = a;
+    aa.clear8 = ctr;
+    HIP_TRY(launch_assemble(P->opt.precision, aa, rec, p0, np, (int)grid_waves(P, P->tune.assemble_wpc, np), st));
+    HIP_TRY(launch_qr(P->H, rec, RL.stride, np, nullptr, nullptr, P->counters.as<SolveCounters>(), ctr + 4,
+                      (int)grid_waves(P, P->tune.qr_wpc, np), st));
+    HIP_TRY(launch_root_counts(rec, P->H, np, sturm_count + p0, companion_real + p0,
+                               (int)grid_waves(P, P->tune.newton_wpc, np), st));
+  }
   return FTP_OK;
 }
 

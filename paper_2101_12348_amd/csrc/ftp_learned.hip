@@ -657,6 +657,50 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
+// Root counts of a record chunk (diagnostic of the count the learned and
+// uniform solvers trust): per pair, the Sturm count of the Cayley polynomial
+// f by the device code k_newton_sturm2 / k_newton_sturm use (-1 when the
+// chain fails its test, -2 for an inactive pair), and the number of real
+// eigenvalues the companion QR (run before this kernel) marked in M_REAL_LO /
+// M_REAL_HI (-1 when the QR did not converge).  Two pairs per wavefront for
+// H <= 10 (the packed chains of k_newton_sturm2), one for H = 11.
+__global__ __launch_bounds__(64) void k_root_counts(const double* rec, int H, int64_t np, int* sturm, int* real) {
+  const int lane = threadIdx.x & 63;
+  const int D = 6 * H - 2;
+  const RecLayout RL(H);
+  const bool two = D < 64;
+  const int64_t per = two ? 2 : 1;
+  for (int64_t w0 = per * (int64_t)blockIdx.x; w0 < np; w0 += per * (int64_t)gridDim.x) {
+    int cnt[2] = {-2, -2};
+    const double* RA = rec + w0 * (int64_t)RL.stride;
+    const bool hasB = two && w0 + 1 < np;
+    const double* RB = hasB ? RA + RL.stride : RA;
+    if (two) {
+      const double fA = lane <= D ? RA[RL.f + lane] : 0.0;
+      const double fB = lane <= D ? RB[RL.f + lane] : 0.0;
+      sturm_count_line_reg2(fA, fB, D, lane, cnt[0], cnt[1]);
+    } else {
+      const double gv = lane <= D ? RA[RL.f + lane] : 0.0;
+      cnt[0] = sturm_count_line_reg(gv, RA[RL.f + D], D, lane);
+    }
+    if (lane < per && w0 + lane < np) {
+      const double* Rq = lane ? RB : RA;
+      const int st = (int)Rq[RL.meta + M_STATUS];
+      const bool act = st != ST_BAD_LC && st != ST_CONSTANT;
+      const unsigned lo = (unsigned)Rq[RL.meta + M_REAL_LO], hi = (unsigned)Rq[RL.meta + M_REAL_HI];
+      const int nreal = __popcll(((unsigned long long)hi << 32) | lo);
+      sturm[w0 + lane] = act ? (lane ? cnt[1] : cnt[0]) : -2;
+      real[w0 + lane] = act ? (st == ST_NO_CONVERGE ? -1 : nreal) : -2;
+    }
+  }
+}
+
+hipError_t launch_root_counts(const double* rec, int H, int64_t np, int* sturm, int* real, int waves,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_root_counts, dim3((unsigned)waves), dim3(64), 0, st, rec, H, np, sturm, real);
+  return hipGetLastError();
+}
+
 bool newton_two_per_wave(int H) { return 6 * H - 2 < 64; }
 
 // `done` (nullable): an event the launch itself records at the kernel's end

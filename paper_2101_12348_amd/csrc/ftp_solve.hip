@@ -995,7 +995,7 @@ __global__ __launch_bounds__(64) void k_gather_sums(SolveArgs a, double* out) {
   }
 }
 
-// chi^2_0 of each lightcurve of a chunk (Section 2.3): sum (y - ybar)^2 /
+// chi^2_0 of each lightcurve of a chunk (Section 2.2): sum (y - ybar)^2 /
 // sigma^2 = YY / w_inv with YY = sum w (y - ybar)^2, sum w = 1 (unit weights:
 // w_inv = 1/N); 0 for a rejected lightcurve.
 __global__ __launch_bounds__(256) void k_lc_chi2(const LcInfo* lcs, int64_t n_lc, double* out) {
@@ -1003,7 +1003,7 @@ __global__ __launch_bounds__(256) void k_lc_chi2(const LcInfo* lcs, int64_t n_lc
   if (i < n_lc) out[i] = lcs[i].status == 0 ? lcs[i].yy / lcs[i].winv : 0.0;
 }
 
-// Multi-phase multi-band combination (Section 2.3, Eq.
+// Multi-phase multi-band combination (Section 2.2, Eq.
 // multibandmultiphase): power[j] = sum_k chi2[k] P_k[j] / sum_k chi2[k] over
 // the band periodograms P_k = bp[k n_f + j]; 0 when every band was rejected.
 __global__ __launch_bounds__(256) void k_mb_combine(const double* bp, int64_t n_band, int64_t n_f,

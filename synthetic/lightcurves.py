@@ -27,6 +27,7 @@ __all__ = [
     "eval_template", "cadence_uniform", "cadence_nightly",
     "frequency_grid", "small_fp64_case", "single_long_case", "ragged_batch_case",
     "learned_train_lightcurves", "learned_heldout_lightcurves", "large_case", "single_long_template",
+    "large_template", "large_train_lightcurves", "large_heldout_lightcurves",
     "learned_template", "h_sweep_case", "multiband_case", "shared_phase_case",
     "tiny_case", "WORKLOADS",
 ]
@@ -269,15 +270,38 @@ def learned_heldout_lightcurves(n_lc: int = 1024, seed: int = SEED0 + 3, n_obs: 
     return tmpl, [_learned_lc(seed + 2000, i, tmpl, n_obs, baseline) for i in range(n_lc)]
 
 
+def large_template() -> Template:
+    """The H=10 eclipsing-binary-like template of the large workload."""
+    return template_eclipsing_binary(10)
+
+
+def _large_lc(rng, tmpl: Template, n_obs: int):
+    t = cadence_nightly(rng, n_obs, 3000.0, season_len=243.0)
+    period = float(np.exp(rng.uniform(np.log(0.2), np.log(50.0))))
+    return _signal_lc(rng, tmpl, t, 0.5, period, 20.0)
+
+
 def large_case(seed: int = SEED0 + 4, n_obs: int = 100_000):
     """N=1e5 over 3000 d: nightly windows within an 8-month season per year;
     H=10 eclipsing-binary-like template; amplitude 0.5; sigma ~ U(0.05, 0.2);
     oversample 5, f_max = 20/day (~3e5 frequencies)."""
     rng = np.random.default_rng(seed)
-    tmpl = template_eclipsing_binary(10)
-    t = cadence_nightly(rng, n_obs, 3000.0, season_len=243.0)
-    period = float(np.exp(rng.uniform(np.log(0.2), np.log(50.0))))
-    return tmpl, _signal_lc(rng, tmpl, t, 0.5, period, 20.0)
+    tmpl = large_template()
+    return tmpl, _large_lc(rng, tmpl, n_obs)
+
+
+def large_train_lightcurves(n_lc: int = 34, seed: int = SEED0 + 4, n_obs: int = 100_000):
+    """Lightcurves drawn like the large case (own seed stream, disjoint from
+    it and from the held-out set): the polynomials the H=10 root-proposal
+    network is trained on (34 x ~3e5 frequencies ~ 1e7 samples)."""
+    tmpl = large_template()
+    return tmpl, [_large_lc(_lc_rng(seed + 1000, i), tmpl, n_obs) for i in range(n_lc)]
+
+
+def large_heldout_lightcurves(n_lc: int = 8, seed: int = SEED0 + 4, n_obs: int = 100_000):
+    """Held-out lightcurves drawn like the large case (disjoint seed stream)."""
+    tmpl = large_template()
+    return tmpl, [_large_lc(_lc_rng(seed + 2000, i), tmpl, n_obs) for i in range(n_lc)]
 
 
 def multiband_case(seed: int = SEED0 + 6, n_band: int = 5, n_obs: int = 2000, baseline: float = 1000.0,

@@ -82,6 +82,35 @@ def test_mlp_forward_and_gradients_match_reference(ftp, B, din, width, dout):
             o += n
 
 
+def test_adam_steps_match_reference(ftp):
+    """Two Adam steps of the GPU training kernel against the oracle's
+    adam_step (bias corrections at t = 1 and t = 2), each from the gradient
+    the GPU computes at the current weights (the update arithmetic alone is
+    compared; FP32 on the GPU, FP64 in the reference)."""
+    import torch
+    rng = np.random.default_rng(11)
+    din, width, dout, B, R = 22, 32, 8, 64, 6
+    net = ftp.Mlp(din, width, dout, seed=3)
+    Xb = torch.as_tensor(rng.standard_normal((B, din)).astype(np.float32), device="cuda").to(torch.bfloat16)
+    roots = torch.as_tensor(rng.uniform(0, 2 * np.pi, (B, R)).astype(np.float32), device="cuda")
+    nroots = torch.as_tensor(rng.integers(1, R + 1, B).astype(np.int32), device="cuda")
+    w = net.weights().astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    lrs = (3e-3, 1e-3)
+    for t, lr in enumerate(lrs, start=1):
+        _, g = net.loss_grad(Xb, roots, nroots, lam=0.5)
+        g = g.cpu().numpy().astype(np.float64)
+        assert np.count_nonzero(g) > 0.5 * g.size
+        net.train_step(Xb, roots, nroots, lr=lr, lam=0.5)
+        torch.cuda.synchronize()
+        w, m, v = MO.adam_step(w, g, m, v, t, lr=lr)
+        got = net.weights().astype(np.float64)
+        err = np.abs(got - w)
+        assert np.max(err - 4e-6 * np.abs(w)) <= 1e-3 * lr, (t, float(np.max(err)))
+        w = got   # continue from the GPU's weights (FP32 rounding of the masters)
+
+
 def test_training_reduces_loss(ftp):
     import torch
     tmpl, lc = single_long_case(n_obs=1500)

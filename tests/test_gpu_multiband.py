@@ -1,4 +1,4 @@
-"""Multi-phase multi-band periodogram (Section 2.3) through
+"""Multi-phase multi-band periodogram (Section 2.2) through
 ftp_periodogram_multiband, against the oracle's combination
 sum_k chi2_0,k P_k / sum_k chi2_0,k.
 

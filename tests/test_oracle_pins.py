@@ -72,7 +72,7 @@ def test_negative_amplitude_and_tie_rule():
     y = -2.0 * eval_template(tm, 2 * np.pi * 20 * df * t - 0.5) + 0.01 * rng.standard_normal(50)
     r = O.periodogram(t, y, np.ones(50), tm.c, tm.s, df, freq_index=[20])
     assert r["amp"][0] > 0
-    # a template with no such symmetry keeps the negative amplitude (Section 2.2 default)
+    # a template with no such symmetry keeps the negative amplitude (Section 2.1 default)
     tm2 = Template(np.array([1.0, 0.6, 0.3]), np.array([0.0, 0.5, -0.4]))
     y2 = -1.5 * eval_template(tm2, 2 * np.pi * 20 * df * t - 0.5)
     r2 = O.periodogram(t, y2, np.ones(50), tm2.c, tm2.s, df, freq_index=[20])
@@ -291,7 +291,7 @@ def _constrained_grid_max(lc, tmpl, f, th):
 
 @pytest.mark.parametrize("seed,H", [(4, 2), (5, 3), (6, 5)])
 def test_positive_amplitude_brute_force(seed, H):
-    """The theta_1 > 0 variant (Section 2.2's constrained remedy) against a
+    """The theta_1 > 0 variant (Section 2.1's constrained remedy) against a
     dense theta_2 grid restricted to positive amplitudes; it never exceeds
     the unconstrained power and reports a positive amplitude."""
     tmpl, lc = tiny_case(seed, n_obs=45, H=H, n_f=25)
@@ -333,7 +333,7 @@ def _band(seed, n, tmpl, f0, amp, phase):
 
 
 def test_multiband_against_per_band_least_squares():
-    """Multi-phase multi-band power (Section 2.3) against its definition:
+    """Multi-phase multi-band power (Section 2.2) against its definition:
     every band fitted on its own (amplitude, phase, offset) by brute force
     over theta_2, P = 1 - sum_k chi2_k / sum_k chi2_0,k with chi2 summed over
     the residuals directly."""
@@ -458,3 +458,52 @@ def test_shared_phase_special_cases():
     shifted = [(b[0], b[1] + lam[k], b[2]) for k, b in enumerate(bands)]
     r3 = O.shared_phase_periodogram(shifted, [(tm.c, tm.s)] * 2, df, n_f=20, offsets=lam)
     assert np.max(np.abs(r3["power"] - r2["power"])) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_unit_circle_root_count_on_constructed_roots(seed):
+    """Roots placed by hand: m on the unit circle, the rest in pairs psi,
+    1/conj(psi) off it (the root structure of an anti-self-inversive p,
+    Section 2 after Eq. finalpoly).  The count must be m and the distance of
+    the nearest off-circle root must be the one placed."""
+    rng = np.random.default_rng(300 + seed)
+    m = 2 * int(rng.integers(1, 6))
+    on = np.exp(1j * np.sort(rng.uniform(0, 2 * np.pi, m)))
+    radii = rng.uniform(1.05, 3.0, 4)
+    phis = rng.uniform(0, 2 * np.pi, 4)
+    off = np.concatenate([radii * np.exp(1j * phis), np.exp(1j * phis) / radii])
+    p = np.polynomial.polynomial.polyfromroots(np.concatenate([on, off]))
+    cnt, dmin, _ = O.unit_circle_root_count(p, tol=1e-6)
+    assert cnt == m
+    expect = np.min(np.minimum(radii - 1.0, 1.0 - 1.0 / radii))
+    assert abs(dmin - expect) < 1e-8
+
+
+@pytest.mark.parametrize("seed,H", [(0, 2), (1, 3), (2, 4)])
+def test_unit_circle_root_count_equals_sign_changes_of_R(seed, H):
+    """On the method's own polynomials the unit-circle roots are the real
+    zeros of R(theta) = i e^{-i D theta / 2} p(e^{i theta}) (Eq. theta2cond):
+    their number equals the sign changes of the observation-level
+    R(theta) = 2 MM dYM/dtheta - YM dMM/dtheta on a dense theta grid."""
+    tmpl, lc = tiny_case(seed, n_obs=50, H=H, n_f=12, cadence="nightly")
+    js = [3, 7, 11]
+    r = O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, freq_index=js, return_details=True)
+    w = O.weights(lc.sigma)
+    ybar, _ = O.moments(lc.y, w)
+    th = np.linspace(0.0, 2 * np.pi, 60_001)[:-1]
+    h = 1e-6
+    for q, j in enumerate(js):
+        x = 2 * np.pi * j * lc.df * lc.t
+
+        def mm_ym(theta):
+            M = O.template_values(tmpl.c, tmpl.s, x[None, :] - theta[:, None])
+            Mc = M - np.sum(w * M, axis=1, keepdims=True)
+            return np.sum(w * Mc * Mc, axis=1), np.sum(w * Mc * (lc.y - ybar), axis=1)
+
+        MM, YM = mm_ym(th)
+        MMp, YMp = mm_ym(th + h)
+        MMm, YMm = mm_ym(th - h)
+        R = 2 * MM * (YMp - YMm) / (2 * h) - YM * (MMp - MMm) / (2 * h)
+        changes = int(np.sum(np.sign(R) != np.sign(np.roll(R, 1))))
+        cnt, _, _ = O.unit_circle_root_count(r["details"][q]["p"], tol=1e-6)
+        assert cnt == changes
