@@ -118,6 +118,8 @@ typedef struct {
   double ms_verify;        /* learned: Newton + Sturm verification (ms) */
   double ms_aberth;        /* learned / uniform / Aberth: the Aberth kernel (ms) */
   double ms_fallback;      /* learned / uniform / Aberth: companion solve of what is left (ms) */
+  double ms_spread;        /* of the NFFT stage: the spreading kernel (ms) */
+  double ms_fft;           /* of the NFFT stage: the FFT passes (ms) */
 } ftp_stats;
 
 /* Launch shapes of the per-frequency kernels, in wavefronts per compute

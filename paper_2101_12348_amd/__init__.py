@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
                 ("qr_sweeps", ctypes.c_uint64), ("newton_iters", ctypes.c_uint64), ("roots_found", ctypes.c_uint64),
                 ("aberth_iters", ctypes.c_uint64), ("ms_nfft", ctypes.c_double), ("ms_solve", ctypes.c_double),
                 ("ms_roots", ctypes.c_double), ("ms_mlp", ctypes.c_double), ("ms_verify", ctypes.c_double),
-                ("ms_aberth", ctypes.c_double), ("ms_fallback", ctypes.c_double)]
+                ("ms_aberth", ctypes.c_double), ("ms_fallback", ctypes.c_double), ("ms_spread", ctypes.c_double),
+                ("ms_fft", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):

@@ -396,8 +396,10 @@ struct ftp_plan {
   ftp_stats last{};
   // stage timing (FTP_FLAG_TIME_STAGES): one event triple per lightcurve chunk
   // (NFFT start, NFFT end, solve end) and one pair per root-kernel launch
-  std::vector<hipEvent_t> ev, evr, evl;
-  int ev_used = 0, evr_used = 0, evl_used = 0;
+  // and one triple per NFFT launch sequence (before the spreading kernel, after
+  // it, after the FFT passes)
+  std::vector<hipEvent_t> ev, evr, evl, evn;
+  int ev_used = 0, evr_used = 0, evl_used = 0, evn_used = 0;
   // learned
   MlpNet net;
   bool mlp_loaded = false;
@@ -467,6 +469,7 @@ hipEvent_t next_event_in(ftp_plan* P, std::vector<hipEvent_t>& pool, int& used) 
 hipEvent_t next_event(ftp_plan* P) { return next_event_in(P, P->ev, P->ev_used); }
 hipEvent_t next_root_event(ftp_plan* P) { return next_event_in(P, P->evr, P->evr_used); }
 hipEvent_t next_learn_event(ftp_plan* P) { return next_event_in(P, P->evl, P->evl_used); }
+hipEvent_t next_nfft_event(ftp_plan* P) { return next_event_in(P, P->evn, P->evn_used); }
 
 int wait_uploads(ftp_plan* P) {
   if (P->upload_pending) {
@@ -598,9 +601,13 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
   hipLaunchKernelGGL(k_bin_fill<R>, dim3(pblocks), dim3(256), 0, st, dl, n_lc, P->d_obs_off,
                      n_pts, P->pw.as<PointRec<R>>(), P->py.as<PointRec<R>>(), P->tile_off.as<int64_t>(),
                      P->cursor.as<unsigned>(), P->bucket.as<int>());
+  hipEvent_t s0 = next_nfft_event(P);
+  if (s0) HIP_TRY(hipEventRecord(s0, st));
   hipLaunchKernelGGL(k_spread<R>, dim3((unsigned)n_tiles), dim3(256), 0, st, dl, 2 * n_lc,
                      P->d_gtb, P->pw.as<PointRec<R>>(), P->py.as<PointRec<R>>(),
                      P->tile_off.as<int64_t>(), P->bucket.as<int>(), P->grids.as<C>());
+  hipEvent_t s1 = next_nfft_event(P);
+  if (s1) HIP_TRY(hipEventRecord(s1, st));
   const C* tw = reinterpret_cast<const C*>(P->opt.precision == FTP_FP64 ? P->twiddle64.p : P->twiddle32.p);
   int64_t item_base = 0;
   for (size_t r = 0; r < P->fft_round_n.size(); ++r) {
@@ -611,6 +618,8 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
                        P->grids.as<C>());
     item_base += P->fft_round_n[r] + 1;
   }
+  hipEvent_t s2 = next_nfft_event(P);
+  if (s2) HIP_TRY(hipEventRecord(s2, st));
   HIP_TRY(hipGetLastError());
   return FTP_OK;
 }
@@ -732,17 +741,26 @@ int64_t grid_waves(const ftp_plan* P, int wpc, int64_t np) {
 // and the uniform-start ablation without the network); Aberth on every pair
 // -> companion QR on what it leaves (Aberth).  The root kernels take their
 // pairs from queue counters.
-int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) {
-  if (n_pairs <= 0) return FTP_OK;
+// Scratch of the per-frequency stage: records and work lists for chunks of
+// up to `chunk` pairs, and the 8 work counters.
+struct SolveBufs {
+  double* rec;
+  unsigned* ctr;
+  int64_t* fb_list;
+  int64_t* fb2_list;
+  int64_t chunk;
+  SolveCounters* counters;   // statistics copies (nullptr: none kept)
+  bool timing;               // stage events (FTP_FLAG_TIME_STAGES)
+};
+
+// The plan's own scratch for n_pairs pairs (grown on demand).
+int solve_bufs_plan(ftp_plan* P, int64_t n_pairs, SolveBufs* B) {
   const RecLayout RL(P->H);
   const int64_t chunk = std::min<int64_t>(n_pairs, P->pair_chunk);
   int rc;
   if ((rc = P->rec.ensure(sizeof(double) * (size_t)chunk * RL.stride))) return rc;
   if ((rc = P->work_ctr.ensure(8 * sizeof(unsigned)))) return rc;
-  double* rec = P->rec.as<double>();
-  unsigned* ctr = P->work_ctr.as<unsigned>();
-  const bool dataset = P->ds_X != nullptr;
-  const int solver = dataset ? FTP_SOLVER_PLAIN : P->opt.solver;
+  const int solver = P->ds_X != nullptr ? FTP_SOLVER_PLAIN : P->opt.solver;
   if (solver != FTP_SOLVER_PLAIN) {
     if ((rc = P->fb_list.ensure(sizeof(int64_t) * chunk))) return rc;
     if ((rc = P->fb2_list.ensure(sizeof(int64_t) * chunk))) return rc;
@@ -752,6 +770,41 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       if ((rc = P->net.ensure_batch(chunk))) return rc;
     }
   }
+  B->rec = P->rec.as<double>();
+  B->ctr = P->work_ctr.as<unsigned>();
+  B->fb_list = P->fb_list.as<int64_t>();
+  B->fb2_list = P->fb2_list.as<int64_t>();
+  B->chunk = chunk;
+  B->counters = P->counters.as<SolveCounters>();
+  B->timing = (P->opt.flags & FTP_FLAG_TIME_STAGES) != 0;
+  return FTP_OK;
+}
+
+int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const SolveBufs& B, hipStream_t st);
+
+int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) {
+  if (n_pairs <= 0) return FTP_OK;
+  SolveBufs B;
+  int rc;
+  if ((rc = solve_bufs_plan(P, n_pairs, &B))) return rc;
+  return run_solve_with(P, a, n_pairs, B, st);
+}
+
+// The per-frequency stage over n_pairs pairs in chunks of B.chunk, with the
+// scratch in B (the learned solver also uses the plan's network buffers).
+int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const SolveBufs& B, hipStream_t st) {
+  if (n_pairs <= 0) return FTP_OK;
+  const RecLayout RL(P->H);
+  const int64_t chunk = B.chunk;
+  int rc;
+  SolveArgs a = a0;
+  a.counters = B.counters;
+  double* rec = B.rec;
+  unsigned* ctr = B.ctr;
+  const bool dataset = P->ds_X != nullptr;
+  const int solver = dataset ? FTP_SOLVER_PLAIN : P->opt.solver;
+  auto root_ev = [&]() -> hipEvent_t { return B.timing ? next_root_event(P) : nullptr; };
+  auto learn_ev = [&]() -> hipEvent_t { return B.timing ? next_learn_event(P) : nullptr; };
   const ftp_tuning& T = P->tune;
   // scoring of the Newton-root pairs two per wavefront, on the side stream
   const bool overlap_score =
@@ -776,10 +829,10 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
       aa.clear8 = ctr;
       HIP_TRY(launch_assemble(P->opt.precision, aa, rec, p0, np, w_asm, st));
     }
-    hipEvent_t r0 = next_root_event(P);
+    hipEvent_t r0 = root_ev();
     if (r0) HIP_TRY(hipEventRecord(r0, st));
     if (solver == FTP_SOLVER_PLAIN) {
-      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, nullptr, nullptr, P->counters.as<SolveCounters>(), ctr + 4, w_qr,
+      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, nullptr, nullptr, B.counters, ctr + 4, w_qr,
                         st));
     } else {
       const float* seeds = nullptr;
@@ -809,14 +862,14 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
         }
         seeds = P->seeds.as<float>();
       }
-      hipEvent_t ra = next_learn_event(P);
+      hipEvent_t ra = learn_ev();
       if (ra) HIP_TRY(hipEventRecord(ra, st));
       if (solver != FTP_SOLVER_ABERTH) {
         LearnArgs L{};
         L.rec = rec;
         L.np = np;
         L.seeds_out = seeds;
-        L.fb_list = P->fb_list.as<int64_t>();
+        L.fb_list = B.fb_list;
         L.fb_count = ctr;
         L.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
         L.queue = nullptr;   // uniform work per pair: grid striding (a queue costs more than it balances)
@@ -832,29 +885,29 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
           HIP_TRY(launch_score2(as, rec, p0, np, w_sc, P->side, P->join_ev));
         }
       }
-      hipEvent_t rb = next_learn_event(P);
+      hipEvent_t rb = learn_ev();
       if (rb) HIP_TRY(hipEventRecord(rb, st));
       AberthArgs A{};
       A.rec = rec;
       A.np = np;
-      A.list = solver == FTP_SOLVER_ABERTH ? nullptr : P->fb_list.as<int64_t>();
+      A.list = solver == FTP_SOLVER_ABERTH ? nullptr : B.fb_list;
       A.count = ctr;
-      A.qr_list = P->fb2_list.as<int64_t>();
+      A.qr_list = B.fb2_list;
       A.qr_count = ctr + 1;
-      A.counters = P->counters.as<SolveCounters>();
+      A.counters = B.counters;
       A.H = P->H;
       A.mark = 2.0;
       A.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
       A.queue = ctr + 3;
       HIP_TRY(launch_aberth(A, w_ab, st));
-      hipEvent_t rc2 = next_learn_event(P);
+      hipEvent_t rc2 = learn_ev();
       if (rc2) HIP_TRY(hipEventRecord(rc2, st));
       // what the Aberth tier leaves is usually nothing or a few frequencies:
       // a launch of one wave per CU serves it through the queue
-      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, P->fb2_list.as<int64_t>(), ctr + 1,
-                        P->counters.as<SolveCounters>(), ctr + 4, std::min(w_qr, (int)grid_waves(P, 1, np)), st));
+      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, B.fb2_list, ctr + 1,
+                        B.counters, ctr + 4, std::min(w_qr, (int)grid_waves(P, 1, np)), st));
     }
-    hipEvent_t r1 = next_root_event(P);
+    hipEvent_t r1 = root_ev();
     if (r1) HIP_TRY(hipEventRecord(r1, st));
     if (dataset) {
       HIP_TRY(launch_features(rec, P->H, np, P->ds_X + p0 * (int64_t)(2 * (6 * P->H - 1)), 2 * (6 * P->H - 1),
@@ -871,7 +924,7 @@ int run_solve(ftp_plan* P, const SolveArgs& a, int64_t n_pairs, hipStream_t st) 
         // stream's outputs before whatever follows on this one (the next
         // chunk's assembly rewrites the records)
         HIP_TRY(launch_score(as, rec, p0, np, std::min(w_sc, (int)grid_waves(P, 2, np)), st,
-                             P->fb_list.as<int64_t>(), ctr));
+                             B.fb_list, ctr));
         HIP_TRY(hipStreamWaitEvent(st, P->join_ev, 0));
       } else {
         HIP_TRY(launch_score(as, rec, p0, np, w_sc, st));
@@ -1180,6 +1233,7 @@ int ftp_plan_destroy(ftp_plan* P) {
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : P->evr) (void)hipEventDestroy(e);
   for (hipEvent_t e : P->evl) (void)hipEventDestroy(e);
+  for (hipEvent_t e : P->evn) (void)hipEventDestroy(e);
   delete P;
   return FTP_OK;
 }
@@ -1750,6 +1804,14 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
       out->ms_fallback += f;
     }
   }
+  out->ms_spread = out->ms_fft = 0.0;
+  for (int k = 0; k + 3 <= P->evn_used; k += 3) {
+    float a = 0.f, b = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, P->evn[k], P->evn[k + 1]));
+    HIP_TRY(hipEventElapsedTime(&b, P->evn[k + 1], P->evn[k + 2]));
+    out->ms_spread += a;
+    out->ms_fft += b;
+  }
   out->n_fallback = c.fallback;
   out->n_fallback_qr = c.fallback_qr;
   out->aberth_iters = c.aberth_iters;
@@ -1760,6 +1822,7 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
   P->ev_used = 0;
   P->evr_used = 0;
   P->evl_used = 0;
+  P->evn_used = 0;
   P->last = ftp_stats{};
   HIP_TRY(hipMemsetAsync(P->counters.p, 0, sizeof(SolveCounters) * kCounterSlots, (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));

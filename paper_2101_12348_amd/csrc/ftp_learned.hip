@@ -17,10 +17,12 @@
 //   * if they do, the Newton roots are the candidate set; otherwise the
 //     frequency goes to the Aberth iteration (then, if that does not
 //     converge, to the companion-matrix solve) through device work lists.
-// For H <= 10 a wavefront takes two frequencies (k_newton_sturm2, 32 starts
-// each, at most D); for H = 11 one (k_newton_sturm, 4H starts).  The Sturm
-// sequence is formed in registers, one coefficient per lane (for D = 64 the
-// top coefficient is carried as a scalar; see sturm_begin).
+// For H <= 10 a wavefront takes four frequencies (k_newton_sturm4): their
+// Sturm sequences run one per 16-lane row with four coefficients per lane in
+// registers, and Newton runs on two of them at a time (32 starts each, at
+// most D).  For H = 11 a wavefront takes one (k_newton_sturm, 4H starts),
+// its Sturm sequence one coefficient per lane (the degree-64 coefficient
+// carried as a scalar; see sturm_begin).
 #include <hip/hip_ext.h>
 #include "ftp_solve_common.h"
 
@@ -66,18 +68,6 @@ __device__ __forceinline__ int wave_max_int(int h) {
   h = max(h, dpp_i<0x142, 0xa>(h));
   h = max(h, dpp_i<0x143, 0xc>(h));
   return __builtin_amdgcn_readlane(h, 63);
-}
-
-// Maxima of an int over lanes 0..31 and 32..63 (row stages, then
-// row_bcast:15 into rows 1 and 3: lanes 31 and 63).
-__device__ __forceinline__ void half_max_int(int h, int& h_lo, int& h_hi) {
-  h = max(h, dpp_i<0xB1, 0xf>(h));
-  h = max(h, dpp_i<0x4E, 0xf>(h));
-  h = max(h, dpp_i<0x141, 0xf>(h));
-  h = max(h, dpp_i<0x140, 0xf>(h));
-  h = max(h, dpp_i<0x142, 0xa>(h));
-  h_lo = __builtin_amdgcn_readlane(h, 31);
-  h_hi = __builtin_amdgcn_readlane(h, 63);
 }
 
 // The test of one Sturm step on high words: hr = hi(max |t|) of the
@@ -180,90 +170,159 @@ __device__ __forceinline__ double bperm_d(int addr, double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// The same for two polynomials at once (two frequencies of one wavefront).
-// While a member still has more than 32 coefficients the two chains are
-// stepped side by side over the whole wave; from step D - 29 on, every
-// polynomial of both chains fits in 32 lanes, and the chains are packed into
-// the two half-waves (chain b's coefficient c in lane 32 + c) and stepped by
-// one instruction stream.  Coefficients above a member's degree are exact
-// zeros, so the shift by one power of x brings a zero into lane 32 (the
-// scale is kept finite for that: a zero times it stays zero).  In the packed
-// form the per-lane values al bl and bl are equal within each half, the test
-// and the sign count run on scalar registers per chain, and the two
-// coefficients a step needs from its own half (t_db for the quotient, the new
-// leading coefficient) come by ds_bpermute from lane 32 h + db (- 1).
-// One packed step (both chains, one per half-wave): the new member from A and
-// B into A (the caller swaps the roles of A and B on alternate steps, so that
-// the chain needs no register moves).  The step's test values go to scalar
-// registers per chain: hr (hi of max |t|) and hl (the signed high word of the
-// new leading coefficient), which also gives the sign count.
-struct PackedScalars {
-  int hMA, hMB;   // hi(max |coefficient|) of the two members
-  int m12, m13;   // smallest margins of the two tests so far
+// Four Sturm chains per wavefront, one per 16-lane row.  Lane 16 c + l holds
+// coefficients 16 r + l (r = 0..3) of chain c's members in registers, so a
+// member of up to 64 coefficients needs no LDS and every instruction of a
+// step serves four chains: the shift by one power of x is a row rotation
+// (DPP row_ror:1, lane 0 taking lane 15 of the register below), the two
+// coefficients a step needs from its own chain (the quotient's and the new
+// leading coefficient) come by ds_bpermute from the row's lane, and the
+// largest coefficient by a row all-reduction.  Per coefficient the arithmetic
+// is that of sturm_begin / sturm_step (scaled members with leading
+// coefficient +-1, quotients without division, the same step test on high
+// words), and a step only touches the registers below the member's degree
+// (NR of them), so late steps cost a quarter of early ones.
+struct Rows4State {
+  int hMA, hMB;   // hi(max |coefficient|) of the last two members
+  int m12, m13;   // smallest margins of the two step tests so far
   int hmax;       // largest hi(max |t|) so far (finiteness)
   int sp, vp;     // last member positive at +inf (0 / 1); sign changes at +inf
 };
-// hr = hi(max |t|), hl = the high word of the new leading coefficient (signed)
-__device__ __forceinline__ void packed_scalars_step(PackedScalars& c, int hr, int hl) {
-  const int ha = hl & 0x7fffffff;
-  c.m12 = min(c.m12, hr - max(c.hMA, c.hMB));
-  c.m13 = min(c.m13, ha - hr);
-  c.hmax = max(c.hmax, hr);
-  c.hMA = c.hMB;
-  c.hMB = sturm_member_hi(hr, ha);
-  const int tp = (int)((unsigned)hl >> 31);   // P_q = -t / |lead| positive at +inf
-  c.vp += tp ^ c.sp;
-  c.sp = tp;
+
+// maximum of an int over each 16-lane row, left in every lane of the row
+__device__ __forceinline__ int row_max_int(int h) {
+  h = max(h, dpp_i<0xB1, 0xf>(h));    // quad_perm [1, 0, 3, 2]
+  h = max(h, dpp_i<0x4E, 0xf>(h));    // quad_perm [2, 3, 0, 1]
+  h = max(h, dpp_i<0x124, 0xf>(h));   // row_ror:4
+  h = max(h, dpp_i<0x128, 0xf>(h));   // row_ror:8
+  return h;
 }
-__device__ __forceinline__ void sturm_packed_step(double& A, const double B, double& bl, double& ab, PackedScalars& sa,
-                                                  PackedScalars& sb, int db, int hl, int pbase) {
-  double t = fma(-ab, lane_shr1(B), A);
-  const int pl = pbase + ((db - 1) << 2);
-  const double q0 = bperm_d(pl + 4, t) * bl;
-  t = hl < db ? fma(-q0, B, t) : 0.0;
-  const double lead = bperm_d(pl, t);
-  const int hlead = hiword(lead);
-  int hra, hrb;
-  half_max_int(hiword(t) & 0x7fffffff, hra, hrb);
-  packed_scalars_step(sa, hra, __builtin_amdgcn_readlane(hlead, 0));
-  packed_scalars_step(sb, hrb, __builtin_amdgcn_readlane(hlead, 32));
-  const double s = fast_rcp_d(fabs(lead) + 1e-300);
+
+// register r of t for a wave-uniform r < NR, by masks (a chain of selects
+// would be turned into an indexed load from a stack copy of t)
+template <int NR>
+__device__ __forceinline__ double pick_reg(const double (&t)[NR], int r) {
+  unsigned long long v = 0;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const unsigned long long m = 0ull - (unsigned long long)(r == k);
+    v |= (unsigned long long)__double_as_longlong(t[k]) & m;
+  }
+  return __longlong_as_double((long long)v);
+}
+
+__device__ __forceinline__ void sturm4_begin(const double (&G)[4], double gtop, int D, int l, double (&A)[4],
+                                             double (&B)[4], double& bl, double& ab, Rows4State& S, bool& ok) {
+  const double ag = fabs(gtop), sgn = gtop > 0.0 ? 1.0 : -1.0;
+  const double sa = fast_rcp_d(ag + 1e-300), sb = fast_rcp_d(D * ag + 1e-300);
+  ok = ag > 0.0 && ag < INFINITY;
+  int hA = 0, hB = 0;
+  double nxt = dpp_d<0x12F>(G[0]);   // row_ror:15: lane l + 1 of the row (lane 0 at l = 15)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int k = 16 * r + l;
+    const double up = r < 3 ? dpp_d<0x12F>(G[r < 3 ? r + 1 : 3]) : 0.0;
+    const double g1 = l == 15 ? up : nxt;   // coefficient k + 1
+    nxt = up;
+    const double dv = k < D ? (k + 1) * g1 : 0.0;
+    A[r] = k == D ? sgn : G[r] * sa;
+    B[r] = k == D - 1 ? sgn : dv * sb;
+    hA = max(hA, hiword(A[r]) & 0x7fffffff);
+    hB = max(hB, hiword(B[r]) & 0x7fffffff);
+  }
+  S.hMA = max(row_max_int(hA), kHi1);
+  S.hMB = row_max_int(hB);
+  S.m12 = S.m13 = 0x7fffffff;
+  S.hmax = 0;
+  S.sp = gtop > 0.0 ? 1 : 0;
+  S.vp = 0;
+  bl = sgn;
+  ab = 1.0;
+}
+
+// Member q from the last two: A (older, degree db + 1) is overwritten by the
+// new member; B (degree db) is the newer.  db = D - q + 1; NR registers hold
+// every coefficient up to db + 1.
+template <int NR>
+__device__ __forceinline__ void sturm4_step(double (&A)[4], const double (&B)[4], double& bl, double& ab,
+                                            Rows4State& S, int db, int l, int pbase) {
+  double t[NR];
+  double below = 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double rot = dpp_d<0x121>(B[r]);   // row_ror:1: lane l - 1 (lane 0: lane 15)
+    t[r] = fma(-ab, l == 0 ? below : rot, A[r]);
+    below = rot;
+  }
+  const int rq = db >> 4, lq = db & 15;
+  const double q0 = bperm_d(pbase + (lq << 2), pick_reg<NR>(t, rq)) * bl;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double v = fma(-q0, B[r], t[r]);
+    t[r] = (r < rq || (r == rq && l < lq)) ? v : 0.0;
+  }
+  const int rl = (db - 1) >> 4, ll = (db - 1) & 15;
+  const double lead = bperm_d(pbase + (ll << 2), pick_reg<NR>(t, rl));
+  int h = 0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) h = max(h, hiword(t[r]) & 0x7fffffff);
+  const int hr = row_max_int(h);
+  const int hlead = hiword(lead), ha = hlead & 0x7fffffff;
+  S.m12 = min(S.m12, hr - max(S.hMA, S.hMB));
+  S.m13 = min(S.m13, ha - hr);
+  S.hmax = max(S.hmax, hr);
+  S.hMA = S.hMB;
+  S.hMB = sturm_member_hi(hr, ha);
+  const int tp = (int)((unsigned)hlead >> 31);   // P_q = -t / |lead| positive at +inf
+  S.vp += tp ^ S.sp;
+  S.sp = tp;
+  const double sc = fast_rcp_d(fabs(lead) + 1e-300);
   const double nb = from_hiword((hlead & 0x80000000) ^ 0xbff00000);   // -sign(lead)
-  A = -t * s;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) A[r] = -t[r] * sc;
   ab = bl * nb;
   bl = nb;
 }
 
-__device__ void sturm_count_line_reg2(double ga, double gb, int D, int lane, int& ca, int& cb) {
-  SturmChain a = sturm_begin(ga, lrdlane(ga, D), D, lane);
-  SturmChain b = sturm_begin(gb, lrdlane(gb, D), D, lane);
-  const int qpack = D - 29 > 2 ? D - 29 : 2;
+// steps q .. qend - 1 with NR registers; A holds the older member and B the
+// newer on entry and on return
+template <int NR>
+__device__ __forceinline__ void sturm4_phase(double (&A)[4], double (&B)[4], double& bl, double& ab, Rows4State& S,
+                                             int D, int& q, int qend, int l, int pbase) {
+  for (; q + 1 < qend; q += 2) {
+    sturm4_step<NR>(A, B, bl, ab, S, D - q + 1, l, pbase);
+    sturm4_step<NR>(B, A, bl, ab, S, D - q, l, pbase);
+  }
+  if (q < qend) {
+    sturm4_step<NR>(A, B, bl, ab, S, D - q + 1, l, pbase);
+    ++q;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double x = A[r];
+      A[r] = B[r];
+      B[r] = x;
+    }
+  }
+}
+
+// Distinct real roots of the degree-D polynomial of this lane's row (D + 1 <=
+// 64; G[r] = coefficient 16 r + (lane & 15), zero above D; gtop = coefficient
+// D), or -1 when a step fails its test.  All lanes must be active.
+__device__ __forceinline__ int sturm_count_rows4(const double (&G)[4], double gtop, int D, int lane) {
+  const int l = lane & 15, pbase = (lane & 48) << 2;
+  double A[4], B[4], bl, ab;
+  Rows4State S;
+  bool ok;
+  sturm4_begin(G, gtop, D, l, A, B, bl, ab, S, ok);
+  // step q touches coefficients up to D - q + 2: four registers while that is
+  // at least 48, three down to 32, two down to 16, then one
   int q = 2;
-  for (; q < qpack; ++q) {
-    sturm_step(a, D, q, lane);
-    sturm_step(b, D, q, lane);
-  }
-  const int half = lane >> 5, hl = lane & 31;
-  const double bA = __shfl(b.A, hl), bB = __shfl(b.B, hl);   // all lanes active
-  double A = half ? bA : a.A, B = half ? bB : a.B;
-  double bl = half ? b.bl : a.bl, ab = half ? b.al * b.bl : a.al * a.bl;
-  // the steps' tests, kept as the smallest margins and checked at the end
-  // (the same as requiring every step to pass), and the sign counts
-  PackedScalars sa{a.hMA, a.hMB, 0x7fffffff, 0x7fffffff, 0, a.sp, a.vp};
-  PackedScalars sb{b.hMA, b.hMB, 0x7fffffff, 0x7fffffff, 0, b.sp, b.vp};
-  const int pbase = (lane & 32) << 2;   // ds_bpermute byte address of the half's lane 0
-  // two steps per trip: the new member overwrites the older of the two
-  for (; q + 1 <= D; q += 2) {
-    sturm_packed_step(A, B, bl, ab, sa, sb, D - q + 1, hl, pbase);
-    sturm_packed_step(B, A, bl, ab, sa, sb, D - q, hl, pbase);
-  }
-  if (q <= D) {
-    sturm_packed_step(A, B, bl, ab, sa, sb, D - q + 1, hl, pbase);
-  }
-  const bool oka = a.ok && sa.hmax < 0x7ff00000 && sa.m12 > -kHiT12 && sa.m13 > -kHiT13;
-  const bool okb = b.ok && sb.hmax < 0x7ff00000 && sb.m12 > -kHiT12 && sb.m13 > -kHiT13;
-  ca = oka ? D - 2 * sa.vp : -1;
-  cb = okb ? D - 2 * sb.vp : -1;
+  sturm4_phase<4>(A, B, bl, ab, S, D, q, min(D + 1, D - 45), l, pbase);
+  sturm4_phase<3>(A, B, bl, ab, S, D, q, min(D + 1, D - 29), l, pbase);
+  sturm4_phase<2>(A, B, bl, ab, S, D, q, min(D + 1, D - 13), l, pbase);
+  sturm4_phase<1>(A, B, bl, ab, S, D, q, D + 1, l, pbase);
+  ok = ok && S.hmax < 0x7ff00000 && S.m12 > -kHiT12 && S.m13 > -kHiT13;
+  return ok ? D - 2 * S.vp : -1;
 }
 
 struct LearnArgs {
@@ -362,166 +421,187 @@ __device__ __forceinline__ double theta_from_u(double phi0, double u, int sg) {
   return th >= kTwoPi ? th - kTwoPi : (th < 0.0 ? th + kTwoPi : th);
 }
 
-// Two frequencies per wavefront (H <= 10, D < 64): frequencies 2b and 2b + 1 of the
-// list.  Their two Sturm chains are stepped side by side (the chains are
-// serial, so a second independent one fills the latency of the first), then
-// Newton runs on both at once, lanes 0..31 for the first and 32..63 for the
-// second, each half with the merge and stop rule of the one-frequency kernel
-// and min(32, D) starts: the 2H network seeds and min(32, D) - 2H evenly
-// spaced phases (all evenly spaced without network).  The Newton steps are
-// those of R in theta, evaluated on the Cayley polynomial (newton_u_step).  A
-// half that has reached its count is frozen while the other goes on.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_sturm2(SolveArgs a, LearnArgs L) {
-  extern __shared__ double sml[];
-  const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
-  // starts per frequency: every lane of the half (at most D: no more real
-  // roots exist, and the candidate slots hold D)
-  const int H = a.H, K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = D < 32 ? D : 32;
-  const int FS = D + 2;   // f and its reversal for each half, 16-byte aligned
-  const RecLayout RL(H);
+// Four frequencies per wavefront (H <= 10, D < 64): frequencies 4b .. 4b + 3
+// of the list.  Their four Sturm chains run side by side, one per 16-lane
+// row (sturm_count_rows4); then Newton runs on two of them at a time, lanes
+// 0..31 for the first and 32..63 for the second, each half with min(32, D)
+// starts: the 2H network seeds and min(32, D) - 2H evenly spaced phases (all
+// evenly spaced without network).  The Newton steps are those of R in theta,
+// evaluated on the Cayley polynomial (newton_u_step); converged roots are
+// merged one root per pass, and a half that has reached its count is frozen
+// while the other goes on.
+struct NewtonAcc {
+  unsigned long long iters, roots, fb;
+};
+
+// Newton on frequencies wA (lanes 0..31) and wA + 1 (lanes 32..63, if hasB)
+// with Sturm counts cA, cB (-2 inactive, -1 untrusted); f of each half and its
+// reversal in fb (LDS, 2 FS doubles per half).
+__device__ __forceinline__ void newton_pair(const LearnArgs& L, const RecLayout& RL, int H, int64_t wA, int cA, int cB,
+                                            const double* fb, int lane, NewtonAcc& acc) {
+  const int half = lane >> 5, hl = lane & 31;
+  const int K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = D < 32 ? D : 32;
+  const int FS = D + 2;
   const unsigned long long lo32 = 0xffffffffull;
   const unsigned long long hmask = half ? ~lo32 : lo32;
   const unsigned long long below = (1ull << lane) - 1ull;
-  unsigned long long iters_acc = 0, roots_acc = 0, fb_acc = 0;
-  for (int64_t w0 = 2 * (int64_t)blockIdx.x; w0 < L.np; w0 += 2 * (int64_t)gridDim.x) {
-    const bool hasB = w0 + 1 < L.np;
-    double* RA = L.rec + w0 * (int64_t)RL.stride;
-    double* RB = hasB ? RA + RL.stride : RA;
-    const int stA = (int)RA[RL.meta + M_STATUS];
-    const int stB = hasB ? (int)RB[RL.meta + M_STATUS] : ST_BAD_LC;
-    const bool actA = stA != ST_BAD_LC && stA != ST_CONSTANT;
-    const bool actB = stB != ST_BAD_LC && stB != ST_CONSTANT;
-    if (!actA && !actB) continue;
-    double* Rh = half ? RB : RA;            // this lane's frequency
-    const int64_t wh = w0 + half;
-    const bool acth = half ? actB : actA;
-    if (L.flags & 1u) {   // forced fallback
-      if (hl == 0 && acth) {
-        const unsigned slot = atomicAdd(L.fb_count, 1u);
-        L.fb_list[slot] = wh;
-        Rh[RL.meta + M_FALLBACK] = 1.0;
+  if (cA == -2 && cB == -2) return;
+  double* Rh = L.rec + (wA + half) * (int64_t)RL.stride;   // this lane's frequency (unused when inactive)
+  const int64_t wh = wA + half;
+  const int cnt = half ? cB : cA;
+  const double phi0 = cnt != -2 ? Rh[RL.meta + M_PHI0] : 0.0;
+  double u = 0.0;
+  int sg = 1;
+  bool conv = false, live = cnt >= 0 && hl < NS;
+  int its = 0;
+  if (live) {
+    // start direction relative to phi0: a network seed (its output vector
+    // is the root's direction in the canonical frame, rotated here by
+    // -(canon + phi0)) or an evenly spaced phase less phi0
+    const bool seeded = L.seeds_out && hl < S;
+    double bc = 1.0, bs = 0.0, ang;
+    if (seeded) {
+      const float* o = L.seeds_out + wh * 2 * S;
+      bc = (double)o[2 * hl];
+      bs = (double)o[2 * hl + 1];
+      ang = -(Rh[RL.meta + M_CANON] + phi0);
+    } else {
+      ang = (L.seeds_out ? (hl - S + 0.5) * (kTwoPi / (NS - S)) : (hl + 0.5) * (kTwoPi / NS)) - phi0;
+    }
+    double s1, c1;
+    sincos_small(ang, s1, c1);
+    u_from_dir(fma(bc, c1, -bs * s1), fma(bc, s1, bs * c1), u, sg);
+  }
+  const double* fbase = fb + 2 * FS * half;
+  bool doneA = cA < 0, doneB = cB < 0;
+  unsigned long long um = 0ull, merged = 0ull, U = 0ull;   // U: unique converged lanes
+  for (int it = 1; it <= 12 && !(doneA && doneB); ++it) {
+    if (live && !conv) {
+      bool ok;
+      const double sc = newton_u_step(sg > 0 ? fbase : fbase + FS, D, K, u, sg, ok);
+      if (!ok) {
+        live = false;
+      } else {
+        ++its;
+        if (fabs(sc) < 1e-12) conv = true;
       }
-      fb_acc += (unsigned long long)actA + (unsigned long long)actB;
+    }
+    if (it >= 4) {   // merges are incremental, so every iteration from the fourth checks
+      const unsigned long long cm = __ballot(conv);
+      const bool needA = !doneA && __popcll(cm & lo32) >= cA;
+      const bool needB = !doneB && __popcll(cm >> 32) >= cB;
+      if (!needA && !needB && it < 12) continue;
+      // distinct converged roots of each half: a converged lane is unique
+      // unless a lower converged lane of its half lies within 1e-8 rad.
+      // Compared on key = u (sg > 0) or sign(u) 2 - u (sg < 0), which
+      // increases with theta - phi0 over (-pi, pi) and moves by |du| where
+      // theta moves by 2 |du| / (1 + u^2) (the cut at theta - phi0 = pi
+      // sits where R is largest, far from any root).  Converged lanes no
+      // longer move, so each check settles only the lanes converged since
+      // the last: one pass per root, from the lowest pending lane jj, marks
+      // every converged lane of its half within the tolerance of jj; jj is
+      // unique if none of them is lower, and the higher ones (also roots
+      // settled earlier) are not.
+      const double key = sg > 0 ? u : copysign(2.0, u) - u;
+      for (unsigned long long pend = cm & ~merged; pend;) {
+        const int jj = __builtin_ctzll(pend);
+        const double kj = lrdlane(key, jj), uj = lrdlane(u, jj);
+        const double tol = 0.5e-8 * fma(uj, uj, 1.0);
+        const unsigned long long bit = 1ull << jj;
+        const unsigned long long same = __ballot(fabs(key - kj) < tol) & cm & (jj < 32 ? lo32 : ~lo32);
+        const unsigned long long upto = (bit << 1) - 1ull;   // lanes 0..jj
+        U &= upto | ~same;
+        U = (same & (bit - 1ull)) ? (U & ~bit) : (U | bit);
+        pend &= ~(same | bit);
+      }
+      merged = cm;
+      um = U;
+      if (__popcll(um & lo32) == cA) doneA = true;
+      if (__popcll(um >> 32) == cB) doneB = true;
+      if (half ? doneB : doneA) live = false;
+    }
+  }
+  acc.iters += (unsigned long long)wave_sum((double)its);
+  const double thw = theta_from_u(phi0, u, sg);
+  const int nuA = __popcll(um & lo32), nuB = __popcll(um >> 32);
+  const bool okA = cA >= 0 && nuA == cA, okB = cB >= 0 && nuB == cB;
+  const bool ok = half ? okB : okA;
+  const int nu = half ? nuB : nuA;
+  double* cand = Rh + RL.cand;
+  if (cnt != -2 && ok)
+    for (int c = hl; c < D; c += 32) cand[c] = __longlong_as_double(0x7ff8000000000000ll);
+  lwave_sync();
+  // confirmed roots, or the distinct roots found, which start the Aberth
+  // iteration of a fallback frequency
+  if (cnt != -2 && ((um >> lane) & 1ull)) cand[__popcll(um & hmask & below)] = thw;
+  if (cnt != -2 && !ok && hl == 0) {
+    Rh[RL.meta + M_WARM] = (double)nu;
+    Rh[RL.meta + M_FALLBACK] = 1.0;
+    const unsigned slot = atomicAdd(L.fb_count, 1u);
+    L.fb_list[slot] = wh;
+  }
+  acc.roots += (unsigned long long)((okA ? nuA : 0) + (okB ? nuB : 0));
+  acc.fb += (unsigned long long)((cA != -2 && !okA) + (cB != -2 && !okB));
+  lwave_sync();
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_sturm4(SolveArgs a, LearnArgs L) {
+  extern __shared__ double sml[];
+  const int lane = threadIdx.x & 63, row = lane >> 4, l = lane & 15;
+  const int H = a.H, D = 6 * H - 2;
+  const int FS = D + 2;   // f and its reversal for each frequency, 16-byte aligned
+  const RecLayout RL(H);
+  NewtonAcc acc{0, 0, 0};
+  for (int64_t w0 = 4 * (int64_t)blockIdx.x; w0 < L.np; w0 += 4 * (int64_t)gridDim.x) {
+    // statuses of the four frequencies (inactive: past the end, rejected
+    // lightcurve, or P constant in theta_2)
+    int act = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (w0 + c < L.np) {
+        const int st = (int)L.rec[(w0 + c) * (int64_t)RL.stride + RL.meta + M_STATUS];
+        act |= (st != ST_BAD_LC && st != ST_CONSTANT) ? 1 << c : 0;
+      }
+    }
+    if (!act) continue;
+    if (L.flags & 1u) {   // forced fallback
+      if (l == 0 && ((act >> row) & 1)) {
+        const unsigned slot = atomicAdd(L.fb_count, 1u);
+        L.fb_list[slot] = w0 + row;
+        L.rec[(w0 + row) * (int64_t)RL.stride + RL.meta + M_FALLBACK] = 1.0;
+      }
+      acc.fb += (unsigned long long)__popc((unsigned)act);
       continue;
     }
-    const double fA = lane <= D ? RA[RL.f + lane] : 0.0;
-    const double fB = lane <= D ? RB[RL.f + lane] : 0.0;
-    if (lane <= D) {
-      sml[lane] = fA;
-      sml[FS + D - lane] = fA;
-      sml[2 * FS + lane] = fB;
-      sml[3 * FS + D - lane] = fB;
-    }
-    lwave_sync();
-    // counts: -2 inactive (no output), -1 ill-determined or below two (to the
-    // fallback without Newton), else the number of distinct real roots
-    int cA, cB;
-    sturm_count_line_reg2(fA, fB, D, lane, cA, cB);
-    if (cA < 2) cA = -1;
-    if (cB < 2) cB = -1;
-    if (!actA) cA = -2;
-    if (!actB) cB = -2;
-    const int cnt = half ? cB : cA;
-    const double phi0 = Rh[RL.meta + M_PHI0];
-    double u = 0.0;
-    int sg = 1;
-    bool conv = false, live = cnt >= 0 && hl < NS;
-    int its = 0;
-    if (live) {
-      // start direction relative to phi0: a network seed (its output vector
-      // is the root's direction in the canonical frame, rotated here by
-      // -(canon + phi0)) or an evenly spaced phase less phi0
-      const bool seeded = L.seeds_out && hl < S;
-      double bc = 1.0, bs = 0.0, ang;
-      if (seeded) {
-        const float* o = L.seeds_out + wh * 2 * S;
-        bc = (double)o[2 * hl];
-        bs = (double)o[2 * hl + 1];
-        ang = -(Rh[RL.meta + M_CANON] + phi0);
-      } else {
-        ang = (L.seeds_out ? (hl - S + 0.5) * (kTwoPi / (NS - S)) : (hl + 0.5) * (kTwoPi / NS)) - phi0;
-      }
-      double s1, c1;
-      sincos_small(ang, s1, c1);
-      u_from_dir(fma(bc, c1, -bs * s1), fma(bc, s1, bs * c1), u, sg);
-    }
-    const double* fbase = sml + 2 * FS * half;
-    bool doneA = cA < 0, doneB = cB < 0;
-    unsigned long long um = 0ull, merged = 0ull, U = 0ull;   // U: unique converged lanes
-    for (int it = 1; it <= 12 && !(doneA && doneB); ++it) {
-      if (live && !conv) {
-        bool ok;
-        const double sc = newton_u_step(sg > 0 ? fbase : fbase + FS, D, K, u, sg, ok);
-        if (!ok) {
-          live = false;
-        } else {
-          ++its;
-          if (fabs(sc) < 1e-12) conv = true;
-        }
-      }
-      if (it >= 4) {   // merges are incremental, so every iteration from the fourth checks
-        const unsigned long long cm = __ballot(conv);
-        const bool needA = !doneA && __popcll(cm & lo32) >= cA;
-        const bool needB = !doneB && __popcll(cm >> 32) >= cB;
-        if (!needA && !needB && it < 12) continue;
-        // distinct converged roots of each half: a converged lane is unique
-        // unless a lower converged lane of its half lies within 1e-8 rad.
-        // Compared on key = u (sg > 0) or sign(u) 2 - u (sg < 0), which
-        // increases with theta - phi0 over (-pi, pi) and moves by |du| where
-        // theta moves by 2 |du| / (1 + u^2) (the cut at theta - phi0 = pi
-        // sits where R is largest, far from any root).  Converged lanes no
-        // longer move, so each check settles only the lanes converged since
-        // the last: one pass per root, from the lowest pending lane jj, marks
-        // every converged lane of its half within the tolerance of jj; jj is
-        // unique if none of them is lower, and the higher ones (also roots
-        // settled earlier) are not.
-        const double key = sg > 0 ? u : copysign(2.0, u) - u;
-        for (unsigned long long pend = cm & ~merged; pend;) {
-          const int jj = __builtin_ctzll(pend);
-          const double kj = lrdlane(key, jj), uj = lrdlane(u, jj);
-          const double tol = 0.5e-8 * fma(uj, uj, 1.0);
-          const unsigned long long bit = 1ull << jj;
-          const unsigned long long same = __ballot(fabs(key - kj) < tol) & cm & (jj < 32 ? lo32 : ~lo32);
-          const unsigned long long upto = (bit << 1) - 1ull;   // lanes 0..jj
-          U &= upto | ~same;
-          U = (same & (bit - 1ull)) ? (U & ~bit) : (U | bit);
-          pend &= ~(same | bit);
-        }
-        merged = cm;
-        um = U;
-        if (__popcll(um & lo32) == cA) doneA = true;
-        if (__popcll(um >> 32) == cB) doneB = true;
-        if (half ? doneB : doneA) live = false;
+    // lane 16 c + l: coefficients 16 r + l of frequency c (zero above D or
+    // for an inactive frequency); f and its reversal to LDS for Newton
+    const bool mine = (act >> row) & 1;
+    const double* f = L.rec + (w0 + (mine ? row : 0)) * (int64_t)RL.stride + RL.f;
+    double G[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 16 * r + l;
+      G[r] = (mine && k <= D) ? f[k] : 0.0;
+      if (mine && k <= D) {
+        sml[2 * FS * row + k] = G[r];
+        sml[2 * FS * row + FS + D - k] = G[r];
       }
     }
-    iters_acc += (unsigned long long)wave_sum((double)its);
-    const double thw = theta_from_u(phi0, u, sg);
-    const int nuA = __popcll(um & lo32), nuB = __popcll(um >> 32);
-    const bool okA = cA >= 0 && nuA == cA, okB = cB >= 0 && nuB == cB;
-    const bool ok = half ? okB : okA;
-    const int nu = half ? nuB : nuA;
-    double* cand = Rh + RL.cand;
-    if (cnt != -2 && ok)
-      for (int c = hl; c < D; c += 32) cand[c] = __longlong_as_double(0x7ff8000000000000ll);
+    const double gtop = mine ? f[D] : 0.0;
     lwave_sync();
-    // confirmed roots, or the distinct roots found, which start the Aberth
-    // iteration of a fallback frequency
-    if (cnt != -2 && ((um >> lane) & 1ull)) cand[__popcll(um & hmask & below)] = thw;
-    if (cnt != -2 && !ok && hl == 0) {
-      Rh[RL.meta + M_WARM] = (double)nu;
-      Rh[RL.meta + M_FALLBACK] = 1.0;
-      const unsigned slot = atomicAdd(L.fb_count, 1u);
-      L.fb_list[slot] = wh;
-    }
-    roots_acc += (unsigned long long)((okA ? nuA : 0) + (okB ? nuB : 0));
-    fb_acc += (unsigned long long)((actA && !okA) + (actB && !okB));
-    lwave_sync();
+    int cnt = sturm_count_rows4(G, gtop, D, lane);
+    if (cnt < 2) cnt = -1;
+    if (!mine) cnt = -2;
+    const int c0 = __builtin_amdgcn_readlane(cnt, 0), c1 = __builtin_amdgcn_readlane(cnt, 16);
+    const int c2 = __builtin_amdgcn_readlane(cnt, 32), c3 = __builtin_amdgcn_readlane(cnt, 48);
+#pragma unroll 1
+    for (int p = 0; p < 2; ++p) newton_pair(L, RL, H, w0 + 2 * p, p ? c2 : c0, p ? c3 : c1, sml + 4 * FS * p, lane, acc);
   }
   if (lane == 0 && a.counters) {
     SolveCounters* c = counter_slot(a.counters);
-    if (iters_acc) atomicAdd(&c->newton_iters, iters_acc);
-    if (roots_acc) atomicAdd(&c->roots_found, roots_acc);
-    if (fb_acc) atomicAdd(&c->fallback, fb_acc);
+    if (acc.iters) atomicAdd(&c->newton_iters, acc.iters);
+    if (acc.roots) atomicAdd(&c->roots_found, acc.roots);
+    if (acc.fb) atomicAdd(&c->fallback, acc.fb);
   }
 }
 
@@ -529,7 +609,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // registers (the degree-64 coefficient as a scalar), then Newton from 4H
 // starts (the 2H network seeds and 2H evenly spaced phases; all evenly spaced
 // without network), stepped on the Cayley polynomial and merged one root per
-// pass as in k_newton_sturm2, with the same stop rule.
+// pass as in k_newton_sturm4, with the same stop rule.
 __host__ __device__ inline size_t learn_lds_bytes(int H) {
   const int D = 6 * H - 2;
   return (size_t)(2 * (D + 2)) * sizeof(double);   // f and its reversal
@@ -659,37 +739,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 // Root counts of a record chunk (diagnostic of the count the learned and
 // uniform solvers trust): per pair, the Sturm count of the Cayley polynomial
-// f by the device code k_newton_sturm2 / k_newton_sturm use (-1 when the
-// chain fails its test, -2 for an inactive pair), and the number of real
+// f by the device code the Newton kernels use (sturm_count_rows4, four pairs
+// per wavefront, for H <= 10; sturm_count_line_reg for H = 11), -1 when the
+// chain fails its test, -2 for an inactive pair; and the number of real
 // eigenvalues the companion QR (run before this kernel) marked in M_REAL_LO /
-// M_REAL_HI (-1 when the QR did not converge).  Two pairs per wavefront for
-// H <= 10 (the packed chains of k_newton_sturm2), one for H = 11.
+// M_REAL_HI (-1 when the QR did not converge).
 __global__ __launch_bounds__(64) void k_root_counts(const double* rec, int H, int64_t np, int* sturm, int* real) {
   const int lane = threadIdx.x & 63;
   const int D = 6 * H - 2;
   const RecLayout RL(H);
-  const bool two = D < 64;
-  const int64_t per = two ? 2 : 1;
+  const bool four = D < 64;
+  const int64_t per = four ? 4 : 1;
   for (int64_t w0 = per * (int64_t)blockIdx.x; w0 < np; w0 += per * (int64_t)gridDim.x) {
-    int cnt[2] = {-2, -2};
-    const double* RA = rec + w0 * (int64_t)RL.stride;
-    const bool hasB = two && w0 + 1 < np;
-    const double* RB = hasB ? RA + RL.stride : RA;
-    if (two) {
-      const double fA = lane <= D ? RA[RL.f + lane] : 0.0;
-      const double fB = lane <= D ? RB[RL.f + lane] : 0.0;
-      sturm_count_line_reg2(fA, fB, D, lane, cnt[0], cnt[1]);
+    int cnt;
+    if (four) {
+      const int row = lane >> 4, l = lane & 15;
+      const bool in = w0 + row < np;
+      const double* f = rec + (w0 + (in ? row : 0)) * (int64_t)RL.stride + RL.f;
+      double G[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) G[r] = (in && 16 * r + l <= D) ? f[16 * r + l] : 0.0;
+      cnt = sturm_count_rows4(G, in ? f[D] : 0.0, D, lane);
+      cnt = __builtin_amdgcn_readlane(cnt, 0) * (lane == 0) + __builtin_amdgcn_readlane(cnt, 16) * (lane == 1) +
+            __builtin_amdgcn_readlane(cnt, 32) * (lane == 2) + __builtin_amdgcn_readlane(cnt, 48) * (lane == 3);
     } else {
-      const double gv = lane <= D ? RA[RL.f + lane] : 0.0;
-      cnt[0] = sturm_count_line_reg(gv, RA[RL.f + D], D, lane);
+      const double* RA = rec + w0 * (int64_t)RL.stride;
+      const double gv = RA[RL.f + lane];
+      cnt = sturm_count_line_reg(gv, RA[RL.f + D], D, lane);
     }
     if (lane < per && w0 + lane < np) {
-      const double* Rq = lane ? RB : RA;
+      const double* Rq = rec + (w0 + lane) * (int64_t)RL.stride;
       const int st = (int)Rq[RL.meta + M_STATUS];
       const bool act = st != ST_BAD_LC && st != ST_CONSTANT;
       const unsigned lo = (unsigned)Rq[RL.meta + M_REAL_LO], hi = (unsigned)Rq[RL.meta + M_REAL_HI];
       const int nreal = __popcll(((unsigned long long)hi << 32) | lo);
-      sturm[w0 + lane] = act ? (lane ? cnt[1] : cnt[0]) : -2;
+      sturm[w0 + lane] = act ? cnt : -2;
       real[w0 + lane] = act ? (st == ST_NO_CONVERGE ? -1 : nreal) : -2;
     }
   }
@@ -701,14 +785,14 @@ hipError_t launch_root_counts(const double* rec, int H, int64_t np, int* sturm, 
   return hipGetLastError();
 }
 
-bool newton_two_per_wave(int H) { return 6 * H - 2 < 64; }
+bool newton_four_per_wave(int H) { return 6 * H - 2 < 64; }
 
 // `done` (nullable): an event the launch itself records at the kernel's end
 // (no marker packet of its own on the stream).
 hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st, hipEvent_t done) {
-  if (newton_two_per_wave(a.H)) {
-    const size_t lds = (size_t)4 * (6 * a.H) * sizeof(double);   // 4 x (D + 2)
-    hipExtLaunchKernelGGL(k_newton_sturm2, dim3((unsigned)waves), dim3(64), lds, st, nullptr, done, 0, a, L);
+  if (newton_four_per_wave(a.H)) {
+    const size_t lds = (size_t)8 * (6 * a.H) * sizeof(double);   // 8 x (D + 2): f and its reversal, four pairs
+    hipExtLaunchKernelGGL(k_newton_sturm4, dim3((unsigned)waves), dim3(64), lds, st, nullptr, done, 0, a, L);
   } else {
     hipExtLaunchKernelGGL(k_newton_sturm, dim3((unsigned)waves), dim3(64), learn_lds_bytes(a.H), st, nullptr, done, 0,
                           a, L);
