@@ -265,6 +265,24 @@ int ftp_solve_sums(ftp_plan* plan, const double* sums, const double* lc_stats, d
                    void* stream);
 
 /*
+ * ftp_solve_sums without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, outputs and errors as ftp_solve_sums, on a
+ * plan created beforehand (ftp_plan_create allocates; this call does not).
+ * Solvers: plain, uniform and Aberth; FTP_E_OPTION for the learned solver
+ * (its network buffers are the plan's) and for a bands plan.
+ * Scratch: a fixed 64 MiB device array inside the library, one per GPU, held
+ * until the process ends; frequencies are processed in chunks that fit it, so
+ * n_f is not limited by it (FTP_E_SIZE only if one frequency's record would not
+ * fit).  Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams, or host threads without ordering) race and must not
+ * be made.  No statistics are kept and FTP_FLAG_TIME_STAGES is ignored.
+ */
+int ftp_solve_sums_noalloc(ftp_plan* plan, const double* sums, const double* lc_stats, double df, int64_t n_f,
+                           double* power, double* phase, double* amp, double* offset, uint8_t* status,
+                           void* stream);
+
+/*
  * Root counts of the per-frequency phase polynomials (a check of the count
  * the learned and uniform solvers rely on), from given sums in the layout
  * ftp_nfft_sums writes (device `sums`; t_ref, ybar, YY on the host in

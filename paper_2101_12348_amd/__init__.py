@@ -35,7 +35,7 @@ EXPORTED = [
     "ftp_mlp_loss_grad", "ftp_mlp_train_step", "ftp_learned_dataset",
     "ftp_plan_get_tuning", "ftp_plan_set_tuning", "ftp_autotune", "ftp_plan_tune_key",
     "ftp_tune_cache_lookup", "ftp_tune_cache_store", "ftp_periodogram_multiband",
-    "ftp_plan_create_bands", "ftp_periodogram_shared_phase", "ftp_root_counts",
+    "ftp_plan_create_bands", "ftp_periodogram_shared_phase", "ftp_root_counts", "ftp_solve_sums_noalloc",
 ]
 
 FTP_TUNE_FORCE = 1
@@ -92,6 +92,7 @@ def load_library(path: Optional[str] = None):
     lib.ftp_nfft_sums.argtypes = [vp, vp, vp, vp, i64, dbl, i64, vp, vp, vp]
     lib.ftp_solve_sums.argtypes = [vp, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp]
     lib.ftp_root_counts.argtypes = [vp, vp, vp, dbl, i64, vp, vp, vp]
+    lib.ftp_solve_sums_noalloc.argtypes = [vp, vp, vp, dbl, i64, vp, vp, vp, vp, vp, vp]
     lib.ftp_plan_load_mlp.argtypes = [vp, vp, i64, ip]
     lib.ftp_last_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
     lib.ftp_mlp_create.argtypes = [ctypes.POINTER(vp), ip, ip, ip, vp, ctypes.c_uint64]
@@ -264,6 +265,24 @@ class Plan:
                                        float(df), int(n_f), _ptr(out["power"]), _ptr(out["phase"]),
                                        _ptr(out["amp"]), _ptr(out["offset"]), _ptr(out["status"]),
                                        _stream_ptr(stream)))
+        return out
+
+    def solve_sums_noalloc(self, sums, tref: float, ybar: float, yy: float, df: float, out, stream=None):
+        """ftp_solve_sums_noalloc: as solve_sums, into caller-allocated outputs
+        (dict as alloc_outputs makes); sums complex128 or (n_f, 3H, 2) float64
+        on the device."""
+        import numpy as np
+        torch = _torch()
+        if sums.is_complex():
+            sums = torch.view_as_real(sums)
+        if sums.dtype != torch.float64 or not sums.is_contiguous() or sums.shape[1] != 3 * self.H:
+            raise ValueError("sums must be contiguous float64 (n_f, 3H, 2) on the device")
+        n_f = sums.shape[0]
+        stats = np.array([tref, ybar, yy], dtype=np.float64)
+        _check(self.lib.ftp_solve_sums_noalloc(self.handle, _ptr(sums), stats.ctypes.data_as(ctypes.c_void_p),
+                                               float(df), int(n_f), _ptr(out["power"]), _ptr(out["phase"]),
+                                               _ptr(out["amp"]), _ptr(out["offset"]), _ptr(out["status"]),
+                                               _stream_ptr(stream)))
         return out
 
     def root_counts(self, sums, tref: float, ybar: float, yy: float, df: float, device="cuda", stream=None):

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1397,6 +1398,116 @@ int ftp_solve_sums(ftp_plan* P, const double* sums, const double* lc_stats, doub
   a.offset = offset;
   a.status = status;
   if ((rc = run_solve(P, a, n_f, st))) return rc;
+  P->last.n_pairs += (uint64_t)n_f;
+  return FTP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- entry point without allocation
+// ftp_solve_sums_noalloc keeps all of its scratch (the lightcurve table, the
+// work counters, the per-pair records and work lists) in this array: one copy
+// per GPU, held by the loaded code object until the process ends.  In host
+// code the name is a host-side stand-in, not a device address; each GPU's
+// address is looked up once (hipGetSymbolAddress with that GPU current) and
+// only that address is passed to kernels.
+namespace {
+
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+constexpr size_t kNoAllocHead = 4096;   // lightcurve table (1 KB), offsets, counters
+constexpr int kNoAllocDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocDevices] = {};
+
+// Address of this GPU's scratch (looked up on the first call per device).
+int noalloc_scratch(int device, unsigned char** out) {
+  if (device < 0 || device >= kNoAllocDevices) return FTP_E_OPTION;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) HIP_TRY(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+      g_last_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return FTP_E_HIP;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[device]);
+  return FTP_OK;
+}
+
+// The one-lightcurve table of a solve from given sums, written on the device
+// (no host staging): every field zero except n_f, df, t_ref, ybar, YY.
+__global__ void k_noalloc_tables(LcInfo* lc, int64_t* freq_off, int64_t n_f, double df, double tref, double ybar,
+                                 double yy) {
+  if (threadIdx.x != 0) return;
+  LcInfo L{};
+  L.n_f = n_f;
+  L.df = df;
+  L.tref = tref;
+  L.ybar = ybar;
+  L.yy = yy;
+  L.inv_sqrt_yy = 1.0 / sqrt(yy);
+  *lc = L;
+  freq_off[0] = 0;
+  freq_off[1] = n_f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ftp_solve_sums_noalloc(ftp_plan* P, const double* sums, const double* lc_stats, double df, int64_t n_f,
+                           double* power, double* phase, double* amp, double* offset, uint8_t* status,
+                           void* stream) {
+  if (!P || !sums || !lc_stats || !power || !phase || !amp || !offset) return FTP_E_NULL;
+  if (!(std::isfinite(df) && df > 0.0)) return FTP_E_DF;
+  if (n_f < 1) return FTP_E_NF;
+  if (!(lc_stats[2] > 0.0) || !std::isfinite(lc_stats[0]) || !std::isfinite(lc_stats[1]) ||
+      !std::isfinite(lc_stats[2]))
+    return FTP_E_OPTION;
+  if (P->n_band || P->opt.solver == FTP_SOLVER_LEARNED) return FTP_E_OPTION;
+  const RecLayout RL(P->H);
+  const size_t per_pair = sizeof(double) * (size_t)RL.stride + 2 * sizeof(int64_t);
+  const int64_t cap = (int64_t)((kNoAllocBytes - kNoAllocHead) / per_pair);
+  if (cap < 1) return FTP_E_SIZE;
+  unsigned char* base = nullptr;
+  int rc;
+  if ((rc = noalloc_scratch(P->device, &base))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t chunk = std::min<int64_t>(n_f, cap);
+  LcInfo* d_lc = reinterpret_cast<LcInfo*>(base);
+  int64_t* d_foff = reinterpret_cast<int64_t*>(base + 1024);
+  SolveBufs B{};
+  B.ctr = reinterpret_cast<unsigned*>(base + 2048);
+  B.rec = reinterpret_cast<double*>(base + kNoAllocHead);
+  B.fb_list = reinterpret_cast<int64_t*>(base + kNoAllocHead + sizeof(double) * (size_t)RL.stride * chunk);
+  B.fb2_list = B.fb_list + chunk;
+  B.chunk = chunk;
+  B.counters = nullptr;
+  B.timing = false;
+  hipLaunchKernelGGL(k_noalloc_tables, dim3(1), dim3(64), 0, st, d_lc, d_foff, n_f, df, lc_stats[0], lc_stats[1],
+                     lc_stats[2]);
+  HIP_TRY(hipGetLastError());
+  SolveArgs a = base_args(P, 1, n_f);
+  a.lcs = d_lc;
+  a.freq_off = d_foff;
+  a.grids = nullptr;
+  a.sums_in = sums;
+  a.mm_tau = 1e-14;
+  a.power = power;
+  a.phase = phase;
+  a.amp = amp;
+  a.offset = offset;
+  a.status = status;
+  if ((rc = run_solve_with(P, a, n_f, B, st))) return rc;
   P->last.n_pairs += (uint64_t)n_f;
   return FTP_OK;
 }
