@@ -350,7 +350,7 @@ SINGLE_WORKLOADS = {
 # Newton + Sturm kernel; the one-frequency k_newton_sturm serves H = 11)
 KERNEL_NAMES = {"plain_qr": "k_qr (companion QR, FP64 vector)",
                 "fallback_qr": "k_qr on the Aberth tier's leftovers (FP64 vector)",
-                "newton_sturm": "k_newton_sturm2 (FP64 vector)",
+                "newton_sturm": "k_newton_sturm4 (FP64 vector)",
                 "aberth": "k_aberth_split (FP64 vector)",
                 "mlp_forward": "k_features2 + network (MFMA bf16)",
                 "spread": "k_spread (HBM)", "fft": "k_fft_pass (HBM)"}
@@ -476,6 +476,29 @@ def bench_single(args, workload: str):
     ms_pos, _ = run_solver(F, pv, t, y, s, lc, out_pos, args.steps, args.warmup)
     _, out_p, ms_plain, st_plain = runs["plain"]
     value = pairs / (ms_step * 1e-3)
+    # what the network gains over evenly spaced starts at an equal number of
+    # Newton starts per frequency (2H): frequencies left unconfirmed by the
+    # Sturm count after the first round
+    gain = {}
+    for name, sv, fl in (("network_seeds", F.FTP_SOLVER_LEARNED, F.FTP_FLAG_SEEDS_ALL | F.FTP_FLAG_2H_STARTS),
+                         ("evenly_spaced", F.FTP_SOLVER_UNIFORM, F.FTP_FLAG_2H_STARTS)):
+        pg = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=sv, flags=fl)
+        if sv == F.FTP_SOLVER_LEARNED:
+            pg.load_mlp(w, meta["width"])
+        pg.set_tuning(**plan.tuning())
+        pg.stats()
+        pg.periodogram(t, y, s, lc.df, lc.n_f)
+        sg = pg.stats()
+        gain[name] = {"unconfirmed_rate": sg["n_fallback"] / pairs, "to_aberth_rate": sg["n_fallback_aberth"] / pairs}
+        pg.close()
+    gain["starts_per_frequency"] = 2 * H
+    # the network's seeds in every frequency's first round (2H seeds + evenly
+    # spaced starts), instead of only in the second round
+    pa = F.Plan(tmpl.c, tmpl.s, precision=F.FTP_FP32_SUMS, solver=F.FTP_SOLVER_LEARNED, flags=F.FTP_FLAG_SEEDS_ALL)
+    pa.load_mlp(w, meta["width"])
+    pa.set_tuning(**plan.tuning())
+    ms_all, st_all = run_solver(F, pa, t, y, s, lc, pa.alloc_outputs(lc.n_f, dev), args.steps, args.warmup)
+    pa.close()
 
     # end to end from host memory: inputs copied to the device, one periodogram,
     # outputs copied back (PCIe included; not the reported value)
@@ -500,7 +523,9 @@ def bench_single(args, workload: str):
     gate = None
     cpu = None
     variants = {"positive_amplitude": {"value": lc.n_f / (ms_pos * 1e-3), "ms_per_step": ms_pos,
-                                       "solver": args.solver}}
+                                       "solver": args.solver},
+                "seeds_in_every_first_round": {"value": lc.n_f / (ms_all * 1e-3), "ms_per_step": ms_all,
+                                               "unconfirmed_rate": st_all["n_fallback"] / pairs}}
     if not args.no_cpu_baseline:
         n_sample = args.cpu_sample or W["cpu_sample"]
         js = np.unique(np.r_[np.linspace(1, lc.n_f, n_sample).astype(np.int64), jbest, near])
@@ -514,7 +539,7 @@ def bench_single(args, workload: str):
                     top2_gap_oracle=float(srt[0] - srt[1]),
                     pass_=bool(np.max(dP) <= 1e-4 and (jmax_ref == jbest or tie)))
         from oracle import ftp_oracle as O
-        jv = js[:: max(1, len(js) // 96)]
+        jv = js[:: max(1, len(js) // 32)]
         rv = O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, freq_index=jv, positive_amplitude=True,
                            block=W["oracle_block"])
         variants["positive_amplitude"]["max_abs_dP_vs_oracle"] = float(
@@ -544,8 +569,10 @@ def bench_single(args, workload: str):
         # two multiply-adds per coefficient per remainder, ~2 D^2 per pair
         fl_verify = st["newton_iters"] * (4.0 * D + 20.0) + pairs * 2.0 * D * D
         if args.solver == "learned":
-            stages["mlp_forward"] = stage(st["ms_mlp"], mlp_flops(meta["d_in"], meta["width"], meta["d_out"]) * pairs,
-                                          "mfma", BF16_PEAK_TFLOPS)
+            # the network runs on the frequencies the first Newton round left
+            rows = st["n_fallback"]
+            stages["mlp_forward"] = stage(st["ms_mlp"], mlp_flops(meta["d_in"], meta["width"], meta["d_out"]) * rows,
+                                          "mfma", BF16_PEAK_TFLOPS, rows=rows)
         if args.solver != "aberth":
             stages["newton_sturm"] = stage(st["ms_verify"], fl_verify, "alu", FP64_PEAK_TFLOPS,
                                            flops_per_unit=fl_verify / pairs, units=pairs)
@@ -561,7 +588,9 @@ def bench_single(args, workload: str):
         solvers[name] = {"value": pairs / (ms * 1e-3), "ms_per_step": ms, "ms_per_step_stage_events": ms_staged[name],
                          "launch_shapes": pl_.tuning(),
                          "max_abs_dP_vs_plain": float(torch.max(torch.abs(o["power"] - out_p["power"]))),
-                         "unconfirmed_rate": stn["n_fallback"] / pairs, "companion_rate": stn["n_fallback_qr"] / pairs,
+                         "unconfirmed_rate": stn["n_fallback"] / pairs,
+                         "to_aberth_rate": stn["n_fallback_aberth"] / pairs,
+                         "companion_rate": stn["n_fallback_qr"] / pairs, "ms_retry": stn["ms_retry"],
                          "newton_iters_per_pair": stn["newton_iters"] / pairs,
                          "ms_nfft": stn["ms_nfft"], "ms_roots": stn["ms_roots"], "ms_mlp": stn["ms_mlp"],
                          "ms_verify": stn["ms_verify"], "ms_aberth": stn["ms_aberth"],
@@ -569,7 +598,7 @@ def bench_single(args, workload: str):
     d = stages[dom]
     traffic = d.get("traffic")
     if traffic is None and dom in ("newton_sturm", "aberth", "plain_qr"):
-        kname = {"newton_sturm": "k_newton_sturm2", "aberth": "k_aberth_split", "plain_qr": "k_qr"}[dom]
+        kname = {"newton_sturm": "k_newton_sturm4", "aberth": "k_aberth_split", "plain_qr": "k_qr"}[dom]
         traffic = measured_traffic(kname, W["model"])
     line = {
         "metric": "trial-freq x lightcurve pairs/sec at |dP|<=1e-4 vs FP64 oracle; learned vs plain root solve",
@@ -593,6 +622,7 @@ def bench_single(args, workload: str):
         "solvers": solvers,
         "speedup_vs_plain": ms_plain / ms_step,
         "speedup_vs_uniform": (runs["uniform"][2] / ms_step) if "uniform" in runs else None,
+        "network_gain_equal_starts": gain,
         "end_to_end_host": e2e,
         "variants": variants,
         "cpu_baseline": cpu,

@@ -73,10 +73,15 @@ extern "C" {
 
 /* root solver */
 #define FTP_SOLVER_PLAIN 0     /* companion-matrix eigenvalues (Section 2) */
-#define FTP_SOLVER_LEARNED 1   /* 2H MLP seeds + evenly spaced starts (min(32, 6H - 2) starts in
-                                  all for H <= 10, 4H for H = 11), Newton, Sturm check; unconfirmed
-                                  frequencies go to Aberth, then the companion solve */
-#define FTP_SOLVER_UNIFORM 2   /* as LEARNED with evenly spaced starts only (ablation: no network) */
+#define FTP_SOLVER_LEARNED 1   /* per frequency a Sturm count of the real-phase roots, then Newton
+                                  from evenly spaced starts (min(32, 6H - 2) for H <= 10, 4H for
+                                  H = 11); the frequencies whose roots do not reach the count get a
+                                  second Newton round from the network's 2H seeds plus evenly spaced
+                                  starts (with FTP_FLAG_SEEDS_ALL the seeds enter every frequency's
+                                  first round); what is still unconfirmed goes to Aberth, then to
+                                  the companion solve */
+#define FTP_SOLVER_UNIFORM 2   /* as LEARNED without the network (ablation): the second round starts
+                                  from evenly spaced phases only */
 #define FTP_SOLVER_ABERTH 3    /* Aberth-Ehrlich iteration on every frequency; companion solve
                                   where it does not converge */
 
@@ -85,6 +90,12 @@ extern "C" {
                                        the companion solve */
 #define FTP_FLAG_TIME_STAGES 2u     /* record HIP events around the NFFT and per-frequency stages
                                        (read back by ftp_last_stats) */
+#define FTP_FLAG_SEEDS_ALL 16u      /* learned solver: network seeds in every frequency's first
+                                       Newton round (2H seeds + evenly spaced starts), not only in
+                                       the second round of the frequencies the first left */
+#define FTP_FLAG_2H_STARTS 32u      /* learned / uniform (H <= 10): the first Newton round starts from
+                                       2H phases only (with FTP_FLAG_SEEDS_ALL the network's seeds,
+                                       else evenly spaced), for comparing the two at equal starts */
 #define FTP_FLAG_POSITIVE_AMP 8u    /* fit constrained to theta_1 > 0 (Section 2.1): the best
                                        candidate with YM > 0 (P = YM^2/(YY MM) vanishes on YM = 0,
                                        so the constrained maximum is one of the same stationary
@@ -120,6 +131,9 @@ typedef struct {
   double ms_fallback;      /* learned / uniform / Aberth: companion solve of what is left (ms) */
   double ms_spread;        /* of the NFFT stage: the spreading kernel (ms) */
   double ms_fft;           /* of the NFFT stage: the FFT passes (ms) */
+  double ms_retry;         /* learned / uniform: the second Newton round (ms) */
+  uint64_t n_fallback_aberth;   /* learned / uniform: frequencies the second Newton round
+                                   left to the Aberth tier */
 } ftp_stats;
 
 /* Launch shapes of the per-frequency kernels, in wavefronts per compute

@@ -23,6 +23,8 @@ FTP_SOLVER_ABERTH = 3
 FTP_FLAG_FORCE_FALLBACK = 1
 FTP_FLAG_TIME_STAGES = 2
 FTP_FLAG_POSITIVE_AMP = 8
+FTP_FLAG_SEEDS_ALL = 16
+FTP_FLAG_2H_STARTS = 32
 MAX_H = 11
 
 ST_OK, ST_DEGENERATE, ST_CONSTANT, ST_NO_CONVERGE, ST_BAD_LC, ST_FALLBACK, ST_FALLBACK_QR = 0, 1, 2, 3, 4, 8, 16
@@ -53,7 +55,7 @@ class Stats(ctypes.Structure):
                 ("aberth_iters", ctypes.c_uint64), ("ms_nfft", ctypes.c_double), ("ms_solve", ctypes.c_double),
                 ("ms_roots", ctypes.c_double), ("ms_mlp", ctypes.c_double), ("ms_verify", ctypes.c_double),
                 ("ms_aberth", ctypes.c_double), ("ms_fallback", ctypes.c_double), ("ms_spread", ctypes.c_double),
-                ("ms_fft", ctypes.c_double)]
+                ("ms_fft", ctypes.c_double), ("ms_retry", ctypes.c_double), ("n_fallback_aberth", ctypes.c_uint64)]
 
 
 class Tuning(ctypes.Structure):

@@ -19,24 +19,11 @@
 // of psi onto the unit circle (Section 2, after Eq. finalpoly); a conjugate pair gives the same
 // phase twice.
 #include "ftp_solve_common.h"
+#include "ftp_args.h"
 
 namespace ftp {
 
 constexpr int kAberthMaxIt = 60;
-
-struct AberthArgs {
-  double* rec;
-  int64_t np;
-  const int64_t* list;       // pairs to solve; nullptr = every pair of the chunk
-  const unsigned* count;     // length of `list`
-  int64_t* qr_list;          // pairs left to the companion-matrix solve
-  unsigned* qr_count;
-  SolveCounters* counters;
-  int H;
-  double mark;               // M_FALLBACK value written for pairs sent on
-  unsigned flags;            // bit 0: send every pair on (companion solve only)
-  unsigned* queue;           // work counter (zeroed), or nullptr for grid striding
-};
 
 __host__ __device__ inline size_t aberth_lds_bytes(int H) {
   const int D = 6 * H - 2;

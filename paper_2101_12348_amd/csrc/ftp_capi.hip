@@ -21,6 +21,7 @@
 #include "../../include/ftp.h"
 #include "ftp_internal.h"
 #include "ftp_solve_common.h"
+#include "ftp_args.h"
 
 namespace ftp {
 // kernels (defined in the other translation units)
@@ -73,47 +74,18 @@ hipError_t launch_chamfer(const float* out, int64_t B, int Kseeds, const float* 
 hipError_t launch_adam(float* w, uint16_t* wb, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, float c1, float c2, hipStream_t st);
 hipError_t launch_f32_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t st);
-hipError_t launch_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx, int waves, hipStream_t st);
+hipError_t launch_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx, int waves, hipStream_t st,
+                           const int64_t* list = nullptr, const unsigned* list_count = nullptr);
+hipError_t launch_newton_retry(const RetryArgs& A, int waves, hipStream_t st);
 hipError_t launch_labels(const double* rec, int H, int64_t np, float* roots, int* nroots, int Rmax, int waves,
                          hipStream_t st);
-struct LearnArgs {
-  double* rec;
-  int64_t np;
-  const float* seeds_out;
-  int64_t* fb_list;
-  unsigned int* fb_count;
-  unsigned flags;
-  unsigned* queue;
-};
 hipError_t launch_root_counts(const double* rec, int H, int64_t np, int* sturm, int* real, int waves,
                               hipStream_t st);
 hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st,
                                hipEvent_t done = nullptr);
-struct AberthArgs {
-  double* rec;
-  int64_t np;
-  const int64_t* list;
-  const unsigned* count;
-  int64_t* qr_list;
-  unsigned* qr_count;
-  SolveCounters* counters;
-  int H;
-  double mark;
-  unsigned flags;
-  unsigned* queue;
-};
 hipError_t launch_aberth(const AberthArgs& A, int waves, hipStream_t st);
-struct FusedMlpArgs {
-  const uint16_t* X;
-  int64_t np;
-  const uint16_t* wi;
-  const float* w32;
-  int64_t oWi[4], ob[4];
-  int kp[4], nout[4];
-  float* out;
-};
 bool mlp_fused_ok(const int* nin, const int* nout);
-hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st);
+hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st, int max_blocks = 0);
 hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st, unsigned* p2 = nullptr);
 hipError_t launch_lc_chi2(const LcInfo* lcs, int64_t n_lc, double* out, hipStream_t st);
 hipError_t launch_mb_combine(const double* bp, int64_t n_band, int64_t n_f, const double* chi2, double* power,
@@ -412,7 +384,7 @@ struct ftp_plan {
   // work lists: Newton -> Aberth (fb_list, count work_ctr[0]) and
   // Aberth -> companion solve (fb2_list, count work_ctr[1]); work_ctr[2..4]
   // are the queue counters of the Newton, Aberth and QR kernels
-  DevBuf xfeat, seeds, fb_list, fb2_list, work_ctr;
+  DevBuf xfeat, seeds, fb_list, fb2_list, rt_list, work_ctr;
   // launch shapes (waves per compute unit), set by ftp_plan_set_tuning or
   // ftp_autotune
   ftp_tuning tune{32, 32, 16, 16, 32, 0};
@@ -747,8 +719,9 @@ int64_t grid_waves(const ftp_plan* P, int wpc, int64_t np) {
 struct SolveBufs {
   double* rec;
   unsigned* ctr;
-  int64_t* fb_list;
-  int64_t* fb2_list;
+  int64_t* fb_list;          // first Newton round -> second round
+  int64_t* fb2_list;         // Aberth tier -> companion solve
+  int64_t* rt_list;          // second Newton round -> Aberth tier
   int64_t chunk;
   SolveCounters* counters;   // statistics copies (nullptr: none kept)
   bool timing;               // stage events (FTP_FLAG_TIME_STAGES)
@@ -765,6 +738,7 @@ int solve_bufs_plan(ftp_plan* P, int64_t n_pairs, SolveBufs* B) {
   if (solver != FTP_SOLVER_PLAIN) {
     if ((rc = P->fb_list.ensure(sizeof(int64_t) * chunk))) return rc;
     if ((rc = P->fb2_list.ensure(sizeof(int64_t) * chunk))) return rc;
+    if ((rc = P->rt_list.ensure(sizeof(int64_t) * chunk))) return rc;
     if (solver == FTP_SOLVER_LEARNED) {
       if ((rc = P->xfeat.ensure(sizeof(uint16_t) * chunk * P->net.din))) return rc;
       if ((rc = P->seeds.ensure(sizeof(float) * chunk * P->net.dout))) return rc;
@@ -775,6 +749,7 @@ int solve_bufs_plan(ftp_plan* P, int64_t n_pairs, SolveBufs* B) {
   B->ctr = P->work_ctr.as<unsigned>();
   B->fb_list = P->fb_list.as<int64_t>();
   B->fb2_list = P->fb2_list.as<int64_t>();
+  B->rt_list = P->rt_list.as<int64_t>();
   B->chunk = chunk;
   B->counters = P->counters.as<SolveCounters>();
   B->timing = (P->opt.flags & FTP_FLAG_TIME_STAGES) != 0;
@@ -836,11 +811,12 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
       HIP_TRY(launch_qr(P->H, rec, RL.stride, np, nullptr, nullptr, B.counters, ctr + 4, w_qr,
                         st));
     } else {
-      const float* seeds = nullptr;
-      if (solver == FTP_SOLVER_LEARNED) {
+      // the network's seeds: for every pair's first round (FTP_FLAG_SEEDS_ALL),
+      // else for the pairs the first round leaves (list and its device count)
+      auto run_network = [&](const int64_t* list, const unsigned* count) -> int {
         MlpNet& N = P->net;
         if (fused) {
-          HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), dinp, w_asm, st));
+          HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), dinp, w_asm, st, list, count));
           FusedMlpArgs fa{};
           fa.X = P->xfeat.as<uint16_t>();
           fa.np = np;
@@ -853,14 +829,23 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
             fa.nout[l] = N.nout[l];
           }
           fa.out = P->seeds.as<float>();
-          HIP_TRY(launch_mlp_fused(fa, st));
-        } else if (N.dense) {
-          HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), dinp, w_asm, st));
-          if ((rc = mlp_forward_dense(&N, P->xfeat.as<uint16_t>(), dinp, np, P->seeds.as<float>(), st))) return rc;
-        } else {
-          HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), N.din, w_asm, st));
-          if ((rc = mlp_forward(&N, P->xfeat.as<uint16_t>(), np, P->seeds.as<float>(), st))) return rc;
+          fa.np_dev = count;
+          HIP_TRY(launch_mlp_fused(fa, st, 2 * P->n_cu));
+          return FTP_OK;
         }
+        // (the layer-by-layer forms run over all np rows; rows past the list
+        // hold stale features and their outputs are not read)
+        if (N.dense) {
+          HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), dinp, w_asm, st, list, count));
+          return mlp_forward_dense(&N, P->xfeat.as<uint16_t>(), dinp, np, P->seeds.as<float>(), st);
+        }
+        HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), N.din, w_asm, st, list, count));
+        return mlp_forward(&N, P->xfeat.as<uint16_t>(), np, P->seeds.as<float>(), st);
+      };
+      const bool seeds_all = solver == FTP_SOLVER_LEARNED && (P->opt.flags & FTP_FLAG_SEEDS_ALL);
+      const float* seeds = nullptr;
+      if (seeds_all) {
+        if ((rc = run_network(nullptr, nullptr))) return rc;
         seeds = P->seeds.as<float>();
       }
       hipEvent_t ra = learn_ev();
@@ -872,7 +857,7 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
         L.seeds_out = seeds;
         L.fb_list = B.fb_list;
         L.fb_count = ctr;
-        L.flags = (P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u;
+        L.flags = ((P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u) | ((P->opt.flags & FTP_FLAG_2H_STARTS) ? 2u : 0u);
         L.queue = nullptr;   // uniform work per pair: grid striding (a queue costs more than it balances)
         // with the side stream, the Newton launch and the side scoring launch
         // record the fork and join events themselves
@@ -888,11 +873,33 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
       }
       hipEvent_t rb = learn_ev();
       if (rb) HIP_TRY(hipEventRecord(rb, st));
+      // second Newton round on what the first left: the network's seeds for
+      // the learned solver (unless every pair had them already), evenly spaced
+      // starts otherwise; what it leaves goes to the Aberth tier
+      if (solver != FTP_SOLVER_ABERTH && solver == FTP_SOLVER_LEARNED && !seeds_all) {
+        if ((rc = run_network(B.fb_list, ctr))) return rc;
+      }
+      hipEvent_t rr = learn_ev();
+      if (rr) HIP_TRY(hipEventRecord(rr, st));
+      if (solver != FTP_SOLVER_ABERTH) {
+        RetryArgs RA{};
+        RA.rec = rec;
+        RA.H = P->H;
+        RA.list = B.fb_list;
+        RA.count = ctr;
+        RA.seeds = (solver == FTP_SOLVER_LEARNED && !seeds_all) ? P->seeds.as<float>() : nullptr;
+        RA.out_list = B.rt_list;
+        RA.out_count = ctr + 5;
+        RA.counters = B.counters;
+        HIP_TRY(launch_newton_retry(RA, (int)grid_waves(P, 16, np), st));
+      }
+      hipEvent_t rt = learn_ev();
+      if (rt) HIP_TRY(hipEventRecord(rt, st));
       AberthArgs A{};
       A.rec = rec;
       A.np = np;
-      A.list = solver == FTP_SOLVER_ABERTH ? nullptr : B.fb_list;
-      A.count = ctr;
+      A.list = solver == FTP_SOLVER_ABERTH ? nullptr : B.rt_list;
+      A.count = ctr + 5;
       A.qr_list = B.fb2_list;
       A.qr_count = ctr + 1;
       A.counters = B.counters;
@@ -1223,7 +1230,7 @@ int ftp_plan_destroy(ftp_plan* P) {
                     &P->pw, &P->py, &P->tile_count, &P->tile_off, &P->cursor,
                     &P->block_sums, &P->total, &P->bucket, &P->grids,
                     &P->counters, &P->stats_out, &P->rec, &P->stat_part, &P->stat_ticket, &P->xfeat, &P->seeds, &P->fb_list,
-                    &P->fb2_list, &P->work_ctr, &P->tune_out, &P->mb_out, &P->mb_chi2};
+                    &P->fb2_list, &P->rt_list, &P->work_ctr, &P->tune_out, &P->mb_out, &P->mb_chi2};
   P->net.release();
   for (DevBuf* b : bufs) b->release();
   if (P->upload_done) (void)hipEventDestroy(P->upload_done);
@@ -1475,7 +1482,7 @@ int ftp_solve_sums_noalloc(ftp_plan* P, const double* sums, const double* lc_sta
     return FTP_E_OPTION;
   if (P->n_band || P->opt.solver == FTP_SOLVER_LEARNED) return FTP_E_OPTION;
   const RecLayout RL(P->H);
-  const size_t per_pair = sizeof(double) * (size_t)RL.stride + 2 * sizeof(int64_t);
+  const size_t per_pair = sizeof(double) * (size_t)RL.stride + 3 * sizeof(int64_t);
   const int64_t cap = (int64_t)((kNoAllocBytes - kNoAllocHead) / per_pair);
   if (cap < 1) return FTP_E_SIZE;
   unsigned char* base = nullptr;
@@ -1490,6 +1497,7 @@ int ftp_solve_sums_noalloc(ftp_plan* P, const double* sums, const double* lc_sta
   B.rec = reinterpret_cast<double*>(base + kNoAllocHead);
   B.fb_list = reinterpret_cast<int64_t*>(base + kNoAllocHead + sizeof(double) * (size_t)RL.stride * chunk);
   B.fb2_list = B.fb_list + chunk;
+  B.rt_list = B.fb2_list + chunk;
   B.chunk = chunk;
   B.counters = nullptr;
   B.timing = false;
@@ -1883,6 +1891,7 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
     c.qr_sweeps += x.qr_sweeps;
     c.aberth_iters += x.aberth_iters;
     c.fallback_qr += x.fallback_qr;
+    c.fallback_aberth += x.fallback_aberth;
   }
   *out = P->last;
   out->ms_nfft = 0.0;
@@ -1895,22 +1904,28 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
     out->ms_nfft += a;
     out->ms_solve += b;
   }
-  out->ms_mlp = out->ms_verify = out->ms_aberth = out->ms_fallback = 0.0;
+  out->ms_mlp = out->ms_verify = out->ms_retry = out->ms_aberth = out->ms_fallback = 0.0;
   // per chunk: root events (start, end); learned-stage events (after the
   // network, after Newton + Sturm, after Aberth) when the solver has them
   for (int k = 0; k + 2 <= P->evr_used; k += 2) {
     float a = 0.f;
     HIP_TRY(hipEventElapsedTime(&a, P->evr[k], P->evr[k + 1]));
     out->ms_roots += a;
-    const int l = 3 * (k / 2);
-    if (l + 3 <= P->evl_used) {
-      float m = 0.f, v = 0.f, b = 0.f, f = 0.f;
+    // learned / uniform / Aberth: after the network on every pair, after
+    // the first Newton round, after the network on its list, after the
+    // second round, after the Aberth tier
+    const int l = 5 * (k / 2);
+    if (l + 5 <= P->evl_used) {
+      float m = 0.f, v = 0.f, m2 = 0.f, r = 0.f, b = 0.f, f = 0.f;
       HIP_TRY(hipEventElapsedTime(&m, P->evr[k], P->evl[l]));
       HIP_TRY(hipEventElapsedTime(&v, P->evl[l], P->evl[l + 1]));
-      HIP_TRY(hipEventElapsedTime(&b, P->evl[l + 1], P->evl[l + 2]));
-      HIP_TRY(hipEventElapsedTime(&f, P->evl[l + 2], P->evr[k + 1]));
-      out->ms_mlp += m;
+      HIP_TRY(hipEventElapsedTime(&m2, P->evl[l + 1], P->evl[l + 2]));
+      HIP_TRY(hipEventElapsedTime(&r, P->evl[l + 2], P->evl[l + 3]));
+      HIP_TRY(hipEventElapsedTime(&b, P->evl[l + 3], P->evl[l + 4]));
+      HIP_TRY(hipEventElapsedTime(&f, P->evl[l + 4], P->evr[k + 1]));
+      out->ms_mlp += m + m2;
       out->ms_verify += v;
+      out->ms_retry += r;
       out->ms_aberth += b;
       out->ms_fallback += f;
     }
@@ -1925,6 +1940,7 @@ int ftp_last_stats(ftp_plan* P, ftp_stats* out, void* stream) {
   }
   out->n_fallback = c.fallback;
   out->n_fallback_qr = c.fallback_qr;
+  out->n_fallback_aberth = c.fallback_aberth;
   out->aberth_iters = c.aberth_iters;
   out->qr_sweeps = c.qr_sweeps;
   out->newton_iters = c.newton_iters;

@@ -96,6 +96,7 @@ struct SolveCounters {
   unsigned long long qr_sweeps;
   unsigned long long aberth_iters;   // Aberth sweeps summed over solved pairs
   unsigned long long fallback_qr;    // pairs left to the companion solve after Aberth
+  unsigned long long fallback_aberth;   // pairs the second Newton round left to the Aberth tier
 };
 
 }  // namespace ftp

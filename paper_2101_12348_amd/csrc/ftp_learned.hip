@@ -25,6 +25,7 @@
 // carried as a scalar; see sturm_begin).
 #include <hip/hip_ext.h>
 #include "ftp_solve_common.h"
+#include "ftp_args.h"
 
 namespace ftp {
 
@@ -325,16 +326,6 @@ __device__ __forceinline__ int sturm_count_rows4(const double (&G)[4], double gt
   return ok ? D - 2 * S.vp : -1;
 }
 
-struct LearnArgs {
-  double* rec;
-  int64_t np;
-  const float* seeds_out;   // network output, np x 4H (u, v pairs); nullptr = uniform seeds
-  int64_t* fb_list;
-  unsigned int* fb_count;
-  unsigned flags;
-  unsigned* queue;          // work counter (zeroed), or nullptr for grid striding
-};
-
 // Newton on R(theta) carried out on the Cayley polynomial.  With x = tan((theta
 // - phi0) / 2), f(x) = (1 + x^2)^K R(theta), so R'/R = ((1 + x^2) f'/f - 2 K x)
 // / 2 and the Newton step of R in theta is d = 2 f / ((1 + x^2) f' - 2 K x f).
@@ -440,7 +431,9 @@ struct NewtonAcc {
 __device__ __forceinline__ void newton_pair(const LearnArgs& L, const RecLayout& RL, int H, int64_t wA, int cA, int cB,
                                             const double* fb, int lane, NewtonAcc& acc) {
   const int half = lane >> 5, hl = lane & 31;
-  const int K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = D < 32 ? D : 32;
+  // starts per frequency: every lane of the half (at most D), or only 2H
+  // (flag bit 1: the equal-starts comparison of seeds and evenly spaced phases)
+  const int K = 3 * H - 1, D = 2 * K, S = 2 * H, NS = (L.flags & 2u) ? S : (D < 32 ? D : 32);
   const int FS = D + 2;
   const unsigned long long lo32 = 0xffffffffull;
   const unsigned long long hmask = half ? ~lo32 : lo32;
@@ -536,6 +529,7 @@ __device__ __forceinline__ void newton_pair(const LearnArgs& L, const RecLayout&
   if (cnt != -2 && ((um >> lane) & 1ull)) cand[__popcll(um & hmask & below)] = thw;
   if (cnt != -2 && !ok && hl == 0) {
     Rh[RL.meta + M_WARM] = (double)nu;
+    Rh[RL.meta + M_COUNT] = (double)cnt;
     Rh[RL.meta + M_FALLBACK] = 1.0;
     const unsigned slot = atomicAdd(L.fb_count, 1u);
     L.fb_list[slot] = wh;
@@ -568,7 +562,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       if (l == 0 && ((act >> row) & 1)) {
         const unsigned slot = atomicAdd(L.fb_count, 1u);
         L.fb_list[slot] = w0 + row;
-        L.rec[(w0 + row) * (int64_t)RL.stride + RL.meta + M_FALLBACK] = 1.0;
+        double* Rr = L.rec + (w0 + row) * (int64_t)RL.stride;
+        Rr[RL.meta + M_FALLBACK] = 1.0;
+        Rr[RL.meta + M_WARM] = 0.0;
+        Rr[RL.meta + M_COUNT] = -1.0;
       }
       acc.fb += (unsigned long long)__popc((unsigned)act);
       continue;
@@ -632,6 +629,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const unsigned slot = atomicAdd(L.fb_count, 1u);
         L.fb_list[slot] = w;
         R[RL.meta + M_FALLBACK] = 1.0;
+        R[RL.meta + M_WARM] = 0.0;
+        R[RL.meta + M_COUNT] = -1.0;
       }
       ++fb_acc;
       continue;
@@ -721,6 +720,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       if (uniq) R[RL.cand + __popcll(um & below)] = thw;
       if (lane == 0) {
         R[RL.meta + M_WARM] = (double)nu;
+        R[RL.meta + M_COUNT] = (double)cnt;
         R[RL.meta + M_FALLBACK] = 1.0;
         const unsigned slot = atomicAdd(L.fb_count, 1u);
         L.fb_list[slot] = w;
@@ -782,6 +782,134 @@ __global__ __launch_bounds__(64) void k_root_counts(const double* rec, int H, in
 hipError_t launch_root_counts(const double* rec, int H, int64_t np, int* sturm, int* real, int waves,
                               hipStream_t st) {
   hipLaunchKernelGGL(k_root_counts, dim3((unsigned)waves), dim3(64), 0, st, rec, H, np, sturm, real);
+  return hipGetLastError();
+}
+
+// Second Newton round (project addition) for the frequencies the first left
+// unconfirmed: one frequency per wavefront.  Lanes 0..nu - 1 hold the nu
+// distinct roots the first round found (converged, not stepped); lanes
+// nu..63 start from new phases: the network's 2H seeds first when the
+// learned solver supplies them (row i of `seeds` for list entry i), then
+// evenly spaced phases offset from the first round's grid.  Newton steps, the
+// merge of converged roots and the stop rule are those of the first round,
+// against the Sturm count it kept in M_COUNT; a frequency that reaches its
+// count is settled (its roots become the candidates), the others go on to
+// the Aberth tier through out_list with the roots found as its warm start.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_retry(RetryArgs A) {
+  extern __shared__ double sml[];
+  const int lane = threadIdx.x & 63;
+  const int H = A.H, K = 3 * H - 1, D = 2 * K, S = 2 * H;
+  const int FS = D + 2;
+  const RecLayout RL(H);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int64_t n = (int64_t)*A.count;
+  unsigned long long iters_acc = 0, left_acc = 0;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int64_t w = A.list[i];
+    double* R = A.rec + w * (int64_t)RL.stride;
+    const int cnt = (int)R[RL.meta + M_COUNT];
+    if (cnt < 2) {   // no trusted count (or a forced fallback): straight on
+      if (lane == 0) {
+        const unsigned slot = atomicAdd(A.out_count, 1u);
+        A.out_list[slot] = w;
+      }
+      ++left_acc;
+      continue;
+    }
+    for (int c = lane; c <= D; c += 64) {
+      const double fc = R[RL.f + c];
+      sml[c] = fc;
+      sml[FS + D - c] = fc;
+    }
+    const int nu0 = (int)R[RL.meta + M_WARM];
+    const double phi0 = R[RL.meta + M_PHI0];
+    lwave_sync();
+    double u = 0.0;
+    int sg = 1;
+    bool conv = false, live = false;
+    int its = 0;
+    {
+      double bc = 1.0, bs = 0.0, ang;
+      const int k = lane - nu0, nst = 64 - nu0;
+      if (lane < nu0) {
+        ang = R[RL.cand + lane] - phi0;   // a root the first round found
+        conv = true;
+      } else if (A.seeds && k < S) {
+        const float* o = A.seeds + i * 2 * S;
+        bc = (double)o[2 * k];
+        bs = (double)o[2 * k + 1];
+        ang = -(R[RL.meta + M_CANON] + phi0);
+        live = true;
+      } else {
+        const int kk = A.seeds ? k - S : k, nn = A.seeds ? nst - S : nst;
+        ang = (kk + 0.25) * (kTwoPi / nn) - phi0;
+        live = true;
+      }
+      double s1, c1;
+      sincos_small(ang, s1, c1);
+      u_from_dir(fma(bc, c1, -bs * s1), fma(bc, s1, bs * c1), u, sg);
+    }
+    bool done = false;
+    unsigned long long um = 0ull, merged = 0ull, U = 0ull;
+    for (int it = 1; it <= 12 && !done; ++it) {
+      if (live && !conv) {
+        bool ok;
+        const double sc = newton_u_step(sg > 0 ? sml : sml + FS, D, K, u, sg, ok);
+        if (!ok) {
+          live = false;
+        } else {
+          ++its;
+          if (fabs(sc) < 1e-12) conv = true;
+        }
+      }
+      const unsigned long long cm = __ballot(conv);
+      if (__popcll(cm) < cnt && it < 12) continue;
+      const double key = sg > 0 ? u : copysign(2.0, u) - u;
+      for (unsigned long long pend = cm & ~merged; pend;) {
+        const int jj = __builtin_ctzll(pend);
+        const double kj = lrdlane(key, jj), uj = lrdlane(u, jj);
+        const double tol = 0.5e-8 * fma(uj, uj, 1.0);
+        const unsigned long long bit = 1ull << jj;
+        const unsigned long long same = __ballot(fabs(key - kj) < tol) & cm;
+        const unsigned long long upto = (bit << 1) - 1ull;
+        U &= upto | ~same;
+        U = (same & (bit - 1ull)) ? (U & ~bit) : (U | bit);
+        pend &= ~(same | bit);
+      }
+      merged = cm;
+      um = U;
+      if (__popcll(um) == cnt) done = true;
+    }
+    iters_acc += (unsigned long long)wave_sum((double)its);
+    const double thw = theta_from_u(phi0, u, sg);
+    const int nu = __popcll(um);
+    const bool uniq = (um >> lane) & 1ull;
+    lwave_sync();
+    if (done) {
+      double* cand = R + RL.cand;
+      for (int c = lane; c < D; c += 64) cand[c] = __longlong_as_double(0x7ff8000000000000ll);
+      lwave_sync();
+      if (uniq) cand[__popcll(um & below)] = thw;
+    } else {
+      if (uniq) R[RL.cand + __popcll(um & below)] = thw;
+      if (lane == 0) {
+        R[RL.meta + M_WARM] = (double)nu;
+        const unsigned slot = atomicAdd(A.out_count, 1u);
+        A.out_list[slot] = w;
+      }
+      ++left_acc;
+    }
+    lwave_sync();
+  }
+  if (lane == 0 && A.counters) {
+    SolveCounters* c = counter_slot(A.counters);
+    if (iters_acc) atomicAdd(&c->newton_iters, iters_acc);
+    if (left_acc) atomicAdd(&c->fallback_aberth, left_acc);
+  }
+}
+
+hipError_t launch_newton_retry(const RetryArgs& A, int waves, hipStream_t st) {
+  hipLaunchKernelGGL(k_newton_retry, dim3((unsigned)waves), dim3(64), learn_lds_bytes(A.H), st, A);
   return hipGetLastError();
 }
 

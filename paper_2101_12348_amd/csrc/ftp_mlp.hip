@@ -10,6 +10,7 @@
 // scaled to max |p_k| = 1, as (Re, Im) pairs: d_in = 2 (D + 1).
 // Output: 2H (u, v) pairs; seed k is atan2(v_k, u_k) in the canonical frame.
 #include "ftp_solve_common.h"
+#include "ftp_args.h"
 
 namespace ftp {
 
@@ -334,14 +335,17 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(const float* x, uint16_t* y
 // Network features of pairs [0, np) of a record chunk (one wavefront per
 // pair), written to X (row stride ldx >= 2 (D + 1), the rest of the row
 // zeroed); the canonical rotation goes to the record for the Newton kernel.
-__global__ __launch_bounds__(64) void k_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx) {
+__global__ __launch_bounds__(64) void k_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx,
+                                                  const int64_t* list, const unsigned* list_count) {
   const RecLayout RL(H);
   const int D = RL.D;
   const int lane = threadIdx.x & 63;
-  for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
+  if (list) np = (int64_t)*list_count;
+  for (int64_t i = blockIdx.x; i < np; i += gridDim.x) {
+    const int64_t w = list ? list[i] : i;
     double* R = rec + w * (int64_t)RL.stride;
     const int st = (int)R[RL.meta + M_STATUS];
-    uint16_t* x = X + w * ldx;
+    uint16_t* x = X + i * ldx;
     for (int q = 2 * (D + 1) + lane; q < ldx; q += 64) x[q] = 0;
     if (st == ST_BAD_LC || st == ST_CONSTANT) {
       for (int q = lane; q < 2 * (D + 1); q += 64) x[q] = 0;
@@ -357,13 +361,16 @@ __global__ __launch_bounds__(64) void k_features(double* rec, int H, int64_t np,
 // scale from a per-half maximum.  Every lane runs the arithmetic (the per-half
 // reduction needs the whole wavefront); rejected or constant pairs then write
 // zeros instead.
-__global__ __launch_bounds__(64) void k_features2(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx) {
+__global__ __launch_bounds__(64) void k_features2(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx,
+                                                   const int64_t* list, const unsigned* list_count) {
   const RecLayout RL(H);
   const int D = RL.D, K = RL.K;
   const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
+  if (list) np = (int64_t)*list_count;
   for (int64_t w0 = 2 * (int64_t)blockIdx.x; w0 < np; w0 += 2 * (int64_t)gridDim.x) {
     const bool has = w0 + half < np;
-    const int64_t w = has ? w0 + half : w0;
+    const int64_t row = has ? w0 + half : w0;   // row of X
+    const int64_t w = list ? list[row] : row;   // pair of the chunk
     double* R = rec + w * (int64_t)RL.stride;
     const int st = (int)R[RL.meta + M_STATUS];
     const bool zero = st == ST_BAD_LC || st == ST_CONSTANT;
@@ -400,7 +407,7 @@ __global__ __launch_bounds__(64) void k_features2(double* rec, int H, int64_t np
     if (has) {
       // (Re, Im) of coefficient k as one 32-bit store; the padding of the row
       // (ldx and 2 (D + 1) even) likewise
-      unsigned* x = reinterpret_cast<unsigned*>(X + w * ldx);
+      unsigned* x = reinterpret_cast<unsigned*>(X + row * ldx);
       for (int64_t q = (D + 1) + hl; q < ldx / 2; q += 32) x[q] = 0u;
       for (int s = 0; s < 2; ++s) {
         const int k = hl + 32 * s;
@@ -429,15 +436,6 @@ __global__ __launch_bounds__(64) void k_features2(double* rec, int H, int64_t np
 // bf16 rounding as k_dense_bf16, so the result equals the unfused launches
 // bit for bit.  Requirements (checked on the host): width a multiple of 32 up
 // to 256, kp[0] up to 256, d_out up to 64.
-struct FusedMlpArgs {
-  const uint16_t* X;     // np x kp[0] bf16 features (zero padded)
-  int64_t np;
-  const uint16_t* wi;    // padded bf16 weights, layer l at wi + oWi[l], rows of kp[l]
-  const float* w32;      // FP32 parameters (biases at w32 + ob[l])
-  int64_t oWi[4], ob[4];
-  int kp[4], nout[4];
-  float* out;            // np x nout[3]
-};
 
 constexpr int kFRows = 128;          // pairs per workgroup
 constexpr int kFRT = kFRows / 16;    // row tiles
@@ -447,7 +445,14 @@ constexpr int kOutLd = 64 + 4;       // LDS row of one pair's outputs (FP32, d_o
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_fused(FusedMlpArgs a) {
   __shared__ __align__(16) uint16_t act[kFRows * kActLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * kFRows;
+  if (a.np_dev) {
+    const int64_t n = (int64_t)*a.np_dev;
+    if (n < a.np) a.np = n;
+  }
+  // tiles of 128 pairs, strided over the grid (the same for every thread of
+  // the workgroup, so the barriers below are reached by all or none)
+  for (int64_t row0 = (int64_t)blockIdx.x * kFRows; row0 < a.np; row0 += (int64_t)gridDim.x * kFRows) {
+  __syncthreads();   // the previous tile's outputs have been copied out of the LDS
   // features of the 128 pairs (rows of X, stride kp[0]; zero rows past the end)
   {
     const int c8 = a.kp[0] / 8;
@@ -555,6 +560,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
     }
   }
+  }
 }
 
 // Training labels: the real roots found by the companion solve, in the
@@ -632,19 +638,26 @@ bool mlp_fused_ok(const int* nin, const int* nout) {
   return nin[1] == nout[0] && nin[2] == nout[1] && nin[3] == nout[2];
 }
 
-hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st) {
+// grid: at most max_blocks workgroups (two fit a compute unit), each taking
+// every max_blocks-th tile of 128 pairs
+hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st, int max_blocks) {
   if (fa.np <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((fa.np + kFRows - 1) / kFRows);
-  hipLaunchKernelGGL(k_mlp_fused, dim3(blocks), dim3(256), 0, st, fa);
+  int64_t blocks = (fa.np + kFRows - 1) / kFRows;
+  if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
+  hipLaunchKernelGGL(k_mlp_fused, dim3((unsigned)blocks), dim3(256), 0, st, fa);
   return hipGetLastError();
 }
 
-hipError_t launch_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx, int waves, hipStream_t st) {
+// Features of pairs [0, np) of the chunk (row i = pair i), or, with a list,
+// of the pairs list[0 .. *list_count) (row i = pair list[i]; np bounds the
+// grid only).
+hipError_t launch_features(double* rec, int H, int64_t np, uint16_t* X, int64_t ldx, int waves, hipStream_t st,
+                           const int64_t* list, const unsigned* list_count) {
   if (6 * H - 2 < 64) {
     const int w2 = (int)std::max<int64_t>(1, std::min<int64_t>(waves, (np + 1) / 2));
-    hipLaunchKernelGGL(k_features2, dim3((unsigned)w2), dim3(64), 0, st, rec, H, np, X, ldx);
+    hipLaunchKernelGGL(k_features2, dim3((unsigned)w2), dim3(64), 0, st, rec, H, np, X, ldx, list, list_count);
   } else {
-    hipLaunchKernelGGL(k_features, dim3((unsigned)waves), dim3(64), 0, st, rec, H, np, X, ldx);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)waves), dim3(64), 0, st, rec, H, np, X, ldx, list, list_count);
   }
   return hipGetLastError();
 }

@@ -65,8 +65,9 @@ enum : int {
   M_REAL_LO = 5,   // bit mask of real companion eigenvalues (low / high 32 lanes)
   M_REAL_HI = 6,
   M_FALLBACK = 7,  // 0: first method; 1: Aberth tier; 2: companion solve after Aberth
-  M_WARM = 8,      // Newton roots left in the candidate slots for the Aberth tier
-  M_SLOTS = 9,
+  M_WARM = 8,      // Newton roots left in the candidate slots for the next tier
+  M_COUNT = 9,     // Sturm count of a frequency the first Newton round left (-1: none)
+  M_SLOTS = 10,
 };
 struct RecLayout {
   int K, D, r, mu, eta, zw, meta, f, cand, stride;

@@ -67,3 +67,34 @@ def test_large_workload_sampled(ftp):
     ref = O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, freq_index=js, block=4)
     assert np.max(np.abs(P[js - 1] - ref["power"])) <= 1e-4
     assert abs(jbest * lc.df - lc.f0) <= 2 * lc.df or abs(jbest * lc.df - 2 * lc.f0) <= 2 * lc.df
+
+
+def test_large_workload_learned_against_oracle(ftp):
+    """The large workload (N_obs = 1e5, H = 10, ~3e5 frequencies) with the
+    learned solver and its H = 10 network: equal to the companion solve
+    everywhere, within the FP32-sum tolerance of the oracle on 40 sampled
+    frequencies, and best frequency equal to the oracle's (stored window
+    around the injected frequency, tests/golden/large_oracle.json)."""
+    import torch
+    path = os.path.join(GOLDEN, "large_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    gold = json.load(open(path))
+    tmpl, lc = large_case()
+    assert gold["n_f"] == lc.n_f
+    w, meta = ftp.load_model("large_h10")
+    assert meta["H"] == 10
+    lrn = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED)
+    lrn.load_mlp(w, meta["width"])
+    b = {k: v.clone() for k, v in lrn.periodogram(lc.t, lc.y, lc.sigma, lc.df, lc.n_f).items()}
+    plain = ftp.Plan(tmpl.c, tmpl.s)
+    a = plain.periodogram(lc.t, lc.y, lc.sigma, lc.df, lc.n_f)
+    assert float(torch.max(torch.abs(a["power"] - b["power"]))) <= 1e-10
+    P = b["power"].cpu().numpy()
+    gi = np.array(gold["indices"])
+    assert np.max(np.abs(P[gi - 1] - np.array(gold["power"]))) <= 1e-4
+    assert int(np.argmax(P)) + 1 == gold["best_index"]
+    rng = np.random.default_rng(9)
+    js = np.unique(rng.integers(1, lc.n_f + 1, 40))
+    ref = O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, freq_index=js, block=4)
+    assert np.max(np.abs(P[js - 1] - ref["power"])) <= 1e-4

@@ -13,7 +13,9 @@ import numpy as np
 import pytest
 
 from oracle import mlp_oracle as MO
-from synthetic import single_long_case, tiny_case
+from oracle import ftp_oracle as O
+from synthetic import (single_long_case, tiny_case, learned_heldout_lightcurves, large_heldout_lightcurves,
+                       large_case)
 
 pytestmark = pytest.mark.gpu
 
@@ -141,7 +143,8 @@ def test_learned_and_uniform_match_companion(ftp, solver):
     elif solver == "aberth":
         p2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_ABERTH)
     else:
-        p2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED)
+        # an untrained network seeding every frequency's first round
+        p2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED, flags=ftp.FTP_FLAG_SEEDS_ALL)
         din, width, dout = 2 * (6 * tmpl.H - 1), 64, 4 * tmpl.H
         w = np.random.default_rng(3).uniform(-0.2, 0.2, ftp.mlp_param_count(din, width, dout)).astype(np.float32)
         p2.load_mlp(w, width)
@@ -161,9 +164,10 @@ def test_learned_and_uniform_match_companion(ftp, solver):
         assert st["n_fallback"] < n_f
         assert int(fb.sum()) == st["n_fallback"]
         assert st["n_fallback_qr"] <= st["n_fallback"]
+        assert st["n_fallback_aberth"] <= st["n_fallback"]
         if solver == "learned":
-            # an untrained network leaves roots unconfirmed: the Aberth tier runs
-            assert st["n_fallback"] > 0 and st["aberth_iters"] > 0
+            # an untrained network leaves roots unconfirmed: the later tiers run
+            assert st["n_fallback"] > 0
     assert torch.equal(a["status"], b["status"] & (0xFF ^ (ftp.ST_FALLBACK | ftp.ST_FALLBACK_QR)))
 
 
@@ -219,3 +223,74 @@ def test_fused_network_kernel_equals_unfused(ftp, width):
         assert torch.equal(a[k], b[k]), k
     for k in ("n_fallback", "newton_iters", "roots_found"):
         assert sa[k] == sb[k], k
+
+
+def _run_stats(plan, lcs):
+    """Periodograms of the lightcurves (power, status per lightcurve) and the
+    plan's statistics summed over them."""
+    import torch
+    plan.stats()
+    outs = []
+    for lc in lcs:
+        o = plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, lc.n_f)
+        outs.append({k: v.clone() for k, v in o.items()})
+    torch.cuda.synchronize()
+    return outs, plan.stats()
+
+
+@pytest.mark.parametrize("model", ["single_long_h6", "large_h10"])
+def test_network_seeds_beat_evenly_spaced_starts_at_equal_count(ftp, model):
+    """What the trained network gains over the method without it: with the
+    same number of Newton starts per frequency (2H), the network's seeds leave
+    fewer frequencies unconfirmed by the Sturm count than evenly spaced starts,
+    on held-out lightcurves (N_obs = 2000 for the H = 6 network, a large-case
+    lightcurve for the H = 10 one); both periodograms equal the companion
+    solve's."""
+    import torch
+    w, meta = ftp.load_model(model)
+    if model == "single_long_h6":
+        tmpl, lcs = learned_heldout_lightcurves(n_lc=8)
+    else:
+        tmpl, lcs = large_heldout_lightcurves(n_lc=1)
+    uni = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_UNIFORM, flags=ftp.FTP_FLAG_2H_STARTS)
+    lrn = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED,
+                   flags=ftp.FTP_FLAG_2H_STARTS | ftp.FTP_FLAG_SEEDS_ALL)
+    lrn.load_mlp(w, meta["width"])
+    ou, su = _run_stats(uni, lcs)
+    ol, sl = _run_stats(lrn, lcs)
+    plain = ftp.Plan(tmpl.c, tmpl.s)
+    op, _ = _run_stats(plain, lcs[:2])
+    for a, b, c in zip(op, ou, ol):
+        assert float(torch.max(torch.abs(a["power"] - b["power"]))) <= 1e-10
+        assert float(torch.max(torch.abs(a["power"] - c["power"]))) <= 1e-10
+    pairs = sum(lc.n_f for lc in lcs)
+    print(f"{model}: unconfirmed with 2H starts: network {sl['n_fallback'] / pairs:.4f}, "
+          f"evenly spaced {su['n_fallback'] / pairs:.4f}")
+    assert sl["n_fallback"] < 0.75 * su["n_fallback"]
+
+
+@pytest.mark.parametrize("flags", [0, 16])
+def test_learned_matches_oracle_on_heldout_lightcurves(ftp, flags):
+    """The learned solver (trained H = 6 network; second-round seeds, or
+    seeds in every first round) on held-out lightcurves (N_obs = 2000,
+    T = 1000 d) against the oracle on sampled frequencies and at the best
+    frequency, and against the companion solve everywhere."""
+    import torch
+    w, meta = ftp.load_model("single_long_h6")
+    tmpl, lcs = learned_heldout_lightcurves(n_lc=3)
+    lrn = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_LEARNED, flags=flags)
+    lrn.load_mlp(w, meta["width"])
+    plain = ftp.Plan(tmpl.c, tmpl.s)
+    rng = np.random.default_rng(41)
+    for lc in lcs:
+        a = {k: v.clone() for k, v in plain.periodogram(lc.t, lc.y, lc.sigma, lc.df, lc.n_f).items()}
+        b = lrn.periodogram(lc.t, lc.y, lc.sigma, lc.df, lc.n_f)
+        assert float(torch.max(torch.abs(a["power"] - b["power"]))) <= 1e-10
+        P = b["power"].cpu().numpy()
+        top = np.argsort(P)[::-1][:5] + 1
+        js = np.unique(np.r_[rng.integers(1, lc.n_f + 1, 30), top])
+        ref = O.periodogram(lc.t, lc.y, lc.sigma, tmpl.c, tmpl.s, lc.df, freq_index=js)
+        assert np.max(np.abs(P[js - 1] - ref["power"])) <= 1e-4
+        srt = np.sort(ref["power"])[::-1]
+        if srt[0] - srt[1] > 1e-4:
+            assert int(js[np.argmax(ref["power"])]) == int(top[0])
