@@ -199,19 +199,6 @@ __device__ __forceinline__ int row_max_int(int h) {
   return h;
 }
 
-// register r of t for a wave-uniform r < NR, by masks (a chain of selects
-// would be turned into an indexed load from a stack copy of t)
-template <int NR>
-__device__ __forceinline__ double pick_reg(const double (&t)[NR], int r) {
-  unsigned long long v = 0;
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    const unsigned long long m = 0ull - (unsigned long long)(r == k);
-    v |= (unsigned long long)__double_as_longlong(t[k]) & m;
-  }
-  return __longlong_as_double((long long)v);
-}
-
 __device__ __forceinline__ void sturm4_begin(const double (&G)[4], double gtop, int D, int l, double (&A)[4],
                                              double (&B)[4], double& bl, double& ab, Rows4State& S, bool& ok) {
   const double ag = fabs(gtop), sgn = gtop > 0.0 ? 1.0 : -1.0;
@@ -243,7 +230,9 @@ __device__ __forceinline__ void sturm4_begin(const double (&G)[4], double gtop, 
 
 // Member q from the last two: A (older, degree db + 1) is overwritten by the
 // new member; B (degree db) is the newer.  db = D - q + 1; NR registers hold
-// every coefficient up to db + 1.
+// every coefficient up to db + 1, so db itself lies in register NR - 1, or in
+// NR - 2 when db + 1 starts register NR - 1 (db % 16 == 15), and db - 1 one
+// register lower still when db % 16 == 0.
 template <int NR>
 __device__ __forceinline__ void sturm4_step(double (&A)[4], const double (&B)[4], double& bl, double& ab,
                                             Rows4State& S, int db, int l, int pbase) {
@@ -255,15 +244,30 @@ __device__ __forceinline__ void sturm4_step(double (&A)[4], const double (&B)[4]
     t[r] = fma(-ab, l == 0 ? below : rot, A[r]);
     below = rot;
   }
-  const int rq = db >> 4, lq = db & 15;
-  const double q0 = bperm_d(pbase + (lq << 2), pick_reg<NR>(t, rq)) * bl;
+  const int lq = db & 15;
+  const bool top = lq != 15;                          // db in register NR - 1 (else NR - 2)
+  const double tq = NR == 1 ? t[0] : (top ? t[NR - 1] : t[NR > 1 ? NR - 2 : 0]);
+  const double q0 = bperm_d(pbase + (lq << 2), tq) * bl;
+  // remainder: coefficients below db (the rest are zeroed)
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const double v = fma(-q0, B[r], t[r]);
-    t[r] = (r < rq || (r == rq && l < lq)) ? v : 0.0;
+    if (r < NR - 2) {
+      t[r] = v;
+    } else if (r == NR - 2) {
+      t[r] = (top || l < lq) ? v : 0.0;
+    } else {
+      t[r] = (top && l < lq) ? v : 0.0;
+    }
   }
-  const int rl = (db - 1) >> 4, ll = (db - 1) & 15;
-  const double lead = bperm_d(pbase + (ll << 2), pick_reg<NR>(t, rl));
+  // the new leading coefficient, index db - 1
+  const int ll = (db - 1) & 15;
+  const int rl = (db - 1) >> 4, rtop = (db + 1) >> 4;   // rtop = NR - 1
+  const int drop = rtop - rl;                              // 0, 1 or 2 registers below the top
+  double tl = t[NR - 1];
+  if (NR > 1) tl = drop == 1 ? t[NR > 1 ? NR - 2 : 0] : tl;
+  if (NR > 2) tl = drop == 2 ? t[NR > 2 ? NR - 3 : 0] : tl;
+  const double lead = bperm_d(pbase + (ll << 2), tl);
   int h = 0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) h = max(h, hiword(t[r]) & 0x7fffffff);
