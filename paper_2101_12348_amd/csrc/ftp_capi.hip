@@ -85,7 +85,7 @@ hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves
                                hipEvent_t done = nullptr);
 hipError_t launch_aberth(const AberthArgs& A, int waves, hipStream_t st);
 bool mlp_fused_ok(const int* nin, const int* nout);
-hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st, int max_blocks = 0);
+hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st, int max_blocks = 0, hipEvent_t done = nullptr);
 hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t st, unsigned* p2 = nullptr);
 hipError_t launch_lc_chi2(const LcInfo* lcs, int64_t n_lc, double* out, hipStream_t st);
 hipError_t launch_mb_combine(const double* bp, int64_t n_band, int64_t n_f, const double* chi2, double* power,
@@ -813,7 +813,8 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
     } else {
       // the network's seeds: for every pair's first round (FTP_FLAG_SEEDS_ALL),
       // else for the pairs the first round leaves (list and its device count)
-      auto run_network = [&](const int64_t* list, const unsigned* count) -> int {
+      // done (nullable): an event recorded once the seeds are written
+      auto run_network = [&](const int64_t* list, const unsigned* count, hipEvent_t done) -> int {
         MlpNet& N = P->net;
         if (fused) {
           HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), dinp, w_asm, st, list, count));
@@ -830,22 +831,27 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
           }
           fa.out = P->seeds.as<float>();
           fa.np_dev = count;
-          HIP_TRY(launch_mlp_fused(fa, st, 2 * P->n_cu));
+          HIP_TRY(launch_mlp_fused(fa, st, 2 * P->n_cu, done));
           return FTP_OK;
         }
         // (the layer-by-layer forms run over all np rows; rows past the list
         // hold stale features and their outputs are not read)
+        int r2;
         if (N.dense) {
           HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), dinp, w_asm, st, list, count));
-          return mlp_forward_dense(&N, P->xfeat.as<uint16_t>(), dinp, np, P->seeds.as<float>(), st);
+          r2 = mlp_forward_dense(&N, P->xfeat.as<uint16_t>(), dinp, np, P->seeds.as<float>(), st);
+        } else {
+          HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), N.din, w_asm, st, list, count));
+          r2 = mlp_forward(&N, P->xfeat.as<uint16_t>(), np, P->seeds.as<float>(), st);
         }
-        HIP_TRY(launch_features(rec, P->H, np, P->xfeat.as<uint16_t>(), N.din, w_asm, st, list, count));
-        return mlp_forward(&N, P->xfeat.as<uint16_t>(), np, P->seeds.as<float>(), st);
+        if (!r2 && done) HIP_TRY(hipEventRecord(done, st));
+        return r2;
       };
       const bool seeds_all = solver == FTP_SOLVER_LEARNED && (P->opt.flags & FTP_FLAG_SEEDS_ALL);
+      const bool net_list = solver == FTP_SOLVER_LEARNED && !seeds_all;
       const float* seeds = nullptr;
       if (seeds_all) {
-        if ((rc = run_network(nullptr, nullptr))) return rc;
+        if ((rc = run_network(nullptr, nullptr, nullptr))) return rc;
         seeds = P->seeds.as<float>();
       }
       hipEvent_t ra = learn_ev();
@@ -859,25 +865,27 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
         L.fb_count = ctr;
         L.flags = ((P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u) | ((P->opt.flags & FTP_FLAG_2H_STARTS) ? 2u : 0u);
         L.queue = nullptr;   // uniform work per pair: grid striding (a queue costs more than it balances)
-        // with the side stream, the Newton launch and the side scoring launch
-        // record the fork and join events themselves
-        HIP_TRY(launch_newton_sturm(a, L, w_nt, st, overlap_score ? P->fork_ev : nullptr));
-        if (overlap_score) {
-          // the Newton-root pairs are final now: score them on the side
-          // stream while the fallback tiers run on this one
-          SolveArgs as = a;
-          as.newton_cands = true;
-          HIP_TRY(hipStreamWaitEvent(P->side, P->fork_ev, 0));
-          HIP_TRY(launch_score2(as, rec, p0, np, w_sc, P->side, P->join_ev));
-        }
+        // with the side stream, the last launch before the fork and the side
+        // scoring launch record the fork and join events themselves: the
+        // network on the first round's list (learned solver) runs before the
+        // fork, so that its workgroups are not queued behind the scoring's
+        HIP_TRY(launch_newton_sturm(a, L, w_nt, st, (overlap_score && !net_list) ? P->fork_ev : nullptr));
       }
       hipEvent_t rb = learn_ev();
       if (rb) HIP_TRY(hipEventRecord(rb, st));
       // second Newton round on what the first left: the network's seeds for
       // the learned solver (unless every pair had them already), evenly spaced
       // starts otherwise; what it leaves goes to the Aberth tier
-      if (solver != FTP_SOLVER_ABERTH && solver == FTP_SOLVER_LEARNED && !seeds_all) {
-        if ((rc = run_network(B.fb_list, ctr))) return rc;
+      if (net_list) {
+        if ((rc = run_network(B.fb_list, ctr, overlap_score ? P->fork_ev : nullptr))) return rc;
+      }
+      if (solver != FTP_SOLVER_ABERTH && overlap_score) {
+        // the Newton-root pairs are final now: score them on the side stream
+        // while the later tiers run on this one
+        SolveArgs as = a;
+        as.newton_cands = true;
+        HIP_TRY(hipStreamWaitEvent(P->side, P->fork_ev, 0));
+        HIP_TRY(launch_score2(as, rec, p0, np, w_sc, P->side, P->join_ev));
       }
       hipEvent_t rr = learn_ev();
       if (rr) HIP_TRY(hipEventRecord(rr, st));

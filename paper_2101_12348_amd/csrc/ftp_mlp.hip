@@ -9,6 +9,7 @@
 // positive, where p(e^{i theta}) = -i e^{i K theta} sum_d r_d e^{i d theta}) and
 // scaled to max |p_k| = 1, as (Re, Im) pairs: d_in = 2 (D + 1).
 // Output: 2H (u, v) pairs; seed k is atan2(v_k, u_k) in the canonical frame.
+#include <hip/hip_ext.h>
 #include "ftp_solve_common.h"
 #include "ftp_args.h"
 
@@ -640,11 +641,12 @@ bool mlp_fused_ok(const int* nin, const int* nout) {
 
 // grid: at most max_blocks workgroups (two fit a compute unit), each taking
 // every max_blocks-th tile of 128 pairs
-hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st, int max_blocks) {
-  if (fa.np <= 0) return hipSuccess;
+// `done` (nullable): an event the launch records at the kernel's end.
+hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st, int max_blocks, hipEvent_t done) {
+  if (fa.np <= 0) return done ? hipEventRecord(done, st) : hipSuccess;
   int64_t blocks = (fa.np + kFRows - 1) / kFRows;
   if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
-  hipLaunchKernelGGL(k_mlp_fused, dim3((unsigned)blocks), dim3(256), 0, st, fa);
+  hipExtLaunchKernelGGL(k_mlp_fused, dim3((unsigned)blocks), dim3(256), 0, st, nullptr, done, 0, fa);
   return hipGetLastError();
 }
 
