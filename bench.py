@@ -356,20 +356,24 @@ KERNEL_NAMES = {"plain_qr": "k_qr (companion QR, FP64 vector)",
                 "spread": "k_spread (HBM)", "fft": "k_fft_pass (HBM)"}
 
 
-def nfft_bytes(H: int, n_f: int, n_obs: int, R: float = 2.0):
+def nfft_bytes(H: int, n_f: int, n_obs: int, span: float, R: float = 2.0, msp: int = 7):
     """Algorithmic HBM bytes of the spreading kernel and of the FFT passes
-    (FP32 path): the grids are 8 B complex cells, the w grid of length
-    >= R (2 H n_f + 1) and the y grid >= R (H n_f + 1), each rounded up to a
-    power of two.  Spreading writes every cell of both grids once and reads
-    two 16-byte point records per observation; each FFT pass reads and
-    writes every cell once."""
+    (FP32 path).  The grids hold 8-byte complex cells: the w grid has length
+    >= R (2 H n_f + 1) and the y grid >= R (H n_f + 1), each a power of two.
+    The observations cover a fraction span = df (t_max - t_min) of each
+    grid's period (1 / oversampling), so spreading writes only the cells
+    within span n + 2 msp of the reference time, in whole 2048-cell tiles, and
+    reads two 16-byte point records per observation; the first FFT pass reads
+    those cells (the others are known zeros) and writes the whole grid, each
+    later pass reads and writes the whole grid."""
     import math
     n_w = 1 << max(12, math.ceil(math.log2(R * (2 * H * n_f + 1))))
     n_y = 1 << max(12, math.ceil(math.log2(R * (H * n_f + 1))))
     last = 12   # cells of the final in-LDS pass (log2), earlier passes 9 (FP32)
     passes = lambda n: 1 + max(0, math.ceil((int(math.log2(n)) - last) / 9))
-    spread = 8 * (n_w + n_y) + 32 * n_obs
-    fft = 16 * (n_w * passes(n_w) + n_y * passes(n_y))
+    touched = lambda n: min(n, 2048 * (math.ceil((span * n + 2 * msp) / 2048) + 1))
+    spread = 8 * (touched(n_w) + touched(n_y)) + 32 * n_obs
+    fft = sum(8 * (touched(n) + n) + 16 * n * (passes(n) - 1) for n in (n_w, n_y))
     return spread, fft, n_w, n_y
 
 
@@ -556,7 +560,7 @@ def bench_single(args, workload: str):
         return dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, ms=ms,
                     bytes_per_launch=nbytes, **kw)
 
-    sp_bytes, fft_bytes, n_w, n_y = nfft_bytes(H, lc.n_f, len(lc.t))
+    sp_bytes, fft_bytes, n_w, n_y = nfft_bytes(H, lc.n_f, len(lc.t), lc.df * float(np.max(lc.t) - np.min(lc.t)))
     stages = {"plain_qr": stage(st_plain["ms_roots"], qr_flops(H) * pairs, "alu", FP64_PEAK_TFLOPS,
                                 flops_per_unit=qr_flops(H), units=pairs),
               "spread": hbm_stage(st["ms_spread"], sp_bytes, grid_cells=[n_w, n_y],

@@ -44,7 +44,7 @@ __global__ void k_spread(const LcInfo*, int64_t, const int64_t*, const PointRec<
                          const int64_t*, const int*, typename Cplx<R>::T*);
 template <typename R>
 __global__ void k_fft_pass(const FftGridPass*, int64_t, const int64_t*, const typename Cplx<R>::T*,
-                           typename Cplx<R>::T*);
+                           typename Cplx<R>::T*, const int64_t*);
 hipError_t launch_qr(int H, double* rec, int stride, int64_t np, const int64_t* list, const unsigned* list_count,
                      SolveCounters* counters, unsigned* queue, int waves, hipStream_t st);
 hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64_t p0, int64_t np, int waves,
@@ -588,7 +588,7 @@ int run_nfft(ftp_plan* P, int64_t n_lc, int64_t n_pts, int64_t n_grid, int64_t n
     hipLaunchKernelGGL(k_fft_pass<R>, dim3((unsigned)P->fft_round_items[r]), dim3(256),
                        sizeof(C) << P->fft_round_el[r], st,
                        P->d_fft + P->fft_round_tab_off[r], P->fft_round_n[r], P->d_items + item_base, tw,
-                       P->grids.as<C>());
+                       P->grids.as<C>(), P->tile_off.as<int64_t>());
     item_base += P->fft_round_n[r] + 1;
   }
   hipEvent_t s2 = next_nfft_event(P);
@@ -621,6 +621,7 @@ void build_fft_tables(ftp_plan* P) {
         FftGridPass fp{};
         fp.grid_off = L.grid_off[g];
         fp.item_begin = it;
+        fp.tile_base = r == 0 ? L.tile_base[g] : -1;
         fp.log2n = L.log2n[g];
         fp.lp = L.lp[g][r];
         int consumed = 0;

@@ -9,6 +9,7 @@ namespace ftp {
 
 constexpr int kMaxH = 11;             // D = 6H - 2 <= 64
 constexpr int kTileCells = 2048;      // spreading tile (cells per workgroup)
+constexpr int kTileShift = 11;        // log2(kTileCells)
 constexpr int kFixedShift = 60;       // fixed-point scale 2^60 for exact accumulation
 constexpr int kMaxPasses = 4;
 constexpr int kTwiddleN = 4096;       // size of the in-LDS twiddle table (w_4096^r)
@@ -82,6 +83,9 @@ template <> struct Cplx<double> { using T = double2; };
 struct FftGridPass {
   int64_t grid_off;        // element offset of the grid
   int64_t item_begin;      // first work item of this grid in the launch
+  int64_t tile_base;       // first pass of the grid: global index of its first spreading tile
+                           // (tiles that received no point were not written and read as zero);
+                           // later passes: -1
   int log2n, lp, ls, lcols;  // log2 of size, pass size, stride, columns per item
 };
 

@@ -537,9 +537,12 @@ __global__ __launch_bounds__(256) void k_spread(const LcInfo* __restrict__ lcs, 
   const int cell0 = (int)(tile - L.tile_base[g]) * kTileCells;
   const int msp = L.msp;
   const R beta = (R)L.beta[g];
+  const int64_t e0 = tile_off[tile], e1 = tile_off[tile + 1];
+  // a tile no point reaches is not written: the first FFT pass reads it as
+  // zero (with df T = 1/oversample most of each grid is such tiles)
+  if (e1 == e0) return;
   for (int c = threadIdx.x; c < 2 * kTileCells; c += 256) acc[c] = 0ull;
   __syncthreads();
-  const int64_t e0 = tile_off[tile], e1 = tile_off[tile + 1];
   const int64_t work = (e1 - e0) * (2 * msp);
   const double scale = (double)(1ull << kFixedShift);
   for (int64_t wi = threadIdx.x; wi < work; wi += 256) {
@@ -583,7 +586,8 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_fft_pass(const FftGridPass* __restrict__ passes, int64_t n_grids,
                                                   const int64_t* __restrict__ item_begin,
                                                   const typename Cplx<R>::T* __restrict__ twiddle,
-                                                  typename Cplx<R>::T* __restrict__ grids) {
+                                                  typename Cplx<R>::T* __restrict__ grids,
+                                                  const int64_t* __restrict__ tile_off) {
   using C = typename Cplx<R>::T;
   extern __shared__ unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
@@ -597,17 +601,28 @@ __global__ __launch_bounds__(256) void k_fft_pass(const FftGridPass* __restrict_
   const int64_t groups_per_block = s >> lcols;
   const int64_t blk = local_item / groups_per_block;
   const int64_t j0b = (local_item % groups_per_block) << lcols;
-  C* g = grids + P.grid_off + blk * ((int64_t)np << ls) + j0b;
+  const int64_t base = blk * ((int64_t)np << ls) + j0b;   // position of element (0, 0) in the grid
+  C* g = grids + P.grid_off + base;
   const int total = np << lcols;
   // load: element (m, c) -> buf[m * cols + c], eight loads in flight per
-  // thread (total is a multiple of 2048 whenever it exceeds it)
+  // thread (total is a multiple of 2048 whenever it exceeds it).  The first
+  // pass reads elements of spreading tiles that received no point as zero
+  // (those tiles were not written); a column group (cols <= 16 adjacent
+  // cells) never straddles a tile.
+  const bool first = P.tile_base >= 0;
+  auto in_empty_tile = [&](int64_t pos) -> bool {
+    const int64_t t = P.tile_base + (pos >> kTileShift);
+    return tile_off[t + 1] == tile_off[t];
+  };
+  const C zero = {(R)0, (R)0};
   if (total >= 8 * 256) {
     for (int e0 = threadIdx.x; e0 < total; e0 += 8 * 256) {
       C v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + u * 256;
-        v[u] = g[(int64_t)(e >> lcols) * s + (e & (cols - 1))];
+        const int64_t off = (int64_t)(e >> lcols) * s + (e & (cols - 1));
+        v[u] = (first && in_empty_tile(base + off)) ? zero : g[off];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) buf[e0 + u * 256] = v[u];
@@ -615,7 +630,8 @@ __global__ __launch_bounds__(256) void k_fft_pass(const FftGridPass* __restrict_
   } else {
     for (int e = threadIdx.x; e < total; e += 256) {
       const int m = e >> lcols, c = e & (cols - 1);
-      buf[e] = g[(int64_t)m * s + c];
+      const int64_t off = (int64_t)m * s + c;
+      buf[e] = (first && in_empty_tile(base + off)) ? zero : g[off];
     }
   }
   __syncthreads();
@@ -723,8 +739,9 @@ template __global__ void k_spread<float>(const LcInfo*, int64_t, const int64_t*,
                                          const PointRec<float>*, const int64_t*, const int*, float2*);
 template __global__ void k_spread<double>(const LcInfo*, int64_t, const int64_t*, const PointRec<double>*,
                                           const PointRec<double>*, const int64_t*, const int*, double2*);
-template __global__ void k_fft_pass<float>(const FftGridPass*, int64_t, const int64_t*, const float2*, float2*);
+template __global__ void k_fft_pass<float>(const FftGridPass*, int64_t, const int64_t*, const float2*, float2*,
+                                           const int64_t*);
 template __global__ void k_fft_pass<double>(const FftGridPass*, int64_t, const int64_t*, const double2*,
-                                            double2*);
+                                            double2*, const int64_t*);
 
 }  // namespace ftp
