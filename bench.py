@@ -215,14 +215,22 @@ def bench_ragged(args):
     pairs = int(freq_off[-1])
     big = max(range(len(lcs)), key=lambda i: lcs[i].n_f)
     res = {}
+    wanted = set(x for x in args.solvers.split(",") if x)
     for name, sv in (("uniform", F.FTP_SOLVER_UNIFORM), ("aberth", F.FTP_SOLVER_ABERTH), ("plain", F.FTP_SOLVER_PLAIN)):
+        if name not in wanted:
+            continue
         pl = F.Plan(batch.template.c, batch.template.s, solver=sv)
         if not args.no_autotune:
             lb = lcs[big]
             pl.autotune(lb.t, lb.y, lb.sigma, lb.df, lb.n_f, cache_path=args.tune_cache, force=args.retune)
         out = pl.alloc_outputs(pairs, dev)
-        ms = _time_calls(lambda: pl.periodogram_batch(obs_off, t, y, s, df, freq_off, out=out),
-                         max(1, min(args.steps, 3)), 1)
+        nsteps = max(1, min(args.steps, 3))
+        pl.periodogram_batch(obs_off, t, y, s, df, freq_off, out=out)
+        torch.cuda.synchronize()
+        pl.stats()   # reset the accumulation window
+        ms = _time_calls(lambda: pl.periodogram_batch(obs_off, t, y, s, df, freq_off, out=out), nsteps, 0)
+        st = pl.stats()
+        tiers = {k: st[k] / nsteps for k in ("n_fallback", "n_fallback_aberth", "n_fallback_qr")}
         P = out["power"].cpu().numpy()
         rng = np.random.default_rng(7)
         dmax = 0.0
@@ -234,7 +242,7 @@ def bench_ragged(args):
                 ref = O.periodogram(lc.t, lc.y, lc.sigma, batch.template.c, batch.template.s, lc.df, freq_index=js)
                 dmax = max(dmax, float(np.max(np.abs(P[freq_off[b] + js - 1] - ref["power"]))))
         res[name] = {"value": pairs / (ms * 1e-3), "ms_per_call": ms, "max_abs_dP_sampled": dmax,
-                     "launch_shapes": pl.tuning()}
+                     "per_call": tiers, "launch_shapes": pl.tuning()}
         pl.close()
     print(json.dumps({"workload": "ragged batch: 4096 lightcurves, N_obs log-U[50, 5000], T U(30, 1500) d, H=4",
                       "pairs": pairs, "unit": "pairs/s", "solvers": res}))

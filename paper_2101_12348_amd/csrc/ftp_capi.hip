@@ -1171,6 +1171,20 @@ int plan_create_impl(ftp_plan** out, int n_band, int H, const double* c, const d
     }
   }
   if (e != hipSuccess) { g_last_error = hipGetErrorString(e); delete P; return FTP_E_HIP; }
+  {
+    // chunk sizes from the device's free memory at creation: NFFT grids of a
+    // ragged batch up to a quarter of it (8..48 GiB; 288 GB of HBM holds a
+    // 4096-lightcurve batch's grids in one chunk), per-pair records up to
+    // 4 GiB per solve round (2^21 .. 2^23 pairs)
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
+      P->grid_budget = std::min<size_t>(std::max<size_t>(free_b / 4, (size_t)8 << 30), (size_t)48 << 30);
+    }
+    const size_t rec_bytes = sizeof(double) * (size_t)RecLayout(H).stride;
+    int64_t pc = (int64_t)1 << 21;
+    while (pc < ((int64_t)1 << 23) && (size_t)(2 * pc) * rec_bytes <= ((size_t)4 << 30)) pc *= 2;
+    P->pair_chunk = pc;
+  }
   std::vector<double2> al(nt * H);
   for (int n = 0; n < nt * H; ++n) al[n] = make_double2(0.5 * c[n], 0.5 * s[n]);
   std::vector<float2> tw32(kTwiddleN);
