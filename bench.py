@@ -317,8 +317,10 @@ def bench_shared_phase(args):
 
 
 def bench_h_sweep(args):
-    """H = 1..11 at N_f ~ 5e4 (one single-long-like lightcurve per H): time
-    per periodogram for the plain, uniform-start and Aberth solvers."""
+    """H = 1..15 at N_f ~ 5e4 (one single-long-like lightcurve per H): time
+    per periodogram for the plain, uniform-start and Aberth (H <= 11)
+    solvers, the uniform solver's fallback rate and its largest |dP| from the
+    plain solver."""
     import torch
     import paper_2101_12348_amd as F
     from synthetic import h_sweep_case
@@ -330,12 +332,26 @@ def bench_h_sweep(args):
         y = torch.as_tensor(lc.y, device=dev)
         s = torch.as_tensor(lc.sigma, device=dev)
         row = {"H": H, "D": 6 * H - 2, "n_f": int(lc.n_f)}
+        ref = None
         for name, sv in (("plain", F.FTP_SOLVER_PLAIN), ("uniform", F.FTP_SOLVER_UNIFORM),
                          ("aberth", F.FTP_SOLVER_ABERTH)):
+            if sv == F.FTP_SOLVER_ABERTH and 6 * H - 2 > 64:
+                continue
             pl = F.Plan(tmpl.c, tmpl.s, solver=sv)
             out = pl.alloc_outputs(lc.n_f, dev)
-            ms = _time_calls(lambda: pl.periodogram(t, y, s, lc.df, lc.n_f, out=out), 5, 2)
-            row[name] = {"ms": ms, "pairs_per_s": lc.n_f / (ms * 1e-3)}
+            nst = 3 if H > 11 else 5
+            pl.periodogram(t, y, s, lc.df, lc.n_f, out=out)
+            torch.cuda.synchronize()
+            pl.stats()
+            ms = _time_calls(lambda: pl.periodogram(t, y, s, lc.df, lc.n_f, out=out), nst, 1)
+            st = pl.stats()
+            row[name] = {"ms": ms, "pairs_per_s": lc.n_f / (ms * 1e-3),
+                         "unconfirmed_rate": st["n_fallback"] / (nst + 1) / lc.n_f,
+                         "companion_rate": st["n_fallback_qr"] / (nst + 1) / lc.n_f}
+            if ref is None:
+                ref = out["power"].clone()
+            else:
+                row[name]["max_abs_dP_vs_plain"] = float(torch.max(torch.abs(out["power"] - ref)))
             pl.close()
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)

@@ -64,7 +64,7 @@ extern "C" {
 #define FTP_ST_FALLBACK_QR 16  /* bit: the roots came from the companion solve after the
                                   Aberth iteration did not converge (learned / uniform / Aberth) */
 
-#define FTP_MAX_H 11   /* D = 6H - 2 <= 64: one wavefront lane per companion row */
+#define FTP_MAX_H 15   /* D = 6H - 2 <= 88: up to two companion rows and two coefficients per lane */
 
 /* precision of the NFFT stage (spreading, FFT, sums); assembly, roots and
  * scoring are always FP64 */
@@ -75,15 +75,16 @@ extern "C" {
 #define FTP_SOLVER_PLAIN 0     /* companion-matrix eigenvalues (Section 2) */
 #define FTP_SOLVER_LEARNED 1   /* per frequency a Sturm count of the real-phase roots, then Newton
                                   from evenly spaced starts (min(32, 6H - 2) for H <= 10, 4H for
-                                  H = 11); the frequencies whose roots do not reach the count get a
+                                  H >= 11); the frequencies whose roots do not reach the count get a
                                   second Newton round from the network's 2H seeds plus evenly spaced
                                   starts (with FTP_FLAG_SEEDS_ALL the seeds enter every frequency's
-                                  first round); what is still unconfirmed goes to Aberth, then to
-                                  the companion solve */
+                                  first round); what is still unconfirmed goes to Aberth (H <= 11),
+                                  then to the companion solve */
 #define FTP_SOLVER_UNIFORM 2   /* as LEARNED without the network (ablation): the second round starts
                                   from evenly spaced phases only */
 #define FTP_SOLVER_ABERTH 3    /* Aberth-Ehrlich iteration on every frequency; companion solve
-                                  where it does not converge */
+                                  where it does not converge (H <= 11: one root per lane; larger H
+                                  is refused with FTP_E_OPTION) */
 
 /* option flags */
 #define FTP_FLAG_FORCE_FALLBACK 1u  /* learned / uniform / Aberth solvers: send every frequency to
@@ -305,10 +306,11 @@ int ftp_solve_sums_noalloc(ftp_plan* plan, const double* sums, const double* lc_
  *   sturm_count[j-1]    : distinct real roots of R(theta) (the real-phase
  *                         solutions of Eq. theta2cond, Section 2) from the
  *                         Sturm sequence of the solvers' Cayley polynomial, as
- *                         the learned / uniform solvers compute it; -1 when the
- *                         sequence fails its conditioning test (the solvers then
- *                         fall back), -2 for a frequency the solvers skip (P
- *                         constant in theta_2);
+ *                         the learned / uniform solvers compute it; -1000 - n
+ *                         when the sequence fails its conditioning test (the
+ *                         solvers then fall back; n is the count the sequence
+ *                         reached regardless, a diagnostic), -2 for a frequency
+ *                         the solvers skip (P constant in theta_2);
  *   companion_real[j-1] : real eigenvalues of that polynomial's companion
  *                         matrix by the plain solver's QR (the unit-circle roots
  *                         psi of Eq. finalpoly); -1 if the QR did not converge,

@@ -25,7 +25,7 @@ FTP_FLAG_TIME_STAGES = 2
 FTP_FLAG_POSITIVE_AMP = 8
 FTP_FLAG_SEEDS_ALL = 16
 FTP_FLAG_2H_STARTS = 32
-MAX_H = 11
+MAX_H = 15
 
 ST_OK, ST_DEGENERATE, ST_CONSTANT, ST_NO_CONVERGE, ST_BAD_LC, ST_FALLBACK, ST_FALLBACK_QR = 0, 1, 2, 3, 4, 8, 16
 

@@ -383,6 +383,15 @@ __global__ __launch_bounds__(64 * kAbW) void k_aberth_split(AberthArgs A) {
 }
 
 hipError_t launch_aberth(const AberthArgs& A, int waves, hipStream_t st) {
+  if (6 * A.H - 2 > 64) {
+    // degree above 64 (one root per lane does not fit): the tier hands its
+    // list to the companion solve (the Aberth solver is refused at plan
+    // creation for such H)
+    AberthArgs F = A;
+    F.flags |= 1u;
+    hipLaunchKernelGGL(k_aberth, dim3((unsigned)waves), dim3(64), 0, st, F);
+    return hipGetLastError();
+  }
   if (A.list && 6 * A.H - 2 < 64) {
     // fallback tier: kAbW wavefronts per frequency, grid-strided over the list
     const int wg = waves / kAbW > 1 ? waves / kAbW : 1;

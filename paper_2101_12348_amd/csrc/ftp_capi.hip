@@ -1151,6 +1151,7 @@ int plan_create_impl(ftp_plan** out, int n_band, int H, const double* c, const d
   if (opt) o = *opt; else ftp_options_default(&o);
   if (o.precision != FTP_FP32_SUMS && o.precision != FTP_FP64) return FTP_E_OPTION;
   if (o.solver < FTP_SOLVER_PLAIN || o.solver > FTP_SOLVER_ABERTH) return FTP_E_OPTION;
+  if (o.solver == FTP_SOLVER_ABERTH && 6 * H - 2 > 64) return FTP_E_OPTION;   // one root per lane
   if (o.nfft_R != 0.0 && !(o.nfft_R >= 1.5 && o.nfft_R <= 16.0)) return FTP_E_OPTION;
   if (o.nfft_msp < 0 || o.nfft_msp > 24) return FTP_E_OPTION;
   if (o.solve_waves < 0) return FTP_E_OPTION;

@@ -156,11 +156,79 @@ __device__ __forceinline__ void sturm_step(SturmChain& c, int D, int q, int lane
 }
 
 // Distinct real roots of g (coefficient `gv` in lane c, gtop = g[D] != 0,
-// D <= 64), or -1.
-__device__ int sturm_count_line_reg(double gv, double gtop, int D, int lane) {
+// D <= 64), or -1; `raw` receives the count whether or not the chain passed
+// its tests (a diagnostic).
+__device__ int sturm_count_line_reg(double gv, double gtop, int D, int lane, int& raw) {
   SturmChain c = sturm_begin(gv, gtop, D, lane);
   for (int q = 2; q <= D; ++q) sturm_step(c, D, q, lane);
-  return c.ok ? D - 2 * c.vp : -1;
+  raw = D - 2 * c.vp;
+  return c.ok ? raw : -1;
+}
+
+// Distinct real roots of g for 64 < D <= 127, or -1 (`raw` as above):
+// coefficient c = lane + 64 s in register s (g0, g1; zero above D).  The
+// steps are those of sturm_step on 128-coefficient members (the shift by one
+// power of x carries lane 63 of register 0 into lane 0 of register 1); once
+// the older member's degree is below 64 the chain goes on in one register.
+// All lanes active.  At these degrees the coefficients of the Cayley
+// polynomial span so many orders of magnitude that the early remainders'
+// leading coefficients fall below 1e-13 of their largest ones, so the step
+// test refuses the chain on (nearly) every frequency and the solvers send it
+// on to the companion solve; a test relative to the terms that form each
+// leading coefficient would pass, but trusts wrong counts near close pairs of
+// roots at D = 88.
+__device__ int sturm_count_wave2(double g0, double g1, int D, int lane, int& raw) {
+  const double gtop = lrdlane(g1, D - 64);
+  const double ag = fabs(gtop), sgn = gtop > 0.0 ? 1.0 : -1.0;
+  const double sa = fast_rcp_d(ag + 1e-300), sb = fast_rcp_d(D * ag + 1e-300);
+  const int c0 = lane, c1 = lane + 64;
+  // coefficient c + 1 of g (none above 127)
+  const double n0 = lane_shl1(g0), n1 = lane_shl1(g1);
+  const double g64 = lrdlane(g1, 0);
+  const double u0 = lane == 63 ? g64 : n0;
+  const double d0 = c0 < D ? (c0 + 1) * u0 : 0.0, d1 = c1 < D ? (c1 + 1) * n1 : 0.0;
+  double A0 = c0 == D ? sgn : g0 * sa, A1 = c1 == D ? sgn : g1 * sa;
+  double B0 = c0 == D - 1 ? sgn : d0 * sb, B1 = c1 == D - 1 ? sgn : d1 * sb;
+  SturmChain c;
+  c.ok = ag > 0.0 && ag < INFINITY;
+  c.al = sgn;
+  c.bl = sgn;
+  c.hMA = max(wave_max_int(max(hiword(A0) & 0x7fffffff, hiword(A1) & 0x7fffffff)), kHi1);
+  c.hMB = wave_max_int(max(hiword(B0) & 0x7fffffff, hiword(B1) & 0x7fffffff));
+  c.vp = 0;
+  c.sp = gtop > 0.0 ? 1 : 0;
+  int q = 2;
+  for (; D - q + 2 >= 64; ++q) {   // the older member reaches coefficient 64
+    const int db = D - q + 1;
+    const double s0 = lane_shr1(B0), s1r = lane_shr1(B1), b63 = lrdlane(B0, 63);
+    const double s1 = lane == 0 ? b63 : s1r;
+    const double ab = c.al * c.bl;
+    double t0 = A0 - ab * s0, t1 = A1 - ab * s1;
+    const double q0 = (db >= 64 ? lrdlane(t1, db - 64) : lrdlane(t0, db)) * c.bl;
+    t0 = c0 < db ? t0 - q0 * B0 : 0.0;
+    t1 = c1 < db ? t1 - q0 * B1 : 0.0;
+    const double lead = db - 1 >= 64 ? lrdlane(t1, db - 65) : lrdlane(t0, db - 1);
+    const int hl = hiword(lead), hla = hl & 0x7fffffff;
+    const int hr = wave_max_int(max(hiword(t0) & 0x7fffffff, hiword(t1) & 0x7fffffff));
+    c.ok = c.ok && sturm_step_ok(hr, hla, max(c.hMA, c.hMB));
+    const int tp = (int)((unsigned)hl >> 31);
+    c.vp += tp ^ c.sp;
+    c.sp = tp;
+    const double sc = fast_rcp_d(fabs(lead) + 1e-300);
+    A0 = B0;
+    A1 = B1;
+    c.al = c.bl;
+    c.hMA = c.hMB;
+    B0 = -t0 * sc;
+    B1 = -t1 * sc;
+    c.bl = from_hiword((hl & 0x80000000) ^ 0xbff00000);
+    c.hMB = sturm_member_hi(hr, hla);
+  }
+  c.A = A0;
+  c.B = B0;
+  for (; q <= D; ++q) sturm_step(c, D, q, lane);
+  raw = D - 2 * c.vp;
+  return c.ok ? raw : -1;
 }
 
 // v from lane addr / 4 (ds_bpermute, all lanes active)
@@ -312,8 +380,9 @@ __device__ __forceinline__ void sturm4_phase(double (&A)[4], double (&B)[4], dou
 
 // Distinct real roots of the degree-D polynomial of this lane's row (D + 1 <=
 // 64; G[r] = coefficient 16 r + (lane & 15), zero above D; gtop = coefficient
-// D), or -1 when a step fails its test.  All lanes must be active.
-__device__ __forceinline__ int sturm_count_rows4(const double (&G)[4], double gtop, int D, int lane) {
+// D), or -1 when a step fails its test (`raw`: the count regardless).  All
+// lanes must be active.
+__device__ __forceinline__ int sturm_count_rows4(const double (&G)[4], double gtop, int D, int lane, int& raw) {
   const int l = lane & 15, pbase = (lane & 48) << 2;
   double A[4], B[4], bl, ab;
   Rows4State S;
@@ -327,7 +396,8 @@ __device__ __forceinline__ int sturm_count_rows4(const double (&G)[4], double gt
   sturm4_phase<2>(A, B, bl, ab, S, D, q, min(D + 1, D - 13), l, pbase);
   sturm4_phase<1>(A, B, bl, ab, S, D, q, D + 1, l, pbase);
   ok = ok && S.hmax < 0x7ff00000 && S.m12 > -kHiT12 && S.m13 > -kHiT13;
-  return ok ? D - 2 * S.vp : -1;
+  raw = D - 2 * S.vp;
+  return ok ? raw : -1;
 }
 
 // Newton on R(theta) carried out on the Cayley polynomial.  With x = tan((theta
@@ -590,7 +660,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     const double gtop = mine ? f[D] : 0.0;
     lwave_sync();
-    int cnt = sturm_count_rows4(G, gtop, D, lane);
+    int raw;
+    int cnt = sturm_count_rows4(G, gtop, D, lane, raw);
     if (cnt < 2) cnt = -1;
     if (!mine) cnt = -2;
     const int c0 = __builtin_amdgcn_readlane(cnt, 0), c1 = __builtin_amdgcn_readlane(cnt, 16);
@@ -645,11 +716,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       sml[FS + D - c] = fc;
     }
     const double gv = lane <= D ? R[RL.f + lane] : 0.0;
+    const double gv1 = lane + 64 <= D ? R[RL.f + 64 + lane] : 0.0;
     const double gtop = R[RL.f + D];
     lwave_sync();
     // Sturm count first: an ill-determined count (or fewer than the two real
     // roots every non-constant P has) sends the frequency on without Newton
-    int cnt = sturm_count_line_reg(gv, gtop, D, lane);
+    int raw;
+    int cnt = D > 64 ? sturm_count_wave2(gv, gv1, D, lane, raw) : sturm_count_line_reg(gv, gtop, D, lane, raw);
     if (cnt < 2) cnt = -1;
     const double phi0 = R[RL.meta + M_PHI0];
     double u = 0.0;
@@ -744,10 +817,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // Root counts of a record chunk (diagnostic of the count the learned and
 // uniform solvers trust): per pair, the Sturm count of the Cayley polynomial
 // f by the device code the Newton kernels use (sturm_count_rows4, four pairs
-// per wavefront, for H <= 10; sturm_count_line_reg for H = 11), -1 when the
-// chain fails its test, -2 for an inactive pair; and the number of real
-// eigenvalues the companion QR (run before this kernel) marked in M_REAL_LO /
-// M_REAL_HI (-1 when the QR did not converge).
+// per wavefront, for H <= 10; sturm_count_line_reg for H = 11,
+// sturm_count_wave2 above), -1000 - n when the
+// chain fails its test (n: the count it reached regardless), -2 for an
+// inactive pair; and the number of real
+// eigenvalues the companion QR (run before this kernel) marked in M_REAL_LO,
+// M_REAL_HI and M_REAL_X (-1 when the QR did not converge).
 __global__ __launch_bounds__(64) void k_root_counts(const double* rec, int H, int64_t np, int* sturm, int* real) {
   const int lane = threadIdx.x & 63;
   const int D = 6 * H - 2;
@@ -763,20 +838,26 @@ __global__ __launch_bounds__(64) void k_root_counts(const double* rec, int H, in
       double G[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) G[r] = (in && 16 * r + l <= D) ? f[16 * r + l] : 0.0;
-      cnt = sturm_count_rows4(G, in ? f[D] : 0.0, D, lane);
+      int raw;
+      cnt = sturm_count_rows4(G, in ? f[D] : 0.0, D, lane, raw);
+      if (cnt < 0) cnt = -1000 - raw;
       cnt = __builtin_amdgcn_readlane(cnt, 0) * (lane == 0) + __builtin_amdgcn_readlane(cnt, 16) * (lane == 1) +
             __builtin_amdgcn_readlane(cnt, 32) * (lane == 2) + __builtin_amdgcn_readlane(cnt, 48) * (lane == 3);
     } else {
       const double* RA = rec + w0 * (int64_t)RL.stride;
       const double gv = RA[RL.f + lane];
-      cnt = sturm_count_line_reg(gv, RA[RL.f + D], D, lane);
+      const double gv1 = lane + 64 <= D ? RA[RL.f + 64 + lane] : 0.0;
+      int raw;
+      cnt = D > 64 ? sturm_count_wave2(gv, gv1, D, lane, raw) : sturm_count_line_reg(gv, RA[RL.f + D], D, lane, raw);
+      if (cnt < 0) cnt = -1000 - raw;
     }
     if (lane < per && w0 + lane < np) {
       const double* Rq = rec + (w0 + lane) * (int64_t)RL.stride;
       const int st = (int)Rq[RL.meta + M_STATUS];
       const bool act = st != ST_BAD_LC && st != ST_CONSTANT;
       const unsigned lo = (unsigned)Rq[RL.meta + M_REAL_LO], hi = (unsigned)Rq[RL.meta + M_REAL_HI];
-      const int nreal = __popcll(((unsigned long long)hi << 32) | lo);
+      const unsigned x = D > 64 ? (unsigned)Rq[RL.meta + M_REAL_X] : 0u;
+      const int nreal = __popcll(((unsigned long long)hi << 32) | lo) + __popc(x);
       sturm[w0 + lane] = act ? cnt : -2;
       real[w0 + lane] = act ? (st == ST_NO_CONVERGE ? -1 : nreal) : -2;
     }

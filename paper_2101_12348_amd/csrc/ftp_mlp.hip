@@ -573,20 +573,29 @@ __global__ __launch_bounds__(64) void k_labels(const double* rec, int H, int64_t
   for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
     const double* R = rec + w * (int64_t)RL.stride;
     const int st = (int)R[RL.meta + M_STATUS];
-    bool real = false;
-    double th = 0.0;
-    if (st == ST_OK && lane < RL.D) {
+    // candidates c = lane and lane + 64 (degree D > 64); real ones in order of c
+    bool real[2] = {false, false};
+    double th[2] = {0.0, 0.0};
+    if (st == ST_OK) {
       const unsigned lo = (unsigned)R[RL.meta + M_REAL_LO], hi = (unsigned)R[RL.meta + M_REAL_HI];
       const unsigned long long msk = ((unsigned long long)hi << 32) | lo;
-      real = (msk >> lane) & 1ull;
-      th = R[RL.cand + lane] + R[RL.meta + M_CANON];
-      th = fmod(th, kTwoPi);
-      if (th < 0.0) th += kTwoPi;
+      const unsigned x = RL.D > 64 ? (unsigned)R[RL.meta + M_REAL_X] : 0u;
+      for (int sl = 0; sl < 2; ++sl) {
+        const int cidx = lane + 64 * sl;
+        if (cidx >= RL.D) continue;
+        real[sl] = sl == 0 ? ((msk >> lane) & 1ull) != 0ull : lane < 32 && ((x >> lane) & 1u) != 0u;
+        double v = R[RL.cand + cidx] + R[RL.meta + M_CANON];
+        v = fmod(v, kTwoPi);
+        th[sl] = v < 0.0 ? v + kTwoPi : v;
+      }
     }
-    const unsigned long long m = __ballot(real);
-    const int pos = __popcll(m & ((1ull << lane) - 1ull));
-    if (real && pos < Rmax) roots[w * Rmax + pos] = (float)th;
-    if (lane == 0) nroots[w] = __popcll(m) < Rmax ? __popcll(m) : Rmax;
+    const unsigned long long m0 = __ballot(real[0]), m1 = __ballot(real[1]);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int pos0 = __popcll(m0 & below), pos1 = __popcll(m0) + __popcll(m1 & below);
+    if (real[0] && pos0 < Rmax) roots[w * Rmax + pos0] = (float)th[0];
+    if (real[1] && pos1 < Rmax) roots[w * Rmax + pos1] = (float)th[1];
+    const int nr = __popcll(m0) + __popcll(m1);
+    if (lane == 0) nroots[w] = nr < Rmax ? nr : Rmax;
   }
 }
 

@@ -1,9 +1,9 @@
 // NFFT stage of the fast template periodogram on gfx950.
 //
 // The trig sums Z_g(m) = sum_i g_i exp(2 pi i m df (t_i - t_ref)) the method
-// needs (Section 2: "all of which can be evaluated efficiently using the
-// NFFT", Eqs. CCdef-YSdef; the harmonics up to 2H follow from the
-// product-to-sum identities) are evaluated by Gaussian gridding
+// needs (Section 2, Eqs. CCdef-YSdef, where the paper assigns these sums to
+// the NFFT; the harmonics up to 2H follow from the product-to-sum
+// identities) are evaluated by Gaussian gridding
 // (Dutt & Rokhlin 1993; Greengard & Lee 2004):
 //   prep     : weights, weighted mean, chi^2_0 and t_ref per lightcurve; per
 //              point the grid cell, fractional offset and complex strength

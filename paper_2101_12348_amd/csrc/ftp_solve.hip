@@ -222,6 +222,192 @@ __device__ __forceinline__ void balance_wave(double* A, const int lane) {
   }
 }
 
+// The same two steps for 64 < N <= 128 (degree D = 6H - 2 up to 88): lane j
+// owns rows (columns) j and j + 64, and the bulge column is broadcast from
+// whichever of the two registers holds the row.
+__device__ __forceinline__ double rdlane2(double v0, double v1, int r) {
+  return r < 64 ? rdlane(v0, r) : rdlane(v1, r - 64);
+}
+
+template <int N>
+__device__ __forceinline__ int hqr_wave2(double* A, double* wr, double* wi, const int lane) {
+  static_assert(N > 64 && N <= 128, "two rows per lane");
+  constexpr int ld = N + 1;
+  const int j1 = lane + 64;
+  const bool has1 = j1 < N;
+  double anorm = 0.0;
+  for (int j = (lane > 0 ? lane - 1 : 0); j < N; ++j) anorm += fabs(A[lane * ld + j]);
+  if (has1) {
+    for (int j = j1 - 1; j < N; ++j) anorm += fabs(A[j1 * ld + j]);
+  }
+  anorm = wave_sum(anorm);
+  if (anorm == 0.0) anorm = 1.0;
+  int m = N - 1, its = 0, sweeps = 0;
+  constexpr int maxit = 30 * N;
+  bool failed = false;
+  while (m >= 0) {
+    bool ok0 = false, ok1 = false;
+    if (lane >= 1 && lane <= m) {
+      double sd = fabs(A[(lane - 1) * ld + lane - 1]) + fabs(A[lane * ld + lane]);
+      if (sd == 0.0) sd = anorm;
+      ok0 = fabs(A[lane * ld + lane - 1]) <= kEps * sd;
+    }
+    if (has1 && j1 <= m) {
+      double sd = fabs(A[(j1 - 1) * ld + j1 - 1]) + fabs(A[j1 * ld + j1]);
+      if (sd == 0.0) sd = anorm;
+      ok1 = fabs(A[j1 * ld + j1 - 1]) <= kEps * sd;
+    }
+    const unsigned long long mk0 = __ballot(ok0), mk1 = __ballot(ok1);
+    const int l = mk1 ? 127 - __clzll(mk1) : (mk0 ? 63 - __clzll(mk0) : 0);
+    if (l == m) {
+      if (lane == 0) { wr[m] = A[m * ld + m]; wi[m] = 0.0; }
+      m -= 1;
+      its = 0;
+      continue;
+    }
+    if (l == m - 1) {
+      const double a = A[(m - 1) * ld + m - 1], b = A[(m - 1) * ld + m];
+      const double c = A[m * ld + m - 1], d = A[m * ld + m];
+      const double p = 0.5 * (a - d);
+      const double q = p * p + b * c;
+      if (lane == 0) {
+        if (q >= 0.0) {
+          double z = sqrt(q);
+          z = p + copysign(z, p);
+          const double e1 = d + z;
+          const double e2 = z != 0.0 ? d - b * c / z : e1;
+          wr[m - 1] = e1; wr[m] = e2; wi[m - 1] = 0.0; wi[m] = 0.0;
+        } else {
+          const double z = sqrt(-q);
+          wr[m - 1] = d + p; wr[m] = d + p; wi[m - 1] = z; wi[m] = -z;
+        }
+      }
+      m -= 2;
+      its = 0;
+      continue;
+    }
+    if (sweeps >= maxit) { failed = true; break; }
+    double S, T;
+    const double amm = A[m * ld + m], am1 = A[(m - 1) * ld + m - 1];
+    if (its == 10 || its == 20) {
+      const double sx = fabs(A[m * ld + m - 1]) + fabs(A[(m - 1) * ld + m - 2]);
+      const double c = amm + 0.75 * sx;
+      S = 2.0 * c;
+      T = c * c - 0.4375 * sx * sx;
+    } else {
+      S = am1 + amm;
+      T = am1 * amm - A[(m - 1) * ld + m] * A[m * ld + m - 1];
+    }
+    ++its;
+    ++sweeps;
+    const double all = A[l * ld + l], al1 = A[(l + 1) * ld + l];
+    double x = all * all + A[l * ld + l + 1] * al1 - S * all + T;
+    double y = al1 * (all + A[(l + 1) * ld + l + 1] - S);
+    double z = (l + 2 <= m) ? A[(l + 2) * ld + l + 1] * al1 : 0.0;
+    for (int k = l; k <= m - 1; ++k) {
+      const bool three = k < m - 1;
+      const double s2 = x * x + y * y + z * z;
+      double a0n[2] = {0.0, 0.0};
+      if (s2 > 0.0) {
+        const double inv = fast_rsq(s2);
+        const double nrm = s2 * inv;
+        const double alpha = -copysign(nrm, x);
+        const double ax = fabs(x);
+        const double tau = 1.0 + ax * inv;
+        const double rv = copysign(fast_rcp_d(ax + nrm), x);
+        const double v1 = y * rv, v2 = z * rv;
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+          const int j = lane + 64 * sl;
+          if (j >= k && j <= m) {
+            const double b0 = A[k * ld + j], b1 = A[(k + 1) * ld + j];
+            const double b2 = three ? A[(k + 2) * ld + j] : 0.0;
+            const double w = tau * (b0 + v1 * b1 + v2 * b2);
+            A[k * ld + j] = b0 - w;
+            A[(k + 1) * ld + j] = b1 - w * v1;
+            if (three) A[(k + 2) * ld + j] = b2 - w * v2;
+          } else if (k > l && j == k - 1) {
+            A[k * ld + j] = alpha;
+            A[(k + 1) * ld + j] = 0.0;
+            if (three) A[(k + 2) * ld + j] = 0.0;
+          }
+        }
+        wave_sync();
+        const int ihi = k + 3 < m ? k + 3 : m;
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+          const int i = lane + 64 * sl;
+          if (i >= l && i <= ihi) {
+            const double c0 = A[i * ld + k], c1 = A[i * ld + k + 1];
+            const double c2 = three ? A[i * ld + k + 2] : 0.0;
+            const double w = tau * (c0 + v1 * c1 + v2 * c2);
+            a0n[sl] = c0 - w;
+            A[i * ld + k] = a0n[sl];
+            A[i * ld + k + 1] = c1 - w * v1;
+            if (three) A[i * ld + k + 2] = c2 - w * v2;
+          }
+        }
+        wave_sync();
+        if (k + 1 <= m - 1) {
+          x = rdlane2(a0n[0], a0n[1], k + 1);
+          y = rdlane2(a0n[0], a0n[1], k + 2);
+          z = (k + 1 < m - 1) ? rdlane2(a0n[0], a0n[1], k + 3) : 0.0;
+        }
+      } else if (k + 1 <= m - 1) {
+        x = A[(k + 1) * ld + k];
+        y = A[(k + 2) * ld + k];
+        z = (k + 1 < m - 1) ? A[(k + 3) * ld + k] : 0.0;
+      }
+    }
+  }
+  wave_sync();
+  if (failed) {
+    for (int i = lane; i <= m; i += 64) { wr[i] = A[i * ld + i]; wi[i] = 0.0; }
+    wave_sync();
+    return -1;
+  }
+  return sweeps;
+}
+
+template <int N>
+__device__ __forceinline__ void balance_wave2(double* A, const int lane) {
+  static_assert(N > 64 && N <= 128, "two rows per lane");
+  constexpr int ld = N + 1;
+  const int j1 = lane + 64;
+  const bool has1 = j1 < N;
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    bool done = true;
+    for (int i = 0; i < N; ++i) {
+      double cs = lane != i ? fabs(A[lane * ld + i]) : 0.0;
+      double rs = lane != i ? fabs(A[i * ld + lane]) : 0.0;
+      if (has1 && j1 != i) {
+        cs += fabs(A[j1 * ld + i]);
+        rs += fabs(A[i * ld + j1]);
+      }
+      double c = wave_sum(cs);
+      const double r = wave_sum(rs);
+      if (!(c > 0.0) || !(r > 0.0) || !isfinite(c) || !isfinite(r)) continue;
+      const double s = c + r;
+      double f = 1.0, g = 0.5 * r;
+      while (c < g) { f *= 2.0; c *= 4.0; }
+      g = 2.0 * r;
+      while (c >= g) { f *= 0.5; c *= 0.25; }
+      if ((c + r) / f < 0.95 * s) {
+        done = false;
+        const double fi = 1.0 / f;
+        A[i * ld + lane] *= fi;
+        A[lane * ld + i] *= f;
+        if (has1) {
+          A[i * ld + j1] *= fi;
+          A[j1 * ld + i] *= f;
+        }
+        wave_sync();
+      }
+    }
+    if (done) break;
+  }
+}
+
 __host__ __device__ inline size_t qr_lds_bytes(int D) {
   return ((size_t)D * (D + 1) + 2 * (size_t)D + 2) * sizeof(double);
 }
@@ -249,33 +435,45 @@ __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, 
     if (st == ST_BAD_LC || st == ST_CONSTANT) continue;
     const double* f = R + RL.f;
     const double lead = f[N];
-    if (lane < N) {
-      for (int j = 0; j < N; ++j) A[lane * ld + j] = 0.0;
-      if (lane > 0) A[lane * ld + lane - 1] = 1.0;
+    for (int i = lane; i < N; i += 64) {
+      for (int j = 0; j < N; ++j) A[i * ld + j] = 0.0;
+      if (i > 0) A[i * ld + i - 1] = 1.0;
     }
     wave_sync();
-    if (lane < N) A[lane] = -f[N - 1 - lane] / lead;
+    for (int c = lane; c < N; c += 64) A[c] = -f[N - 1 - c] / lead;
     wave_sync();
-    balance_wave<N>(A, lane);
-    const int sw = hqr_wave<N>(A, wr, wi, lane);
+    int sw;
+    if constexpr (N > 64) {
+      balance_wave2<N>(A, lane);
+      sw = hqr_wave2<N>(A, wr, wi, lane);
+    } else {
+      balance_wave<N>(A, lane);
+      sw = hqr_wave<N>(A, wr, wi, lane);
+    }
     if (sw < 0) {
       if (lane == 0) R[RL.meta + M_STATUS] = (double)ST_NO_CONVERGE;
     } else {
       sweeps_acc += (unsigned long long)sw;
     }
     const double phi0 = R[RL.meta + M_PHI0];
-    bool real = false;
-    if (lane < N) {
-      const double xr = wr[lane], xi = wi[lane];
-      double th = __longlong_as_double(0x7ff8000000000000ll);
-      if (xi >= 0.0 && isfinite(xr) && isfinite(xi)) th = phi0 + atan2(xr, 1.0 - xi) + atan2(xr, 1.0 + xi);
-      real = xi == 0.0 && isfinite(xr);
-      R[RL.cand + lane] = th;
+    bool real[2] = {false, false};
+#pragma unroll
+    for (int sl = 0; sl < (N > 64 ? 2 : 1); ++sl) {
+      const int c = lane + 64 * sl;
+      if (c < N) {
+        const double xr = wr[c], xi = wi[c];
+        double th = __longlong_as_double(0x7ff8000000000000ll);
+        if (xi >= 0.0 && isfinite(xr) && isfinite(xi)) th = phi0 + atan2(xr, 1.0 - xi) + atan2(xr, 1.0 + xi);
+        real[sl] = xi == 0.0 && isfinite(xr);
+        R[RL.cand + c] = th;
+      }
     }
-    const unsigned long long rmask = __ballot(real);
+    const unsigned long long rmask = __ballot(real[0]);
+    const unsigned long long rmask1 = N > 64 ? __ballot(real[1]) : 0ull;
     if (lane == 0) {
       R[RL.meta + M_REAL_LO] = (double)(unsigned)(rmask & 0xffffffffull);
       R[RL.meta + M_REAL_HI] = (double)(unsigned)(rmask >> 32);
+      R[RL.meta + M_REAL_X] = (double)(unsigned)(rmask1 & 0xffffffffull);
     }
     wave_sync();
   }
@@ -708,6 +906,30 @@ __device__ __forceinline__ Best select_best(double P, double th_rel, double th_a
   return b;
 }
 
+// select_best over two candidates per lane (candidate c = lane + 64 slot,
+// degree D > 64); `slot` receives the winner's slot, Best.lane its lane.
+__device__ __forceinline__ Best select_best2(const double (&P)[2], const double (&th_rel)[2],
+                                             const double (&th_abs)[2], const double (&ym)[2],
+                                             const bool (&valid)[2], int& slot) {
+  const double p0 = valid[0] ? P[0] : -1.0, p1 = valid[1] ? P[1] : -1.0;
+  const double pmax = wave_max(fmax(p0, p1));
+  const double lo = pmax - 1e-12 * fmax(pmax, 1e-300);
+  const bool n0 = valid[0] && p0 >= lo, n1 = valid[1] && p1 >= lo;
+  const double k0 = n0 ? ((ym[0] > 0.0 ? 0.0 : 8.0) + th_abs[0]) : 1e30;
+  const double k1 = n1 ? ((ym[1] > 0.0 ? 0.0 : 8.0) + th_abs[1]) : 1e30;
+  const double kmin = -wave_max(-fmin(k0, k1));
+  const unsigned long long m0 = __ballot(n0 && k0 == kmin), m1 = __ballot(n1 && k1 == kmin);
+  slot = m0 ? 0 : (m1 ? 1 : 0);
+  const unsigned long long mask = m0 ? m0 : m1;
+  Best b;
+  b.lane = mask ? __ffsll((long long)mask) - 1 : 0;
+  b.P = slot ? __shfl(p1, b.lane) : __shfl(p0, b.lane);
+  b.th_rel = slot ? __shfl(th_rel[1], b.lane) : __shfl(th_rel[0], b.lane);
+  b.th_abs = slot ? __shfl(th_abs[1], b.lane) : __shfl(th_abs[0], b.lane);
+  b.amp_sign = slot ? __shfl(ym[1], b.lane) : __shfl(ym[0], b.lane);
+  return b;
+}
+
 __device__ __forceinline__ double wrap_2pi(double x) {
   x = fmod(x, kTwoPi);
   if (x < 0.0) x += kTwoPi;
@@ -733,6 +955,8 @@ __host__ __device__ inline size_t score_lds_bytes(int H) {
 // least four waves per SIMD (at most 128 VGPRs, no spills; measured faster
 // than five waves with spills, or than the uncapped allocation).
 // `list` (device, *list_n entries): score only those pairs of the chunk.
+// NSL: candidates per lane (2 for degree D > 64).
+template <int NSL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_score(SolveArgs a, const double* rec, int64_t p0, int64_t np,
                                                                                       const int64_t* list,
                                                                                       const unsigned* list_n) {
@@ -755,15 +979,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   wave_sync();
   const double floor_mm = a.n_band ? a.mm_tau * a.lcs[0].mm_scale : mm_floor(W, H, a.mm_tau);
   // the record fields each lane needs (lane d <= K: r_d; e <= 2H: mu_e;
-  // k < H: eta, Z_w; c < D: candidate c; D <= 64) are loaded one pair ahead,
-  // so their latency overlaps the scoring of the current pair
-  struct Fields { double2 r, mu, eta, zw; double cand; };
+  // k < H: eta, Z_w; candidates c = lane + 64 s < D) are loaded one pair
+  // ahead, so their latency overlaps the scoring of the current pair
+  struct Fields { double2 r, mu, eta, zw; double cand[NSL]; };
   const int64_t n = list ? (int64_t)*list_n : np;
   auto item = [&](int64_t i) { return list ? list[i] : i; };
   auto fetch = [&](int64_t i) {
     Fields f;
     f.r = f.mu = f.eta = f.zw = make_double2(0.0, 0.0);
-    f.cand = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < NSL; ++sl) f.cand[sl] = 0.0;
     if (i < n) {
       const double* R = rec + item(i) * (int64_t)RL.stride;
       if (lane <= K) f.r = make_double2(R[RL.r + 2 * lane], R[RL.r + 2 * lane + 1]);
@@ -772,7 +997,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         f.eta = make_double2(R[RL.eta + 2 * lane], R[RL.eta + 2 * lane + 1]);
         f.zw = make_double2(R[RL.zw + 2 * lane], R[RL.zw + 2 * lane + 1]);
       }
-      if (lane < D) f.cand = R[RL.cand + lane];
+#pragma unroll
+      for (int sl = 0; sl < NSL; ++sl)
+        if (lane + 64 * sl < D) f.cand[sl] = R[RL.cand + 64 * sl + lane];
     }
     return f;
   };
@@ -803,31 +1030,60 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     if (lane == 0) W.eta[0] = make_double2(0.0, 0.0);
     wave_sync();
-    double th = 0.0;
-    bool valid = false;
-    if (st == ST_CONSTANT) {
-      // P does not depend on the phase: score theta_2 = 0 (absolute)
-      th = -kTwoPi * ref;
-      valid = lane == 0;
-    } else if (lane < D) {
-      th = cur.cand;
-      valid = !isnan(th);
-      if (!valid) th = 0.0;
+    double th[NSL];
+    bool valid[NSL];
+    Cand c[NSL];
+#pragma unroll
+    for (int sl = 0; sl < NSL; ++sl) {
+      th[sl] = 0.0;
+      valid[sl] = false;
+      if (st == ST_CONSTANT) {
+        // P does not depend on the phase: score theta_2 = 0 (absolute)
+        th[sl] = -kTwoPi * ref;
+        valid[sl] = lane == 0 && sl == 0;
+      } else if (lane + 64 * sl < D) {
+        th[sl] = cur.cand[sl];
+        valid[sl] = !isnan(th[sl]);
+        if (!valid[sl]) th[sl] = 0.0;
+      }
+      c[sl] = eval_candidate(W, H, th[sl]);
     }
-    const Cand c = eval_candidate(W, H, th);
-    const double mmmax = wave_max(valid ? c.MM : -1.0);
+    double mml = valid[0] ? c[0].MM : -1.0;
+    if (NSL > 1) mml = fmax(mml, valid[NSL - 1] ? c[NSL - 1].MM : -1.0);
+    const double mmmax = wave_max(mml);
     int stout = st;
     if (mmmax <= floor_mm) stout = ST_DEGENERATE;
     // positive-amplitude variant: only candidates with theta_1 = YM/MM > 0
     const bool pos = (a.flags & kFlagPositiveAmp) != 0u;
-    const bool ok = valid && (c.MM > floor_mm || stout == ST_DEGENERATE) && (!pos || c.YM > 0.0);
-    const bool none = pos && stout != ST_DEGENERATE && __ballot(ok) == 0ull;
-    Best b = select_best(c.P, th, wrap_2pi(th + kTwoPi * ref), c.YM, ok, lane);
+    bool ok[NSL];
+    bool any_ok = false;
+#pragma unroll
+    for (int sl = 0; sl < NSL; ++sl) {
+      ok[sl] = valid[sl] && (c[sl].MM > floor_mm || stout == ST_DEGENERATE) && (!pos || c[sl].YM > 0.0);
+      any_ok = any_ok || ok[sl];
+    }
+    const bool none = pos && stout != ST_DEGENERATE && __ballot(any_ok) == 0ull;
+    Best b;
+    int bslot = 0;
+    if constexpr (NSL == 1) {
+      b = select_best(c[0].P, th[0], wrap_2pi(th[0] + kTwoPi * ref), c[0].YM, ok[0], lane);
+    } else {
+      const double P2[2] = {c[0].P, c[NSL - 1].P}, ym2[2] = {c[0].YM, c[NSL - 1].YM};
+      const double th2[2] = {th[0], th[NSL - 1]};
+      const double ta2[2] = {wrap_2pi(th[0] + kTwoPi * ref), wrap_2pi(th[NSL - 1] + kTwoPi * ref)};
+      const bool ok2[2] = {ok[0], ok[NSL - 1]};
+      b = select_best2(P2, th2, ta2, ym2, ok2, bslot);
+    }
     // Newton polish of the winner on R(theta) (Eq. theta2cond): a step is
     // kept only if it is small and P does not drop; a step below 1e-13 rad
     // changes P by O(1e-26) and ends the polish without re-scoring
     double best_th = b.th_rel;
-    Cand cb = {__shfl(c.P, b.lane), __shfl(c.YM, b.lane), __shfl(c.MM, b.lane), __shfl(c.Mbar, b.lane)};
+    const Cand& cw = c[0];
+    Cand cb = {__shfl(cw.P, b.lane), __shfl(cw.YM, b.lane), __shfl(cw.MM, b.lane), __shfl(cw.Mbar, b.lane)};
+    if (NSL > 1 && bslot) {
+      const Cand& cx = c[NSL - 1];
+      cb = Cand{__shfl(cx.P, b.lane), __shfl(cx.YM, b.lane), __shfl(cx.MM, b.lane), __shfl(cx.Mbar, b.lane)};
+    }
     // roots that Newton already converged (steps below 1e-12 rad, learned and
     // uniform solvers) are not polished: the polish step would be rounding noise
     const bool newton_root = a.newton_cands && Rr[RL.meta + M_FALLBACK] == 0.0;
@@ -1062,6 +1318,10 @@ hipError_t launch_qr(int H, double* rec, int stride, int64_t np, const int64_t* 
     case 9: return launch_qr_n<52>(rec, stride, np, list, list_count, counters, queue, waves, st);
     case 10: return launch_qr_n<58>(rec, stride, np, list, list_count, counters, queue, waves, st);
     case 11: return launch_qr_n<64>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 12: return launch_qr_n<70>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 13: return launch_qr_n<76>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 14: return launch_qr_n<82>(rec, stride, np, list, list_count, counters, queue, waves, st);
+    case 15: return launch_qr_n<88>(rec, stride, np, list, list_count, counters, queue, waves, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1088,8 +1348,12 @@ hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64
 
 hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves,
                         hipStream_t st, const int64_t* list, const unsigned* list_n) {
-  hipLaunchKernelGGL(k_score, dim3((unsigned)waves), dim3(64), score_lds_bytes(a.H), st, a, rec, p0, np, list,
-                     list_n);
+  if (6 * a.H - 2 > 64)
+    hipLaunchKernelGGL(k_score<2>, dim3((unsigned)waves), dim3(64), score_lds_bytes(a.H), st, a, rec, p0, np, list,
+                       list_n);
+  else
+    hipLaunchKernelGGL(k_score<1>, dim3((unsigned)waves), dim3(64), score_lds_bytes(a.H), st, a, rec, p0, np, list,
+                       list_n);
   return hipGetLastError();
 }
 

@@ -67,7 +67,8 @@ enum : int {
   M_FALLBACK = 7,  // 0: first method; 1: Aberth tier; 2: companion solve after Aberth
   M_WARM = 8,      // Newton roots left in the candidate slots for the next tier
   M_COUNT = 9,     // Sturm count of a frequency the first Newton round left (-1: none)
-  M_SLOTS = 10,
+  M_REAL_X = 10,   // bit mask of real companion eigenvalues 64..95 (degree D > 64)
+  M_SLOTS = 12,    // (an even count keeps f 16-byte aligned)
 };
 struct RecLayout {
   int K, D, r, mu, eta, zw, meta, f, cand, stride;

@@ -68,7 +68,7 @@ def test_host_validation_without_device():
     assert lib.ftp_plan_create(ctypes.byref(h), 3, vp(c), vp(s), None) == -2      # all zero
     c[0] = 1.0
     assert lib.ftp_plan_create(ctypes.byref(h), 0, vp(c), vp(s), None) == -2      # H < 1
-    assert lib.ftp_plan_create(ctypes.byref(h), 12, vp(np.ones(12)), vp(np.ones(12)), None) == -2
+    assert lib.ftp_plan_create(ctypes.byref(h), 16, vp(np.ones(16)), vp(np.ones(16)), None) == -2      # H > 15
     bad = np.array([np.nan, 1.0, 1.0])
     assert lib.ftp_plan_create(ctypes.byref(h), 3, vp(bad), vp(s), None) == -2
     opt = F.Options()
