@@ -422,7 +422,7 @@ def main():
                     choices=["large", "single_long", "ragged", "h_sweep", "multiband", "shared_phase"],
                     help="large: the reported line (N_obs = 1e5, H = 10, ~3e5 frequencies); single_long: "
                          "N_obs = 1e4, H = 6, ~5e4 frequencies; ragged: the 4096-lightcurve batch (H = 4); "
-                         "h_sweep: H = 1..11 at N_f ~ 5e4 (extra measurements)")
+                         "h_sweep: H = 1..15 at N_f ~ 5e4 (extra measurements)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy before the bench (reference kernel for "
                          "the HBM byte counters)")

@@ -388,7 +388,7 @@ int ftp_plan_set_tuning(ftp_plan* plan, const ftp_tuning* tuning);
  * and written to *out.
  * cache_path (nullable): a text file of "key assemble newton aberth qr score
  * mlp_fused" lines; the key (ftp_plan_tune_key) names the device, its compute units, H,
- * precision and solver.  An entry found there is applied without measuring
+ * precision, solver and a bucket of n_f.  An entry found there is applied without measuring
  * (unless flags has FTP_TUNE_FORCE); a measured result is stored there.
  * Returns 1 when the cache supplied the shapes, 0 when they were measured, or
  * an error (FTP_E_*; the plan's shapes are then unchanged).  Allocates
@@ -398,9 +398,12 @@ int ftp_plan_set_tuning(ftp_plan* plan, const ftp_tuning* tuning);
 int ftp_autotune(ftp_plan* plan, const double* t, const double* y, const double* sigma, int64_t n_obs, double df,
                  int64_t n_f, const char* cache_path, unsigned flags, ftp_tuning* out, void* stream);
 
-/* Cache key of the plan ("<arch>/<CUs>cu/H<H>/p<precision>/s<solver>") into
- * buf (len bytes, NUL terminated).  FTP_E_SIZE if it does not fit. */
-int ftp_plan_tune_key(const ftp_plan* plan, char* buf, int len);
+/* Cache key of the plan for periodograms of n_f frequencies
+ * ("<arch>/<CUs>cu/H<H>/p<precision>/s<solver>/nf<b>", b even with 2^b <= n_f
+ * < 2^(b+2), clamped to 10..24: launch shapes depend on the work per launch)
+ * into buf (len bytes, NUL terminated).  FTP_E_NF if n_f < 1, FTP_E_SIZE if
+ * it does not fit. */
+int ftp_plan_tune_key(const ftp_plan* plan, int64_t n_f, char* buf, int len);
 
 /* Tuning-cache file access (host only, no device use).  lookup: 1 and *out
  * filled when `key` has a well-formed entry, 0 when it has none (or the file

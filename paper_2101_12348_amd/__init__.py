@@ -74,11 +74,26 @@ class FtpError(RuntimeError):
 _lib = None
 
 
+def _init_torch_device():
+    """torch ships its own HIP runtime beside the one libftp.so links; the
+    first runtime to initialise in a process must be torch's, or torch can
+    find no device afterwards.  Initialise it before the library's first
+    call when a device is present (device_count() itself initialises
+    nothing)."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.device_count() > 0:
+        torch.cuda.init()
+
+
 def load_library(path: Optional[str] = None):
     """Load ``libftp.so`` and declare its C signatures (raises if absent)."""
     global _lib
     if _lib is not None and path is None:
         return _lib
+    _init_torch_device()
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise FtpError(f"HIP library not built: {p} (run __graft_entry__.build())")
@@ -111,7 +126,7 @@ def load_library(path: Optional[str] = None):
     lib.ftp_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.ftp_autotune.argtypes = [vp, vp, vp, vp, i64, dbl, i64, ctypes.c_char_p, ctypes.c_uint,
                                  ctypes.POINTER(Tuning), vp]
-    lib.ftp_plan_tune_key.argtypes = [vp, ctypes.c_char_p, ip]
+    lib.ftp_plan_tune_key.argtypes = [vp, i64, ctypes.c_char_p, ip]
     lib.ftp_tune_cache_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(Tuning)]
     lib.ftp_tune_cache_store.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(Tuning)]
     lib.ftp_status_string.restype = ctypes.c_char_p
@@ -342,9 +357,9 @@ class Plan:
             setattr(tu, k, int(v))
         _check(self.lib.ftp_plan_set_tuning(self.handle, ctypes.byref(tu)))
 
-    def tune_key(self) -> str:
+    def tune_key(self, n_f: int) -> str:
         buf = ctypes.create_string_buffer(256)
-        _check(self.lib.ftp_plan_tune_key(self.handle, buf, 256))
+        _check(self.lib.ftp_plan_tune_key(self.handle, int(n_f), buf, 256))
         return buf.value.decode()
 
     def autotune(self, t, y, sigma, df: float, n_f: int, cache_path: Optional[str] = None, force: bool = False,

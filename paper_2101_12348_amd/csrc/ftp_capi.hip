@@ -1752,10 +1752,16 @@ int ftp_plan_set_tuning(ftp_plan* P, const ftp_tuning* t) {
   return FTP_OK;
 }
 
-int ftp_plan_tune_key(const ftp_plan* P, char* buf, int len) {
+int ftp_plan_tune_key(const ftp_plan* P, int64_t n_f, char* buf, int len) {
   if (!P || !buf) return FTP_E_NULL;
-  const int n = std::snprintf(buf, len > 0 ? (size_t)len : 0, "%s/%dcu/H%d/p%d/s%d", P->arch.c_str(), P->n_cu,
-                              P->H, P->opt.precision, P->opt.solver);
+  if (n_f < 1) return FTP_E_NF;
+  // frequency-count bucket: even powers of two (2^(2b) <= n_f < 2^(2b+2)),
+  // 2^10 .. 2^24 and beyond in one bucket
+  int lg = 0;
+  while (lg < 62 && ((int64_t)1 << (lg + 1)) <= n_f) ++lg;
+  const int bucket = std::min(std::max(lg & ~1, 10), 24);
+  const int n = std::snprintf(buf, len > 0 ? (size_t)len : 0, "%s/%dcu/H%d/p%d/s%d/nf%d", P->arch.c_str(),
+                              P->n_cu, P->H, P->opt.precision, P->opt.solver, bucket);
   if (n < 0 || n >= len) return FTP_E_SIZE;
   return FTP_OK;
 }
@@ -1821,7 +1827,7 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
   if (P->opt.solver == FTP_SOLVER_LEARNED && !P->mlp_loaded) return FTP_E_NO_MODEL;
   if (P->n_band) return FTP_E_OPTION;
   char key[256];
-  if ((rc = ftp_plan_tune_key(P, key, (int)sizeof(key)))) return rc;
+  if ((rc = ftp_plan_tune_key(P, n_f, key, (int)sizeof(key)))) return rc;
   if (cache_path && !(flags & FTP_TUNE_FORCE)) {
     ftp_tuning c{};
     rc = ftp_tune_cache_lookup(cache_path, key, &c);

@@ -60,12 +60,18 @@ def test_autotune_and_cache(ftp, tmp_path):
     assert not cached
     assert all(1 <= v <= 256 for k, v in shapes.items() if k != "mlp_fused") and shapes["mlp_fused"] in (0, 1)
     assert plan.tuning() == shapes
-    assert ftp.tune_cache_lookup(cache, plan.tune_key()) == shapes
+    assert ftp.tune_cache_lookup(cache, plan.tune_key(n_f)) == shapes
     out = plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
     for k in ref:
         assert torch.equal(ref[k], out[k]), k
     plan2 = ftp.Plan(tmpl.c, tmpl.s, solver=ftp.FTP_SOLVER_UNIFORM)
     shapes2, cached2 = plan2.autotune(lc.t, lc.y, lc.sigma, lc.df, n_f, cache_path=cache)
     assert cached2 and shapes2 == shapes and plan2.tuning() == shapes
-    key = plan.tune_key()
-    assert key.endswith("/H6/p0/s2") and "cu/" in key
+    key = plan.tune_key(n_f)
+    assert key.endswith("/H6/p0/s2/nf12") and "cu/" in key
+    # size buckets: even powers of two, clamped to 2^10 .. 2^24
+    assert plan.tune_key(1).endswith("/nf10") and plan.tune_key(4095).endswith("/nf10")
+    assert plan.tune_key(4096).endswith("/nf12") and plan.tune_key(299931).endswith("/nf18")
+    assert plan.tune_key(1 << 30).endswith("/nf24")
+    with pytest.raises(ftp.FtpError):
+        plan.tune_key(0)
