@@ -36,6 +36,10 @@ __device__ __forceinline__ void awave_sync() {
 }
 
 __global__ __launch_bounds__(64) void k_aberth(AberthArgs A) {
+  // the fallback tiers run beside the side stream's scoring: their waves
+  // take issue priority over it on a shared SIMD (the tiers are few, latency-bound
+  // waves on the step's critical path)
+  __builtin_amdgcn_s_setprio(2);
   extern __shared__ double sab[];
   const int lane = threadIdx.x & 63;
   const int H = A.H, D = 6 * H - 2;
@@ -205,6 +209,10 @@ __host__ __device__ inline size_t aberth_split_lds_bytes(int H) {
 }
 
 __global__ __launch_bounds__(64 * kAbW) void k_aberth_split(AberthArgs A) {
+  // the fallback tiers run beside the side stream's scoring: their waves
+  // take issue priority over it on a shared SIMD (the tiers are few, latency-bound
+  // waves on the step's critical path)
+  __builtin_amdgcn_s_setprio(2);
   extern __shared__ double sab[];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int H = A.H, D = 6 * H - 2;

@@ -940,7 +940,7 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
         // still be scored on the side stream; the join then orders the side
         // stream's outputs before whatever follows on this one (the next
         // chunk's assembly rewrites the records)
-        HIP_TRY(launch_score(as, rec, p0, np, std::min(w_sc, (int)grid_waves(P, 2, np)), st,
+        HIP_TRY(launch_score(as, rec, p0, np, std::min(w_sc, (int)grid_waves(P, 16, np)), st,
                              B.fb_list, ctr));
         HIP_TRY(hipStreamWaitEvent(st, P->join_ev, 0));
       } else {

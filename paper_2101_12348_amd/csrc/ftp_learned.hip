@@ -422,12 +422,16 @@ __device__ __forceinline__ double newton_u_step(const double* cp, int D, int K, 
   // Horner chains of D/2 steps in place of two of D
   const double v = u * u;
   double E = cp[D], dE = 0.0, O = cp[D - 1], dO = 0.0;
-#pragma unroll 2
+  // (the new E and O are formed in the loaded coefficients' registers and the
+  // derivatives in the old ones', so no step needs a register copy)
+#pragma unroll 4
   for (int c = D - 2; c >= 2; c -= 2) {
+    const double a = cp[c], b = cp[c - 1];
+    const double nE = fma(E, v, a), nO = fma(O, v, b);
     dE = fma(dE, v, E);
-    E = fma(E, v, cp[c]);
     dO = fma(dO, v, O);
-    O = fma(O, v, cp[c - 1]);
+    E = nE;
+    O = nO;
   }
   dE = fma(dE, v, E);
   E = fma(E, v, cp[0]);
@@ -444,6 +448,20 @@ __device__ __forceinline__ double newton_u_step(const double* cp, int D, int K, 
   u = (flip ? dd : num) * fast_rcp_d(flip ? num : dd);
   sg = flip ? -sg : sg;
   return sc;
+}
+
+// Convergence of a Newton lane from its step sizes: a step below 1e-12, or,
+// in the quadratic regime, a step small enough that the iterate it produced
+// is already within ~1e-14 of the root.  With steps s_{k-1}, s_k and the
+// error after step k about C s_k^2, C ~ s_k / s_{k-1}^2, the second test is
+// s_k^3 < 1e-14 s_{k-1}^2 (and s_k < 1e-6); a slowly (linearly) converging
+// lane, as near a double root, passes only the first.  Saves the step that
+// would merely confirm convergence.
+__device__ __forceinline__ bool newton_settled(double sc, double& prev) {
+  const double a = fabs(sc);
+  const bool c = a < 1e-12 || (a < 1e-6 && a * a * a < 1e-14 * prev * prev);
+  prev = a;
+  return c;
 }
 
 // Iterate (u, sg) of the phase whose direction is (c, s) (any length r > 0)
@@ -521,6 +539,7 @@ __device__ __forceinline__ void newton_pair(const LearnArgs& L, const RecLayout&
   int sg = 1;
   bool conv = false, live = cnt >= 0 && hl < NS;
   int its = 0;
+  double prev_step = 1.0;
   if (live) {
     // start direction relative to phi0: a network seed (its output vector
     // is the root's direction in the canonical frame, rotated here by
@@ -550,10 +569,10 @@ __device__ __forceinline__ void newton_pair(const LearnArgs& L, const RecLayout&
         live = false;
       } else {
         ++its;
-        if (fabs(sc) < 1e-12) conv = true;
+        if (newton_settled(sc, prev_step)) conv = true;
       }
     }
-    if (it >= 4) {   // merges are incremental, so every iteration from the fourth checks
+    if (it >= 2) {   // merges are incremental, so every iteration from the second checks
       const unsigned long long cm = __ballot(conv);
       const bool needA = !doneA && __popcll(cm & lo32) >= cA;
       const bool needB = !doneB && __popcll(cm >> 32) >= cB;
@@ -729,6 +748,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     int sg = 1;
     bool conv = false, live = cnt >= 0 && lane < NS;
     int its = 0;
+    double prev_step = 1.0;
     if (live) {
       const bool seeded = L.seeds_out && lane < S;
       double bc = 1.0, bs = 0.0, ang;
@@ -754,10 +774,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           live = false;
         } else {
           ++its;
-          if (fabs(sc) < 1e-12) conv = true;
+          if (newton_settled(sc, prev_step)) conv = true;
         }
       }
-      if (it >= 4) {
+      if (it >= 2) {
         const unsigned long long cm = __ballot(conv);
         // fewer converged lanes than the count cannot reach it (the last
         // check always runs: its roots seed the fallback)
@@ -881,6 +901,10 @@ hipError_t launch_root_counts(const double* rec, int H, int64_t np, int* sturm, 
 // count is settled (its roots become the candidates), the others go on to
 // the Aberth tier through out_list with the roots found as its warm start.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_retry(RetryArgs A) {
+  // the fallback tiers run beside the side stream's scoring: their waves
+  // take issue priority over it on a shared SIMD (the tiers are few, latency-bound
+  // waves on the step's critical path)
+  __builtin_amdgcn_s_setprio(2);
   extern __shared__ double sml[];
   const int lane = threadIdx.x & 63;
   const int H = A.H, K = 3 * H - 1, D = 2 * K, S = 2 * H;
@@ -913,6 +937,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     int sg = 1;
     bool conv = false, live = false;
     int its = 0;
+    double prev_step = 1.0;
     {
       double bc = 1.0, bs = 0.0, ang;
       const int k = lane - nu0, nst = 64 - nu0;
@@ -944,7 +969,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           live = false;
         } else {
           ++its;
-          if (fabs(sc) < 1e-12) conv = true;
+          if (newton_settled(sc, prev_step)) conv = true;
         }
       }
       const unsigned long long cm = __ballot(conv);

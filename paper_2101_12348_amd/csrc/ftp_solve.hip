@@ -54,6 +54,31 @@ __device__ __forceinline__ double fast_rsq(double s) {
 
 // ------------------------------------------------------------------ QR
 
+// f_c = sum_j rc[j] T[j][c] over the Cayley table's rows j = 0..K (column
+// `col`, row stride D + 1): the table loads of eight rows are issued before
+// their multiply-adds, so their latency is paid once per eight rows; the
+// sums run in the order of a two-accumulator loop (even rows, odd rows).
+__device__ __forceinline__ double cayley_dot(const double* rc, const double* col, int K, int D) {
+  double acc0 = 0.0, acc1 = 0.0;
+  int jx = 0;
+  for (; jx + 7 <= K; jx += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = col[(jx + u) * (D + 1)];
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+      acc0 = fma(rc[jx + u], t[u], acc0);
+      acc1 = fma(rc[jx + u + 1], t[u + 1], acc1);
+    }
+  }
+  for (; jx + 1 <= K; jx += 2) {
+    acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
+    acc1 = fma(rc[jx + 1], col[(jx + 1) * (D + 1)], acc1);
+  }
+  if (jx <= K) acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
+  return acc0 + acc1;
+}
+
 // Eigenvalues of the N x N upper Hessenberg matrix A (LDS, leading dim N + 1,
 // N <= 64), EISPACK hqr structure, eigenvalues only: Francis double-shift
 // sweeps over the active window [l, m], deflating at negligible subdiagonals.
@@ -418,6 +443,10 @@ template <int N>
 __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, const int64_t* list,
                                            const unsigned int* list_count, SolveCounters* counters,
                                            unsigned* queue) {
+  // the fallback tiers run beside the side stream's scoring: their waves
+  // take issue priority over it on a shared SIMD (the tiers are few, latency-bound
+  // waves on the step's critical path)
+  __builtin_amdgcn_s_setprio(2);
   extern __shared__ double smq[];
   constexpr int ld = N + 1;
   double* A = smq;
@@ -696,15 +725,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         wave_sync();
         if (lane <= D) {
           const double* rc = (lane & 1) ? ry : rx;
-          const double* col = a.ctab + lane;
-          double acc0 = 0.0, acc1 = 0.0;
-          int jx = 0;
-          for (; jx + 1 <= K; jx += 2) {
-            acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
-            acc1 = fma(rc[jx + 1], col[(jx + 1) * (D + 1)], acc1);
-          }
-          if (jx <= K) acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
-          Rr[RL.f + lane] = acc0 + acc1;
+          Rr[RL.f + lane] = cayley_dot(rc, a.ctab + lane, K, D);
         }
       } else {
         for (int c = lane; c <= D; c += 64) {
@@ -846,15 +867,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const bool write = has && !bad;
     for (int c = hl; c <= D; c += 32) {
       const double* rc = (c & 1) ? ry : rx;
-      const double* col = a.ctab + c;
-      double acc0 = 0.0, acc1 = 0.0;
-      int jx = 0;
-      for (; jx + 1 <= K; jx += 2) {
-        acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
-        acc1 = fma(rc[jx + 1], col[(jx + 1) * (D + 1)], acc1);
-      }
-      if (jx <= K) acc0 = fma(rc[jx], col[jx * (D + 1)], acc0);
-      if (write && !constant) Rr[RL.f + c] = acc0 + acc1;
+      const double fc = cayley_dot(rc, a.ctab + c, K, D);
+      if (write && !constant) Rr[RL.f + c] = fc;
     }
     if (write) {
       for (int d = hl; d <= K; d += 32) { Rr[RL.r + 2 * d] = W.r[d].x; Rr[RL.r + 2 * d + 1] = W.r[d].y; }
@@ -960,6 +974,10 @@ template <int NSL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_score(SolveArgs a, const double* rec, int64_t p0, int64_t np,
                                                                                       const int64_t* list,
                                                                                       const unsigned* list_n) {
+  // the fallback tiers run beside the side stream's scoring: their waves
+  // take issue priority over it on a shared SIMD (the tiers are few, latency-bound
+  // waves on the step's critical path)
+  __builtin_amdgcn_s_setprio(2);
   extern __shared__ double sms[];
   const int lane = wave_lane();
   const int H = a.H, K = 3 * H - 1, D = 2 * K;
