@@ -542,6 +542,35 @@ __device__ __forceinline__ AsmLayout asm_layout(double* sm, int H, int nb) {
   return s;
 }
 
+// Compact per-frequency working set of k_assemble2 (single band, D < 64):
+// Z, mu, eta, r, alpha and a scratch of max(8H + 2, K + 1) complex values
+// (assemble_r's MM and YM coefficient rows; later the rotated 2 rho_j).
+__host__ __device__ inline int asm2_doubles(int H) {
+  const int K = 3 * H - 1;
+  const int scr = 8 * H + 2 > K + 1 ? 8 * H + 2 : K + 1;
+  return 2 * ((3 * H + 1) + (2 * H + 1) + (H + 1) + (K + 1) + H + scr);
+}
+__device__ __forceinline__ FreqWork asm2_layout(double* sm, int H, double2*& scr) {
+  const int K = 3 * H - 1;
+  FreqWork W;
+  double2* q = reinterpret_cast<double2*>(sm);
+  W.Z = q; q += 3 * H + 1;
+  W.mu = q; q += 2 * H + 1;
+  W.eta = q; q += H + 1;
+  W.r = q; q += K + 1;
+  W.al = q; q += H;
+  scr = q;
+  return W;
+}
+// Waves per workgroup of k_assemble2: they share one LDS copy of the Cayley
+// table ((K + 1) (D + 1) doubles, 14 KB at H = 10), which the dot products
+// read with LDS latency instead of the L2's.
+constexpr int kAsmWaves = 4;
+__host__ __device__ inline size_t asm2_lds_bytes(int H) {
+  const int K = 3 * H - 1, D = 2 * K;
+  return ((size_t)(K + 1) * (D + 1) + (size_t)kAsmWaves * 2 * asm2_doubles(H)) * sizeof(double);
+}
+
 // Shared-phase bands (Appendix A): trig coefficients of MM and YM from the
 // sums of every band.  With Z^b_n (weights normalised over all bands, Z^b_0 =
 // W_b the band's share) and Zy^b_n:
@@ -786,22 +815,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // "constant" or from a rejected lightcurve still runs the (cheap) rotation and
 // dot products of its half, whose results are not written.
 template <typename R>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble2(SolveArgs a, double* rec,
+__global__ __launch_bounds__(64 * kAsmWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble2(SolveArgs a, double* rec,
                                                                                           int64_t p0, int64_t np) {
   extern __shared__ double sma[];
-  const int lane = wave_lane(), half = lane >> 5, hl = lane & 31;
-  if (a.clear8 && blockIdx.x == 0 && lane < 8) a.clear8[lane] = 0u;
+  const int lane = wave_lane(), half = lane >> 5, hl = lane & 31, wv = threadIdx.x >> 6;
+  if (a.clear8 && blockIdx.x == 0 && threadIdx.x < 8) a.clear8[threadIdx.x] = 0u;
   const int H = a.H, K = 3 * H - 1, D = 2 * K;
   const RecLayout RL(H);
-  const size_t per = asm_lds_bytes(H, 0) / sizeof(double);
-  AsmLayout S = asm_layout(sma + half * per, H, 0);
-  const FreqWork& W = S.W;
-  for (int q = hl; q < H; q += 32) S.W.al[q] = a.alpha[q];
-  wave_sync();
+  // the Cayley table, shared by the workgroup's waves
+  double* ctab = sma;
+  const int ntab = (K + 1) * (D + 1);
+  for (int i = threadIdx.x; i < ntab; i += 64 * kAsmWaves) ctab[i] = a.ctab[i];
+  double2* scr;
+  const FreqWork W = asm2_layout(sma + ntab + (2 * wv + half) * asm2_doubles(H), H, scr);
+  for (int q = hl; q < H; q += 32) W.al[q] = a.alpha[q];
+  __syncthreads();
   double tab_c, tab_s;
   sincos(kTwoPi * (lane & 15) / 16.0, &tab_s, &tab_c);
   const typename Cplx<R>::T* grids = reinterpret_cast<const typename Cplx<R>::T*>(a.grids);
-  for (int64_t w0 = 2 * (int64_t)blockIdx.x; w0 < np; w0 += 2 * (int64_t)gridDim.x) {
+  const int64_t gw = (int64_t)blockIdx.x * kAsmWaves + wv, nw = (int64_t)gridDim.x * kAsmWaves;
+  for (int64_t w0 = 2 * gw; w0 < np; w0 += 2 * nw) {
     const bool has = w0 + half < np;                    // an empty second half repeats the first
     const int64_t w = has ? w0 + half : w0;
     const int64_t pidx = p0 + w;
@@ -817,7 +850,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       W.Z[q + 1] = bad ? make_double2(0.0, 0.0) : gather_mode<R>(L, g, (int64_t)k * j, grids);
     }
     wave_sync();
-    assemble_poly(W, H, hl, S.hb[0], 32);
+    assemble_poly(W, H, hl, scr, 32);
     const double ref = ref_cycles(j, L.df, L.tref);
     double rmax = 0.0, mumax = 0.0, etamax = 0.0;
     for (int d = hl; d <= K; d += 32) rmax = fmax(rmax, sqrt(cabs2(W.r[d])));
@@ -850,7 +883,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     // 2 rho_j = 2 r_{j-K} e^{i (j-K) phi0}, j = 0..K - 1, and rho_K (K + 1 <=
     // 30 lanes: every lane takes part in the table reads), then the dot
     // products over the table's rows j <= K (the terms j and D - j are equal)
-    double* rx = reinterpret_cast<double*>(S.hb[0]);
+    double* rx = reinterpret_cast<double*>(scr);
     double* ry = rx + (K + 1);
     {
       const int jx = hl, d = jx - K;
@@ -867,7 +900,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const bool write = has && !bad;
     for (int c = hl; c <= D; c += 32) {
       const double* rc = (c & 1) ? ry : rx;
-      const double fc = cayley_dot(rc, a.ctab + c, K, D);
+      const double fc = cayley_dot(rc, ctab + c, K, D);
       if (write && !constant) Rr[RL.f + c] = fc;
     }
     if (write) {
@@ -1347,13 +1380,14 @@ hipError_t launch_qr(int H, double* rec, int stride, int64_t np, const int64_t* 
 hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64_t p0, int64_t np, int waves,
                            hipStream_t st) {
   if (a.n_band == 0 && !a.sums_in && 6 * a.H - 2 < 64) {
-    // two frequencies per wavefront
-    const size_t lds2 = 2 * asm_lds_bytes(a.H, 0);
-    const int w2 = (int)std::max<int64_t>(1, std::min<int64_t>(waves, (np + 1) / 2));
+    // two frequencies per wavefront, kAsmWaves wavefronts per workgroup
+    const size_t lds2 = asm2_lds_bytes(a.H);
+    const int64_t w2 = std::max<int64_t>(1, std::min<int64_t>(waves, (np + 1) / 2));
+    const int g2 = (int)((w2 + kAsmWaves - 1) / kAsmWaves);
     if (precision == 1)
-      hipLaunchKernelGGL(k_assemble2<double>, dim3((unsigned)w2), dim3(64), lds2, st, a, rec, p0, np);
+      hipLaunchKernelGGL(k_assemble2<double>, dim3((unsigned)g2), dim3(64 * kAsmWaves), lds2, st, a, rec, p0, np);
     else
-      hipLaunchKernelGGL(k_assemble2<float>, dim3((unsigned)w2), dim3(64), lds2, st, a, rec, p0, np);
+      hipLaunchKernelGGL(k_assemble2<float>, dim3((unsigned)g2), dim3(64 * kAsmWaves), lds2, st, a, rec, p0, np);
     return hipGetLastError();
   }
   const size_t lds = asm_lds_bytes(a.H, a.n_band);
