@@ -712,9 +712,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       assemble_r(W, H, lane, S.hb[0]);
     }
     double rmax = 0.0, mumax = 0.0, etamax = 0.0;
-    for (int d = lane; d <= K; d += 64) rmax = fmax(rmax, sqrt(cabs2(W.r[d])));
-    for (int e = lane; e <= 2 * H; e += 64) mumax = fmax(mumax, sqrt(cabs2(W.mu[e])));
-    for (int k = lane; k <= H; k += 64) etamax = fmax(etamax, sqrt(cabs2(W.eta[k])));
+    // (largest squared magnitudes, one square root each: sqrt is monotone and
+    // correctly rounded, so this is the largest magnitude)
+    for (int d = lane; d <= K; d += 64) rmax = fmax(rmax, cabs2(W.r[d]));
+    for (int e = lane; e <= 2 * H; e += 64) mumax = fmax(mumax, cabs2(W.mu[e]));
+    for (int k = lane; k <= H; k += 64) etamax = fmax(etamax, cabs2(W.eta[k]));
+    rmax = sqrt(rmax);
+    mumax = sqrt(mumax);
+    etamax = sqrt(etamax);
     // maxima from the doubles' high words (within 2^-20): the threshold
     // below only separates R = 0 from rounding noise
     rmax = wave_max_abs_hi(rmax);
@@ -853,9 +858,12 @@ __global__ __launch_bounds__(64 * kAsmWaves) __attribute__((amdgpu_waves_per_eu(
     assemble_poly(W, H, hl, scr, 32);
     const double ref = ref_cycles(j, L.df, L.tref);
     double rmax = 0.0, mumax = 0.0, etamax = 0.0;
-    for (int d = hl; d <= K; d += 32) rmax = fmax(rmax, sqrt(cabs2(W.r[d])));
-    for (int e = hl; e <= 2 * H; e += 32) mumax = fmax(mumax, sqrt(cabs2(W.mu[e])));
-    for (int k = hl; k <= H; k += 32) etamax = fmax(etamax, sqrt(cabs2(W.eta[k])));
+    for (int d = hl; d <= K; d += 32) rmax = fmax(rmax, cabs2(W.r[d]));
+    for (int e = hl; e <= 2 * H; e += 32) mumax = fmax(mumax, cabs2(W.mu[e]));
+    for (int k = hl; k <= H; k += 32) etamax = fmax(etamax, cabs2(W.eta[k]));
+    rmax = sqrt(rmax);
+    mumax = sqrt(mumax);
+    etamax = sqrt(etamax);
     {
       double lo, hi;
       half_max_abs_hi(rmax, lo, hi);

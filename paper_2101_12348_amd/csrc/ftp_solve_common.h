@@ -201,14 +201,22 @@ __device__ __forceinline__ void half_max_d(double v, double& m_lo, double& m_hi)
 
 // Position of mode index q (0 <= q < n) in the digit-reversed FFT output.
 __device__ __forceinline__ int64_t fft_pos(int64_t q, const LcInfo& L, int g) {
+  // the pass sizes are loaded together (independent loads) before the loop
+  int lps[kMaxPasses];
+#pragma unroll
+  for (int p = 0; p < kMaxPasses; ++p) lps[p] = L.lp[g][p];
+  const int npass = L.npass[g];
   int64_t pos = 0;
   int rem = L.log2n[g];
-  for (int p = 0; p < L.npass[g]; ++p) {
-    const int lp = L.lp[g][p];
-    rem -= lp;
-    const int64_t d = q & ((1LL << lp) - 1);
-    q >>= lp;
-    pos += d << rem;
+#pragma unroll
+  for (int p = 0; p < kMaxPasses; ++p) {
+    if (p < npass) {
+      const int lp = lps[p];
+      rem -= lp;
+      const int64_t d = q & ((1LL << lp) - 1);
+      q >>= lp;
+      pos += d << rem;
+    }
   }
   return pos;
 }
