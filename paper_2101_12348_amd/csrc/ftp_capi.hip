@@ -51,7 +51,7 @@ hipError_t launch_assemble(int precision, const SolveArgs& a, double* rec, int64
                            hipStream_t st);
 hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves,
                         hipStream_t st, const int64_t* list = nullptr, const unsigned* list_n = nullptr);
-hipError_t launch_score2(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves, hipStream_t st,
+hipError_t launch_score_newton(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves, hipStream_t st,
                          hipEvent_t done = nullptr);
 hipError_t launch_gather_sums(int precision, const SolveArgs& a, double* out, int blocks, hipStream_t st);
 hipError_t launch_export_stats(const LcInfo* lcs, double* out, hipStream_t st);
@@ -866,11 +866,12 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
         L.fb_count = ctr;
         L.flags = ((P->opt.flags & FTP_FLAG_FORCE_FALLBACK) ? 1u : 0u) | ((P->opt.flags & FTP_FLAG_2H_STARTS) ? 2u : 0u);
         L.queue = nullptr;   // uniform work per pair: grid striding (a queue costs more than it balances)
-        // with the side stream, the last launch before the fork and the side
-        // scoring launch record the fork and join events themselves: the
-        // network on the first round's list (learned solver) runs before the
-        // fork, so that its workgroups are not queued behind the scoring's
-        HIP_TRY(launch_newton_sturm(a, L, w_nt, st, (overlap_score && !net_list) ? P->fork_ev : nullptr));
+        // with the side stream, the Newton kernel and the side scoring launch
+        // record the fork and join events themselves: the scoring of the
+        // Newton-root pairs is the longest branch after the fork, so it starts
+        // as soon as the first round ends, beside the network on the first
+        // round's list (learned solver) and the later tiers
+        HIP_TRY(launch_newton_sturm(a, L, w_nt, st, overlap_score ? P->fork_ev : nullptr));
       }
       hipEvent_t rb = learn_ev();
       if (rb) HIP_TRY(hipEventRecord(rb, st));
@@ -878,7 +879,7 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
       // the learned solver (unless every pair had them already), evenly spaced
       // starts otherwise; what it leaves goes to the Aberth tier
       if (net_list) {
-        if ((rc = run_network(B.fb_list, ctr, overlap_score ? P->fork_ev : nullptr))) return rc;
+        if ((rc = run_network(B.fb_list, ctr, nullptr))) return rc;
       }
       if (solver != FTP_SOLVER_ABERTH && overlap_score) {
         // the Newton-root pairs are final now: score them on the side stream
@@ -886,7 +887,7 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
         SolveArgs as = a;
         as.newton_cands = true;
         HIP_TRY(hipStreamWaitEvent(P->side, P->fork_ev, 0));
-        HIP_TRY(launch_score2(as, rec, p0, np, w_sc, P->side, P->join_ev));
+        HIP_TRY(launch_score_newton(as, rec, p0, np, w_sc, P->side, P->join_ev));
       }
       hipEvent_t rr = learn_ev();
       if (rr) HIP_TRY(hipEventRecord(rr, st));

@@ -1178,58 +1178,76 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
-// select_best within each half-wave (the tie rule of select_best).
-__device__ __forceinline__ Best select_best_half(double P, double th_rel, double th_abs, double ym, bool valid,
-                                                 int lane) {
-  const int half = lane >> 5;
-  const double pv = valid ? P : -1.0;
-  double lo, hi;
-  half_max_d(pv, lo, hi);
-  const double pmax = half ? hi : lo;
-  const bool near = valid && pv >= pmax - 1e-12 * fmax(pmax, 1e-300);
-  const double key = near ? ((ym > 0.0 ? 0.0 : 8.0) + th_abs) : 1e30;
-  half_max_d(-key, lo, hi);
-  const double kmin = -(half ? hi : lo);
-  const unsigned long long mask = __ballot(near && key == kmin);
-  const unsigned hm = half ? (unsigned)(mask >> 32) : (unsigned)mask;
+
+// Writes the deconvolved sums of every pair (3H complex per pair: Z_w(k j),
+// k = 1..2H, then Z_y(k j), k = 1..H with the 1/sqrt(YY) normalisation undone).
+// Maximum of a double over each 16-lane row, in every lane of the row.
+__device__ __forceinline__ double row_max_d(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));    // quad_perm [1, 0, 3, 2]
+  v = fmax(v, dpp_d<0x4E>(v));    // quad_perm [2, 3, 0, 1]
+  v = fmax(v, dpp_d<0x141>(v));   // row_half_mirror
+  v = fmax(v, dpp_d<0x140>(v));   // row_mirror
+  return v;
+}
+
+// select_best within each 16-lane row over two candidates per lane (slot 0:
+// candidate l, slot 1: candidate 16 + l of the row's frequency); the same
+// rule, and the same winner, as select_best over the row's candidates in
+// index order.  `slot` receives the winner's slot.
+__device__ __forceinline__ Best select_best_row(const double (&P)[2], const double (&th_rel)[2],
+                                                const double (&th_abs)[2], const double (&ym)[2],
+                                                const bool (&valid)[2], int lane, int& slot) {
+  const int row = lane >> 4;
+  const double p0 = valid[0] ? P[0] : -1.0, p1 = valid[1] ? P[1] : -1.0;
+  const double pmax = row_max_d(fmax(p0, p1));
+  const double lo = pmax - 1e-12 * fmax(pmax, 1e-300);
+  const bool n0 = valid[0] && p0 >= lo, n1 = valid[1] && p1 >= lo;
+  const double k0 = n0 ? ((ym[0] > 0.0 ? 0.0 : 8.0) + th_abs[0]) : 1e30;
+  const double k1 = n1 ? ((ym[1] > 0.0 ? 0.0 : 8.0) + th_abs[1]) : 1e30;
+  const double kmin = -row_max_d(-fmin(k0, k1));
+  const unsigned m0 = (unsigned)(__ballot(n0 && k0 == kmin) >> (16 * row)) & 0xffffu;
+  const unsigned m1 = (unsigned)(__ballot(n1 && k1 == kmin) >> (16 * row)) & 0xffffu;
+  slot = m0 ? 0 : (m1 ? 1 : 0);
+  const unsigned m = m0 ? m0 : m1;
   Best b;
-  b.lane = (hm ? __ffs(hm) - 1 : 0) + 32 * half;
-  b.P = __shfl(pv, b.lane);
-  b.th_rel = __shfl(th_rel, b.lane);
-  b.th_abs = __shfl(th_abs, b.lane);
-  b.amp_sign = __shfl(ym, b.lane);
+  b.lane = (m ? __ffs(m) - 1 : 0) + 16 * row;
+  b.P = slot ? __shfl(p1, b.lane) : __shfl(p0, b.lane);
+  b.th_rel = slot ? __shfl(th_rel[1], b.lane) : __shfl(th_rel[0], b.lane);
+  b.th_abs = slot ? __shfl(th_abs[1], b.lane) : __shfl(th_abs[0], b.lane);
+  b.amp_sign = slot ? __shfl(ym[1], b.lane) : __shfl(ym[0], b.lane);
   return b;
 }
 
-// Scoring of the pairs whose candidates are Newton-converged roots (learned
-// and uniform solvers with two frequencies per Newton wavefront: at most 32
-// roots, in candidate slots 0..31), two pairs per wavefront: frequencies 2b
-// and 2b + 1 on the half-waves, each with its own LDS working set, candidates
-// one per lane, maxima and the best candidate per half.  These candidates need
-// no polish.  Pairs sent to a fallback tier (M_FALLBACK != 0) are left to
-// k_score over the fallback list.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_score2(SolveArgs a, const double* rec,
+// Scoring of the first round's Newton-root pairs (M_FALLBACK = 0), four
+// frequencies per wavefront, one per 16-lane row: the roots (at most 32 per
+// frequency, its starts) are scored 16 at a time, and the candidates 16..31
+// of a row take a second evaluation only when some row of the wavefront has
+// more than 16 roots (a frequency has ~12 real roots at H = 10).  The
+// candidates, tie rule and outputs of k_score, without the polish (the roots
+// are Newton-converged).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_score4(SolveArgs a, const double* rec,
                                                                                        int64_t p0, int64_t np) {
   extern __shared__ double sms[];
-  const int lane = wave_lane(), half = lane >> 5, hl = lane & 31;
+  const int lane = wave_lane(), row = lane >> 4, l = lane & 15;
   const int H = a.H, K = 3 * H - 1, D = 2 * K;
   const RecLayout RL(H);
   FreqWork W;
   {
-    double2* q = reinterpret_cast<double2*>(sms + half * (score_lds_bytes(H) / sizeof(double)));
+    double2* q = reinterpret_cast<double2*>(sms + row * (score_lds_bytes(H) / sizeof(double)));
     W.Z = q; q += 3 * H + 1;
     W.mu = q; q += 2 * H + 1;
     W.eta = q; q += H + 1;
     W.r = q; q += K + 1;
     W.al = q;
   }
-  for (int q = hl; q < H; q += 32) W.al[q] = a.n_band ? make_double2(1.0, 0.0) : a.alpha[q];
+  for (int q = l; q < H; q += 16) W.al[q] = a.n_band ? make_double2(1.0, 0.0) : a.alpha[q];
   wave_sync();
   const double floor_mm = a.n_band ? a.mm_tau * a.lcs[0].mm_scale : mm_floor(W, H, a.mm_tau);
   const bool pos = (a.flags & kFlagPositiveAmp) != 0u;
-  for (int64_t w0 = 2 * (int64_t)blockIdx.x; w0 < np; w0 += 2 * (int64_t)gridDim.x) {
-    const bool has = w0 + half < np;
-    const int64_t w = has ? w0 + half : w0;
+  const int ncand = D < 32 ? D : 32;   // the first round's starts per frequency
+  for (int64_t w0 = 4 * (int64_t)blockIdx.x; w0 < np; w0 += 4 * (int64_t)gridDim.x) {
+    const bool has = w0 + row < np;
+    const int64_t w = has ? w0 + row : w0;
     const int64_t pidx = p0 + w;
     const double* Rr = rec + w * (int64_t)RL.stride;
     const int st = (int)Rr[RL.meta + M_STATUS];
@@ -1237,37 +1255,52 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int64_t lc = (int64_t)Rr[RL.meta + M_LC];
     const LcInfo& L = a.lcs[lc];
     const double ref = Rr[RL.meta + M_REF];
-    if (hl <= K) W.r[hl] = make_double2(Rr[RL.r + 2 * hl], Rr[RL.r + 2 * hl + 1]);
-    if (hl <= 2 * H) W.mu[hl] = make_double2(Rr[RL.mu + 2 * hl], Rr[RL.mu + 2 * hl + 1]);
-    if (hl < H) {
-      W.eta[hl + 1] = make_double2(Rr[RL.eta + 2 * hl], Rr[RL.eta + 2 * hl + 1]);
-      const double2 z = make_double2(Rr[RL.zw + 2 * hl], Rr[RL.zw + 2 * hl + 1]);
-      W.Z[hl + 1] = cconj(cmul(W.al[hl], cconj(z)));
+    for (int d = l; d <= K; d += 16) W.r[d] = make_double2(Rr[RL.r + 2 * d], Rr[RL.r + 2 * d + 1]);
+    for (int e = l; e <= 2 * H; e += 16) W.mu[e] = make_double2(Rr[RL.mu + 2 * e], Rr[RL.mu + 2 * e + 1]);
+    for (int k = l; k < H; k += 16) {
+      W.eta[k + 1] = make_double2(Rr[RL.eta + 2 * k], Rr[RL.eta + 2 * k + 1]);
+      const double2 z = make_double2(Rr[RL.zw + 2 * k], Rr[RL.zw + 2 * k + 1]);
+      W.Z[k + 1] = cconj(cmul(W.al[k], cconj(z)));
     }
-    if (hl == 0) W.eta[0] = make_double2(0.0, 0.0);
-    wave_sync();
-    double th = 0.0;
-    bool valid = false;
+    if (l == 0) W.eta[0] = make_double2(0.0, 0.0);
+    double th[2] = {0.0, 0.0};
+    bool valid[2] = {false, false};
     if (st == ST_CONSTANT) {
-      th = -kTwoPi * ref;
-      valid = hl == 0;
-    } else if (st != ST_BAD_LC && hl < D) {
-      th = Rr[RL.cand + hl];
-      valid = !isnan(th);
-      if (!valid) th = 0.0;
+      th[0] = -kTwoPi * ref;
+      valid[0] = l == 0;
+    } else if (st != ST_BAD_LC) {
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        const int c = l + 16 * sl;
+        if (c < ncand) {
+          th[sl] = Rr[RL.cand + c];
+          valid[sl] = !isnan(th[sl]);
+          if (!valid[sl]) th[sl] = 0.0;
+        }
+      }
     }
-    const Cand c = eval_candidate(W, H, th);
-    double lo, hi;
-    half_max_d(valid ? c.MM : -1.0, lo, hi);
-    const double mmmax = half ? hi : lo;
+    wave_sync();
+    Cand c[2];
+    c[0] = eval_candidate(W, H, th[0]);
+    c[1] = Cand{0.0, 0.0, 0.0, 0.0};
+    const bool second = __ballot(valid[1]) != 0ull;   // wave-uniform
+    if (second) c[1] = eval_candidate(W, H, th[1]);
+    const double mmmax = row_max_d(fmax(valid[0] ? c[0].MM : -1.0, valid[1] ? c[1].MM : -1.0));
     int stout = st;
     if (st != ST_BAD_LC && mmmax <= floor_mm) stout = ST_DEGENERATE;
-    const bool ok = valid && (c.MM > floor_mm || stout == ST_DEGENERATE) && (!pos || c.YM > 0.0);
-    const unsigned long long okm = __ballot(ok);
-    const bool none = pos && stout != ST_DEGENERATE && (half ? (okm >> 32) : (okm & 0xffffffffull)) == 0ull;
-    const Best b = select_best_half(c.P, th, wrap_2pi(th + kTwoPi * ref), c.YM, ok, lane);
-    const Cand cb = {__shfl(c.P, b.lane), __shfl(c.YM, b.lane), __shfl(c.MM, b.lane), __shfl(c.Mbar, b.lane)};
-    if (hl == 0 && mine) {
+    bool ok[2];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl)
+      ok[sl] = valid[sl] && (c[sl].MM > floor_mm || stout == ST_DEGENERATE) && (!pos || c[sl].YM > 0.0);
+    const unsigned okm = (unsigned)(__ballot(ok[0] || ok[1]) >> (16 * row)) & 0xffffu;
+    const bool none = pos && stout != ST_DEGENERATE && okm == 0u;
+    const double P2[2] = {c[0].P, c[1].P}, ym2[2] = {c[0].YM, c[1].YM};
+    const double ta2[2] = {wrap_2pi(th[0] + kTwoPi * ref), wrap_2pi(th[1] + kTwoPi * ref)};
+    int bslot;
+    const Best b = select_best_row(P2, th, ta2, ym2, ok, lane, bslot);
+    Cand cb = {__shfl(c[0].P, b.lane), __shfl(c[0].YM, b.lane), __shfl(c[0].MM, b.lane), __shfl(c[0].Mbar, b.lane)};
+    if (bslot) cb = Cand{__shfl(c[1].P, b.lane), __shfl(c[1].YM, b.lane), __shfl(c[1].MM, b.lane), __shfl(c[1].Mbar, b.lane)};
+    if (l == 0 && mine) {
       if (st == ST_BAD_LC) {
         a.power[pidx] = 0.0; a.phase[pidx] = 0.0; a.amp[pidx] = 0.0; a.offset[pidx] = 0.0;
         if (a.status) a.status[pidx] = ST_BAD_LC;
@@ -1288,8 +1321,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
-// Writes the deconvolved sums of every pair (3H complex per pair: Z_w(k j),
-// k = 1..2H, then Z_y(k j), k = 1..H with the 1/sqrt(YY) normalisation undone).
 template <typename R>
 __global__ __launch_bounds__(64) void k_gather_sums(SolveArgs a, double* out) {
   const int lane = wave_lane();
@@ -1417,14 +1448,18 @@ hipError_t launch_score(const SolveArgs& a, const double* rec, int64_t p0, int64
   return hipGetLastError();
 }
 
-// Newton-candidate pairs two per wavefront (see k_score2); `done` (nullable):
+// Newton-candidate pairs four per wavefront (see k_score4); `done` (nullable):
 // an event the launch itself records at the kernel's end.
-hipError_t launch_score2(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves, hipStream_t st,
+hipError_t launch_score_newton(const SolveArgs& a, const double* rec, int64_t p0, int64_t np, int waves, hipStream_t st,
                          hipEvent_t done) {
-  const int w2 = (int)std::max<int64_t>(1, std::min<int64_t>(waves, (np + 1) / 2));
-  hipExtLaunchKernelGGL(k_score2, dim3((unsigned)w2), dim3(64), 2 * score_lds_bytes(a.H), st, nullptr, done, 0, a, rec,
-                        p0, np);
-  return hipGetLastError();
+  {
+    // the first round's roots (at most 32 per frequency) in two rounds of a
+    // 16-lane row: four frequencies per wavefront
+    const int w4 = (int)std::max<int64_t>(1, std::min<int64_t>(waves, (np + 3) / 4));
+    hipExtLaunchKernelGGL(k_score4, dim3((unsigned)w4), dim3(64), 4 * score_lds_bytes(a.H), st, nullptr, done, 0, a,
+                          rec, p0, np);
+    return hipGetLastError();
+  }
 }
 
 hipError_t launch_gather_sums(int precision, const SolveArgs& a, double* out, int blocks, hipStream_t st) {
