@@ -370,8 +370,8 @@ SINGLE_WORKLOADS = {
                              "oversample 5, f_max=10/day"),
 }
 
-# kernels behind each stage for H <= 10 (two frequencies per wavefront in the
-# Newton + Sturm kernel; the one-frequency k_newton_sturm serves H = 11)
+# kernels behind each stage for H <= 10 (four frequencies per wavefront in the
+# Newton + Sturm kernel; the one-frequency k_newton_sturm serves H >= 11)
 KERNEL_NAMES = {"plain_qr": "k_qr (companion QR, FP64 vector)",
                 "fallback_qr": "k_qr on the Aberth tier's leftovers (FP64 vector)",
                 "newton_sturm": "k_newton_sturm4 (FP64 vector)",
