@@ -921,9 +921,13 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
       hipEvent_t rc2 = learn_ev();
       if (rc2) HIP_TRY(hipEventRecord(rc2, st));
       // what the Aberth tier leaves is usually nothing or a few frequencies:
-      // a launch of one wave per CU serves it through the queue
-      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, B.fb2_list, ctr + 1,
-                        B.counters, ctr + 4, std::min(w_qr, (int)grid_waves(P, 1, np)), st));
+      // a launch of one wave per CU serves it through the queue.  Above
+      // D = 64 (or with the forced fallback) the Sturm count is refused on
+      // most frequencies and the list holds most of them: the plain solve's
+      // launch shape
+      const bool big_list = 6 * P->H - 2 > 64 || (P->opt.flags & FTP_FLAG_FORCE_FALLBACK);
+      HIP_TRY(launch_qr(P->H, rec, RL.stride, np, B.fb2_list, ctr + 1, B.counters, ctr + 4,
+                        big_list ? w_qr : std::min(w_qr, (int)grid_waves(P, 1, np)), st));
     }
     hipEvent_t r1 = root_ev();
     if (r1) HIP_TRY(hipEventRecord(r1, st));

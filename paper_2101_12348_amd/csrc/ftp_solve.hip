@@ -86,12 +86,33 @@ __device__ __forceinline__ double cayley_dot(const double* rc, const double* col
 // column update; the next bulge column is broadcast from the updating lanes'
 // registers.  Returns the number of sweeps, or -1 when the iteration limit is
 // reached (the remaining diagonal entries are then used as estimates).
+// Storage of the N x N upper Hessenberg matrix the QR iteration works on.
+// Dense: row-major with leading dimension N + 1.  Packed: column j holds rows
+// 0 .. min(j + 3, N - 1) (the Hessenberg band and the chase's bulge, which
+// never leaves it) at cs(j) + i: (N - 3)(N - 4)/2 + 4 (N - 3) + 3 N doubles,
+// 15 KB instead of 27 KB at N = 58, so twice as many matrices fit the LDS
+// of a compute unit (the iteration is latency-bound: occupancy is its
+// throughput).
 template <int N>
-__device__ __forceinline__ int hqr_wave(double* A, double* wr, double* wi, const int lane) {
-  constexpr int ld = N + 1;
+struct DenseHess {
+  double* A;
+  __device__ __forceinline__ double& operator()(int i, int j) const { return A[i * (N + 1) + j]; }
+};
+template <int N>
+struct PackedHess {
+  double* P;
+  __host__ __device__ static constexpr int cs(int j) {
+    return ((j < N - 3 ? j : N - 3) * ((j < N - 3 ? j : N - 3) - 1)) / 2 + 4 * (j < N - 3 ? j : N - 3) +
+           (j - (j < N - 3 ? j : N - 3)) * N;
+  }
+  __device__ __forceinline__ double& operator()(int i, int j) const { return P[cs(j) + i]; }
+};
+
+template <int N, typename Acc>
+__device__ __forceinline__ int hqr_wave(const Acc& X, double* wr, double* wi, const int lane) {
   double anorm = 0.0;
   if (lane < N) {
-    for (int j = (lane > 0 ? lane - 1 : 0); j < N; ++j) anorm += fabs(A[lane * ld + j]);
+    for (int j = (lane > 0 ? lane - 1 : 0); j < N; ++j) anorm += fabs(X(lane, j));
   }
   anorm = wave_sum(anorm);
   if (anorm == 0.0) anorm = 1.0;
@@ -101,21 +122,21 @@ __device__ __forceinline__ int hqr_wave(double* A, double* wr, double* wi, const
   while (m >= 0) {
     bool ok = false;
     if (lane >= 1 && lane <= m) {
-      double sd = fabs(A[(lane - 1) * ld + lane - 1]) + fabs(A[lane * ld + lane]);
+      double sd = fabs(X(lane - 1, lane - 1)) + fabs(X(lane, lane));
       if (sd == 0.0) sd = anorm;
-      ok = fabs(A[lane * ld + lane - 1]) <= kEps * sd;
+      ok = fabs(X(lane, lane - 1)) <= kEps * sd;
     }
     const unsigned long long mask = __ballot(ok);
     const int l = mask ? 63 - __clzll(mask) : 0;
     if (l == m) {
-      if (lane == 0) { wr[m] = A[m * ld + m]; wi[m] = 0.0; }
+      if (lane == 0) { wr[m] = X(m, m); wi[m] = 0.0; }
       m -= 1;
       its = 0;
       continue;
     }
     if (l == m - 1) {
-      const double a = A[(m - 1) * ld + m - 1], b = A[(m - 1) * ld + m];
-      const double c = A[m * ld + m - 1], d = A[m * ld + m];
+      const double a = X(m - 1, m - 1), b = X(m - 1, m);
+      const double c = X(m, m - 1), d = X(m, m);
       const double p = 0.5 * (a - d);
       const double q = p * p + b * c;
       if (lane == 0) {
@@ -136,22 +157,22 @@ __device__ __forceinline__ int hqr_wave(double* A, double* wr, double* wi, const
     }
     if (sweeps >= maxit) { failed = true; break; }
     double S, T;
-    const double amm = A[m * ld + m], am1 = A[(m - 1) * ld + m - 1];
+    const double amm = X(m, m), am1 = X(m - 1, m - 1);
     if (its == 10 || its == 20) {
-      const double sx = fabs(A[m * ld + m - 1]) + fabs(A[(m - 1) * ld + m - 2]);
+      const double sx = fabs(X(m, m - 1)) + fabs(X(m - 1, m - 2));
       const double c = amm + 0.75 * sx;
       S = 2.0 * c;
       T = c * c - 0.4375 * sx * sx;
     } else {
       S = am1 + amm;
-      T = am1 * amm - A[(m - 1) * ld + m] * A[m * ld + m - 1];
+      T = am1 * amm - X(m - 1, m) * X(m, m - 1);
     }
     ++its;
     ++sweeps;
-    const double all = A[l * ld + l], al1 = A[(l + 1) * ld + l];
-    double x = all * all + A[l * ld + l + 1] * al1 - S * all + T;
-    double y = al1 * (all + A[(l + 1) * ld + l + 1] - S);
-    double z = (l + 2 <= m) ? A[(l + 2) * ld + l + 1] * al1 : 0.0;
+    const double all = X(l, l), al1 = X(l + 1, l);
+    double x = all * all + X(l, l + 1) * al1 - S * all + T;
+    double y = al1 * (all + X(l + 1, l + 1) - S);
+    double z = (l + 2 <= m) ? X(l + 2, l + 1) * al1 : 0.0;
     for (int k = l; k <= m - 1; ++k) {
       const bool three = k < m - 1;
       const double s2 = x * x + y * y + z * z;
@@ -167,28 +188,28 @@ __device__ __forceinline__ int hqr_wave(double* A, double* wr, double* wi, const
         // row update: rows k..k+2, columns k..m (lane = column); the bulge
         // column k-1 becomes (alpha, 0, 0)
         if (lane >= k && lane <= m) {
-          const double b0 = A[k * ld + lane], b1 = A[(k + 1) * ld + lane];
-          const double b2 = three ? A[(k + 2) * ld + lane] : 0.0;
+          const double b0 = X(k, lane), b1 = X(k + 1, lane);
+          const double b2 = three ? X(k + 2, lane) : 0.0;
           const double w = tau * (b0 + v1 * b1 + v2 * b2);
-          A[k * ld + lane] = b0 - w;
-          A[(k + 1) * ld + lane] = b1 - w * v1;
-          if (three) A[(k + 2) * ld + lane] = b2 - w * v2;
+          X(k, lane) = b0 - w;
+          X(k + 1, lane) = b1 - w * v1;
+          if (three) X(k + 2, lane) = b2 - w * v2;
         } else if (k > l && lane == k - 1) {
-          A[k * ld + lane] = alpha;
-          A[(k + 1) * ld + lane] = 0.0;
-          if (three) A[(k + 2) * ld + lane] = 0.0;
+          X(k, lane) = alpha;
+          X(k + 1, lane) = 0.0;
+          if (three) X(k + 2, lane) = 0.0;
         }
         wave_sync();
         // column update: columns k..k+2, rows l..min(k+3, m) (lane = row)
         const int ihi = k + 3 < m ? k + 3 : m;
         if (lane >= l && lane <= ihi) {
-          const double c0 = A[lane * ld + k], c1 = A[lane * ld + k + 1];
-          const double c2 = three ? A[lane * ld + k + 2] : 0.0;
+          const double c0 = X(lane, k), c1 = X(lane, k + 1);
+          const double c2 = three ? X(lane, k + 2) : 0.0;
           const double w = tau * (c0 + v1 * c1 + v2 * c2);
           a0n = c0 - w;
-          A[lane * ld + k] = a0n;
-          A[lane * ld + k + 1] = c1 - w * v1;
-          if (three) A[lane * ld + k + 2] = c2 - w * v2;
+          X(lane, k) = a0n;
+          X(lane, k + 1) = c1 - w * v1;
+          if (three) X(lane, k + 2) = c2 - w * v2;
         }
         wave_sync();
         if (k + 1 <= m - 1) {
@@ -197,15 +218,15 @@ __device__ __forceinline__ int hqr_wave(double* A, double* wr, double* wi, const
           z = (k + 1 < m - 1) ? rdlane(a0n, k + 3) : 0.0;
         }
       } else if (k + 1 <= m - 1) {
-        x = A[(k + 1) * ld + k];
-        y = A[(k + 2) * ld + k];
-        z = (k + 1 < m - 1) ? A[(k + 3) * ld + k] : 0.0;
+        x = X(k + 1, k);
+        y = X(k + 2, k);
+        z = (k + 1 < m - 1) ? X(k + 3, k) : 0.0;
       }
     }
   }
   wave_sync();
   if (failed) {
-    if (lane <= m) { wr[lane] = A[lane * ld + lane]; wi[lane] = 0.0; }
+    if (lane <= m) { wr[lane] = X(lane, lane); wi[lane] = 0.0; }
     wave_sync();
     return -1;
   }
@@ -218,15 +239,16 @@ __device__ __forceinline__ int hqr_wave(double* A, double* wr, double* wi, const
 // companion matrix of the Cayley polynomial has entries spread over many
 // orders of magnitude (binomial growth with D), and without this step the QR
 // iteration loses the roots' accuracy relative to the matrix norm.
-template <int N>
-__device__ __forceinline__ void balance_wave(double* A, const int lane) {
-  constexpr int ld = N + 1;
+template <int N, typename Acc>
+__device__ __forceinline__ void balance_wave(const Acc& X, const int lane) {
   for (int sweep = 0; sweep < 16; ++sweep) {
     bool done = true;
     for (int i = 0; i < N; ++i) {
+      // off-diagonal entries of column i and row i inside the band that can
+      // be nonzero (rows up to the column + 3)
       const bool off = lane < N && lane != i;
-      double c = wave_sum(off ? fabs(A[lane * ld + i]) : 0.0);
-      const double r = wave_sum(off ? fabs(A[i * ld + lane]) : 0.0);
+      double c = wave_sum(off && lane <= i + 3 ? fabs(X(lane, i)) : 0.0);
+      const double r = wave_sum(off && i <= lane + 3 ? fabs(X(i, lane)) : 0.0);
       if (!(c > 0.0) || !(r > 0.0) || !isfinite(c) || !isfinite(r)) continue;   // (also ends the loops below)
       const double s = c + r;
       double f = 1.0, g = 0.5 * r;
@@ -237,8 +259,8 @@ __device__ __forceinline__ void balance_wave(double* A, const int lane) {
         done = false;
         const double fi = 1.0 / f;
         if (lane < N) {
-          A[i * ld + lane] *= fi;
-          A[lane * ld + i] *= f;
+          if (i <= lane + 3) X(i, lane) *= fi;
+          if (lane <= i + 3) X(lane, i) *= f;
         }
         wave_sync();
       }
@@ -433,8 +455,21 @@ __device__ __forceinline__ void balance_wave2(double* A, const int lane) {
   }
 }
 
+// Packed storage where the dense matrix would hold a compute unit's LDS to
+// fewer than ~10 matrices (N >= 46); below, the dense layout's simpler
+// addressing is faster (measured: N = 34 dense 11.5 ms, packed 12.0 ms per
+// 5e4 matrices; N = 58 dense 412 ms, packed 292 ms per 3e5).
+__host__ __device__ inline constexpr bool qr_packed(int N) { return N >= 46 && N <= 64; }
+
+// doubles of the matrix storage of k_qr<N>, even so that the eigenvalue
+// arrays after it stay aligned
+__host__ __device__ inline size_t qr_mat_doubles(int N) {
+  const int j1 = N > 3 ? N - 3 : 0;   // PackedHess<N>::cs(N)
+  const size_t m = qr_packed(N) ? (size_t)((j1 * (j1 - 1)) / 2 + 4 * j1 + (N - j1) * N) : (size_t)N * (N + 1);
+  return (m + 1) & ~(size_t)1;
+}
 __host__ __device__ inline size_t qr_lds_bytes(int D) {
-  return ((size_t)D * (D + 1) + 2 * (size_t)D + 2) * sizeof(double);
+  return (qr_mat_doubles(D) + 2 * (size_t)D + 2) * sizeof(double);
 }
 
 // Companion eigenvalues for the pairs of a chunk (or of a list of them).
@@ -448,9 +483,8 @@ __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, 
   // waves on the step's critical path)
   __builtin_amdgcn_s_setprio(2);
   extern __shared__ double smq[];
-  constexpr int ld = N + 1;
   double* A = smq;
-  double* wr = A + N * ld;
+  double* wr = A + qr_mat_doubles(N);
   double* wi = wr + N;
   const int lane = wave_lane();
   const RecLayout RL((N + 2) / 6);
@@ -464,20 +498,31 @@ __global__ __launch_bounds__(64) void k_qr(double* rec, int stride, int64_t np, 
     if (st == ST_BAD_LC || st == ST_CONSTANT) continue;
     const double* f = R + RL.f;
     const double lead = f[N];
-    for (int i = lane; i < N; i += 64) {
-      for (int j = 0; j < N; ++j) A[i * ld + j] = 0.0;
-      if (i > 0) A[i * ld + i - 1] = 1.0;
-    }
-    wave_sync();
-    for (int c = lane; c < N; c += 64) A[c] = -f[N - 1 - c] / lead;
-    wave_sync();
     int sw;
     if constexpr (N > 64) {
+      constexpr int ld = N + 1;
+      for (int i = lane; i < N; i += 64) {
+        for (int j = 0; j < N; ++j) A[i * ld + j] = 0.0;
+        if (i > 0) A[i * ld + i - 1] = 1.0;
+      }
+      wave_sync();
+      for (int c = lane; c < N; c += 64) A[c] = -f[N - 1 - c] / lead;
+      wave_sync();
       balance_wave2<N>(A, lane);
       sw = hqr_wave2<N>(A, wr, wi, lane);
     } else {
-      balance_wave<N>(A, lane);
-      sw = hqr_wave<N>(A, wr, wi, lane);
+      // the companion matrix of f: zeros, the first row, the subdiagonal of ones
+      auto run = [&](const auto& X) {
+        for (int q = lane; q < (int)qr_mat_doubles(N); q += 64) A[q] = 0.0;
+        wave_sync();
+        if (lane < N) X(0, lane) = -f[N - 1 - lane] / lead;
+        if (lane >= 1 && lane < N) X(lane, lane - 1) = 1.0;
+        wave_sync();
+        balance_wave<N>(X, lane);
+        return hqr_wave<N>(X, wr, wi, lane);
+      };
+      if constexpr (qr_packed(N)) sw = run(PackedHess<N>{A});
+      else sw = run(DenseHess<N>{A});
     }
     if (sw < 0) {
       if (lane == 0) R[RL.meta + M_STATUS] = (double)ST_NO_CONVERGE;
