@@ -165,70 +165,142 @@ __device__ int sturm_count_line_reg(double gv, double gtop, int D, int lane, int
   return c.ok ? raw : -1;
 }
 
-// Distinct real roots of g for 64 < D <= 127, or -1 (`raw` as above):
-// coefficient c = lane + 64 s in register s (g0, g1; zero above D).  The
-// steps are those of sturm_step on 128-coefficient members (the shift by one
-// power of x carries lane 63 of register 0 into lane 0 of register 1); once
-// the older member's degree is below 64 the chain goes on in one register.
-// All lanes active.  At these degrees the coefficients of the Cayley
-// polynomial span so many orders of magnitude that the early remainders'
-// leading coefficients fall below 1e-13 of their largest ones, so the step
-// test refuses the chain on (nearly) every frequency and the solvers send it
-// on to the companion solve; a test relative to the terms that form each
-// leading coefficient would pass, but trusts wrong counts near close pairs of
-// roots at D = 88.
-__device__ int sturm_count_wave2(double g0, double g1, int D, int lane, int& raw) {
-  const double gtop = lrdlane(g1, D - 64);
-  const double ag = fabs(gtop), sgn = gtop > 0.0 ? 1.0 : -1.0;
-  const double sa = fast_rcp_d(ag + 1e-300), sb = fast_rcp_d(D * ag + 1e-300);
+// ---- double-double arithmetic (value hi + lo, |lo| <= ulp(hi) / 2): the
+// error-free transformations of Knuth (TAOCP vol. 2, two-sum) and Dekker
+// (1971, the product, here through the fused multiply-add).  Contraction of
+// a product into a later sum is off in these helpers: the error terms assume
+// each operation rounded on its own (a fused p + e in the product's
+// normalisation drops the double-double precision to double's).
+struct dd { double hi, lo; };
+__device__ __forceinline__ dd dd_two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  const double s = a + b, bb = s - a;
+  return dd{s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dd dd_quick(double a, double b) {   // |a| >= |b|
+#pragma clang fp contract(off)
+  const double s = a + b;
+  return dd{s, b - (s - a)};
+}
+__device__ __forceinline__ dd dd_add(dd x, dd y) {
+#pragma clang fp contract(off)
+  dd s = dd_two_sum(x.hi, y.hi);
+  const dd t = dd_two_sum(x.lo, y.lo);
+  s.lo += t.hi;
+  s = dd_quick(s.hi, s.lo);
+  s.lo += t.lo;
+  return dd_quick(s.hi, s.lo);
+}
+__device__ __forceinline__ dd dd_neg(dd x) { return dd{-x.hi, -x.lo}; }
+__device__ __forceinline__ dd dd_mul(dd x, dd y) {
+#pragma clang fp contract(off)
+  const double p = x.hi * y.hi;
+  double e = fma(x.hi, y.hi, -p);
+  e = fma(x.hi, y.lo, fma(x.lo, y.hi, e));
+  return dd_quick(p, e);
+}
+__device__ __forceinline__ dd dd_div(dd x, dd y) {
+#pragma clang fp contract(off)
+  // two quotient digits: q1 = x / y in double, q2 from the remainder
+  const double q1 = x.hi / y.hi;
+  const dd r = dd_add(x, dd_neg(dd_mul(dd{q1, 0.0}, y)));
+  const double q2 = r.hi / y.hi;
+  return dd_quick(q1, q2);
+}
+__device__ __forceinline__ dd dd_ldexp(dd x, int e) { return dd{ldexp(x.hi, e), ldexp(x.lo, e)}; }
+__device__ __forceinline__ dd dd_lane(dd v, int src) { return dd{lrdlane(v.hi, src), lrdlane(v.lo, src)}; }
+// v from lane - 1 (lane 0: 0), both parts
+__device__ __forceinline__ dd dd_shr1(dd v) { return dd{lane_shr1(v.hi), lane_shr1(v.lo)}; }
+
+// largest |v| over the wavefront, from the doubles' high words (within a
+// factor 1 + 2^-20: enough for the chain's tests)
+__device__ __forceinline__ double wave_max_abs(double v) {
+  return from_hiword(wave_max_int(hiword(v) & 0x7fffffff));
+}
+
+// Distinct real roots of g for 64 < D <= 127 in double-double, or -1
+// (`raw`: the count regardless of the tests).  Coefficient c = lane + 64 s of
+// a member in register s.  Each remainder is the exact-arithmetic step
+// (quotient q1 x + q0 from the two leading coefficients, by double-double
+// division) and each member is scaled by a power of two that brings its
+// leading coefficient into [1, 2) (exact).  The chain is trusted when every
+// remainder's largest coefficient exceeds 1e-24 of the larger of its two
+// members' and its leading coefficient 1e-24 of its largest, all finite: in
+// double precision the spread of the Cayley polynomial's coefficients at
+// these degrees (1e-15 .. 1e-19) defeats the 1e-13 test of the other chains,
+// while 106 bits leave room (a 106-bit emulation of this chain trusted and
+// matched the exact count on every polynomial tried at H = 12..15, also where
+// a double-precision chain with a relaxed test was wrong).  All lanes active.
+__device__ int sturm_count_dd(double g0, double g1, int D, int lane, int& raw) {
+#pragma clang fp contract(off)
   const int c0 = lane, c1 = lane + 64;
-  // coefficient c + 1 of g (none above 127)
+  // g and g' (exact in double-double: (c + 1) g_{c+1} is one product)
   const double n0 = lane_shl1(g0), n1 = lane_shl1(g1);
   const double g64 = lrdlane(g1, 0);
   const double u0 = lane == 63 ? g64 : n0;
-  const double d0 = c0 < D ? (c0 + 1) * u0 : 0.0, d1 = c1 < D ? (c1 + 1) * n1 : 0.0;
-  double A0 = c0 == D ? sgn : g0 * sa, A1 = c1 == D ? sgn : g1 * sa;
-  double B0 = c0 == D - 1 ? sgn : d0 * sb, B1 = c1 == D - 1 ? sgn : d1 * sb;
-  SturmChain c;
-  c.ok = ag > 0.0 && ag < INFINITY;
-  c.al = sgn;
-  c.bl = sgn;
-  c.hMA = max(wave_max_int(max(hiword(A0) & 0x7fffffff, hiword(A1) & 0x7fffffff)), kHi1);
-  c.hMB = wave_max_int(max(hiword(B0) & 0x7fffffff, hiword(B1) & 0x7fffffff));
-  c.vp = 0;
-  c.sp = gtop > 0.0 ? 1 : 0;
-  int q = 2;
-  for (; D - q + 2 >= 64; ++q) {   // the older member reaches coefficient 64
-    const int db = D - q + 1;
-    const double s0 = lane_shr1(B0), s1r = lane_shr1(B1), b63 = lrdlane(B0, 63);
-    const double s1 = lane == 0 ? b63 : s1r;
-    const double ab = c.al * c.bl;
-    double t0 = A0 - ab * s0, t1 = A1 - ab * s1;
-    const double q0 = (db >= 64 ? lrdlane(t1, db - 64) : lrdlane(t0, db)) * c.bl;
-    t0 = c0 < db ? t0 - q0 * B0 : 0.0;
-    t1 = c1 < db ? t1 - q0 * B1 : 0.0;
-    const double lead = db - 1 >= 64 ? lrdlane(t1, db - 65) : lrdlane(t0, db - 1);
-    const int hl = hiword(lead), hla = hl & 0x7fffffff;
-    const int hr = wave_max_int(max(hiword(t0) & 0x7fffffff, hiword(t1) & 0x7fffffff));
-    c.ok = c.ok && sturm_step_ok(hr, hla, max(c.hMA, c.hMB));
-    const int tp = (int)((unsigned)hl >> 31);
-    c.vp += tp ^ c.sp;
-    c.sp = tp;
-    const double sc = fast_rcp_d(fabs(lead) + 1e-300);
-    A0 = B0;
-    A1 = B1;
-    c.al = c.bl;
-    c.hMA = c.hMB;
-    B0 = -t0 * sc;
-    B1 = -t1 * sc;
-    c.bl = from_hiword((hl & 0x80000000) ^ 0xbff00000);
-    c.hMB = sturm_member_hi(hr, hla);
+  dd A[2], B[2];
+  A[0] = dd{g0, 0.0};
+  A[1] = dd{g1, 0.0};
+  {
+    const double p0 = (double)(c0 + 1) * u0, p1 = (double)(c1 + 1) * n1;
+    B[0] = c0 < D ? dd{p0, fma((double)(c0 + 1), u0, -p0)} : dd{0.0, 0.0};
+    B[1] = c1 < D ? dd{p1, fma((double)(c1 + 1), n1, -p1)} : dd{0.0, 0.0};
   }
-  c.A = A0;
-  c.B = B0;
-  for (; q <= D; ++q) sturm_step(c, D, q, lane);
-  raw = D - 2 * c.vp;
-  return c.ok ? raw : -1;
+  // scale both to leading coefficients in [1, 2) in magnitude
+  auto lead_of = [&](const dd (&X)[2], int deg) { return deg >= 64 ? dd_lane(X[1], deg - 64) : dd_lane(X[0], deg); };
+  int e;
+  {
+    dd la = lead_of(A, D);
+    frexp(la.hi, &e);
+    A[0] = dd_ldexp(A[0], 1 - e);
+    A[1] = dd_ldexp(A[1], 1 - e);
+    dd lb = lead_of(B, D - 1);
+    frexp(lb.hi, &e);
+    B[0] = dd_ldexp(B[0], 1 - e);
+    B[1] = dd_ldexp(B[1], 1 - e);
+  }
+  bool ok = lead_of(A, D).hi != 0.0 && isfinite(lead_of(A, D).hi) && lead_of(B, D - 1).hi != 0.0;
+  double mA = wave_max_abs(fmax(fabs(A[0].hi), fabs(A[1].hi)));
+  double mB = wave_max_abs(fmax(fabs(B[0].hi), fabs(B[1].hi)));
+  int sp = lead_of(A, D).hi > 0.0 ? 1 : 0;
+  int vp = 0;
+  {
+    const int tb = lead_of(B, D - 1).hi > 0.0 ? 1 : 0;
+    vp += tb ^ sp;
+    sp = tb;
+  }
+  for (int db = D - 1; db >= 1; --db) {   // B has degree db, A degree db + 1
+    const bool two = db + 1 >= 64;         // (wave-uniform)
+    const dd at = lead_of(A, db + 1), bt = lead_of(B, db);
+    const dd q1 = dd_div(at, bt);
+    // t = A - q1 x B (the coefficient db + 1 cancels)
+    dd sh0 = dd_shr1(B[0]), sh1 = dd_shr1(B[1]);
+    const dd b63 = dd_lane(B[0], 63);
+    if (lane == 0) sh1 = b63;
+    dd t0 = dd_add(A[0], dd_neg(dd_mul(q1, sh0)));
+    dd t1 = two ? dd_add(A[1], dd_neg(dd_mul(q1, sh1))) : dd{0.0, 0.0};
+    const dd ct = db >= 64 ? dd_lane(t1, db - 64) : dd_lane(t0, db);
+    const dd q0 = dd_div(ct, bt);
+    // rem = -(t - q0 B): coefficients below db
+    t0 = c0 < db ? dd_neg(dd_add(t0, dd_neg(dd_mul(q0, B[0])))) : dd{0.0, 0.0};
+    t1 = (two && c1 < db) ? dd_neg(dd_add(t1, dd_neg(dd_mul(q0, B[1])))) : dd{0.0, 0.0};
+    const dd lead = db - 1 >= 64 ? dd_lane(t1, db - 65) : dd_lane(t0, db - 1);
+    const double mr = wave_max_abs(fmax(fabs(t0.hi), fabs(t1.hi)));
+    ok = ok && isfinite(mr) && mr > 1e-24 * fmax(mA, mB) && fabs(lead.hi) > 1e-24 * mr;
+    const int tp = lead.hi > 0.0 ? 1 : 0;
+    vp += tp ^ sp;
+    sp = tp;
+    frexp(lead.hi, &e);
+    if (!(lead.hi != 0.0 && isfinite(lead.hi))) e = 0;
+    A[0] = B[0];
+    A[1] = B[1];
+    B[0] = dd_ldexp(t0, 1 - e);
+    B[1] = dd_ldexp(t1, 1 - e);
+    mA = mB;
+    mB = ldexp(mr, 1 - e);
+  }
+  raw = D - 2 * vp;
+  return ok ? raw : -1;
 }
 
 // v from lane addr / 4 (ds_bpermute, all lanes active)
@@ -454,12 +526,13 @@ __device__ __forceinline__ double newton_u_step(const double* cp, int D, int K, 
 // in the quadratic regime, a step small enough that the iterate it produced
 // is already within ~1e-14 of the root.  With steps s_{k-1}, s_k and the
 // error after step k about C s_k^2, C ~ s_k / s_{k-1}^2, the second test is
-// s_k^3 < 1e-14 s_{k-1}^2 (and s_k < 1e-6); a slowly (linearly) converging
+// s_k^3 < 1e-14 s_{k-1}^2 (with s_k < 1e-6 and s_{k-1} < 1e-3, so that both
+// steps are local ones, not a clamped jump); a slowly (linearly) converging
 // lane, as near a double root, passes only the first.  Saves the step that
 // would merely confirm convergence.
 __device__ __forceinline__ bool newton_settled(double sc, double& prev) {
   const double a = fabs(sc);
-  const bool c = a < 1e-12 || (a < 1e-6 && a * a * a < 1e-14 * prev * prev);
+  const bool c = a < 1e-12 || (a < 1e-6 && prev < 1e-3 && a * a * a < 1e-14 * prev * prev);
   prev = a;
   return c;
 }
@@ -741,7 +814,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     // Sturm count first: an ill-determined count (or fewer than the two real
     // roots every non-constant P has) sends the frequency on without Newton
     int raw;
-    int cnt = D > 64 ? sturm_count_wave2(gv, gv1, D, lane, raw) : sturm_count_line_reg(gv, gtop, D, lane, raw);
+    int cnt = D > 64 ? sturm_count_dd(gv, gv1, D, lane, raw) : sturm_count_line_reg(gv, gtop, D, lane, raw);
     if (cnt < 2) cnt = -1;
     const double phi0 = R[RL.meta + M_PHI0];
     double u = 0.0;
@@ -838,7 +911,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // uniform solvers trust): per pair, the Sturm count of the Cayley polynomial
 // f by the device code the Newton kernels use (sturm_count_rows4, four pairs
 // per wavefront, for H <= 10; sturm_count_line_reg for H = 11,
-// sturm_count_wave2 above), -1000 - n when the
+// sturm_count_dd above), -1000 - n when the
 // chain fails its test (n: the count it reached regardless), -2 for an
 // inactive pair; and the number of real
 // eigenvalues the companion QR (run before this kernel) marked in M_REAL_LO,
@@ -868,7 +941,7 @@ __global__ __launch_bounds__(64) void k_root_counts(const double* rec, int H, in
       const double gv = RA[RL.f + lane];
       const double gv1 = lane + 64 <= D ? RA[RL.f + 64 + lane] : 0.0;
       int raw;
-      cnt = D > 64 ? sturm_count_wave2(gv, gv1, D, lane, raw) : sturm_count_line_reg(gv, RA[RL.f + D], D, lane, raw);
+      cnt = D > 64 ? sturm_count_dd(gv, gv1, D, lane, raw) : sturm_count_line_reg(gv, RA[RL.f + D], D, lane, raw);
       if (cnt < 0) cnt = -1000 - raw;
     }
     if (lane < per && w0 + lane < np) {
