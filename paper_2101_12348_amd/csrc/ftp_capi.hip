@@ -783,7 +783,7 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
   auto root_ev = [&]() -> hipEvent_t { return B.timing ? next_root_event(P) : nullptr; };
   auto learn_ev = [&]() -> hipEvent_t { return B.timing ? next_learn_event(P) : nullptr; };
   const ftp_tuning& T = P->tune;
-  // scoring of the Newton-root pairs two per wavefront, on the side stream
+  // scoring of the Newton-root pairs four per wavefront, on the side stream
   const bool overlap_score =
       !dataset && (solver == FTP_SOLVER_LEARNED || solver == FTP_SOLVER_UNIFORM) && 6 * P->H - 2 < 64;
   // learned solver with a fusable network: features in rows of dinp bf16
