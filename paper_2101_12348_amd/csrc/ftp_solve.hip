@@ -1300,7 +1300,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int64_t lc = (int64_t)Rr[RL.meta + M_LC];
     const LcInfo& L = a.lcs[lc];
     const double ref = Rr[RL.meta + M_REF];
-    for (int d = l; d <= K; d += 16) W.r[d] = make_double2(Rr[RL.r + 2 * d], Rr[RL.r + 2 * d + 1]);
+    // (the evaluation reads mu, eta and Z: the Newton roots take no polish on R)
     for (int e = l; e <= 2 * H; e += 16) W.mu[e] = make_double2(Rr[RL.mu + 2 * e], Rr[RL.mu + 2 * e + 1]);
     for (int k = l; k < H; k += 16) {
       W.eta[k + 1] = make_double2(Rr[RL.eta + 2 * k], Rr[RL.eta + 2 * k + 1]);
