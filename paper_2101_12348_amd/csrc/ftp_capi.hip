@@ -33,7 +33,6 @@ __global__ void k_prep_points(const LcInfo*, int64_t, const int64_t*, int64_t, c
                               const double*, PointRec<R>*, PointRec<R>*, unsigned int*);
 __global__ void k_scan_blocks(const unsigned int*, int64_t, int64_t*, int64_t*);
 __global__ void k_scan_single(const unsigned int*, int64_t, int64_t*, int64_t*);
-constexpr int64_t kScanSingleMax = 1024 * 8;
 __global__ void k_scan_sums(int64_t*, int64_t);
 __global__ void k_scan_add(int64_t*, int64_t, const int64_t*, const unsigned int*, int64_t*);
 template <typename R>

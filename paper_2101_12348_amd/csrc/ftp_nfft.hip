@@ -368,7 +368,6 @@ __global__ __launch_bounds__(256) void k_prep_points(const LcInfo* __restrict__ 
 // to kScanSingleMax counts: thread k scans a contiguous run of
 // ceil(n / 1024) counts; the run totals are scanned across the workgroup.
 // out[n] and *total receive the sum.
-constexpr int64_t kScanSingleMax = 1024 * 8;
 __global__ __launch_bounds__(1024) void k_scan_single(const unsigned int* __restrict__ in, int64_t n,
                                                       int64_t* __restrict__ out, int64_t* __restrict__ total) {
   __shared__ int64_t sh[1024];

@@ -269,7 +269,6 @@ __device__ __forceinline__ void assemble_r(const FreqWork& W, int H, int lane, d
 // a half-wave, two frequencies per wavefront); every lane of the wavefront
 // calls this.
 __device__ __forceinline__ void assemble_poly(const FreqWork& W, int H, int lane, double2* scr, int nl = 64) {
-  const int K = 3 * H - 1;
   for (int e = lane; e <= 2 * H; e += nl) {
     double2 acc = make_double2(0.0, 0.0);
     if (e == 0) {
