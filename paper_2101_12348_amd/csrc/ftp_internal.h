@@ -12,7 +12,7 @@ constexpr int kTileCells = 2048;      // spreading tile (cells per workgroup)
 constexpr int kTileShift = 11;        // log2(kTileCells)
 constexpr int kFixedShift = 60;       // fixed-point scale 2^60 for exact accumulation
 constexpr int kMaxPasses = 4;
-constexpr int64_t kScanSingleMax = 1024 * 8;   // tile counts the one-workgroup scan handles
+constexpr int64_t kScanSingleMax = 1024 * 16;   // tile counts the one-workgroup scan handles (16 per thread)
 constexpr int kTwiddleN = 4096;       // size of the in-LDS twiddle table (w_4096^r)
 
 // Per-lightcurve record.  The host fills the plan part; k_prep_stats fills the
