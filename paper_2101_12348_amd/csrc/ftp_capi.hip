@@ -344,6 +344,7 @@ struct ftp_plan {
   // host staging (kept alive until the uploads completed)
   std::vector<LcInfo> h_lc;
   std::vector<int64_t> h_obs_off, h_freq_off, h_gtb;
+  std::vector<int32_t> h_lcb;   // lightcurve of pair b * kLcBlock of the chunk (b = 0..nb), see SolveArgs
   std::vector<FftGridPass> h_fft;
   std::vector<int64_t> h_items;
   std::vector<int64_t> fft_round_tab_off, fft_round_n, fft_round_items;
@@ -356,6 +357,7 @@ struct ftp_plan {
   DevBuf d_stage;
   LcInfo* d_lc = nullptr;
   int64_t *d_obs_off = nullptr, *d_freq_off = nullptr, *d_gtb = nullptr, *d_items = nullptr;
+  int32_t* d_lcb = nullptr;
   FftGridPass* d_fft = nullptr;
   hipEvent_t upload_done = nullptr;
   // side stream of the learned / uniform solve: the scoring of the pairs the
@@ -364,7 +366,7 @@ struct ftp_plan {
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   bool upload_pending = false;
-  size_t stage_sizes[6] = {0, 0, 0, 0, 0, 0};   // piece sizes of the tables last sent (all 0: none)
+  size_t stage_sizes[7] = {0, 0, 0, 0, 0, 0, 0};   // piece sizes of the tables last sent (all 0: none)
   ftp_stats last{};
   // stage timing (FTP_FLAG_TIME_STAGES): one event triple per lightcurve chunk
   // (NFFT start, NFFT end, solve end) and one pair per root-kernel launch
@@ -520,6 +522,19 @@ int plan_chunk(ftp_plan* P, int64_t lc0, int64_t lc1, const int64_t* obs_off, co
   P->h_obs_off[n] = obs_off[lc1] - obs_off[lc0];
   P->h_freq_off[n] = freq_off[lc1] - freq_off[lc0];
   P->h_gtb[2 * n] = tbase;
+  {
+    // lightcurve of every kLcBlock-th pair (and of the last): a pair's
+    // lightcurve lies between its block's two entries
+    const int64_t np_chunk = P->h_freq_off[n];
+    const int64_t nb = (np_chunk + kLcBlock - 1) / kLcBlock;
+    P->h_lcb.resize((size_t)nb + 1);
+    int64_t lc = 0;
+    for (int64_t b = 0; b <= nb; ++b) {
+      const int64_t pr = std::min<int64_t>(b * kLcBlock, std::max<int64_t>(np_chunk - 1, 0));
+      while (lc + 1 < n && P->h_freq_off[lc + 1] <= pr) ++lc;
+      P->h_lcb[b] = (int32_t)lc;
+    }
+  }
   *n_grid_elems = goff;
   *n_tiles = tbase;
   return FTP_OK;
@@ -659,11 +674,12 @@ int upload_tables(ftp_plan* P, int64_t n_lc, hipStream_t st, bool with_fft) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t s_lc = sizeof(LcInfo) * n_lc, s_off = sizeof(int64_t) * (n_lc + 1),
                s_gtb = sizeof(int64_t) * (2 * n_lc + 1), s_fft = sizeof(FftGridPass) * P->h_fft.size(),
-               s_it = sizeof(int64_t) * P->h_items.size();
+               s_it = sizeof(int64_t) * P->h_items.size(), s_lcb = sizeof(int32_t) * P->h_lcb.size();
   const size_t o_lc = 0, o_obs = al(o_lc + s_lc), o_freq = al(o_obs + s_off), o_gtb = al(o_freq + s_off),
-               o_fft = al(o_gtb + s_gtb), o_it = al(o_fft + s_fft), total = al(o_it + s_it);
+               o_fft = al(o_gtb + s_gtb), o_it = al(o_fft + s_fft), o_lcb = al(o_it + s_it),
+               total = al(o_lcb + s_lcb);
   if (total > P->h_stage_cap) {
-    for (int k = 0; k < 6; ++k) P->stage_sizes[k] = 0;
+    for (int k = 0; k < 7; ++k) P->stage_sizes[k] = 0;
     if (P->h_stage) HIP_TRY(hipHostFree(P->h_stage));
     P->h_stage = nullptr;
     P->h_stage_cap = 0;
@@ -674,22 +690,22 @@ int upload_tables(ftp_plan* P, int64_t n_lc, hipStream_t st, bool with_fft) {
   // the staging still holds the tables last sent, and the device copy is
   // complete (waited for above); the kernels rewrite only the fields the
   // device fills, which the host leaves 0. Tables equal to those need no copy.
-  const size_t sizes[6] = {s_lc, s_off, s_off, s_gtb, s_fft, s_it};
-  const void* src[6] = {P->h_lc.data(), P->h_obs_off.data(), P->h_freq_off.data(), P->h_gtb.data(),
-                        P->h_fft.data(), P->h_items.data()};
-  const size_t offs[6] = {o_lc, o_obs, o_freq, o_gtb, o_fft, o_it};
+  const size_t sizes[7] = {s_lc, s_off, s_off, s_gtb, s_fft, s_it, s_lcb};
+  const void* src[7] = {P->h_lc.data(), P->h_obs_off.data(), P->h_freq_off.data(), P->h_gtb.data(),
+                        P->h_fft.data(), P->h_items.data(), P->h_lcb.data()};
+  const size_t offs[7] = {o_lc, o_obs, o_freq, o_gtb, o_fft, o_it, o_lcb};
   bool same = P->d_stage.p != nullptr && P->d_stage.cap >= total;
-  for (int k = 0; k < 6 && same; ++k)
+  for (int k = 0; k < 7 && same; ++k)
     same = sizes[k] == P->stage_sizes[k] && (sizes[k] == 0 || std::memcmp(h + offs[k], src[k], sizes[k]) == 0);
   if (!same) {
-    for (int k = 0; k < 6; ++k) P->stage_sizes[k] = 0;
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 7; ++k) P->stage_sizes[k] = 0;
+    for (int k = 0; k < 7; ++k)
       if (sizes[k]) std::memcpy(h + offs[k], src[k], sizes[k]);
     if ((rc = P->d_stage.ensure(total))) return rc;
     HIP_TRY(hipMemcpyAsync(P->d_stage.p, h, total, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(P->upload_done, st));
     P->upload_pending = true;
-    for (int k = 0; k < 6; ++k) P->stage_sizes[k] = sizes[k];
+    for (int k = 0; k < 7; ++k) P->stage_sizes[k] = sizes[k];
   }
   unsigned char* d = P->d_stage.as<unsigned char>();
   P->d_lc = reinterpret_cast<LcInfo*>(d + o_lc);
@@ -698,6 +714,7 @@ int upload_tables(ftp_plan* P, int64_t n_lc, hipStream_t st, bool with_fft) {
   P->d_gtb = reinterpret_cast<int64_t*>(d + o_gtb);
   P->d_fft = reinterpret_cast<FftGridPass*>(d + o_fft);
   P->d_items = reinterpret_cast<int64_t*>(d + o_it);
+  P->d_lcb = s_lcb ? reinterpret_cast<int32_t*>(d + o_lcb) : nullptr;
   return FTP_OK;
 }
 
@@ -971,6 +988,7 @@ SolveArgs base_args(ftp_plan* P, int64_t n_lc, int64_t n_pairs) {
   a.lcs = P->d_lc;
   a.n_lc = n_lc;
   a.freq_off = P->d_freq_off;
+  a.lc_block = n_lc > 1 ? P->d_lcb : nullptr;
   a.total = n_pairs;
   a.grids = P->grids.p;
   a.alpha = P->alpha.as<double2>();
@@ -1433,6 +1451,7 @@ int ftp_solve_sums(ftp_plan* P, const double* sums, const double* lc_stats, doub
   L.inv_sqrt_yy = 1.0 / std::sqrt(lc_stats[2]);
   P->h_obs_off.assign(2, 0);
   P->h_freq_off = {0, n_f};
+  P->h_lcb.clear();
   P->h_gtb.assign(3, 0);
   if ((rc = upload_tables(P, 1, st, false))) return rc;
   SolveArgs a = base_args(P, 1, n_f);
@@ -1579,6 +1598,7 @@ int ftp_root_counts(ftp_plan* P, const double* sums, const double* lc_stats, dou
   L.inv_sqrt_yy = 1.0 / std::sqrt(lc_stats[2]);
   P->h_obs_off.assign(2, 0);
   P->h_freq_off = {0, n_f};
+  P->h_lcb.clear();
   P->h_gtb.assign(3, 0);
   if ((rc = upload_tables(P, 1, st, false))) return rc;
   SolveArgs a = base_args(P, 1, n_f);

@@ -13,6 +13,7 @@ constexpr int kTileShift = 11;        // log2(kTileCells)
 constexpr int kFixedShift = 60;       // fixed-point scale 2^60 for exact accumulation
 constexpr int kMaxPasses = 4;
 constexpr int64_t kScanSingleMax = 1024 * 16;   // tile counts the one-workgroup scan handles (16 per thread)
+constexpr int64_t kLcBlock = 1024;   // pairs per entry of the lightcurve hint table of a batch
 constexpr int kTwiddleN = 4096;       // size of the in-LDS twiddle table (w_4096^r)
 
 // Per-lightcurve record.  The host fills the plan part; k_prep_stats fills the

@@ -727,7 +727,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int64_t w = blockIdx.x; w < np; w += gridDim.x) {
     const int64_t pidx = p0 + w;
     double* Rr = rec + w * (int64_t)RL.stride;
-    const int64_t lc = find_seg(a.freq_off, a.n_lc, pidx);
+    const int64_t lc = pair_lc(a, pidx);
     const LcInfo& L = a.lcs[lc];
     const int64_t j = pidx - a.freq_off[lc] + 1;
     if (L.status != 0) {
@@ -889,7 +889,7 @@ __global__ __launch_bounds__(64 * kAsmWaves) __attribute__((amdgpu_waves_per_eu(
     const int64_t w = has ? w0 + half : w0;
     const int64_t pidx = p0 + w;
     double* Rr = rec + w * (int64_t)RL.stride;
-    const int64_t lc = find_seg(a.freq_off, a.n_lc, pidx);
+    const int64_t lc = pair_lc(a, pidx);
     const LcInfo& L = a.lcs[lc];
     const int64_t j = pidx - a.freq_off[lc] + 1;
     const bool bad = L.status != 0;
@@ -1372,7 +1372,7 @@ __global__ __launch_bounds__(64) void k_gather_sums(SolveArgs a, double* out) {
   const int H = a.H;
   const typename Cplx<R>::T* grids = reinterpret_cast<const typename Cplx<R>::T*>(a.grids);
   for (int64_t pidx = blockIdx.x; pidx < a.total; pidx += gridDim.x) {
-    const int64_t lc = find_seg(a.freq_off, a.n_lc, pidx);
+    const int64_t lc = pair_lc(a, pidx);
     const LcInfo& L = a.lcs[lc];
     const int64_t j = pidx - a.freq_off[lc] + 1;
     for (int q = lane; q < 3 * H; q += 64) {

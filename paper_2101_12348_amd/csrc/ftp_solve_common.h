@@ -11,6 +11,8 @@ struct SolveArgs {
   const LcInfo* lcs;
   int64_t n_lc;
   const int64_t* freq_off;       // device, n_lc + 1 (prefix of n_f)
+  const int32_t* lc_block;       // optional: entry b = lightcurve of pair min(b kLcBlock, total - 1)
+                                 // (b = 0..ceil(total / kLcBlock)); narrows the lightcurve search
   int64_t total;                 // number of pairs
   const void* grids;             // float2 or double2 grids
   const double* sums_in;         // optional: per pair 3H complex sums (see gather)
@@ -103,13 +105,24 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 
-__device__ __forceinline__ int64_t find_seg(const int64_t* off, int64_t n, int64_t x) {
-  int64_t lo = 0, hi = n - 1;
+__device__ __forceinline__ int64_t find_seg_in(const int64_t* off, int64_t lo, int64_t hi, int64_t x) {
   while (lo < hi) {
     int64_t mid = (lo + hi + 1) >> 1;
     if (off[mid] <= x) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+__device__ __forceinline__ int64_t find_seg(const int64_t* off, int64_t n, int64_t x) {
+  return find_seg_in(off, 0, n - 1, x);
+}
+// Lightcurve of pair x (the last one whose first pair is <= x): between the
+// hint table's entries of x's block when there is one.
+__device__ __forceinline__ int64_t pair_lc(const SolveArgs& a, int64_t x) {
+  if (a.lc_block) {
+    const int64_t b = x / kLcBlock;
+    return find_seg_in(a.freq_off, a.lc_block[b], a.lc_block[b + 1], x);
+  }
+  return find_seg(a.freq_off, a.n_lc, x);
 }
 
 // Wavefront reductions of doubles: DPP moves inside each row of 16 lanes
