@@ -152,6 +152,8 @@ typedef struct {
   int mlp_fused;        /* learned: 1 = one kernel for the four network layers (LDS-staged
                            weights, activations kept per wavefront), 0 = four GEMM
                            launches; identical results */
+  int newton_occ;       /* Newton + Sturm (H <= 10): the build compiled for 4 or 5
+                           resident wavefronts per SIMD (fewer registers per lane at 5) */
 } ftp_tuning;
 
 #define FTP_TUNE_FORCE 1u   /* ftp_autotune: measure even if the cache holds an entry */
@@ -374,8 +376,8 @@ int ftp_learned_dataset(ftp_plan* plan, const double* t, const double* y, const 
 /* Current launch shapes of the plan (defaults until set or tuned). */
 int ftp_plan_get_tuning(const ftp_plan* plan, ftp_tuning* out);
 
-/* Set the launch shapes.  FTP_E_OPTION if a shape is outside 1..256 or
- * mlp_fused is not 0 or 1. */
+/* Set the launch shapes.  FTP_E_OPTION if a shape is outside 1..256,
+ * mlp_fused is not 0 or 1 or newton_occ is not 4 or 5. */
 int ftp_plan_set_tuning(ftp_plan* plan, const ftp_tuning* tuning);
 
 /*
@@ -387,7 +389,7 @@ int ftp_plan_set_tuning(ftp_plan* plan, const ftp_tuning* tuning);
  * (best of two, HIP events on `stream`).  The result is applied to the plan
  * and written to *out.
  * cache_path (nullable): a text file of "key assemble newton aberth qr score
- * mlp_fused" lines; the key (ftp_plan_tune_key) names the device, its compute units, H,
+ * mlp_fused newton_occ" lines (a line without newton_occ reads as 4); the key (ftp_plan_tune_key) names the device, its compute units, H,
  * precision, solver and a bucket of n_f.  An entry found there is applied without measuring
  * (unless flags has FTP_TUNE_FORCE); a measured result is stored there.
  * Returns 1 when the cache supplied the shapes, 0 when they were measured, or

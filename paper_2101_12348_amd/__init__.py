@@ -61,7 +61,8 @@ class Stats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """Launch shapes of the per-frequency kernels (waves per compute unit)."""
     _fields_ = [("assemble_wpc", ctypes.c_int), ("newton_wpc", ctypes.c_int), ("aberth_wpc", ctypes.c_int),
-                ("qr_wpc", ctypes.c_int), ("score_wpc", ctypes.c_int), ("mlp_fused", ctypes.c_int)]
+                ("qr_wpc", ctypes.c_int), ("score_wpc", ctypes.c_int), ("mlp_fused", ctypes.c_int),
+                ("newton_occ", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -353,7 +354,10 @@ class Plan:
     def set_tuning(self, **kw):
         tu = Tuning()
         _check(self.lib.ftp_plan_get_tuning(self.handle, ctypes.byref(tu)))
+        names = {k for k, _ in Tuning._fields_}
         for k, v in kw.items():
+            if k not in names:
+                raise KeyError(f"unknown launch shape {k!r} (one of {sorted(names)})")
             setattr(tu, k, int(v))
         _check(self.lib.ftp_plan_set_tuning(self.handle, ctypes.byref(tu)))
 

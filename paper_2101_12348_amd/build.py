@@ -18,6 +18,17 @@ FLAGS = [
     "-munsafe-fp-atomics",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
+# Per-file code generation flags (each file's device code is compiled on its
+# own: no kernel calls device code of another file).  The assembly, scoring,
+# companion-QR and Aberth kernels are built without machine-level loop-invariant
+# code motion, which otherwise keeps constants of their loop bodies in vector
+# registers for the whole loop and pushes them past their register budgets
+# (measured: assembly, scoring and the Aberth tier faster without it); the
+# Newton kernel's short loops gain from the motion and keep it.
+FILE_FLAGS = {
+    "ftp_solve.hip": ["-mllvm", "-disable-machine-licm"],
+    "ftp_aberth.hip": ["-mllvm", "-disable-machine-licm"],
+}
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:
@@ -29,14 +40,15 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for s in srcs:
         o = os.path.join(objdir, os.path.basename(s) + ".o")
         objs.append(o)
-        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-fgpu-rdc", "-c", s, "-o", o]
+        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + FILE_FLAGS.get(os.path.basename(s), []) + \
+            ["-c", s, "-o", o]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         if len(procs) >= jobs:
             _wait(procs, verbose)
             procs = []
     _wait(procs, verbose)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-fgpu-rdc", "--hip-link", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     _run(cmd, verbose)
     os.replace(tmp, LIB)
     return LIB

@@ -80,7 +80,8 @@ hipError_t launch_labels(const double* rec, int H, int64_t np, float* roots, int
                          hipStream_t st);
 hipError_t launch_root_counts(const double* rec, int H, int64_t np, int* sturm, int* real, int waves,
                               hipStream_t st);
-hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st,
+bool newton_four_per_wave(int H);
+hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, int occ, hipStream_t st,
                                hipEvent_t done = nullptr);
 hipError_t launch_aberth(const AberthArgs& A, int waves, hipStream_t st);
 bool mlp_fused_ok(const int* nin, const int* nout);
@@ -388,7 +389,7 @@ struct ftp_plan {
   DevBuf xfeat, seeds, fb_list, fb2_list, rt_list, work_ctr;
   // launch shapes (waves per compute unit), set by ftp_plan_set_tuning or
   // ftp_autotune
-  ftp_tuning tune{32, 32, 16, 16, 32, 0};
+  ftp_tuning tune{32, 32, 16, 16, 32, 0, 4};
   DevBuf tune_out;
   // multi-band calls: chi^2_0 of every lightcurve of the batch (device, set
   // for the duration of the call) and the band outputs' scratch
@@ -890,7 +891,7 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
         // the second round instead, so that the network's large workgroups
         // and the round do not wait for CU room behind the scoring's
         // wavefronts (measured: learned -15 us, uniform +11 us that way)
-        HIP_TRY(launch_newton_sturm(a, L, w_nt, st, (overlap_score && !net_list) ? P->fork_ev : nullptr));
+        HIP_TRY(launch_newton_sturm(a, L, w_nt, T.newton_occ, st, (overlap_score && !net_list) ? P->fork_ev : nullptr));
       }
       hipEvent_t rb = learn_ev();
       if (rb) HIP_TRY(hipEventRecord(rb, st));
@@ -1076,7 +1077,7 @@ bool tuning_valid(const ftp_tuning& t) {
   const int v[5] = {t.assemble_wpc, t.newton_wpc, t.aberth_wpc, t.qr_wpc, t.score_wpc};
   for (int x : v)
     if (x < 1 || x > 256) return false;
-  return t.mlp_fused == 0 || t.mlp_fused == 1;
+  return (t.mlp_fused == 0 || t.mlp_fused == 1) && (t.newton_occ == 4 || t.newton_occ == 5);
 }
 
 bool key_valid(const char* key) {
@@ -1814,6 +1815,7 @@ int ftp_tune_cache_lookup(const char* path, const char* key, ftp_tuning* out) {
     ftp_tuning t{};
     if (!(ls >> k) || k != key) continue;
     if (!(ls >> t.assemble_wpc >> t.newton_wpc >> t.aberth_wpc >> t.qr_wpc >> t.score_wpc >> t.mlp_fused)) continue;
+    if (!(ls >> t.newton_occ)) t.newton_occ = 4;
     if (!tuning_valid(t)) continue;
     *out = t;
     found = 1;   // the last well-formed entry wins
@@ -1836,8 +1838,8 @@ int ftp_tune_cache_store(const char* path, const char* key, const ftp_tuning* t)
     }
   }
   char entry[512];
-  std::snprintf(entry, sizeof(entry), "%s %d %d %d %d %d %d", key, t->assemble_wpc, t->newton_wpc, t->aberth_wpc,
-                t->qr_wpc, t->score_wpc, t->mlp_fused);
+  std::snprintf(entry, sizeof(entry), "%s %d %d %d %d %d %d %d", key, t->assemble_wpc, t->newton_wpc, t->aberth_wpc,
+                t->qr_wpc, t->score_wpc, t->mlp_fused, t->newton_occ);
   keep.push_back(entry);
   const std::string tmp = std::string(path) + ".tmp";
   {
@@ -1882,7 +1884,7 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
   float ms = 0.f;
   // the knobs that matter for the solver; the QR knob also for the others
   // (it then only serves the companion fallback, but is cheap to sweep)
-  int* knobs[6];
+  int* knobs[7];
   int nk = 0;
   if (P->opt.solver == FTP_SOLVER_PLAIN) {
     knobs[nk++] = &cur.qr_wpc;
@@ -1894,8 +1896,12 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
   knobs[nk++] = &cur.score_wpc;
   const bool tune_mlp = P->opt.solver == FTP_SOLVER_LEARNED && mlp_fused_ok(P->net.nin, P->net.nout);
   if (tune_mlp) knobs[nk++] = &cur.mlp_fused;
+  const bool tune_occ = (P->opt.solver == FTP_SOLVER_LEARNED || P->opt.solver == FTP_SOLVER_UNIFORM) &&
+                        newton_four_per_wave(P->H);
+  if (tune_occ) knobs[nk++] = &cur.newton_occ;
   const int cand[] = {4, 8, 12, 16, 24, 32, 48, 64};
   const int cand01[] = {0, 1};
+  const int cand45[] = {4, 5};
   auto measure = [&](float* best) -> int {
     P->tune = cur;
     float m0 = 0.f, m1 = 0.f;
@@ -1911,8 +1917,8 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
     int best_v = *knobs[k];
     float best_ms = 0.f;
     if ((rc = measure(&best_ms))) break;
-    const bool binary = knobs[k] == &cur.mlp_fused;
-    const int* cv = binary ? cand01 : cand;
+    const bool binary = knobs[k] == &cur.mlp_fused || knobs[k] == &cur.newton_occ;
+    const int* cv = knobs[k] == &cur.mlp_fused ? cand01 : (knobs[k] == &cur.newton_occ ? cand45 : cand);
     const int ncv = binary ? 2 : 8;
     for (int ci = 0; ci < ncv; ++ci) {
       const int v = cv[ci];

@@ -550,21 +550,18 @@ __device__ __forceinline__ void u_from_dir(double c, double s, double& u, int& s
 // atan(u) for |u| <= 1.  Two halvings, atan(u) = 2 atan(u / (1 + sqrt(1 +
 // u^2))), bring the argument below tan(pi / 16) < 0.199, where the Taylor
 // series through z^23 leaves a remainder below 2e-17 of the result.
+// (coefficients (-1)^n / (2n + 1), n = 11 .. 1, read through poly_table)
+static __constant__ double kAtanTab[11] = {
+    -1.0 / 23.0, 1.0 / 21.0, -1.0 / 19.0, 1.0 / 17.0, -1.0 / 15.0, 1.0 / 13.0,
+    -1.0 / 11.0, 1.0 / 9.0,  -1.0 / 7.0,  1.0 / 5.0,  -1.0 / 3.0};
 __device__ __forceinline__ double atan_unit(double u) {
+  const const_table T = poly_table((const_table)kAtanTab);
   double z = u * fast_rcp_d(1.0 + sqrt(fma(u, u, 1.0)));
   z = z * fast_rcp_d(1.0 + sqrt(fma(z, z, 1.0)));
   const double z2 = z * z;
-  double p = -1.0 / 23.0;
-  p = fma(p, z2, 1.0 / 21.0);
-  p = fma(p, z2, -1.0 / 19.0);
-  p = fma(p, z2, 1.0 / 17.0);
-  p = fma(p, z2, -1.0 / 15.0);
-  p = fma(p, z2, 1.0 / 13.0);
-  p = fma(p, z2, -1.0 / 11.0);
-  p = fma(p, z2, 1.0 / 9.0);
-  p = fma(p, z2, -1.0 / 7.0);
-  p = fma(p, z2, 1.0 / 5.0);
-  p = fma(p, z2, -1.0 / 3.0);
+  double p = T[0];
+#pragma unroll
+  for (int i = 1; i < 11; ++i) p = fma(p, z2, T[i]);
   return 4.0 * fma(p * z2, z, z);
 }
 
@@ -705,7 +702,11 @@ __device__ __forceinline__ void newton_pair(const LearnArgs& L, const RecLayout&
   lwave_sync();
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_newton_sturm4(SolveArgs a, LearnArgs L) {
+// OCC: resident wavefronts per SIMD the register allocation is made for (4:
+// up to 128 VGPRs, 5: up to 96, with a few spills outside the Newton loop);
+// which is faster depends on the workload, so the launch shape picks it.
+template <int OCC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void k_newton_sturm4(SolveArgs a, LearnArgs L) {
   extern __shared__ double sml[];
   const int lane = threadIdx.x & 63, row = lane >> 4, l = lane & 15;
   const int H = a.H, D = 6 * H - 2;
@@ -1099,11 +1100,15 @@ hipError_t launch_newton_retry(const RetryArgs& A, int waves, hipStream_t st) {
 bool newton_four_per_wave(int H) { return 6 * H - 2 < 64; }
 
 // `done` (nullable): an event the launch itself records at the kernel's end
-// (no marker packet of its own on the stream).
-hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, hipStream_t st, hipEvent_t done) {
+// (no marker packet of its own on the stream); `occ`: 4 or 5 (k_newton_sturm4).
+hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, int occ, hipStream_t st,
+                               hipEvent_t done) {
   if (newton_four_per_wave(a.H)) {
     const size_t lds = (size_t)8 * (6 * a.H) * sizeof(double);   // 8 x (D + 2): f and its reversal, four pairs
-    hipExtLaunchKernelGGL(k_newton_sturm4, dim3((unsigned)waves), dim3(64), lds, st, nullptr, done, 0, a, L);
+    if (occ == 5)
+      hipExtLaunchKernelGGL(k_newton_sturm4<5>, dim3((unsigned)waves), dim3(64), lds, st, nullptr, done, 0, a, L);
+    else
+      hipExtLaunchKernelGGL(k_newton_sturm4<4>, dim3((unsigned)waves), dim3(64), lds, st, nullptr, done, 0, a, L);
   } else {
     hipExtLaunchKernelGGL(k_newton_sturm, dim3((unsigned)waves), dim3(64), learn_lds_bytes(a.H), st, nullptr, done, 0,
                           a, L);

@@ -1270,6 +1270,35 @@ __device__ __forceinline__ Best select_best_row(const double (&P)[2], const doub
 // more than 16 roots (a frequency has ~12 real roots at H = 10).  The
 // candidates, tie rule and outputs of k_score, without the polish (the roots
 // are Newton-converged).
+//
+// The record fields a row's lanes read (meta; mu_e, e = l, l + 16 <= 2H;
+// eta_k and Z_w k, k = l < H; candidates l, l + 16) are loaded one iteration
+// ahead, so that their latency overlaps the scoring of the current four pairs
+// (2H + 1 <= 31 and H <= 15: two, one, one and two per lane cover them).
+struct Score4Fetch {
+  double st, fb, lc, ref, c0, c1;
+  double2 mu0, mu1, eta, zw;
+};
+
+__device__ __forceinline__ void score4_fetch(const double* rec, const RecLayout& RL, int H, int ncand, int64_t np,
+                                             int64_t w0, int row, int l, Score4Fetch& F) {
+  const bool has = w0 + row < np;
+  const double* Rr = rec + (has ? w0 + row : w0) * (int64_t)RL.stride;
+  const double2 z = make_double2(0.0, 0.0);
+  const double qnan = __longlong_as_double(0x7ff8000000000000ll);
+  F.st = Rr[RL.meta + M_STATUS];
+  F.fb = has ? Rr[RL.meta + M_FALLBACK] : 1.0;   // past the end: scored, never written
+  F.lc = Rr[RL.meta + M_LC];
+  F.ref = Rr[RL.meta + M_REF];
+  const double2* mu = reinterpret_cast<const double2*>(Rr + RL.mu);
+  F.mu0 = l <= 2 * H ? mu[l] : z;
+  F.mu1 = l + 16 <= 2 * H ? mu[l + 16] : z;
+  F.eta = l < H ? reinterpret_cast<const double2*>(Rr + RL.eta)[l] : z;
+  F.zw = l < H ? reinterpret_cast<const double2*>(Rr + RL.zw)[l] : z;
+  F.c0 = l < ncand ? Rr[RL.cand + l] : qnan;
+  F.c1 = l + 16 < ncand ? Rr[RL.cand + l + 16] : qnan;
+}
+
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_score4(SolveArgs a, const double* rec,
                                                                                        int64_t p0, int64_t np) {
   extern __shared__ double sms[];
@@ -1290,22 +1319,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const double floor_mm = a.n_band ? a.mm_tau * a.lcs[0].mm_scale : mm_floor(W, H, a.mm_tau);
   const bool pos = (a.flags & kFlagPositiveAmp) != 0u;
   const int ncand = D < 32 ? D : 32;   // the first round's starts per frequency
-  for (int64_t w0 = 4 * (int64_t)blockIdx.x; w0 < np; w0 += 4 * (int64_t)gridDim.x) {
-    const bool has = w0 + row < np;
-    const int64_t w = has ? w0 + row : w0;
-    const int64_t pidx = p0 + w;
-    const double* Rr = rec + w * (int64_t)RL.stride;
-    const int st = (int)Rr[RL.meta + M_STATUS];
-    const bool mine = has && Rr[RL.meta + M_FALLBACK] == 0.0;
-    const int64_t lc = (int64_t)Rr[RL.meta + M_LC];
-    const LcInfo& L = a.lcs[lc];
-    const double ref = Rr[RL.meta + M_REF];
-    // (the evaluation reads mu, eta and Z: the Newton roots take no polish on R)
-    for (int e = l; e <= 2 * H; e += 16) W.mu[e] = make_double2(Rr[RL.mu + 2 * e], Rr[RL.mu + 2 * e + 1]);
-    for (int k = l; k < H; k += 16) {
-      W.eta[k + 1] = make_double2(Rr[RL.eta + 2 * k], Rr[RL.eta + 2 * k + 1]);
-      const double2 z = make_double2(Rr[RL.zw + 2 * k], Rr[RL.zw + 2 * k + 1]);
-      W.Z[k + 1] = cconj(cmul(W.al[k], cconj(z)));
+  const int64_t step = 4 * (int64_t)gridDim.x;
+  Score4Fetch F;
+  int64_t w0 = 4 * (int64_t)blockIdx.x;
+  if (w0 < np) score4_fetch(rec, RL, H, ncand, np, w0, row, l, F);
+  for (; w0 < np; w0 += step) {
+    // this iteration's fields into LDS and registers, then the next
+    // iteration's loads
+    const int64_t pidx = p0 + (w0 + row < np ? w0 + row : w0);
+    const int st = (int)F.st;
+    const bool mine = F.fb == 0.0;
+    const int64_t lc = (int64_t)F.lc;
+    const double ref = F.ref;
+    if (l <= 2 * H) W.mu[l] = F.mu0;
+    if (l + 16 <= 2 * H) W.mu[l + 16] = F.mu1;
+    if (l < H) {
+      W.eta[l + 1] = F.eta;
+      W.Z[l + 1] = cconj(cmul(W.al[l], cconj(F.zw)));
     }
     if (l == 0) W.eta[0] = make_double2(0.0, 0.0);
     double th[2] = {0.0, 0.0};
@@ -1314,22 +1344,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       th[0] = -kTwoPi * ref;
       valid[0] = l == 0;
     } else if (st != ST_BAD_LC) {
+      th[0] = F.c0;
+      th[1] = F.c1;
 #pragma unroll
       for (int sl = 0; sl < 2; ++sl) {
-        const int c = l + 16 * sl;
-        if (c < ncand) {
-          th[sl] = Rr[RL.cand + c];
-          valid[sl] = !isnan(th[sl]);
-          if (!valid[sl]) th[sl] = 0.0;
-        }
+        valid[sl] = !isnan(th[sl]);
+        if (!valid[sl]) th[sl] = 0.0;
       }
     }
+    if (w0 + step < np) score4_fetch(rec, RL, H, ncand, np, w0 + step, row, l, F);
     wave_sync();
-    Cand c[2];
-    c[0] = eval_candidate(W, H, th[0]);
-    c[1] = Cand{0.0, 0.0, 0.0, 0.0};
+    // (the evaluation reads mu, eta and Z: the Newton roots take no polish on R)
     const bool second = __ballot(valid[1]) != 0ull;   // wave-uniform
-    if (second) c[1] = eval_candidate(W, H, th[1]);
+    Cand c[2];
+    c[1] = Cand{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int sl = 0; sl < (second ? 2 : 1); ++sl) {
+      const Cand t = eval_candidate(W, H, sl ? th[1] : th[0]);
+      if (sl) c[1] = t; else c[0] = t;
+    }
     const double mmmax = row_max_d(fmax(valid[0] ? c[0].MM : -1.0, valid[1] ? c[1].MM : -1.0));
     int stout = st;
     if (st != ST_BAD_LC && mmmax <= floor_mm) stout = ST_DEGENERATE;
@@ -1350,6 +1383,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         a.power[pidx] = 0.0; a.phase[pidx] = 0.0; a.amp[pidx] = 0.0; a.offset[pidx] = 0.0;
         if (a.status) a.status[pidx] = ST_BAD_LC;
       } else {
+        const LcInfo& L = a.lcs[lc];
         const double sq = sqrt(L.yy);
         double P = cb.P, amp = cb.MM > 0.0 ? cb.YM / cb.MM * sq : 0.0;
         double off = L.ybar - cb.Mbar * amp;

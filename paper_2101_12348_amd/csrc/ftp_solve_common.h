@@ -234,6 +234,43 @@ __device__ __forceinline__ int64_t fft_pos(int64_t q, const LcInfo& L, int g) {
   return pos;
 }
 
+// Constant tables of the polynomial kernels below.  They are read through
+// poly_table(), whose empty asm makes the pointer opaque where the function
+// is used: the compiler then loads the coefficients into SGPRs at each use
+// (scalar loads, kept in the scalar cache) instead of holding every
+// coefficient of a loop body in a VGPR pair across the whole loop, which
+// pushed the Newton kernel past its register budget.
+typedef const __attribute__((address_space(4))) double* const_table;
+__device__ __forceinline__ const_table poly_table(const_table t) {
+  asm volatile("" : "+s"(t));
+  return t;
+}
+
+// e^x for a moderate argument (|x| < 700; the deconvolution's exponents are
+// below ~10): Cody-Waite reduction x = k ln 2 + r, |r| <= ln 2 / 2 (ln 2 as
+// the nearest double and its remainder, each product taken in one FMA), the
+// Taylor series of e^r through r^13 (truncation below 4e-18 on that
+// interval), then the scaling by 2^k (the coefficients read through poly_table).
+static __constant__ double kExpTab[14] = {
+    1.4426950408889634074,     6.9314718055994530942e-01, 2.3190468138462996154e-17,
+    1.6059043836821614599e-10, 2.0876756987868098979e-09, 2.5052108385441718775e-08,
+    2.7557319223985890653e-07, 2.7557319223985890653e-06, 2.4801587301587301587e-05,
+    1.9841269841269841270e-04, 1.3888888888888888889e-03, 8.3333333333333333333e-03,
+    4.1666666666666666667e-02, 1.6666666666666666667e-01};
+__device__ __forceinline__ double exp_small(double x) {
+  const const_table T = poly_table((const_table)kExpTab);
+  const double k = rint(x * T[0]);
+  double r = fma(-k, T[1], x);
+  r = fma(-k, T[2], r);
+  double p = T[3];
+#pragma unroll
+  for (int i = 4; i <= 13; ++i) p = fma(p, r, T[i]);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
 // Deconvolved sum Z(m) for harmonic index m on grid g (relative to t_ref;
 // the y grid carries the 1/sqrt(YY) normalisation).
 template <typename R>
@@ -243,7 +280,7 @@ __device__ __forceinline__ double2 gather_mode(const LcInfo& L, int g, int64_t m
   const int64_t mp = m - L.mc[g];
   const int64_t q = mp & (n - 1);   // mp mod n (n a power of two)
   const typename Cplx<R>::T v = grids[L.grid_off[g] + fft_pos(q, L, g)];
-  const double fac = L.dec_a[g] * exp(L.dec_b[g] * (double)mp * (double)mp);
+  const double fac = L.dec_a[g] * exp_small(L.dec_b[g] * (double)mp * (double)mp);
   return make_double2((double)v.x * fac, (double)v.y * fac);
 }
 
@@ -449,33 +486,35 @@ __device__ __forceinline__ int64_t next_item(unsigned* q, int lane, int64_t w) {
 // YY = 1), YM, MM and Mbar.
 struct Cand { double P, YM, MM, Mbar; };
 
+// sincos_small: 2/pi, pi/2 as a leading double and its remainder, then the
+// sine series 1/17!, -1/15!, ..., -1/3! and the cosine series 1/18!, ..., -1/4!
+static __constant__ double kSinCosTab[20] = {
+    0.63661977236758134308,    1.5707963267948966192,     6.1232339957367660359e-17,
+    2.8114572543455207632e-15, -7.6471637318198164759e-13, 1.6059043836821614599e-10,
+    -2.5052108385441718775e-08, 2.7557319223985890653e-06, -1.9841269841269841270e-04,
+    8.3333333333333333333e-03, -1.6666666666666666667e-01, 1.5619206968586225271e-16,
+    -4.7794773323873852974e-14, 1.1470745597729724714e-11, -2.0876756987868098979e-09,
+    2.7557319223985890653e-07, -2.4801587301587301587e-05, 1.3888888888888888889e-03,
+    -4.1666666666666666667e-02, 0.0};
+
 // sin and cos of a moderate angle (|x| < 2^30; every phase here is within a
 // few turns of [0, 2 pi)): Cody-Waite reduction by pi/2 in two parts
 // (k = rint(2x/pi), r = x - k pi/2 in [-pi/4, pi/4], the products exact in
 // FMA), the Taylor series of sin and cos to r^17 and r^18 (truncation below
 // 1e-19 on that interval; the coefficients are 1/n!), then the quadrant.
 __device__ __forceinline__ void sincos_small(double x, double& s, double& c) {
-  const double k = rint(x * 0.63661977236758134308);        // 2 / pi
-  double r = fma(-k, 1.5707963267948966192, x);             // pi/2, leading double
-  r = fma(-k, 6.1232339957367660359e-17, r);                // pi/2 - leading double
+  const const_table T = poly_table((const_table)kSinCosTab);
+  const double k = rint(x * T[0]);
+  double r = fma(-k, T[1], x);
+  r = fma(-k, T[2], r);
   const double z = r * r;
-  double ps = 2.8114572543455207632e-15;                    // 1/17!
-  ps = fma(ps, z, -7.6471637318198164759e-13);              // -1/15!
-  ps = fma(ps, z, 1.6059043836821614599e-10);               // 1/13!
-  ps = fma(ps, z, -2.5052108385441718775e-08);              // -1/11!
-  ps = fma(ps, z, 2.7557319223985890653e-06);               // 1/9!
-  ps = fma(ps, z, -1.9841269841269841270e-04);              // -1/7!
-  ps = fma(ps, z, 8.3333333333333333333e-03);               // 1/5!
-  ps = fma(ps, z, -1.6666666666666666667e-01);              // -1/3!
+  double ps = T[3];
+#pragma unroll
+  for (int i = 4; i <= 10; ++i) ps = fma(ps, z, T[i]);
   const double sr = fma(ps * z, r, r);
-  double pc = 1.5619206968586225271e-16;                    // 1/18!
-  pc = fma(pc, z, -4.7794773323873852974e-14);              // -1/16!
-  pc = fma(pc, z, 1.1470745597729724714e-11);               // 1/14!
-  pc = fma(pc, z, -2.0876756987868098979e-09);              // -1/12!
-  pc = fma(pc, z, 2.7557319223985890653e-07);               // 1/10!
-  pc = fma(pc, z, -2.4801587301587301587e-05);              // -1/8!
-  pc = fma(pc, z, 1.3888888888888888889e-03);               // 1/6!
-  pc = fma(pc, z, -4.1666666666666666667e-02);              // -1/4!
+  double pc = T[11];
+#pragma unroll
+  for (int i = 12; i <= 18; ++i) pc = fma(pc, z, T[i]);
   pc = fma(pc, z, 0.5);
   const double cr = fma(-pc, z, 1.0);
   const int q = (int)k & 3;

@@ -100,9 +100,10 @@ def test_tuning_cache_file_round_trip(tmp_path):
     p = str(tmp_path / "tune.txt")
     key = "gfx950/256cu/H6/p0/s1"
     assert F.tune_cache_lookup(p, key) is None
-    shapes = dict(assemble_wpc=32, newton_wpc=16, aberth_wpc=8, qr_wpc=16, score_wpc=24, mlp_fused=0)
+    shapes = dict(assemble_wpc=32, newton_wpc=16, aberth_wpc=8, qr_wpc=16, score_wpc=24, mlp_fused=0, newton_occ=5)
     F.tune_cache_store(p, key, **shapes)
     F.tune_cache_store(p, "gfx950/256cu/H4/p0/s0", **dict({k: 4 for k in shapes}, mlp_fused=1))
+    assert F.tune_cache_lookup(p, "gfx950/256cu/H4/p0/s0")["newton_occ"] == 4
     assert F.tune_cache_lookup(p, key) == shapes
     shapes2 = dict(shapes, qr_wpc=48)
     F.tune_cache_store(p, key, **shapes2)
@@ -111,14 +112,18 @@ def test_tuning_cache_file_round_trip(tmp_path):
     assert F.tune_cache_lookup(p, key) == shapes2
     with open(p, "a") as fh:
         fh.write("garbage line\n" + key + " 1 2 3\n" + "gfx950/256cu/H3/p0/s0 0 4 4 4 4 0\n"
-                 + "gfx950/256cu/H2/p0/s0 4 4 4 4 4 2\n")
+                 + "gfx950/256cu/H2/p0/s0 4 4 4 4 4 2\n" + "gfx950/256cu/H1/p0/s0 4 4 4 4 4 0 3\n"
+                 + "gfx950/256cu/H5/p0/s0 8 8 8 8 8 1\n")
     assert F.tune_cache_lookup(p, key) == shapes2
     assert F.tune_cache_lookup(p, "gfx950/256cu/H3/p0/s0") is None
     assert F.tune_cache_lookup(p, "gfx950/256cu/H2/p0/s0") is None
+    assert F.tune_cache_lookup(p, "gfx950/256cu/H1/p0/s0") is None
+    # a line without the Newton occupancy (the older six-column form) reads as 4
+    assert F.tune_cache_lookup(p, "gfx950/256cu/H5/p0/s0") == dict({k: 8 for k in shapes}, mlp_fused=1, newton_occ=4)
     for bad_key in ("", "has space"):
         with pytest.raises(F.FtpError):
             F.tune_cache_store(p, bad_key, **shapes)
-    for bad in (dict(shapes, score_wpc=0), dict(shapes, mlp_fused=2)):
+    for bad in (dict(shapes, score_wpc=0), dict(shapes, mlp_fused=2), dict(shapes, newton_occ=3)):
         with pytest.raises(F.FtpError):
             F.tune_cache_store(p, key, **bad)
     with pytest.raises(F.FtpError):

@@ -1,7 +1,8 @@
 """Launch shapes and the autotuner (the schedule of the per-frequency stage).
 
 * Every frequency is computed by one wavefront whatever the grid and the
-  queue order, so outputs are bit-identical across launch shapes.
+  queue order, and the Newton kernel's register budgets (newton_occ) compile
+  the same arithmetic, so outputs are bit-identical across launch shapes.
 * The autotuner returns valid shapes, applies them, stores them in its cache
   and serves the next request for the same key from there.
 """
@@ -30,8 +31,8 @@ def test_outputs_do_not_depend_on_launch_shapes(ftp, solver):
     n_f = 6000
     plan = ftp.Plan(tmpl.c, tmpl.s, solver=solver)
     ref = {k: v.clone() for k, v in plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
-    for wpc in (1, 3, 64):
-        plan.set_tuning(assemble_wpc=wpc, newton_wpc=wpc, aberth_wpc=wpc, qr_wpc=wpc, score_wpc=wpc)
+    for wpc, occ in ((1, 4), (3, 5), (64, 5)):
+        plan.set_tuning(assemble_wpc=wpc, newton_wpc=wpc, aberth_wpc=wpc, qr_wpc=wpc, score_wpc=wpc, newton_occ=occ)
         out = plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
         for k in ref:
             assert torch.equal(ref[k], out[k]), (wpc, k)
@@ -46,6 +47,11 @@ def test_set_tuning_rejects_bad_shapes(ftp):
             plan.set_tuning(qr_wpc=bad)
     with pytest.raises(ftp.FtpError):
         plan.set_tuning(mlp_fused=2)
+    for bad in (0, 3, 6):
+        with pytest.raises(ftp.FtpError):
+            plan.set_tuning(newton_occ=bad)
+    with pytest.raises(KeyError):
+        plan.set_tuning(no_such_shape=4)
     assert plan.tuning() == before
 
 
@@ -58,7 +64,8 @@ def test_autotune_and_cache(ftp, tmp_path):
     cache = str(tmp_path / "tune.txt")
     shapes, cached = plan.autotune(lc.t, lc.y, lc.sigma, lc.df, n_f, cache_path=cache)
     assert not cached
-    assert all(1 <= v <= 256 for k, v in shapes.items() if k != "mlp_fused") and shapes["mlp_fused"] in (0, 1)
+    assert all(1 <= v <= 256 for k, v in shapes.items() if k not in ("mlp_fused", "newton_occ"))
+    assert shapes["mlp_fused"] in (0, 1) and shapes["newton_occ"] in (4, 5)
     assert plan.tuning() == shapes
     assert ftp.tune_cache_lookup(cache, plan.tune_key(n_f)) == shapes
     out = plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
