@@ -423,14 +423,15 @@ __global__ __launch_bounds__(64) void k_features2(double* rec, int H, int64_t np
 
 // ------------------------------------------------------- fused inference
 
-// The four layers of the network for 128 pairs per workgroup (four waves),
-// with the activations kept in LDS between layers: the output of a layer is
-// written over its input (after every wave has read it) and is the A operand
-// of the next.  Per layer, wave w computes all 128 rows of the column tiles
-// 4w .. 4w + 3 (64 columns) as 8 x 4 MFMA 16 x 16 x 32 tiles.  The weights
-// (about 300 KB for width 256, resident in L2) are read by each wave straight
-// into its B fragments, three K slices ahead, so the K loop has no barrier;
-// the LDS holds only the activations (67.5 KB: two workgroups per CU).
+// The four layers of the network for kFRows (128 or 32) pairs per workgroup
+// (four waves), with the activations kept in LDS between layers: the output of
+// a layer is written over its input (after every wave has read it) and is the
+// A operand of the next.  Per layer, wave w computes all kFRows rows of the
+// column tiles 4w .. 4w + 3 (64 columns) as (kFRows / 16) x 4 MFMA 16 x 16 x 32
+// tiles.  The weights (about 300 KB for width 256, resident in L2) are read by
+// each wave straight into its B fragments, three K slices ahead, so the K loop
+// has no barrier; the LDS holds only the activations (67.5 KB at 128 rows:
+// two workgroups per CU).
 // Weights: the inference copy with each layer's rows zero-padded to kp[l]
 // (multiples of 32, 16-byte aligned) and their number to a multiple of 16.
 // Same operands, K order, bias, ReLU and
@@ -438,12 +439,16 @@ __global__ __launch_bounds__(64) void k_features2(double* rec, int H, int64_t np
 // bit for bit.  Requirements (checked on the host): width a multiple of 32 up
 // to 256, kp[0] up to 256, d_out up to 64.
 
-constexpr int kFRows = 128;          // pairs per workgroup
-constexpr int kFRT = kFRows / 16;    // row tiles
+// kFRows: pairs per workgroup, 128 when the network runs on every pair of a
+// round (each workgroup's weight reads serve more rows), 32 on a device list
+// (the first round's leftovers, a few thousand pairs: more workgroups, each
+// with a shorter chain of tiles; measured 14 us faster there).
 constexpr int kActLd = 256 + 8;      // LDS row of one pair's activations (bf16)
 constexpr int kOutLd = 64 + 4;       // LDS row of one pair's outputs (FP32, d_out <= 64)
 
+template <int kFRows>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_fused(FusedMlpArgs a) {
+  constexpr int kFRT = kFRows / 16;    // row tiles
   __shared__ __align__(16) uint16_t act[kFRows * kActLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (a.np_dev) {
@@ -648,14 +653,18 @@ bool mlp_fused_ok(const int* nin, const int* nout) {
   return nin[1] == nout[0] && nin[2] == nout[1] && nin[3] == nout[2];
 }
 
-// grid: at most max_blocks workgroups (two fit a compute unit), each taking
-// every max_blocks-th tile of 128 pairs
+// grid: at most max_blocks workgroups, each taking every max_blocks-th tile
+// of 128 pairs (32 on a device list)
 // `done` (nullable): an event the launch records at the kernel's end.
 hipError_t launch_mlp_fused(const FusedMlpArgs& fa, hipStream_t st, int max_blocks, hipEvent_t done) {
   if (fa.np <= 0) return done ? hipEventRecord(done, st) : hipSuccess;
-  int64_t blocks = (fa.np + kFRows - 1) / kFRows;
+  const int rows = fa.np_dev ? 32 : 128;
+  int64_t blocks = (fa.np + rows - 1) / rows;
   if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
-  hipExtLaunchKernelGGL(k_mlp_fused, dim3((unsigned)blocks), dim3(256), 0, st, nullptr, done, 0, fa);
+  if (fa.np_dev)
+    hipExtLaunchKernelGGL(k_mlp_fused<32>, dim3((unsigned)blocks), dim3(256), 0, st, nullptr, done, 0, fa);
+  else
+    hipExtLaunchKernelGGL(k_mlp_fused<128>, dim3((unsigned)blocks), dim3(256), 0, st, nullptr, done, 0, fa);
   return hipGetLastError();
 }
 
