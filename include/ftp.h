@@ -383,8 +383,9 @@ int ftp_plan_set_tuning(ftp_plan* plan, const ftp_tuning* tuning);
 /*
  * Autotuner of the launch shapes (the schedule of the ragged-batch path): on
  * the given lightcurve (same arguments as ftp_periodogram; device arrays),
- * each shape that matters for the plan's solver is swept over 4..64 waves per
- * compute unit (and, for the learned solver, both network implementations),
+ * each shape that matters for the plan's solver is swept over 4..256 waves per
+ * compute unit (and, for the learned solver, both network implementations; for
+ * the Sturm-verified Newton solvers, both register budgets of its kernel),
  * one at a time, keeping the fastest whole periodogram call
  * (best of two, HIP events on `stream`).  The result is applied to the plan
  * and written to *out.

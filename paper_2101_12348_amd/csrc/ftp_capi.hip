@@ -1899,7 +1899,10 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
   const bool tune_occ = (P->opt.solver == FTP_SOLVER_LEARNED || P->opt.solver == FTP_SOLVER_UNIFORM) &&
                         newton_four_per_wave(P->H);
   if (tune_occ) knobs[nk++] = &cur.newton_occ;
-  const int cand[] = {4, 8, 12, 16, 24, 32, 48, 64};
+  // (grids well beyond the resident waves pay for the grid-strided kernels:
+  // the dispatcher then balances the uneven per-pair work)
+  const int cand[] = {4, 8, 12, 16, 24, 32, 48, 64, 128, 256};
+  const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
   const int cand01[] = {0, 1};
   const int cand45[] = {4, 5};
   auto measure = [&](float* best) -> int {
@@ -1919,7 +1922,7 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
     if ((rc = measure(&best_ms))) break;
     const bool binary = knobs[k] == &cur.mlp_fused || knobs[k] == &cur.newton_occ;
     const int* cv = knobs[k] == &cur.mlp_fused ? cand01 : (knobs[k] == &cur.newton_occ ? cand45 : cand);
-    const int ncv = binary ? 2 : 8;
+    const int ncv = binary ? 2 : ncand;
     for (int ci = 0; ci < ncv; ++ci) {
       const int v = cv[ci];
       if (v == best_v) continue;
