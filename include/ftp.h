@@ -373,7 +373,9 @@ int ftp_mlp_train_step(ftp_mlp* net, const uint16_t* X, int64_t B, const float* 
 int ftp_learned_dataset(ftp_plan* plan, const double* t, const double* y, const double* sigma, int64_t n_obs,
                         double df, int64_t n_f, uint16_t* X, float* roots, int* nroots, int R, void* stream);
 
-/* Current launch shapes of the plan (defaults until set or tuned). */
+/* Current launch shapes of the plan (until set or tuned: assembly, Newton and
+ * scoring 256 waves per CU, Aberth and QR 16, four GEMM launches for the
+ * network, the Newton kernel built for 5 waves per SIMD). */
 int ftp_plan_get_tuning(const ftp_plan* plan, ftp_tuning* out);
 
 /* Set the launch shapes.  FTP_E_OPTION if a shape is outside 1..256,

@@ -389,7 +389,10 @@ struct ftp_plan {
   DevBuf xfeat, seeds, fb_list, fb2_list, rt_list, work_ctr;
   // launch shapes (waves per compute unit), set by ftp_plan_set_tuning or
   // ftp_autotune
-  ftp_tuning tune{32, 32, 16, 16, 32, 0, 4};
+  // default launch shapes: grids far beyond the resident waves for the
+  // grid-strided assembly, Newton and scoring kernels (measured on the H
+  // sweep's lightcurves: equal or faster at every H, -6 % at H = 11)
+  ftp_tuning tune{256, 256, 16, 16, 256, 0, 5};
   DevBuf tune_out;
   // multi-band calls: chi^2_0 of every lightcurve of the batch (device, set
   // for the duration of the call) and the band outputs' scratch
