@@ -928,7 +928,9 @@ int run_solve_with(ftp_plan* P, const SolveArgs& a0, int64_t n_pairs, const Solv
         RA.out_list = B.rt_list;
         RA.out_count = ctr + 5;
         RA.counters = B.counters;
-        HIP_TRY(launch_newton_retry(RA, (int)grid_waves(P, 16, np), st));
+        // (one wavefront per listed frequency: a grid at least as long as the
+        // list gives no wavefront a second one)
+        HIP_TRY(launch_newton_retry(RA, (int)grid_waves(P, 64, np), st));
       }
       if (solver != FTP_SOLVER_ABERTH && overlap_score && net_list) {
         HIP_TRY(hipEventRecord(P->fork_ev, st));
