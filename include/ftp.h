@@ -152,8 +152,8 @@ typedef struct {
   int mlp_fused;        /* learned: 1 = one kernel for the four network layers (LDS-staged
                            weights, activations kept per wavefront), 0 = four GEMM
                            launches; identical results */
-  int newton_occ;       /* Newton + Sturm (H <= 10): the build compiled for 4 or 5
-                           resident wavefronts per SIMD (fewer registers per lane at 5) */
+  int newton_occ;       /* Newton + Sturm (H <= 10): the build compiled for 4, 5 or 6
+                           resident wavefronts per SIMD (fewer registers per lane at more) */
 } ftp_tuning;
 
 #define FTP_TUNE_FORCE 1u   /* ftp_autotune: measure even if the cache holds an entry */
@@ -379,7 +379,7 @@ int ftp_learned_dataset(ftp_plan* plan, const double* t, const double* y, const 
 int ftp_plan_get_tuning(const ftp_plan* plan, ftp_tuning* out);
 
 /* Set the launch shapes.  FTP_E_OPTION if a shape is outside 1..256,
- * mlp_fused is not 0 or 1 or newton_occ is not 4 or 5. */
+ * mlp_fused is not 0 or 1 or newton_occ is not 4, 5 or 6. */
 int ftp_plan_set_tuning(ftp_plan* plan, const ftp_tuning* tuning);
 
 /*

@@ -1082,7 +1082,7 @@ bool tuning_valid(const ftp_tuning& t) {
   const int v[5] = {t.assemble_wpc, t.newton_wpc, t.aberth_wpc, t.qr_wpc, t.score_wpc};
   for (int x : v)
     if (x < 1 || x > 256) return false;
-  return (t.mlp_fused == 0 || t.mlp_fused == 1) && (t.newton_occ == 4 || t.newton_occ == 5);
+  return (t.mlp_fused == 0 || t.mlp_fused == 1) && t.newton_occ >= 4 && t.newton_occ <= 6;
 }
 
 bool key_valid(const char* key) {
@@ -1909,7 +1909,7 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
   const int cand[] = {4, 8, 12, 16, 24, 32, 48, 64, 128, 256};
   const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
   const int cand01[] = {0, 1};
-  const int cand45[] = {4, 5};
+  const int cand_occ[] = {4, 5, 6};
   auto measure = [&](float* best) -> int {
     P->tune = cur;
     float m0 = 0.f, m1 = 0.f;
@@ -1925,9 +1925,9 @@ int ftp_autotune(ftp_plan* P, const double* t, const double* y, const double* si
     int best_v = *knobs[k];
     float best_ms = 0.f;
     if ((rc = measure(&best_ms))) break;
-    const bool binary = knobs[k] == &cur.mlp_fused || knobs[k] == &cur.newton_occ;
-    const int* cv = knobs[k] == &cur.mlp_fused ? cand01 : (knobs[k] == &cur.newton_occ ? cand45 : cand);
-    const int ncv = binary ? 2 : ncand;
+    const bool is_mlp = knobs[k] == &cur.mlp_fused, is_occ = knobs[k] == &cur.newton_occ;
+    const int* cv = is_mlp ? cand01 : (is_occ ? cand_occ : cand);
+    const int ncv = is_mlp ? 2 : (is_occ ? 3 : ncand);
     for (int ci = 0; ci < ncv; ++ci) {
       const int v = cv[ci];
       if (v == best_v) continue;

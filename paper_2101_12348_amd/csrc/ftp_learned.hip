@@ -703,8 +703,10 @@ __device__ __forceinline__ void newton_pair(const LearnArgs& L, const RecLayout&
 }
 
 // OCC: resident wavefronts per SIMD the register allocation is made for (4:
-// up to 128 VGPRs, 5: up to 96, with a few spills outside the Newton loop);
-// which is faster depends on the workload, so the launch shape picks it.
+// up to 128 VGPRs; 5: up to 96, a few spills outside the Newton loop; 6: up
+// to 80, more spills, but more waves to cover the Sturm steps' latency);
+// which is faster depends on the workload and the grid, so the launch shape
+// picks it.
 template <int OCC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void k_newton_sturm4(SolveArgs a, LearnArgs L) {
   extern __shared__ double sml[];
@@ -1100,12 +1102,14 @@ hipError_t launch_newton_retry(const RetryArgs& A, int waves, hipStream_t st) {
 bool newton_four_per_wave(int H) { return 6 * H - 2 < 64; }
 
 // `done` (nullable): an event the launch itself records at the kernel's end
-// (no marker packet of its own on the stream); `occ`: 4 or 5 (k_newton_sturm4).
+// (no marker packet of its own on the stream); `occ`: 4, 5 or 6 (k_newton_sturm4).
 hipError_t launch_newton_sturm(const SolveArgs& a, const LearnArgs& L, int waves, int occ, hipStream_t st,
                                hipEvent_t done) {
   if (newton_four_per_wave(a.H)) {
     const size_t lds = (size_t)8 * (6 * a.H) * sizeof(double);   // 8 x (D + 2): f and its reversal, four pairs
-    if (occ == 5)
+    if (occ == 6)
+      hipExtLaunchKernelGGL(k_newton_sturm4<6>, dim3((unsigned)waves), dim3(64), lds, st, nullptr, done, 0, a, L);
+    else if (occ == 5)
       hipExtLaunchKernelGGL(k_newton_sturm4<5>, dim3((unsigned)waves), dim3(64), lds, st, nullptr, done, 0, a, L);
     else
       hipExtLaunchKernelGGL(k_newton_sturm4<4>, dim3((unsigned)waves), dim3(64), lds, st, nullptr, done, 0, a, L);

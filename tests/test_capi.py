@@ -112,7 +112,7 @@ def test_tuning_cache_file_round_trip(tmp_path):
     assert F.tune_cache_lookup(p, key) == shapes2
     with open(p, "a") as fh:
         fh.write("garbage line\n" + key + " 1 2 3\n" + "gfx950/256cu/H3/p0/s0 0 4 4 4 4 0\n"
-                 + "gfx950/256cu/H2/p0/s0 4 4 4 4 4 2\n" + "gfx950/256cu/H1/p0/s0 4 4 4 4 4 0 3\n"
+                 + "gfx950/256cu/H2/p0/s0 4 4 4 4 4 2\n" + "gfx950/256cu/H1/p0/s0 4 4 4 4 4 0 7\n"
                  + "gfx950/256cu/H5/p0/s0 8 8 8 8 8 1\n")
     assert F.tune_cache_lookup(p, key) == shapes2
     assert F.tune_cache_lookup(p, "gfx950/256cu/H3/p0/s0") is None

@@ -31,7 +31,7 @@ def test_outputs_do_not_depend_on_launch_shapes(ftp, solver):
     n_f = 6000
     plan = ftp.Plan(tmpl.c, tmpl.s, solver=solver)
     ref = {k: v.clone() for k, v in plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f).items()}
-    for wpc, occ in ((1, 4), (3, 5), (64, 5)):
+    for wpc, occ in ((1, 4), (3, 5), (64, 6)):
         plan.set_tuning(assemble_wpc=wpc, newton_wpc=wpc, aberth_wpc=wpc, qr_wpc=wpc, score_wpc=wpc, newton_occ=occ)
         out = plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
         for k in ref:
@@ -47,7 +47,7 @@ def test_set_tuning_rejects_bad_shapes(ftp):
             plan.set_tuning(qr_wpc=bad)
     with pytest.raises(ftp.FtpError):
         plan.set_tuning(mlp_fused=2)
-    for bad in (0, 3, 6):
+    for bad in (0, 3, 7):
         with pytest.raises(ftp.FtpError):
             plan.set_tuning(newton_occ=bad)
     with pytest.raises(KeyError):
@@ -65,7 +65,7 @@ def test_autotune_and_cache(ftp, tmp_path):
     shapes, cached = plan.autotune(lc.t, lc.y, lc.sigma, lc.df, n_f, cache_path=cache)
     assert not cached
     assert all(1 <= v <= 256 for k, v in shapes.items() if k not in ("mlp_fused", "newton_occ"))
-    assert shapes["mlp_fused"] in (0, 1) and shapes["newton_occ"] in (4, 5)
+    assert shapes["mlp_fused"] in (0, 1) and shapes["newton_occ"] in (4, 5, 6)
     assert plan.tuning() == shapes
     assert ftp.tune_cache_lookup(cache, plan.tune_key(n_f)) == shapes
     out = plan.periodogram(lc.t, lc.y, lc.sigma, lc.df, n_f)
